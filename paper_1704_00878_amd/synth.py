@@ -1,0 +1,247 @@
+"""Seeded synthetic protein families and the scoring tables they are scored with.
+
+This module holds inputs only: the substitution matrix s(a, b) and the gap
+scheme W_k that the method takes as parameters (Methods, "Smith-Waterman
+algorithm for protein sequences with Spark", eq. 2 and the sentence before
+eq. 1), the residue alphabet, and a deterministic generator of
+family-structured protein sets.  It contains none of the method's arithmetic,
+so the CPU oracle and the HIP path can both be fed from it.
+
+The real protein benchmark the paper uses (BAliBASE 4 R10, Table 1) is not
+available; the generator produces stand-ins with the same kind of structure:
+sequences descended from a few random roots by substitution and indels, with
+configurable length distributions.
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Callable, Sequence
+
+import numpy as np
+
+# NCBI 24-letter protein order; codes 0..23.  Codes 0..19 are the 20 standard
+# amino acids, 20..22 the ambiguity letters B, Z, X and 23 the stop '*'.
+ALPHABET = "ARNDCQEGHILKMFPSTWYVBZX*"
+N_STANDARD = 20
+GAP_CODE = 255
+
+# BLOSUM62 (Henikoff & Henikoff, PNAS 1992), half-bit units, NCBI layout.
+_BLOSUM62_TEXT = """
+   A  R  N  D  C  Q  E  G  H  I  L  K  M  F  P  S  T  W  Y  V  B  Z  X  *
+A  4 -1 -2 -2  0 -1 -1  0 -2 -1 -1 -1 -1 -2 -1  1  0 -3 -2  0 -2 -1  0 -4
+R -1  5  0 -2 -3  1  0 -2  0 -3 -2  2 -1 -3 -2 -1 -1 -3 -2 -3 -1  0 -1 -4
+N -2  0  6  1 -3  0  0  0  1 -3 -3  0 -2 -3 -2  1  0 -4 -2 -3  3  0 -1 -4
+D -2 -2  1  6 -3  0  2 -1 -1 -3 -4 -1 -3 -3 -1  0 -1 -4 -3 -3  4  1 -1 -4
+C  0 -3 -3 -3  9 -3 -4 -3 -3 -1 -1 -3 -1 -2 -3 -1 -1 -2 -2 -1 -3 -3 -2 -4
+Q -1  1  0  0 -3  5  2 -2  0 -3 -2  1  0 -3 -1  0 -1 -2 -1 -2  0  3 -1 -4
+E -1  0  0  2 -4  2  5 -2  0 -3 -3  1 -2 -3 -1  0 -1 -3 -2 -2  1  4 -1 -4
+G  0 -2  0 -1 -3 -2 -2  6 -2 -4 -4 -2 -3 -3 -2  0 -2 -2 -3 -3 -1 -2 -1 -4
+H -2  0  1 -1 -3  0  0 -2  8 -3 -3 -1 -2 -1 -2 -1 -2 -2  2 -3  0  0 -1 -4
+I -1 -3 -3 -3 -1 -3 -3 -4 -3  4  2 -3  1  0 -3 -2 -1 -3 -1  3 -3 -3 -1 -4
+L -1 -2 -3 -4 -1 -2 -3 -4 -3  2  4 -2  2  0 -3 -2 -1 -2 -1  1 -4 -3 -1 -4
+K -1  2  0 -1 -3  1  1 -2 -1 -3 -2  5 -1 -3 -1  0 -1 -3 -2 -2  0  1 -1 -4
+M -1 -1 -2 -3 -1  0 -2 -3 -2  1  2 -1  5  0 -2 -1 -1 -1 -1  1 -3 -1 -1 -4
+F -2 -3 -3 -3 -2 -3 -3 -3 -1  0  0 -3  0  6 -4 -2 -2  1  3 -1 -3 -3 -1 -4
+P -1 -2 -2 -1 -3 -1 -1 -2 -2 -3 -3 -1 -2 -4  7 -1 -1 -4 -3 -2 -2 -1 -2 -4
+S  1 -1  1  0 -1  0  0  0 -1 -2 -2  0 -1 -2 -1  4  1 -3 -2 -2  0  0  0 -4
+T  0 -1  0 -1 -1 -1 -1 -2 -2 -1 -1 -1 -1 -2 -1  1  5 -2 -2  0 -1 -1  0 -4
+W -3 -3 -4 -4 -2 -2 -3 -2 -2 -3 -2 -3 -1  1 -4 -3 -2 11  2 -3 -4 -3 -2 -4
+Y -2 -2 -2 -3 -2 -1 -2 -3  2 -1 -1 -2 -1  3 -3 -2 -2  2  7 -1 -3 -2 -1 -4
+V  0 -3 -3 -3 -1 -2 -2 -3 -3  3  1 -2  1 -1 -2 -2  0 -3 -1  4 -3 -2 -1 -4
+B -2 -1  3  4 -3  0  1 -1  0 -3 -4  0 -3 -3 -2  0 -1 -4 -3 -3  4  1 -1 -4
+Z -1  0  0  1 -3  3  4 -2  0 -3 -3  1 -1 -3 -1  0 -1 -3 -2 -2  1  4 -1 -4
+X  0 -1 -1 -1 -2 -1 -1 -1 -1 -1 -1 -1 -1 -1 -2  0  0 -2 -1 -1 -1 -1 -1 -4
+* -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4 -4  1
+"""
+
+
+def _parse_matrix(text: str) -> np.ndarray:
+    lines = [ln.split() for ln in text.strip().splitlines()]
+    header = lines[0]
+    assert "".join(header) == ALPHABET
+    mat = np.zeros((24, 24), dtype=np.int8)
+    for r, row in enumerate(lines[1:]):
+        assert row[0] == ALPHABET[r]
+        mat[r] = [int(v) for v in row[1:]]
+    return mat
+
+
+BLOSUM62 = _parse_matrix(_BLOSUM62_TEXT)
+BLOSUM62.setflags(write=False)
+
+# Background amino-acid frequencies that BLOSUM62 was derived with
+# (Henikoff & Henikoff 1992), three decimals, order ARNDCQEGHILKMFPSTWYV.
+BACKGROUND = np.array(
+    [0.074, 0.052, 0.045, 0.054, 0.025, 0.034, 0.054, 0.074, 0.026, 0.068,
+     0.099, 0.058, 0.025, 0.047, 0.039, 0.057, 0.051, 0.013, 0.032, 0.073],
+    dtype=np.float64)
+
+# Default gap scheme: W_k = GAP_OPEN + GAP_EXTEND * k (a 1-residue gap costs 12).
+GAP_OPEN = 11
+GAP_EXTEND = 1
+
+_ENCODE = np.full(256, 22, dtype=np.uint8)  # unknown letters -> X
+for _i, _ch in enumerate(ALPHABET):
+    _ENCODE[ord(_ch)] = _i
+    _ENCODE[ord(_ch.lower())] = _i
+_ENCODE[ord("U")] = _ENCODE[ord("u")] = ALPHABET.index("C")  # selenocysteine
+_ENCODE[ord("O")] = _ENCODE[ord("o")] = ALPHABET.index("K")  # pyrrolysine
+ENCODE_TABLE = _ENCODE
+ENCODE_TABLE.setflags(write=False)
+
+
+def encode(text: str) -> np.ndarray:
+    """ASCII protein string -> uint8 codes (host-side convenience)."""
+    return ENCODE_TABLE[np.frombuffer(text.encode("ascii"), dtype=np.uint8)]
+
+
+def decode(codes: Sequence[int]) -> str:
+    return "".join("-" if int(x) == GAP_CODE else ALPHABET[int(x)] for x in codes)
+
+
+# ---------------------------------------------------------------------------
+# Packed sequence sets
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass
+class SeqSet:
+    """N sequences as one concatenated uint8 code array plus int64 offsets."""
+    residues: np.ndarray  # uint8[sum n]
+    offsets: np.ndarray   # int64[N+1]
+
+    @property
+    def n(self) -> int:
+        return len(self.offsets) - 1
+
+    def seq(self, k: int) -> np.ndarray:
+        return self.residues[self.offsets[k]:self.offsets[k + 1]]
+
+    def lengths(self) -> np.ndarray:
+        return np.diff(self.offsets)
+
+    @staticmethod
+    def from_list(seqs: Sequence[np.ndarray]) -> "SeqSet":
+        lens = np.array([len(s) for s in seqs], dtype=np.int64)
+        offs = np.zeros(len(seqs) + 1, dtype=np.int64)
+        np.cumsum(lens, out=offs[1:])
+        res = (np.concatenate([np.asarray(s, dtype=np.uint8) for s in seqs])
+               if len(seqs) and offs[-1] > 0 else np.zeros(0, np.uint8))
+        return SeqSet(res.astype(np.uint8), offs)
+
+    def subset(self, idx: Sequence[int]) -> "SeqSet":
+        return SeqSet.from_list([self.seq(int(k)) for k in idx])
+
+
+# ---------------------------------------------------------------------------
+# Family generator
+# ---------------------------------------------------------------------------
+@dataclasses.dataclass(frozen=True)
+class FamilyConfig:
+    name: str
+    n_seqs: int
+    n_roots: int
+    p_sub: float
+    p_indel: float
+    length: Callable[[np.random.Generator, int], np.ndarray]
+    seed: int
+
+
+def _uniform(lo: int, hi: int):
+    def draw(rng: np.random.Generator, k: int) -> np.ndarray:
+        return rng.integers(lo, hi + 1, size=k)
+    return draw
+
+
+def _lognormal(mu: float, sigma: float, lo: int, hi: int):
+    def draw(rng: np.random.Generator, k: int) -> np.ndarray:
+        x = np.round(np.exp(rng.normal(mu, sigma, size=k)))
+        return np.clip(x, lo, hi).astype(np.int64)
+    return draw
+
+
+SEED_BASE = 20170403
+
+# The five workloads (sizes, length laws, family structure, mutation rates).
+CONFIGS = {
+    "plain64": FamilyConfig("plain64", 64, 1, 0.20, 0.05, _uniform(80, 160), SEED_BASE + 1),
+    "batch20k": FamilyConfig("batch20k", 20_000, 8, 0.25, 0.05, _uniform(200, 500), SEED_BASE + 2),
+    "longtail200k": FamilyConfig("longtail200k", 200_000, 32, 0.30, 0.08,
+                                 _lognormal(5.8, 0.5, 50, 2000), SEED_BASE + 3),
+    "learned50k": FamilyConfig("learned50k", 50_000, 32, 0.25, 0.05, _uniform(150, 600), SEED_BASE + 4),
+    "ultra1m": FamilyConfig("ultra1m", 1_000_000, 128, 0.30, 0.06, _uniform(50, 1000), SEED_BASE + 5),
+}
+
+
+def _background_draw(rng: np.random.Generator, k: int) -> np.ndarray:
+    return rng.choice(N_STANDARD, size=k, p=BACKGROUND).astype(np.uint8)
+
+
+def _mutate(rng: np.random.Generator, seq: np.ndarray, p_sub: float, p_indel: float) -> np.ndarray:
+    seq = seq.copy()
+    n = len(seq)
+    # substitutions: redraw from the background conditioned on being different
+    hit = np.nonzero(rng.random(n) < p_sub)[0]
+    if len(hit):
+        new = _background_draw(rng, len(hit))
+        same = new == seq[hit]
+        while same.any():
+            new[same] = _background_draw(rng, int(same.sum()))
+            same = new == seq[hit]
+        seq[hit] = new
+    # indels: at each position start one with probability p_indel
+    starts = np.nonzero(rng.random(n) < p_indel)[0]
+    if len(starts) == 0:
+        return seq
+    kinds = rng.random(len(starts)) < 0.5          # True -> insertion
+    lens = rng.geometric(0.5, size=len(starts))
+    pieces = []
+    pos = 0
+    for st, ins, ln in zip(starts.tolist(), kinds.tolist(), lens.tolist()):
+        if st < pos:  # inside a previous deletion
+            continue
+        pieces.append(seq[pos:st])
+        if ins:
+            pieces.append(_background_draw(rng, ln))
+            pos = st
+        else:
+            pos = min(n, st + ln)
+    pieces.append(seq[pos:])
+    return np.concatenate(pieces).astype(np.uint8)
+
+
+def generate(cfg: FamilyConfig | str, n_seqs: int | None = None, seed: int | None = None) -> SeqSet:
+    """Deterministic family-structured protein set.
+
+    Each sequence picks a root uniformly, draws a target length L from the
+    config's length law, takes a uniform window of the root (or the whole root
+    padded at random on both ends with background residues when L exceeds the
+    root), then mutates it by substitution and by geometric(0.5)-length indels.
+    """
+    if isinstance(cfg, str):
+        cfg = CONFIGS[cfg]
+    n_seqs = cfg.n_seqs if n_seqs is None else n_seqs
+    rng = np.random.Generator(np.random.PCG64(cfg.seed if seed is None else seed))
+    root_lens = cfg.length(rng, cfg.n_roots)
+    roots = [_background_draw(rng, int(L)) for L in root_lens]
+    which = rng.integers(0, cfg.n_roots, size=n_seqs)
+    targets = cfg.length(rng, n_seqs)
+    seqs = []
+    for k in range(n_seqs):
+        root = roots[which[k]]
+        L = int(targets[k])
+        if L <= len(root):
+            st = int(rng.integers(0, len(root) - L + 1))
+            base = root[st:st + L]
+        else:
+            extra = L - len(root)
+            left = int(rng.integers(0, extra + 1))
+            base = np.concatenate([_background_draw(rng, left), root,
+                                   _background_draw(rng, extra - left)])
+        seqs.append(_mutate(rng, base, cfg.p_sub, cfg.p_indel))
+    return SeqSet.from_list(seqs)
+
+
+def random_set(rng: np.random.Generator, n_seqs: int, lo: int, hi: int,
+               alphabet: int = N_STANDARD) -> SeqSet:
+    """Unrelated iid sequences with uniform lengths (edge-case tests)."""
+    lens = rng.integers(lo, hi + 1, size=n_seqs)
+    return SeqSet.from_list([rng.integers(0, alphabet, size=int(L)).astype(np.uint8) for L in lens])
