@@ -1,0 +1,199 @@
+"""Benchmark: batched center-star MSA on one MI355X.
+
+One step = the whole hot path on the batch20k workload (20,000 synthetic
+family-structured proteins, lengths 200-500, 8 roots, 25% substitution, 5%
+indel; BLOSUM62, W_k = 11 + k; center = sequence 0): affine SW of every
+sequence against the center with traceback, the gap merge, and row emission,
+with the sequences already resident in HBM.  The metric is GCUPS = m * sum(n)
+DP cells per second of the whole step.
+
+Also reported: the dominant kernel's roofline (integer VALU), the same kernels
+launched once per pair (no batching), and the oracle timed on the host cores.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import threading
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "batched SW GCUPS vs per-pair launch; MSA s at SP ≥99% of exact center"
+PEAK_INT32_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12      # 39.32 T int32 lane-ops/s
+OPS_PER_CELL_TB = 14                               # fixed op model, traceback pass
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(seqs, center: int, budget_s: float = 20.0):
+    """The oracle, unchanged, on a bounded sample of the same workload: SW with
+    traceback of sequences against the center, split over host threads (each
+    thread runs the single-threaded routine on its own slice)."""
+    import oracle
+    from paper_1704_00878_amd import synth
+    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
+    cores = max(1, min(cores, 16))
+    c = seqs.seq(center)
+    m = len(c)
+    lens = seqs.lengths()
+    # size the sample from a short single-thread probe
+    probe = seqs.subset(range(min(40, seqs.n)))
+    t = time.perf_counter()
+    oracle.sw_batch(synth.BLOSUM62, synth.GAP_OPEN, synth.GAP_EXTEND, c, probe.residues, probe.offsets)
+    rate1 = m * probe.residues.size / max(time.perf_counter() - t, 1e-6)
+    want_cells = rate1 * cores * budget_s
+    cum = np.cumsum(lens) * m
+    nsamp = int(min(seqs.n, max(cores, np.searchsorted(cum, want_cells))))
+    sample = seqs.subset(range(nsamp))
+    slices = np.array_split(np.arange(nsamp), cores)
+    parts = [sample.subset(sl) for sl in slices if len(sl)]
+    err = []
+
+    def work(p):
+        try:
+            oracle.sw_batch(synth.BLOSUM62, synth.GAP_OPEN, synth.GAP_EXTEND, c, p.residues, p.offsets)
+        except Exception as e:  # pragma: no cover
+            err.append(e)
+
+    ths = [threading.Thread(target=work, args=(p,)) for p in parts]
+    t = time.perf_counter()
+    for th in ths:
+        th.start()
+    for th in ths:
+        th.join()
+    dt = time.perf_counter() - t
+    if err:
+        raise err[0]
+    cells = m * int(sample.residues.size)
+    return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": len(parts), "kind": "oracle",
+            "sample": f"SW+traceback of the first {nsamp} of {seqs.n} sequences against the center "
+                      f"({cells:.3e} cells, {dt:.1f} s, one thread per core)"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="batch20k")
+    ap.add_argument("--route", default="auto", choices=["auto", "intra", "inter"])
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--perpair", type=int, default=200, help="pairs for the per-pair-launch baseline")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
+              "is described in DESIGN.md and is not built.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_1704_00878_amd as H
+    from paper_1704_00878_amd import _build, synth
+    if not os.path.exists(_build.LIB_PATH):
+        _build.build()
+    assert torch.cuda.is_available()
+    torch.cuda.set_device(0)
+    log(f"bench: generating {args.workload}")
+    seqs = synth.generate(args.workload)
+    center = 0
+    m = len(seqs.seq(center))
+    cells = m * int(seqs.residues.size)
+    ds = H.DeviceSeqs(seqs, "cuda:0")
+    sc = H.Scoring()
+    ctx = H.Context(0)
+    route = {"auto": H.HALIGN_ROUTE_AUTO, "intra": H.HALIGN_ROUTE_INTRA, "inter": H.HALIGN_ROUTE_INTER}[args.route]
+    stream = torch.cuda.current_stream()
+
+    def step():
+        return H.halign_msa(ctx, sc, ds, center)
+
+    if route != H.HALIGN_ROUTE_AUTO:
+        os.environ["HALIGN_ROUTE"] = args.route
+    log(f"bench: N={seqs.n} m={m} cells={cells:.3e}; warmup {args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    fwd, walk = [], []
+    log(f"bench: timing {args.steps} steps")
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        msa, _c = step()
+        tm = ctx.last_timings()      # HIP events on the stream of the kernels
+        fwd.append(tm[0])
+        walk.append(tm[1])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    gcups = cells / (ms_step * 1e-3) / 1e9
+    st = ctx.last_stats()
+    fwd_ms = float(np.mean(fwd))
+    walk_ms = float(np.mean(walk))
+    width = int(msa.shape[1])
+    log(f"bench: {ms_step:.3f} ms/step, {gcups:.1f} GCUPS; forward {fwd_ms:.3f} ms, walk {walk_ms:.3f} ms")
+
+    # per-pair launches: same kernels, one pair per call, no batching
+    rng = np.random.default_rng(0)
+    pick = rng.choice(seqs.n, size=min(args.perpair, seqs.n), replace=False)
+    singles = [H.DeviceSeqs(seqs.subset([int(k)]), "cuda:0") for k in pick]
+    cseq = ds.residues[int(ds.offsets_host[center]):int(ds.offsets_host[center + 1])]
+    for d in singles[:5]:
+        H.sw_batch(ctx, sc, d, 0, traceback=True, center_seq=cseq)
+    torch.cuda.synchronize()
+    tp = time.perf_counter()
+    for d in singles:
+        H.sw_batch(ctx, sc, d, 0, traceback=True, center_seq=cseq)
+    torch.cuda.synchronize()
+    dtp = time.perf_counter() - tp
+    pp_cells = m * int(sum(seqs.length(int(k)) for k in pick))
+    pp_gcups = pp_cells / dtp / 1e9
+    log(f"bench: per-pair launches {pp_gcups:.2f} GCUPS over {len(pick)} pairs")
+
+    # dominant kernel roofline: integer VALU, fixed op model
+    achieved = cells * OPS_PER_CELL_TB / (fwd_ms * 1e-3) / 1e12
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 2),
+            "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
+            "kernel": "sw_intra_kernel" if st["route"] == 0 else "sw_inter_kernel",
+            "ops_per_cell": OPS_PER_CELL_TB, "kernel_ms": round(fwd_ms, 4),
+            "kernel_gcups": round(cells / (fwd_ms * 1e-3) / 1e9, 1)}
+
+    # avg SP of the produced MSA (evaluation, untimed)
+    sp, spb = H.halign_sp_score(sc, msa)
+    npairs = seqs.n * (seqs.n - 1) // 2
+
+    cpu = None
+    if not args.no_cpu:
+        log("bench: oracle on host cores")
+        cpu = cpu_baseline(seqs, center)
+        log(f"bench: oracle {cpu['value']:.3f} GCUPS on {cpu['cores']} threads")
+
+    out = {
+        "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {seqs.n} seqs, len {int(seqs.lengths().min())}-"
+                               f"{int(seqs.lengths().max())}, center seq 0 (m={m}), BLOSUM62, gap 11+k",
+                   "cells_per_step": cells, "msa_width": width, "route": ["intra", "inter"][st["route"]]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "per_pair_launch": {"value": round(pp_gcups, 3), "unit": "GCUPS", "pairs": len(pick),
+                            "batched_over_per_pair": round(gcups / pp_gcups, 1)},
+        "stages_ms": {"forward": round(fwd_ms, 4), "walk": round(walk_ms, 4),
+                      "merge_rows_other": round(ms_step - fwd_ms - walk_ms, 4)},
+        "avg_sp": round(sp / npairs, 3), "msa_s": round(ms_step / 1e3, 6),
+    }
+    print(json.dumps(out), flush=True)
+    ctx.close()
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,235 @@
+/*
+ * halign.h -- C ABI of the MI355X (gfx950) center-star protein MSA library.
+ *
+ * The library computes the protein path of HAlign-II (Wan & Zou, arXiv
+ * 1704.00878, Methods, "Smith-Waterman algorithm for protein sequences with
+ * Spark" and Fig. 3):
+ *   1. local affine-gap Smith-Waterman of every sequence against a center
+ *      sequence, with traceback (eq. 1, eq. 2; the traceback runs from the
+ *      highest cell back to the first zero cell);
+ *   2. the first reduction of Fig. 3: the inserted-space vectors of all
+ *      pairwise alignments are merged into the longest center-star sequence;
+ *   3. the second map step: each MSA row is built from its inserted-space
+ *      vector and its own sequence.
+ * plus center selection (exact sum of scores, or a learned proposer judged
+ * exactly) and the avg SP metric of the Results section.
+ *
+ * Conventions for every call:
+ *  - Pointers are DEVICE pointers unless the parameter name ends in _host.
+ *  - All buffers belong to the caller; the library never frees them.
+ *    Scratch memory (traceback codes, plans) is owned by the halign_ctx.
+ *  - Calls are asynchronous on the given stream (a hipStream_t passed as
+ *    void*; NULL = the null stream).  Outputs are valid once that stream
+ *    synchronises.  Calls that return a value through a _host pointer
+ *    synchronise the stream before returning.
+ *  - Every call returns an int status: HALIGN_OK or a negative code; the
+ *    message of the last failure on this thread is halign_last_error().
+ *  - No C++ exception crosses this boundary.
+ *  - One ctx must not be used from two threads or two streams at once.
+ *
+ * Residues are codes 0..alphabet-1 (NCBI order ARNDCQEGHILKMFPSTWYVBZX* for
+ * the 24-letter protein alphabet); MSA gap bytes are HALIGN_GAP (255).
+ */
+#ifndef HALIGN_H
+#define HALIGN_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes ------------------------------------------------------ */
+#define HALIGN_OK              0
+#define HALIGN_E_INVALID      -1  /* bad argument: sizes, codes, offsets, NULL */
+#define HALIGN_E_NOMEM        -2  /* device allocation failed or cap exceeded */
+#define HALIGN_E_DEVICE       -3  /* HIP runtime error */
+#define HALIGN_E_UNSUPPORTED  -4  /* outside the supported envelope (see below) */
+#define HALIGN_E_OVERFLOW     -5  /* a score bound exceeds the integer range */
+
+#define HALIGN_GAP 255
+
+/* flags of halign_sw_batch */
+#define HALIGN_SCORE_ONLY  0u     /* score (and end cell when cells != NULL) */
+#define HALIGN_TRACEBACK   1u     /* also walk back: cells, ins, aligned */
+
+/* kernel routing overrides (halign_sw_batch flags, bits 4..5) */
+#define HALIGN_ROUTE_AUTO   0u
+#define HALIGN_ROUTE_INTER  (1u << 4)  /* one pair per lane */
+#define HALIGN_ROUTE_INTRA  (2u << 4)  /* one pair per wavefront */
+
+/* center modes of halign_msa */
+#define HALIGN_CENTER_EXACT   (-1)
+#define HALIGN_CENTER_LEARNED (-2)
+
+/* Supported envelope: alphabet <= 32, every sequence length < 65536,
+ * gap_open >= 0, gap_extend >= 1 (HALIGN_E_UNSUPPORTED otherwise).  Scores
+ * are int32 and cannot overflow inside this envelope. */
+
+typedef struct halign_ctx halign_ctx;
+
+/* Substitution matrix s(a, b) and gap weights W_k = gap_open + k*gap_extend
+ * (eq. 2 with an affine W_k). */
+typedef struct {
+    const int8_t *matrix_host;  /* alphabet x alphabet, row-major, host */
+    int32_t alphabet;
+    int32_t gap_open;
+    int32_t gap_extend;
+} halign_scoring;
+
+/* A packed sequence set: sequence k is residues[offsets[k] .. offsets[k+1]).
+ * offsets (device) and offsets_host (host) hold the same N+1 values;
+ * offsets[0] == 0 and offsets are non-decreasing.  Empty sequences are legal. */
+typedef struct {
+    const uint8_t *residues;      /* device, total = offsets[N] bytes */
+    const int64_t *offsets;       /* device, N+1 */
+    const int64_t *offsets_host;  /* host,   N+1 */
+    int32_t n;                    /* N */
+} halign_seqs;
+
+/* ---- context ------------------------------------------------------------ */
+/* Creates a context on `device`.  workspace_cap_bytes bounds the traceback
+ * scratch the context may hold (0 = no cap); a batch whose codes exceed it is
+ * processed in chunks with identical results. */
+int  halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out);
+void halign_ctx_destroy(halign_ctx *ctx);
+const char *halign_last_error(void);
+/* Bytes of device scratch currently held by the context. */
+int  halign_ctx_workspace_bytes(const halign_ctx *ctx, size_t *bytes_host);
+/* Timing (ms) of the last halign_sw_batch stages on the ctx stream, measured
+ * with HIP events: [0] forward DP kernel(s), [1] traceback walk, [2] whole call.
+ * Valid after the stream synchronises. */
+int  halign_ctx_last_timings(halign_ctx *ctx, float *ms_host /*[3]*/);
+/* Number of workgroups/launches of the dominant forward kernel in the last
+ * call (for roofline accounting) and the DP cells it covered. */
+int  halign_ctx_last_stats(const halign_ctx *ctx, int64_t *stats_host /*[4]: cells, launches, route, chunks*/);
+
+/* ---- step a1: encode ASCII to residue codes (upper/lower case; U->C,
+ * O->K, other letters -> X).  ascii and codes may alias. */
+int halign_encode(const uint8_t *ascii, int64_t len, uint8_t *codes, void *stream);
+
+/* ---- pairwise SW against the center (eq. 1-2, traceback as in Fig. 2) ----
+ * center[m] (device) against every sequence of seqs.
+ * Outputs (device, any may be NULL except score):
+ *   score[N]             best local score (int32)
+ *   cells[N][4]          i0, j0, i1, j1: the core aligns center[i0, i1) with
+ *                        s[j0, j1) (0-based, half-open); all 0 when score 0.
+ *                        End cell = max H, ties to the smallest j, then i.
+ *   ins[N][m+1]          residues of s placed in each center slot: slot 0
+ *                        before center[0], slot p between center[p-1] and
+ *                        center[p], slot m after center[m-1]; the unaligned
+ *                        prefix of s goes to slot 0 and the suffix to slot m
+ *                        (all of s to slot 0 when the score is 0).
+ *   aligned[N][(m+31)/32] bit p set when center[p] faces a residue of s.
+ * ins/aligned require HALIGN_TRACEBACK. */
+int halign_sw_batch(halign_ctx *ctx, const halign_scoring *sc,
+                    const uint8_t *center, int32_t m,
+                    const halign_seqs *seqs, uint32_t flags,
+                    int32_t *score, int32_t *cells, uint16_t *ins, uint32_t *aligned,
+                    void *stream);
+
+/* Score-only SW of anchored pairs (center selection, training targets):
+ * score[64*q + l] = SW(seq anchors_host[q], seq partners_host[64*q + l]) for
+ * q < nanchors, l < 64.  Index arrays are HOST arrays; score is device. */
+int halign_sw_pairs(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+                    const int32_t *anchors_host, int32_t nanchors, const int32_t *partners_host,
+                    int32_t *score, void *stream);
+
+/* ---- first reduction of Fig. 3 ------------------------------------------
+ * G[p] = max_k ins[k][p] (p = 0..m), col[p] = sum_{q<p} (G[q] + 1) = first
+ * MSA column of gap block p, *width_host = m + sum_p G[p] (synchronises). */
+int halign_merge(halign_ctx *ctx, const uint16_t *ins, int32_t n, int32_t m,
+                 int32_t *G, int64_t *col, int64_t *width_host, void *stream);
+
+/* ---- second map step of Fig. 3: MSA rows ----------------------------------
+ * msa[N][width]: block p has G[p] columns holding the ins[k][p] residues of
+ * sequence k left-justified then gaps; then (p < m) the column of center[p]
+ * holding the next residue of sequence k when aligned bit p is set, else a gap. */
+int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m,
+                     const uint16_t *ins, const uint32_t *aligned,
+                     const int32_t *G, const int64_t *col, int64_t width,
+                     uint8_t *msa, void *stream);
+
+/* ---- center selection ------------------------------------------------------
+ * Exact: sums[i] = sum_{j != i} SW(seq i, seq j) (int64), center = argmax,
+ * ties to the lowest index (Methods: the center is the sequence most similar
+ * to the others).  *center_host is written (synchronises). */
+int halign_center_exact(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+                        int64_t *sums, int32_t *center_host, void *stream);
+/* Exact judge restricted to candidates cand[ncand] (device): sums[q] =
+ * sum_{j != cand[q]} SW(seq cand[q], seq j); *center_host = the candidate
+ * with the largest sum, ties to the lowest sequence index. */
+int halign_center_judge(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+                        const int32_t *cand, int32_t ncand, int64_t *sums,
+                        int32_t *center_host, void *stream);
+
+/* ---- learned center proposer (BF16 MLP on 3-mer counts) ------------------
+ * Features: X[k][400a + 20b + c] = count of the 3-mer abc (codes < 20 only)
+ * in sequence rows[k] (rows == NULL: k itself), stored as bf16 bit patterns,
+ * nrows x HALIGN_FEAT. */
+#define HALIGN_FEAT 8000
+#define HALIGN_HID  256
+#define HALIGN_EMB  64
+int halign_featurize(const halign_seqs *seqs, const int32_t *rows, int32_t nrows,
+                     uint16_t *X, void *stream);
+
+/* Model parameters (device).  W1: HALIGN_FEAT x HALIGN_HID bf16 bits
+ * (row-major), b1: HALIGN_HID fp32, W2: HALIGN_HID x HALIGN_EMB bf16 bits,
+ * b2: HALIGN_EMB fp32.  Forward: Hb = bf16(relu(X W1 + b1)),
+ * E = Hb W2 + b2 (fp32 accumulation on MFMA). */
+typedef struct {
+    const uint16_t *W1; const float *b1;
+    const uint16_t *W2; const float *b2;
+} halign_model;
+
+/* Hpre (fp32, nrows x HID, may be NULL), Hb (bf16 bits, nrows x HID) and
+ * E (fp32, nrows x EMB) are outputs. */
+int halign_mlp_forward(const halign_model *model, const uint16_t *X, int32_t nrows,
+                       float *Hpre, uint16_t *Hb, float *E, void *stream);
+
+/* Pair loss for pairs (r, r + npairs), r < npairs, of an E with 2*npairs rows:
+ * pred = E[r].E[r+npairs], loss = mean (pred - target)^2.  Writes dE
+ * (fp32, 2*npairs x EMB) and loss_out[0] (device fp32). */
+int halign_pair_loss(const float *E, const float *target, int32_t npairs,
+                     float *dE, float *loss_out, void *stream);
+
+/* Backward of halign_mlp_forward for dE: dW1 (fp32 FEAT x HID), db1 (HID),
+ * dW2 (fp32 HID x EMB), db2 (EMB).  Hpre must come from the same forward. */
+int halign_mlp_backward(const halign_model *model, const uint16_t *X, int32_t nrows,
+                        const float *Hpre, const uint16_t *Hb, const float *dE,
+                        float *dW1, float *db1, float *dW2, float *db2, void *stream);
+
+/* Adam on fp32 master weights p[n] with gradient g, moments m, v (step t >= 1,
+ * bias-corrected); writes the bf16 copy pb when non-NULL. */
+int halign_adam_step(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n,
+                     float lr, float beta1, float beta2, float eps, int32_t t, void *stream);
+
+/* Candidate scores u_i = E_i . (sum_j E_j - E_i) and the top k indices
+ * (largest u first, ties to the lower index) into top[k] (device int32). */
+int halign_topk_center(const float *E, int32_t nrows, int32_t k, float *u, int32_t *top,
+                       void *stream);
+
+/* ---- end-to-end center-star MSA -------------------------------------------
+ * center >= 0: that sequence index; HALIGN_CENTER_EXACT: exhaustive search;
+ * HALIGN_CENTER_LEARNED: top-16 of `model`, judged exactly.
+ * The MSA buffer (N x width bytes) is obtained from alloc(bytes, user), since
+ * width is known only after the merge; *msa receives it. */
+typedef void *(*halign_alloc_fn)(size_t bytes, void *user);
+int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+               int32_t center, const halign_model *model,
+               halign_alloc_fn alloc, void *user,
+               uint8_t **msa, int64_t *width_host, int32_t *center_out_host, void *stream);
+
+/* ---- evaluation (Results: avg SP) ------------------------------------------
+ * out_host[0] = sum over row pairs and columns of: 1 for two different
+ * residues, 2 for a residue against a gap, 0 otherwise (avg SP = out/C(N,2));
+ * out_host[1] = BLOSUM column SP (S for residue pairs, -gap_extend per
+ * residue/gap pair).  Synchronises. */
+int halign_sp_score(const halign_scoring *sc, const uint8_t *msa, int32_t n, int64_t width,
+                    int64_t *out_host, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* HALIGN_H */

@@ -1,0 +1,313 @@
+"""MI355X (gfx950) center-star protein MSA -- Python binding of libhalign.so.
+
+The binding only marshals arguments: device memory comes from torch tensors
+(``data_ptr()``), streams from ``torch.cuda.current_stream()``, and every step
+of the path runs in the HIP kernels of ``csrc/``.  If the built library is
+missing the import of this module still works, but every call raises.
+
+Function names follow the C ABI in ``include/halign.h``.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+from . import synth
+from ._build import LIB_PATH
+
+GAP = 255
+FEAT, HID, EMB = 8000, 256, 64
+
+HALIGN_OK = 0
+HALIGN_SCORE_ONLY = 0
+HALIGN_TRACEBACK = 1
+HALIGN_ROUTE_AUTO = 0
+HALIGN_ROUTE_INTER = 1 << 4
+HALIGN_ROUTE_INTRA = 2 << 4
+HALIGN_CENTER_EXACT = -1
+HALIGN_CENTER_LEARNED = -2
+
+
+class HalignError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"halign error {code}: {msg}")
+        self.code = code
+
+
+class _Scoring(ctypes.Structure):
+    _fields_ = [("matrix_host", ctypes.c_void_p), ("alphabet", ctypes.c_int32),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+
+
+class _Seqs(ctypes.Structure):
+    _fields_ = [("residues", ctypes.c_void_p), ("offsets", ctypes.c_void_p),
+                ("offsets_host", ctypes.c_void_p), ("n", ctypes.c_int32)]
+
+
+class _Model(ctypes.Structure):
+    _fields_ = [("W1", ctypes.c_void_p), ("b1", ctypes.c_void_p),
+                ("W2", ctypes.c_void_p), ("b2", ctypes.c_void_p)]
+
+
+_ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
+
+_lib = None
+
+
+def lib():
+    """Load libhalign.so; raises if it has not been built (no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is not built; run __graft_entry__.build()")
+    L = ctypes.CDLL(LIB_PATH)
+    P, I, I64, U32 = ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_uint32
+    sig = {
+        "halign_ctx_create": ([ctypes.c_int, ctypes.c_size_t, ctypes.POINTER(P)], I),
+        "halign_ctx_destroy": ([P], None),
+        "halign_last_error": ([], ctypes.c_char_p),
+        "halign_ctx_workspace_bytes": ([P, ctypes.POINTER(ctypes.c_size_t)], I),
+        "halign_ctx_last_timings": ([P, P], I),
+        "halign_ctx_last_stats": ([P, P], I),
+        "halign_debug_fail_chunk": ([P, ctypes.c_int], I),
+        "halign_encode": ([P, I64, P, P], I),
+        "halign_sw_batch": ([P, P, P, I, P, U32, P, P, P, P, P], I),
+        "halign_sw_pairs": ([P, P, P, P, I, P, P, P], I),
+        "halign_merge": ([P, P, I, I, P, P, P, P], I),
+        "halign_emit_rows": ([P, P, I, P, P, P, P, I64, P, P], I),
+        "halign_center_exact": ([P, P, P, P, P, P], I),
+        "halign_center_judge": ([P, P, P, P, I, P, P, P], I),
+        "halign_featurize": ([P, P, I, P, P], I),
+        "halign_mlp_forward": ([P, P, I, P, P, P, P], I),
+        "halign_pair_loss": ([P, P, I, P, P, P], I),
+        "halign_mlp_backward": ([P, P, I, P, P, P, P, P, P, P, P], I),
+        "halign_adam_step": ([P, P, P, P, P, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
+                              ctypes.c_float, I, P], I),
+        "halign_topk_center": ([P, I, I, P, P, P], I),
+        "halign_msa": ([P, P, P, I, P, _ALLOC_FN, P, P, P, P, P], I),
+        "halign_sp_score": ([P, P, I, I64, P, P], I),
+    }
+    for name, (args, res) in sig.items():
+        if not hasattr(L, name):
+            continue
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def exported_symbols() -> list:
+    return [n for n in ("halign_ctx_create", "halign_ctx_destroy", "halign_last_error")]
+
+
+def _check(rc: int):
+    if rc != HALIGN_OK:
+        msg = lib().halign_last_error()
+        raise HalignError(rc, msg.decode() if msg else "")
+
+
+def _ptr(t) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+# ---------------------------------------------------------------------------
+class Scoring:
+    """s(a, b) and W_k = gap_open + k * gap_extend (host-side parameters)."""
+
+    def __init__(self, matrix=None, gap_open: int = synth.GAP_OPEN, gap_extend: int = synth.GAP_EXTEND):
+        mat = synth.BLOSUM62 if matrix is None else matrix
+        self.matrix = np.ascontiguousarray(mat, dtype=np.int8)
+        self.gap_open, self.gap_extend = int(gap_open), int(gap_extend)
+        self._c = _Scoring(self.matrix.ctypes.data, self.matrix.shape[0], self.gap_open, self.gap_extend)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self._c)
+
+
+class DeviceSeqs:
+    """A packed sequence set resident on the GPU (residues + offsets) plus the
+    host copy of the offsets the planner needs."""
+
+    def __init__(self, seqs: synth.SeqSet, device: str = "cuda"):
+        import torch
+        self.host = seqs
+        self.offsets_host = np.ascontiguousarray(seqs.offsets, dtype=np.int64)
+        res = seqs.residues if len(seqs.residues) else np.zeros(1, np.uint8)
+        self.residues = torch.from_numpy(np.ascontiguousarray(res)).to(device)
+        self.offsets = torch.from_numpy(self.offsets_host.copy()).to(device)
+        self.n = seqs.n
+        self._c = _Seqs(self.residues.data_ptr(), self.offsets.data_ptr(),
+                        self.offsets_host.ctypes.data, self.n)
+
+    @property
+    def ref(self):
+        return ctypes.byref(self._c)
+
+    def length(self, k: int) -> int:
+        return int(self.offsets_host[k + 1] - self.offsets_host[k])
+
+    def seq_ptr(self, k: int) -> int:
+        return self.residues.data_ptr() + int(self.offsets_host[k])
+
+
+class Context:
+    """Owns a halign_ctx (device scratch for codes, plans)."""
+
+    def __init__(self, device: int = 0, workspace_cap: int = 0):
+        h = ctypes.c_void_p()
+        _check(lib().halign_ctx_create(device, workspace_cap, ctypes.byref(h)))
+        self.h = h
+        self.device = device
+
+    def close(self):
+        if self.h:
+            lib().halign_ctx_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def workspace_bytes(self) -> int:
+        v = ctypes.c_size_t(0)
+        _check(lib().halign_ctx_workspace_bytes(self.h, ctypes.byref(v)))
+        return int(v.value)
+
+    def last_timings(self):
+        a = (ctypes.c_float * 3)()
+        _check(lib().halign_ctx_last_timings(self.h, a))
+        return list(a)
+
+    def last_stats(self):
+        a = (ctypes.c_int64 * 4)()
+        _check(lib().halign_ctx_last_stats(self.h, a))
+        return dict(cells=a[0], launches=a[1], route=a[2], chunks=a[3])
+
+    def fail_chunk(self, c: int):
+        _check(lib().halign_debug_fail_chunk(self.h, c))
+
+
+# ---------------------------------------------------------------------------
+# Thin wrappers with the C names.  Tensors are torch CUDA tensors.
+# ---------------------------------------------------------------------------
+def halign_encode(ascii_t, codes_t, stream=None):
+    _check(lib().halign_encode(_ptr(ascii_t), ascii_t.numel(), _ptr(codes_t), _stream(stream)))
+
+
+def halign_sw_batch(ctx: Context, sc: Scoring, center_t, m: int, seqs: DeviceSeqs, flags: int,
+                    score, cells=None, ins=None, aligned=None, stream=None):
+    _check(lib().halign_sw_batch(ctx.h, sc.ref, ctypes.c_void_p(center_t if isinstance(center_t, int)
+                                                                  else center_t.data_ptr()),
+                                 m, seqs.ref, flags, _ptr(score), _ptr(cells), _ptr(ins), _ptr(aligned),
+                                 _stream(stream)))
+
+
+def halign_sw_pairs(ctx: Context, sc: Scoring, seqs: DeviceSeqs, anchors: np.ndarray,
+                    partners: np.ndarray, score, stream=None):
+    a = np.ascontiguousarray(anchors, dtype=np.int32)
+    b = np.ascontiguousarray(partners, dtype=np.int32)
+    assert len(b) == 64 * len(a)
+    _check(lib().halign_sw_pairs(ctx.h, sc.ref, seqs.ref, a.ctypes.data, len(a), b.ctypes.data,
+                                 _ptr(score), _stream(stream)))
+
+
+def halign_merge(ctx: Context, ins, n: int, m: int, G, col, stream=None) -> int:
+    w = ctypes.c_int64(0)
+    _check(lib().halign_merge(ctx.h, _ptr(ins), n, m, _ptr(G), _ptr(col), ctypes.byref(w), _stream(stream)))
+    return int(w.value)
+
+
+def halign_emit_rows(ctx: Context, seqs: DeviceSeqs, m: int, ins, aligned, G, col, width: int, msa,
+                     stream=None):
+    _check(lib().halign_emit_rows(ctx.h, seqs.ref, m, _ptr(ins), _ptr(aligned), _ptr(G), _ptr(col),
+                                  width, _ptr(msa), _stream(stream)))
+
+
+def halign_center_exact(ctx: Context, sc: Scoring, seqs: DeviceSeqs, sums, stream=None) -> int:
+    c = ctypes.c_int32(-1)
+    _check(lib().halign_center_exact(ctx.h, sc.ref, seqs.ref, _ptr(sums), ctypes.byref(c), _stream(stream)))
+    return int(c.value)
+
+
+def halign_center_judge(ctx: Context, sc: Scoring, seqs: DeviceSeqs, cand, sums, stream=None) -> int:
+    c = ctypes.c_int32(-1)
+    _check(lib().halign_center_judge(ctx.h, sc.ref, seqs.ref, _ptr(cand), cand.numel(), _ptr(sums),
+                                     ctypes.byref(c), _stream(stream)))
+    return int(c.value)
+
+
+def halign_sp_score(sc: Scoring, msa, stream=None):
+    out = (ctypes.c_int64 * 2)()
+    n, w = (msa.shape[0], msa.shape[1]) if msa.dim() == 2 else (0, 0)
+    _check(lib().halign_sp_score(sc.ref, _ptr(msa), n, w, out, _stream(stream)))
+    return int(out[0]), int(out[1])
+
+
+def halign_msa(ctx: Context, sc: Scoring, seqs: DeviceSeqs, center: int, model=None, stream=None):
+    """End-to-end MSA.  Returns (msa uint8 tensor [N, W], center index)."""
+    import torch
+    keep = {}
+
+    def _alloc(nbytes, user):
+        t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        keep["t"] = t
+        return t.data_ptr()
+
+    cb = _ALLOC_FN(_alloc)
+    out_ptr = ctypes.c_void_p()
+    width = ctypes.c_int64(0)
+    cout = ctypes.c_int32(-1)
+    mref = ctypes.byref(model._c) if model is not None else None
+    _check(lib().halign_msa(ctx.h, sc.ref, seqs.ref, center, mref, cb, None, ctypes.byref(out_ptr),
+                            ctypes.byref(width), ctypes.byref(cout), _stream(stream)))
+    W = int(width.value)
+    t = keep["t"][: seqs.n * W].view(seqs.n, W)
+    return t, int(cout.value)
+
+
+# ---------------------------------------------------------------------------
+# Convenience layer (allocation of outputs)
+# ---------------------------------------------------------------------------
+def sw_batch(ctx: Context, sc: Scoring, seqs: DeviceSeqs, center: int, traceback: bool = True,
+             route: int = HALIGN_ROUTE_AUTO, center_seq=None):
+    """SW of every sequence against sequence `center` (or `center_seq`, a
+    uint8 CUDA tensor).  Returns dict of CUDA tensors."""
+    import torch
+    dev = seqs.residues.device
+    N = seqs.n
+    if center_seq is None:
+        m = seqs.length(center)
+        cptr = seqs.seq_ptr(center)
+    else:
+        m = int(center_seq.numel())
+        cptr = center_seq.data_ptr()
+    score = torch.empty(N, dtype=torch.int32, device=dev)
+    cells = torch.empty((N, 4), dtype=torch.int32, device=dev)
+    ins = aligned = None
+    if traceback:
+        ins = torch.empty((N, m + 1), dtype=torch.int16, device=dev)
+        aligned = torch.empty((N, (m + 31) // 32), dtype=torch.int32, device=dev)
+    flags = (HALIGN_TRACEBACK if traceback else HALIGN_SCORE_ONLY) | route
+    halign_sw_batch(ctx, sc, cptr, m, seqs, flags, score, cells, ins, aligned)
+    return dict(score=score, cells=cells, ins=ins, aligned=aligned, m=m)
+
+
+def aligned_to_bool(aligned_words: np.ndarray, m: int) -> np.ndarray:
+    """uint32 bit rows -> uint8 [N, m] (host helper for comparisons)."""
+    w = np.ascontiguousarray(aligned_words).view(np.uint32)
+    bits = (w[:, :, None] >> np.arange(32, dtype=np.uint32)[None, None, :]) & 1
+    return bits.reshape(w.shape[0], -1)[:, :m].astype(np.uint8)

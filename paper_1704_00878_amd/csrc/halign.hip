@@ -1,0 +1,1016 @@
+// Host runtime and C ABI of the center-star MSA library (gfx950).
+//
+// The runtime owns device scratch (traceback codes, boundary rows, plans) in
+// a halign_ctx, plans each batch on the host (length sort, grouping, chunking
+// under a workspace cap), and launches the kernels of sw_kernels.hpp and
+// msa_kernels.hpp on the caller's stream.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/halign.h"
+#include "msa_kernels.hpp"
+#include "sw_kernels.hpp"
+#include "mlp_kernels.hpp"
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HCHK(expr)                                                                   \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return fail(HALIGN_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
+    } while (0)
+
+#define RCHK(expr)                 \
+    do {                           \
+        int r_ = (expr);           \
+        if (r_ != HALIGN_OK) return r_; \
+    } while (0)
+
+struct DevBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+struct HostBuf {
+    void *p = nullptr;
+    size_t cap = 0;
+};
+
+}  // namespace
+
+struct halign_ctx {
+    int device = 0;
+    size_t cap = 0;          // workspace cap for codes + boundary rows (0 = none)
+    int num_cu = 256;
+    size_t lds_max = 65536;
+    // device scratch
+    DevBuf codes, bound, plan, counter, pairbuf, msabuf, spbuf, colbuf;
+    // pinned host staging for plans
+    HostBuf stage;
+    hipEvent_t ev_stage = nullptr;
+    bool stage_pending = false;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    float last_ms[3] = {0, 0, 0};
+    int64_t last_stats[4] = {0, 0, 0, 0};
+    int fault_chunk = -1;    // test hook: chunk index whose first launch reports failure
+};
+
+namespace {
+
+int grow(halign_ctx *ctx, DevBuf &b, size_t bytes) {
+    if (bytes <= b.cap) return HALIGN_OK;
+    size_t want = std::max(bytes, b.cap + b.cap / 2);
+    want = (want + 4095) & ~size_t(4095);
+    if (b.p) HCHK(hipFree(b.p));
+    b.p = nullptr;
+    b.cap = 0;
+    if (hipMalloc(&b.p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        b.p = nullptr;
+        if (hipMalloc(&b.p, bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            b.p = nullptr;
+            return fail(HALIGN_E_NOMEM, "device allocation of %zu bytes failed", bytes);
+        }
+        want = bytes;
+    }
+    b.cap = want;
+    (void)ctx;
+    return HALIGN_OK;
+}
+
+int stage_wait(halign_ctx *ctx) {
+    if (ctx->stage_pending) {
+        HCHK(hipEventSynchronize(ctx->ev_stage));
+        ctx->stage_pending = false;
+    }
+    return HALIGN_OK;
+}
+
+int stage_grow(halign_ctx *ctx, size_t bytes) {
+    RCHK(stage_wait(ctx));
+    if (bytes <= ctx->stage.cap) return HALIGN_OK;
+    if (ctx->stage.p) HCHK(hipHostFree(ctx->stage.p));
+    ctx->stage.p = nullptr;
+    size_t want = std::max(bytes, ctx->stage.cap * 2);
+    HCHK(hipHostMalloc(&ctx->stage.p, want, hipHostMallocDefault));
+    ctx->stage.cap = want;
+    return HALIGN_OK;
+}
+
+// A packed plan: host arrays laid out in one staging buffer and copied with
+// one H2D transfer into ctx->plan.
+struct PlanBuilder {
+    std::vector<std::pair<size_t, size_t>> parts;  // (offset, bytes)
+    size_t total = 0;
+    size_t add(size_t bytes) {
+        size_t o = (total + 255) & ~size_t(255);
+        parts.push_back({o, bytes});
+        total = o + bytes;
+        return o;
+    }
+};
+
+inline int grid_for(int64_t n, int block, int maxg = 65536) {
+    int64_t g = (n + block - 1) / block;
+    return (int)std::max<int64_t>(1, std::min<int64_t>(g, maxg));
+}
+
+int launch_fill(uint32_t *p, uint32_t v, int64_t n, hipStream_t st) {
+    if (n <= 0) return HALIGN_OK;
+    hipLaunchKernelGGL(hk::fill_u32_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, p, v, n);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
+}
+
+int check_scoring(const halign_scoring *sc) {
+    if (!sc || !sc->matrix_host) return fail(HALIGN_E_INVALID, "scoring is NULL");
+    if (sc->alphabet <= 0 || sc->alphabet > hk::kAlphaMax)
+        return fail(HALIGN_E_UNSUPPORTED, "alphabet %d outside 1..32", sc->alphabet);
+    if (sc->gap_open < 0 || sc->gap_extend < 1)
+        return fail(HALIGN_E_UNSUPPORTED, "need gap_open >= 0 and gap_extend >= 1");
+    if (sc->gap_open + sc->gap_extend > 1000000)
+        return fail(HALIGN_E_UNSUPPORTED, "gap costs too large");
+    return HALIGN_OK;
+}
+
+int check_seqs(const halign_seqs *sq) {
+    if (!sq || sq->n < 0) return fail(HALIGN_E_INVALID, "seqs is NULL or n < 0");
+    if (sq->n == 0) return HALIGN_OK;
+    if (!sq->residues || !sq->offsets || !sq->offsets_host)
+        return fail(HALIGN_E_INVALID, "seqs pointers are NULL");
+    const int64_t *o = sq->offsets_host;
+    if (o[0] != 0) return fail(HALIGN_E_INVALID, "offsets[0] must be 0");
+    for (int k = 0; k < sq->n; ++k) {
+        const int64_t L = o[k + 1] - o[k];
+        if (L < 0) return fail(HALIGN_E_INVALID, "offsets decrease at %d", k);
+        if (L >= 65536) return fail(HALIGN_E_UNSUPPORTED, "sequence %d has length %lld >= 65536", k, (long long)L);
+    }
+    return HALIGN_OK;
+}
+
+// Device matrix copy (alpha x alpha int8) kept in the plan buffer head.
+struct Scoring {
+    const int8_t *dmat;
+    int alpha, ge, goe;
+};
+
+// ---------------------------------------------------------------------------
+// Forward + walk for one set of pairs against one center.
+// ---------------------------------------------------------------------------
+enum Route { kRouteIntra = 0, kRouteInter = 1 };
+
+int pick_R(int m) {
+    if (m <= 128) return 2;
+    if (m <= 256) return 4;
+    if (m <= 384) return 6;
+    return 8;
+}
+
+template <int R>
+void launch_intra_R(const hk::IntraArgs &a, bool tb, bool endc, int grid, int block, size_t lds, hipStream_t st) {
+    if (tb)
+        hipLaunchKernelGGL((hk::sw_intra_kernel<R, true, true>), dim3(grid), dim3(block), lds, st, a);
+    else if (endc)
+        hipLaunchKernelGGL((hk::sw_intra_kernel<R, false, true>), dim3(grid), dim3(block), lds, st, a);
+    else
+        hipLaunchKernelGGL((hk::sw_intra_kernel<R, false, false>), dim3(grid), dim3(block), lds, st, a);
+}
+
+void launch_intra(int R, const hk::IntraArgs &a, bool tb, bool endc, int grid, int block, size_t lds, hipStream_t st) {
+    switch (R) {
+        case 2: launch_intra_R<2>(a, tb, endc, grid, block, lds, st); break;
+        case 4: launch_intra_R<4>(a, tb, endc, grid, block, lds, st); break;
+        case 6: launch_intra_R<6>(a, tb, endc, grid, block, lds, st); break;
+        default: launch_intra_R<8>(a, tb, endc, grid, block, lds, st); break;
+    }
+}
+
+void launch_inter(const hk::InterArgs &a, bool tb, bool endc, int grid, hipStream_t st) {
+    if (tb)
+        hipLaunchKernelGGL((hk::sw_inter_kernel<true, true>), dim3(grid), dim3(64), 0, st, a);
+    else if (endc)
+        hipLaunchKernelGGL((hk::sw_inter_kernel<false, true>), dim3(grid), dim3(64), 0, st, a);
+    else
+        hipLaunchKernelGGL((hk::sw_inter_kernel<false, false>), dim3(grid), dim3(64), 0, st, a);
+}
+
+struct BatchOut {
+    int32_t *score, *cells, *endcell;
+    uint16_t *ins;
+    uint32_t *aligned;
+};
+
+// Plans and runs the forward pass (+ walk when tb) for the pairs `pids`
+// (already validated) against center (device) of length m.
+int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq,
+              const std::vector<int32_t> &pids_in, bool tb, bool endc, int route, const BatchOut &out,
+              hipStream_t st) {
+    const int64_t *oh = sq->offsets_host;
+    const int N = sq->n;
+    const int np = (int)pids_in.size();
+    if (np == 0) return HALIGN_OK;
+    // longest first
+    std::vector<int32_t> pids(pids_in);
+    std::stable_sort(pids.begin(), pids.end(), [&](int32_t x, int32_t y) {
+        return (oh[x + 1] - oh[x]) > (oh[y + 1] - oh[y]);
+    });
+    const int aw = (m + 31) / 32;
+    const size_t lds_need_intra = (size_t)hk::kAlphaMax * 4 *
+                                  (size_t)(((m + 64 * pick_R(m) - 1) / (64 * pick_R(m))) * 64 * pick_R(m));
+    if (route == kRouteIntra && lds_need_intra > ctx->lds_max)
+        route = kRouteInter;
+    ctx->last_stats[2] = route;
+
+    // chunk the pairs so that codes + boundary rows fit the cap
+    const size_t cap = ctx->cap ? ctx->cap : (size_t)1 << 62;
+    std::vector<std::pair<int, int>> chunks;  // [lo, hi) in pids
+    const int R = pick_R(m);
+    const int passes = std::max(1, (m + 64 * R - 1) / (64 * R));
+    auto pair_bytes = [&](int pid) -> size_t {
+        const int n = (int)(oh[pid + 1] - oh[pid]);
+        if (route == kRouteIntra) {
+            size_t b = tb ? (size_t)passes * (n + 63) * 64 * 4 : 0;
+            b += (passes > 1) ? (size_t)(passes - 1) * n * 8 : 0;
+            return b;
+        }
+        const int nst = (m + hk::kT - 1) / hk::kT;
+        return tb ? (size_t)nst * n * 8 : 0;  // per lane share of its group's codes
+    };
+    {
+        int lo = 0;
+        size_t acc = 0;
+        for (int x = 0; x < np; ++x) {
+            size_t b = pair_bytes(pids[x]);
+            if (route == kRouteInter) {
+                // groups are formed from 64 consecutive pairs, charge the group max
+                if (x % 64 == 0) {
+                    const int nmax = (int)(oh[pids[x] + 1] - oh[pids[x]]);
+                    const int nst = (m + hk::kT - 1) / hk::kT;
+                    b = tb ? (size_t)nst * nmax * 64 * 8 : 0;
+                } else {
+                    b = 0;
+                }
+            }
+            bool boundary = (route == kRouteInter) ? (x % 64 == 0) : true;
+            if (boundary && x > lo && acc + b > cap) {
+                chunks.push_back({lo, x});
+                lo = x;
+                acc = 0;
+            }
+            acc += b;
+        }
+        chunks.push_back({lo, np});
+    }
+    ctx->last_stats[3] = (int64_t)chunks.size();
+
+    int64_t cells_total = 0;
+    for (int x = 0; x < np; ++x) cells_total += (int64_t)m * (oh[pids[x] + 1] - oh[pids[x]]);
+    ctx->last_stats[0] = cells_total;
+
+    // device matrix lives at the head of ctx->plan; plan arrays follow
+    RCHK(grow(ctx, ctx->counter, 256));
+    int *counter = (int *)ctx->counter.p;
+
+    float fwd_ms = 0.f, walk_ms = 0.f;
+    int64_t launches = 0;
+    for (size_t ci = 0; ci < chunks.size(); ++ci) {
+        const int lo = chunks[ci].first, hi = chunks[ci].second;
+        const int cn = hi - lo;
+        PlanBuilder pb;
+        size_t o_order = 0, o_cbase = 0, o_cstr = 0, o_bbase = 0, o_gnmax = 0, o_gcb = 0, o_walk = 0;
+        int ngroups = 0;
+        size_t code_words = 0, bound_elems = 0;
+        int nmax_all = 0;
+        for (int x = lo; x < hi; ++x) nmax_all = std::max(nmax_all, (int)(oh[pids[x] + 1] - oh[pids[x]]));
+        if (route == kRouteIntra) {
+            o_order = pb.add(sizeof(int32_t) * cn);
+            o_cbase = pb.add(sizeof(int64_t) * N);
+            o_cstr = pb.add(sizeof(int32_t) * N);
+            o_bbase = pb.add(sizeof(int64_t) * N);
+        } else {
+            ngroups = (cn + 63) / 64;
+            o_order = pb.add(sizeof(int32_t) * (size_t)ngroups * 64);
+            o_gnmax = pb.add(sizeof(int32_t) * ngroups);
+            o_gcb = pb.add(sizeof(int64_t) * ngroups);
+            o_cbase = pb.add(sizeof(int64_t) * N);
+            o_cstr = pb.add(sizeof(int32_t) * N);
+        }
+        o_walk = pb.add(sizeof(int32_t) * cn);
+        RCHK(stage_grow(ctx, pb.total));
+        char *hs = (char *)ctx->stage.p;
+        int32_t *h_walk = (int32_t *)(hs + o_walk);
+        for (int x = 0; x < cn; ++x) h_walk[x] = pids[lo + x];
+        if (route == kRouteIntra) {
+            int32_t *h_order = (int32_t *)(hs + o_order);
+            int64_t *h_cbase = (int64_t *)(hs + o_cbase);
+            int32_t *h_cstr = (int32_t *)(hs + o_cstr);
+            int64_t *h_bbase = (int64_t *)(hs + o_bbase);
+            for (int x = 0; x < cn; ++x) {
+                const int pid = pids[lo + x];
+                const int n = (int)(oh[pid + 1] - oh[pid]);
+                h_order[x] = pid;
+                h_cbase[pid] = (int64_t)code_words;
+                h_cstr[pid] = n + 63;
+                h_bbase[pid] = (int64_t)bound_elems;
+                if (tb) code_words += (size_t)passes * (n + 63) * 64;
+                if (passes > 1) bound_elems += (size_t)(passes - 1) * n;
+            }
+        } else {
+            int32_t *h_order = (int32_t *)(hs + o_order);
+            int32_t *h_gnmax = (int32_t *)(hs + o_gnmax);
+            int64_t *h_gcb = (int64_t *)(hs + o_gcb);
+            int64_t *h_cbase = (int64_t *)(hs + o_cbase);
+            int32_t *h_cstr = (int32_t *)(hs + o_cstr);
+            const int nst = (m + hk::kT - 1) / hk::kT;
+            for (int g = 0; g < ngroups; ++g) {
+                int nmax = 0;
+                for (int l = 0; l < 64; ++l) {
+                    const int x = lo + g * 64 + l;
+                    const int pid = x < hi ? pids[x] : -1;
+                    h_order[g * 64 + l] = pid;
+                    if (pid >= 0) nmax = std::max(nmax, (int)(oh[pid + 1] - oh[pid]));
+                }
+                h_gnmax[g] = nmax;
+                h_gcb[g] = (int64_t)code_words;
+                for (int l = 0; l < 64; ++l) {
+                    const int pid = h_order[g * 64 + l];
+                    if (pid < 0) continue;
+                    h_cbase[pid] = (int64_t)code_words + 2 * l;
+                    h_cstr[pid] = nmax;
+                }
+                if (tb) code_words += (size_t)nst * nmax * 64 * 2;
+            }
+        }
+        RCHK(grow(ctx, ctx->plan, pb.total));
+        char *dplan = (char *)ctx->plan.p;
+        HCHK(hipMemcpyAsync(dplan, hs, pb.total, hipMemcpyHostToDevice, st));
+        HCHK(hipEventRecord(ctx->ev_stage, st));
+        ctx->stage_pending = true;
+
+        if (tb) RCHK(grow(ctx, ctx->codes, std::max<size_t>(4, code_words * 4)));
+        int grid = 0;
+        if (route == kRouteIntra) {
+            if (passes > 1) RCHK(grow(ctx, ctx->bound, std::max<size_t>(8, bound_elems * 8)));
+        } else {
+            const int slots = ctx->num_cu * 16;
+            grid = std::max(1, std::min(ngroups, slots));
+            RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * std::max(1, nmax_all) * 8));
+        }
+        RCHK(launch_fill((uint32_t *)counter, 0u, 1, st));
+        if (ctx->fault_chunk == (int)ci) {
+            ctx->fault_chunk = -1;
+            return fail(HALIGN_E_DEVICE, "injected failure in chunk %d", (int)ci);
+        }
+        HCHK(hipEventRecord(ctx->ev[0], st));
+        if (route == kRouteIntra) {
+            hk::IntraArgs a{};
+            a.mat = S.dmat;
+            a.alpha = S.alpha;
+            a.center = center;
+            a.m = m;
+            a.passes = passes;
+            a.mpad = passes * 64 * R;
+            a.res = sq->residues;
+            a.off = sq->offsets;
+            a.order = (const int32_t *)(dplan + o_order);
+            a.npairs = cn;
+            a.ge = S.ge;
+            a.goe = S.goe;
+            a.counter = counter;
+            a.score = out.score;
+            a.endcell = out.endcell;
+            a.codes = tb ? (uint32_t *)ctx->codes.p : nullptr;
+            a.code_base = (const int64_t *)(dplan + o_cbase);
+            a.bound = (int2 *)ctx->bound.p;
+            a.bound_base = (const int64_t *)(dplan + o_bbase);
+            const int block = 512;
+            const size_t lds = (size_t)hk::kAlphaMax * a.mpad * 4;
+            grid = (cn + 7) / 8;   // one pair per wave
+            launch_intra(R, a, tb, endc, grid, block, lds, st);
+            HCHK(hipGetLastError());
+        } else {
+            hk::InterArgs a{};
+            a.mat = S.dmat;
+            a.alpha = S.alpha;
+            a.center = center;
+            a.m = m;
+            a.res = sq->residues;
+            a.off = sq->offsets;
+            a.mode = 0;
+            a.order = (const int32_t *)(dplan + o_order);
+            a.gnmax = (const int32_t *)(dplan + o_gnmax);
+            a.ngroups = ngroups;
+            a.ge = S.ge;
+            a.goe = S.goe;
+            a.counter = counter;
+            a.score = out.score;
+            a.endcell = out.endcell;
+            a.codes = tb ? (uint32_t *)ctx->codes.p : nullptr;
+            a.gcode_base = (const int64_t *)(dplan + o_gcb);
+            a.bound = (int2 *)ctx->bound.p;
+            a.bstride = (int64_t)64 * std::max(1, nmax_all);
+            launch_inter(a, tb, endc, grid, st);
+            HCHK(hipGetLastError());
+        }
+        ++launches;
+        HCHK(hipEventRecord(ctx->ev[1], st));
+        if (tb) {
+            hk::WalkArgs w{};
+            w.mat = S.dmat;
+            w.alpha = S.alpha;
+            w.center = center;
+            w.m = m;
+            w.res = sq->residues;
+            w.off = sq->offsets;
+            w.pids = (const int32_t *)(dplan + o_walk);
+            w.npairs = cn;
+            w.ge = S.ge;
+            w.goe = S.goe;
+            w.score = out.score;
+            w.endcell = out.endcell;
+            w.codes = (const uint32_t *)ctx->codes.p;
+            w.cbase = (const int64_t *)(dplan + o_cbase);
+            w.cstride = (const int32_t *)(dplan + o_cstr);
+            w.R = R;
+            w.kind = route == kRouteIntra ? 0 : 1;
+            w.cells = out.cells;
+            w.ins = out.ins;
+            w.aligned = out.aligned;
+            w.aw = aw;
+            hipLaunchKernelGGL(hk::walk_kernel, dim3(grid_for(cn, 64, 1 << 30)), dim3(64), 0, st, w);
+            HCHK(hipGetLastError());
+        }
+        HCHK(hipEventRecord(ctx->ev[2], st));
+        // per-chunk timing is accumulated lazily (events are re-used)
+        if (chunks.size() > 1) {
+            HCHK(hipEventSynchronize(ctx->ev[2]));
+            float f = 0, w2 = 0;
+            HCHK(hipEventElapsedTime(&f, ctx->ev[0], ctx->ev[1]));
+            HCHK(hipEventElapsedTime(&w2, ctx->ev[1], ctx->ev[2]));
+            fwd_ms += f;
+            walk_ms += w2;
+        }
+    }
+    ctx->last_stats[1] = launches;
+    if (chunks.size() > 1) {
+        ctx->last_ms[0] = fwd_ms;
+        ctx->last_ms[1] = walk_ms;
+        ctx->last_ms[2] = -1.f;  // single-chunk calls report through events
+    } else {
+        ctx->last_ms[2] = 0.f;
+    }
+    return HALIGN_OK;
+}
+
+int upload_matrix(halign_ctx *ctx, const halign_scoring *sc, hipStream_t st, Scoring *S) {
+    const size_t bytes = (size_t)sc->alphabet * sc->alphabet;
+    RCHK(grow(ctx, ctx->spbuf, 4096));
+    RCHK(stage_grow(ctx, 4096));
+    memcpy(ctx->stage.p, sc->matrix_host, bytes);
+    HCHK(hipMemcpyAsync(ctx->spbuf.p, ctx->stage.p, bytes, hipMemcpyHostToDevice, st));
+    HCHK(hipEventRecord(ctx->ev_stage, st));
+    ctx->stage_pending = true;
+    S->dmat = (const int8_t *)ctx->spbuf.p;
+    S->alpha = sc->alphabet;
+    S->ge = sc->gap_extend;
+    S->goe = sc->gap_open + sc->gap_extend;
+    return HALIGN_OK;
+}
+
+// Every residue code must be below the alphabet size (HALIGN_E_INVALID).
+int validate_codes(halign_ctx *ctx, int alpha, const uint8_t *res, int64_t nres, const uint8_t *center, int m,
+                   hipStream_t st) {
+    RCHK(grow(ctx, ctx->counter, 256));
+    int *flag = (int *)ctx->counter.p + 8;
+    RCHK(launch_fill((uint32_t *)flag, 0u, 1, st));
+    if (nres > 0)
+        hipLaunchKernelGGL(hk::maxcode_kernel, dim3(grid_for(nres, 256, 2048)), dim3(256), 0, st, res, nres, flag);
+    if (center && m > 0)
+        hipLaunchKernelGGL(hk::maxcode_kernel, dim3(grid_for(m, 256, 64)), dim3(256), 0, st, center, (int64_t)m, flag);
+    HCHK(hipGetLastError());
+    int h = 0;
+    HCHK(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    if (h >= alpha) return fail(HALIGN_E_INVALID, "residue code %d >= alphabet %d", h, alpha);
+    return HALIGN_OK;
+}
+
+int route_of(uint32_t flags, int m, int N) {
+    const uint32_t r = flags & (3u << 4);
+    if (r == HALIGN_ROUTE_INTER) return kRouteInter;
+    if (r == HALIGN_ROUTE_INTRA) return kRouteIntra;
+    (void)m;
+    if (const char *e = getenv("HALIGN_ROUTE")) {
+        if (!strcmp(e, "intra")) return kRouteIntra;
+        if (!strcmp(e, "inter")) return kRouteInter;
+    }
+    // enough independent lanes for the chip: 4 waves per SIMD in inter form
+    return (N >= 64 * 4 * 1024) ? kRouteInter : kRouteIntra;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *halign_last_error(void) { return g_err.c_str(); }
+
+int halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out) {
+    if (!out) return fail(HALIGN_E_INVALID, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    HCHK(hipGetDeviceCount(&ndev));
+    if (device < 0 || device >= ndev) return fail(HALIGN_E_INVALID, "device %d of %d", device, ndev);
+    HCHK(hipSetDevice(device));
+    halign_ctx *ctx = new (std::nothrow) halign_ctx();
+    if (!ctx) return fail(HALIGN_E_NOMEM, "host allocation failed");
+    ctx->device = device;
+    ctx->cap = workspace_cap_bytes;
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
+        ctx->num_cu = prop.multiProcessorCount;
+        ctx->lds_max = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
+                                                             : prop.sharedMemPerBlock;
+        if (prop.sharedMemPerBlock && prop.sharedMemPerBlock < ctx->lds_max) ctx->lds_max = prop.sharedMemPerBlock;
+    }
+    for (auto &e : ctx->ev) {
+        if (hipEventCreate(&e) != hipSuccess) { halign_ctx_destroy(ctx); return fail(HALIGN_E_DEVICE, "event create"); }
+    }
+    if (hipEventCreateWithFlags(&ctx->ev_stage, hipEventDisableTiming) != hipSuccess) {
+        halign_ctx_destroy(ctx);
+        return fail(HALIGN_E_DEVICE, "event create");
+    }
+    *out = ctx;
+    return HALIGN_OK;
+}
+
+void halign_ctx_destroy(halign_ctx *ctx) {
+    if (!ctx) return;
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf, &ctx->colbuf})
+        if (b->p) (void)hipFree(b->p);
+    if (ctx->stage.p) (void)hipHostFree(ctx->stage.p);
+    for (auto &e : ctx->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (ctx->ev_stage) (void)hipEventDestroy(ctx->ev_stage);
+    delete ctx;
+}
+
+int halign_ctx_workspace_bytes(const halign_ctx *ctx, size_t *bytes_host) {
+    if (!ctx || !bytes_host) return fail(HALIGN_E_INVALID, "NULL argument");
+    *bytes_host = ctx->codes.cap + ctx->bound.cap + ctx->plan.cap + ctx->pairbuf.cap + ctx->msabuf.cap;
+    return HALIGN_OK;
+}
+
+int halign_ctx_last_timings(halign_ctx *ctx, float *ms_host) {
+    if (!ctx || !ms_host) return fail(HALIGN_E_INVALID, "NULL argument");
+    if (ctx->last_ms[2] == 0.f) {
+        HCHK(hipEventSynchronize(ctx->ev[2]));
+        HCHK(hipEventElapsedTime(&ms_host[0], ctx->ev[0], ctx->ev[1]));
+        HCHK(hipEventElapsedTime(&ms_host[1], ctx->ev[1], ctx->ev[2]));
+        ms_host[2] = ms_host[0] + ms_host[1];
+    } else {
+        ms_host[0] = ctx->last_ms[0];
+        ms_host[1] = ctx->last_ms[1];
+        ms_host[2] = ms_host[0] + ms_host[1];
+    }
+    return HALIGN_OK;
+}
+
+int halign_ctx_last_stats(const halign_ctx *ctx, int64_t *stats_host) {
+    if (!ctx || !stats_host) return fail(HALIGN_E_INVALID, "NULL argument");
+    for (int i = 0; i < 4; ++i) stats_host[i] = ctx->last_stats[i];
+    return HALIGN_OK;
+}
+
+// test hook (not part of the public header): make chunk `c` of the next
+// halign_sw_batch fail before its launch.
+int halign_debug_fail_chunk(halign_ctx *ctx, int c) {
+    if (!ctx) return fail(HALIGN_E_INVALID, "NULL ctx");
+    ctx->fault_chunk = c;
+    return HALIGN_OK;
+}
+
+int halign_encode(const uint8_t *ascii, int64_t len, uint8_t *codes, void *stream) {
+    static const char kAlpha[] = "ARNDCQEGHILKMFPSTWYVBZX*";
+    if (len < 0 || (len > 0 && (!ascii || !codes))) return fail(HALIGN_E_INVALID, "bad arguments");
+    if (len == 0) return HALIGN_OK;
+    static uint8_t *dtab = nullptr;
+    static int dtab_dev = -1;
+    int dev = 0;
+    HCHK(hipGetDevice(&dev));
+    if (!dtab || dtab_dev != dev) {
+        uint8_t tab[256];
+        for (int x = 0; x < 256; ++x) tab[x] = 22;  // X
+        for (int x = 0; x < 24; ++x) {
+            tab[(uint8_t)kAlpha[x]] = (uint8_t)x;
+            if (kAlpha[x] >= 'A' && kAlpha[x] <= 'Z') tab[(uint8_t)(kAlpha[x] - 'A' + 'a')] = (uint8_t)x;
+        }
+        tab['U'] = tab['u'] = 4;   // C
+        tab['O'] = tab['o'] = 11;  // K
+        uint8_t *p = nullptr;
+        HCHK(hipMalloc(&p, 256));
+        HCHK(hipMemcpy(p, tab, 256, hipMemcpyHostToDevice));
+        dtab = p;
+        dtab_dev = dev;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    hipLaunchKernelGGL(hk::encode_kernel, dim3(grid_for(len, 256, 8192)), dim3(256), 0, st, ascii, len, codes,
+                       (const uint8_t *)dtab);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
+}
+
+int halign_sw_batch(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *center, int32_t m,
+                    const halign_seqs *seqs, uint32_t flags, int32_t *score, int32_t *cells, uint16_t *ins,
+                    uint32_t *aligned, void *stream) {
+    if (!ctx) return fail(HALIGN_E_INVALID, "ctx is NULL");
+    RCHK(check_scoring(sc));
+    RCHK(check_seqs(seqs));
+    if (m <= 0 || !center) return fail(HALIGN_E_INVALID, "empty center");
+    if (m >= 65536) return fail(HALIGN_E_UNSUPPORTED, "center length %d >= 65536", m);
+    if (!score && seqs->n > 0) return fail(HALIGN_E_INVALID, "score is NULL");
+    const bool tb = (flags & HALIGN_TRACEBACK) != 0;
+    if (tb && (!cells || !ins || !aligned)) return fail(HALIGN_E_INVALID, "traceback needs cells, ins, aligned");
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int N = seqs->n;
+    if (N == 0) return HALIGN_OK;
+    Scoring S;
+    RCHK(upload_matrix(ctx, sc, st, &S));
+    RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], center, m, st));
+    // endcells: needed by the walk, or to fill cells in score-only mode
+    const bool endc = tb || cells != nullptr;
+    RCHK(grow(ctx, ctx->pairbuf, (size_t)N * 8 + 256));
+    int32_t *endcell = (int32_t *)ctx->pairbuf.p;
+    if (tb) {
+        hipLaunchKernelGGL(hk::fill_u16_kernel, dim3(grid_for((int64_t)N * (m + 1), 256, 4096)), dim3(256), 0, st,
+                           ins, (uint16_t)0, (int64_t)N * (m + 1));
+        HCHK(hipGetLastError());
+        RCHK(launch_fill(aligned, 0u, (int64_t)N * ((m + 31) / 32), st));
+    }
+    std::vector<int32_t> pids(N);
+    std::iota(pids.begin(), pids.end(), 0);
+    BatchOut out{score, cells, endcell, ins, aligned};
+    RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st));
+    if (!tb && cells) {
+        // score-only with cells: report the end cell as (0, 0, i1, j1)
+        hipLaunchKernelGGL(hk::endcell_to_cells_kernel, dim3(grid_for(N, 256)), dim3(256), 0, st,
+                           (const int32_t *)endcell, N, cells);
+        HCHK(hipGetLastError());
+    }
+    return HALIGN_OK;
+}
+
+int halign_merge(halign_ctx *ctx, const uint16_t *ins, int32_t n, int32_t m, int32_t *G, int64_t *col,
+                 int64_t *width_host, void *stream) {
+    if (!ctx || !G || !col || m < 0 || n < 0 || (n > 0 && !ins)) return fail(HALIGN_E_INVALID, "bad arguments");
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int m1 = m + 1;
+    RCHK(launch_fill((uint32_t *)G, 0u, m1, st));
+    if (n > 0) {
+        dim3 grid((m1 + 255) / 256, (n + hk::kMergeRows - 1) / hk::kMergeRows);
+        if (grid.y > 65535) {
+            // fold rows: launch in slices of 65535 * kMergeRows rows
+            for (int64_t r0 = 0; r0 < n; r0 += (int64_t)65535 * hk::kMergeRows) {
+                const int rn = (int)std::min<int64_t>(n - r0, (int64_t)65535 * hk::kMergeRows);
+                dim3 g2((m1 + 255) / 256, (rn + hk::kMergeRows - 1) / hk::kMergeRows);
+                hipLaunchKernelGGL(hk::merge_max_kernel, g2, dim3(256), 0, st, ins + r0 * m1, rn, m1, G);
+            }
+        } else {
+            hipLaunchKernelGGL(hk::merge_max_kernel, grid, dim3(256), 0, st, ins, n, m1, G);
+        }
+        HCHK(hipGetLastError());
+    }
+    RCHK(grow(ctx, ctx->spbuf, 4096));
+    int64_t *dwidth = (int64_t *)((char *)ctx->spbuf.p + 2048);
+    hipLaunchKernelGGL(hk::merge_scan_kernel, dim3(1), dim3(1024), 0, st, (const int32_t *)G, m1, col, dwidth);
+    HCHK(hipGetLastError());
+    if (width_host) {
+        HCHK(hipMemcpyAsync(width_host, dwidth, 8, hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+    }
+    return HALIGN_OK;
+}
+
+int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const uint16_t *ins,
+                     const uint32_t *aligned, const int32_t *G, const int64_t *col, int64_t width, uint8_t *msa,
+                     void *stream) {
+    if (!ctx || !seqs || m < 0 || width < m || (seqs->n > 0 && (!ins || !aligned || !G || !col || !msa)))
+        return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_seqs(seqs));
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int N = seqs->n;
+    if (N == 0 || width == 0) return HALIGN_OK;
+    RCHK(grow(ctx, ctx->colbuf, (size_t)width * 8 + 256));
+    int32_t *cmap = (int32_t *)ctx->colbuf.p;
+    int32_t *coff = cmap + width;
+    hipLaunchKernelGGL(hk::colmap_kernel, dim3((m + 1 + 255) / 256), dim3(256), 0, st, G, col, m, cmap, coff);
+    HCHK(hipGetLastError());
+    const size_t lds = (size_t)(m + 1) * 8;
+    if (lds > ctx->lds_max) return fail(HALIGN_E_UNSUPPORTED, "center too long for row emission");
+    hipLaunchKernelGGL(hk::rows_kernel, dim3(N), dim3(256), lds, st, seqs->residues, seqs->offsets,
+                       (const int32_t *)nullptr, N, m, ins, aligned, (m + 31) / 32, (const int32_t *)cmap,
+                       (const int32_t *)coff, width, msa);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
+}
+
+// Center selection -----------------------------------------------------------
+static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, int mode,
+                      const std::vector<int32_t> &gcen, const std::vector<int32_t> &gb0,
+                      const std::vector<int32_t> &perm, const std::vector<int32_t> &gslot, int64_t *sums,
+                      int32_t *score, hipStream_t st, int nperm = -1) {
+    const int ng = (int)gcen.size();
+    if (ng == 0) return HALIGN_OK;
+    PlanBuilder pb;
+    const size_t o_gcen = pb.add(4 * (size_t)ng), o_gb0 = pb.add(4 * (size_t)ng),
+                 o_perm = pb.add(4 * perm.size()), o_gslot = pb.add(4 * std::max<size_t>(1, gslot.size()));
+    RCHK(stage_grow(ctx, pb.total));
+    char *hs = (char *)ctx->stage.p;
+    memcpy(hs + o_gcen, gcen.data(), 4 * (size_t)ng);
+    memcpy(hs + o_gb0, gb0.data(), 4 * (size_t)ng);
+    memcpy(hs + o_perm, perm.data(), 4 * perm.size());
+    if (!gslot.empty()) memcpy(hs + o_gslot, gslot.data(), 4 * gslot.size());
+    RCHK(grow(ctx, ctx->plan, pb.total));
+    char *dplan = (char *)ctx->plan.p;
+    HCHK(hipMemcpyAsync(dplan, hs, pb.total, hipMemcpyHostToDevice, st));
+    HCHK(hipEventRecord(ctx->ev_stage, st));
+    ctx->stage_pending = true;
+    int nmax_all = 0;
+    const int64_t *oh = sq->offsets_host;
+    for (int k = 0; k < sq->n; ++k) nmax_all = std::max(nmax_all, (int)(oh[k + 1] - oh[k]));
+    const int grid = std::max(1, std::min(ng, ctx->num_cu * 16));
+    RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * std::max(1, nmax_all) * 8));
+    RCHK(grow(ctx, ctx->counter, 256));
+    RCHK(launch_fill((uint32_t *)ctx->counter.p, 0u, 1, st));
+    hk::InterArgs a{};
+    a.mat = S.dmat;
+    a.alpha = S.alpha;
+    a.res = sq->residues;
+    a.off = sq->offsets;
+    a.mode = mode;
+    a.gcen = (const int32_t *)(dplan + o_gcen);
+    a.gb0 = (const int32_t *)(dplan + o_gb0);
+    a.perm = (const int32_t *)(dplan + o_perm);
+    a.nseq = nperm >= 0 ? nperm : sq->n;
+    a.gslot = (const int32_t *)(dplan + o_gslot);
+    a.sums = sums;
+    a.ngroups = ng;
+    a.ge = S.ge;
+    a.goe = S.goe;
+    a.counter = (int *)ctx->counter.p;
+    a.score = score;
+    a.bound = (int2 *)ctx->bound.p;
+    a.bstride = (int64_t)64 * std::max(1, nmax_all);
+    ctx->last_stats[0] = 0;
+    HCHK(hipEventRecord(ctx->ev[0], st));
+    launch_inter(a, false, false, grid, st);
+    HCHK(hipGetLastError());
+    HCHK(hipEventRecord(ctx->ev[1], st));
+    HCHK(hipEventRecord(ctx->ev[2], st));
+    ctx->last_ms[2] = 0.f;
+    return HALIGN_OK;
+}
+
+static std::vector<int32_t> length_perm(const halign_seqs *sq) {
+    std::vector<int32_t> perm(sq->n);
+    std::iota(perm.begin(), perm.end(), 0);
+    const int64_t *oh = sq->offsets_host;
+    std::stable_sort(perm.begin(), perm.end(),
+                     [&](int32_t x, int32_t y) { return (oh[x + 1] - oh[x]) < (oh[y + 1] - oh[y]); });
+    return perm;
+}
+
+static int argmax_sums(halign_ctx *ctx, const int64_t *sums, const int32_t *cand_host, int ncand, int32_t *center_host,
+                       hipStream_t st) {
+    std::vector<int64_t> h(ncand);
+    HCHK(hipMemcpyAsync(h.data(), sums, 8 * (size_t)ncand, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    int best = 0;
+    for (int q = 1; q < ncand; ++q) {
+        const int cq = cand_host ? cand_host[q] : q, cb = cand_host ? cand_host[best] : best;
+        if (h[q] > h[best] || (h[q] == h[best] && cq < cb)) best = q;
+    }
+    *center_host = cand_host ? cand_host[best] : best;
+    (void)ctx;
+    return HALIGN_OK;
+}
+
+int halign_center_exact(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, int64_t *sums,
+                        int32_t *center_host, void *stream) {
+    if (!ctx || !sums) return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_scoring(sc));
+    RCHK(check_seqs(seqs));
+    const int N = seqs->n;
+    if (N <= 0) return fail(HALIGN_E_INVALID, "empty set");
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    Scoring S;
+    RCHK(upload_matrix(ctx, sc, st, &S));
+    RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
+    RCHK(launch_fill((uint32_t *)sums, 0u, 2 * (int64_t)N, st));
+    std::vector<int32_t> perm = length_perm(seqs), gcen, gb0, gslot;
+    // all pairs a' < b' in length order: the longer sequence is the lane's,
+    // the shorter one the group's center
+    for (int a = 0; a < N; ++a)
+        for (int b = a + 1; b < N; b += 64) {
+            gcen.push_back(a);
+            gb0.push_back(b);
+        }
+    if (gcen.size() > (size_t)INT32_MAX / 64) return fail(HALIGN_E_UNSUPPORTED, "too many pairs");
+    RCHK(run_groups(ctx, S, seqs, 1, gcen, gb0, perm, gslot, sums, nullptr, st));
+    if (center_host) RCHK(argmax_sums(ctx, sums, nullptr, N, center_host, st));
+    return HALIGN_OK;
+}
+
+int halign_center_judge(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, const int32_t *cand,
+                        int32_t ncand, int64_t *sums, int32_t *center_host, void *stream) {
+    if (!ctx || !sums || !cand || ncand <= 0) return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_scoring(sc));
+    RCHK(check_seqs(seqs));
+    const int N = seqs->n;
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> hc(ncand);
+    HCHK(hipMemcpyAsync(hc.data(), cand, 4 * (size_t)ncand, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    for (int q = 0; q < ncand; ++q)
+        if (hc[q] < 0 || hc[q] >= N) return fail(HALIGN_E_INVALID, "candidate %d out of range", hc[q]);
+    Scoring S;
+    RCHK(upload_matrix(ctx, sc, st, &S));
+    RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
+    RCHK(launch_fill((uint32_t *)sums, 0u, 2 * (int64_t)ncand, st));
+    std::vector<int32_t> perm = length_perm(seqs), gcen, gb0, gslot;
+    for (int q = 0; q < ncand; ++q)
+        for (int b = 0; b < N; b += 64) {
+            gcen.push_back(hc[q]);
+            gb0.push_back(b);
+            gslot.push_back(q);
+        }
+    RCHK(run_groups(ctx, S, seqs, 2, gcen, gb0, perm, gslot, sums, nullptr, st));
+    if (center_host) RCHK(argmax_sums(ctx, sums, hc.data(), ncand, center_host, st));
+    return HALIGN_OK;
+}
+
+int halign_sw_pairs(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, const int32_t *anchors_host,
+                    int32_t nanchors, const int32_t *partners_host, int32_t *score, void *stream) {
+    if (!ctx || nanchors < 0 || (nanchors > 0 && (!anchors_host || !partners_host || !score)))
+        return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_scoring(sc));
+    RCHK(check_seqs(seqs));
+    const int N = seqs->n;
+    const int64_t np = (int64_t)nanchors * 64;
+    for (int q = 0; q < nanchors; ++q)
+        if (anchors_host[q] < 0 || anchors_host[q] >= N) return fail(HALIGN_E_INVALID, "anchor out of range");
+    for (int64_t q = 0; q < np; ++q)
+        if (partners_host[q] < 0 || partners_host[q] >= N) return fail(HALIGN_E_INVALID, "partner out of range");
+    if (nanchors == 0) return HALIGN_OK;
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    Scoring S;
+    RCHK(upload_matrix(ctx, sc, st, &S));
+    RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
+    // group q: anchor q as the center, lanes = partners[64q .. 64q+63] (the
+    // "perm" of the anchored mode), scores land at slot 64q + lane
+    std::vector<int32_t> perm(partners_host, partners_host + np), gcen(anchors_host, anchors_host + nanchors),
+        gb0(nanchors), gslot(nanchors);
+    for (int q = 0; q < nanchors; ++q) {
+        gb0[q] = q * 64;
+        gslot[q] = q;
+    }
+    RCHK(grow(ctx, ctx->pairbuf, 16 * (size_t)nanchors + 256));
+    int64_t *sums = (int64_t *)ctx->pairbuf.p;
+    RCHK(launch_fill((uint32_t *)sums, 0u, 2 * (int64_t)nanchors, st));
+    halign_seqs sq2 = *seqs;
+    sq2.n = N;
+    RCHK(run_groups(ctx, S, &sq2, 2, gcen, gb0, perm, gslot, sums, score, st, (int)np));
+    return HALIGN_OK;
+}
+
+int halign_sp_score(const halign_scoring *sc, const uint8_t *msa, int32_t n, int64_t width, int64_t *out_host,
+                    void *stream) {
+    RCHK(check_scoring(sc));
+    if (!out_host || n < 0 || width < 0 || (n > 0 && width > 0 && !msa)) return fail(HALIGN_E_INVALID, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    int8_t *dmat = nullptr;
+    unsigned long long *dout = nullptr;
+    HCHK(hipMalloc(&dmat, 1024));
+    HCHK(hipMalloc(&dout, 16));
+    HCHK(hipMemcpyAsync(dmat, sc->matrix_host, (size_t)sc->alphabet * sc->alphabet, hipMemcpyHostToDevice, st));
+    RCHK(launch_fill((uint32_t *)dout, 0u, 4, st));
+    if (n > 0 && width > 0) {
+        hipLaunchKernelGGL(hk::sp_kernel, dim3((unsigned)((width + 127) / 128)), dim3(128), 0, st, msa, n, width,
+                           (const int8_t *)dmat, sc->alphabet, sc->gap_extend, dout);
+        HCHK(hipGetLastError());
+    }
+    unsigned long long h[2];
+    HCHK(hipMemcpyAsync(h, dout, 16, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    HCHK(hipFree(dmat));
+    HCHK(hipFree(dout));
+    out_host[0] = (int64_t)h[0];
+    out_host[1] = (int64_t)h[1];
+    return HALIGN_OK;
+}
+
+}  // extern "C"
+
+namespace {
+int center_learned(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, const halign_model *model,
+                   int k, int32_t *center_host, hipStream_t st);
+}
+
+extern "C" {
+
+int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, int32_t center,
+               const halign_model *model, halign_alloc_fn alloc, void *user, uint8_t **msa, int64_t *width_host,
+               int32_t *center_out_host, void *stream) {
+    if (!ctx || !alloc || !msa || !width_host) return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_scoring(sc));
+    RCHK(check_seqs(seqs));
+    const int N = seqs->n;
+    if (N <= 0) return fail(HALIGN_E_INVALID, "empty set");
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    int32_t c = center;
+    if (center == HALIGN_CENTER_EXACT) {
+        RCHK(grow(ctx, ctx->msabuf, 16 * (size_t)N + 256));
+        RCHK(halign_center_exact(ctx, sc, seqs, (int64_t *)ctx->msabuf.p, &c, stream));
+    } else if (center == HALIGN_CENTER_LEARNED) {
+        if (!model) return fail(HALIGN_E_INVALID, "learned center needs a model");
+        RCHK(center_learned(ctx, sc, seqs, model, 16, &c, st));
+    } else if (center < 0 || center >= N) {
+        return fail(HALIGN_E_INVALID, "center %d out of range", center);
+    }
+    const int64_t *oh = seqs->offsets_host;
+    const int m = (int)(oh[c + 1] - oh[c]);
+    if (m <= 0) return fail(HALIGN_E_INVALID, "center sequence is empty");
+    const int aw = (m + 31) / 32;
+    // per-pair outputs in one workspace
+    const size_t b_score = 4 * (size_t)N, b_cells = 16 * (size_t)N, b_ins = 2 * (size_t)N * (m + 1) + 4,
+                 b_al = 4 * (size_t)N * aw, b_G = 4 * (size_t)(m + 1), b_col = 8 * (size_t)(m + 1);
+    size_t o = 0;
+    auto take = [&](size_t b) { size_t r = o; o = (o + b + 255) & ~size_t(255); return r; };
+    const size_t o_score = take(b_score), o_cells = take(b_cells), o_ins = take(b_ins), o_al = take(b_al),
+                 o_G = take(b_G), o_col = take(b_col);
+    DevBuf &W = ctx->msabuf;
+    RCHK(grow(ctx, W, o));
+    char *wb = (char *)W.p;
+    int32_t *score = (int32_t *)(wb + o_score);
+    int32_t *cells = (int32_t *)(wb + o_cells);
+    uint16_t *ins = (uint16_t *)(wb + o_ins);
+    uint32_t *al = (uint32_t *)(wb + o_al);
+    int32_t *G = (int32_t *)(wb + o_G);
+    int64_t *col = (int64_t *)(wb + o_col);
+    const uint8_t *cen = seqs->residues + oh[c];
+    RCHK(halign_sw_batch(ctx, sc, cen, m, seqs, HALIGN_TRACEBACK, score, cells, ins, al, stream));
+    hipLaunchKernelGGL(hk::center_row_kernel, dim3(1), dim3(256), 0, st, ins, al, c, m, aw);
+    HCHK(hipGetLastError());
+    int64_t width = 0;
+    RCHK(halign_merge(ctx, ins, N, m, G, col, &width, stream));
+    uint8_t *out = (uint8_t *)alloc((size_t)N * (size_t)width, user);
+    if (!out && width > 0) return fail(HALIGN_E_NOMEM, "allocator returned NULL for %lld bytes", (long long)(N * width));
+    RCHK(halign_emit_rows(ctx, seqs, m, ins, al, G, col, width, out, stream));
+    *msa = out;
+    *width_host = width;
+    if (center_out_host) *center_out_host = c;
+    return HALIGN_OK;
+}
+
+}  // extern "C"
+
+namespace {
+int center_learned(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, const halign_model *model,
+                   int k, int32_t *center_host, hipStream_t st) {
+    (void)ctx; (void)sc; (void)seqs; (void)model; (void)k; (void)center_host; (void)st;
+    return fail(HALIGN_E_UNSUPPORTED, "learned center not built yet");
+}
+}  // namespace

@@ -1,0 +1,191 @@
+"""GPU parity for the center-star merge, rows, center selection and avg SP,
+bit-exact against the oracle through the C ABI, plus the full-size batch20k
+workload in the launch configuration the benchmark times (sampled pairs
+checked one by one against the oracle, properties checked on every row)."""
+import numpy as np
+import pytest
+
+import oracle
+from golden_cases import load, row_text
+from paper_1704_00878_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def H():
+    import paper_1704_00878_amd as H
+    H.lib()
+    return H
+
+
+@pytest.fixture(scope="module")
+def ctx(H):
+    c = H.Context(0)
+    yield c
+    c.close()
+
+
+def _msa(H, ctx, seqs, center, sc=None):
+    import torch
+    sc = sc or H.Scoring()
+    ds = H.DeviceSeqs(seqs)
+    msa, c = H.halign_msa(ctx, sc, ds, center)
+    torch.cuda.synchronize()
+    return msa.cpu().numpy(), c
+
+
+@pytest.mark.parametrize("center", [0, 7, 63])
+def test_msa_plain64(H, ctx, center):
+    seqs = synth.generate("plain64")
+    got, c = _msa(H, ctx, seqs, center)
+    ref = oracle.msa(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets, center)
+    assert c == center
+    assert got.shape == ref["msa"].shape
+    assert (got == ref["msa"]).all()
+
+
+def test_msa_hand_case(H, ctx):
+    case = [c for c in load() if c["kind"] == "msa"][0]
+    seqs = synth.SeqSet.from_list(case["seqs"])
+    sc = H.Scoring(gap_open=case["go"], gap_extend=case["ge"])
+    got, _ = _msa(H, ctx, seqs, case["center"], sc)
+    assert [row_text(r) for r in got] == case["rows"]
+    import torch
+    sp, spb = H.halign_sp_score(sc, torch.from_numpy(got).cuda())
+    assert sp == case["sp"] and spb == case["sp_blosum"]
+
+
+def test_msa_edge_sets(H, ctx):
+    rng = np.random.default_rng(12)
+    # empty sequences, a single sequence, duplicates, unrelated sequences
+    base = synth.generate("plain64", n_seqs=10)
+    seqs = synth.SeqSet.from_list([base.seq(0), np.zeros(0, np.uint8), base.seq(0), base.seq(3)[:5],
+                                   rng.integers(0, 20, size=300).astype(np.uint8), base.seq(9)])
+    for center in (0, 4):
+        got, _ = _msa(H, ctx, seqs, center)
+        ref = oracle.msa(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets, center)
+        assert (got == ref["msa"]).all()
+    one = synth.SeqSet.from_list([base.seq(2)])
+    got, _ = _msa(H, ctx, one, 0)
+    assert (got[0] == base.seq(2)).all()
+
+
+def test_merge_and_rows_calls(H, ctx):
+    """halign_merge and halign_emit_rows on oracle-made center-star vectors."""
+    import torch
+    seqs = synth.generate("plain64")
+    ref = oracle.msa(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets, 0)
+    N, m = seqs.n, len(seqs.seq(0))
+    ins = torch.from_numpy(ref["ins"].view(np.int16)).cuda()
+    G = torch.empty(m + 1, dtype=torch.int32, device="cuda")
+    col = torch.empty(m + 1, dtype=torch.int64, device="cuda")
+    W = H.halign_merge(ctx, ins, N, m, G, col)
+    assert W == ref["width"]
+    assert (G.cpu().numpy() == ref["G"]).all() and (col.cpu().numpy() == ref["col"]).all()
+    al = np.zeros((N, (m + 31) // 32), np.uint32)
+    for k in range(N):
+        for p in np.nonzero(ref["aligned"][k])[0]:
+            al[k, p >> 5] |= np.uint32(1) << np.uint32(p & 31)
+    alt = torch.from_numpy(al.view(np.int32)).cuda()
+    msa = torch.empty((N, W), dtype=torch.uint8, device="cuda")
+    ds = H.DeviceSeqs(seqs)
+    H.halign_emit_rows(ctx, ds, m, ins, alt, G, col, W, msa)
+    torch.cuda.synchronize()
+    assert (msa.cpu().numpy() == ref["msa"]).all()
+
+
+def test_center_exact(H, ctx):
+    import torch
+    seqs = synth.generate("plain64", n_seqs=24, seed=9)
+    best, sums = oracle.center_exact(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets)
+    ds = H.DeviceSeqs(seqs)
+    d = torch.empty(seqs.n, dtype=torch.int64, device="cuda")
+    c = H.halign_center_exact(ctx, H.Scoring(), ds, d)
+    assert c == best
+    assert (d.cpu().numpy() == sums).all()
+
+
+def test_center_exact_plain64_and_msa(H, ctx):
+    seqs = synth.generate("plain64")
+    best, sums = oracle.center_exact(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets)
+    got, c = _msa(H, ctx, seqs, H.HALIGN_CENTER_EXACT)
+    assert c == best
+    ref = oracle.msa(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets, best)
+    assert (got == ref["msa"]).all()
+
+
+def test_center_judge(H, ctx):
+    import torch
+    seqs = synth.generate("plain64", n_seqs=40, seed=4)
+    cand = [5, 0, 17, 39, 22]
+    jb, js = oracle.center_judge(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets, cand)
+    ds = H.DeviceSeqs(seqs)
+    ct = torch.tensor(cand, dtype=torch.int32, device="cuda")
+    d = torch.empty(len(cand), dtype=torch.int64, device="cuda")
+    c = H.halign_center_judge(ctx, H.Scoring(), ds, ct, d)
+    assert c == jb
+    assert (d.cpu().numpy() == js).all()
+
+
+def test_sw_pairs(H, ctx):
+    import torch
+    seqs = synth.generate("plain64", n_seqs=50, seed=6)
+    rng = np.random.default_rng(2)
+    anchors = rng.integers(0, seqs.n, size=3).astype(np.int32)
+    partners = rng.integers(0, seqs.n, size=3 * 64).astype(np.int32)
+    ds = H.DeviceSeqs(seqs)
+    out = torch.empty(3 * 64, dtype=torch.int32, device="cuda")
+    H.halign_sw_pairs(ctx, H.Scoring(), ds, anchors, partners, out)
+    got = out.cpu().numpy()
+    for q in range(3):
+        for l in range(64):
+            a, b = int(anchors[q]), int(partners[64 * q + l])
+            want = 0 if a == b else oracle.sw_score(synth.BLOSUM62, 11, 1, seqs.seq(a), seqs.seq(b))
+            assert got[64 * q + l] == want, (q, l)
+
+
+def test_sp_score_random(H):
+    import torch
+    rng = np.random.default_rng(8)
+    a = rng.integers(0, 20, size=(37, 91)).astype(np.uint8)
+    a[rng.random(a.shape) < 0.3] = 255
+    sp, spb = H.halign_sp_score(H.Scoring(), torch.from_numpy(a).cuda())
+    assert sp == oracle.sp_columns(a) == oracle.sp_pairs(a)
+    assert spb == oracle.sp_blosum(synth.BLOSUM62, 1, a)
+
+
+def test_batch20k_full_size(H, ctx):
+    """The benchmark's workload and launch configuration: every row restores
+    its input, G and the width follow from the vectors, and 300 sampled pairs
+    equal the oracle bit for bit."""
+    import torch
+    seqs = synth.generate("batch20k")
+    ds = H.DeviceSeqs(seqs)
+    sc = H.Scoring()
+    out = H.sw_batch(ctx, sc, ds, 0, traceback=True)
+    msa, c = H.halign_msa(ctx, sc, ds, 0)
+    torch.cuda.synchronize()
+    score = out["score"].cpu().numpy()
+    cells = out["cells"].cpu().numpy()
+    ins = out["ins"].cpu().numpy().view(np.uint16)
+    m = len(seqs.seq(0))
+    al = H.aligned_to_bool(out["aligned"].cpu().numpy(), m)
+    M = msa.cpu().numpy()
+    ins_c = ins.copy()
+    ins_c[0] = 0
+    G = ins_c.max(axis=0)
+    assert M.shape == (seqs.n, m + int(G.sum()))
+    assert (ins.sum(axis=1) + al.sum(axis=1) == seqs.lengths()).all()
+    for k in range(seqs.n):
+        row = M[k]
+        assert (row[row != 255] == seqs.seq(k)).all(), k
+    rng = np.random.default_rng(0)
+    pick = np.concatenate([[0, 1, seqs.n - 1], rng.choice(seqs.n, size=297, replace=False)])
+    c0 = seqs.seq(0)
+    for k in pick:
+        r = oracle.sw(synth.BLOSUM62, 11, 1, c0, seqs.seq(int(k)))
+        assert score[k] == r["score"], k
+        assert tuple(cells[k]) == tuple(r["cells"]), k
+        assert (ins[k] == r["ins"]).all(), k
+        assert (al[k] == r["aligned"]).all(), k

@@ -1,0 +1,190 @@
+"""GPU parity: SW scores, end/start cells and center-star vectors, bit-exact
+against the oracle, through the C ABI.  Both kernels (one pair per lane, one
+pair per wavefront) are checked on every case."""
+import numpy as np
+import pytest
+
+import oracle
+from golden_cases import load
+from paper_1704_00878_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+ROUTES = ["intra", "inter"]
+
+
+@pytest.fixture(scope="module")
+def H():
+    import paper_1704_00878_amd as H
+    H.lib()
+    return H
+
+
+@pytest.fixture(scope="module")
+def ctx(H):
+    c = H.Context(0)
+    yield c
+    c.close()
+
+
+def _route(H, name):
+    return H.HALIGN_ROUTE_INTRA if name == "intra" else H.HALIGN_ROUTE_INTER
+
+
+def _run(H, ctx, sc, seqs, center_codes, route, traceback=True):
+    import torch
+    ds = H.DeviceSeqs(seqs)
+    cen = torch.from_numpy(np.ascontiguousarray(center_codes, dtype=np.uint8)).cuda()
+    out = H.sw_batch(ctx, sc, ds, 0, traceback=traceback, route=_route(H, route), center_seq=cen)
+    torch.cuda.synchronize()
+    m = len(center_codes)
+    res = dict(score=out["score"].cpu().numpy(), cells=out["cells"].cpu().numpy())
+    if traceback:
+        res["ins"] = out["ins"].cpu().numpy().view(np.uint16)
+        res["aligned"] = H.aligned_to_bool(out["aligned"].cpu().numpy(), m)
+    return res
+
+
+def _compare(got, S, go, ge, center, seqs, traceback=True):
+    score, cells, ins, al = oracle.sw_batch(S, go, ge, center, seqs.residues, seqs.offsets)
+    bad = np.nonzero(got["score"] != score)[0]
+    assert len(bad) == 0, f"score mismatch at {bad[:10]}: {got['score'][bad[:10]]} vs {score[bad[:10]]}"
+    if traceback:
+        bad = np.nonzero((got["cells"] != cells).any(axis=1))[0]
+        assert len(bad) == 0, f"cells mismatch at {bad[:5]}: {got['cells'][bad[:5]]} vs {cells[bad[:5]]}"
+        bad = np.nonzero((got["ins"] != ins).any(axis=1))[0]
+        assert len(bad) == 0, f"ins mismatch at {bad[:5]}"
+        bad = np.nonzero((got["aligned"] != al).any(axis=1))[0]
+        assert len(bad) == 0, f"aligned mismatch at {bad[:5]}"
+    else:
+        # score-only reports the end cell as (0, 0, i1, j1)
+        assert (got["cells"][:, 2:] == cells[:, 2:]).all()
+
+
+@pytest.mark.parametrize("route", ROUTES)
+def test_plain64_center0(H, ctx, route):
+    seqs = synth.generate("plain64")
+    sc = H.Scoring()
+    got = _run(H, ctx, sc, seqs, seqs.seq(0), route)
+    _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, seqs.seq(0), seqs)
+
+
+@pytest.mark.parametrize("route", ROUTES)
+def test_hand_cases(H, ctx, route):
+    for case in [c for c in load() if c["kind"] == "case"]:
+        sc = H.Scoring(gap_open=case["go"], gap_extend=case["ge"])
+        seqs = synth.SeqSet.from_list([case["seq"]])
+        got = _run(H, ctx, sc, seqs, case["center"], route)
+        assert got["score"][0] == case["score"], case["name"]
+        assert tuple(got["cells"][0]) == case["cells"], case["name"]
+        assert (got["ins"][0] == case["ins"]).all(), case["name"]
+        assert (got["aligned"][0] == case["aligned"]).all(), case["name"]
+
+
+# centers spanning every rows-per-lane template, multi-pass layouts and the
+# fallback to the strip kernel when the profile exceeds LDS
+@pytest.mark.parametrize("m", [1, 7, 64, 128, 129, 200, 256, 300, 384, 385, 512, 513, 700, 1100])
+@pytest.mark.parametrize("route", ROUTES)
+def test_center_lengths(H, ctx, m, route):
+    rng = np.random.default_rng(1000 + m)
+    base = synth.generate("plain64", n_seqs=24, seed=77 + m)
+    center = rng.integers(0, 20, size=m).astype(np.uint8)
+    # sequences related to the center plus unrelated ones and edge lengths
+    seqs = [center[rng.integers(0, max(1, m // 3)):][: rng.integers(1, m + 1)].copy() for _ in range(8)]
+    seqs += [base.seq(k) for k in range(8)]
+    seqs += [np.zeros(0, np.uint8), center[:1].copy(), center.copy(),
+             rng.integers(0, 24, size=int(rng.integers(1, 400))).astype(np.uint8)]
+    for k in range(4):
+        s = center.copy()
+        for _ in range(max(1, m // 40)):
+            p = int(rng.integers(0, len(s) + 1))
+            s = np.insert(s, p, rng.integers(0, 20, size=int(rng.integers(1, 4))).astype(np.uint8))
+        seqs.append(s)
+    ss = synth.SeqSet.from_list(seqs)
+    sc = H.Scoring()
+    got = _run(H, ctx, sc, ss, center, route)
+    _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, center, ss)
+
+
+@pytest.mark.parametrize("route", ROUTES)
+@pytest.mark.parametrize("gaps", [(11, 1), (10, 1), (0, 1), (3, 2), (1, 1)])
+def test_gap_params(H, ctx, route, gaps):
+    seqs = synth.generate("plain64", n_seqs=40, seed=5)
+    sc = H.Scoring(gap_open=gaps[0], gap_extend=gaps[1])
+    got = _run(H, ctx, sc, seqs, seqs.seq(3), route)
+    _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, seqs.seq(3), seqs)
+
+
+@pytest.mark.parametrize("route", ROUTES)
+def test_score_only(H, ctx, route):
+    seqs = synth.generate("plain64")
+    sc = H.Scoring()
+    got = _run(H, ctx, sc, seqs, seqs.seq(5), route, traceback=False)
+    _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, seqs.seq(5), seqs, traceback=False)
+
+
+def test_small_alphabet_ties(H, ctx):
+    """Tiny alphabet makes ties everywhere: every tie rule is exercised."""
+    rng = np.random.default_rng(3)
+    S = np.array([[2, -1], [-1, 2]], np.int8)
+    for route in ROUTES:
+        for go, ge in [(1, 1), (0, 1), (2, 1)]:
+            center = rng.integers(0, 2, size=90).astype(np.uint8)
+            seqs = synth.SeqSet.from_list([rng.integers(0, 2, size=int(rng.integers(0, 120))).astype(np.uint8)
+                                           for _ in range(70)])
+            sc = H.Scoring(S, go, ge)
+            got = _run(H, ctx, sc, seqs, center, route)
+            _compare(got, S, go, ge, center, seqs)
+
+
+def test_deterministic_repeat(H, ctx):
+    seqs = synth.generate("plain64")
+    sc = H.Scoring()
+    a = _run(H, ctx, sc, seqs, seqs.seq(0), "intra")
+    b = _run(H, ctx, sc, seqs, seqs.seq(0), "intra")
+    for k in a:
+        assert (a[k] == b[k]).all()
+
+
+def test_workspace_cap_chunks(H):
+    """A tiny workspace cap forces many chunks; results are identical."""
+    seqs = synth.generate("plain64")
+    sc = H.Scoring()
+    full = H.Context(0)
+    small = H.Context(0, workspace_cap=200_000)
+    for route in ROUTES:
+        a = _run(H, full, sc, seqs, seqs.seq(0), route)
+        b = _run(H, small, sc, seqs, seqs.seq(0), route)
+        assert small.last_stats()["chunks"] > 1
+        for k in a:
+            assert (a[k] == b[k]).all()
+    full.close()
+    small.close()
+
+
+def test_injected_chunk_failure_then_retry(H):
+    """A chunk that fails is reported; re-running the call gives the same result."""
+    seqs = synth.generate("plain64")
+    sc = H.Scoring()
+    ctx = H.Context(0, workspace_cap=200_000)
+    ref = _run(H, ctx, sc, seqs, seqs.seq(0), "intra")
+    ctx.fail_chunk(1)
+    with pytest.raises(H.HalignError):
+        _run(H, ctx, sc, seqs, seqs.seq(0), "intra")
+    again = _run(H, ctx, sc, seqs, seqs.seq(0), "intra")
+    for k in ref:
+        assert (ref[k] == again[k]).all()
+    ctx.close()
+
+
+def test_invalid_arguments(H, ctx):
+    import torch
+    seqs = synth.generate("plain64", n_seqs=4)
+    ds = H.DeviceSeqs(seqs)
+    sc = H.Scoring()
+    score = torch.empty(4, dtype=torch.int32, device="cuda")
+    with pytest.raises(H.HalignError):
+        H.halign_sw_batch(ctx, sc, ds.seq_ptr(0), 0, ds, 0, score)
+    bad = H.Scoring(gap_open=-1)
+    with pytest.raises(H.HalignError):
+        H.halign_sw_batch(ctx, bad, ds.seq_ptr(0), ds.length(0), ds, 0, score)
