@@ -88,6 +88,7 @@ def main():
     ap.add_argument("--route", default="auto", choices=["auto", "intra", "inter"])
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--perpair", type=int, default=200, help="pairs for the per-pair-launch baseline")
+    ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
@@ -140,9 +141,20 @@ def main():
     width = int(msa.shape[1])
     log(f"bench: {ms_step:.3f} ms/step, {gcups:.1f} GCUPS; forward {fwd_ms:.3f} ms, walk {walk_ms:.3f} ms")
 
+    if args.calibrate_copy:
+        # plain device copy of a known size: reference reading for HBM counters
+        nb = 256 << 20
+        xs = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        ys = torch.empty_like(xs)
+        xs.fill_(1)
+        for _ in range(3):
+            ys.copy_(xs)
+        torch.cuda.synchronize()
+        log(f"bench: calibration copy of {nb} bytes x3 done")
+
     # per-pair launches: same kernels, one pair per call, no batching
     rng = np.random.default_rng(0)
-    pick = rng.choice(seqs.n, size=min(args.perpair, seqs.n), replace=False)
+    pick = rng.choice(seqs.n, size=min(max(args.perpair, 1), seqs.n), replace=False)
     singles = [H.DeviceSeqs(seqs.subset([int(k)]), "cuda:0") for k in pick]
     cseq = ds.residues[int(ds.offsets_host[center]):int(ds.offsets_host[center + 1])]
     for d in singles[:5]:
@@ -153,7 +165,7 @@ def main():
         H.sw_batch(ctx, sc, d, 0, traceback=True, center_seq=cseq)
     torch.cuda.synchronize()
     dtp = time.perf_counter() - tp
-    pp_cells = m * int(sum(seqs.length(int(k)) for k in pick))
+    pp_cells = m * int(seqs.lengths()[pick].sum())
     pp_gcups = pp_cells / dtp / 1e9
     log(f"bench: per-pair launches {pp_gcups:.2f} GCUPS over {len(pick)} pairs")
 

@@ -23,8 +23,8 @@
 //
 // End cell: max H, ties to the smallest j, then the smallest i.  Kernels form
 // key = (H << 5) | (31 - t) for the T rows of a column, take the max over the
-// column (max H, then min row), and update the running best only on a
-// strictly larger H at a later column.
+// column (max H, then min row); the running best moves on a strictly larger H,
+// or on an equal H at a smaller j (a later strip or pass, which holds larger i).
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -187,8 +187,9 @@ sw_intra_kernel(IntraArgs a) {
                 if (TB) cw[(int64_t)k * 64 + lane] = word;
                 if (bout && lane == 63 && j >= 1 && j <= n) bout[j - 1] = make_int2(botg, botf);
                 if (ENDC) {
+                    // later passes hold larger i: on equal H they win only with a smaller j
                     const int ch = colkey >> 5;
-                    if (ch > best.h) {
+                    if (ch > 0 && (ch > best.h || (ch == best.h && j < best.j))) {
                         best.h = ch;
                         best.j = j;
                         best.i = myrow + (31 - (colkey & 31));
@@ -304,9 +305,9 @@ sw_inter_kernel(InterArgs a) {
             cid = a.mode == 1 ? a.perm[a.gcen[g]] : a.gcen[g];
             if (bpos < a.nseq) {
                 sid = a.perm[bpos];
+                pid = g * 64 + lane;          // output slot; a self pair scores 0
                 if (sid == cid) sid = -1;
             }
-            pid = sid >= 0 ? g * 64 + lane : -1;
             cen = a.res + a.off[cid];
             m = (int)(a.off[cid + 1] - a.off[cid]);
         }
@@ -366,8 +367,9 @@ sw_inter_kernel(InterArgs a) {
                     *dst = make_uint2(w0, w1);
                 }
                 if (ENDC) {
+                    // later strips hold larger i: on equal H they win only with a smaller j
                     const int ch = colkey >> 5;
-                    if (ch > best.h) {
+                    if (ch > 0 && (ch > best.h || (ch == best.h && j < best.j))) {
                         best.h = ch;
                         best.j = j;
                         best.i = i0 + (31 - (colkey & 31));

@@ -148,10 +148,10 @@ def test_deterministic_repeat(H, ctx):
 
 def test_workspace_cap_chunks(H):
     """A tiny workspace cap forces many chunks; results are identical."""
-    seqs = synth.generate("plain64")
+    seqs = synth.generate("plain64", n_seqs=300, seed=21)
     sc = H.Scoring()
     full = H.Context(0)
-    small = H.Context(0, workspace_cap=200_000)
+    small = H.Context(0, workspace_cap=1_000_000)
     for route in ROUTES:
         a = _run(H, full, sc, seqs, seqs.seq(0), route)
         b = _run(H, small, sc, seqs, seqs.seq(0), route)
