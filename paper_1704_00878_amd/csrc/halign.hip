@@ -65,7 +65,7 @@ struct halign_ctx {
     int num_cu = 256;
     size_t lds_max = 65536;
     // device scratch
-    DevBuf codes, bound, plan, counter, pairbuf, msabuf, spbuf, colbuf;
+    DevBuf codes, bound, plan, counter, pairbuf, msabuf, spbuf, colbuf, sbuf;
     // pinned host staging for plans
     HostBuf stage;
     hipEvent_t ev_stage = nullptr;
@@ -74,6 +74,8 @@ struct halign_ctx {
     float last_ms[3] = {0, 0, 0};
     int64_t last_stats[4] = {0, 0, 0, 0};
     int fault_chunk = -1;    // test hook: chunk index whose first launch reports failure
+    int *flag_host = nullptr; // pinned: largest residue code of the last validated call
+    int flag_alpha = 0;       // alphabet that value is checked against (0 = nothing pending)
 };
 
 namespace {
@@ -181,29 +183,34 @@ struct Scoring {
 // ---------------------------------------------------------------------------
 enum Route { kRouteIntra = 0, kRouteInter = 1 };
 
-int pick_R(int m) {
-    if (m <= 128) return 2;
-    if (m <= 256) return 4;
-    if (m <= 384) return 6;
-    return 8;
+// Rows per lane and passes of the wavefront kernel: passes = ceil(m / 512),
+// R = ceil(m / (64 * passes)) <= 8, so a pass holds 64*R >= m/passes rows.
+void pick_geom(int m, int *R, int *passes) {
+    const int p = std::max(1, (m + 511) / 512);
+    *passes = p;
+    *R = std::max(1, std::min(8, (m + 64 * p - 1) / (64 * p)));
 }
 
 template <int R>
-void launch_intra_R(const hk::IntraArgs &a, bool tb, bool endc, int grid, int block, size_t lds, hipStream_t st) {
+void launch_stream_R(const hk::StreamArgs &a, bool tb, bool endc, int grid, size_t lds, hipStream_t st) {
     if (tb)
-        hipLaunchKernelGGL((hk::sw_intra_kernel<R, true, true>), dim3(grid), dim3(block), lds, st, a);
+        hipLaunchKernelGGL((hk::sw_stream_kernel<R, true, true>), dim3(grid), dim3(512), lds, st, a);
     else if (endc)
-        hipLaunchKernelGGL((hk::sw_intra_kernel<R, false, true>), dim3(grid), dim3(block), lds, st, a);
+        hipLaunchKernelGGL((hk::sw_stream_kernel<R, false, true>), dim3(grid), dim3(512), lds, st, a);
     else
-        hipLaunchKernelGGL((hk::sw_intra_kernel<R, false, false>), dim3(grid), dim3(block), lds, st, a);
+        hipLaunchKernelGGL((hk::sw_stream_kernel<R, false, false>), dim3(grid), dim3(512), lds, st, a);
 }
 
-void launch_intra(int R, const hk::IntraArgs &a, bool tb, bool endc, int grid, int block, size_t lds, hipStream_t st) {
+void launch_stream(int R, const hk::StreamArgs &a, bool tb, bool endc, int grid, size_t lds, hipStream_t st) {
     switch (R) {
-        case 2: launch_intra_R<2>(a, tb, endc, grid, block, lds, st); break;
-        case 4: launch_intra_R<4>(a, tb, endc, grid, block, lds, st); break;
-        case 6: launch_intra_R<6>(a, tb, endc, grid, block, lds, st); break;
-        default: launch_intra_R<8>(a, tb, endc, grid, block, lds, st); break;
+        case 1: launch_stream_R<1>(a, tb, endc, grid, lds, st); break;
+        case 2: launch_stream_R<2>(a, tb, endc, grid, lds, st); break;
+        case 3: launch_stream_R<3>(a, tb, endc, grid, lds, st); break;
+        case 4: launch_stream_R<4>(a, tb, endc, grid, lds, st); break;
+        case 5: launch_stream_R<5>(a, tb, endc, grid, lds, st); break;
+        case 6: launch_stream_R<6>(a, tb, endc, grid, lds, st); break;
+        case 7: launch_stream_R<7>(a, tb, endc, grid, lds, st); break;
+        default: launch_stream_R<8>(a, tb, endc, grid, lds, st); break;
     }
 }
 
@@ -222,8 +229,8 @@ struct BatchOut {
     uint32_t *aligned;
 };
 
-// Plans and runs the forward pass (+ walk when tb) for the pairs `pids`
-// (already validated) against center (device) of length m.
+// Plans and runs the forward pass (+ walk when tb) for the pairs `pids_in`
+// against center (device) of length m.
 int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq,
               const std::vector<int32_t> &pids_in, bool tb, bool endc, int route, const BatchOut &out,
               hipStream_t st) {
@@ -231,49 +238,42 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
     const int N = sq->n;
     const int np = (int)pids_in.size();
     if (np == 0) return HALIGN_OK;
-    // longest first
-    std::vector<int32_t> pids(pids_in);
-    std::stable_sort(pids.begin(), pids.end(), [&](int32_t x, int32_t y) {
-        return (oh[x + 1] - oh[x]) > (oh[y + 1] - oh[y]);
-    });
+    auto len = [&](int pid) { return (int)(oh[pid + 1] - oh[pid]); };
+    // longest first (counting sort on length, stable)
+    std::vector<int32_t> pids(np);
+    {
+        int maxlen = 0;
+        for (int x = 0; x < np; ++x) maxlen = std::max(maxlen, len(pids_in[x]));
+        std::vector<int32_t> cnt(maxlen + 2, 0);
+        for (int x = 0; x < np; ++x) cnt[maxlen - len(pids_in[x])]++;
+        int acc = 0;
+        for (auto &c : cnt) { const int v = c; c = acc; acc += v; }
+        for (int x = 0; x < np; ++x) pids[cnt[maxlen - len(pids_in[x])]++] = pids_in[x];
+    }
     const int aw = (m + 31) / 32;
-    const size_t lds_need_intra = (size_t)hk::kAlphaMax * 4 *
-                                  (size_t)(((m + 64 * pick_R(m) - 1) / (64 * pick_R(m))) * 64 * pick_R(m));
-    if (route == kRouteIntra && lds_need_intra > ctx->lds_max)
-        route = kRouteInter;
+    int R = 8, passes = 1;
+    pick_geom(m, &R, &passes);
+    const size_t lds_stream = (size_t)hk::kAlphaMax * 64 * R * 4 + (tb ? 8 * 64 * 8 * 4 : 0);
+    if (route == kRouteIntra && lds_stream > ctx->lds_max) route = kRouteInter;
     ctx->last_stats[2] = route;
 
     // chunk the pairs so that codes + boundary rows fit the cap
     const size_t cap = ctx->cap ? ctx->cap : (size_t)1 << 62;
     std::vector<std::pair<int, int>> chunks;  // [lo, hi) in pids
-    const int R = pick_R(m);
-    const int passes = std::max(1, (m + 64 * R - 1) / (64 * R));
-    auto pair_bytes = [&](int pid) -> size_t {
-        const int n = (int)(oh[pid + 1] - oh[pid]);
-        if (route == kRouteIntra) {
-            size_t b = tb ? (size_t)passes * (n + 63) * 64 * 4 : 0;
-            b += (passes > 1) ? (size_t)(passes - 1) * n * 8 : 0;
-            return b;
-        }
-        const int nst = (m + hk::kT - 1) / hk::kT;
-        return tb ? (size_t)nst * n * 8 : 0;  // per lane share of its group's codes
-    };
     {
+        const int nst = (m + hk::kT - 1) / hk::kT;
         int lo = 0;
         size_t acc = 0;
         for (int x = 0; x < np; ++x) {
-            size_t b = pair_bytes(pids[x]);
-            if (route == kRouteInter) {
-                // groups are formed from 64 consecutive pairs, charge the group max
-                if (x % 64 == 0) {
-                    const int nmax = (int)(oh[pids[x] + 1] - oh[pids[x]]);
-                    const int nst = (m + hk::kT - 1) / hk::kT;
-                    b = tb ? (size_t)nst * nmax * 64 * 8 : 0;
-                } else {
-                    b = 0;
-                }
+            const int n = len(pids[x]);
+            size_t b = 0;
+            bool boundary = true;
+            if (route == kRouteIntra) {
+                b = (tb ? (size_t)passes * (n + 8) * 64 * 4 : 0) + (size_t)(passes - 1) * n * 8;
+            } else {
+                boundary = (x - lo) % 64 == 0;
+                b = (boundary && tb) ? (size_t)nst * ((n + 3) / 4) * 512 * 4 : 0;  // group charged by its longest
             }
-            bool boundary = (route == kRouteInter) ? (x % 64 == 0) : true;
             if (boundary && x > lo && acc + b > cap) {
                 chunks.push_back({lo, x});
                 lo = x;
@@ -284,12 +284,9 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         chunks.push_back({lo, np});
     }
     ctx->last_stats[3] = (int64_t)chunks.size();
-
     int64_t cells_total = 0;
-    for (int x = 0; x < np; ++x) cells_total += (int64_t)m * (oh[pids[x] + 1] - oh[pids[x]]);
+    for (int x = 0; x < np; ++x) cells_total += (int64_t)m * len(pids[x]);
     ctx->last_stats[0] = cells_total;
-
-    // device matrix lives at the head of ctx->plan; plan arrays follow
     RCHK(grow(ctx, ctx->counter, 256));
     int *counter = (int *)ctx->counter.p;
 
@@ -299,50 +296,110 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         const int lo = chunks[ci].first, hi = chunks[ci].second;
         const int cn = hi - lo;
         PlanBuilder pb;
-        size_t o_order = 0, o_cbase = 0, o_cstr = 0, o_bbase = 0, o_gnmax = 0, o_gcb = 0, o_walk = 0;
-        int ngroups = 0;
         size_t code_words = 0, bound_elems = 0;
         int nmax_all = 0;
-        for (int x = lo; x < hi; ++x) nmax_all = std::max(nmax_all, (int)(oh[pids[x] + 1] - oh[pids[x]]));
+        for (int x = lo; x < hi; ++x) nmax_all = std::max(nmax_all, len(pids[x]));
+        // common: per-pid walk descriptors and the walk list
+        const size_t o_cbase = pb.add(sizeof(int64_t) * N), o_cstr = pb.add(sizeof(int32_t) * N),
+                     o_ccol = pb.add(sizeof(int32_t) * N), o_walk = pb.add(sizeof(int32_t) * cn);
+        size_t o_sbeg = 0, o_slot0 = 0, o_scb = 0, o_sbb = 0, o_spid = 0, o_scol = 0;
+        size_t o_order = 0, o_gnmax = 0, o_gcb = 0;
+        int nstreams = 0, nslots = 0, ngroups = 0;
+        int64_t total_cols = 0;
         if (route == kRouteIntra) {
-            o_order = pb.add(sizeof(int32_t) * cn);
-            o_cbase = pb.add(sizeof(int64_t) * N);
-            o_cstr = pb.add(sizeof(int32_t) * N);
-            o_bbase = pb.add(sizeof(int64_t) * N);
+            // streams: snake-deal the (longest first) non-empty pairs over the
+            // resident waves so that every stream has about the same columns
+            int nonempty = 0;
+            for (int x = lo; x < hi; ++x) nonempty += len(pids[x]) > 0;
+            const int wg_per_cu = std::max(1, std::min(4, (int)(ctx->lds_max / lds_stream)));
+            const int resident = ctx->num_cu * wg_per_cu * 8;
+            nstreams = std::max(1, std::min(nonempty, resident));
+            if (const char *e = getenv("HALIGN_MAX_STREAMS")) {   // test knob: many pairs per stream
+                const int cap_s = atoi(e);
+                if (cap_s > 0) nstreams = std::min(nstreams, cap_s);
+            }
+            nslots = cn;
+            o_sbeg = pb.add(sizeof(int64_t) * (nstreams + 1));
+            o_slot0 = pb.add(sizeof(int32_t) * nstreams);
+            o_scb = pb.add(sizeof(int64_t) * nstreams);
+            o_sbb = pb.add(sizeof(int64_t) * nstreams);
+            o_spid = pb.add(sizeof(int32_t) * nslots);
+            o_scol = pb.add(sizeof(int64_t) * nslots);
         } else {
             ngroups = (cn + 63) / 64;
             o_order = pb.add(sizeof(int32_t) * (size_t)ngroups * 64);
             o_gnmax = pb.add(sizeof(int32_t) * ngroups);
             o_gcb = pb.add(sizeof(int64_t) * ngroups);
-            o_cbase = pb.add(sizeof(int64_t) * N);
-            o_cstr = pb.add(sizeof(int32_t) * N);
         }
-        o_walk = pb.add(sizeof(int32_t) * cn);
         RCHK(stage_grow(ctx, pb.total));
         char *hs = (char *)ctx->stage.p;
         int32_t *h_walk = (int32_t *)(hs + o_walk);
+        int64_t *h_cbase = (int64_t *)(hs + o_cbase);
+        int32_t *h_cstr = (int32_t *)(hs + o_cstr);
+        int32_t *h_ccol = (int32_t *)(hs + o_ccol);
         for (int x = 0; x < cn; ++x) h_walk[x] = pids[lo + x];
         if (route == kRouteIntra) {
-            int32_t *h_order = (int32_t *)(hs + o_order);
-            int64_t *h_cbase = (int64_t *)(hs + o_cbase);
-            int32_t *h_cstr = (int32_t *)(hs + o_cstr);
-            int64_t *h_bbase = (int64_t *)(hs + o_bbase);
+            int64_t *h_sbeg = (int64_t *)(hs + o_sbeg);
+            int32_t *h_slot0 = (int32_t *)(hs + o_slot0);
+            int64_t *h_scb = (int64_t *)(hs + o_scb);
+            int64_t *h_sbb = (int64_t *)(hs + o_sbb);
+            int32_t *h_spid = (int32_t *)(hs + o_spid);
+            int64_t *h_scol = (int64_t *)(hs + o_scol);
+            // stream of each non-empty pair (snake order), then slots grouped by stream
+            std::vector<int32_t> scount(nstreams, 0), sfill(nstreams, 0);
+            std::vector<int64_t> scols(nstreams, 0);
+            std::vector<int32_t> sof(cn, -1);
+            int e = 0;
+            for (int x = 0; x < cn; ++x) {
+                const int n = len(pids[lo + x]);
+                if (n == 0) continue;
+                const int r = e / nstreams, q = e % nstreams;
+                const int s = (r & 1) ? nstreams - 1 - q : q;
+                sof[x] = s;
+                scount[s]++;
+                scols[s] += n;
+                ++e;
+            }
+            int slot = 0;
+            int64_t col = 0;
+            for (int s = 0; s < nstreams; ++s) {
+                h_slot0[s] = slot;
+                h_sbeg[s] = col;
+                slot += scount[s];
+                col += scols[s];
+                h_scb[s] = (int64_t)code_words;
+                h_sbb[s] = (int64_t)bound_elems;
+                if (tb) code_words += (size_t)passes * ((scols[s] + 63 + 7) / 8) * 512;
+                if (passes > 1) bound_elems += (size_t)(passes - 1) * scols[s];
+            }
+            h_sbeg[nstreams] = col;
+            total_cols = col;
+            std::vector<int64_t> spos(nstreams, 0);   // column within stream
+            int eslot = slot;                         // empty pairs after the streamed ones
             for (int x = 0; x < cn; ++x) {
                 const int pid = pids[lo + x];
-                const int n = (int)(oh[pid + 1] - oh[pid]);
-                h_order[x] = pid;
-                h_cbase[pid] = (int64_t)code_words;
-                h_cstr[pid] = n + 63;
-                h_bbase[pid] = (int64_t)bound_elems;
-                if (tb) code_words += (size_t)passes * (n + 63) * 64;
-                if (passes > 1) bound_elems += (size_t)(passes - 1) * n;
+                const int s = sof[x];
+                if (s < 0) {
+                    h_spid[eslot] = pid;
+                    h_scol[eslot] = 0;
+                    ++eslot;
+                    h_cbase[pid] = 0;
+                    h_cstr[pid] = 1;
+                    h_ccol[pid] = 0;
+                    continue;
+                }
+                const int q = h_slot0[s] + sfill[s]++;
+                h_spid[q] = pid;
+                h_scol[q] = h_sbeg[s] + spos[s];
+                h_cbase[pid] = h_scb[s];
+                h_ccol[pid] = (int)spos[s];
+                h_cstr[pid] = (int)(scols[s] + 63);
+                spos[s] += len(pid);
             }
         } else {
             int32_t *h_order = (int32_t *)(hs + o_order);
             int32_t *h_gnmax = (int32_t *)(hs + o_gnmax);
             int64_t *h_gcb = (int64_t *)(hs + o_gcb);
-            int64_t *h_cbase = (int64_t *)(hs + o_cbase);
-            int32_t *h_cstr = (int32_t *)(hs + o_cstr);
             const int nst = (m + hk::kT - 1) / hk::kT;
             for (int g = 0; g < ngroups; ++g) {
                 int nmax = 0;
@@ -350,17 +407,18 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                     const int x = lo + g * 64 + l;
                     const int pid = x < hi ? pids[x] : -1;
                     h_order[g * 64 + l] = pid;
-                    if (pid >= 0) nmax = std::max(nmax, (int)(oh[pid + 1] - oh[pid]));
+                    if (pid >= 0) nmax = std::max(nmax, len(pid));
                 }
                 h_gnmax[g] = nmax;
                 h_gcb[g] = (int64_t)code_words;
                 for (int l = 0; l < 64; ++l) {
                     const int pid = h_order[g * 64 + l];
                     if (pid < 0) continue;
-                    h_cbase[pid] = (int64_t)code_words + 2 * l;
+                    h_cbase[pid] = (int64_t)code_words;
+                    h_ccol[pid] = l;
                     h_cstr[pid] = nmax;
                 }
-                if (tb) code_words += (size_t)nst * nmax * 64 * 2;
+                if (tb) code_words += (size_t)nst * ((nmax + 3) / 4) * 512;
             }
         }
         RCHK(grow(ctx, ctx->plan, pb.total));
@@ -370,47 +428,52 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         ctx->stage_pending = true;
 
         if (tb) RCHK(grow(ctx, ctx->codes, std::max<size_t>(4, code_words * 4)));
-        int grid = 0;
-        if (route == kRouteIntra) {
-            if (passes > 1) RCHK(grow(ctx, ctx->bound, std::max<size_t>(8, bound_elems * 8)));
-        } else {
-            const int slots = ctx->num_cu * 16;
-            grid = std::max(1, std::min(ngroups, slots));
-            RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * std::max(1, nmax_all) * 8));
-        }
-        RCHK(launch_fill((uint32_t *)counter, 0u, 1, st));
         if (ctx->fault_chunk == (int)ci) {
             ctx->fault_chunk = -1;
             return fail(HALIGN_E_DEVICE, "injected failure in chunk %d", (int)ci);
         }
-        HCHK(hipEventRecord(ctx->ev[0], st));
         if (route == kRouteIntra) {
-            hk::IntraArgs a{};
+            // staged stream residues and per-slot keys share one scratch buffer
+            const size_t keys_b = ((size_t)nslots * 8 + 255) & ~size_t(255);
+            RCHK(grow(ctx, ctx->sbuf, keys_b + (size_t)total_cols + 64));
+            unsigned long long *keys = (unsigned long long *)ctx->sbuf.p;
+            uint8_t *sres = (uint8_t *)ctx->sbuf.p + keys_b;
+            if (passes > 1) RCHK(grow(ctx, ctx->bound, std::max<size_t>(8, bound_elems * 8)));
+            RCHK(launch_fill((uint32_t *)keys, 0u, 2 * (int64_t)nslots, st));
+            hipLaunchKernelGGL(hk::stage_stream_kernel, dim3(nslots), dim3(128), 0, st, sq->residues, sq->offsets,
+                               (const int32_t *)(dplan + o_spid), (const int64_t *)(dplan + o_scol), nslots, sres);
+            HCHK(hipGetLastError());
+            HCHK(hipEventRecord(ctx->ev[0], st));
+            hk::StreamArgs a{};
             a.mat = S.dmat;
             a.alpha = S.alpha;
             a.center = center;
             a.m = m;
             a.passes = passes;
-            a.mpad = passes * 64 * R;
-            a.res = sq->residues;
-            a.off = sq->offsets;
-            a.order = (const int32_t *)(dplan + o_order);
-            a.npairs = cn;
+            a.sres = sres;
+            a.sbeg = (const int64_t *)(dplan + o_sbeg);
+            a.nstreams = nstreams;
             a.ge = S.ge;
             a.goe = S.goe;
-            a.counter = counter;
-            a.score = out.score;
-            a.endcell = out.endcell;
+            a.keys = keys;
+            a.sslot0 = (const int32_t *)(dplan + o_slot0);
             a.codes = tb ? (uint32_t *)ctx->codes.p : nullptr;
-            a.code_base = (const int64_t *)(dplan + o_cbase);
+            a.scbase = (const int64_t *)(dplan + o_scb);
             a.bound = (int2 *)ctx->bound.p;
-            a.bound_base = (const int64_t *)(dplan + o_bbase);
-            const int block = 512;
-            const size_t lds = (size_t)hk::kAlphaMax * a.mpad * 4;
-            grid = (cn + 7) / 8;   // one pair per wave
-            launch_intra(R, a, tb, endc, grid, block, lds, st);
+            a.sbbase = (const int64_t *)(dplan + o_sbb);
+            launch_stream(R, a, tb, endc, (nstreams + 7) / 8, lds_stream, st);
+            HCHK(hipGetLastError());
+            HCHK(hipEventRecord(ctx->ev[1], st));
+            hipLaunchKernelGGL(hk::decode_keys_kernel, dim3(grid_for(nslots, 256, 1 << 30)), dim3(256), 0, st,
+                               (const unsigned long long *)keys, (const int32_t *)(dplan + o_spid), nslots, out.score,
+                               endc ? out.endcell : (int32_t *)nullptr);
             HCHK(hipGetLastError());
         } else {
+            const int slots = ctx->num_cu * 16;
+            const int grid = std::max(1, std::min(ngroups, slots));
+            RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * std::max(1, nmax_all) * 8));
+            RCHK(launch_fill((uint32_t *)counter, 0u, 1, st));
+            HCHK(hipEventRecord(ctx->ev[0], st));
             hk::InterArgs a{};
             a.mat = S.dmat;
             a.alpha = S.alpha;
@@ -433,9 +496,9 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             a.bstride = (int64_t)64 * std::max(1, nmax_all);
             launch_inter(a, tb, endc, grid, st);
             HCHK(hipGetLastError());
+            HCHK(hipEventRecord(ctx->ev[1], st));
         }
         ++launches;
-        HCHK(hipEventRecord(ctx->ev[1], st));
         if (tb) {
             hk::WalkArgs w{};
             w.mat = S.dmat;
@@ -453,6 +516,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             w.codes = (const uint32_t *)ctx->codes.p;
             w.cbase = (const int64_t *)(dplan + o_cbase);
             w.cstride = (const int32_t *)(dplan + o_cstr);
+            w.ccol = (const int32_t *)(dplan + o_ccol);
             w.R = R;
             w.kind = route == kRouteIntra ? 0 : 1;
             w.cells = out.cells;
@@ -463,7 +527,6 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             HCHK(hipGetLastError());
         }
         HCHK(hipEventRecord(ctx->ev[2], st));
-        // per-chunk timing is accumulated lazily (events are re-used)
         if (chunks.size() > 1) {
             HCHK(hipEventSynchronize(ctx->ev[2]));
             float f = 0, w2 = 0;
@@ -477,7 +540,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
     if (chunks.size() > 1) {
         ctx->last_ms[0] = fwd_ms;
         ctx->last_ms[1] = walk_ms;
-        ctx->last_ms[2] = -1.f;  // single-chunk calls report through events
+        ctx->last_ms[2] = -1.f;
     } else {
         ctx->last_ms[2] = 0.f;
     }
@@ -500,21 +563,39 @@ int upload_matrix(halign_ctx *ctx, const halign_scoring *sc, hipStream_t st, Sco
 }
 
 // Every residue code must be below the alphabet size (HALIGN_E_INVALID).
+// The check is enqueued without waiting: the kernels are memory-safe for any
+// code (they mask codes to 5 bits), and the result lands in pinned host memory
+// that validate_check() reads after the call's synchronisation point.
 int validate_codes(halign_ctx *ctx, int alpha, const uint8_t *res, int64_t nres, const uint8_t *center, int m,
                    hipStream_t st) {
     RCHK(grow(ctx, ctx->counter, 256));
     int *flag = (int *)ctx->counter.p + 8;
     RCHK(launch_fill((uint32_t *)flag, 0u, 1, st));
     if (nres > 0)
-        hipLaunchKernelGGL(hk::maxcode_kernel, dim3(grid_for(nres, 256, 2048)), dim3(256), 0, st, res, nres, flag);
+        hipLaunchKernelGGL(hk::maxcode_kernel, dim3(grid_for((nres + 15) / 16, 256, 1024)), dim3(256), 0, st, res,
+                           nres, flag);
     if (center && m > 0)
-        hipLaunchKernelGGL(hk::maxcode_kernel, dim3(grid_for(m, 256, 64)), dim3(256), 0, st, center, (int64_t)m, flag);
+        hipLaunchKernelGGL(hk::maxcode_kernel, dim3(1), dim3(256), 0, st, center, (int64_t)m, flag);
     HCHK(hipGetLastError());
-    int h = 0;
-    HCHK(hipMemcpyAsync(&h, flag, 4, hipMemcpyDeviceToHost, st));
-    HCHK(hipStreamSynchronize(st));
+    HCHK(hipMemcpyAsync(ctx->flag_host, flag, 4, hipMemcpyDeviceToHost, st));
+    ctx->flag_alpha = alpha;
+    return HALIGN_OK;
+}
+
+// Call after the stream has synchronised past validate_codes().
+int validate_check(halign_ctx *ctx) {
+    if (!ctx->flag_alpha) return HALIGN_OK;
+    const int h = *ctx->flag_host, alpha = ctx->flag_alpha;
+    ctx->flag_alpha = 0;
     if (h >= alpha) return fail(HALIGN_E_INVALID, "residue code %d >= alphabet %d", h, alpha);
     return HALIGN_OK;
+}
+
+int validate_now(halign_ctx *ctx, int alpha, const uint8_t *res, int64_t nres, const uint8_t *center, int m,
+                 hipStream_t st) {
+    RCHK(validate_codes(ctx, alpha, res, nres, center, m, st));
+    HCHK(hipStreamSynchronize(st));
+    return validate_check(ctx);
 }
 
 int route_of(uint32_t flags, int m, int N) {
@@ -560,6 +641,10 @@ int halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out) 
     for (auto &e : ctx->ev) {
         if (hipEventCreate(&e) != hipSuccess) { halign_ctx_destroy(ctx); return fail(HALIGN_E_DEVICE, "event create"); }
     }
+    if (hipHostMalloc((void **)&ctx->flag_host, 64, hipHostMallocDefault) != hipSuccess) {
+        halign_ctx_destroy(ctx);
+        return fail(HALIGN_E_DEVICE, "pinned allocation");
+    }
     if (hipEventCreateWithFlags(&ctx->ev_stage, hipEventDisableTiming) != hipSuccess) {
         halign_ctx_destroy(ctx);
         return fail(HALIGN_E_DEVICE, "event create");
@@ -572,9 +657,10 @@ void halign_ctx_destroy(halign_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
-    for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf, &ctx->colbuf})
+    for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf, &ctx->colbuf, &ctx->sbuf})
         if (b->p) (void)hipFree(b->p);
     if (ctx->stage.p) (void)hipHostFree(ctx->stage.p);
+    if (ctx->flag_host) (void)hipHostFree(ctx->flag_host);
     for (auto &e : ctx->ev)
         if (e) (void)hipEventDestroy(e);
     if (ctx->ev_stage) (void)hipEventDestroy(ctx->ev_stage);
@@ -646,9 +732,13 @@ int halign_encode(const uint8_t *ascii, int64_t len, uint8_t *codes, void *strea
     return HALIGN_OK;
 }
 
-int halign_sw_batch(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *center, int32_t m,
-                    const halign_seqs *seqs, uint32_t flags, int32_t *score, int32_t *cells, uint16_t *ins,
-                    uint32_t *aligned, void *stream) {
+}  // extern "C"
+
+// halign_sw_batch without the final synchronisation: the code check is left
+// pending for the caller's next synchronisation point (validate_check).
+static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *center, int32_t m,
+                          const halign_seqs *seqs, uint32_t flags, int32_t *score, int32_t *cells, uint16_t *ins,
+                          uint32_t *aligned, void *stream) {
     if (!ctx) return fail(HALIGN_E_INVALID, "ctx is NULL");
     RCHK(check_scoring(sc));
     RCHK(check_seqs(seqs));
@@ -683,6 +773,19 @@ int halign_sw_batch(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *ce
         hipLaunchKernelGGL(hk::endcell_to_cells_kernel, dim3(grid_for(N, 256)), dim3(256), 0, st,
                            (const int32_t *)endcell, N, cells);
         HCHK(hipGetLastError());
+    }
+    return HALIGN_OK;
+}
+
+extern "C" {
+
+int halign_sw_batch(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *center, int32_t m,
+                    const halign_seqs *seqs, uint32_t flags, int32_t *score, int32_t *cells, uint16_t *ins,
+                    uint32_t *aligned, void *stream) {
+    RCHK(sw_batch_async(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream));
+    if (ctx->flag_alpha) {
+        HCHK(hipStreamSynchronize((hipStream_t)stream));
+        RCHK(validate_check(ctx));
     }
     return HALIGN_OK;
 }
@@ -729,16 +832,17 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const 
     hipStream_t st = (hipStream_t)stream;
     const int N = seqs->n;
     if (N == 0 || width == 0) return HALIGN_OK;
-    RCHK(grow(ctx, ctx->colbuf, (size_t)width * 8 + 256));
-    int32_t *cmap = (int32_t *)ctx->colbuf.p;
-    int32_t *coff = cmap + width;
-    hipLaunchKernelGGL(hk::colmap_kernel, dim3((m + 1 + 255) / 256), dim3(256), 0, st, G, col, m, cmap, coff);
+    RCHK(grow(ctx, ctx->colbuf, (size_t)width * 4 + 256));
+    uint32_t *cmap = (uint32_t *)ctx->colbuf.p;
+    hipLaunchKernelGGL(hk::colmap_kernel, dim3((m + 1 + 255) / 256), dim3(256), 0, st, G, col, m, cmap);
     HCHK(hipGetLastError());
-    const size_t lds = (size_t)(m + 1) * 8;
-    if (lds > ctx->lds_max) return fail(HALIGN_E_UNSUPPORTED, "center too long for row emission");
-    hipLaunchKernelGGL(hk::rows_kernel, dim3(N), dim3(256), lds, st, seqs->residues, seqs->offsets,
-                       (const int32_t *)nullptr, N, m, ins, aligned, (m + 31) / 32, (const int32_t *)cmap,
-                       (const int32_t *)coff, width, msa);
+    const size_t lds_rows = (size_t)(m + 1) * 8;
+    if (lds_rows > ctx->lds_max) return fail(HALIGN_E_UNSUPPORTED, "center too long for row emission");
+    const int cm_lds = lds_rows + (size_t)width * 4 <= 64 * 1024 ? 1 : 0;
+    const size_t lds = lds_rows + (cm_lds ? (size_t)width * 4 : 0);
+    const int grid = std::max(1, std::min(N, ctx->num_cu * 4));
+    hipLaunchKernelGGL(hk::rows_kernel, dim3(grid), dim3(256), lds, st, seqs->residues, seqs->offsets, N, m, ins,
+                       aligned, (m + 31) / 32, (const uint32_t *)cmap, width, cm_lds, msa);
     HCHK(hipGetLastError());
     return HALIGN_OK;
 }
@@ -835,7 +939,7 @@ int halign_center_exact(halign_ctx *ctx, const halign_scoring *sc, const halign_
     hipStream_t st = (hipStream_t)stream;
     Scoring S;
     RCHK(upload_matrix(ctx, sc, st, &S));
-    RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
+    RCHK(validate_now(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
     RCHK(launch_fill((uint32_t *)sums, 0u, 2 * (int64_t)N, st));
     std::vector<int32_t> perm = length_perm(seqs), gcen, gb0, gslot;
     // all pairs a' < b' in length order: the longer sequence is the lane's,
@@ -866,7 +970,7 @@ int halign_center_judge(halign_ctx *ctx, const halign_scoring *sc, const halign_
         if (hc[q] < 0 || hc[q] >= N) return fail(HALIGN_E_INVALID, "candidate %d out of range", hc[q]);
     Scoring S;
     RCHK(upload_matrix(ctx, sc, st, &S));
-    RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
+    RCHK(validate_now(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
     RCHK(launch_fill((uint32_t *)sums, 0u, 2 * (int64_t)ncand, st));
     std::vector<int32_t> perm = length_perm(seqs), gcen, gb0, gslot;
     for (int q = 0; q < ncand; ++q)
@@ -897,7 +1001,7 @@ int halign_sw_pairs(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs
     hipStream_t st = (hipStream_t)stream;
     Scoring S;
     RCHK(upload_matrix(ctx, sc, st, &S));
-    RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
+    RCHK(validate_now(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
     // group q: anchor q as the center, lanes = partners[64q .. 64q+63] (the
     // "perm" of the anchored mode), scores land at slot 64q + lane
     std::vector<int32_t> perm(partners_host, partners_host + np), gcen(anchors_host, anchors_host + nanchors),
@@ -991,11 +1095,12 @@ int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seq
     int32_t *G = (int32_t *)(wb + o_G);
     int64_t *col = (int64_t *)(wb + o_col);
     const uint8_t *cen = seqs->residues + oh[c];
-    RCHK(halign_sw_batch(ctx, sc, cen, m, seqs, HALIGN_TRACEBACK, score, cells, ins, al, stream));
+    RCHK(sw_batch_async(ctx, sc, cen, m, seqs, HALIGN_TRACEBACK, score, cells, ins, al, stream));
     hipLaunchKernelGGL(hk::center_row_kernel, dim3(1), dim3(256), 0, st, ins, al, c, m, aw);
     HCHK(hipGetLastError());
     int64_t width = 0;
-    RCHK(halign_merge(ctx, ins, N, m, G, col, &width, stream));
+    RCHK(halign_merge(ctx, ins, N, m, G, col, &width, stream));   // synchronises
+    RCHK(validate_check(ctx));
     uint8_t *out = (uint8_t *)alloc((size_t)N * (size_t)width, user);
     if (!out && width > 0) return fail(HALIGN_E_NOMEM, "allocator returned NULL for %lld bytes", (long long)(N * width));
     RCHK(halign_emit_rows(ctx, seqs, m, ins, al, G, col, width, out, stream));

@@ -31,13 +31,32 @@ __global__ void endcell_to_cells_kernel(const int32_t *endcell, int n, int32_t *
 }
 
 // Largest residue code in [p, p + n) -> *out (atomicMax; *out zeroed before).
-__global__ void maxcode_kernel(const uint8_t *p, int64_t n, int *out) {
+// 16-byte loads where aligned, one atomic per workgroup.
+__global__ void __launch_bounds__(256) maxcode_kernel(const uint8_t *p, int64_t n, int *out) {
+    __shared__ int red[4];
     int mx = 0;
-    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n;
-         x += (int64_t)gridDim.x * blockDim.x)
-        mx = max(mx, (int)p[x]);
+    const int64_t head = min<int64_t>(n, (int64_t)((16 - ((uintptr_t)p & 15)) & 15));
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    for (int64_t x = tid; x < head; x += stride) mx = max(mx, (int)p[x]);
+    const int64_t nv = (n - head) >> 4;
+    const uint4 *pv = reinterpret_cast<const uint4 *>(p + head);
+    for (int64_t x = tid; x < nv; x += stride) {
+        const uint4 q = pv[x];
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int y = 0; y < 4; ++y)
+            mx = max(mx, max(max((int)(w[y] & 255), (int)((w[y] >> 8) & 255)),
+                             max((int)((w[y] >> 16) & 255), (int)(w[y] >> 24))));
+    }
+    for (int64_t x = head + (nv << 4) + tid; x < n; x += stride) mx = max(mx, (int)p[x]);
     for (int sh = 32; sh > 0; sh >>= 1) mx = max(mx, __shfl_xor(mx, sh));
-    if ((threadIdx.x & 63) == 0 && mx > 0) atomicMax(out, mx);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const int b = max(max(red[0], red[1]), max(red[2], red[3]));
+        if (b > 0) atomicMax(out, b);
+    }
 }
 
 // ASCII -> residue code through a 256-entry table.
@@ -94,71 +113,92 @@ __global__ void __launch_bounds__(1024) merge_scan_kernel(const int32_t *G, int 
     if (tid == 1023) *width = part[1023] - 1;
 }
 
-// Column map: for every MSA column x, (p << 1) | 1 for the column of center
-// position p, (p << 1) for a column of gap block p; off[x] = offset in block.
-__global__ void colmap_kernel(const int32_t *G, const int64_t *col, int m, int32_t *cmap, int32_t *coff) {
+// Column map: for every MSA column x, cmap[x] = (p << 16) | t for offset t of
+// gap block p, or (p << 16) | 0xffff for the column of center position p.
+// (A gap block holds at most max_k ins_k[p] < 65535 columns.)
+__global__ void colmap_kernel(const int32_t *G, const int64_t *col, int m, uint32_t *cmap) {
     const int p = blockIdx.x * blockDim.x + threadIdx.x;
     if (p > m) return;
     const int64_t c0 = col[p];
     const int g = G[p];
-    for (int t = 0; t < g; ++t) { cmap[c0 + t] = p << 1; coff[c0 + t] = t; }
-    if (p < m) { cmap[c0 + g] = (p << 1) | 1; coff[c0 + g] = 0; }
+    for (int t = 0; t < g; ++t) cmap[c0 + t] = ((uint32_t)p << 16) | (uint32_t)t;
+    if (p < m) cmap[c0 + g] = ((uint32_t)p << 16) | 0xffffu;
 }
 
-// One workgroup per row: scan the row's (ins + aligned) to get the sequence
-// position where each block starts, then write the row column by column.
+// Rows: a workgroup keeps the column map in LDS (when it fits) and emits many
+// rows; per row it scans (ins + aligned) to find where each block starts in
+// the sequence, then writes the row four columns per store where aligned.
+__device__ __forceinline__ uint8_t row_byte(uint32_t cm, const int *spos, const int *sins, const uint32_t *ar,
+                                            const uint8_t *s, int n) {
+    const int p = (int)(cm >> 16), t = (int)(cm & 0xffffu);
+    uint8_t b = kGap;
+    if (t == 0xffff) {
+        const int q = spos[p] + sins[p];
+        if (((ar[p >> 5] >> (p & 31)) & 1u) && q < n) b = s[q];
+    } else {
+        const int q = spos[p] + t;
+        if (t < sins[p] && q < n) b = s[q];
+    }
+    return b;
+}
+
 __global__ void __launch_bounds__(256)
-rows_kernel(const uint8_t *res, const int64_t *off, const int32_t *rowids, int nrows, int m,
+rows_kernel(const uint8_t *res, const int64_t *off, int nrows, int m,
             const uint16_t *ins, const uint32_t *aligned, int aw,
-            const int32_t *cmap, const int32_t *coff, int64_t width, uint8_t *msa) {
-    extern __shared__ int spos[];    // [m+1] start of block p in s, then ins copy
-    int *sins = spos + (m + 1);
+            const uint32_t *cmap_g, int64_t width, int cmap_in_lds, uint8_t *msa) {
+    extern __shared__ int sh[];
+    int *spos = sh;                 // [m+1] start of block p in s
+    int *sins = spos + (m + 1);     // [m+1] ins copy
+    uint32_t *cml = reinterpret_cast<uint32_t *>(sins + (m + 1));   // [width] when in LDS
     __shared__ int partial[256];
-    const int r = blockIdx.x;
-    if (r >= nrows) return;
-    const int k = rowids ? rowids[r] : r;
-    const uint8_t *s = res + off[k];
-    const int n = (int)(off[k + 1] - off[k]);
-    const uint16_t *ir = ins + (int64_t)k * (m + 1);
-    const uint32_t *ar = aligned + (int64_t)k * aw;
     const int tid = threadIdx.x;
+    if (cmap_in_lds) {
+        for (int64_t x = tid; x < width; x += 256) cml[x] = cmap_g[x];
+    }
+    const uint32_t *cm = cmap_in_lds ? cml : cmap_g;
     const int m1 = m + 1;
     const int per = (m1 + 255) / 256;
     const int lo = min(m1, tid * per), hi = min(m1, lo + per);
-    int sum = 0;
-    for (int p = lo; p < hi; ++p) {
-        const int v = ir[p];
-        sins[p] = v;
-        sum += v + ((p < m) ? (int)((ar[p >> 5] >> (p & 31)) & 1u) : 0);
-    }
-    partial[tid] = sum;
-    __syncthreads();
-    for (int d = 1; d < 256; d <<= 1) {
-        const int v = tid >= d ? partial[tid - d] : 0;
-        __syncthreads();
-        partial[tid] += v;
-        __syncthreads();
-    }
-    int acc = tid > 0 ? partial[tid - 1] : 0;
-    for (int p = lo; p < hi; ++p) {
-        spos[p] = acc;
-        acc += sins[p] + ((p < m) ? (int)((ar[p >> 5] >> (p & 31)) & 1u) : 0);
-    }
-    __syncthreads();
-    uint8_t *row = msa + (int64_t)k * width;
-    for (int64_t x = tid; x < width; x += 256) {
-        const int cm = cmap[x];
-        const int p = cm >> 1;
-        uint8_t b = kGap;
-        if (cm & 1) {
-            const int q = spos[p] + sins[p];
-            if (((ar[p >> 5] >> (p & 31)) & 1u) && q < n) b = s[q];
-        } else {
-            const int t = coff[x];
-            const int q = spos[p] + t;
-            if (t < sins[p] && q < n) b = s[q];
+    for (int k = blockIdx.x; k < nrows; k += gridDim.x) {
+        const uint8_t *s = res + off[k];
+        const int n = (int)(off[k + 1] - off[k]);
+        const uint16_t *ir = ins + (int64_t)k * m1;
+        const uint32_t *ar = aligned + (int64_t)k * aw;
+        __syncthreads();   // previous row done with spos / sins
+        int sum = 0;
+        for (int p = lo; p < hi; ++p) {
+            const int v = ir[p];
+            sins[p] = v;
+            sum += v + ((p < m) ? (int)((ar[p >> 5] >> (p & 31)) & 1u) : 0);
         }
-        row[x] = b;
+        partial[tid] = sum;
+        __syncthreads();
+        for (int d = 1; d < 256; d <<= 1) {
+            const int v = tid >= d ? partial[tid - d] : 0;
+            __syncthreads();
+            partial[tid] += v;
+            __syncthreads();
+        }
+        int acc = tid > 0 ? partial[tid - 1] : 0;
+        for (int p = lo; p < hi; ++p) {
+            spos[p] = acc;
+            acc += sins[p] + ((p < m) ? (int)((ar[p >> 5] >> (p & 31)) & 1u) : 0);
+        }
+        __syncthreads();
+        uint8_t *row = msa + (int64_t)k * width;
+        const int64_t head = min<int64_t>(width, (int64_t)((4 - ((uintptr_t)row & 3)) & 3));
+        if (tid < head) row[tid] = row_byte(cm[tid], spos, sins, ar, s, n);
+        const int64_t nq = (width - head) >> 2;
+        uint32_t *rq = reinterpret_cast<uint32_t *>(row + head);
+        for (int64_t q = tid; q < nq; q += 256) {
+            const int64_t x = head + 4 * q;
+            const uint32_t v = (uint32_t)row_byte(cm[x], spos, sins, ar, s, n) |
+                               ((uint32_t)row_byte(cm[x + 1], spos, sins, ar, s, n) << 8) |
+                               ((uint32_t)row_byte(cm[x + 2], spos, sins, ar, s, n) << 16) |
+                               ((uint32_t)row_byte(cm[x + 3], spos, sins, ar, s, n) << 24);
+            rq[q] = v;
+        }
+        for (int64_t x = head + 4 * nq + tid; x < width; x += 256) row[x] = row_byte(cm[x], spos, sins, ar, s, n);
     }
 }
 

@@ -35,6 +35,14 @@ constexpr int kPad = 31;             // residue code of padding columns / alphab
 constexpr int kAlphaMax = 32;
 constexpr int kNegProf = -(1 << 22); // profile value of padding: never a source
 
+// v_max3_i32 (the compiler splits max(max(a,b),c) into a signed and an
+// unsigned max once it knows two operands are non-negative)
+__device__ __forceinline__ int vmax3(int a, int b, int c) {
+    int r;
+    asm("v_max3_i32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+    return r;
+}
+
 // shift the sign bit of d into the low end of w
 __device__ __forceinline__ uint32_t push_sign(uint32_t w, int d) {
     return __builtin_amdgcn_alignbit(w, (uint32_t)d, 31);
@@ -51,7 +59,7 @@ __device__ __forceinline__ int sw_cell(int &hg, int &e, int &diag, int &upg, int
     const int fext = upf - ge;
     const int fn = max(max(fext, upg), 0);
     const int hd = diag + p;
-    const int h = max(max(hd, en), fn);
+    const int h = vmax3(hd, en, fn);
     if (TB) {
         word = push_sign(word, upg - fext);   // fext
         word = push_sign(word, hg - eext);    // eext
@@ -75,150 +83,216 @@ __device__ __forceinline__ bool better(int h, int j, int i, const BestCell &b) {
 }
 
 // ---------------------------------------------------------------------------
-// Intra-task kernel: one pair per wavefront.  Lane l owns center rows
-// [row0 + l*R, row0 + l*R + R) of a pass of 64*R rows and works on column
-// j = k - l + 1 at step k (a skewed wavefront).  The bottom row of lane l-1
-// reaches lane l through DPP wave_shr:1 one step later; the residue stream
-// enters at lane 0 and moves down the same way.  Passes over m > 64*R chain
-// through a per-pair boundary row in global scratch.
+// Intra-task (wavefront) kernel: each wavefront streams a list of pairs.
+// Lane l owns center rows [row0 + l*R, row0 + l*R + R) of a pass of 64*R rows
+// and works on stream column K = k - l at step k (a skewed wavefront).  The
+// columns of the stream are the concatenated sequences of its pairs; a pair's
+// first column carries a flag (bit 7 of the staged residue) at which each
+// lane resets its row state to the column-0 boundary, so consecutive pairs
+// overlap in the pipeline and only the stream pays the 63-step fill/drain.
+// The bottom row of lane l-1 (Hg, F*) and the residue stream reach lane l
+// through DPP wave_shr:1.  Passes over m > 64*R run one after the other for
+// the whole workgroup; the boundary row between passes goes through global
+// scratch per stream.
 //
-// The query profile P[r][i] = S[c_i][r] + goe (int32, 32 x mpad) is built once
-// per workgroup in LDS and shared by its waves; wave w of the grid takes the
-// w-th pair of the (longest first) order.
+// Profile: P[r][t] = S[c_{row0+t}][r] + goe (int32, 32 x 64R) for the current
+// pass, in LDS, shared by the 8 waves of the workgroup.
 //
-// Codes: word (u32, R nibbles) per (pass, step k, lane):
-//   codes[cbase + (pass*(n+63) + k)*64 + lane], row t nibble at 4*(R-1-t).
+// End cell: when a lane leaves a pair it publishes its best cell as a 64-bit
+// key (H << 32 | (0xffff - j) << 16 | (0xffff - i)) with atomicMax, so the
+// pair's maximum over lanes and passes is max H, then min j, then min i,
+// independent of the order of the atomics.
+//
+// Codes: one u32 word (R nibbles, row t at bit 4*(R-1-t)) per (pass, step k,
+// lane), tiled so that a lane's 8 consecutive steps share 32 bytes: with
+// G = ceil((C+63)/8) groups per pass,
+//   codes[sbase + ((pass*G + k/8)*64 + lane)*8 + k%8].
+// Each lane stages its words in LDS and stores 32 B every 8 steps (2 KB per
+// wave per store, coalesced); the walk then finds a diagonal run of up to 8
+// steps in one line.  For a pair starting at stream column c0, cell (i, j)
+// is at step k = c0 + j - 1 + lane(i).
 // ---------------------------------------------------------------------------
-struct IntraArgs {
+constexpr uint8_t kFirstCol = 0x80;
+
+struct StreamArgs {
     const int8_t *mat;        // alpha x alpha
     int alpha;
     const uint8_t *center;    // m residues
-    int m, mpad, passes;
-    const uint8_t *res;
-    const int64_t *off;
-    const int32_t *order;     // pair indices, processing order
-    int npairs;
+    int m, passes;
+    const uint8_t *sres;      // staged stream residues (bit 7: first column of a pair)
+    const int64_t *sbeg;      // per stream: first column in sres (nstreams + 1 entries)
+    int nstreams;
     int ge, goe;
-    int *counter;             // work counter (zeroed before launch)
-    int32_t *score;           // [N]
-    int32_t *endcell;         // [N][2] (i1, j1) or null
-    uint32_t *codes;          // code words or null
-    const int64_t *code_base; // per pair (indexed by pair id) or null
-    int2 *bound;              // boundary rows for passes > 0
-    const int64_t *bound_base;// per pair or null
+    unsigned long long *keys; // per pair-slot end-cell keys (zeroed); score-only: H << 32
+    const int32_t *sslot0;    // per stream: slot of its first pair
+    uint32_t *codes;          // null: no traceback
+    const int64_t *scbase;    // per stream: code word base
+    int2 *bound;              // per stream boundary rows: (passes-1) * C entries
+    const int64_t *sbbase;    // per stream
 };
+
+__device__ __forceinline__ unsigned long long cell_key(const BestCell &b, bool endc) {
+    unsigned long long k = (unsigned long long)b.h << 32;
+    if (endc) k |= ((unsigned long long)(0xffff - b.j) << 16) | (unsigned long long)(0xffff - b.i);
+    return k;
+}
 
 template <int R, bool TB, bool ENDC>
 __global__ void __launch_bounds__(512)
-sw_intra_kernel(IntraArgs a) {
-    extern __shared__ int prof[];   // [32][mpad]
+sw_stream_kernel(StreamArgs a) {
+    extern __shared__ int prof[];   // [32][64R], then code staging [8 waves][64][8]
+    constexpr int SPAN = 64 * R;
+    uint32_t *stage = reinterpret_cast<uint32_t *>(prof + kAlphaMax * SPAN) + (threadIdx.x >> 6) * 512 +
+                      (threadIdx.x & 63) * 8;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int nthreads = blockDim.x;
-    // build P'[r][i] = S[c_i][r] + goe, padding -> kNegProf
-    for (int x = tid; x < kAlphaMax * a.mpad; x += nthreads) {
-        const int r = x / a.mpad, i = x - r * a.mpad;
-        int v = kNegProf;
-        if (r < a.alpha && i < a.m) v = (int)a.mat[a.center[i] * a.alpha + r] + a.goe;
-        prof[x] = v;
-    }
-    __syncthreads();
-
     const int ge = a.ge, goe = a.goe;
-    // one pair per wave, longest pairs in the lowest workgroups
-    const int w = blockIdx.x * (nthreads >> 6) + (tid >> 6);
-    if (w < a.npairs) {
-        // every lane loads the same value: readfirstlane only moves it to SGPRs
-        const int pid = __builtin_amdgcn_readfirstlane(a.order[w]);
-        const int64_t so = a.off[pid];
-        const int n = __builtin_amdgcn_readfirstlane((int)(a.off[pid + 1] - so));
-        const uint8_t *s = a.res + so;
-        const int steps = n + 63;
-        BestCell best{0, 0x7fffffff, 0x7fffffff};
-        int hmax = 0;
-        for (int pass = 0; pass < a.passes; ++pass) {
-            const int row0 = pass * 64 * R;
-            const int myrow = row0 + lane * R;
-            int hg[R], e[R];
-#pragma unroll
-            for (int t = 0; t < R; ++t) { hg[t] = -goe; e[t] = 0; }
-            int botg = -goe, botf = 0;  // this lane's bottom row values (last step)
-            int diag0 = -goe;           // Hg(myrow-1, j-1) for row 0
-            int rcur = kPad;            // residue of this lane's column
-            int rbuf = kPad;            // residues s[kb .. kb+63] across lanes
-            int2 bbuf = make_int2(-goe, 0);
-            const int2 *bin = (pass > 0) ? a.bound + a.bound_base[pid] + (int64_t)(pass - 1) * n : nullptr;
-            int2 *bout = (pass + 1 < a.passes) ? a.bound + a.bound_base[pid] + (int64_t)pass * n : nullptr;
-            uint32_t *cw = TB ? a.codes + a.code_base[pid] + (int64_t)pass * steps * 64 : nullptr;
-            const int *prow_base = prof + myrow;
-            for (int k = 0; k < steps; ++k) {
-                if ((k & 63) == 0) {
-                    const int kk = k + lane;
-                    rbuf = (kk < n) ? (int)(s[kk] & 31) : kPad;
-                    if (bin) bbuf = (kk < n) ? bin[kk] : make_int2(-goe, 0);
-                }
-                const int rin = __builtin_amdgcn_readlane(rbuf, k & 63);
-                int tg = -goe, tf = 0;
-                if (bin) {
-                    tg = __builtin_amdgcn_readlane(bbuf.x, k & 63);
-                    tf = __builtin_amdgcn_readlane(bbuf.y, k & 63);
-                }
-                // lane l <- lane l-1 (lane 0 keeps the boundary value)
-                rcur = __builtin_amdgcn_update_dpp(rin, rcur, 0x138, 0xf, 0xf, false);
-                int upg = __builtin_amdgcn_update_dpp(tg, botg, 0x138, 0xf, 0xf, false);
-                int upf = __builtin_amdgcn_update_dpp(tf, botf, 0x138, 0xf, 0xf, false);
-                int diag = diag0;
-                diag0 = upg;
-                const int *prow = prow_base + rcur * a.mpad;
-                int p[R];
-#pragma unroll
-                for (int t = 0; t < R; ++t) p[t] = prow[t];
-                uint32_t word = 0;
-                int colkey = 0;
-#pragma unroll
-                for (int t = 0; t < R; ++t) {
-                    const int h = sw_cell<TB>(hg[t], e[t], diag, upg, upf, p[t], ge, goe, word);
-                    if (ENDC) colkey = max(colkey, (h << 5) | (31 - t));
-                    else hmax = max(hmax, h);
-                }
-                botg = upg;
-                botf = upf;
-                const int j = k - lane + 1;
-                if (TB) cw[(int64_t)k * 64 + lane] = word;
-                if (bout && lane == 63 && j >= 1 && j <= n) bout[j - 1] = make_int2(botg, botf);
-                if (ENDC) {
-                    // later passes hold larger i: on equal H they win only with a smaller j
-                    const int ch = colkey >> 5;
-                    if (ch > 0 && (ch > best.h || (ch == best.h && j < best.j))) {
-                        best.h = ch;
-                        best.j = j;
-                        best.i = myrow + (31 - (colkey & 31));
-                    }
-                }
-            }
+    // the wave index is the same in all 64 lanes; readfirstlane makes that visible
+    const int sid = __builtin_amdgcn_readfirstlane(blockIdx.x * (nthreads >> 6) + (tid >> 6));
+    const bool active = sid < a.nstreams;
+    int64_t b0 = 0;
+    int C = 0, slot0 = 0;
+    if (active) {
+        b0 = a.sbeg[sid];
+        C = __builtin_amdgcn_readfirstlane((int)(a.sbeg[sid + 1] - b0));  // same in every lane
+        slot0 = __builtin_amdgcn_readfirstlane(a.sslot0[sid]);
+    }
+    const uint8_t *sr = a.sres + b0;
+    const int steps = C + 63;
+    for (int pass = 0; pass < a.passes; ++pass) {
+        const int row0 = pass * SPAN;
+        __syncthreads();
+        for (int x = tid; x < kAlphaMax * SPAN; x += nthreads) {
+            const int r = x / SPAN, i = row0 + (x - r * SPAN);
+            int v = kNegProf;
+            if (r < a.alpha && i < a.m) v = (int)a.mat[(a.center[i] & 31) * a.alpha + r] + goe;
+            prof[x] = v;
         }
-        if (ENDC) {
-            // wave reduction: max h, then min j, then min i
+        __syncthreads();
+        if (!active) continue;
+        const int myrow = row0 + lane * R;
+        int hg[R], e[R];
 #pragma unroll
-            for (int sh = 1; sh < 64; sh <<= 1) {
-                const int oh = __shfl_xor(best.h, sh);
-                const int oj = __shfl_xor(best.j, sh);
-                const int oi = __shfl_xor(best.i, sh);
-                if (better(oh, oj, oi, best)) { best.h = oh; best.j = oj; best.i = oi; }
+        for (int t = 0; t < R; ++t) { hg[t] = -goe; e[t] = 0; }
+        int botg = -goe, botf = 0;   // this lane's bottom row values (last step)
+        int diag0 = -goe;            // Hg(myrow-1, j-1) for row 0
+        int rcur = kPad;             // staged residue of this lane's column
+        int rbuf = kPad;             // staged residues of columns kb .. kb+63 across lanes
+        int2 bbuf = make_int2(-goe, 0);
+        const int2 *bin = (pass > 0) ? a.bound + a.sbbase[sid] + (int64_t)(pass - 1) * C : nullptr;
+        int2 *bout = (pass + 1 < a.passes) ? a.bound + a.sbbase[sid] + (int64_t)pass * C : nullptr;
+        const int G = (steps + 7) >> 3;
+        uint32_t *cw = TB ? a.codes + a.scbase[sid] + (int64_t)pass * G * 512 + lane * 8 : nullptr;
+        const int *pbase = prof + lane * R;
+        int pl = -1;                 // this lane's pair index within the stream
+        int jl = 0;                  // column index within that pair
+        BestCell best{0, 0x7fffffff, 0x7fffffff};
+        int hm = 0;
+        for (int k = 0; k < steps; ++k) {
+            if ((k & 63) == 0) {
+                const int kk = k + lane;
+                rbuf = (kk < C) ? (int)sr[kk] : kPad;
+                if (bin) bbuf = (kk < C) ? bin[kk] : make_int2(-goe, 0);
             }
-            if (lane == 0) {
-                a.score[pid] = best.h;
-                if (a.endcell) {
-                    a.endcell[2 * pid] = best.h > 0 ? best.i + 1 : 0;
-                    a.endcell[2 * pid + 1] = best.h > 0 ? best.j : 0;
+            const int rin = __builtin_amdgcn_readlane(rbuf, k & 63);
+            int tg = -goe, tf = 0;
+            if (bin) {
+                tg = __builtin_amdgcn_readlane(bbuf.x, k & 63);
+                tf = __builtin_amdgcn_readlane(bbuf.y, k & 63);
+            }
+            rcur = __builtin_amdgcn_update_dpp(rin, rcur, 0x138, 0xf, 0xf, false);
+            int upg = __builtin_amdgcn_update_dpp(tg, botg, 0x138, 0xf, 0xf, false);
+            int upf = __builtin_amdgcn_update_dpp(tf, botf, 0x138, 0xf, 0xf, false);
+            const int K = k - lane;  // stream column of this lane
+            if (rcur & kFirstCol) {
+                // leave the previous pair, enter the next one at its column 1
+                if (pl >= 0 && best.h > 0) atomicMax(a.keys + slot0 + pl, cell_key(best, ENDC));
+                ++pl;
+                jl = 0;
+                best.h = 0; best.j = 0x7fffffff; best.i = 0x7fffffff;
+#pragma unroll
+                for (int t = 0; t < R; ++t) { hg[t] = -goe; e[t] = 0; }
+                diag0 = -goe;
+            }
+            ++jl;
+            int diag = diag0;
+            diag0 = upg;
+            const int *prow = pbase + (rcur & 31) * SPAN;
+            int p[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) p[t] = prow[t];
+            uint32_t word = 0;
+            int colkey = 0;
+#pragma unroll
+            for (int t = 0; t < R; t += 2) {
+                const int h0 = sw_cell<TB>(hg[t], e[t], diag, upg, upf, p[t], ge, goe, word);
+                if (t + 1 < R) {
+                    const int h1 = sw_cell<TB>(hg[t + 1], e[t + 1], diag, upg, upf, p[t + 1], ge, goe, word);
+                    if (ENDC) colkey = vmax3(colkey, (h0 << 5) | (31 - t), (h1 << 5) | (30 - t));
+                    else hm = vmax3(hm, h0, h1);
+                } else {
+                    if (ENDC) colkey = max(colkey, (h0 << 5) | (31 - t));
+                    else hm = max(hm, h0);
                 }
             }
-        } else {
-#pragma unroll
-            for (int sh = 1; sh < 64; sh <<= 1) hmax = max(hmax, __shfl_xor(hmax, sh));
-            if (lane == 0) a.score[pid] = hmax;
+            botg = upg;
+            botf = upf;
+            if (TB) {
+                stage[k & 7] = word;
+                if ((k & 7) == 7 || k == steps - 1) {
+                    const uint4 lo = *reinterpret_cast<const uint4 *>(stage);
+                    const uint4 hi = *reinterpret_cast<const uint4 *>(stage + 4);
+                    uint4 *dst = reinterpret_cast<uint4 *>(cw + (int64_t)(k >> 3) * 512);
+                    dst[0] = lo;
+                    dst[1] = hi;
+                }
+            }
+            if (bout && lane == 63 && K >= 0 && K < C) bout[K] = make_int2(botg, botf);
+            if (ENDC) {
+                const int ch = colkey >> 5;
+                if (K >= 0 && K < C && ch > best.h) {
+                    best.h = ch;
+                    best.j = jl;
+                    best.i = myrow + (31 - (colkey & 31));
+                }
+            } else if (K >= 0 && K < C) {
+                best.h = max(best.h, hm);
+            }
+            hm = 0;
+            // last column of the stream: publish the last pair
+            if (K == C - 1 && pl >= 0 && best.h > 0) atomicMax(a.keys + slot0 + pl, cell_key(best, ENDC));
         }
     }
+}
+
+// keys -> score and end cell (i1, j1), 1-based; slot q belongs to pair pid[q].
+__global__ void decode_keys_kernel(const unsigned long long *keys, const int32_t *slot_pid, int nslots,
+                                   int32_t *score, int32_t *endcell) {
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nslots) return;
+    const unsigned long long k = keys[q];
+    const int pid = slot_pid[q];
+    const int h = (int)(k >> 32);
+    score[pid] = h;
+    if (endcell) {
+        endcell[2 * pid] = h > 0 ? (0xffff - (int)(k & 0xffff)) + 1 : 0;
+        endcell[2 * pid + 1] = h > 0 ? 0xffff - (int)((k >> 16) & 0xffff) : 0;
+    }
+}
+
+// Stage the residues of every stream: sres[sbase + c0(q) + x] = s_q[x], with
+// kFirstCol on x = 0.  One workgroup per pair slot.
+__global__ void stage_stream_kernel(const uint8_t *res, const int64_t *off, const int32_t *slot_pid,
+                                    const int64_t *slot_col, int nslots, uint8_t *sres) {
+    const int q = blockIdx.x;
+    if (q >= nslots) return;
+    const int pid = slot_pid[q];
+    const int64_t so = off[pid];
+    const int n = (int)(off[pid + 1] - so);
+    uint8_t *dst = sres + slot_col[q];
+    for (int x = threadIdx.x; x < n; x += blockDim.x)
+        dst[x] = (uint8_t)((res[so + x] & 31) | (x == 0 ? kFirstCol : 0));
 }
 
 // ---------------------------------------------------------------------------
@@ -232,9 +306,10 @@ sw_intra_kernel(IntraArgs a) {
 // per-workgroup scratch row, read with agent-scope loads so that no stale L1
 // line is seen.
 //
-// Codes: u64 (two u32 words: rows 0-7, 8-15) per (strip s, column j, lane):
-//   codes[gbase + ((s*nmax + j-1)*64 + lane)*2 + half], row t nibble at
-//   4*(7 - t%8).
+// Codes: u64 (two u32 words: rows 0-7, 8-15; row t nibble at 4*(7 - t%8))
+// per (strip s, column j, lane), tiled so that a lane's 4 consecutive columns
+// share 32 bytes: with G = ceil(nmax/4),
+//   codes[gbase + ((s*G + (j-1)/4)*64 + lane)*8 + ((j-1)%4)*2 + half].
 // ---------------------------------------------------------------------------
 constexpr int kT = 16;
 constexpr int kPS = kT + 4;  // LDS row stride of the strip profile
@@ -276,6 +351,7 @@ template <bool TB, bool ENDC>
 __global__ void __launch_bounds__(64)
 sw_inter_kernel(InterArgs a) {
     __shared__ int prof[kAlphaMax * kPS];
+    __shared__ uint32_t stage_all[64 * 8];
     __shared__ int8_t smat[kAlphaMax * kAlphaMax];
     const int lane = threadIdx.x;
     for (int x = lane; x < kAlphaMax * kAlphaMax; x += 64) {
@@ -324,7 +400,9 @@ sw_inter_kernel(InterArgs a) {
         m = __builtin_amdgcn_readfirstlane(m);        // same in every lane
         nmax = __builtin_amdgcn_readfirstlane(nmax);  // same in every lane
         const int nstrips = (m + kT - 1) / kT;
-        uint32_t *cw = TB ? a.codes + a.gcode_base[g] : nullptr;
+        const int G = (nmax + 3) >> 2;
+        uint32_t *cw = TB ? a.codes + a.gcode_base[g] + lane * 8 : nullptr;
+        uint32_t *stage = stage_all + lane * 8;
         BestCell best{0, 0x7fffffff, 0x7fffffff};
         int hmax = 0;
         for (int st = 0; st < nstrips; ++st) {
@@ -363,8 +441,16 @@ sw_inter_kernel(InterArgs a) {
                 }
                 if (st + 1 < nstrips) *bp = make_int2(upg, upf);
                 if (TB) {
-                    uint2 *dst = reinterpret_cast<uint2 *>(cw) + ((int64_t)st * nmax + (j - 1)) * 64 + lane;
-                    *dst = make_uint2(w0, w1);
+                    const int jj = (j - 1) & 3;
+                    stage[2 * jj] = w0;
+                    stage[2 * jj + 1] = w1;
+                    if (jj == 3 || j == nmax) {
+                        const uint4 lo = *reinterpret_cast<const uint4 *>(stage);
+                        const uint4 hi = *reinterpret_cast<const uint4 *>(stage + 4);
+                        uint4 *dst = reinterpret_cast<uint4 *>(cw + ((int64_t)st * G + ((j - 1) >> 2)) * 512);
+                        dst[0] = lo;
+                        dst[1] = hi;
+                    }
                 }
                 if (ENDC) {
                     // later strips hold larger i: on equal H they win only with a smaller j
@@ -408,6 +494,10 @@ sw_inter_kernel(InterArgs a) {
 // extend while the ext bit is set (open wins ties).  The running value is
 // H (or the gap value) of the current cell, kept exactly from the score.
 // Emits the center-star vector: ins[k][0..m], aligned bits, cells.
+//
+// Code words arrive in 32-byte chunks (8 steps of one lane of the wavefront
+// layout, or 4 columns of one lane of the strip layout) held in a two-entry
+// per-lane LDS cache, so a diagonal run costs one line fetch per chunk.
 // ---------------------------------------------------------------------------
 struct WalkArgs {
     const int8_t *mat;
@@ -422,10 +512,11 @@ struct WalkArgs {
     const int32_t *score;
     const int32_t *endcell;   // [N][2]
     const uint32_t *codes;
-    // layout descriptor per pair id: kind 0 = intra (R rows/lane), 1 = inter
-    const int64_t *cbase;     // word base per pair
-    const int32_t *cstride;   // intra: steps (n+63); inter: nmax
-    int R;                    // intra rows per lane
+    // layout per pair id: kind 0 = wavefront (R rows/lane), 1 = strip (16 rows)
+    const int64_t *cbase;     // word base of the stream / group
+    const int32_t *ccol;      // wavefront: first stream column of the pair; strip: lane in group
+    const int32_t *cstride;   // wavefront: steps per pass (C+63); strip: nmax of the group
+    int R;                    // wavefront rows per lane
     int kind;
     int32_t *cells;           // [N][4]
     uint16_t *ins;            // [N][m+1] (zeroed)
@@ -433,47 +524,108 @@ struct WalkArgs {
     int aw;
 };
 
-__device__ __forceinline__ uint32_t code_at(const WalkArgs &a, int64_t base, int stride, int i, int j) {
-    const int row = i - 1;
-    if (a.kind == 0) {
-        const int span = 64 * a.R;
-        const int pass = row / span;
-        const int rr = row - pass * span;
-        const int ln = rr / a.R, t = rr - ln * a.R;
-        const int k = j - 1 + ln;
-        const uint32_t w = a.codes[base + ((int64_t)pass * stride + k) * 64 + ln];
-        return (w >> (4 * (a.R - 1 - t))) & 15u;
-    } else {
-        const int st = row >> 4, t = row & 15;
-        const uint32_t w = a.codes[base + (((int64_t)st * stride + (j - 1)) * 64) * 2 + (t >> 3)];
-        return (w >> (4 * (7 - (t & 7)))) & 15u;
-    }
-}
+constexpr int kWalkCenterLds = 8192;   // centers up to this length are staged in LDS
 
-__global__ void __launch_bounds__(256)
+__global__ void __launch_bounds__(64)
 walk_kernel(WalkArgs a) {
-    const int w = blockIdx.x * blockDim.x + threadIdx.x;
+    __shared__ uint32_t cache[2][8][64];   // two 32-byte code chunks per lane
+    __shared__ int8_t smat[32 * 32];
+    __shared__ uint8_t scen[kWalkCenterLds];
+    const int lane = threadIdx.x;
+    const int m = a.m;
+    const bool cen_lds = m <= kWalkCenterLds;
+    for (int x = lane; x < 1024; x += 64) {
+        const int r = x >> 5, q = x & 31;
+        smat[x] = (r < a.alpha && q < a.alpha) ? a.mat[r * a.alpha + q] : (int8_t)0;
+    }
+    if (cen_lds)
+        for (int x = lane; x < m; x += 64) scen[x] = a.center[x] & 31;
+    __syncthreads();
+    const int w = blockIdx.x * 64 + lane;
     if (w >= a.npairs) return;
     const int pid = a.pids[w];
     const int64_t so = a.off[pid];
     const int n = (int)(a.off[pid + 1] - so);
-    const uint8_t *s = a.res + so;
-    const int m = a.m;
+    // s is read backwards through an aligned 16-byte chunk held in registers
+    // (an aligned 16-byte read that holds a valid byte cannot leave its page)
+    const uint8_t *sres0 = a.res;
+    int64_t schunk = -1;
+    uint4 sbuf = make_uint4(0, 0, 0, 0);
+    auto sres = [&](int jj) __attribute__((always_inline)) -> int {   // s[jj]
+        const int64_t g = so + jj;
+        const int64_t c = g >> 4;
+        if (c != schunk) {
+            schunk = c;
+            sbuf = *reinterpret_cast<const uint4 *>(sres0 + (c << 4));
+        }
+        const int b = (int)(g & 15);
+        const uint64_t q0 = (uint64_t)sbuf.x | ((uint64_t)sbuf.y << 32);
+        const uint64_t q1 = (uint64_t)sbuf.z | ((uint64_t)sbuf.w << 32);
+        const uint64_t q = (b & 8) ? q1 : q0;
+        return (int)((q >> (8 * (b & 7))) & 31u);
+    };
     uint16_t *ins = a.ins + (int64_t)pid * (m + 1);
     uint32_t *al = a.aligned + (int64_t)pid * a.aw;
     int v = a.score[pid];
+    int4 *cp = reinterpret_cast<int4 *>(a.cells) + pid;
     if (v <= 0) {
         ins[0] = (uint16_t)n;
-        int4 *cp = reinterpret_cast<int4 *>(a.cells) + pid;
         *cp = make_int4(0, 0, 0, 0);
         return;
     }
     const int i1 = a.endcell[2 * pid], j1 = a.endcell[2 * pid + 1];
     const int64_t base = a.cbase[pid];
+    const int ccol = a.ccol[pid];
     const int stride = a.cstride[pid];
+    const bool strip = a.kind != 0;
+    const int R = strip ? 16 : a.R;
+    const int G = strip ? (stride + 3) >> 2 : (stride + 7) >> 3;   // groups per pass / strip
     int i = i1, j = j1;
+    // row decomposition of i-1: block (pass*64 + lane, or strip) and row t in block
+    int blk = 0, t = 0;
+    {
+        const int row = i - 1;
+        if (strip) { blk = row >> 4; t = row & 15; }
+        else { const int span = 64 * R, ps = row / span, rr = row - ps * span; blk = ps * 64 + rr / R; t = rr % R; }
+    }
+    int tb0 = -1, tg0 = -1, tb1 = -1, tg1 = -1, victim = 0;
+    auto nibble = [&]() __attribute__((always_inline)) -> uint32_t {
+        int grp, wi;
+        int64_t addr;
+        if (strip) {
+            grp = (j - 1) >> 2;
+            wi = ((j - 1) & 3) * 2 + (t >> 3);
+            addr = base + (((int64_t)blk * G + grp) * 64 + ccol) * 8;
+        } else {
+            const int k = ccol + j - 1 + (blk & 63);
+            grp = k >> 3;
+            wi = k & 7;
+            addr = base + (((int64_t)(blk >> 6) * G + grp) * 64 + (blk & 63)) * 8;
+        }
+        int sl;
+        if (tb0 == blk && tg0 == grp) sl = 0;
+        else if (tb1 == blk && tg1 == grp) sl = 1;
+        else {
+            sl = victim;
+            victim ^= 1;
+            const uint4 lo = *reinterpret_cast<const uint4 *>(a.codes + addr);
+            const uint4 hi = *reinterpret_cast<const uint4 *>(a.codes + addr + 4);
+            cache[sl][0][lane] = lo.x; cache[sl][1][lane] = lo.y; cache[sl][2][lane] = lo.z; cache[sl][3][lane] = lo.w;
+            cache[sl][4][lane] = hi.x; cache[sl][5][lane] = hi.y; cache[sl][6][lane] = hi.z; cache[sl][7][lane] = hi.w;
+            if (sl == 0) { tb0 = blk; tg0 = grp; }
+            else { tb1 = blk; tg1 = grp; }
+        }
+        const uint32_t word = cache[sl][wi][lane];
+        const int sh = strip ? 4 * (7 - (t & 7)) : 4 * (R - 1 - t);
+        return (word >> sh) & 15u;
+    };
+    auto up = [&]() __attribute__((always_inline)) {   // i -> i - 1
+        --i;
+        if (--t < 0) { t = R - 1; --blk; }
+    };
     int state = 0;              // 0 = H, 1 = E, 2 = F
     int run = 0;                // pending insertions at row i
+    int insrow = -1, inssum = 0;
     int curw = -1;              // aligned word being accumulated
     uint32_t bits = 0;
     bool bad = (i1 < 1 || i1 > m || j1 < 1 || j1 > n);
@@ -485,7 +637,7 @@ walk_kernel(WalkArgs a) {
         if (state == 0) {
             if (v == 0) break;
             if (i < 1 || j < 1) { bad = true; break; }
-            const uint32_t nib = code_at(a, base, stride, i, j);
+            const uint32_t nib = nibble();
             if (!(nib & 1u)) {
                 const int p = i - 1;
                 const int wi = p >> 5;
@@ -495,8 +647,9 @@ walk_kernel(WalkArgs a) {
                     bits = 0;
                 }
                 bits |= 1u << (p & 31);
-                v -= (int)a.mat[a.center[i - 1] * a.alpha + s[j - 1]];
-                --i;
+                const int cr = cen_lds ? (int)scen[i - 1] : (int)(a.center[i - 1] & 31);
+                v -= (int)smat[cr * 32 + sres(j - 1)];
+                up();
                 --j;
             } else if (!(nib & 2u)) {
                 state = 1;
@@ -504,7 +657,7 @@ walk_kernel(WalkArgs a) {
                 state = 2;
             }
         } else if (state == 1) {
-            const uint32_t nib = code_at(a, base, stride, i, j);
+            const uint32_t nib = nibble();
             ++run;
             --j;
             if (nib & 4u) {
@@ -512,25 +665,31 @@ walk_kernel(WalkArgs a) {
             } else {
                 v += a.goe;
                 state = 0;
-                ins[i] = (uint16_t)(ins[i] + run);
+                if (insrow == i) {
+                    inssum += run;
+                } else {
+                    if (insrow >= 0) ins[insrow] = (uint16_t)inssum;
+                    insrow = i;
+                    inssum = run;
+                }
                 run = 0;
             }
         } else {
-            const uint32_t nib = code_at(a, base, stride, i, j);
-            --i;
+            const uint32_t nib = nibble();
+            up();
             if (nib & 8u) v += a.ge;
             else { v += a.goe; state = 0; }
         }
     }
     if (bad) {
-        int4 *cp = reinterpret_cast<int4 *>(a.cells) + pid;
         *cp = make_int4(-1, -1, -1, -1);
         return;
     }
+    if (insrow >= 0) ins[insrow] = (uint16_t)inssum;
     if (curw >= 0) al[curw] = bits;
-    ins[0] = (uint16_t)(ins[0] + j);
-    ins[m] = (uint16_t)(ins[m] + (n - j1));
-    int4 *cp = reinterpret_cast<int4 *>(a.cells) + pid;
+    // core insertions sit in slots 1..m-1, so slots 0 and m hold the flanks only
+    ins[0] = (uint16_t)j;
+    ins[m] = (uint16_t)(n - j1);
     *cp = make_int4(i, j, i1, j1);
 }
 

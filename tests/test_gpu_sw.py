@@ -137,6 +137,25 @@ def test_small_alphabet_ties(H, ctx):
             _compare(got, S, go, ge, center, seqs)
 
 
+@pytest.mark.parametrize("streams", [1, 2, 5])
+def test_stream_packing(H, ctx, streams, monkeypatch):
+    """Many pairs per wavefront: pair boundaries inside a stream reset the
+    state exactly; empty and 1-residue sequences sit between long ones."""
+    monkeypatch.setenv("HALIGN_MAX_STREAMS", str(streams))
+    rng = np.random.default_rng(streams)
+    base = synth.generate("plain64")
+    seqs = [base.seq(k) for k in range(64)]
+    for x in (3, 10, 11, 40):
+        seqs[x] = np.zeros(0, np.uint8)
+    for x in (5, 6, 7, 50):
+        seqs[x] = rng.integers(0, 20, size=1).astype(np.uint8)
+    ss = synth.SeqSet.from_list(seqs)
+    sc = H.Scoring()
+    for center in (base.seq(0), rng.integers(0, 20, size=700).astype(np.uint8)):
+        got = _run(H, ctx, sc, ss, center, "intra")
+        _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, center, ss)
+
+
 def test_deterministic_repeat(H, ctx):
     seqs = synth.generate("plain64")
     sc = H.Scoring()
@@ -188,3 +207,18 @@ def test_invalid_arguments(H, ctx):
     bad = H.Scoring(gap_open=-1)
     with pytest.raises(H.HalignError):
         H.halign_sw_batch(ctx, bad, ds.seq_ptr(0), ds.length(0), ds, 0, score)
+    # residue codes at or above the alphabet size are rejected (after a safe run)
+    res = seqs.residues.copy()
+    res[5] = 30
+    ds2 = H.DeviceSeqs(synth.SeqSet(res, seqs.offsets))
+    with pytest.raises(H.HalignError) as ei:
+        H.halign_sw_batch(ctx, sc, ds2.seq_ptr(0), ds2.length(0), ds2, H.HALIGN_TRACEBACK, score,
+                          torch.empty((4, 4), dtype=torch.int32, device="cuda"),
+                          torch.empty((4, ds2.length(0) + 1), dtype=torch.int16, device="cuda"),
+                          torch.empty((4, (ds2.length(0) + 31) // 32), dtype=torch.int32, device="cuda"))
+    assert ei.value.code == -1
+    with pytest.raises(H.HalignError):
+        H.halign_msa(ctx, sc, ds2, 1)
+    # the context stays usable
+    out = H.sw_batch(ctx, sc, ds, 0)
+    torch.cuda.synchronize()
