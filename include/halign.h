@@ -165,54 +165,87 @@ int halign_center_judge(halign_ctx *ctx, const halign_scoring *sc, const halign_
                         int32_t *center_host, void *stream);
 
 /* ---- learned center proposer (BF16 MLP on 3-mer counts) ------------------
- * Features: X[k][400a + 20b + c] = count of the 3-mer abc (codes < 20 only)
- * in sequence rows[k] (rows == NULL: k itself), stored as bf16 bit patterns,
- * nrows x HALIGN_FEAT. */
+ * Not in the paper: the paper's center is the sequence most similar to all
+ * others (exhaustive, O(N^2) alignments).  A small MLP proposes candidates
+ * whose exact sums of scores are then compared (halign_center_judge).
+ *
+ * Features: X[r][400a + 20b + c] = count of the 3-mer abc (codes < 20 only)
+ * in sequence rows[r] (rows == NULL: r), stored as bf16 bit patterns,
+ * nrows x HALIGN_FEAT, row-major. */
 #define HALIGN_FEAT 8000
 #define HALIGN_HID  256
 #define HALIGN_EMB  64
 int halign_featurize(const halign_seqs *seqs, const int32_t *rows, int32_t nrows,
                      uint16_t *X, void *stream);
 
-/* Model parameters (device).  W1: HALIGN_FEAT x HALIGN_HID bf16 bits
- * (row-major), b1: HALIGN_HID fp32, W2: HALIGN_HID x HALIGN_EMB bf16 bits,
- * b2: HALIGN_EMB fp32.  Forward: Hb = bf16(relu(X W1 + b1)),
- * E = Hb W2 + b2 (fp32 accumulation on MFMA). */
+/* Model for inference (device): W1 HALIGN_FEAT x HALIGN_HID bf16 bits
+ * (row-major), b1 HALIGN_HID fp32, W2 HALIGN_HID x HALIGN_EMB bf16 bits, b2
+ * HALIGN_EMB fp32.  Forward: Z = X W1 + b1, Hb = bf16(relu(Z)),
+ * E = Hb W2 + b2, products on MFMA with fp32 accumulation. */
 typedef struct {
     const uint16_t *W1; const float *b1;
     const uint16_t *W2; const float *b2;
 } halign_model;
 
-/* Hpre (fp32, nrows x HID, may be NULL), Hb (bf16 bits, nrows x HID) and
- * E (fp32, nrows x EMB) are outputs. */
-int halign_mlp_forward(const halign_model *model, const uint16_t *X, int32_t nrows,
-                       float *Hpre, uint16_t *Hb, float *E, void *stream);
+/* Z (fp32 nrows x HID, may be NULL), Hb (bf16 bits nrows x HID) and
+ * E (fp32 nrows x EMB) are outputs. */
+int halign_mlp_forward(halign_ctx *ctx, const halign_model *model, const uint16_t *X, int32_t nrows,
+                       float *Z, uint16_t *Hb, float *E, void *stream);
 
 /* Pair loss for pairs (r, r + npairs), r < npairs, of an E with 2*npairs rows:
- * pred = E[r].E[r+npairs], loss = mean (pred - target)^2.  Writes dE
+ * pred = E[r] . E[r + npairs], loss = mean (pred - target)^2.  Writes dE
  * (fp32, 2*npairs x EMB) and loss_out[0] (device fp32). */
-int halign_pair_loss(const float *E, const float *target, int32_t npairs,
+int halign_pair_loss(halign_ctx *ctx, const float *E, const float *target, int32_t npairs,
                      float *dE, float *loss_out, void *stream);
 
-/* Backward of halign_mlp_forward for dE: dW1 (fp32 FEAT x HID), db1 (HID),
- * dW2 (fp32 HID x EMB), db2 (EMB).  Hpre must come from the same forward. */
-int halign_mlp_backward(const halign_model *model, const uint16_t *X, int32_t nrows,
-                        const float *Hpre, const uint16_t *Hb, const float *dE,
+/* Backward of halign_mlp_forward for dE (Z and Hb from the same forward):
+ * dW1 (fp32 FEAT x HID), db1 (HID), dW2 (fp32 HID x EMB), db2 (EMB).  The
+ * GEMM operands dE and dZ are rounded to bf16; the bias gradients are the
+ * fp32 column sums of dE and dZ. */
+int halign_mlp_backward(halign_ctx *ctx, const halign_model *model, const uint16_t *X, int32_t nrows,
+                        const float *Z, const uint16_t *Hb, const float *dE,
                         float *dW1, float *db1, float *dW2, float *db2, void *stream);
 
-/* Adam on fp32 master weights p[n] with gradient g, moments m, v (step t >= 1,
- * bias-corrected); writes the bf16 copy pb when non-NULL. */
+/* Adam (bias-corrected, step t >= 1) on fp32 master weights p[n] with
+ * gradient g and moments m, v; writes the bf16 copy pb when non-NULL. */
 int halign_adam_step(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n,
                      float lr, float beta1, float beta2, float eps, int32_t t, void *stream);
 
-/* Candidate scores u_i = E_i . (sum_j E_j - E_i) and the top k indices
- * (largest u first, ties to the lower index) into top[k] (device int32). */
-int halign_topk_center(const float *E, int32_t nrows, int32_t k, float *u, int32_t *top,
-                       void *stream);
+/* Candidate scores u_i = E_i . (sum_j E_j - E_i) (fp32, fixed-order sums)
+ * and the top k indices (largest u first, ties to the lower index). */
+int halign_topk_center(halign_ctx *ctx, const float *E, int32_t nrows, int32_t k, float *u,
+                       int32_t *top, void *stream);
+
+/* Trainer.  Parameters (device): fp32 masters and their bf16 copies, updated
+ * in place.  Training pairs: `anchors` random sequences, each with 64 random
+ * partners (seeded), targets SW(a, b) / 100 from halign_sw_pairs; `epochs`
+ * passes of Adam over them in batches of `batch` pairs.  loss_host[e] gets
+ * the mean batch loss of epoch e (synchronises). */
+typedef struct {
+    float *W1, *b1, *W2, *b2;     /* fp32 masters */
+    uint16_t *W1b, *W2b;          /* bf16 copies read by the forward */
+} halign_params;
+typedef struct {
+    int32_t anchors;
+    int32_t batch;
+    int32_t epochs;
+    float lr;
+    uint64_t seed;
+} halign_train_opts;
+int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+                          const halign_train_opts *opts, const halign_params *params,
+                          float *loss_host, void *stream);
+
+/* Learned center: featurize and embed every sequence, take the top k by u,
+ * judge them exactly; *center_host = the best candidate (synchronises).
+ * cand_host (optional, k entries) receives the candidates. */
+int halign_center_learned(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+                          const halign_model *model, int32_t k, int32_t *cand_host,
+                          int32_t *center_host, void *stream);
 
 /* ---- end-to-end center-star MSA -------------------------------------------
  * center >= 0: that sequence index; HALIGN_CENTER_EXACT: exhaustive search;
- * HALIGN_CENTER_LEARNED: top-16 of `model`, judged exactly.
+ * HALIGN_CENTER_LEARNED: top-16 of `model` (halign_center_learned).
  * The MSA buffer (N x width bytes) is obtained from alloc(bytes, user), since
  * width is known only after the merge; *msa receives it. */
 typedef void *(*halign_alloc_fn)(size_t bytes, void *user);

@@ -52,6 +52,16 @@ class _Model(ctypes.Structure):
                 ("W2", ctypes.c_void_p), ("b2", ctypes.c_void_p)]
 
 
+class _Params(ctypes.Structure):
+    _fields_ = [("W1", ctypes.c_void_p), ("b1", ctypes.c_void_p), ("W2", ctypes.c_void_p),
+                ("b2", ctypes.c_void_p), ("W1b", ctypes.c_void_p), ("W2b", ctypes.c_void_p)]
+
+
+class _TrainOpts(ctypes.Structure):
+    _fields_ = [("anchors", ctypes.c_int32), ("batch", ctypes.c_int32), ("epochs", ctypes.c_int32),
+                ("lr", ctypes.c_float), ("seed", ctypes.c_uint64)]
+
+
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
 
 _lib = None
@@ -82,12 +92,14 @@ def lib():
         "halign_center_exact": ([P, P, P, P, P, P], I),
         "halign_center_judge": ([P, P, P, P, I, P, P, P], I),
         "halign_featurize": ([P, P, I, P, P], I),
-        "halign_mlp_forward": ([P, P, I, P, P, P, P], I),
-        "halign_pair_loss": ([P, P, I, P, P, P], I),
-        "halign_mlp_backward": ([P, P, I, P, P, P, P, P, P, P, P], I),
+        "halign_mlp_forward": ([P, P, P, I, P, P, P, P], I),
+        "halign_pair_loss": ([P, P, P, I, P, P, P], I),
+        "halign_mlp_backward": ([P, P, P, I, P, P, P, P, P, P, P, P], I),
         "halign_adam_step": ([P, P, P, P, P, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, I, P], I),
-        "halign_topk_center": ([P, I, I, P, P, P], I),
+        "halign_topk_center": ([P, P, I, I, P, P, P], I),
+        "halign_train_proposer": ([P, P, P, P, P, P, P], I),
+        "halign_center_learned": ([P, P, P, P, I, P, P, P], I),
         "halign_msa": ([P, P, P, I, P, _ALLOC_FN, P, P, P, P, P], I),
         "halign_sp_score": ([P, P, I, I64, P, P], I),
     }
@@ -311,3 +323,89 @@ def aligned_to_bool(aligned_words: np.ndarray, m: int) -> np.ndarray:
     w = np.ascontiguousarray(aligned_words).view(np.uint32)
     bits = (w[:, :, None] >> np.arange(32, dtype=np.uint32)[None, None, :]) & 1
     return bits.reshape(w.shape[0], -1)[:, :m].astype(np.uint8)
+
+
+# ---------------------------------------------------------------------------
+# Learned center proposer
+# ---------------------------------------------------------------------------
+class Proposer:
+    """MLP parameters on the GPU: fp32 masters and the bf16 copies the
+    forward reads.  Initialised He-uniform from a seed (host numpy)."""
+
+    def __init__(self, seed: int = 1, device: str = "cuda", params=None):
+        import torch
+        if params is None:
+            rng = np.random.default_rng(seed)
+            l1, l2 = np.sqrt(6.0 / FEAT), np.sqrt(6.0 / HID)
+            params = (rng.uniform(-l1, l1, size=(FEAT, HID)).astype(np.float32), np.zeros(HID, np.float32),
+                      rng.uniform(-l2, l2, size=(HID, EMB)).astype(np.float32), np.zeros(EMB, np.float32))
+        W1, b1, W2, b2 = [torch.from_numpy(np.ascontiguousarray(x, dtype=np.float32)).to(device) for x in params]
+        self.W1, self.b1, self.W2, self.b2 = W1, b1, W2, b2
+        self.W1b = torch.empty(W1.shape, dtype=torch.int16, device=device)
+        self.W2b = torch.empty(W2.shape, dtype=torch.int16, device=device)
+        self.refresh_bf16()
+
+    def refresh_bf16(self):
+        import torch
+        for src, dst in ((self.W1, self.W1b), (self.W2, self.W2b)):
+            u = src.contiguous().view(torch.int32).to(torch.int64) & 0xFFFFFFFF
+            r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF
+            dst.copy_(r.to(torch.int32).to(torch.int16))
+
+    def model(self):
+        m = _Model(self.W1b.data_ptr(), self.b1.data_ptr(), self.W2b.data_ptr(), self.b2.data_ptr())
+        self._c = m
+        return m
+
+    def params(self):
+        return _Params(self.W1.data_ptr(), self.b1.data_ptr(), self.W2.data_ptr(), self.b2.data_ptr(),
+                       self.W1b.data_ptr(), self.W2b.data_ptr())
+
+
+def halign_featurize(seqs: DeviceSeqs, X, rows=None, nrows=None, stream=None):
+    n = seqs.n if rows is None else rows.numel()
+    _check(lib().halign_featurize(seqs.ref, _ptr(rows), n if nrows is None else nrows, _ptr(X), _stream(stream)))
+
+
+def halign_mlp_forward(ctx: Context, prop: Proposer, X, nrows: int, Z, Hb, E, stream=None):
+    m = prop.model()
+    _check(lib().halign_mlp_forward(ctx.h, ctypes.byref(m), _ptr(X), nrows, _ptr(Z), _ptr(Hb), _ptr(E),
+                                    _stream(stream)))
+
+
+def halign_pair_loss(ctx: Context, E, target, npairs: int, dE, loss, stream=None):
+    _check(lib().halign_pair_loss(ctx.h, _ptr(E), _ptr(target), npairs, _ptr(dE), _ptr(loss), _stream(stream)))
+
+
+def halign_mlp_backward(ctx: Context, prop: Proposer, X, nrows: int, Z, Hb, dE, dW1, db1, dW2, db2, stream=None):
+    m = prop.model()
+    _check(lib().halign_mlp_backward(ctx.h, ctypes.byref(m), _ptr(X), nrows, _ptr(Z), _ptr(Hb), _ptr(dE),
+                                     _ptr(dW1), _ptr(db1), _ptr(dW2), _ptr(db2), _stream(stream)))
+
+
+def halign_adam_step(p, g, m, v, pb, lr, b1, b2, eps, t, stream=None):
+    _check(lib().halign_adam_step(_ptr(p), _ptr(g), _ptr(m), _ptr(v), _ptr(pb), p.numel(), lr, b1, b2, eps, t,
+                                  _stream(stream)))
+
+
+def halign_topk_center(ctx: Context, E, nrows: int, k: int, u, top, stream=None):
+    _check(lib().halign_topk_center(ctx.h, _ptr(E), nrows, k, _ptr(u), _ptr(top), _stream(stream)))
+
+
+def halign_train_proposer(ctx: Context, sc: Scoring, seqs: DeviceSeqs, prop: Proposer, anchors: int,
+                          batch: int = 1024, epochs: int = 4, lr: float = 1e-3, seed: int = 7, stream=None):
+    opts = _TrainOpts(anchors, batch, epochs, lr, seed)
+    pr = prop.params()
+    losses = (ctypes.c_float * epochs)()
+    _check(lib().halign_train_proposer(ctx.h, sc.ref, seqs.ref, ctypes.byref(opts), ctypes.byref(pr), losses,
+                                       _stream(stream)))
+    return list(losses)
+
+
+def halign_center_learned(ctx: Context, sc: Scoring, seqs: DeviceSeqs, prop: Proposer, k: int = 16, stream=None):
+    cand = (ctypes.c_int32 * k)()
+    c = ctypes.c_int32(-1)
+    m = prop.model()
+    _check(lib().halign_center_learned(ctx.h, sc.ref, seqs.ref, ctypes.byref(m), k, cand, ctypes.byref(c),
+                                       _stream(stream)))
+    return int(c.value), list(cand)[: min(k, seqs.n)]

@@ -66,6 +66,7 @@ struct halign_ctx {
     size_t lds_max = 65536;
     // device scratch
     DevBuf codes, bound, plan, counter, pairbuf, msabuf, spbuf, colbuf, sbuf;
+    DevBuf mlp[10];          // learned-center scratch (features, activations, gradients, moments)
     // pinned host staging for plans
     HostBuf stage;
     hipEvent_t ev_stage = nullptr;
@@ -659,6 +660,8 @@ void halign_ctx_destroy(halign_ctx *ctx) {
     (void)hipDeviceSynchronize();
     for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf, &ctx->colbuf, &ctx->sbuf})
         if (b->p) (void)hipFree(b->p);
+    for (DevBuf &b : ctx->mlp)
+        if (b.p) (void)hipFree(b.p);
     if (ctx->stage.p) (void)hipHostFree(ctx->stage.p);
     if (ctx->flag_host) (void)hipHostFree(ctx->flag_host);
     for (auto &e : ctx->ev)
@@ -1045,15 +1048,6 @@ int halign_sp_score(const halign_scoring *sc, const uint8_t *msa, int32_t n, int
     return HALIGN_OK;
 }
 
-}  // extern "C"
-
-namespace {
-int center_learned(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, const halign_model *model,
-                   int k, int32_t *center_host, hipStream_t st);
-}
-
-extern "C" {
-
 int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, int32_t center,
                const halign_model *model, halign_alloc_fn alloc, void *user, uint8_t **msa, int64_t *width_host,
                int32_t *center_out_host, void *stream) {
@@ -1070,7 +1064,7 @@ int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seq
         RCHK(halign_center_exact(ctx, sc, seqs, (int64_t *)ctx->msabuf.p, &c, stream));
     } else if (center == HALIGN_CENTER_LEARNED) {
         if (!model) return fail(HALIGN_E_INVALID, "learned center needs a model");
-        RCHK(center_learned(ctx, sc, seqs, model, 16, &c, st));
+        RCHK(halign_center_learned(ctx, sc, seqs, model, 16, nullptr, &c, stream));
     } else if (center < 0 || center >= N) {
         return fail(HALIGN_E_INVALID, "center %d out of range", center);
     }
@@ -1112,10 +1106,333 @@ int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seq
 
 }  // extern "C"
 
+// ===========================================================================
+// Learned center proposer
+// ===========================================================================
 namespace {
-int center_learned(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, const halign_model *model,
-                   int k, int32_t *center_host, hipStream_t st) {
-    (void)ctx; (void)sc; (void)seqs; (void)model; (void)k; (void)center_host; (void)st;
-    return fail(HALIGN_E_UNSUPPORTED, "learned center not built yet");
+
+template <bool TA, bool TB, int EPI>
+int gemm(const hk::GemmArgs &g, hipStream_t st) {
+    if (g.M <= 0 || g.N <= 0) return HALIGN_OK;
+    dim3 grid((g.N + 63) / 64, (g.M + 63) / 64);
+    if (grid.y > 65535) return fail(HALIGN_E_UNSUPPORTED, "GEMM with %d rows", g.M);
+    hipLaunchKernelGGL((hk::gemm_bf16_kernel<TA, TB, EPI>), grid, dim3(256), 0, st, g);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
 }
+
+// fixed-order column sums of a rows x cols fp32 matrix into out[cols]
+int colsum(halign_ctx *ctx, DevBuf &scratch, const float *A, int rows, int cols, int lda, float *out, hipStream_t st) {
+    const int nblk = std::max(1, (rows + 1023) / 1024);
+    RCHK(grow(ctx, scratch, (size_t)nblk * cols * 4 + 256));
+    float *part = (float *)scratch.p;
+    if (rows > 0) {
+        hipLaunchKernelGGL(hk::colsum_partial_kernel, dim3((cols + 255) / 256, nblk), dim3(256), 0, st, A, rows, cols,
+                           lda, part);
+    } else {
+        RCHK(launch_fill((uint32_t *)part, 0u, cols, st));
+    }
+    hipLaunchKernelGGL(hk::colsum_final_kernel, dim3((cols + 255) / 256), dim3(256), 0, st, (const float *)part,
+                       rows > 0 ? nblk : 1, cols, out);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
+}
+
+uint64_t splitmix(uint64_t &s) {
+    uint64_t z = (s += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+int check_model(const halign_model *md) {
+    if (!md || !md->W1 || !md->b1 || !md->W2 || !md->b2) return fail(HALIGN_E_INVALID, "model pointers are NULL");
+    return HALIGN_OK;
+}
+
 }  // namespace
+
+extern "C" {
+
+int halign_featurize(const halign_seqs *seqs, const int32_t *rows, int32_t nrows, uint16_t *X, void *stream) {
+    if (!seqs || nrows < 0 || (nrows > 0 && !X)) return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_seqs(seqs));
+    if (!rows && nrows > seqs->n) return fail(HALIGN_E_INVALID, "nrows > N");
+    if (nrows == 0) return HALIGN_OK;
+    hipLaunchKernelGGL(hk::featurize_kernel, dim3(nrows), dim3(256), 0, (hipStream_t)stream, seqs->residues,
+                       seqs->offsets, rows, nrows, X);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
+}
+
+int halign_mlp_forward(halign_ctx *ctx, const halign_model *model, const uint16_t *X, int32_t nrows, float *Z,
+                       uint16_t *Hb, float *E, void *stream) {
+    if (!ctx || nrows < 0 || (nrows > 0 && (!X || !Hb || !E))) return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_model(model));
+    hipStream_t st = (hipStream_t)stream;
+    hk::GemmArgs g1{};
+    g1.A = X; g1.B = model->W1; g1.M = nrows; g1.N = hk::kHid; g1.K = hk::kFeat; g1.lda = hk::kFeat; g1.ldb = hk::kHid;
+    g1.C = Z; g1.ldc = hk::kHid; g1.bias = model->b1; g1.Cb = Hb; g1.ldcb = hk::kHid;
+    RCHK((gemm<false, false, 1>(g1, st)));
+    hk::GemmArgs g2{};
+    g2.A = Hb; g2.B = model->W2; g2.M = nrows; g2.N = hk::kEmb; g2.K = hk::kHid; g2.lda = hk::kHid; g2.ldb = hk::kEmb;
+    g2.C = E; g2.ldc = hk::kEmb; g2.bias = model->b2;
+    RCHK((gemm<false, false, 0>(g2, st)));
+    return HALIGN_OK;
+}
+
+int halign_pair_loss(halign_ctx *ctx, const float *E, const float *target, int32_t npairs, float *dE,
+                     float *loss_out, void *stream) {
+    if (!ctx || npairs < 0 || (npairs > 0 && (!E || !target || !dE || !loss_out)))
+        return fail(HALIGN_E_INVALID, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    RCHK(grow(ctx, ctx->mlp[0], (size_t)npairs * 4 + (size_t)2 * npairs * hk::kEmb * 2 + 512));
+    float *sq = (float *)ctx->mlp[0].p;
+    uint16_t *dEb = (uint16_t *)((char *)ctx->mlp[0].p + (((size_t)npairs * 4 + 255) & ~size_t(255)));
+    if (npairs > 0) {
+        hipLaunchKernelGGL(hk::pair_loss_kernel, dim3((npairs + 255) / 256), dim3(256), 0, st, E, target, npairs, dE,
+                           dEb, sq);
+        HCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(hk::mean_kernel, dim3(1), dim3(256), 0, st, (const float *)sq, npairs, loss_out);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
+}
+
+int halign_mlp_backward(halign_ctx *ctx, const halign_model *model, const uint16_t *X, int32_t nrows, const float *Z,
+                        const uint16_t *Hb, const float *dE, float *dW1, float *db1, float *dW2, float *db2,
+                        void *stream) {
+    if (!ctx || nrows < 0 || !dW1 || !db1 || !dW2 || !db2 || (nrows > 0 && (!X || !Z || !Hb || !dE)))
+        return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_model(model));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t b_dEb = ((size_t)nrows * hk::kEmb * 2 + 255) & ~size_t(255);
+    const size_t b_dZ = ((size_t)nrows * hk::kHid * 4 + 255) & ~size_t(255);
+    const size_t b_dZb = ((size_t)nrows * hk::kHid * 2 + 255) & ~size_t(255);
+    RCHK(grow(ctx, ctx->mlp[1], b_dEb + b_dZ + b_dZb + 256));
+    uint16_t *dEb = (uint16_t *)ctx->mlp[1].p;
+    float *dZ = (float *)((char *)ctx->mlp[1].p + b_dEb);
+    uint16_t *dZb = (uint16_t *)((char *)ctx->mlp[1].p + b_dEb + b_dZ);
+    if (nrows > 0) {
+        hipLaunchKernelGGL(hk::f32_to_bf16_kernel, dim3(grid_for((int64_t)nrows * hk::kEmb, 256, 4096)), dim3(256), 0,
+                           st, dE, dEb, (int64_t)nrows * hk::kEmb);
+        HCHK(hipGetLastError());
+    }
+    hk::GemmArgs a{};
+    // dW2 = Hb^T dEb
+    a.A = Hb; a.B = dEb; a.M = hk::kHid; a.N = hk::kEmb; a.K = nrows; a.lda = hk::kHid; a.ldb = hk::kEmb;
+    a.C = dW2; a.ldc = hk::kEmb;
+    if (nrows > 0) RCHK((gemm<true, false, 0>(a, st)));
+    else RCHK(launch_fill((uint32_t *)dW2, 0u, (int64_t)hk::kHid * hk::kEmb, st));
+    RCHK(colsum(ctx, ctx->mlp[2], dE, nrows, hk::kEmb, hk::kEmb, db2, st));
+    // dZ = (dEb W2^T) * (Z > 0)
+    hk::GemmArgs b{};
+    b.A = dEb; b.B = model->W2; b.M = nrows; b.N = hk::kHid; b.K = hk::kEmb; b.lda = hk::kEmb; b.ldb = hk::kEmb;
+    b.C = dZ; b.ldc = hk::kHid; b.Cb = dZb; b.ldcb = hk::kHid; b.Hpre = Z; b.ldh = hk::kHid;
+    RCHK((gemm<false, true, 2>(b, st)));
+    RCHK(colsum(ctx, ctx->mlp[2], dZ, nrows, hk::kHid, hk::kHid, db1, st));
+    // dW1 = X^T dZb
+    hk::GemmArgs c{};
+    c.A = X; c.B = dZb; c.M = hk::kFeat; c.N = hk::kHid; c.K = nrows; c.lda = hk::kFeat; c.ldb = hk::kHid;
+    c.C = dW1; c.ldc = hk::kHid;
+    if (nrows > 0) RCHK((gemm<true, false, 0>(c, st)));
+    else RCHK(launch_fill((uint32_t *)dW1, 0u, (int64_t)hk::kFeat * hk::kHid, st));
+    return HALIGN_OK;
+}
+
+int halign_adam_step(float *p, const float *g, float *m, float *v, uint16_t *pb, int64_t n, float lr, float beta1,
+                     float beta2, float eps, int32_t t, void *stream) {
+    if (n < 0 || t < 1 || (n > 0 && (!p || !g || !m || !v))) return fail(HALIGN_E_INVALID, "bad arguments");
+    if (n == 0) return HALIGN_OK;
+    const float c1 = 1.f - powf(beta1, (float)t), c2 = 1.f - powf(beta2, (float)t);
+    hipLaunchKernelGGL(hk::adam_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, (hipStream_t)stream, p, g, m, v, pb,
+                       n, lr, beta1, beta2, eps, c1, c2);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
+}
+
+int halign_topk_center(halign_ctx *ctx, const float *E, int32_t nrows, int32_t k, float *u, int32_t *top,
+                       void *stream) {
+    if (!ctx || !E || !u || !top || nrows <= 0 || k <= 0 || k > nrows || k > 256)
+        return fail(HALIGN_E_INVALID, "bad arguments (1 <= k <= min(N, 256))");
+    hipStream_t st = (hipStream_t)stream;
+    RCHK(grow(ctx, ctx->mlp[3], 4096));
+    float *S = (float *)ctx->mlp[3].p;
+    RCHK(colsum(ctx, ctx->mlp[2], E, nrows, hk::kEmb, hk::kEmb, S, st));
+    hipLaunchKernelGGL(hk::center_score_kernel, dim3((nrows + 255) / 256), dim3(256), 0, st, E, (const float *)S, nrows,
+                       u);
+    HCHK(hipGetLastError());
+    // rounds of block top-k until one block holds everything
+    int n = nrows;
+    const float *val = u;
+    const int32_t *idx = nullptr;
+    int round = 0;
+    for (;;) {
+        const int nblk = (n + hk::kTopkChunk - 1) / hk::kTopkChunk;
+        const size_t need = (size_t)nblk * k * 8 + 512;
+        DevBuf &buf = ctx->mlp[4 + (round & 1)];
+        RCHK(grow(ctx, buf, need));
+        float *ov = (float *)buf.p;
+        int32_t *oi = (int32_t *)((char *)buf.p + (((size_t)nblk * k * 4 + 255) & ~size_t(255)));
+        hipLaunchKernelGGL(hk::topk_kernel, dim3(nblk), dim3(256), 0, st, val, idx, n, k, ov, oi);
+        HCHK(hipGetLastError());
+        if (nblk == 1) {
+            HCHK(hipMemcpyAsync(top, oi, 4 * (size_t)k, hipMemcpyDeviceToDevice, st));
+            break;
+        }
+        val = ov;
+        idx = oi;
+        n = nblk * k;
+        ++round;
+    }
+    return HALIGN_OK;
+}
+
+int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+                          const halign_train_opts *opts, const halign_params *pr, float *loss_host, void *stream) {
+    if (!ctx || !opts || !pr || !pr->W1 || !pr->b1 || !pr->W2 || !pr->b2 || !pr->W1b || !pr->W2b)
+        return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_scoring(sc));
+    RCHK(check_seqs(seqs));
+    const int N = seqs->n;
+    if (N < 2 || opts->anchors <= 0 || opts->batch <= 0 || opts->epochs <= 0)
+        return fail(HALIGN_E_INVALID, "need N >= 2 and positive anchors, batch, epochs");
+    hipStream_t st = (hipStream_t)stream;
+    HCHK(hipSetDevice(ctx->device));
+    // training pairs: anchors with 64 partners each (never the anchor itself)
+    uint64_t rs = opts->seed;
+    const int A = opts->anchors;
+    const int P = A * 64;
+    std::vector<int32_t> anc(A), par(P);
+    for (int q = 0; q < A; ++q) anc[q] = (int32_t)(splitmix(rs) % (uint64_t)N);
+    for (int q = 0; q < P; ++q) {
+        int32_t b;
+        do { b = (int32_t)(splitmix(rs) % (uint64_t)N); } while (b == anc[q / 64]);
+        par[q] = b;
+    }
+    // scratch layout in mlp[6]: scores, targets, batch index lists, X_all
+    const int B = std::min(opts->batch, P);
+    const int steps_per_epoch = P / B;
+    const int nsteps = steps_per_epoch * opts->epochs;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t r = off; off = (off + bytes + 255) & ~size_t(255); return r; };
+    const size_t o_score = take(4 * (size_t)P), o_tgt = take(4 * (size_t)P), o_idx = take(4 * (size_t)nsteps * 2 * B),
+                 o_tix = take(4 * (size_t)nsteps * B), o_tb = take(4 * (size_t)B), o_loss = take(4 * (size_t)nsteps),
+                 o_X = take(2 * (size_t)N * hk::kFeat), o_Xb = take(2 * (size_t)2 * B * hk::kFeat),
+                 o_Z = take(4 * (size_t)2 * B * hk::kHid), o_Hb = take(2 * (size_t)2 * B * hk::kHid),
+                 o_E = take(4 * (size_t)2 * B * hk::kEmb), o_dE = take(4 * (size_t)2 * B * hk::kEmb),
+                 o_g = take(4 * (size_t)(hk::kFeat * hk::kHid + hk::kHid + hk::kHid * hk::kEmb + hk::kEmb)),
+                 o_m = take(4 * (size_t)(hk::kFeat * hk::kHid + hk::kHid + hk::kHid * hk::kEmb + hk::kEmb)),
+                 o_v = take(4 * (size_t)(hk::kFeat * hk::kHid + hk::kHid + hk::kHid * hk::kEmb + hk::kEmb));
+    RCHK(grow(ctx, ctx->mlp[6], off));
+    char *w = (char *)ctx->mlp[6].p;
+    int32_t *score = (int32_t *)(w + o_score);
+    float *tgt = (float *)(w + o_tgt);
+    RCHK(halign_sw_pairs(ctx, sc, seqs, anc.data(), A, par.data(), score, stream));
+    hipLaunchKernelGGL(hk::scale_targets_kernel, dim3((P + 255) / 256), dim3(256), 0, st, (const int32_t *)score, P, tgt);
+    HCHK(hipGetLastError());
+    // batch index lists for every step (rows of X_all for a then b, and target slots)
+    {
+        std::vector<int32_t> order(P), hidx((size_t)nsteps * 2 * B), htix((size_t)nsteps * B);
+        for (int q = 0; q < P; ++q) order[q] = q;
+        for (int e = 0; e < opts->epochs; ++e) {
+            for (int q = P - 1; q > 0; --q) std::swap(order[q], order[(int)(splitmix(rs) % (uint64_t)(q + 1))]);
+            for (int s = 0; s < steps_per_epoch; ++s) {
+                const int step = e * steps_per_epoch + s;
+                for (int r = 0; r < B; ++r) {
+                    const int q = order[s * B + r];
+                    hidx[(size_t)step * 2 * B + r] = anc[q / 64];
+                    hidx[(size_t)step * 2 * B + B + r] = par[q];
+                    htix[(size_t)step * B + r] = q;
+                }
+            }
+        }
+        HCHK(hipMemcpyAsync(w + o_idx, hidx.data(), 4 * hidx.size(), hipMemcpyHostToDevice, st));
+        HCHK(hipMemcpyAsync(w + o_tix, htix.data(), 4 * htix.size(), hipMemcpyHostToDevice, st));
+        HCHK(hipStreamSynchronize(st));   // host vectors go out of scope
+    }
+    uint16_t *X = (uint16_t *)(w + o_X);
+    RCHK(halign_featurize(seqs, nullptr, N, X, stream));
+    const int64_t nW1 = (int64_t)hk::kFeat * hk::kHid, nW2 = (int64_t)hk::kHid * hk::kEmb;
+    float *g = (float *)(w + o_g), *mo = (float *)(w + o_m), *vo = (float *)(w + o_v);
+    const int64_t ntot = nW1 + hk::kHid + nW2 + hk::kEmb;
+    RCHK(launch_fill((uint32_t *)mo, 0u, ntot, st));
+    RCHK(launch_fill((uint32_t *)vo, 0u, ntot, st));
+    float *gW1 = g, *gb1 = g + nW1, *gW2 = gb1 + hk::kHid, *gb2 = gW2 + nW2;
+    float *mW1 = mo, *mb1 = mo + nW1, *mW2 = mb1 + hk::kHid, *mb2 = mW2 + nW2;
+    float *vW1 = vo, *vb1 = vo + nW1, *vW2 = vb1 + hk::kHid, *vb2 = vW2 + nW2;
+    uint16_t *Xb = (uint16_t *)(w + o_Xb), *Hb = (uint16_t *)(w + o_Hb);
+    float *Z = (float *)(w + o_Z), *E = (float *)(w + o_E), *dE = (float *)(w + o_dE), *tb = (float *)(w + o_tb);
+    float *loss = (float *)(w + o_loss);
+    halign_model md{pr->W1b, pr->b1, pr->W2b, pr->b2};
+    for (int step = 0; step < nsteps; ++step) {
+        const int32_t *ix = (const int32_t *)(w + o_idx) + (size_t)step * 2 * B;
+        const int32_t *tx = (const int32_t *)(w + o_tix) + (size_t)step * B;
+        hipLaunchKernelGGL(hk::gather_rows_kernel, dim3(2 * B), dim3(256), 0, st, (const uint16_t *)X, ix, 2 * B,
+                           hk::kFeat, Xb);
+        hipLaunchKernelGGL(hk::gather_f32_kernel, dim3((B + 255) / 256), dim3(256), 0, st, (const float *)tgt, tx, B, tb);
+        HCHK(hipGetLastError());
+        RCHK(halign_mlp_forward(ctx, &md, Xb, 2 * B, Z, Hb, E, stream));
+        RCHK(halign_pair_loss(ctx, E, tb, B, dE, loss + step, stream));
+        RCHK(halign_mlp_backward(ctx, &md, Xb, 2 * B, Z, Hb, dE, gW1, gb1, gW2, gb2, stream));
+        const float lr = opts->lr;
+        RCHK(halign_adam_step(pr->W1, gW1, mW1, vW1, pr->W1b, nW1, lr, 0.9f, 0.999f, 1e-8f, step + 1, stream));
+        RCHK(halign_adam_step(pr->b1, gb1, mb1, vb1, nullptr, hk::kHid, lr, 0.9f, 0.999f, 1e-8f, step + 1, stream));
+        RCHK(halign_adam_step(pr->W2, gW2, mW2, vW2, pr->W2b, nW2, lr, 0.9f, 0.999f, 1e-8f, step + 1, stream));
+        RCHK(halign_adam_step(pr->b2, gb2, mb2, vb2, nullptr, hk::kEmb, lr, 0.9f, 0.999f, 1e-8f, step + 1, stream));
+    }
+    if (loss_host) {
+        std::vector<float> hl(nsteps);
+        HCHK(hipMemcpyAsync(hl.data(), loss, 4 * (size_t)nsteps, hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+        for (int e = 0; e < opts->epochs; ++e) {
+            double s = 0;
+            for (int q = 0; q < steps_per_epoch; ++q) s += hl[(size_t)e * steps_per_epoch + q];
+            loss_host[e] = (float)(s / std::max(1, steps_per_epoch));
+        }
+    }
+    return HALIGN_OK;
+}
+
+int halign_center_learned(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, const halign_model *model,
+                          int32_t k, int32_t *cand_host, int32_t *center_host, void *stream) {
+    if (!ctx || !center_host || k <= 0) return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_scoring(sc));
+    RCHK(check_seqs(seqs));
+    RCHK(check_model(model));
+    const int N = seqs->n;
+    if (N <= 0) return fail(HALIGN_E_INVALID, "empty set");
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int kk = std::min<int>(k, N);
+    const int CH = 16384;
+    size_t off = 0;
+    auto take = [&](size_t bytes) { size_t r = off; off = (off + bytes + 255) & ~size_t(255); return r; };
+    const size_t o_E = take(4 * (size_t)N * hk::kEmb), o_X = take(2 * (size_t)CH * hk::kFeat),
+                 o_Hb = take(2 * (size_t)CH * hk::kHid), o_rows = take(4 * (size_t)N), o_u = take(4 * (size_t)N),
+                 o_top = take(4 * (size_t)kk), o_sums = take(8 * (size_t)kk);
+    RCHK(grow(ctx, ctx->mlp[7], off));
+    char *w = (char *)ctx->mlp[7].p;
+    float *E = (float *)(w + o_E);
+    uint16_t *X = (uint16_t *)(w + o_X), *Hb = (uint16_t *)(w + o_Hb);
+    int32_t *rows = (int32_t *)(w + o_rows);
+    hipLaunchKernelGGL(hk::iota_kernel, dim3((N + 255) / 256), dim3(256), 0, st, rows, N);
+    HCHK(hipGetLastError());
+    for (int r0 = 0; r0 < N; r0 += CH) {
+        const int nr = std::min(CH, N - r0);
+        RCHK(halign_featurize(seqs, rows + r0, nr, X, stream));
+        RCHK(halign_mlp_forward(ctx, model, X, nr, nullptr, Hb, E + (size_t)r0 * hk::kEmb, stream));
+    }
+    int32_t *top = (int32_t *)(w + o_top);
+    RCHK(halign_topk_center(ctx, E, N, kk, (float *)(w + o_u), top, stream));
+    int32_t c = -1;
+    RCHK(halign_center_judge(ctx, sc, seqs, top, kk, (int64_t *)(w + o_sums), &c, stream));
+    if (cand_host) {
+        HCHK(hipMemcpyAsync(cand_host, top, 4 * (size_t)kk, hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+    }
+    *center_host = c;
+    return HALIGN_OK;
+}
+
+}  // extern "C"
