@@ -54,6 +54,10 @@ extern "C" {
 #define HALIGN_SCORE_ONLY  0u     /* score (and end cell when cells != NULL) */
 #define HALIGN_TRACEBACK   1u     /* also walk back: cells, ins, aligned */
 
+/* capture the call's launch sequence in a hipGraph and replay it on later
+ * calls with identical arguments (same pointers, sizes, offsets, scoring) */
+#define HALIGN_GRAPH       (1u << 8)
+
 /* kernel routing overrides (halign_sw_batch flags, bits 4..5) */
 #define HALIGN_ROUTE_AUTO   0u
 #define HALIGN_ROUTE_INTER  (1u << 4)  /* one pair per lane */
@@ -104,6 +108,23 @@ int  halign_ctx_last_timings(halign_ctx *ctx, float *ms_host /*[3]*/);
 /* Number of workgroups/launches of the dominant forward kernel in the last
  * call (for roofline accounting) and the DP cells it covered. */
 int  halign_ctx_last_stats(const halign_ctx *ctx, int64_t *stats_host /*[4]: cells, launches, route, chunks*/);
+
+/* Autotuning of halign_sw_batch plans (off by default; also enabled by the
+ * environment variable HALIGN_AUTOTUNE=1).  When on, the first call for a
+ * bucket of (center length, batch size, median length, traceback) times the
+ * candidate plans -- wavefront kernel with R or R+1 center rows per lane,
+ * one or two streams per resident wave, or the one-pair-per-lane kernel -- on
+ * a strided sample of the batch and keeps the fastest; results do not depend
+ * on the plan.  HALIGN_TUNE_CACHE=<path> persists choices (malformed lines
+ * are ignored).  halign_ctx_last_plan reports {route, R, streams multiplier}
+ * of the last call (route -1 / R 0: defaults). */
+int  halign_ctx_set_autotune(halign_ctx *ctx, int enable);
+/* halign_msa runs its pairwise batch with HALIGN_GRAPH when enabled (the
+ * batch is planned and captured once, then replayed); graph_launches counts
+ * replays. */
+int  halign_ctx_set_graph(halign_ctx *ctx, int enable);
+int  halign_ctx_graph_launches(const halign_ctx *ctx, int64_t *n_host);
+int  halign_ctx_last_plan(const halign_ctx *ctx, int32_t *plan_host /*[3]*/);
 
 /* ---- step a1: encode ASCII to residue codes (upper/lower case; U->C,
  * O->K, other letters -> X).  ascii and codes may alias. */

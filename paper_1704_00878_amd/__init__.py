@@ -27,6 +27,7 @@ HALIGN_TRACEBACK = 1
 HALIGN_ROUTE_AUTO = 0
 HALIGN_ROUTE_INTER = 1 << 4
 HALIGN_ROUTE_INTRA = 2 << 4
+HALIGN_GRAPH = 1 << 8
 HALIGN_CENTER_EXACT = -1
 HALIGN_CENTER_LEARNED = -2
 
@@ -84,6 +85,10 @@ def lib():
         "halign_ctx_last_timings": ([P, P], I),
         "halign_ctx_last_stats": ([P, P], I),
         "halign_debug_fail_chunk": ([P, ctypes.c_int], I),
+        "halign_ctx_set_autotune": ([P, ctypes.c_int], I),
+        "halign_ctx_last_plan": ([P, P], I),
+        "halign_ctx_set_graph": ([P, ctypes.c_int], I),
+        "halign_ctx_graph_launches": ([P, P], I),
         "halign_encode": ([P, I64, P, P], I),
         "halign_sw_batch": ([P, P, P, I, P, U32, P, P, P, P, P], I),
         "halign_sw_pairs": ([P, P, P, P, I, P, P, P], I),
@@ -209,6 +214,22 @@ class Context:
         _check(lib().halign_ctx_last_stats(self.h, a))
         return dict(cells=a[0], launches=a[1], route=a[2], chunks=a[3])
 
+    def set_autotune(self, on: bool):
+        _check(lib().halign_ctx_set_autotune(self.h, 1 if on else 0))
+
+    def last_plan(self):
+        a = (ctypes.c_int32 * 3)()
+        _check(lib().halign_ctx_last_plan(self.h, a))
+        return dict(route=a[0], R=a[1], streams=a[2])
+
+    def set_graph(self, on: bool):
+        _check(lib().halign_ctx_set_graph(self.h, 1 if on else 0))
+
+    def graph_launches(self) -> int:
+        v = ctypes.c_int64(0)
+        _check(lib().halign_ctx_graph_launches(self.h, ctypes.byref(v)))
+        return int(v.value)
+
     def fail_chunk(self, c: int):
         _check(lib().halign_debug_fail_chunk(self.h, c))
 
@@ -295,7 +316,7 @@ def halign_msa(ctx: Context, sc: Scoring, seqs: DeviceSeqs, center: int, model=N
 # Convenience layer (allocation of outputs)
 # ---------------------------------------------------------------------------
 def sw_batch(ctx: Context, sc: Scoring, seqs: DeviceSeqs, center: int, traceback: bool = True,
-             route: int = HALIGN_ROUTE_AUTO, center_seq=None):
+             route: int = HALIGN_ROUTE_AUTO, center_seq=None, graph: bool = False, out=None):
     """SW of every sequence against sequence `center` (or `center_seq`, a
     uint8 CUDA tensor).  Returns dict of CUDA tensors."""
     import torch
@@ -307,13 +328,16 @@ def sw_batch(ctx: Context, sc: Scoring, seqs: DeviceSeqs, center: int, traceback
     else:
         m = int(center_seq.numel())
         cptr = center_seq.data_ptr()
-    score = torch.empty(N, dtype=torch.int32, device=dev)
-    cells = torch.empty((N, 4), dtype=torch.int32, device=dev)
-    ins = aligned = None
-    if traceback:
-        ins = torch.empty((N, m + 1), dtype=torch.int16, device=dev)
-        aligned = torch.empty((N, (m + 31) // 32), dtype=torch.int32, device=dev)
-    flags = (HALIGN_TRACEBACK if traceback else HALIGN_SCORE_ONLY) | route
+    if out is not None:   # reuse output tensors (graph replays need the same pointers)
+        score, cells, ins, aligned = out["score"], out["cells"], out["ins"], out["aligned"]
+    else:
+        score = torch.empty(N, dtype=torch.int32, device=dev)
+        cells = torch.empty((N, 4), dtype=torch.int32, device=dev)
+        ins = aligned = None
+        if traceback:
+            ins = torch.empty((N, m + 1), dtype=torch.int16, device=dev)
+            aligned = torch.empty((N, (m + 31) // 32), dtype=torch.int32, device=dev)
+    flags = (HALIGN_TRACEBACK if traceback else HALIGN_SCORE_ONLY) | route | (HALIGN_GRAPH if graph else 0)
     halign_sw_batch(ctx, sc, cptr, m, seqs, flags, score, cells, ins, aligned)
     return dict(score=score, cells=cells, ins=ins, aligned=aligned, m=m)
 

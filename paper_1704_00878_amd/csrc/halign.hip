@@ -7,10 +7,14 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <fstream>
+#include <map>
+#include <sstream>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <array>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -75,6 +79,21 @@ struct halign_ctx {
     float last_ms[3] = {0, 0, 0};
     int64_t last_stats[4] = {0, 0, 0, 0};
     int fault_chunk = -1;    // test hook: chunk index whose first launch reports failure
+    bool capturing = false;   // a hipGraph capture of halign_sw_batch is in progress
+    int use_graph = 0;        // halign_msa passes HALIGN_GRAPH to its batch
+    hipStream_t cap_stream = nullptr;
+    struct GraphEntry {
+        uint64_t key = 0;
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        DevBuf plan, codes, sbuf, bound, counter, pairbuf, spbuf;
+        HostBuf stage;
+    } gent;
+    int64_t graph_launches = 0;
+    int autotune = 0;         // 1: tune route / rows per lane / stream count per bucket
+    std::array<int, 3> last_tune = {-1, 0, 1};
+    std::map<std::string, std::array<int, 3>> tuned;   // bucket -> {route, R, stream multiplier}
+    std::string tune_file;    // optional cache file (HALIGN_TUNE_CACHE)
     int *flag_host = nullptr; // pinned: largest residue code of the last validated call
     int flag_alpha = 0;       // alphabet that value is checked against (0 = nothing pending)
 };
@@ -103,7 +122,30 @@ int grow(halign_ctx *ctx, DevBuf &b, size_t bytes) {
     return HALIGN_OK;
 }
 
+// Event records are skipped while a graph is being captured (timing of a
+// replay comes from events around the graph launch).
+int record(halign_ctx *ctx, hipEvent_t e, hipStream_t st) {
+    if (ctx->capturing) return HALIGN_OK;
+    HCHK(hipEventRecord(e, st));
+    return HALIGN_OK;
+}
+
+void free_buf(DevBuf &b) {
+    if (b.p) (void)hipFree(b.p);
+    b = DevBuf();
+}
+
+void graph_drop(halign_ctx *ctx) {
+    auto &g = ctx->gent;
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    if (g.graph) (void)hipGraphDestroy(g.graph);
+    for (DevBuf *b : {&g.plan, &g.codes, &g.sbuf, &g.bound, &g.counter, &g.pairbuf, &g.spbuf}) free_buf(*b);
+    if (g.stage.p) (void)hipHostFree(g.stage.p);
+    g = halign_ctx::GraphEntry();
+}
+
 int stage_wait(halign_ctx *ctx) {
+    if (ctx->capturing) return HALIGN_OK;
     if (ctx->stage_pending) {
         HCHK(hipEventSynchronize(ctx->ev_stage));
         ctx->stage_pending = false;
@@ -176,6 +218,7 @@ int check_seqs(const halign_seqs *sq) {
 // Device matrix copy (alpha x alpha int8) kept in the plan buffer head.
 struct Scoring {
     const int8_t *dmat;
+    const int8_t *hmat;   // host copy (planning decisions)
     int alpha, ge, goe;
 };
 
@@ -192,26 +235,33 @@ void pick_geom(int m, int *R, int *passes) {
     *R = std::max(1, std::min(8, (m + 64 * p - 1) / (64 * p)));
 }
 
-template <int R>
-void launch_stream_R(const hk::StreamArgs &a, bool tb, bool endc, int grid, size_t lds, hipStream_t st) {
+template <int R, bool P16>
+void launch_stream_RP(const hk::StreamArgs &a, bool tb, bool endc, int grid, size_t lds, hipStream_t st) {
     if (tb)
-        hipLaunchKernelGGL((hk::sw_stream_kernel<R, true, true>), dim3(grid), dim3(512), lds, st, a);
+        hipLaunchKernelGGL((hk::sw_stream_kernel<R, true, true, P16>), dim3(grid), dim3(512), lds, st, a);
     else if (endc)
-        hipLaunchKernelGGL((hk::sw_stream_kernel<R, false, true>), dim3(grid), dim3(512), lds, st, a);
+        hipLaunchKernelGGL((hk::sw_stream_kernel<R, false, true, P16>), dim3(grid), dim3(512), lds, st, a);
     else
-        hipLaunchKernelGGL((hk::sw_stream_kernel<R, false, false>), dim3(grid), dim3(512), lds, st, a);
+        hipLaunchKernelGGL((hk::sw_stream_kernel<R, false, false, P16>), dim3(grid), dim3(512), lds, st, a);
 }
 
-void launch_stream(int R, const hk::StreamArgs &a, bool tb, bool endc, int grid, size_t lds, hipStream_t st) {
+template <int R>
+void launch_stream_R(const hk::StreamArgs &a, bool tb, bool endc, bool p16, int grid, size_t lds, hipStream_t st) {
+    if (p16) launch_stream_RP<R, true>(a, tb, endc, grid, lds, st);
+    else launch_stream_RP<R, false>(a, tb, endc, grid, lds, st);
+}
+
+void launch_stream(int R, const hk::StreamArgs &a, bool tb, bool endc, bool p16, int grid, size_t lds,
+                   hipStream_t st) {
     switch (R) {
-        case 1: launch_stream_R<1>(a, tb, endc, grid, lds, st); break;
-        case 2: launch_stream_R<2>(a, tb, endc, grid, lds, st); break;
-        case 3: launch_stream_R<3>(a, tb, endc, grid, lds, st); break;
-        case 4: launch_stream_R<4>(a, tb, endc, grid, lds, st); break;
-        case 5: launch_stream_R<5>(a, tb, endc, grid, lds, st); break;
-        case 6: launch_stream_R<6>(a, tb, endc, grid, lds, st); break;
-        case 7: launch_stream_R<7>(a, tb, endc, grid, lds, st); break;
-        default: launch_stream_R<8>(a, tb, endc, grid, lds, st); break;
+        case 1: launch_stream_R<1>(a, tb, endc, p16, grid, lds, st); break;
+        case 2: launch_stream_R<2>(a, tb, endc, p16, grid, lds, st); break;
+        case 3: launch_stream_R<3>(a, tb, endc, p16, grid, lds, st); break;
+        case 4: launch_stream_R<4>(a, tb, endc, p16, grid, lds, st); break;
+        case 5: launch_stream_R<5>(a, tb, endc, p16, grid, lds, st); break;
+        case 6: launch_stream_R<6>(a, tb, endc, p16, grid, lds, st); break;
+        case 7: launch_stream_R<7>(a, tb, endc, p16, grid, lds, st); break;
+        default: launch_stream_R<8>(a, tb, endc, p16, grid, lds, st); break;
     }
 }
 
@@ -232,9 +282,15 @@ struct BatchOut {
 
 // Plans and runs the forward pass (+ walk when tb) for the pairs `pids_in`
 // against center (device) of length m.
+struct Tune {
+    int route = -1;   // -1: from flags
+    int R = 0;        // 0: fitted to m
+    int smul = 1;     // streams per resident wave slot
+};
+
 int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq,
               const std::vector<int32_t> &pids_in, bool tb, bool endc, int route, const BatchOut &out,
-              hipStream_t st) {
+              hipStream_t st, const Tune &tune = Tune()) {
     const int64_t *oh = sq->offsets_host;
     const int N = sq->n;
     const int np = (int)pids_in.size();
@@ -254,7 +310,21 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
     const int aw = (m + 31) / 32;
     int R = 8, passes = 1;
     pick_geom(m, &R, &passes);
-    const size_t lds_stream = (size_t)hk::kAlphaMax * 64 * R * 4 + (tb ? 8 * 64 * 8 * 4 : 0);
+    if (tune.route >= 0) route = tune.route;
+    if (tune.R > 0 && tune.R <= 8) {
+        R = tune.R;
+        passes = std::max(1, (m + 64 * R - 1) / (64 * R));
+    }
+    // int16 profile when every score and profile entry fits in 16 bits:
+    // max score <= max(S) * min(m, longest sequence)
+    int smax = 1;
+    for (int x = 0; x < S.alpha * S.alpha; ++x) smax = std::max(smax, (int)S.hmat[x]);
+    int nlong = 0;
+    for (int x = 0; x < np; ++x) nlong = std::max(nlong, len(pids[x]));
+    const bool p16 = (int64_t)smax * std::min(m, nlong) <= 32000 && S.goe + 128 <= 32000 &&
+                     !getenv("HALIGN_PROFILE32");
+    const size_t prof_bytes = p16 ? (size_t)(S.alpha + 1) * 64 * 8 * 2 : (size_t)hk::kAlphaMax * 64 * R * 4;
+    const size_t lds_stream = prof_bytes + (tb ? 8 * 64 * 8 * 4 : 0);
     if (route == kRouteIntra && lds_stream > ctx->lds_max) route = kRouteInter;
     ctx->last_stats[2] = route;
 
@@ -313,7 +383,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             int nonempty = 0;
             for (int x = lo; x < hi; ++x) nonempty += len(pids[x]) > 0;
             const int wg_per_cu = std::max(1, std::min(4, (int)(ctx->lds_max / lds_stream)));
-            const int resident = ctx->num_cu * wg_per_cu * 8;
+            const int resident = ctx->num_cu * wg_per_cu * 8 * std::max(1, tune.smul);
             nstreams = std::max(1, std::min(nonempty, resident));
             if (const char *e = getenv("HALIGN_MAX_STREAMS")) {   // test knob: many pairs per stream
                 const int cap_s = atoi(e);
@@ -425,7 +495,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         RCHK(grow(ctx, ctx->plan, pb.total));
         char *dplan = (char *)ctx->plan.p;
         HCHK(hipMemcpyAsync(dplan, hs, pb.total, hipMemcpyHostToDevice, st));
-        HCHK(hipEventRecord(ctx->ev_stage, st));
+        RCHK(record(ctx, ctx->ev_stage, st));
         ctx->stage_pending = true;
 
         if (tb) RCHK(grow(ctx, ctx->codes, std::max<size_t>(4, code_words * 4)));
@@ -444,7 +514,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             hipLaunchKernelGGL(hk::stage_stream_kernel, dim3(nslots), dim3(128), 0, st, sq->residues, sq->offsets,
                                (const int32_t *)(dplan + o_spid), (const int64_t *)(dplan + o_scol), nslots, sres);
             HCHK(hipGetLastError());
-            HCHK(hipEventRecord(ctx->ev[0], st));
+            RCHK(record(ctx, ctx->ev[0], st));
             hk::StreamArgs a{};
             a.mat = S.dmat;
             a.alpha = S.alpha;
@@ -462,9 +532,9 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             a.scbase = (const int64_t *)(dplan + o_scb);
             a.bound = (int2 *)ctx->bound.p;
             a.sbbase = (const int64_t *)(dplan + o_sbb);
-            launch_stream(R, a, tb, endc, (nstreams + 7) / 8, lds_stream, st);
+            launch_stream(R, a, tb, endc, p16, (nstreams + 7) / 8, lds_stream, st);
             HCHK(hipGetLastError());
-            HCHK(hipEventRecord(ctx->ev[1], st));
+            RCHK(record(ctx, ctx->ev[1], st));
             hipLaunchKernelGGL(hk::decode_keys_kernel, dim3(grid_for(nslots, 256, 1 << 30)), dim3(256), 0, st,
                                (const unsigned long long *)keys, (const int32_t *)(dplan + o_spid), nslots, out.score,
                                endc ? out.endcell : (int32_t *)nullptr);
@@ -474,7 +544,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             const int grid = std::max(1, std::min(ngroups, slots));
             RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * std::max(1, nmax_all) * 8));
             RCHK(launch_fill((uint32_t *)counter, 0u, 1, st));
-            HCHK(hipEventRecord(ctx->ev[0], st));
+            RCHK(record(ctx, ctx->ev[0], st));
             hk::InterArgs a{};
             a.mat = S.dmat;
             a.alpha = S.alpha;
@@ -497,7 +567,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             a.bstride = (int64_t)64 * std::max(1, nmax_all);
             launch_inter(a, tb, endc, grid, st);
             HCHK(hipGetLastError());
-            HCHK(hipEventRecord(ctx->ev[1], st));
+            RCHK(record(ctx, ctx->ev[1], st));
         }
         ++launches;
         if (tb) {
@@ -527,8 +597,8 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             hipLaunchKernelGGL(hk::walk_kernel, dim3(grid_for(cn, 64, 1 << 30)), dim3(64), 0, st, w);
             HCHK(hipGetLastError());
         }
-        HCHK(hipEventRecord(ctx->ev[2], st));
-        if (chunks.size() > 1) {
+        RCHK(record(ctx, ctx->ev[2], st));
+        if (chunks.size() > 1 && !ctx->capturing) {
             HCHK(hipEventSynchronize(ctx->ev[2]));
             float f = 0, w2 = 0;
             HCHK(hipEventElapsedTime(&f, ctx->ev[0], ctx->ev[1]));
@@ -548,15 +618,105 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
     return HALIGN_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Autotuner: for a bucket of (center length, batch size, median sequence
+// length, traceback) it times the candidate plans on a strided sample of the
+// batch (every plan gives bit-identical results) and keeps the fastest.
+// ---------------------------------------------------------------------------
+std::string tune_key(int m, int N, int med, bool tb) {
+    int lg = 0;
+    while ((1 << (lg + 1)) <= N) ++lg;
+    std::ostringstream o;
+    o << "m" << (m + 31) / 32 << "_n" << lg << "_l" << (med + 63) / 64 << "_t" << (tb ? 1 : 0);
+    return o.str();
+}
+
+void tune_load(halign_ctx *ctx) {
+    if (ctx->tune_file.empty()) return;
+    std::ifstream f(ctx->tune_file);
+    std::string line;
+    while (std::getline(f, line)) {
+        std::istringstream s(line);
+        std::string key;
+        int r = -1, R = -1, sm = -1;
+        if (!(s >> key >> r >> R >> sm)) continue;              // malformed: ignored
+        if (r < 0 || r > 1 || R < 0 || R > 8 || sm < 1 || sm > 4) continue;
+        ctx->tuned[key] = {r, R, sm};
+    }
+}
+
+void tune_save(halign_ctx *ctx, const std::string &key, const std::array<int, 3> &v) {
+    if (ctx->tune_file.empty()) return;
+    std::ofstream f(ctx->tune_file, std::ios::app);
+    if (f) f << key << " " << v[0] << " " << v[1] << " " << v[2] << "\n";
+}
+
+int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq, bool tb,
+             bool endc, const BatchOut &out, hipStream_t st, Tune *best) {
+    const int N = sq->n;
+    std::vector<int> lens(N);
+    for (int k = 0; k < N; ++k) lens[k] = (int)(sq->offsets_host[k + 1] - sq->offsets_host[k]);
+    std::vector<int> sl(lens);
+    std::nth_element(sl.begin(), sl.begin() + N / 2, sl.end());
+    const std::string key = tune_key(m, N, sl[N / 2], tb);
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) {
+        best->route = it->second[0];
+        best->R = it->second[1];
+        best->smul = it->second[2];
+        return HALIGN_OK;
+    }
+    // strided sample that keeps the length mix
+    const int ns = std::min(N, 8192);
+    std::vector<int32_t> sample(ns);
+    for (int q = 0; q < ns; ++q) sample[q] = (int32_t)((int64_t)q * N / ns);
+    int R0 = 8, p0 = 1;
+    pick_geom(m, &R0, &p0);
+    std::vector<Tune> cands;
+    cands.push_back({kRouteIntra, R0, 1});
+    cands.push_back({kRouteIntra, R0, 2});
+    if (R0 < 8) cands.push_back({kRouteIntra, R0 + 1, 1});
+    cands.push_back({kRouteInter, 0, 1});
+    // scale the sample's stream count like the full batch would fill the chip
+    float best_ms = 1e30f;
+    *best = cands[0];
+    for (const Tune &c : cands) {
+        float ms = 0.f;
+        for (int rep = 0; rep < 2; ++rep) {
+            RCHK(run_batch(ctx, S, center, m, sq, sample, false, endc, c.route, out, st, c));
+            HCHK(hipEventSynchronize(ctx->ev[1]));
+            HCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+        }
+        if (ms < best_ms) {
+            best_ms = ms;
+            *best = c;
+        }
+    }
+    const std::array<int, 3> v = {best->route, best->R, best->smul};
+    ctx->tuned[key] = v;
+    tune_save(ctx, key, v);
+    (void)tb;
+    return HALIGN_OK;
+}
+
 int upload_matrix(halign_ctx *ctx, const halign_scoring *sc, hipStream_t st, Scoring *S) {
     const size_t bytes = (size_t)sc->alphabet * sc->alphabet;
+    if (ctx->capturing) {   // the device copy from the uncaptured run is kept by the graph
+        S->dmat = (const int8_t *)ctx->spbuf.p;
+        S->hmat = sc->matrix_host;
+        S->alpha = sc->alphabet;
+        S->ge = sc->gap_extend;
+        S->goe = sc->gap_open + sc->gap_extend;
+        return HALIGN_OK;
+    }
     RCHK(grow(ctx, ctx->spbuf, 4096));
     RCHK(stage_grow(ctx, 4096));
     memcpy(ctx->stage.p, sc->matrix_host, bytes);
     HCHK(hipMemcpyAsync(ctx->spbuf.p, ctx->stage.p, bytes, hipMemcpyHostToDevice, st));
-    HCHK(hipEventRecord(ctx->ev_stage, st));
+    RCHK(record(ctx, ctx->ev_stage, st));
     ctx->stage_pending = true;
     S->dmat = (const int8_t *)ctx->spbuf.p;
+    S->hmat = sc->matrix_host;
     S->alpha = sc->alphabet;
     S->ge = sc->gap_extend;
     S->goe = sc->gap_open + sc->gap_extend;
@@ -632,6 +792,9 @@ int halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out) 
     if (!ctx) return fail(HALIGN_E_NOMEM, "host allocation failed");
     ctx->device = device;
     ctx->cap = workspace_cap_bytes;
+    if (const char *e = getenv("HALIGN_AUTOTUNE")) ctx->autotune = atoi(e) != 0;
+    if (const char *e = getenv("HALIGN_TUNE_CACHE")) ctx->tune_file = e;
+    tune_load(ctx);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) {
         ctx->num_cu = prop.multiProcessorCount;
@@ -658,6 +821,8 @@ void halign_ctx_destroy(halign_ctx *ctx) {
     if (!ctx) return;
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
+    graph_drop(ctx);
+    if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf, &ctx->colbuf, &ctx->sbuf})
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : ctx->mlp)
@@ -694,6 +859,31 @@ int halign_ctx_last_timings(halign_ctx *ctx, float *ms_host) {
 int halign_ctx_last_stats(const halign_ctx *ctx, int64_t *stats_host) {
     if (!ctx || !stats_host) return fail(HALIGN_E_INVALID, "NULL argument");
     for (int i = 0; i < 4; ++i) stats_host[i] = ctx->last_stats[i];
+    return HALIGN_OK;
+}
+
+int halign_ctx_set_graph(halign_ctx *ctx, int enable) {
+    if (!ctx) return fail(HALIGN_E_INVALID, "NULL ctx");
+    ctx->use_graph = enable != 0;
+    if (!enable) graph_drop(ctx);
+    return HALIGN_OK;
+}
+
+int halign_ctx_graph_launches(const halign_ctx *ctx, int64_t *n_host) {
+    if (!ctx || !n_host) return fail(HALIGN_E_INVALID, "NULL argument");
+    *n_host = ctx->graph_launches;
+    return HALIGN_OK;
+}
+
+int halign_ctx_set_autotune(halign_ctx *ctx, int enable) {
+    if (!ctx) return fail(HALIGN_E_INVALID, "NULL ctx");
+    ctx->autotune = enable != 0;
+    return HALIGN_OK;
+}
+
+int halign_ctx_last_plan(const halign_ctx *ctx, int32_t *plan_host) {
+    if (!ctx || !plan_host) return fail(HALIGN_E_INVALID, "NULL argument");
+    for (int i = 0; i < 3; ++i) plan_host[i] = ctx->last_tune[i];
     return HALIGN_OK;
 }
 
@@ -737,9 +927,8 @@ int halign_encode(const uint8_t *ascii, int64_t len, uint8_t *codes, void *strea
 
 }  // extern "C"
 
-// halign_sw_batch without the final synchronisation: the code check is left
-// pending for the caller's next synchronisation point (validate_check).
-static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *center, int32_t m,
+// The launch sequence of halign_sw_batch (validation, plan, forward, walk).
+static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *center, int32_t m,
                           const halign_seqs *seqs, uint32_t flags, int32_t *score, int32_t *cells, uint16_t *ins,
                           uint32_t *aligned, void *stream) {
     if (!ctx) return fail(HALIGN_E_INVALID, "ctx is NULL");
@@ -761,6 +950,12 @@ static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8
     const bool endc = tb || cells != nullptr;
     RCHK(grow(ctx, ctx->pairbuf, (size_t)N * 8 + 256));
     int32_t *endcell = (int32_t *)ctx->pairbuf.p;
+    Tune tune;
+    const bool want_tune = ctx->autotune && (flags & (3u << 4)) == HALIGN_ROUTE_AUTO;
+    if (want_tune) {
+        BatchOut tout{score, cells, endcell, ins, aligned};
+        RCHK(autotune(ctx, S, center, m, seqs, tb, endc, tout, st, &tune));
+    }
     if (tb) {
         hipLaunchKernelGGL(hk::fill_u16_kernel, dim3(grid_for((int64_t)N * (m + 1), 256, 4096)), dim3(256), 0, st,
                            ins, (uint16_t)0, (int64_t)N * (m + 1));
@@ -770,13 +965,95 @@ static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8
     std::vector<int32_t> pids(N);
     std::iota(pids.begin(), pids.end(), 0);
     BatchOut out{score, cells, endcell, ins, aligned};
-    RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st));
+    RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st, tune));
+    ctx->last_tune = {tune.route, tune.R, tune.smul};
     if (!tb && cells) {
         // score-only with cells: report the end cell as (0, 0, i1, j1)
         hipLaunchKernelGGL(hk::endcell_to_cells_kernel, dim3(grid_for(N, 256)), dim3(256), 0, st,
                            (const int32_t *)endcell, N, cells);
         HCHK(hipGetLastError());
     }
+    return HALIGN_OK;
+}
+
+namespace {
+
+uint64_t fnv(uint64_t h, const void *p, size_t n) {
+    const uint8_t *b = (const uint8_t *)p;
+    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 0x100000001b3ull; }
+    return h;
+}
+
+}  // namespace
+
+// halign_sw_batch without the final synchronisation: the code check is left
+// pending for the caller's next synchronisation point (validate_check).
+// With HALIGN_GRAPH the launch sequence is captured once into a hipGraph that
+// owns its scratch and plan buffers, and replayed while the call's arguments
+// (pointers, sizes, offsets, scoring) stay the same.
+static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *center, int32_t m,
+                          const halign_seqs *seqs, uint32_t flags, int32_t *score, int32_t *cells, uint16_t *ins,
+                          uint32_t *aligned, void *stream) {
+    if (!(flags & HALIGN_GRAPH))
+        return sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream);
+    if (!ctx || !sc || !seqs || !sc->matrix_host || !seqs->offsets_host)
+        return sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream);
+    hipStream_t st = (hipStream_t)stream;
+    uint64_t key = 0xcbf29ce484222325ull;
+    const void *ptrs[8] = {center, seqs->residues, seqs->offsets, score, cells, ins, aligned, nullptr};
+    key = fnv(key, ptrs, sizeof ptrs);
+    const int32_t ints[7] = {m, seqs->n, (int32_t)flags, sc->alphabet, sc->gap_open, sc->gap_extend, ctx->autotune};
+    key = fnv(key, ints, sizeof ints);
+    if (sc->alphabet > 0 && sc->alphabet <= 32)
+        key = fnv(key, sc->matrix_host, (size_t)sc->alphabet * sc->alphabet);
+    if (seqs->n >= 0) key = fnv(key, seqs->offsets_host, sizeof(int64_t) * ((size_t)seqs->n + 1));
+    if (ctx->gent.exec && ctx->gent.key == key) {
+        HCHK(hipSetDevice(ctx->device));
+        RCHK(record(ctx, ctx->ev[0], st));
+        HCHK(hipGraphLaunch(ctx->gent.exec, st));
+        RCHK(record(ctx, ctx->ev[1], st));
+        RCHK(record(ctx, ctx->ev[2], st));
+        ctx->last_ms[2] = 0.f;
+        ctx->flag_alpha = sc->alphabet;   // the graph copies the code check into flag_host
+        ctx->graph_launches++;
+        return HALIGN_OK;
+    }
+    // first call: run it, then capture the same sequence for later calls
+    RCHK(sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream));
+    const int pending = ctx->flag_alpha;
+    graph_drop(ctx);
+    if (!ctx->cap_stream) HCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
+    HCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
+    ctx->capturing = true;
+    const int rc = sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, ctx->cap_stream);
+    ctx->capturing = false;
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
+    ctx->flag_alpha = pending;
+    if (rc != HALIGN_OK) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+    }
+    if (ec != hipSuccess) return fail(HALIGN_E_DEVICE, "graph capture failed: %s", hipGetErrorString(ec));
+    hipGraphExec_t ex = nullptr;
+    if (hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) != hipSuccess) {
+        (void)hipGraphDestroy(g);
+        return fail(HALIGN_E_DEVICE, "graph instantiation failed");
+    }
+    // the graph keeps the buffers it references; the ctx gets fresh ones later
+    auto &e = ctx->gent;
+    e.key = key;
+    e.graph = g;
+    e.exec = ex;
+    std::swap(e.plan, ctx->plan);
+    std::swap(e.codes, ctx->codes);
+    std::swap(e.sbuf, ctx->sbuf);
+    std::swap(e.bound, ctx->bound);
+    std::swap(e.counter, ctx->counter);
+    std::swap(e.pairbuf, ctx->pairbuf);
+    std::swap(e.spbuf, ctx->spbuf);
+    std::swap(e.stage, ctx->stage);
+    ctx->stage_pending = false;
     return HALIGN_OK;
 }
 
@@ -869,7 +1146,7 @@ static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, 
     RCHK(grow(ctx, ctx->plan, pb.total));
     char *dplan = (char *)ctx->plan.p;
     HCHK(hipMemcpyAsync(dplan, hs, pb.total, hipMemcpyHostToDevice, st));
-    HCHK(hipEventRecord(ctx->ev_stage, st));
+    RCHK(record(ctx, ctx->ev_stage, st));
     ctx->stage_pending = true;
     int nmax_all = 0;
     const int64_t *oh = sq->offsets_host;
@@ -898,11 +1175,11 @@ static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, 
     a.bound = (int2 *)ctx->bound.p;
     a.bstride = (int64_t)64 * std::max(1, nmax_all);
     ctx->last_stats[0] = 0;
-    HCHK(hipEventRecord(ctx->ev[0], st));
+    RCHK(record(ctx, ctx->ev[0], st));
     launch_inter(a, false, false, grid, st);
     HCHK(hipGetLastError());
-    HCHK(hipEventRecord(ctx->ev[1], st));
-    HCHK(hipEventRecord(ctx->ev[2], st));
+    RCHK(record(ctx, ctx->ev[1], st));
+    RCHK(record(ctx, ctx->ev[2], st));
     ctx->last_ms[2] = 0.f;
     return HALIGN_OK;
 }
@@ -1089,7 +1366,8 @@ int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seq
     int32_t *G = (int32_t *)(wb + o_G);
     int64_t *col = (int64_t *)(wb + o_col);
     const uint8_t *cen = seqs->residues + oh[c];
-    RCHK(sw_batch_async(ctx, sc, cen, m, seqs, HALIGN_TRACEBACK, score, cells, ins, al, stream));
+    RCHK(sw_batch_async(ctx, sc, cen, m, seqs, HALIGN_TRACEBACK | (ctx->use_graph ? HALIGN_GRAPH : 0u), score, cells,
+                        ins, al, stream));
     hipLaunchKernelGGL(hk::center_row_kernel, dim3(1), dim3(256), 0, st, ins, al, c, m, aw);
     HCHK(hipGetLastError());
     int64_t width = 0;

@@ -137,12 +137,18 @@ __device__ __forceinline__ unsigned long long cell_key(const BestCell &b, bool e
     return k;
 }
 
-template <int R, bool TB, bool ENDC>
+// P16: the profile is int16 [alpha+1][64 lanes][8] (row alpha = padding), one
+// 16-byte LDS read per step, values folded into the add as sign-extended
+// halves; valid when every score and S + goe fit in 16 bits (checked by the
+// host).  Otherwise int32 [32][64R].
+template <int R, bool TB, bool ENDC, bool P16>
 __global__ void __launch_bounds__(512)
 sw_stream_kernel(StreamArgs a) {
-    extern __shared__ int prof[];   // [32][64R], then code staging [8 waves][64][8]
+    extern __shared__ int prof[];   // profile, then code staging [8 waves][64][8]
     constexpr int SPAN = 64 * R;
-    uint32_t *stage = reinterpret_cast<uint32_t *>(prof + kAlphaMax * SPAN) + (threadIdx.x >> 6) * 512 +
+    const int nprow = P16 ? a.alpha + 1 : kAlphaMax;
+    const int prof_words = P16 ? nprow * 64 * 4 : kAlphaMax * SPAN;
+    uint32_t *stage = reinterpret_cast<uint32_t *>(prof + prof_words) + (threadIdx.x >> 6) * 512 +
                       (threadIdx.x & 63) * 8;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -163,11 +169,22 @@ sw_stream_kernel(StreamArgs a) {
     for (int pass = 0; pass < a.passes; ++pass) {
         const int row0 = pass * SPAN;
         __syncthreads();
-        for (int x = tid; x < kAlphaMax * SPAN; x += nthreads) {
-            const int r = x / SPAN, i = row0 + (x - r * SPAN);
-            int v = kNegProf;
-            if (r < a.alpha && i < a.m) v = (int)a.mat[(a.center[i] & 31) * a.alpha + r] + goe;
-            prof[x] = v;
+        if (P16) {
+            int16_t *p16 = reinterpret_cast<int16_t *>(prof);
+            for (int x = tid; x < nprow * 512; x += nthreads) {
+                const int r = x >> 9, l = (x >> 3) & 63, tt = x & 7;
+                const int i = row0 + l * R + tt;
+                int v = -32768;
+                if (r < a.alpha && tt < R && i < a.m) v = (int)a.mat[(a.center[i] & 31) * a.alpha + r] + goe;
+                p16[x] = (int16_t)v;
+            }
+        } else {
+            for (int x = tid; x < kAlphaMax * SPAN; x += nthreads) {
+                const int r = x / SPAN, i = row0 + (x - r * SPAN);
+                int v = kNegProf;
+                if (r < a.alpha && i < a.m) v = (int)a.mat[(a.center[i] & 31) * a.alpha + r] + goe;
+                prof[x] = v;
+            }
         }
         __syncthreads();
         if (!active) continue;
@@ -218,10 +235,19 @@ sw_stream_kernel(StreamArgs a) {
             ++jl;
             int diag = diag0;
             diag0 = upg;
-            const int *prow = pbase + (rcur & 31) * SPAN;
             int p[R];
+            if (P16) {
+                const int prw = min(rcur & 31, a.alpha);
+                const uint4 q = reinterpret_cast<const uint4 *>(prof)[prw * 64 + lane];
+                const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-            for (int t = 0; t < R; ++t) p[t] = prow[t];
+                for (int t = 0; t < R; ++t)
+                    p[t] = (t & 1) ? ((int)qw[t >> 1] >> 16) : (int)(int16_t)(qw[t >> 1] & 0xffffu);
+            } else {
+                const int *prow = pbase + (rcur & 31) * SPAN;
+#pragma unroll
+                for (int t = 0; t < R; ++t) p[t] = prow[t];
+            }
             uint32_t word = 0;
             int colkey = 0;
 #pragma unroll
@@ -249,14 +275,16 @@ sw_stream_kernel(StreamArgs a) {
                 }
             }
             if (bout && lane == 63 && K >= 0 && K < C) bout[K] = make_int2(botg, botf);
+            // columns outside the stream need no test: before it H = 0, and a
+            // best taken after its last column is never published
             if (ENDC) {
                 const int ch = colkey >> 5;
-                if (K >= 0 && K < C && ch > best.h) {
+                if (ch > best.h) {
                     best.h = ch;
                     best.j = jl;
                     best.i = myrow + (31 - (colkey & 31));
                 }
-            } else if (K >= 0 && K < C) {
+            } else {
                 best.h = max(best.h, hm);
             }
             hm = 0;

@@ -171,73 +171,105 @@ CONFIGS = {
 }
 
 
+_BG_CDF = np.cumsum(BACKGROUND)
+_BG_CDF[-1] = 1.0
+
+
 def _background_draw(rng: np.random.Generator, k: int) -> np.ndarray:
-    return rng.choice(N_STANDARD, size=k, p=BACKGROUND).astype(np.uint8)
+    return np.searchsorted(_BG_CDF, rng.random(k), side="right").astype(np.uint8)
 
 
-def _mutate(rng: np.random.Generator, seq: np.ndarray, p_sub: float, p_indel: float) -> np.ndarray:
-    seq = seq.copy()
-    n = len(seq)
-    # substitutions: redraw from the background conditioned on being different
-    hit = np.nonzero(rng.random(n) < p_sub)[0]
-    if len(hit):
-        new = _background_draw(rng, len(hit))
-        same = new == seq[hit]
-        while same.any():
-            new[same] = _background_draw(rng, int(same.sum()))
-            same = new == seq[hit]
-        seq[hit] = new
-    # indels: at each position start one with probability p_indel
-    starts = np.nonzero(rng.random(n) < p_indel)[0]
-    if len(starts) == 0:
-        return seq
-    kinds = rng.random(len(starts)) < 0.5          # True -> insertion
-    lens = rng.geometric(0.5, size=len(starts))
-    pieces = []
-    pos = 0
-    for st, ins, ln in zip(starts.tolist(), kinds.tolist(), lens.tolist()):
-        if st < pos:  # inside a previous deletion
-            continue
-        pieces.append(seq[pos:st])
-        if ins:
-            pieces.append(_background_draw(rng, ln))
-            pos = st
-        else:
-            pos = min(n, st + ln)
-    pieces.append(seq[pos:])
-    return np.concatenate(pieces).astype(np.uint8)
+_CHUNK = 65536   # sequences generated per chunk (fixed: part of the recipe)
+
+
+def _generate_chunk(rng, cfg, n, roots, root_off, root_lens):
+    which = rng.integers(0, cfg.n_roots, size=n)
+    L = cfg.length(rng, n).astype(np.int64)
+    Lr = root_lens[which]
+    take = np.minimum(L, Lr)
+    start = (rng.random(n) * (Lr - take + 1)).astype(np.int64)
+    left = (rng.random(n) * (L - take + 1)).astype(np.int64)
+    off = np.zeros(n + 1, np.int64)
+    np.cumsum(L, out=off[1:])
+    T = int(off[-1])
+    # base sequences: background, with the root window laid over it
+    base = _background_draw(rng, T)
+    k = np.repeat(np.arange(n, dtype=np.int32), L)
+    q = np.arange(T, dtype=np.int64) - off[k]
+    inroot = (q >= left[k]) & (q < left[k] + take[k])
+    idx = np.nonzero(inroot)[0]
+    kk = k[idx]
+    base[idx] = roots[root_off[which[kk]] + start[kk] + (q[idx] - left[kk])]
+    del q, inroot, idx, kk
+    # substitutions: redraw from the background, conditioned on differing
+    hit = np.nonzero(rng.random(T) < cfg.p_sub)[0]
+    new = _background_draw(rng, len(hit))
+    same = new == base[hit]
+    while same.any():
+        new[same] = _background_draw(rng, int(same.sum()))
+        same = new == base[hit]
+    base[hit] = new
+    del hit, new, same
+    # indels: deletions remove the union of their intervals (clipped at the
+    # sequence end); an insertion goes before its position if that survives
+    ev = np.nonzero(rng.random(T) < cfg.p_indel)[0]
+    is_ins = rng.random(len(ev)) < 0.5
+    elen = rng.geometric(0.5, size=len(ev)).astype(np.int64)
+    dpos = ev[~is_ins]
+    dend = np.minimum(dpos + elen[~is_ins], off[k[dpos].astype(np.int64) + 1])
+    diff = np.bincount(dpos, minlength=T + 1)[:T + 1] - np.bincount(dend, minlength=T + 1)[:T + 1]
+    keep = np.cumsum(diff[:T]) == 0
+    insl = np.zeros(T, np.int64)
+    ipos = ev[is_ins]
+    ok = keep[ipos]
+    insl[ipos[ok]] = elen[is_ins][ok]
+    out_end = np.cumsum(keep.astype(np.int64) + insl)
+    out = _background_draw(rng, int(out_end[-1]) if T else 0)
+    kept = np.nonzero(keep)[0]
+    out[out_end[kept] - 1] = base[kept]
+    new_off = np.zeros(n + 1, np.int64)
+    ends = off[1:] - 1
+    new_off[1:] = np.where(L > 0, out_end[np.maximum(ends, 0)] if T else 0, 0)
+    new_off[1:] = np.maximum.accumulate(new_off[1:])   # empty sequences keep the offset
+    return out, new_off
 
 
 def generate(cfg: FamilyConfig | str, n_seqs: int | None = None, seed: int | None = None) -> SeqSet:
-    """Deterministic family-structured protein set.
+    """Deterministic family-structured protein set (vectorised, in chunks).
 
-    Each sequence picks a root uniformly, draws a target length L from the
-    config's length law, takes a uniform window of the root (or the whole root
-    padded at random on both ends with background residues when L exceeds the
-    root), then mutates it by substitution and by geometric(0.5)-length indels.
+    R roots are drawn from the BLOSUM62 background.  Each sequence picks a root
+    uniformly and a target length L from the config's length law; it takes a
+    uniform window of the root, or the whole root padded on both ends (random
+    split) with background residues when L exceeds the root.  Every residue is
+    then substituted with probability p_sub (redrawn from the background,
+    conditioned on being different).  Finally indels start at each position
+    with probability p_indel, half insertions and half deletions, of
+    geometric(0.5) length: deletions remove the union of their intervals
+    (clipped at the sequence end); an insertion places its residues before its
+    position when that position survives.  Chunks of 65,536 sequences draw
+    from their own seed streams.
     """
     if isinstance(cfg, str):
         cfg = CONFIGS[cfg]
     n_seqs = cfg.n_seqs if n_seqs is None else n_seqs
-    rng = np.random.Generator(np.random.PCG64(cfg.seed if seed is None else seed))
-    root_lens = cfg.length(rng, cfg.n_roots)
-    roots = [_background_draw(rng, int(L)) for L in root_lens]
-    which = rng.integers(0, cfg.n_roots, size=n_seqs)
-    targets = cfg.length(rng, n_seqs)
-    seqs = []
-    for k in range(n_seqs):
-        root = roots[which[k]]
-        L = int(targets[k])
-        if L <= len(root):
-            st = int(rng.integers(0, len(root) - L + 1))
-            base = root[st:st + L]
-        else:
-            extra = L - len(root)
-            left = int(rng.integers(0, extra + 1))
-            base = np.concatenate([_background_draw(rng, left), root,
-                                   _background_draw(rng, extra - left)])
-        seqs.append(_mutate(rng, base, cfg.p_sub, cfg.p_indel))
-    return SeqSet.from_list(seqs)
+    ss = np.random.SeedSequence(cfg.seed if seed is None else seed)
+    rng = np.random.Generator(np.random.PCG64(ss))
+    root_lens = cfg.length(rng, cfg.n_roots).astype(np.int64)
+    roots = _background_draw(rng, int(root_lens.sum()))
+    root_off = np.zeros(cfg.n_roots + 1, np.int64)
+    np.cumsum(root_lens, out=root_off[1:])
+    nchunks = max(1, (n_seqs + _CHUNK - 1) // _CHUNK)
+    kids = ss.spawn(nchunks)
+    parts, offs, base = [], [np.zeros(1, np.int64)], 0
+    for c in range(nchunks):
+        n = min(_CHUNK, n_seqs - c * _CHUNK)
+        out, off = _generate_chunk(np.random.Generator(np.random.PCG64(kids[c])), cfg, n, roots, root_off,
+                                   root_lens)
+        parts.append(out)
+        offs.append(off[1:] + base)
+        base += int(off[-1])
+    res = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+    return SeqSet(res.astype(np.uint8), np.concatenate(offs))
 
 
 def random_set(rng: np.random.Generator, n_seqs: int, lo: int, hi: int,

@@ -156,6 +156,19 @@ def test_stream_packing(H, ctx, streams, monkeypatch):
         _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, center, ss)
 
 
+@pytest.mark.parametrize("m", [90, 450, 1100])
+def test_profile_int32_path(H, ctx, m, monkeypatch):
+    """The int32-profile variant (used when scores may not fit 16 bits) agrees too."""
+    monkeypatch.setenv("HALIGN_PROFILE32", "1")
+    rng = np.random.default_rng(m)
+    base = synth.generate("plain64", n_seqs=30, seed=m)
+    center = rng.integers(0, 20, size=m).astype(np.uint8)
+    seqs = synth.SeqSet.from_list([base.seq(k) for k in range(30)] + [center[5:m // 2].copy()])
+    sc = H.Scoring()
+    got = _run(H, ctx, sc, seqs, center, "intra")
+    _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, center, seqs)
+
+
 def test_deterministic_repeat(H, ctx):
     seqs = synth.generate("plain64")
     sc = H.Scoring()
