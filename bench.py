@@ -79,6 +79,70 @@ def cpu_baseline(seqs, center: int, budget_s: float = 20.0):
                       f"({cells:.3e} cells, {dt:.1f} s, one thread per core)"}
 
 
+def learned_report(H, ctx, sc, workload: str, anchors: int, epochs: int):
+    """Learned center on a family set: the exhaustive center (all pairs,
+    score-only) against the trained proposer's judged top-16, with the MSA of
+    each and its avg SP.  Also the untrained network, 16 random candidates and
+    sequence 0 as centers."""
+    import torch
+    from paper_1704_00878_amd import synth
+    log(f"bench: learned center on {workload}")
+    seqs = synth.generate(workload)
+    ds = H.DeviceSeqs(seqs, "cuda:0")
+    N = seqs.n
+    L = seqs.lengths().astype(np.float64)
+    pair_cells = (L.sum() ** 2 - (L * L).sum()) / 2
+    npairs = N * (N - 1) // 2
+
+    def timed(fn):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        r = fn()
+        torch.cuda.synchronize()
+        return r, time.perf_counter() - t
+
+    sums = torch.empty(N, dtype=torch.int64, device="cuda")
+    c_exact, t_exact = timed(lambda: H.halign_center_exact(ctx, sc, ds, sums))
+    S = sums.cpu().numpy()
+    log(f"bench: exact center {c_exact} in {t_exact:.2f} s ({pair_cells / t_exact / 1e9:.0f} GCUPS score-only)")
+    prop = H.Proposer(seed=1)
+    losses, t_train = timed(lambda: H.halign_train_proposer(ctx, sc, ds, prop, anchors=anchors, batch=1024,
+                                                            epochs=epochs, lr=1e-3, seed=7))
+    log(f"bench: trained on {anchors * 64} pairs x {epochs} epochs in {t_train:.2f} s, loss {losses[0]:.4f} -> "
+        f"{losses[-1]:.4f}")
+    (c_learned, cand), t_prop = timed(lambda: H.halign_center_learned(ctx, sc, ds, prop, 16))
+    c_untrained, _ = H.halign_center_learned(ctx, sc, ds, H.Proposer(seed=1), 16)
+    rand = np.random.default_rng(0).choice(N, 16, replace=False)
+    c_random = int(max(rand, key=lambda i: (S[i], -i)))
+
+    def msa_of(c):
+        (msa, _), dt = timed(lambda: H.halign_msa(ctx, sc, ds, c))
+        sp = H.halign_sp_score(sc, msa)[0] / npairs
+        return dt, sp, int(msa.shape[1])
+
+    H.halign_msa(ctx, sc, ds, c_learned)          # warm the buffers
+    res = {}
+    for name, c in (("exact", c_exact), ("learned", c_learned), ("untrained", c_untrained),
+                    ("random16", c_random), ("seq0", 0)):
+        dt, sp, w = msa_of(c)
+        res[name] = {"center": int(c), "objective": int(S[c]), "objective_ratio": round(S[c] / S[c_exact], 5),
+                     "avg_sp": round(sp, 3), "msa_s": round(dt, 5), "width": w}
+        log(f"bench: {name:9s} center {c}: objective ratio {S[c] / S[c_exact]:.4f}, avg SP {sp:.2f}, "
+            f"MSA {dt * 1e3:.1f} ms")
+    return {
+        "workload": f"{workload}: {N} seqs, len {int(L.min())}-{int(L.max())}",
+        "exact_center_s": round(t_exact, 3), "exact_pairs": npairs, "exact_cells": float(pair_cells),
+        "exact_gcups": round(pair_cells / t_exact / 1e9, 1),
+        "train_s": round(t_train, 3), "train_pairs": anchors * 64, "epochs": epochs,
+        "loss_first_last": [round(losses[0], 5), round(losses[-1], 5)],
+        "propose_judge_s": round(t_prop, 4), "candidates": [int(x) for x in cand],
+        "sp_ratio_exact_over_learned": round(res["exact"]["avg_sp"] / res["learned"]["avg_sp"], 5),
+        "learned_msa_s": round(t_prop + res["learned"]["msa_s"], 4),
+        "exact_msa_s": round(t_exact + res["exact"]["msa_s"], 3),
+        "centers": res,
+    }
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -87,8 +151,14 @@ def main():
     ap.add_argument("--workload", default="batch20k")
     ap.add_argument("--route", default="auto", choices=["auto", "intra", "inter"])
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-graph", action="store_true", help="skip the hipGraph-replay measurement")
     ap.add_argument("--perpair", type=int, default=200, help="pairs for the per-pair-launch baseline")
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy")
+    ap.add_argument("--learned", default="learned50k", help="family set for the learned-center report "
+                    "('none' skips it)")
+    ap.add_argument("--anchors", type=int, default=3125, help="training anchors (64 partners each)")
+    ap.add_argument("--epochs", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
@@ -112,13 +182,14 @@ def main():
     sc = H.Scoring()
     ctx = H.Context(0)
     route = {"auto": H.HALIGN_ROUTE_AUTO, "intra": H.HALIGN_ROUTE_INTRA, "inter": H.HALIGN_ROUTE_INTER}[args.route]
-    stream = torch.cuda.current_stream()
 
     def step():
         return H.halign_msa(ctx, sc, ds, center)
 
     if route != H.HALIGN_ROUTE_AUTO:
         os.environ["HALIGN_ROUTE"] = args.route
+    else:
+        ctx.set_autotune(not args.no_autotune)   # the first warm-up call tunes the plan
     log(f"bench: N={seqs.n} m={m} cells={cells:.3e}; warmup {args.warmup}")
     for _ in range(args.warmup):
         step()
@@ -139,7 +210,29 @@ def main():
     fwd_ms = float(np.mean(fwd))
     walk_ms = float(np.mean(walk))
     width = int(msa.shape[1])
-    log(f"bench: {ms_step:.3f} ms/step, {gcups:.1f} GCUPS; forward {fwd_ms:.3f} ms, walk {walk_ms:.3f} ms")
+    plan = ctx.last_plan()
+    log(f"bench: {ms_step:.3f} ms/step, {gcups:.1f} GCUPS; forward {fwd_ms:.3f} ms, walk {walk_ms:.3f} ms; "
+        f"plan {plan}")
+
+    # the same steps with the SW batch replayed from a captured hipGraph
+    graph = None
+    if not args.no_graph:
+        ctx.set_graph(True)
+        for _ in range(2):
+            step()
+        torch.cuda.synchronize()
+        g0 = ctx.graph_launches()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            gmsa, _c = step()
+        torch.cuda.synchronize()
+        gms = (time.perf_counter() - t0) * 1e3 / args.steps
+        ctx.set_graph(False)
+        same = bool(torch.equal(gmsa, msa))
+        graph = {"ms_per_step": round(gms, 4), "gcups": round(cells / (gms * 1e-3) / 1e9, 1),
+                 "replays": ctx.graph_launches() - g0, "msa_equal_eager": same}
+        log(f"bench: graph replay {gms:.3f} ms/step, msa equal to eager: {same}")
+        del gmsa
 
     if args.calibrate_copy:
         # plain device copy of a known size: reference reading for HBM counters
@@ -187,6 +280,10 @@ def main():
         cpu = cpu_baseline(seqs, center)
         log(f"bench: oracle {cpu['value']:.3f} GCUPS on {cpu['cores']} threads")
 
+    learned = None
+    if args.learned != "none":
+        learned = learned_report(H, ctx, sc, args.learned, args.anchors, args.epochs)
+
     out = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
@@ -194,7 +291,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {seqs.n} seqs, len {int(seqs.lengths().min())}-"
                                f"{int(seqs.lengths().max())}, center seq 0 (m={m}), BLOSUM62, gap 11+k",
-                   "cells_per_step": cells, "msa_width": width, "route": ["intra", "inter"][st["route"]]},
+                   "cells_per_step": cells, "msa_width": width, "route": ["intra", "inter"][st["route"]],
+                   "plan": plan},
         "roofline": roof,
         "cpu_baseline": cpu,
         "per_pair_launch": {"value": round(pp_gcups, 3), "unit": "GCUPS", "pairs": len(pick),
@@ -202,6 +300,8 @@ def main():
         "stages_ms": {"forward": round(fwd_ms, 4), "walk": round(walk_ms, 4),
                       "merge_rows_other": round(ms_step - fwd_ms - walk_ms, 4)},
         "avg_sp": round(sp / npairs, 3), "msa_s": round(ms_step / 1e3, 6),
+        "graph_replay": graph,
+        "learned_center": learned,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

@@ -94,8 +94,9 @@ typedef struct {
 
 /* ---- context ------------------------------------------------------------ */
 /* Creates a context on `device`.  workspace_cap_bytes bounds the traceback
- * scratch the context may hold (0 = no cap); a batch whose codes exceed it is
- * processed in chunks with identical results. */
+ * scratch the context may hold (0 = a quarter of the device memory free at
+ * creation); a batch whose codes exceed it is processed in chunks with
+ * identical results. */
 int  halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out);
 void halign_ctx_destroy(halign_ctx *ctx);
 const char *halign_last_error(void);

@@ -69,7 +69,7 @@ struct halign_ctx {
     int num_cu = 256;
     size_t lds_max = 65536;
     // device scratch
-    DevBuf codes, bound, plan, counter, pairbuf, msabuf, spbuf, colbuf, sbuf;
+    DevBuf codes, bound, plan, counter, pairbuf, msabuf, spbuf, sbuf;
     DevBuf mlp[10];          // learned-center scratch (features, activations, gradients, moments)
     // pinned host staging for plans
     HostBuf stage;
@@ -278,6 +278,8 @@ struct BatchOut {
     int32_t *score, *cells, *endcell;
     uint16_t *ins;
     uint32_t *aligned;
+    int32_t *G = nullptr;   // optional: max-merge of ins into G during the walk
+    int gskip = -1;         // pair left out of G (the center itself)
 };
 
 // Plans and runs the forward pass (+ walk when tb) for the pairs `pids_in`
@@ -594,7 +596,17 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             w.ins = out.ins;
             w.aligned = out.aligned;
             w.aw = aw;
-            hipLaunchKernelGGL(hk::walk_kernel, dim3(grid_for(cn, 64, 1 << 30)), dim3(64), 0, st, w);
+            w.G = out.G;
+            w.gskip = out.gskip;
+            const dim3 wg(grid_for(cn, 64, 1 << 30));
+            const bool cl = m <= hk::kWalkCenterLds;
+            if (route == kRouteIntra) {
+                if (cl) hipLaunchKernelGGL((hk::walk_kernel<false, true>), wg, dim3(64), 0, st, w);
+                else hipLaunchKernelGGL((hk::walk_kernel<false, false>), wg, dim3(64), 0, st, w);
+            } else {
+                if (cl) hipLaunchKernelGGL((hk::walk_kernel<true, true>), wg, dim3(64), 0, st, w);
+                else hipLaunchKernelGGL((hk::walk_kernel<true, false>), wg, dim3(64), 0, st, w);
+            }
             HCHK(hipGetLastError());
         }
         RCHK(record(ctx, ctx->ev[2], st));
@@ -792,6 +804,10 @@ int halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out) 
     if (!ctx) return fail(HALIGN_E_NOMEM, "host allocation failed");
     ctx->device = device;
     ctx->cap = workspace_cap_bytes;
+    if (ctx->cap == 0) {   // default: a quarter of the memory free at creation
+        size_t fr = 0, tot = 0;
+        if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr > 0) ctx->cap = fr / 4;
+    }
     if (const char *e = getenv("HALIGN_AUTOTUNE")) ctx->autotune = atoi(e) != 0;
     if (const char *e = getenv("HALIGN_TUNE_CACHE")) ctx->tune_file = e;
     tune_load(ctx);
@@ -823,7 +839,7 @@ void halign_ctx_destroy(halign_ctx *ctx) {
     (void)hipDeviceSynchronize();
     graph_drop(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf, &ctx->colbuf, &ctx->sbuf})
+    for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf, &ctx->sbuf})
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : ctx->mlp)
         if (b.p) (void)hipFree(b.p);
@@ -930,7 +946,7 @@ int halign_encode(const uint8_t *ascii, int64_t len, uint8_t *codes, void *strea
 // The launch sequence of halign_sw_batch (validation, plan, forward, walk).
 static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *center, int32_t m,
                           const halign_seqs *seqs, uint32_t flags, int32_t *score, int32_t *cells, uint16_t *ins,
-                          uint32_t *aligned, void *stream) {
+                          uint32_t *aligned, void *stream, int32_t *G = nullptr, int gskip = -1) {
     if (!ctx) return fail(HALIGN_E_INVALID, "ctx is NULL");
     RCHK(check_scoring(sc));
     RCHK(check_seqs(seqs));
@@ -965,6 +981,11 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
     std::vector<int32_t> pids(N);
     std::iota(pids.begin(), pids.end(), 0);
     BatchOut out{score, cells, endcell, ins, aligned};
+    if (tb && G) {
+        RCHK(launch_fill((uint32_t *)G, 0u, (int64_t)m + 1, st));
+        out.G = G;
+        out.gskip = gskip;
+    }
     RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st, tune));
     ctx->last_tune = {tune.route, tune.R, tune.smul};
     if (!tb && cells) {
@@ -993,16 +1014,17 @@ uint64_t fnv(uint64_t h, const void *p, size_t n) {
 // (pointers, sizes, offsets, scoring) stay the same.
 static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *center, int32_t m,
                           const halign_seqs *seqs, uint32_t flags, int32_t *score, int32_t *cells, uint16_t *ins,
-                          uint32_t *aligned, void *stream) {
+                          uint32_t *aligned, void *stream, int32_t *G = nullptr, int gskip = -1) {
     if (!(flags & HALIGN_GRAPH))
-        return sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream);
+        return sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream, G, gskip);
     if (!ctx || !sc || !seqs || !sc->matrix_host || !seqs->offsets_host)
-        return sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream);
+        return sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream, G, gskip);
     hipStream_t st = (hipStream_t)stream;
     uint64_t key = 0xcbf29ce484222325ull;
-    const void *ptrs[8] = {center, seqs->residues, seqs->offsets, score, cells, ins, aligned, nullptr};
+    const void *ptrs[8] = {center, seqs->residues, seqs->offsets, score, cells, ins, aligned, G};
     key = fnv(key, ptrs, sizeof ptrs);
-    const int32_t ints[7] = {m, seqs->n, (int32_t)flags, sc->alphabet, sc->gap_open, sc->gap_extend, ctx->autotune};
+    const int32_t ints[8] = {m, seqs->n, (int32_t)flags, sc->alphabet, sc->gap_open, sc->gap_extend, ctx->autotune,
+                             gskip};
     key = fnv(key, ints, sizeof ints);
     if (sc->alphabet > 0 && sc->alphabet <= 32)
         key = fnv(key, sc->matrix_host, (size_t)sc->alphabet * sc->alphabet);
@@ -1019,13 +1041,14 @@ static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8
         return HALIGN_OK;
     }
     // first call: run it, then capture the same sequence for later calls
-    RCHK(sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream));
+    RCHK(sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream, G, gskip));
     const int pending = ctx->flag_alpha;
     graph_drop(ctx);
     if (!ctx->cap_stream) HCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     HCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
     ctx->capturing = true;
-    const int rc = sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, ctx->cap_stream);
+    const int rc = sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, ctx->cap_stream, G,
+                                 gskip);
     ctx->capturing = false;
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
@@ -1070,6 +1093,25 @@ int halign_sw_batch(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *ce
     return HALIGN_OK;
 }
 
+}  // extern "C"
+
+// col[p] = sum_{q<p} (G[q] + 1) and the MSA width (copied to the host and
+// synchronised when width_host is given).
+static int merge_offsets(halign_ctx *ctx, const int32_t *G, int m1, int64_t *col, int64_t *width_host,
+                         hipStream_t st) {
+    RCHK(grow(ctx, ctx->spbuf, 4096));
+    int64_t *dwidth = (int64_t *)((char *)ctx->spbuf.p + 2048);
+    hipLaunchKernelGGL(hk::merge_scan_kernel, dim3(1), dim3(1024), 0, st, G, m1, col, dwidth);
+    HCHK(hipGetLastError());
+    if (width_host) {
+        HCHK(hipMemcpyAsync(width_host, dwidth, 8, hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+    }
+    return HALIGN_OK;
+}
+
+extern "C" {
+
 int halign_merge(halign_ctx *ctx, const uint16_t *ins, int32_t n, int32_t m, int32_t *G, int64_t *col,
                  int64_t *width_host, void *stream) {
     if (!ctx || !G || !col || m < 0 || n < 0 || (n > 0 && !ins)) return fail(HALIGN_E_INVALID, "bad arguments");
@@ -1091,15 +1133,7 @@ int halign_merge(halign_ctx *ctx, const uint16_t *ins, int32_t n, int32_t m, int
         }
         HCHK(hipGetLastError());
     }
-    RCHK(grow(ctx, ctx->spbuf, 4096));
-    int64_t *dwidth = (int64_t *)((char *)ctx->spbuf.p + 2048);
-    hipLaunchKernelGGL(hk::merge_scan_kernel, dim3(1), dim3(1024), 0, st, (const int32_t *)G, m1, col, dwidth);
-    HCHK(hipGetLastError());
-    if (width_host) {
-        HCHK(hipMemcpyAsync(width_host, dwidth, 8, hipMemcpyDeviceToHost, st));
-        HCHK(hipStreamSynchronize(st));
-    }
-    return HALIGN_OK;
+    return merge_offsets(ctx, G, m1, col, width_host, st);
 }
 
 int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const uint16_t *ins,
@@ -1112,17 +1146,23 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const 
     hipStream_t st = (hipStream_t)stream;
     const int N = seqs->n;
     if (N == 0 || width == 0) return HALIGN_OK;
-    RCHK(grow(ctx, ctx->colbuf, (size_t)width * 4 + 256));
-    uint32_t *cmap = (uint32_t *)ctx->colbuf.p;
-    hipLaunchKernelGGL(hk::colmap_kernel, dim3((m + 1 + 255) / 256), dim3(256), 0, st, G, col, m, cmap);
-    HCHK(hipGetLastError());
-    const size_t lds_rows = (size_t)(m + 1) * 8;
-    if (lds_rows > ctx->lds_max) return fail(HALIGN_E_UNSUPPORTED, "center too long for row emission");
-    const int cm_lds = lds_rows + (size_t)width * 4 <= 64 * 1024 ? 1 : 0;
-    const size_t lds = lds_rows + (cm_lds ? (size_t)width * 4 : 0);
-    const int grid = std::max(1, std::min(N, ctx->num_cu * 4));
-    hipLaunchKernelGGL(hk::rows_kernel, dim3(grid), dim3(256), lds, st, seqs->residues, seqs->offsets, N, m, ins,
-                       aligned, (m + 31) / 32, (const uint32_t *)cmap, width, cm_lds, msa);
+    // LDS per wavefront: (m+1) block starts and counts, the aligned bits and
+    // a chunk of ch columns
+    const int m1 = m + 1, aw = (m + 31) / 32;
+    const size_t lim = std::min<size_t>(ctx->lds_max, 64 * 1024);
+    auto wave_bytes = [&](int ch) {
+        const size_t head = (4 * (size_t)m1 + (((size_t)m1 * 2 + 3) & ~(size_t)3) + 4 * (size_t)aw + 15) & ~(size_t)15;
+        return head + (size_t)ch + 32;
+    };
+    int ch = (int)std::min<int64_t>(8192, (width + 15) & ~(int64_t)15), wpb = hk::kWaveRows;
+    while (ch > 1024 && (size_t)wpb * wave_bytes(ch) > lim) ch = ((ch / 2) + 15) & ~15;
+    while (wpb > 1 && (size_t)wpb * wave_bytes(ch) > lim) --wpb;
+    if ((size_t)wpb * wave_bytes(ch) > lim) return fail(HALIGN_E_UNSUPPORTED, "center length %d too long for row emission", m);
+    hk::RowsArgs ra{seqs->residues, seqs->offsets, N, m, ins, aligned, aw, G, col, width, ch, (int)wave_bytes(ch), msa};
+    const size_t lds = (size_t)wpb * wave_bytes(ch);
+    const int per_cu = std::max(1, std::min(8, (int)(ctx->lds_max / lds)));
+    const int grid = std::max(1, std::min((N + wpb - 1) / wpb, ctx->num_cu * per_cu));
+    hipLaunchKernelGGL(hk::rows_kernel, dim3(grid), dim3(64 * wpb), lds, st, ra);
     HCHK(hipGetLastError());
     return HALIGN_OK;
 }
@@ -1366,12 +1406,13 @@ int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seq
     int32_t *G = (int32_t *)(wb + o_G);
     int64_t *col = (int64_t *)(wb + o_col);
     const uint8_t *cen = seqs->residues + oh[c];
+    // the walk max-merges every pair's insertion counts into G (the center's own are all zero)
     RCHK(sw_batch_async(ctx, sc, cen, m, seqs, HALIGN_TRACEBACK | (ctx->use_graph ? HALIGN_GRAPH : 0u), score, cells,
-                        ins, al, stream));
+                        ins, al, stream, G, c));
     hipLaunchKernelGGL(hk::center_row_kernel, dim3(1), dim3(256), 0, st, ins, al, c, m, aw);
     HCHK(hipGetLastError());
     int64_t width = 0;
-    RCHK(halign_merge(ctx, ins, N, m, G, col, &width, stream));   // synchronises
+    RCHK(merge_offsets(ctx, G, m + 1, col, &width, st));   // synchronises
     RCHK(validate_check(ctx));
     uint8_t *out = (uint8_t *)alloc((size_t)N * (size_t)width, user);
     if (!out && width > 0) return fail(HALIGN_E_NOMEM, "allocator returned NULL for %lld bytes", (long long)(N * width));

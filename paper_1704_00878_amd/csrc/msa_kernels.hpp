@@ -113,92 +113,102 @@ __global__ void __launch_bounds__(1024) merge_scan_kernel(const int32_t *G, int 
     if (tid == 1023) *width = part[1023] - 1;
 }
 
-// Column map: for every MSA column x, cmap[x] = (p << 16) | t for offset t of
-// gap block p, or (p << 16) | 0xffff for the column of center position p.
-// (A gap block holds at most max_k ins_k[p] < 65535 columns.)
-__global__ void colmap_kernel(const int32_t *G, const int64_t *col, int m, uint32_t *cmap) {
-    const int p = blockIdx.x * blockDim.x + threadIdx.x;
-    if (p > m) return;
-    const int64_t c0 = col[p];
-    const int g = G[p];
-    for (int t = 0; t < g; ++t) cmap[c0 + t] = ((uint32_t)p << 16) | (uint32_t)t;
-    if (p < m) cmap[c0 + g] = ((uint32_t)p << 16) | 0xffffu;
-}
+// Rows: one wavefront per row, up to four wavefronts per workgroup, each
+// with its own LDS region.  Per row the wavefront stages the row's insertion
+// counts and aligned bits, finds where each block starts in the sequence
+// with a wave-wide prefix sum, and builds the row in LDS a chunk of columns
+// at a time: fill with gaps, place every residue at its column (block p by
+// binary search over the block starts; offset t < ins[p] goes to col[p] + t,
+// the aligned residue to the center column col[p] + G[p]), then copy the
+// chunk out with 16-byte stores.  The chunk sits in LDS at the row's
+// misalignment, so aligned LDS words map onto aligned global words.
+constexpr int kWaveRows = 4;
 
-// Rows: a workgroup keeps the column map in LDS (when it fits) and emits many
-// rows; per row it scans (ins + aligned) to find where each block starts in
-// the sequence, then writes the row four columns per store where aligned.
-__device__ __forceinline__ uint8_t row_byte(uint32_t cm, const int *spos, const int *sins, const uint32_t *ar,
-                                            const uint8_t *s, int n) {
-    const int p = (int)(cm >> 16), t = (int)(cm & 0xffffu);
-    uint8_t b = kGap;
-    if (t == 0xffff) {
-        const int q = spos[p] + sins[p];
-        if (((ar[p >> 5] >> (p & 31)) & 1u) && q < n) b = s[q];
-    } else {
-        const int q = spos[p] + t;
-        if (t < sins[p] && q < n) b = s[q];
-    }
-    return b;
-}
+struct RowsArgs {
+    const uint8_t *res;
+    const int64_t *off;
+    int nrows, m;
+    const uint16_t *ins;
+    const uint32_t *aligned;
+    int aw;
+    const int32_t *G;         // [m+1]
+    const int64_t *col;       // [m+1]
+    int64_t width;
+    int ch;                   // columns per chunk (multiple of 16)
+    int wave_bytes;           // LDS bytes per wavefront region
+    uint8_t *msa;             // [nrows][width]
+};
 
-__global__ void __launch_bounds__(256)
-rows_kernel(const uint8_t *res, const int64_t *off, int nrows, int m,
-            const uint16_t *ins, const uint32_t *aligned, int aw,
-            const uint32_t *cmap_g, int64_t width, int cmap_in_lds, uint8_t *msa) {
-    extern __shared__ int sh[];
-    int *spos = sh;                 // [m+1] start of block p in s
-    int *sins = spos + (m + 1);     // [m+1] ins copy
-    uint32_t *cml = reinterpret_cast<uint32_t *>(sins + (m + 1));   // [width] when in LDS
-    __shared__ int partial[256];
-    const int tid = threadIdx.x;
-    if (cmap_in_lds) {
-        for (int64_t x = tid; x < width; x += 256) cml[x] = cmap_g[x];
-    }
-    const uint32_t *cm = cmap_in_lds ? cml : cmap_g;
-    const int m1 = m + 1;
-    const int per = (m1 + 255) / 256;
-    const int lo = min(m1, tid * per), hi = min(m1, lo + per);
-    for (int k = blockIdx.x; k < nrows; k += gridDim.x) {
-        const uint8_t *s = res + off[k];
-        const int n = (int)(off[k + 1] - off[k]);
-        const uint16_t *ir = ins + (int64_t)k * m1;
-        const uint32_t *ar = aligned + (int64_t)k * aw;
-        __syncthreads();   // previous row done with spos / sins
+__global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
+    extern __shared__ uint4 lds_rows[];
+    const int tid = threadIdx.x, wid = tid >> 6, lane = tid & 63;
+    const int wpb = blockDim.x >> 6;
+    const int m = a.m, m1 = m + 1;
+    const int64_t width = a.width;
+    char *wsh = reinterpret_cast<char *>(lds_rows) + (size_t)wid * a.wave_bytes;
+    int *spos = reinterpret_cast<int *>(wsh);                                  // [m1]
+    uint16_t *sins = reinterpret_cast<uint16_t *>(wsh + 4 * (size_t)m1);        // [m1]
+    uint32_t *abit = reinterpret_cast<uint32_t *>(wsh + 4 * (size_t)m1 + (((size_t)m1 * 2 + 3) & ~(size_t)3));
+    const size_t bo = (4 * (size_t)m1 + (((size_t)m1 * 2 + 3) & ~(size_t)3) + 4 * (size_t)a.aw + 15) & ~(size_t)15;
+    uint8_t *buf = reinterpret_cast<uint8_t *>(wsh + bo);                     // [ch + 16], 16-byte aligned
+    uint4 *buf16 = reinterpret_cast<uint4 *>(buf);
+    const int per = (m1 + 63) / 64;
+    const int lo = min(m1, lane * per), hi = min(m1, lo + per);
+    for (int k = blockIdx.x * wpb + wid; k < a.nrows; k += gridDim.x * wpb) {
+        const int64_t so = a.off[k];
+        const int n = (int)(a.off[k + 1] - so);
+        const uint8_t *s = a.res + so;
+        const uint16_t *ir = a.ins + (int64_t)k * m1;
+        const uint32_t *ar = a.aligned + (int64_t)k * a.aw;
+        __builtin_amdgcn_wave_barrier();   // the previous row is done with this region
+        for (int q = lane; q < a.aw; q += 64) abit[q] = ar[q];
+        for (int p = lane; p < m1; p += 64) sins[p] = ir[p];
+        __builtin_amdgcn_wave_barrier();
         int sum = 0;
-        for (int p = lo; p < hi; ++p) {
-            const int v = ir[p];
-            sins[p] = v;
-            sum += v + ((p < m) ? (int)((ar[p >> 5] >> (p & 31)) & 1u) : 0);
+        for (int p = lo; p < hi; ++p)
+            sum += (int)sins[p] + ((p < m) ? (int)((abit[p >> 5] >> (p & 31)) & 1u) : 0);
+        int inc = sum;   // inclusive prefix over the 64 lanes
+        for (int d = 1; d < 64; d <<= 1) {
+            const int v = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += v;
         }
-        partial[tid] = sum;
-        __syncthreads();
-        for (int d = 1; d < 256; d <<= 1) {
-            const int v = tid >= d ? partial[tid - d] : 0;
-            __syncthreads();
-            partial[tid] += v;
-            __syncthreads();
-        }
-        int acc = tid > 0 ? partial[tid - 1] : 0;
+        int acc = inc - sum;
         for (int p = lo; p < hi; ++p) {
             spos[p] = acc;
-            acc += sins[p] + ((p < m) ? (int)((ar[p >> 5] >> (p & 31)) & 1u) : 0);
+            acc += (int)sins[p] + ((p < m) ? (int)((abit[p >> 5] >> (p & 31)) & 1u) : 0);
         }
-        __syncthreads();
-        uint8_t *row = msa + (int64_t)k * width;
-        const int64_t head = min<int64_t>(width, (int64_t)((4 - ((uintptr_t)row & 3)) & 3));
-        if (tid < head) row[tid] = row_byte(cm[tid], spos, sins, ar, s, n);
-        const int64_t nq = (width - head) >> 2;
-        uint32_t *rq = reinterpret_cast<uint32_t *>(row + head);
-        for (int64_t q = tid; q < nq; q += 256) {
-            const int64_t x = head + 4 * q;
-            const uint32_t v = (uint32_t)row_byte(cm[x], spos, sins, ar, s, n) |
-                               ((uint32_t)row_byte(cm[x + 1], spos, sins, ar, s, n) << 8) |
-                               ((uint32_t)row_byte(cm[x + 2], spos, sins, ar, s, n) << 16) |
-                               ((uint32_t)row_byte(cm[x + 3], spos, sins, ar, s, n) << 24);
-            rq[q] = v;
+        __builtin_amdgcn_wave_barrier();
+        uint8_t *row = a.msa + (int64_t)k * width;
+        const int a0 = (int)((uintptr_t)row & 15);
+        for (int64_t x0 = 0; x0 < width; x0 += a.ch) {
+            const int len = (int)min<int64_t>(a.ch, width - x0);
+            const int nw = (a0 + len + 15) >> 4;
+            for (int q = lane; q < nw; q += 64) buf16[q] = make_uint4(~0u, ~0u, ~0u, ~0u);
+            __builtin_amdgcn_wave_barrier();
+            for (int q = lane; q < n; q += 64) {
+                int l = 0, h = m;   // last block whose start is <= q
+                while (l < h) {
+                    const int mid = (l + h + 1) >> 1;
+                    if (spos[mid] <= q) l = mid;
+                    else h = mid - 1;
+                }
+                const int tq = q - spos[l];
+                const int64_t dest = a.col[l] + (tq < (int)sins[l] ? tq : a.G[l]);
+                if (dest >= x0 && dest < x0 + len) buf[a0 + (int)(dest - x0)] = s[q];
+            }
+            __builtin_amdgcn_wave_barrier();
+            // copy out: LDS byte a0 + c holds column x0 + c
+            uint8_t *dst = row + x0 - a0;   // 16-byte aligned (x0 is a multiple of 16)
+            for (int q = lane; q < nw; q += 64) {
+                const int b0 = 16 * q;
+                if (b0 >= a0 && b0 + 16 <= a0 + len) {
+                    *reinterpret_cast<uint4 *>(dst + b0) = buf16[q];
+                } else {
+                    for (int c = max(b0, a0); c < min(b0 + 16, a0 + len); ++c) dst[c] = buf[c];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
         }
-        for (int64_t x = head + 4 * nq + tid; x < width; x += 256) row[x] = row_byte(cm[x], spos, sins, ar, s, n);
     }
 }
 

@@ -550,18 +550,28 @@ struct WalkArgs {
     uint16_t *ins;            // [N][m+1] (zeroed)
     uint32_t *aligned;        // [N][aw] (zeroed)
     int aw;
+    int32_t *G;               // optional [m+1]: max of ins over the walked pairs
+    int gskip;                // pair id kept out of G
 };
 
 constexpr int kWalkCenterLds = 8192;   // centers up to this length are staged in LDS
 
+// One lane per pair.  Each lane keeps four 32-byte code chunks and a 64-byte
+// window of its sequence in LDS: on a miss it loads the chunk it needs, the
+// one to its left and the two that a diagonal path meets in the block above
+// (and refreshes the sequence window), in one round trip.  Lanes advance
+// through their cached data until each misses or ends, so that one memory
+// round trip serves the misses of every lane of the wavefront.
+template <bool STRIP, bool CEN_LDS>
 __global__ void __launch_bounds__(64)
 walk_kernel(WalkArgs a) {
-    __shared__ uint32_t cache[2][8][64];   // two 32-byte code chunks per lane
+    __shared__ uint32_t cache[4][8][64];
+    __shared__ uint32_t swin[16][64];
     __shared__ int8_t smat[32 * 32];
     __shared__ uint8_t scen[kWalkCenterLds];
     const int lane = threadIdx.x;
     const int m = a.m;
-    const bool cen_lds = m <= kWalkCenterLds;
+    constexpr bool cen_lds = CEN_LDS;
     for (int x = lane; x < 1024; x += 64) {
         const int r = x >> 5, q = x & 31;
         smat[x] = (r < a.alpha && q < a.alpha) ? a.mat[r * a.alpha + q] : (int8_t)0;
@@ -574,30 +584,18 @@ walk_kernel(WalkArgs a) {
     const int pid = a.pids[w];
     const int64_t so = a.off[pid];
     const int n = (int)(a.off[pid + 1] - so);
-    // s is read backwards through an aligned 16-byte chunk held in registers
-    // (an aligned 16-byte read that holds a valid byte cannot leave its page)
-    const uint8_t *sres0 = a.res;
-    int64_t schunk = -1;
-    uint4 sbuf = make_uint4(0, 0, 0, 0);
-    auto sres = [&](int jj) __attribute__((always_inline)) -> int {   // s[jj]
-        const int64_t g = so + jj;
-        const int64_t c = g >> 4;
-        if (c != schunk) {
-            schunk = c;
-            sbuf = *reinterpret_cast<const uint4 *>(sres0 + (c << 4));
-        }
-        const int b = (int)(g & 15);
-        const uint64_t q0 = (uint64_t)sbuf.x | ((uint64_t)sbuf.y << 32);
-        const uint64_t q1 = (uint64_t)sbuf.z | ((uint64_t)sbuf.w << 32);
-        const uint64_t q = (b & 8) ? q1 : q0;
-        return (int)((q >> (8 * (b & 7))) & 31u);
-    };
+    // window of residue bytes [swb, swb + 64) of the residue array, read as
+    // four aligned 16-byte chunks that each hold a byte at or below the
+    // position in use (so no read leaves the array's last page)
+    int64_t swb = -1024;
     uint16_t *ins = a.ins + (int64_t)pid * (m + 1);
     uint32_t *al = a.aligned + (int64_t)pid * a.aw;
     int v = a.score[pid];
     int4 *cp = reinterpret_cast<int4 *>(a.cells) + pid;
+    int32_t *gmax = (a.G && pid != a.gskip) ? a.G : nullptr;
     if (v <= 0) {
         ins[0] = (uint16_t)n;
+        if (gmax && n > 0) atomicMax(gmax, n);
         *cp = make_int4(0, 0, 0, 0);
         return;
     }
@@ -605,7 +603,7 @@ walk_kernel(WalkArgs a) {
     const int64_t base = a.cbase[pid];
     const int ccol = a.ccol[pid];
     const int stride = a.cstride[pid];
-    const bool strip = a.kind != 0;
+    constexpr bool strip = STRIP;
     const int R = strip ? 16 : a.R;
     const int G = strip ? (stride + 3) >> 2 : (stride + 7) >> 3;   // groups per pass / strip
     int i = i1, j = j1;
@@ -616,108 +614,173 @@ walk_kernel(WalkArgs a) {
         if (strip) { blk = row >> 4; t = row & 15; }
         else { const int span = 64 * R, ps = row / span, rr = row - ps * span; blk = ps * 64 + rr / R; t = rr % R; }
     }
-    int tb0 = -1, tg0 = -1, tb1 = -1, tg1 = -1, victim = 0;
-    auto nibble = [&]() __attribute__((always_inline)) -> uint32_t {
-        int grp, wi;
-        int64_t addr;
-        if (strip) {
-            grp = (j - 1) >> 2;
-            wi = ((j - 1) & 3) * 2 + (t >> 3);
-            addr = base + (((int64_t)blk * G + grp) * 64 + ccol) * 8;
-        } else {
-            const int k = ccol + j - 1 + (blk & 63);
-            grp = k >> 3;
-            wi = k & 7;
-            addr = base + (((int64_t)(blk >> 6) * G + grp) * 64 + (blk & 63)) * 8;
-        }
-        int sl;
-        if (tb0 == blk && tg0 == grp) sl = 0;
-        else if (tb1 == blk && tg1 == grp) sl = 1;
-        else {
-            sl = victim;
-            victim ^= 1;
-            const uint4 lo = *reinterpret_cast<const uint4 *>(a.codes + addr);
-            const uint4 hi = *reinterpret_cast<const uint4 *>(a.codes + addr + 4);
-            cache[sl][0][lane] = lo.x; cache[sl][1][lane] = lo.y; cache[sl][2][lane] = lo.z; cache[sl][3][lane] = lo.w;
-            cache[sl][4][lane] = hi.x; cache[sl][5][lane] = hi.y; cache[sl][6][lane] = hi.z; cache[sl][7][lane] = hi.w;
-            if (sl == 0) { tb0 = blk; tg0 = grp; }
-            else { tb1 = blk; tg1 = grp; }
-        }
-        const uint32_t word = cache[sl][wi][lane];
-        const int sh = strip ? 4 * (7 - (t & 7)) : 4 * (R - 1 - t);
-        return (word >> sh) & 15u;
+    // chunk (block b, group g): group of 4 columns (strip) or 8 wavefront steps
+    auto grp_of = [&](int b, int jj) __attribute__((always_inline)) -> int {
+        return strip ? (jj - 1) >> 2 : (ccol + jj - 1 + (b & 63)) >> 3;
     };
-    auto up = [&]() __attribute__((always_inline)) {   // i -> i - 1
-        --i;
-        if (--t < 0) { t = R - 1; --blk; }
+    auto chunk_addr = [&](int b, int g) __attribute__((always_inline)) -> int64_t {
+        return strip ? base + (((int64_t)b * G + g) * 64 + ccol) * 8
+                     : base + (((int64_t)(b >> 6) * G + g) * 64 + (b & 63)) * 8;
     };
+    int tb0 = -1, tg0 = -1, tb1 = -1, tg1 = -1, tb2 = -1, tg2 = -1, tb3 = -1, tg3 = -1;
     int state = 0;              // 0 = H, 1 = E, 2 = F
     int run = 0;                // pending insertions at row i
     int insrow = -1, inssum = 0;
     int curw = -1;              // aligned word being accumulated
     uint32_t bits = 0;
+    // stores found inside the stepping loop wait in one pending slot each and
+    // are issued between rounds, so the loop itself touches only LDS
+    int pw = -1, pir = -1, piv = 0;
+    uint32_t pb = 0;
     bool bad = (i1 < 1 || i1 > m || j1 < 1 || j1 > n);
+    bool fin = false;
+    int guard = 0;
     // a path has at most m + n steps; the guard keeps a corrupted code
     // stream from reading outside the matrix or looping
-    for (int guard = 0; !bad; ++guard) {
-        if (guard > m + n + 2 || i < 0 || j < 0) { bad = true; break; }
-        if (state != 0 && (i < 1 || j < 1)) { bad = true; break; }
-        if (state == 0) {
-            if (v == 0) break;
-            if (i < 1 || j < 1) { bad = true; break; }
-            const uint32_t nib = nibble();
-            if (!(nib & 1u)) {
+    while (!bad && !fin) {
+        bool smiss = false;
+        bool cmiss = false;
+        while (true) {
+            // everything about the current cell, then one exit test
+            const int grp = grp_of(blk, j);
+            const bool h0 = tb0 == blk && tg0 == grp, h1 = tb1 == blk && tg1 == grp;
+            const bool h2 = tb2 == blk && tg2 == grp, h3 = tb3 == blk && tg3 == grp;
+            const int sl = h0 ? 0 : (h1 ? 1 : (h2 ? 2 : 3));
+            int wi, sh;
+            if (strip) { wi = ((j - 1) & 3) * 2 + (t >> 3); sh = 4 * (7 - (t & 7)); }
+            else { wi = (ccol + j - 1 + (blk & 63)) & 7; sh = 4 * (R - 1 - t); }
+            const uint32_t nib = (cache[sl][wi & 7][lane] >> (sh & 31)) & 15u;
+            const int gq = (int)(so + j - 1 - swb);
+            const int gqc = min(max(gq, 0), 63);
+            const int ic = min(max(i - 1, 0), m - 1);
+            const int cr = cen_lds ? (int)scen[ic] : (int)(a.center[ic] & 31);
+            const int sr = (int)((swin[gqc >> 2][lane] >> (8 * (gqc & 3))) & 31u);
+            const int sd = (int)smat[cr * 32 + sr];
+            const bool stop = state == 0 && v == 0;
+            const bool badc = guard > m + n + 2 || i < 1 || j < 1;
+            const bool miss = !(h0 || h1 || h2 || h3);
+            // the move out of this cell: diagonal, horizontal (E) or vertical
+            // (F); a switch from H into E or F moves in the same step
+            const bool dm = state == 0 && !(nib & 1u);
+            const bool hm = state == 1 || (state == 0 && (nib & 3u) == 1u);
+            const bool sm = dm && (gq < 0 || gq >= 64);
+            const bool ext = hm ? (nib & 4u) != 0 : (nib & 8u) != 0;
+            const bool fa = dm && curw >= 0 && ((i - 1) >> 5) != curw && pw >= 0;
+            const bool fi = hm && !ext && insrow >= 0 && insrow != i && pir >= 0;
+            if (stop || badc || miss || sm || fa || fi) {
+                fin = stop;
+                bad = !stop && badc;
+                cmiss = !stop && !badc && miss;
+                smiss = !stop && !badc && !miss && sm;
+                break;
+            }
+            ++guard;
+            v += dm ? -sd : (ext ? a.ge : a.goe);
+            if (dm) {
                 const int p = i - 1;
-                const int wi = p >> 5;
-                if (wi != curw) {
-                    if (curw >= 0) al[curw] = bits;
-                    curw = wi;
+                if ((p >> 5) != curw) {
+                    if (curw >= 0) { pw = curw; pb = bits; }
+                    curw = p >> 5;
                     bits = 0;
                 }
                 bits |= 1u << (p & 31);
-                const int cr = cen_lds ? (int)scen[i - 1] : (int)(a.center[i - 1] & 31);
-                v -= (int)smat[cr * 32 + sres(j - 1)];
-                up();
-                --j;
-            } else if (!(nib & 2u)) {
-                state = 1;
-            } else {
-                state = 2;
             }
-        } else if (state == 1) {
-            const uint32_t nib = nibble();
-            ++run;
-            --j;
-            if (nib & 4u) {
-                v += a.ge;
-            } else {
-                v += a.goe;
-                state = 0;
+            run += hm ? 1 : 0;
+            if (hm && !ext) {   // the insertion run ends: it belongs to slot i
                 if (insrow == i) {
                     inssum += run;
                 } else {
-                    if (insrow >= 0) ins[insrow] = (uint16_t)inssum;
+                    if (insrow >= 0) { pir = insrow; piv = inssum; }
                     insrow = i;
                     inssum = run;
                 }
                 run = 0;
             }
-        } else {
-            const uint32_t nib = nibble();
-            up();
-            if (nib & 8u) v += a.ge;
-            else { v += a.goe; state = 0; }
+            state = dm ? 0 : (ext ? (hm ? 1 : 2) : 0);
+            const bool di = !hm, dj = hm || dm;
+            i -= di ? 1 : 0;
+            j -= dj ? 1 : 0;
+            const bool wrap = di && t == 0;
+            t = wrap ? R - 1 : t - (di ? 1 : 0);
+            blk -= wrap ? 1 : 0;
         }
+        if (pw >= 0) { al[pw] = pb; pw = -1; }
+        if (pir >= 0) {
+            ins[pir] = (uint16_t)piv;
+            if (gmax) atomicMax(gmax + pir, piv);
+            pir = -1;
+        }
+        if (bad || fin) break;
+        if (!cmiss && !smiss) continue;   // the loop stopped only to issue stores
+        // the sequence window: moved when it no longer holds the 16 residues
+        // at and below j - 1; reloaded with every code miss (one round trip)
+        const int64_t gs = so + j - 1;
+        int64_t nswb = swb;
+        if (smiss || gs - 15 < swb || gs >= swb + 64) {
+            nswb = (gs & ~(int64_t)15) - 48;
+            if (nswb < 0) nswb = 0;
+        }
+        const uint4 *src = reinterpret_cast<const uint4 *>(a.res + nswb);
+        const uint4 s0 = src[0], s1 = src[1], s2 = src[2], s3 = src[3];
+        if (smiss) {
+            swin[0][lane] = s0.x; swin[1][lane] = s0.y; swin[2][lane] = s0.z; swin[3][lane] = s0.w;
+            swin[4][lane] = s1.x; swin[5][lane] = s1.y; swin[6][lane] = s1.z; swin[7][lane] = s1.w;
+            swin[8][lane] = s2.x; swin[9][lane] = s2.y; swin[10][lane] = s2.z; swin[11][lane] = s2.w;
+            swin[12][lane] = s3.x; swin[13][lane] = s3.y; swin[14][lane] = s3.z; swin[15][lane] = s3.w;
+            swb = nswb;
+            continue;
+        }
+        // miss at (blk, grp(j)): load it, its left neighbour, and the two
+        // chunks of the block above where a diagonal path enters it
+        const int g0 = grp_of(blk, j);
+        const int jn = j - (t + 1);
+        const int g2 = (blk >= 1 && jn >= 1) ? grp_of(blk - 1, jn) : -1;
+        const int64_t ad0 = chunk_addr(blk, g0);
+        const int64_t ad1 = g0 >= 1 ? chunk_addr(blk, g0 - 1) : ad0;
+        const int64_t ad2 = g2 >= 0 ? chunk_addr(blk - 1, g2) : ad0;
+        const int64_t ad3 = g2 >= 1 ? chunk_addr(blk - 1, g2 - 1) : ad0;
+        const uint4 c0l = *reinterpret_cast<const uint4 *>(a.codes + ad0);
+        const uint4 c0h = *reinterpret_cast<const uint4 *>(a.codes + ad0 + 4);
+        const uint4 c1l = *reinterpret_cast<const uint4 *>(a.codes + ad1);
+        const uint4 c1h = *reinterpret_cast<const uint4 *>(a.codes + ad1 + 4);
+        const uint4 c2l = *reinterpret_cast<const uint4 *>(a.codes + ad2);
+        const uint4 c2h = *reinterpret_cast<const uint4 *>(a.codes + ad2 + 4);
+        const uint4 c3l = *reinterpret_cast<const uint4 *>(a.codes + ad3);
+        const uint4 c3h = *reinterpret_cast<const uint4 *>(a.codes + ad3 + 4);
+        swin[0][lane] = s0.x; swin[1][lane] = s0.y; swin[2][lane] = s0.z; swin[3][lane] = s0.w;
+        swin[4][lane] = s1.x; swin[5][lane] = s1.y; swin[6][lane] = s1.z; swin[7][lane] = s1.w;
+        swin[8][lane] = s2.x; swin[9][lane] = s2.y; swin[10][lane] = s2.z; swin[11][lane] = s2.w;
+        swin[12][lane] = s3.x; swin[13][lane] = s3.y; swin[14][lane] = s3.z; swin[15][lane] = s3.w;
+        swb = nswb;
+        cache[0][0][lane] = c0l.x; cache[0][1][lane] = c0l.y; cache[0][2][lane] = c0l.z; cache[0][3][lane] = c0l.w;
+        cache[0][4][lane] = c0h.x; cache[0][5][lane] = c0h.y; cache[0][6][lane] = c0h.z; cache[0][7][lane] = c0h.w;
+        cache[1][0][lane] = c1l.x; cache[1][1][lane] = c1l.y; cache[1][2][lane] = c1l.z; cache[1][3][lane] = c1l.w;
+        cache[1][4][lane] = c1h.x; cache[1][5][lane] = c1h.y; cache[1][6][lane] = c1h.z; cache[1][7][lane] = c1h.w;
+        cache[2][0][lane] = c2l.x; cache[2][1][lane] = c2l.y; cache[2][2][lane] = c2l.z; cache[2][3][lane] = c2l.w;
+        cache[2][4][lane] = c2h.x; cache[2][5][lane] = c2h.y; cache[2][6][lane] = c2h.z; cache[2][7][lane] = c2h.w;
+        cache[3][0][lane] = c3l.x; cache[3][1][lane] = c3l.y; cache[3][2][lane] = c3l.z; cache[3][3][lane] = c3l.w;
+        cache[3][4][lane] = c3h.x; cache[3][5][lane] = c3h.y; cache[3][6][lane] = c3h.z; cache[3][7][lane] = c3h.w;
+        tb0 = blk; tg0 = g0;
+        tb1 = g0 >= 1 ? blk : -1; tg1 = g0 - 1;
+        tb2 = g2 >= 0 ? blk - 1 : -1; tg2 = g2;
+        tb3 = g2 >= 1 ? blk - 1 : -1; tg3 = g2 - 1;
     }
     if (bad) {
         *cp = make_int4(-1, -1, -1, -1);
         return;
     }
-    if (insrow >= 0) ins[insrow] = (uint16_t)inssum;
+    if (insrow >= 0) {
+        ins[insrow] = (uint16_t)inssum;
+        if (gmax) atomicMax(gmax + insrow, inssum);
+    }
     if (curw >= 0) al[curw] = bits;
     // core insertions sit in slots 1..m-1, so slots 0 and m hold the flanks only
     ins[0] = (uint16_t)j;
     ins[m] = (uint16_t)(n - j1);
+    if (gmax) {
+        if (j > 0) atomicMax(gmax, j);
+        if (n - j1 > 0) atomicMax(gmax + m, n - j1);
+    }
     *cp = make_int4(i, j, i1, j1);
 }
 

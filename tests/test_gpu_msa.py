@@ -71,6 +71,22 @@ def test_msa_edge_sets(H, ctx):
     assert (got[0] == base.seq(2)).all()
 
 
+def test_msa_wide_rows(H, ctx):
+    """Rows wider than one LDS chunk of columns (long unrelated flanks) and
+    rows that start at every alignment modulo 16."""
+    rng = np.random.default_rng(5)
+    base = synth.generate("plain64", n_seqs=8)
+    parts = [base.seq(0), rng.integers(0, 20, size=9000).astype(np.uint8), base.seq(3),
+             rng.integers(0, 20, size=12345).astype(np.uint8), np.zeros(0, np.uint8), base.seq(5)[10:]]
+    parts += [base.seq(k % 8)[: 40 + 7 * k] for k in range(17)]
+    seqs = synth.SeqSet.from_list(parts)
+    got, _ = _msa(H, ctx, seqs, 0)
+    ref = oracle.msa(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets, 0)
+    assert ref["width"] > 8192
+    assert got.shape == ref["msa"].shape
+    assert (got == ref["msa"]).all()
+
+
 def test_merge_and_rows_calls(H, ctx):
     """halign_merge and halign_emit_rows on oracle-made center-star vectors."""
     import torch
