@@ -290,15 +290,20 @@ def halign_sp_score(sc: Scoring, msa, stream=None):
     return int(out[0]), int(out[1])
 
 
-def halign_msa(ctx: Context, sc: Scoring, seqs: DeviceSeqs, center: int, model=None, stream=None):
-    """End-to-end MSA.  Returns (msa uint8 tensor [N, W], center index)."""
+def halign_msa(ctx: Context, sc: Scoring, seqs: DeviceSeqs, center: int, model=None, stream=None, out=None):
+    """End-to-end MSA.  Returns (msa uint8 tensor [N, W], center index).
+    `out`: an optional uint8 device tensor that the MSA is written into when it
+    holds N * W bytes (the result is then a view of it); otherwise a new
+    tensor is allocated once W is known."""
     import torch
     keep = {}
 
     def _alloc(nbytes, user):
-        t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{ctx.device}")
-        keep["t"] = t
-        return t.data_ptr()
+        if out is not None and out.dtype == torch.uint8 and out.is_contiguous() and out.numel() >= nbytes:
+            keep["t"] = out.view(-1)
+        else:
+            keep["t"] = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        return keep["t"].data_ptr()
 
     cb = _ALLOC_FN(_alloc)
     out_ptr = ctypes.c_void_p()

@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <fstream>
+#include <functional>
 #include <map>
 #include <sstream>
 #include <cstdarg>
@@ -292,22 +293,33 @@ struct Tune {
 
 int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq,
               const std::vector<int32_t> &pids_in, bool tb, bool endc, int route, const BatchOut &out,
-              hipStream_t st, const Tune &tune = Tune()) {
+              hipStream_t st, const Tune &tune = Tune(), const std::function<int()> &after_forward = nullptr) {
     const int64_t *oh = sq->offsets_host;
     const int N = sq->n;
     const int np = (int)pids_in.size();
     if (np == 0) return HALIGN_OK;
     auto len = [&](int pid) { return (int)(oh[pid + 1] - oh[pid]); };
-    // longest first (counting sort on length, stable)
-    std::vector<int32_t> pids(np);
+    // longest first (counting sort on length, stable); plen[x] = length of
+    // pids[x], so that later passes read lengths in order
+    std::vector<int32_t> pids(np), plen(np);
+    int64_t sum_len = 0;
     {
+        std::vector<int32_t> lin(np);
         int maxlen = 0;
-        for (int x = 0; x < np; ++x) maxlen = std::max(maxlen, len(pids_in[x]));
+        for (int x = 0; x < np; ++x) {
+            lin[x] = len(pids_in[x]);
+            maxlen = std::max(maxlen, lin[x]);
+            sum_len += lin[x];
+        }
         std::vector<int32_t> cnt(maxlen + 2, 0);
-        for (int x = 0; x < np; ++x) cnt[maxlen - len(pids_in[x])]++;
+        for (int x = 0; x < np; ++x) cnt[maxlen - lin[x]]++;
         int acc = 0;
         for (auto &c : cnt) { const int v = c; c = acc; acc += v; }
-        for (int x = 0; x < np; ++x) pids[cnt[maxlen - len(pids_in[x])]++] = pids_in[x];
+        for (int x = 0; x < np; ++x) {
+            const int q = cnt[maxlen - lin[x]]++;
+            pids[q] = pids_in[x];
+            plen[q] = lin[x];
+        }
     }
     const int aw = (m + 31) / 32;
     int R = 8, passes = 1;
@@ -321,8 +333,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
     // max score <= max(S) * min(m, longest sequence)
     int smax = 1;
     for (int x = 0; x < S.alpha * S.alpha; ++x) smax = std::max(smax, (int)S.hmat[x]);
-    int nlong = 0;
-    for (int x = 0; x < np; ++x) nlong = std::max(nlong, len(pids[x]));
+    const int nlong = plen[0];
     const bool p16 = (int64_t)smax * std::min(m, nlong) <= 32000 && S.goe + 128 <= 32000 &&
                      !getenv("HALIGN_PROFILE32");
     const size_t prof_bytes = p16 ? (size_t)(S.alpha + 1) * 64 * 8 * 2 : (size_t)hk::kAlphaMax * 64 * R * 4;
@@ -333,12 +344,16 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
     // chunk the pairs so that codes + boundary rows fit the cap
     const size_t cap = ctx->cap ? ctx->cap : (size_t)1 << 62;
     std::vector<std::pair<int, int>> chunks;  // [lo, hi) in pids
-    {
+    const size_t intra_bytes = (tb ? (size_t)passes * 64 * 4 * ((size_t)sum_len + 8 * (size_t)np) : 0) +
+                               (size_t)(passes - 1) * 8 * (size_t)sum_len;
+    if (route == kRouteIntra && intra_bytes <= cap) {
+        chunks.push_back({0, np});
+    } else {
         const int nst = (m + hk::kT - 1) / hk::kT;
         int lo = 0;
         size_t acc = 0;
         for (int x = 0; x < np; ++x) {
-            const int n = len(pids[x]);
+            const int n = plen[x];
             size_t b = 0;
             bool boundary = true;
             if (route == kRouteIntra) {
@@ -357,8 +372,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         chunks.push_back({lo, np});
     }
     ctx->last_stats[3] = (int64_t)chunks.size();
-    int64_t cells_total = 0;
-    for (int x = 0; x < np; ++x) cells_total += (int64_t)m * len(pids[x]);
+    const int64_t cells_total = (int64_t)m * sum_len;
     ctx->last_stats[0] = cells_total;
     RCHK(grow(ctx, ctx->counter, 256));
     int *counter = (int *)ctx->counter.p;
@@ -371,10 +385,14 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         PlanBuilder pb;
         size_t code_words = 0, bound_elems = 0;
         int nmax_all = 0;
-        for (int x = lo; x < hi; ++x) nmax_all = std::max(nmax_all, len(pids[x]));
-        // common: per-pid walk descriptors and the walk list
-        const size_t o_cbase = pb.add(sizeof(int64_t) * N), o_cstr = pb.add(sizeof(int32_t) * N),
-                     o_ccol = pb.add(sizeof(int32_t) * N), o_walk = pb.add(sizeof(int32_t) * cn);
+        nmax_all = plen[lo];
+        // strip route: per-pid walk descriptors and the walk list (the
+        // wavefront route's walk reads the per-slot and per-stream plan)
+        const bool strip_plan = route != kRouteIntra;
+        const size_t o_cbase = strip_plan ? pb.add(sizeof(int64_t) * N) : 0,
+                     o_cstr = strip_plan ? pb.add(sizeof(int32_t) * N) : 0,
+                     o_ccol = strip_plan ? pb.add(sizeof(int32_t) * N) : 0,
+                     o_walk = strip_plan ? pb.add(sizeof(int32_t) * cn) : 0;
         size_t o_sbeg = 0, o_slot0 = 0, o_scb = 0, o_sbb = 0, o_spid = 0, o_scol = 0;
         size_t o_order = 0, o_gnmax = 0, o_gcb = 0;
         int nstreams = 0, nslots = 0, ngroups = 0;
@@ -383,7 +401,8 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             // streams: snake-deal the (longest first) non-empty pairs over the
             // resident waves so that every stream has about the same columns
             int nonempty = 0;
-            for (int x = lo; x < hi; ++x) nonempty += len(pids[x]) > 0;
+            for (int x = hi - 1; x >= lo && plen[x] == 0; --x) ++nonempty;
+            nonempty = cn - nonempty;   // empty pairs sort last
             const int wg_per_cu = std::max(1, std::min(4, (int)(ctx->lds_max / lds_stream)));
             const int resident = ctx->num_cu * wg_per_cu * 8 * std::max(1, tune.smul);
             nstreams = std::max(1, std::min(nonempty, resident));
@@ -410,7 +429,8 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         int64_t *h_cbase = (int64_t *)(hs + o_cbase);
         int32_t *h_cstr = (int32_t *)(hs + o_cstr);
         int32_t *h_ccol = (int32_t *)(hs + o_ccol);
-        for (int x = 0; x < cn; ++x) h_walk[x] = pids[lo + x];
+        if (strip_plan)
+            for (int x = 0; x < cn; ++x) h_walk[x] = pids[lo + x];
         if (route == kRouteIntra) {
             int64_t *h_sbeg = (int64_t *)(hs + o_sbeg);
             int32_t *h_slot0 = (int32_t *)(hs + o_slot0);
@@ -422,16 +442,15 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             std::vector<int32_t> scount(nstreams, 0), sfill(nstreams, 0);
             std::vector<int64_t> scols(nstreams, 0);
             std::vector<int32_t> sof(cn, -1);
-            int e = 0;
+            int r = 0, q = 0;   // round and position of the next non-empty pair
             for (int x = 0; x < cn; ++x) {
-                const int n = len(pids[lo + x]);
+                const int n = plen[lo + x];
                 if (n == 0) continue;
-                const int r = e / nstreams, q = e % nstreams;
                 const int s = (r & 1) ? nstreams - 1 - q : q;
                 sof[x] = s;
                 scount[s]++;
                 scols[s] += n;
-                ++e;
+                if (++q == nstreams) { q = 0; ++r; }
             }
             int slot = 0;
             int64_t col = 0;
@@ -456,18 +475,12 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                     h_spid[eslot] = pid;
                     h_scol[eslot] = 0;
                     ++eslot;
-                    h_cbase[pid] = 0;
-                    h_cstr[pid] = 1;
-                    h_ccol[pid] = 0;
                     continue;
                 }
                 const int q = h_slot0[s] + sfill[s]++;
                 h_spid[q] = pid;
                 h_scol[q] = h_sbeg[s] + spos[s];
-                h_cbase[pid] = h_scb[s];
-                h_ccol[pid] = (int)spos[s];
-                h_cstr[pid] = (int)(scols[s] + 63);
-                spos[s] += len(pid);
+                spos[s] += plen[lo + x];
             }
         } else {
             int32_t *h_order = (int32_t *)(hs + o_order);
@@ -541,6 +554,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                                (const unsigned long long *)keys, (const int32_t *)(dplan + o_spid), nslots, out.score,
                                endc ? out.endcell : (int32_t *)nullptr);
             HCHK(hipGetLastError());
+            if (ci == 0 && after_forward) RCHK(after_forward());
         } else {
             const int slots = ctx->num_cu * 16;
             const int grid = std::max(1, std::min(ngroups, slots));
@@ -570,6 +584,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             launch_inter(a, tb, endc, grid, st);
             HCHK(hipGetLastError());
             RCHK(record(ctx, ctx->ev[1], st));
+            if (ci == 0 && after_forward) RCHK(after_forward());
         }
         ++launches;
         if (tb) {
@@ -580,16 +595,24 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             w.m = m;
             w.res = sq->residues;
             w.off = sq->offsets;
-            w.pids = (const int32_t *)(dplan + o_walk);
+            w.pids = strip_plan ? (const int32_t *)(dplan + o_walk) : nullptr;
             w.npairs = cn;
+            if (!strip_plan) {
+                w.slot_pid = (const int32_t *)(dplan + o_spid);
+                w.slot_col = (const int64_t *)(dplan + o_scol);
+                w.sbeg = (const int64_t *)(dplan + o_sbeg);
+                w.slot0 = (const int32_t *)(dplan + o_slot0);
+                w.scb = (const int64_t *)(dplan + o_scb);
+                w.nstreams = nstreams;
+            }
             w.ge = S.ge;
             w.goe = S.goe;
             w.score = out.score;
             w.endcell = out.endcell;
             w.codes = (const uint32_t *)ctx->codes.p;
-            w.cbase = (const int64_t *)(dplan + o_cbase);
-            w.cstride = (const int32_t *)(dplan + o_cstr);
-            w.ccol = (const int32_t *)(dplan + o_ccol);
+            w.cbase = strip_plan ? (const int64_t *)(dplan + o_cbase) : nullptr;
+            w.cstride = strip_plan ? (const int32_t *)(dplan + o_cstr) : nullptr;
+            w.ccol = strip_plan ? (const int32_t *)(dplan + o_ccol) : nullptr;
             w.R = R;
             w.kind = route == kRouteIntra ? 0 : 1;
             w.cells = out.cells;
@@ -635,11 +658,11 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
 // length, traceback) it times the candidate plans on a strided sample of the
 // batch (every plan gives bit-identical results) and keeps the fastest.
 // ---------------------------------------------------------------------------
-std::string tune_key(int m, int N, int med, bool tb) {
+std::string tune_key(int m, int N, int mean_len, bool tb) {
     int lg = 0;
     while ((1 << (lg + 1)) <= N) ++lg;
     std::ostringstream o;
-    o << "m" << (m + 31) / 32 << "_n" << lg << "_l" << (med + 63) / 64 << "_t" << (tb ? 1 : 0);
+    o << "m" << (m + 31) / 32 << "_n" << lg << "_l" << (mean_len + 63) / 64 << "_t" << (tb ? 1 : 0);
     return o.str();
 }
 
@@ -666,11 +689,8 @@ void tune_save(halign_ctx *ctx, const std::string &key, const std::array<int, 3>
 int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq, bool tb,
              bool endc, const BatchOut &out, hipStream_t st, Tune *best) {
     const int N = sq->n;
-    std::vector<int> lens(N);
-    for (int k = 0; k < N; ++k) lens[k] = (int)(sq->offsets_host[k + 1] - sq->offsets_host[k]);
-    std::vector<int> sl(lens);
-    std::nth_element(sl.begin(), sl.begin() + N / 2, sl.end());
-    const std::string key = tune_key(m, N, sl[N / 2], tb);
+    const int mean = N > 0 ? (int)((sq->offsets_host[N] - sq->offsets_host[0]) / N) : 0;
+    const std::string key = tune_key(m, N, mean, tb);
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) {
         best->route = it->second[0];
@@ -961,7 +981,6 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
     if (N == 0) return HALIGN_OK;
     Scoring S;
     RCHK(upload_matrix(ctx, sc, st, &S));
-    RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], center, m, st));
     // endcells: needed by the walk, or to fill cells in score-only mode
     const bool endc = tb || cells != nullptr;
     RCHK(grow(ctx, ctx->pairbuf, (size_t)N * 8 + 256));
@@ -972,21 +991,29 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
         BatchOut tout{score, cells, endcell, ins, aligned};
         RCHK(autotune(ctx, S, center, m, seqs, tb, endc, tout, st, &tune));
     }
-    if (tb) {
-        hipLaunchKernelGGL(hk::fill_u16_kernel, dim3(grid_for((int64_t)N * (m + 1), 256, 4096)), dim3(256), 0, st,
-                           ins, (uint16_t)0, (int64_t)N * (m + 1));
-        HCHK(hipGetLastError());
-        RCHK(launch_fill(aligned, 0u, (int64_t)N * ((m + 31) / 32), st));
-    }
+    // the code check and the zeroing of the outputs go in behind the first
+    // forward launch (the forward kernels read codes masked to 5 bits, and the
+    // outputs are first written by the walk), so the GPU starts on the DP as
+    // soon as the plan is ready
+    auto prep = [&]() -> int {
+        RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], center, m, st));
+        if (tb) {
+            hipLaunchKernelGGL(hk::fill_u16_kernel, dim3(grid_for((int64_t)N * (m + 1), 256, 4096)), dim3(256), 0,
+                               st, ins, (uint16_t)0, (int64_t)N * (m + 1));
+            HCHK(hipGetLastError());
+            RCHK(launch_fill(aligned, 0u, (int64_t)N * ((m + 31) / 32), st));
+            if (G) RCHK(launch_fill((uint32_t *)G, 0u, (int64_t)m + 1, st));
+        }
+        return HALIGN_OK;
+    };
     std::vector<int32_t> pids(N);
     std::iota(pids.begin(), pids.end(), 0);
     BatchOut out{score, cells, endcell, ins, aligned};
     if (tb && G) {
-        RCHK(launch_fill((uint32_t *)G, 0u, (int64_t)m + 1, st));
         out.G = G;
         out.gskip = gskip;
     }
-    RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st, tune));
+    RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st, tune, prep));
     ctx->last_tune = {tune.route, tune.R, tune.smul};
     if (!tb && cells) {
         // score-only with cells: report the end cell as (0, 0, i1, j1)
@@ -999,9 +1026,18 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
 
 namespace {
 
+// FNV-1a over 8-byte words (then the tail bytes)
 uint64_t fnv(uint64_t h, const void *p, size_t n) {
     const uint8_t *b = (const uint8_t *)p;
-    for (size_t i = 0; i < n; ++i) { h ^= b[i]; h *= 0x100000001b3ull; }
+    size_t i = 0;
+    for (; i + 8 <= n; i += 8) {
+        uint64_t w;
+        memcpy(&w, b + i, 8);
+        h ^= w;
+        h *= 0x100000001b3ull;
+        h ^= h >> 29;
+    }
+    for (; i < n; ++i) { h ^= b[i]; h *= 0x100000001b3ull; }
     return h;
 }
 

@@ -552,6 +552,16 @@ struct WalkArgs {
     int aw;
     int32_t *G;               // optional [m+1]: max of ins over the walked pairs
     int gskip;                // pair id kept out of G
+    // wavefront layout: the walk runs over slots; slot q holds pair
+    // slot_pid[q] at stream column slot_col[q] of the stream s with
+    // slot0[s] <= q < slot0[s+1] (streams hold at least one pair each;
+    // empty pairs sit in slots after the streamed ones)
+    const int32_t *slot_pid;
+    const int64_t *slot_col;
+    const int64_t *sbeg;      // [nstreams + 1]
+    const int32_t *slot0;     // [nstreams]
+    const int64_t *scb;       // [nstreams] code word base
+    int nstreams;
 };
 
 constexpr int kWalkCenterLds = 8192;   // centers up to this length are staged in LDS
@@ -581,7 +591,7 @@ walk_kernel(WalkArgs a) {
     __syncthreads();
     const int w = blockIdx.x * 64 + lane;
     if (w >= a.npairs) return;
-    const int pid = a.pids[w];
+    const int pid = STRIP ? a.pids[w] : a.slot_pid[w];
     const int64_t so = a.off[pid];
     const int n = (int)(a.off[pid + 1] - so);
     // window of residue bytes [swb, swb + 64) of the residue array, read as
@@ -600,9 +610,23 @@ walk_kernel(WalkArgs a) {
         return;
     }
     const int i1 = a.endcell[2 * pid], j1 = a.endcell[2 * pid + 1];
-    const int64_t base = a.cbase[pid];
-    const int ccol = a.ccol[pid];
-    const int stride = a.cstride[pid];
+    int64_t base;
+    int ccol, stride;
+    if (STRIP) {
+        base = a.cbase[pid];
+        ccol = a.ccol[pid];
+        stride = a.cstride[pid];
+    } else {   // stream of slot w: the last s with slot0[s] <= w
+        int lo = 0, hi = a.nstreams - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.slot0[mid] <= w) lo = mid;
+            else hi = mid - 1;
+        }
+        base = a.scb[lo];
+        ccol = (int)(a.slot_col[w] - a.sbeg[lo]);
+        stride = (int)(a.sbeg[lo + 1] - a.sbeg[lo]) + 63;
+    }
     constexpr bool strip = STRIP;
     const int R = strip ? 16 : a.R;
     const int G = strip ? (stride + 3) >> 2 : (stride + 7) >> 3;   // groups per pass / strip
