@@ -527,7 +527,8 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             if (passes > 1) RCHK(grow(ctx, ctx->bound, std::max<size_t>(8, bound_elems * 8)));
             RCHK(launch_fill((uint32_t *)keys, 0u, 2 * (int64_t)nslots, st));
             hipLaunchKernelGGL(hk::stage_stream_kernel, dim3(nslots), dim3(128), 0, st, sq->residues, sq->offsets,
-                               (const int32_t *)(dplan + o_spid), (const int64_t *)(dplan + o_scol), nslots, sres);
+                               (const int32_t *)(dplan + o_spid), (const int64_t *)(dplan + o_scol), nslots,
+                               p16 ? S.alpha : 31, sres);
             HCHK(hipGetLastError());
             RCHK(record(ctx, ctx->ev[0], st));
             hk::StreamArgs a{};

@@ -28,6 +28,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <type_traits>
 
 namespace hk {
 
@@ -141,8 +142,17 @@ __device__ __forceinline__ unsigned long long cell_key(const BestCell &b, bool e
 // 16-byte LDS read per step, values folded into the add as sign-extended
 // halves; valid when every score and S + goe fit in 16 bits (checked by the
 // host).  Otherwise int32 [32][64R].
+// The step loop is unrolled by 8: a lane's 8 code words of a tile are staged
+// in LDS and go out as two 16-byte stores, and the loop runs over whole
+// tiles (steps rounded up to a multiple of 8; the extra steps see padding
+// columns).  A lane keeps, for the current pair, its max H, the step of the
+// first column that reached it and that column's key (smallest row), which
+// is the max-H / min-j / min-i rule restricted to its rows.  The last pair
+// of a stream is published after the loop: padding columns after a stream
+// never raise H above the stream's maximum (E and F only decay there).  The
+// loop is compiled twice: with and without boundary rows between passes.
 template <int R, bool TB, bool ENDC, bool P16>
-__global__ void __launch_bounds__(512)
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
 sw_stream_kernel(StreamArgs a) {
     extern __shared__ int prof[];   // profile, then code staging [8 waves][64][8]
     constexpr int SPAN = 64 * R;
@@ -166,6 +176,7 @@ sw_stream_kernel(StreamArgs a) {
     }
     const uint8_t *sr = a.sres + b0;
     const int steps = C + 63;
+    const int steps8 = (steps + 7) & ~7;
     for (int pass = 0; pass < a.passes; ++pass) {
         const int row0 = pass * SPAN;
         __syncthreads();
@@ -189,108 +200,127 @@ sw_stream_kernel(StreamArgs a) {
         __syncthreads();
         if (!active) continue;
         const int myrow = row0 + lane * R;
-        int hg[R], e[R];
-#pragma unroll
-        for (int t = 0; t < R; ++t) { hg[t] = -goe; e[t] = 0; }
-        int botg = -goe, botf = 0;   // this lane's bottom row values (last step)
-        int diag0 = -goe;            // Hg(myrow-1, j-1) for row 0
-        int rcur = kPad;             // staged residue of this lane's column
-        int rbuf = kPad;             // staged residues of columns kb .. kb+63 across lanes
-        int2 bbuf = make_int2(-goe, 0);
+        const int *pbase = prof + lane * R;
         const int2 *bin = (pass > 0) ? a.bound + a.sbbase[sid] + (int64_t)(pass - 1) * C : nullptr;
         int2 *bout = (pass + 1 < a.passes) ? a.bound + a.sbbase[sid] + (int64_t)pass * C : nullptr;
         const int G = (steps + 7) >> 3;
         uint32_t *cw = TB ? a.codes + a.scbase[sid] + (int64_t)pass * G * 512 + lane * 8 : nullptr;
-        const int *pbase = prof + lane * R;
-        int pl = -1;                 // this lane's pair index within the stream
-        int jl = 0;                  // column index within that pair
-        BestCell best{0, 0x7fffffff, 0x7fffffff};
-        int hm = 0;
-        for (int k = 0; k < steps; ++k) {
-            if ((k & 63) == 0) {
-                const int kk = k + lane;
-                rbuf = (kk < C) ? (int)sr[kk] : kPad;
-                if (bin) bbuf = (kk < C) ? bin[kk] : make_int2(-goe, 0);
-            }
-            const int rin = __builtin_amdgcn_readlane(rbuf, k & 63);
-            int tg = -goe, tf = 0;
-            if (bin) {
-                tg = __builtin_amdgcn_readlane(bbuf.x, k & 63);
-                tf = __builtin_amdgcn_readlane(bbuf.y, k & 63);
-            }
-            rcur = __builtin_amdgcn_update_dpp(rin, rcur, 0x138, 0xf, 0xf, false);
-            int upg = __builtin_amdgcn_update_dpp(tg, botg, 0x138, 0xf, 0xf, false);
-            int upf = __builtin_amdgcn_update_dpp(tf, botf, 0x138, 0xf, 0xf, false);
-            const int K = k - lane;  // stream column of this lane
-            if (rcur & kFirstCol) {
-                // leave the previous pair, enter the next one at its column 1
-                if (pl >= 0 && best.h > 0) atomicMax(a.keys + slot0 + pl, cell_key(best, ENDC));
-                ++pl;
-                jl = 0;
-                best.h = 0; best.j = 0x7fffffff; best.i = 0x7fffffff;
+        // staged residue codes are already clamped to the profile rows; the
+        // first-column flag moves to bit 31 (so the profile index shifts it out)
+        const int padc = P16 ? a.alpha : kPad;
+        auto conv = [&](int b) __attribute__((always_inline)) { return (b & 0x7f) | ((b & 0x80) << 24); };
+        // the loop, specialised on whether boundary rows come in or go out
+        auto run = [&](auto hb_tag) __attribute__((always_inline)) {
+            constexpr bool HB = decltype(hb_tag)::value;
+            int hg[R], e[R];
 #pragma unroll
-                for (int t = 0; t < R; ++t) { hg[t] = -goe; e[t] = 0; }
-                diag0 = -goe;
-            }
-            ++jl;
-            int diag = diag0;
-            diag0 = upg;
-            int p[R];
-            if (P16) {
-                const int prw = min(rcur & 31, a.alpha);
-                const uint4 q = reinterpret_cast<const uint4 *>(prof)[prw * 64 + lane];
-                const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
+            for (int t = 0; t < R; ++t) { hg[t] = -goe; e[t] = 0; }
+            int botg = -goe, botf = 0;   // this lane's bottom row values (last step)
+            int diag0 = -goe;            // Hg(myrow-1, j-1) for row 0
+            int rcur = padc;             // staged residue of this lane's column
+            int rbuf = padc;             // staged residues of columns kb .. kb+63 across lanes
+            int2 bbuf = make_int2(-goe, 0);
+            int pl = -1;                 // this lane's pair index within the stream
+            // lane's best cell in the current pair: first column with its max H
+            int bh = 0, bcol = 0, bk = 0, kflag = 0;
+            auto publish = [&]() __attribute__((always_inline)) {
+                if (pl >= 0 && bh > 0) {
+                    BestCell b{bh, bk - kflag + 1, myrow + (31 - (bcol & 31))};
+                    atomicMax(a.keys + slot0 + pl, cell_key(b, ENDC));
+                }
+            };
+            for (int k8 = 0; k8 < steps8; k8 += 8) {
+                if ((k8 & 63) == 0) {
+                    const int kk = k8 + lane;
+                    rbuf = (kk < C) ? conv((int)sr[kk]) : padc;
+                    if (HB && bin) bbuf = (kk < C) ? bin[kk] : make_int2(-goe, 0);
+                }
 #pragma unroll
-                for (int t = 0; t < R; ++t)
-                    p[t] = (t & 1) ? ((int)qw[t >> 1] >> 16) : (int)(int16_t)(qw[t >> 1] & 0xffffu);
-            } else {
-                const int *prow = pbase + (rcur & 31) * SPAN;
+                for (int u = 0; u < 8; ++u) {
+                    const int k = k8 + u;
+                    const int rl = (k8 & 63) + u;   // wave-uniform
+                    const int rin = __builtin_amdgcn_readlane(rbuf, rl);
+                    rcur = __builtin_amdgcn_update_dpp(rin, rcur, 0x138, 0xf, 0xf, false);
+                    int upg, upf;
+                    if (HB) {
+                        int tg = -goe, tf = 0;
+                        if (bin) {
+                            tg = __builtin_amdgcn_readlane(bbuf.x, rl);
+                            tf = __builtin_amdgcn_readlane(bbuf.y, rl);
+                        }
+                        upg = __builtin_amdgcn_update_dpp(tg, botg, 0x138, 0xf, 0xf, false);
+                        upf = __builtin_amdgcn_update_dpp(tf, botf, 0x138, 0xf, 0xf, false);
+                    } else {
+                        upg = __builtin_amdgcn_update_dpp(-goe, botg, 0x138, 0xf, 0xf, false);
+                        upf = __builtin_amdgcn_mov_dpp(botf, 0x138, 0xf, 0xf, true);   // lane 0: 0
+                    }
+                    if (rcur < 0) {
+                        // leave the previous pair, enter the next one at its column 1
+                        publish();
+                        ++pl;
+                        bh = 0;
+                        bcol = 0;
+                        bk = k;
+                        kflag = k;
 #pragma unroll
-                for (int t = 0; t < R; ++t) p[t] = prow[t];
-            }
-            uint32_t word = 0;
-            int colkey = 0;
+                        for (int t = 0; t < R; ++t) { hg[t] = -goe; e[t] = 0; }
+                        diag0 = -goe;
+                    }
+                    int diag = diag0;
+                    diag0 = upg;
+                    int p[R];
+                    if (P16) {
+                        const uint4 q = reinterpret_cast<const uint4 *>(prof)[((uint32_t)rcur << 6) + lane];
+                        const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-            for (int t = 0; t < R; t += 2) {
-                const int h0 = sw_cell<TB>(hg[t], e[t], diag, upg, upf, p[t], ge, goe, word);
-                if (t + 1 < R) {
-                    const int h1 = sw_cell<TB>(hg[t + 1], e[t + 1], diag, upg, upf, p[t + 1], ge, goe, word);
-                    if (ENDC) colkey = vmax3(colkey, (h0 << 5) | (31 - t), (h1 << 5) | (30 - t));
-                    else hm = vmax3(hm, h0, h1);
-                } else {
-                    if (ENDC) colkey = max(colkey, (h0 << 5) | (31 - t));
-                    else hm = max(hm, h0);
+                        for (int t = 0; t < R; ++t)
+                            p[t] = (t & 1) ? ((int)qw[t >> 1] >> 16) : (int)(int16_t)(qw[t >> 1] & 0xffffu);
+                    } else {
+                        const int *prow = pbase + (rcur & 31) * SPAN;
+#pragma unroll
+                        for (int t = 0; t < R; ++t) p[t] = prow[t];
+                    }
+                    uint32_t word = 0;
+                    int colkey = 0, hm = 0;
+#pragma unroll
+                    for (int t = 0; t < R; t += 2) {
+                        const int h0 = sw_cell<TB>(hg[t], e[t], diag, upg, upf, p[t], ge, goe, word);
+                        if (t + 1 < R) {
+                            const int h1 = sw_cell<TB>(hg[t + 1], e[t + 1], diag, upg, upf, p[t + 1], ge, goe, word);
+                            if (ENDC) colkey = vmax3(colkey, (h0 << 5) | (31 - t), (h1 << 5) | (30 - t));
+                            else hm = vmax3(hm, h0, h1);
+                        } else {
+                            if (ENDC) colkey = max(colkey, (h0 << 5) | (31 - t));
+                            else hm = max(hm, h0);
+                        }
+                    }
+                    botg = upg;
+                    botf = upf;
+                    if (TB) stage[u] = word;
+                    if (HB && bout) {
+                        const int K = k - lane;   // stream column of this lane
+                        if (lane == 63 && K >= 0 && K < C) bout[K] = make_int2(botg, botf);
+                    }
+                    if (ENDC) {
+                        const int ch = colkey >> 5;
+                        const bool up = ch > bh;
+                        bcol = up ? colkey : bcol;
+                        bk = up ? k : bk;
+                        bh = max(bh, ch);
+                    } else {
+                        bh = max(bh, hm);
+                    }
+                }
+                if (TB) {
+                    uint4 *dst = reinterpret_cast<uint4 *>(cw + (int64_t)(k8 >> 3) * 512);
+                    dst[0] = *reinterpret_cast<const uint4 *>(stage);
+                    dst[1] = *reinterpret_cast<const uint4 *>(stage + 4);
                 }
             }
-            botg = upg;
-            botf = upf;
-            if (TB) {
-                stage[k & 7] = word;
-                if ((k & 7) == 7 || k == steps - 1) {
-                    const uint4 lo = *reinterpret_cast<const uint4 *>(stage);
-                    const uint4 hi = *reinterpret_cast<const uint4 *>(stage + 4);
-                    uint4 *dst = reinterpret_cast<uint4 *>(cw + (int64_t)(k >> 3) * 512);
-                    dst[0] = lo;
-                    dst[1] = hi;
-                }
-            }
-            if (bout && lane == 63 && K >= 0 && K < C) bout[K] = make_int2(botg, botf);
-            // columns outside the stream need no test: before it H = 0, and a
-            // best taken after its last column is never published
-            if (ENDC) {
-                const int ch = colkey >> 5;
-                if (ch > best.h) {
-                    best.h = ch;
-                    best.j = jl;
-                    best.i = myrow + (31 - (colkey & 31));
-                }
-            } else {
-                best.h = max(best.h, hm);
-            }
-            hm = 0;
-            // last column of the stream: publish the last pair
-            if (K == C - 1 && pl >= 0 && best.h > 0) atomicMax(a.keys + slot0 + pl, cell_key(best, ENDC));
-        }
+            publish();   // the stream's last pair
+        };
+        if (bin || bout) run(std::true_type{});
+        else run(std::false_type{});
     }
 }
 
@@ -312,7 +342,7 @@ __global__ void decode_keys_kernel(const unsigned long long *keys, const int32_t
 // Stage the residues of every stream: sres[sbase + c0(q) + x] = s_q[x], with
 // kFirstCol on x = 0.  One workgroup per pair slot.
 __global__ void stage_stream_kernel(const uint8_t *res, const int64_t *off, const int32_t *slot_pid,
-                                    const int64_t *slot_col, int nslots, uint8_t *sres) {
+                                    const int64_t *slot_col, int nslots, int clamp, uint8_t *sres) {
     const int q = blockIdx.x;
     if (q >= nslots) return;
     const int pid = slot_pid[q];
@@ -320,7 +350,7 @@ __global__ void stage_stream_kernel(const uint8_t *res, const int64_t *off, cons
     const int n = (int)(off[pid + 1] - so);
     uint8_t *dst = sres + slot_col[q];
     for (int x = threadIdx.x; x < n; x += blockDim.x)
-        dst[x] = (uint8_t)((res[so + x] & 31) | (x == 0 ? kFirstCol : 0));
+        dst[x] = (uint8_t)(min((int)(res[so + x] & 31), clamp) | (x == 0 ? kFirstCol : 0));
 }
 
 // ---------------------------------------------------------------------------
