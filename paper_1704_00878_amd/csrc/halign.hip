@@ -289,6 +289,7 @@ struct Tune {
     int route = -1;   // -1: from flags
     int R = 0;        // 0: fitted to m
     int smul = 1;     // streams per resident wave slot
+    double scale = 1; // stream count scale (a sample keeps the batch's pairs per stream)
 };
 
 int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq,
@@ -405,7 +406,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             nonempty = cn - nonempty;   // empty pairs sort last
             const int wg_per_cu = std::max(1, std::min(4, (int)(ctx->lds_max / lds_stream)));
             const int resident = ctx->num_cu * wg_per_cu * 8 * std::max(1, tune.smul);
-            nstreams = std::max(1, std::min(nonempty, resident));
+            nstreams = std::max(1, std::min(nonempty, (int)std::max(1.0, resident * tune.scale)));
             if (const char *e = getenv("HALIGN_MAX_STREAMS")) {   // test knob: many pairs per stream
                 const int cap_s = atoi(e);
                 if (cap_s > 0) nstreams = std::min(nstreams, cap_s);
@@ -699,24 +700,26 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
         best->smul = it->second[2];
         return HALIGN_OK;
     }
-    // strided sample that keeps the length mix
-    const int ns = std::min(N, 8192);
+    // the batch itself, or a strided sample that keeps the length mix and,
+    // through the stream count, the number of pairs per stream
+    const int ns = std::min(N, 65536);
     std::vector<int32_t> sample(ns);
     for (int q = 0; q < ns; ++q) sample[q] = (int32_t)((int64_t)q * N / ns);
     int R0 = 8, p0 = 1;
     pick_geom(m, &R0, &p0);
+    const double scale = (double)ns / N;
     std::vector<Tune> cands;
-    cands.push_back({kRouteIntra, R0, 1});
-    cands.push_back({kRouteIntra, R0, 2});
-    if (R0 < 8) cands.push_back({kRouteIntra, R0 + 1, 1});
-    cands.push_back({kRouteInter, 0, 1});
-    // scale the sample's stream count like the full batch would fill the chip
+    cands.push_back({kRouteIntra, R0, 1, scale});
+    cands.push_back({kRouteIntra, R0, 2, scale});
+    if (R0 < 8) cands.push_back({kRouteIntra, R0 + 1, 1, scale});
+    cands.push_back({kRouteInter, 0, 1, scale});
+    // the forward kernels are timed in the same traceback mode as the call
     float best_ms = 1e30f;
     *best = cands[0];
     for (const Tune &c : cands) {
         float ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {
-            RCHK(run_batch(ctx, S, center, m, sq, sample, false, endc, c.route, out, st, c));
+            RCHK(run_batch(ctx, S, center, m, sq, sample, tb, endc, c.route, out, st, c));
             HCHK(hipEventSynchronize(ctx->ev[1]));
             HCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
         }
@@ -725,10 +728,10 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
             *best = c;
         }
     }
+    best->scale = 1;
     const std::array<int, 3> v = {best->route, best->R, best->smul};
     ctx->tuned[key] = v;
     tune_save(ctx, key, v);
-    (void)tb;
     return HALIGN_OK;
 }
 

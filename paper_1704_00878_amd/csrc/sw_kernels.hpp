@@ -154,12 +154,12 @@ __device__ __forceinline__ unsigned long long cell_key(const BestCell &b, bool e
 template <int R, bool TB, bool ENDC, bool P16>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
 sw_stream_kernel(StreamArgs a) {
-    extern __shared__ int prof[];   // profile, then code staging [8 waves][64][8]
+    extern __shared__ int prof[];   // profile, then code staging [8 waves][8 steps][64 lanes]
     constexpr int SPAN = 64 * R;
     const int nprow = P16 ? a.alpha + 1 : kAlphaMax;
     const int prof_words = P16 ? nprow * 64 * 4 : kAlphaMax * SPAN;
     uint32_t *stage = reinterpret_cast<uint32_t *>(prof + prof_words) + (threadIdx.x >> 6) * 512 +
-                      (threadIdx.x & 63) * 8;
+                      (threadIdx.x & 63);   // word of step u at stage[64 * u]: no bank conflicts
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int nthreads = blockDim.x;
@@ -296,7 +296,7 @@ sw_stream_kernel(StreamArgs a) {
                     }
                     botg = upg;
                     botf = upf;
-                    if (TB) stage[u] = word;
+                    if (TB) stage[64 * u] = word;
                     if (HB && bout) {
                         const int K = k - lane;   // stream column of this lane
                         if (lane == 63 && K >= 0 && K < C) bout[K] = make_int2(botg, botf);
@@ -313,8 +313,8 @@ sw_stream_kernel(StreamArgs a) {
                 }
                 if (TB) {
                     uint4 *dst = reinterpret_cast<uint4 *>(cw + (int64_t)(k8 >> 3) * 512);
-                    dst[0] = *reinterpret_cast<const uint4 *>(stage);
-                    dst[1] = *reinterpret_cast<const uint4 *>(stage + 4);
+                    dst[0] = make_uint4(stage[0], stage[64], stage[128], stage[192]);
+                    dst[1] = make_uint4(stage[256], stage[320], stage[384], stage[448]);
                 }
             }
             publish();   // the stream's last pair
