@@ -79,6 +79,29 @@ def cpu_baseline(seqs, center: int, budget_s: float = 20.0):
                       f"({cells:.3e} cells, {dt:.1f} s, one thread per core)"}
 
 
+def counter_record(kernel: str, workload: str):
+    """HBM counters of the forward kernel taken with rocprofv3 --pmc on this
+    workload, from the profiles/ summaries; None unless they were taken on the
+    kernel source as it is now (sha256 of csrc/sw_kernels.hpp)."""
+    import glob
+    import hashlib
+    import re
+    src = os.path.join(ROOT, "paper_1704_00878_amd", "csrc", "sw_kernels.hpp")
+    try:
+        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    except OSError:
+        return None
+    for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        for m in re.finditer(r"<!-- record (\{.*?\}) -->", open(path).read()):
+            try:
+                rec = json.loads(m.group(1))
+            except ValueError:
+                continue
+            if rec.get("kernel") == kernel and rec.get("workload") == workload and rec.get("source_sha256") == sha:
+                return rec
+    return None
+
+
 def learned_report(H, ctx, sc, workload: str, anchors: int, epochs: int):
     """Learned center on a family set: the exhaustive center (all pairs,
     score-only) against the trained proposer's judged top-16, with the MSA of
@@ -271,11 +294,19 @@ def main():
 
     # dominant kernel roofline: integer VALU, fixed op model
     achieved = cells * OPS_PER_CELL_TB / (fwd_ms * 1e-3) / 1e12
+    kname = "sw_stream_kernel" if st["route"] == 0 else "sw_inter_kernel"
+    rec = counter_record(kname, args.workload)
+    traffic = clock = None
+    if rec is not None:
+        traffic = int(rec["fetch_kib"] * 1024 * rec["fetch_factor"] + rec["write_kib"] * 1024 * rec["write_factor"])
+        clock = rec["clock_ghz"]
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(PEAK_INT32_TOPS, 2),
-            "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": None,
-            "kernel": "sw_intra_kernel" if st["route"] == 0 else "sw_inter_kernel",
-            "ops_per_cell": OPS_PER_CELL_TB, "kernel_ms": round(fwd_ms, 4),
-            "kernel_gcups": round(cells / (fwd_ms * 1e-3) / 1e9, 1)}
+            "unit": "TOP/s", "frac": round(achieved / PEAK_INT32_TOPS, 4), "traffic": traffic,
+            "kernel": kname, "ops_per_cell": OPS_PER_CELL_TB, "kernel_ms": round(fwd_ms, 4),
+            "kernel_gcups": round(cells / (fwd_ms * 1e-3) / 1e9, 1),
+            "measured_clock_ghz": clock,
+            "frac_at_measured_clock": round(achieved / (PEAK_INT32_TOPS * clock / 2.4), 4) if clock else None,
+            "algorithmic_bytes": int(cells // 2 + seqs.residues.size)}
 
     # avg SP of the produced MSA (evaluation, untimed)
     sp, spb = H.halign_sp_score(sc, msa)

@@ -92,6 +92,7 @@ struct halign_ctx {
     } gent;
     int64_t graph_launches = 0;
     int autotune = 0;         // 1: tune route / rows per lane / stream count per bucket
+    int progress = 0;         // 1: a line on stderr after each chunk of a chunked batch
     std::array<int, 3> last_tune = {-1, 0, 1};
     std::map<std::string, std::array<int, 3>> tuned;   // bucket -> {route, R, stream multiplier}
     std::string tune_file;    // optional cache file (HALIGN_TUNE_CACHE)
@@ -642,6 +643,9 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             HCHK(hipEventElapsedTime(&w2, ctx->ev[1], ctx->ev[2]));
             fwd_ms += f;
             walk_ms += w2;
+            if (ctx->progress)
+                fprintf(stderr, "halign: chunk %d/%d done (%d pairs, forward %.1f ms, walk %.1f ms)\n", (int)ci + 1,
+                        (int)chunks.size(), cn, f, w2), fflush(stderr);
         }
     }
     ctx->last_stats[1] = launches;
@@ -833,6 +837,7 @@ int halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out) 
         if (hipMemGetInfo(&fr, &tot) == hipSuccess && fr > 0) ctx->cap = fr / 4;
     }
     if (const char *e = getenv("HALIGN_AUTOTUNE")) ctx->autotune = atoi(e) != 0;
+    if (const char *e = getenv("HALIGN_PROGRESS")) ctx->progress = atoi(e) != 0;
     if (const char *e = getenv("HALIGN_TUNE_CACHE")) ctx->tune_file = e;
     tune_load(ctx);
     hipDeviceProp_t prop;
