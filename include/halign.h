@@ -113,14 +113,15 @@ int  halign_ctx_last_stats(const halign_ctx *ctx, int64_t *stats_host /*[4]: cel
 /* Autotuning of halign_sw_batch plans (off by default; also enabled by the
  * environment variable HALIGN_AUTOTUNE=1).  When on, the first call for a
  * bucket of (center length, batch size, mean length, traceback) times the
- * candidate plans -- wavefront kernel with R or R+1 center rows per lane,
- * one or two streams per resident wave, or the one-pair-per-lane kernel -- on
+ * candidate plans -- wavefront streams of 64 lanes with R or R+1 center rows
+ * per lane and one or two streams per resident wave slot, streams of 32 or 16
+ * lanes with up to 16 rows per lane, or the one-pair-per-lane kernel -- on
  * the batch (a strided sample of 65,536 pairs for larger batches, with the
  * stream count scaled to keep the pairs per stream) in the call's own mode,
  * and keeps the fastest; results do not depend on the plan.
  * HALIGN_TUNE_CACHE=<path> persists choices (malformed lines are ignored).
- * halign_ctx_last_plan reports {route, R, streams multiplier} of the last
- * call (route -1 / R 0: defaults).  HALIGN_PROGRESS=1 prints one line on
+ * halign_ctx_last_plan reports {route, R, streams multiplier, lanes per
+ * stream} of the last call (route -1 / R 0: defaults).  HALIGN_PROGRESS=1 prints one line on
  * stderr as each chunk of a chunked batch completes. */
 int  halign_ctx_set_autotune(halign_ctx *ctx, int enable);
 /* halign_msa runs its pairwise batch with HALIGN_GRAPH when enabled (the
@@ -128,7 +129,7 @@ int  halign_ctx_set_autotune(halign_ctx *ctx, int enable);
  * replays. */
 int  halign_ctx_set_graph(halign_ctx *ctx, int enable);
 int  halign_ctx_graph_launches(const halign_ctx *ctx, int64_t *n_host);
-int  halign_ctx_last_plan(const halign_ctx *ctx, int32_t *plan_host /*[3]*/);
+int  halign_ctx_last_plan(const halign_ctx *ctx, int32_t *plan_host /*[4]*/);
 
 /* ---- step a1: encode ASCII to residue codes (upper/lower case; U->C,
  * O->K, other letters -> X).  ascii and codes may alias. */

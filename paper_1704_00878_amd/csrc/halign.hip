@@ -93,8 +93,8 @@ struct halign_ctx {
     int64_t graph_launches = 0;
     int autotune = 0;         // 1: tune route / rows per lane / stream count per bucket
     int progress = 0;         // 1: a line on stderr after each chunk of a chunked batch
-    std::array<int, 3> last_tune = {-1, 0, 1};
-    std::map<std::string, std::array<int, 3>> tuned;   // bucket -> {route, R, stream multiplier}
+    std::array<int, 4> last_tune = {-1, 0, 1, 64};
+    std::map<std::string, std::array<int, 4>> tuned;   // bucket -> {route, R, stream multiplier, lanes per stream}
     std::string tune_file;    // optional cache file (HALIGN_TUNE_CACHE)
     int *flag_host = nullptr; // pinned: largest residue code of the last validated call
     int flag_alpha = 0;       // alphabet that value is checked against (0 = nothing pending)
@@ -237,33 +237,58 @@ void pick_geom(int m, int *R, int *passes) {
     *R = std::max(1, std::min(8, (m + 64 * p - 1) / (64 * p)));
 }
 
-template <int R, bool P16>
-void launch_stream_RP(const hk::StreamArgs &a, bool tb, bool endc, int grid, size_t lds, hipStream_t st) {
+template <int R, int LS, bool P16>
+void launch_stream_RLP(const hk::StreamArgs &a, bool tb, bool endc, int grid, size_t lds, hipStream_t st) {
     if (tb)
-        hipLaunchKernelGGL((hk::sw_stream_kernel<R, true, true, P16>), dim3(grid), dim3(512), lds, st, a);
+        hipLaunchKernelGGL((hk::sw_stream_kernel<R, LS, true, true, P16>), dim3(grid), dim3(512), lds, st, a);
     else if (endc)
-        hipLaunchKernelGGL((hk::sw_stream_kernel<R, false, true, P16>), dim3(grid), dim3(512), lds, st, a);
+        hipLaunchKernelGGL((hk::sw_stream_kernel<R, LS, false, true, P16>), dim3(grid), dim3(512), lds, st, a);
     else
-        hipLaunchKernelGGL((hk::sw_stream_kernel<R, false, false, P16>), dim3(grid), dim3(512), lds, st, a);
+        hipLaunchKernelGGL((hk::sw_stream_kernel<R, LS, false, false, P16>), dim3(grid), dim3(512), lds, st, a);
+}
+
+// instantiated geometries: 64-lane streams with R = 1..8 (int16 or int32
+// profile); 32- and 16-lane streams with R = 2..16 (int16 profile)
+bool stream_supported(int R, int LS, bool p16) {
+    if (LS == 64) return R >= 1 && R <= 8;
+    return (LS == 32 || LS == 16) && p16 && R >= 2 && R <= 16;
 }
 
 template <int R>
-void launch_stream_R(const hk::StreamArgs &a, bool tb, bool endc, bool p16, int grid, size_t lds, hipStream_t st) {
-    if (p16) launch_stream_RP<R, true>(a, tb, endc, grid, lds, st);
-    else launch_stream_RP<R, false>(a, tb, endc, grid, lds, st);
+void launch_stream_R(int LS, const hk::StreamArgs &a, bool tb, bool endc, bool p16, int grid, size_t lds,
+                     hipStream_t st) {
+    if constexpr (R <= 8) {
+        if (LS == 64) {
+            if (p16) launch_stream_RLP<R, 64, true>(a, tb, endc, grid, lds, st);
+            else launch_stream_RLP<R, 64, false>(a, tb, endc, grid, lds, st);
+            return;
+        }
+    }
+    if constexpr (R >= 2) {
+        if (LS == 32) launch_stream_RLP<R, 32, true>(a, tb, endc, grid, lds, st);
+        else launch_stream_RLP<R, 16, true>(a, tb, endc, grid, lds, st);
+    }
 }
 
-void launch_stream(int R, const hk::StreamArgs &a, bool tb, bool endc, bool p16, int grid, size_t lds,
+void launch_stream(int R, int LS, const hk::StreamArgs &a, bool tb, bool endc, bool p16, int grid, size_t lds,
                    hipStream_t st) {
     switch (R) {
-        case 1: launch_stream_R<1>(a, tb, endc, p16, grid, lds, st); break;
-        case 2: launch_stream_R<2>(a, tb, endc, p16, grid, lds, st); break;
-        case 3: launch_stream_R<3>(a, tb, endc, p16, grid, lds, st); break;
-        case 4: launch_stream_R<4>(a, tb, endc, p16, grid, lds, st); break;
-        case 5: launch_stream_R<5>(a, tb, endc, p16, grid, lds, st); break;
-        case 6: launch_stream_R<6>(a, tb, endc, p16, grid, lds, st); break;
-        case 7: launch_stream_R<7>(a, tb, endc, p16, grid, lds, st); break;
-        default: launch_stream_R<8>(a, tb, endc, p16, grid, lds, st); break;
+        case 1: launch_stream_R<1>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 2: launch_stream_R<2>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 3: launch_stream_R<3>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 4: launch_stream_R<4>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 5: launch_stream_R<5>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 6: launch_stream_R<6>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 7: launch_stream_R<7>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 8: launch_stream_R<8>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 9: launch_stream_R<9>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 10: launch_stream_R<10>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 11: launch_stream_R<11>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 12: launch_stream_R<12>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 13: launch_stream_R<13>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 14: launch_stream_R<14>(LS, a, tb, endc, p16, grid, lds, st); break;
+        case 15: launch_stream_R<15>(LS, a, tb, endc, p16, grid, lds, st); break;
+        default: launch_stream_R<16>(LS, a, tb, endc, p16, grid, lds, st); break;
     }
 }
 
@@ -291,6 +316,7 @@ struct Tune {
     int R = 0;        // 0: fitted to m
     int smul = 1;     // streams per resident wave slot
     double scale = 1; // stream count scale (a sample keeps the batch's pairs per stream)
+    int LS = 0;       // lanes per stream (0: 64)
 };
 
 int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq,
@@ -324,13 +350,6 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         }
     }
     const int aw = (m + 31) / 32;
-    int R = 8, passes = 1;
-    pick_geom(m, &R, &passes);
-    if (tune.route >= 0) route = tune.route;
-    if (tune.R > 0 && tune.R <= 8) {
-        R = tune.R;
-        passes = std::max(1, (m + 64 * R - 1) / (64 * R));
-    }
     // int16 profile when every score and profile entry fits in 16 bits:
     // max score <= max(S) * min(m, longest sequence)
     int smax = 1;
@@ -338,16 +357,36 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
     const int nlong = plen[0];
     const bool p16 = (int64_t)smax * std::min(m, nlong) <= 32000 && S.goe + 128 <= 32000 &&
                      !getenv("HALIGN_PROFILE32");
-    const size_t prof_bytes = p16 ? (size_t)(S.alpha + 1) * 64 * 8 * 2 : (size_t)hk::kAlphaMax * 64 * R * 4;
-    const size_t lds_stream = prof_bytes + (tb ? 8 * 64 * 8 * 4 : 0);
+    int R = 8, passes = 1, LS = 64;
+    pick_geom(m, &R, &passes);
+    if (tune.route >= 0) route = tune.route;
+    if (tune.R > 0 && stream_supported(tune.R, tune.LS > 0 ? tune.LS : 64, p16)) {
+        LS = tune.LS > 0 ? tune.LS : 64;
+        R = tune.R;
+        passes = std::max(1, (m + LS * R - 1) / (LS * R));
+    } else if (const char *e = getenv("HALIGN_STREAM_LANES")) {   // test knob: narrower streams
+        const int ls = atoi(e);
+        const int ps = std::max(1, (m + ls * 16 - 1) / std::max(1, ls * 16));
+        const int r = std::max(2, (m + ls * ps - 1) / std::max(1, ls * ps));
+        if ((ls == 32 || ls == 16) && stream_supported(r, ls, p16)) {
+            LS = ls;
+            R = r;
+            passes = ps;
+        }
+    }
+    const int W = (R + 7) / 8, NS = 64 / LS;
+    const size_t prof_bytes =
+        p16 ? (size_t)(S.alpha + 1) * LS * 16 * W : (size_t)hk::kAlphaMax * LS * R * 4;
+    const size_t lds_stream = prof_bytes + (tb ? (size_t)8 * 512 * 4 * W : 0);
     if (route == kRouteIntra && lds_stream > ctx->lds_max) route = kRouteInter;
     ctx->last_stats[2] = route;
 
     // chunk the pairs so that codes + boundary rows fit the cap
     const size_t cap = ctx->cap ? ctx->cap : (size_t)1 << 62;
     std::vector<std::pair<int, int>> chunks;  // [lo, hi) in pids
-    const size_t intra_bytes = (tb ? (size_t)passes * 64 * 4 * ((size_t)sum_len + 8 * (size_t)np) : 0) +
-                               (size_t)(passes - 1) * 8 * (size_t)sum_len;
+    const size_t intra_bytes =
+        (tb ? (size_t)passes * LS * 4 * W * ((size_t)sum_len + (size_t)(LS + 8) * (size_t)np) : 0) +
+        (size_t)(passes - 1) * 8 * (size_t)sum_len;
     if (route == kRouteIntra && intra_bytes <= cap) {
         chunks.push_back({0, np});
     } else {
@@ -359,7 +398,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             size_t b = 0;
             bool boundary = true;
             if (route == kRouteIntra) {
-                b = (tb ? (size_t)passes * (n + 8) * 64 * 4 : 0) + (size_t)(passes - 1) * n * 8;
+                b = (tb ? (size_t)passes * (n + LS + 8) * LS * 4 * W : 0) + (size_t)(passes - 1) * n * 8;
             } else {
                 boundary = (x - lo) % 64 == 0;
                 b = (boundary && tb) ? (size_t)nst * ((n + 3) / 4) * 512 * 4 : 0;  // group charged by its longest
@@ -406,7 +445,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             for (int x = hi - 1; x >= lo && plen[x] == 0; --x) ++nonempty;
             nonempty = cn - nonempty;   // empty pairs sort last
             const int wg_per_cu = std::max(1, std::min(4, (int)(ctx->lds_max / lds_stream)));
-            const int resident = ctx->num_cu * wg_per_cu * 8 * std::max(1, tune.smul);
+            const int resident = ctx->num_cu * wg_per_cu * 8 * NS * std::max(1, tune.smul);
             nstreams = std::max(1, std::min(nonempty, (int)std::max(1.0, resident * tune.scale)));
             if (const char *e = getenv("HALIGN_MAX_STREAMS")) {   // test knob: many pairs per stream
                 const int cap_s = atoi(e);
@@ -463,7 +502,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                 col += scols[s];
                 h_scb[s] = (int64_t)code_words;
                 h_sbb[s] = (int64_t)bound_elems;
-                if (tb) code_words += (size_t)passes * ((scols[s] + 63 + 7) / 8) * 512;
+                if (tb) code_words += (size_t)passes * ((scols[s] + LS - 1 + 7) / 8) * LS * 8 * W;
                 if (passes > 1) bound_elems += (size_t)(passes - 1) * scols[s];
             }
             h_sbeg[nstreams] = col;
@@ -550,7 +589,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             a.scbase = (const int64_t *)(dplan + o_scb);
             a.bound = (int2 *)ctx->bound.p;
             a.sbbase = (const int64_t *)(dplan + o_sbb);
-            launch_stream(R, a, tb, endc, p16, (nstreams + 7) / 8, lds_stream, st);
+            launch_stream(R, LS, a, tb, endc, p16, ((nstreams + NS - 1) / NS + 7) / 8, lds_stream, st);
             HCHK(hipGetLastError());
             RCHK(record(ctx, ctx->ev[1], st));
             hipLaunchKernelGGL(hk::decode_keys_kernel, dim3(grid_for(nslots, 256, 1 << 30)), dim3(256), 0, st,
@@ -617,6 +656,8 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             w.cstride = strip_plan ? (const int32_t *)(dplan + o_cstr) : nullptr;
             w.ccol = strip_plan ? (const int32_t *)(dplan + o_ccol) : nullptr;
             w.R = R;
+            w.lg_ls = LS == 64 ? 6 : (LS == 32 ? 5 : 4);
+            w.W = W;
             w.kind = route == kRouteIntra ? 0 : 1;
             w.cells = out.cells;
             w.ins = out.ins;
@@ -679,17 +720,18 @@ void tune_load(halign_ctx *ctx) {
     while (std::getline(f, line)) {
         std::istringstream s(line);
         std::string key;
-        int r = -1, R = -1, sm = -1;
+        int r = -1, R = -1, sm = -1, ls = 64;
         if (!(s >> key >> r >> R >> sm)) continue;              // malformed: ignored
-        if (r < 0 || r > 1 || R < 0 || R > 8 || sm < 1 || sm > 4) continue;
-        ctx->tuned[key] = {r, R, sm};
+        if (!(s >> ls)) ls = 64;                                // lines without the lane count
+        if (r < 0 || r > 1 || R < 0 || R > 16 || sm < 1 || sm > 4 || (ls != 64 && ls != 32 && ls != 16)) continue;
+        ctx->tuned[key] = {r, R, sm, ls};
     }
 }
 
-void tune_save(halign_ctx *ctx, const std::string &key, const std::array<int, 3> &v) {
+void tune_save(halign_ctx *ctx, const std::string &key, const std::array<int, 4> &v) {
     if (ctx->tune_file.empty()) return;
     std::ofstream f(ctx->tune_file, std::ios::app);
-    if (f) f << key << " " << v[0] << " " << v[1] << " " << v[2] << "\n";
+    if (f) f << key << " " << v[0] << " " << v[1] << " " << v[2] << " " << v[3] << "\n";
 }
 
 int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq, bool tb,
@@ -702,6 +744,7 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
         best->route = it->second[0];
         best->R = it->second[1];
         best->smul = it->second[2];
+        best->LS = it->second[3];
         return HALIGN_OK;
     }
     // the batch itself, or a strided sample that keeps the length mix and,
@@ -713,10 +756,17 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
     pick_geom(m, &R0, &p0);
     const double scale = (double)ns / N;
     std::vector<Tune> cands;
-    cands.push_back({kRouteIntra, R0, 1, scale});
-    cands.push_back({kRouteIntra, R0, 2, scale});
-    if (R0 < 8) cands.push_back({kRouteIntra, R0 + 1, 1, scale});
-    cands.push_back({kRouteInter, 0, 1, scale});
+    cands.push_back({kRouteIntra, R0, 1, scale, 64});
+    cands.push_back({kRouteIntra, R0, 2, scale, 64});
+    if (R0 < 8) cands.push_back({kRouteIntra, R0 + 1, 1, scale, 64});
+    // narrower streams: fewer fill/drain steps, more rows per lane (int16 profile only;
+    // run_batch falls back to 64 lanes otherwise)
+    for (int ls : {32, 16}) {
+        const int ps = std::max(1, (m + ls * 16 - 1) / (ls * 16));
+        const int r = std::max(2, (m + ls * ps - 1) / (ls * ps));
+        cands.push_back({kRouteIntra, r, 1, scale, ls});
+    }
+    cands.push_back({kRouteInter, 0, 1, scale, 64});
     // the forward kernels are timed in the same traceback mode as the call
     float best_ms = 1e30f;
     *best = cands[0];
@@ -733,7 +783,7 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
         }
     }
     best->scale = 1;
-    const std::array<int, 3> v = {best->route, best->R, best->smul};
+    const std::array<int, 4> v = {best->route, best->R, best->smul, best->LS > 0 ? best->LS : 64};
     ctx->tuned[key] = v;
     tune_save(ctx, key, v);
     return HALIGN_OK;
@@ -928,7 +978,7 @@ int halign_ctx_set_autotune(halign_ctx *ctx, int enable) {
 
 int halign_ctx_last_plan(const halign_ctx *ctx, int32_t *plan_host) {
     if (!ctx || !plan_host) return fail(HALIGN_E_INVALID, "NULL argument");
-    for (int i = 0; i < 3; ++i) plan_host[i] = ctx->last_tune[i];
+    for (int i = 0; i < 4; ++i) plan_host[i] = ctx->last_tune[i];
     return HALIGN_OK;
 }
 
@@ -1023,7 +1073,7 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
         out.gskip = gskip;
     }
     RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st, tune, prep));
-    ctx->last_tune = {tune.route, tune.R, tune.smul};
+    ctx->last_tune = {tune.route, tune.R, tune.smul, tune.LS > 0 ? tune.LS : 64};
     if (!tb && cells) {
         // score-only with cells: report the end cell as (0, 0, i1, j1)
         hipLaunchKernelGGL(hk::endcell_to_cells_kernel, dim3(grid_for(N, 256)), dim3(256), 0, st,

@@ -84,34 +84,39 @@ __device__ __forceinline__ bool better(int h, int j, int i, const BestCell &b) {
 }
 
 // ---------------------------------------------------------------------------
-// Intra-task (wavefront) kernel: each wavefront streams a list of pairs.
-// Lane l owns center rows [row0 + l*R, row0 + l*R + R) of a pass of 64*R rows
-// and works on stream column K = k - l at step k (a skewed wavefront).  The
-// columns of the stream are the concatenated sequences of its pairs; a pair's
-// first column carries a flag (bit 7 of the staged residue) at which each
+// Intra-task (wavefront) kernel: each stream of LS lanes (LS = 64, 32 or 16,
+// so a wavefront runs 64/LS streams side by side) works through a list of
+// pairs.  Lane l of a stream owns center rows [row0 + l*R, row0 + l*R + R)
+// of a pass of LS*R rows and works on stream column K = k - l at step k (a
+// skewed wavefront).  The columns of the stream are the concatenated
+// sequences of its pairs; a pair's first column carries a flag at which each
 // lane resets its row state to the column-0 boundary, so consecutive pairs
-// overlap in the pipeline and only the stream pays the 63-step fill/drain.
+// overlap in the pipeline and only the stream pays the LS-1 step fill/drain.
 // The bottom row of lane l-1 (Hg, F*) and the residue stream reach lane l
-// through DPP wave_shr:1.  Passes over m > 64*R run one after the other for
-// the whole workgroup; the boundary row between passes goes through global
-// scratch per stream.
+// through DPP wave_shr:1; the first lane of each stream takes its inputs by
+// readlane / writelane instead.  Passes over m > LS*R run one after the other
+// for the whole workgroup; the boundary row between passes goes through
+// global scratch per stream.
 //
-// Profile: P[r][t] = S[c_{row0+t}][r] + goe (int32, 32 x 64R) for the current
-// pass, in LDS, shared by the 8 waves of the workgroup.
+// Profile: int16 [alpha+1][LS lanes][8*W] (W = ceil(R/8); row alpha is the
+// padding row) when every score and S + goe fit in 16 bits (P16), one or two
+// 16-byte LDS reads per step (the streams of a wavefront read the same
+// entries); otherwise int32 [32][LS*R] (LS = 64 only).
 //
 // End cell: when a lane leaves a pair it publishes its best cell as a 64-bit
 // key (H << 32 | (0xffff - j) << 16 | (0xffff - i)) with atomicMax, so the
 // pair's maximum over lanes and passes is max H, then min j, then min i,
 // independent of the order of the atomics.
 //
-// Codes: one u32 word (R nibbles, row t at bit 4*(R-1-t)) per (pass, step k,
-// lane), tiled so that a lane's 8 consecutive steps share 32 bytes: with
-// G = ceil((C+63)/8) groups per pass,
-//   codes[sbase + ((pass*G + k/8)*64 + lane)*8 + k%8].
-// Each lane stages its words in LDS and stores 32 B every 8 steps (2 KB per
-// wave per store, coalesced); the walk then finds a diagonal run of up to 8
-// steps in one line.  For a pair starting at stream column c0, cell (i, j)
-// is at step k = c0 + j - 1 + lane(i).
+// Codes: W u32 words per (pass, step k, lane); word q holds rows 8q.. of the
+// lane, row t at bit 4*(n_q - 1 - (t - 8q)) with n_q rows in word q.  They
+// are tiled so that a lane's 8 consecutive steps share 32*W bytes: with
+// G = ceil((C + LS - 1)/8) groups per pass,
+//   codes[sbase + ((pass*G + k/8)*LS + l)*8W + (k%8)*W + q].
+// Each lane stages its words in LDS and stores 32*W bytes every 8 steps
+// (coalesced); the walk then finds a diagonal run of up to 8 steps in one
+// line.  For a pair starting at stream column c0, cell (i, j) is at step
+// k = c0 + j - 1 + lane(i).
 // ---------------------------------------------------------------------------
 constexpr uint8_t kFirstCol = 0x80;
 
@@ -138,52 +143,61 @@ __device__ __forceinline__ unsigned long long cell_key(const BestCell &b, bool e
     return k;
 }
 
-// P16: the profile is int16 [alpha+1][64 lanes][8] (row alpha = padding), one
-// 16-byte LDS read per step, values folded into the add as sign-extended
-// halves; valid when every score and S + goe fit in 16 bits (checked by the
-// host).  Otherwise int32 [32][64R].
-// The step loop is unrolled by 8: a lane's 8 code words of a tile are staged
-// in LDS and go out as two 16-byte stores, and the loop runs over whole
-// tiles (steps rounded up to a multiple of 8; the extra steps see padding
-// columns).  A lane keeps, for the current pair, its max H, the step of the
-// first column that reached it and that column's key (smallest row), which
-// is the max-H / min-j / min-i rule restricted to its rows.  The last pair
-// of a stream is published after the loop: padding columns after a stream
-// never raise H above the stream's maximum (E and F only decay there).  The
-// loop is compiled twice: with and without boundary rows between passes.
-template <int R, bool TB, bool ENDC, bool P16>
-__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(6)))
+// The step loop is unrolled by 8: a lane's 8 steps of code words are staged
+// in LDS and go out as one 32*W-byte tile, and the loop runs over whole tiles
+// (steps rounded up to a multiple of 8, to the longest stream of the
+// wavefront; the extra steps see padding columns).  A lane keeps, for the
+// current pair, its max H, the step of the first column that reached it and
+// that column's key (smallest row), which is the max-H / min-j / min-i rule
+// restricted to its rows.  A stream's last pair is published after the loop:
+// padding columns after a stream never raise H above the stream's maximum (E
+// and F only decay there).  The loop is compiled twice: with and without
+// boundary rows between passes.
+template <int R, int LS, bool TB, bool ENDC, bool P16>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(R > 6 ? 4 : 6)))
 sw_stream_kernel(StreamArgs a) {
-    extern __shared__ int prof[];   // profile, then code staging [8 waves][8 steps][64 lanes]
-    constexpr int SPAN = 64 * R;
+    static_assert(LS == 64 || LS == 32 || LS == 16, "lanes per stream");
+    static_assert(P16 || LS == 64, "the int32 profile serves 64-lane streams only");
+    constexpr int W = (R + 7) / 8;           // code words per step
+    constexpr int NS = 64 / LS;              // streams per wavefront
+    constexpr int SPAN = LS * R;             // rows per pass
+    extern __shared__ int prof[];   // profile, then code staging [8 waves][8 steps][W][64 lanes]
     const int nprow = P16 ? a.alpha + 1 : kAlphaMax;
-    const int prof_words = P16 ? nprow * 64 * 4 : kAlphaMax * SPAN;
-    uint32_t *stage = reinterpret_cast<uint32_t *>(prof + prof_words) + (threadIdx.x >> 6) * 512 +
-                      (threadIdx.x & 63);   // word of step u at stage[64 * u]: no bank conflicts
+    const int prof_words = P16 ? nprow * LS * 4 * W : kAlphaMax * SPAN;
+    uint32_t *stage = reinterpret_cast<uint32_t *>(prof + prof_words) + (threadIdx.x >> 6) * 512 * W +
+                      (threadIdx.x & 63);   // word (u, q) at stage[64 * (u*W + q)]: no bank conflicts
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    const int ll = lane & (LS - 1);          // lane within its stream
     const int nthreads = blockDim.x;
     const int ge = a.ge, goe = a.goe;
-    // the wave index is the same in all 64 lanes; readfirstlane makes that visible
-    const int sid = __builtin_amdgcn_readfirstlane(blockIdx.x * (nthreads >> 6) + (tid >> 6));
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (nthreads >> 6) + (tid >> 6));
+    const int sid = wave * NS + lane / LS;   // this lane's stream
     const bool active = sid < a.nstreams;
     int64_t b0 = 0;
     int C = 0, slot0 = 0;
     if (active) {
         b0 = a.sbeg[sid];
-        C = __builtin_amdgcn_readfirstlane((int)(a.sbeg[sid + 1] - b0));  // same in every lane
-        slot0 = __builtin_amdgcn_readfirstlane(a.sslot0[sid]);
+        C = (int)(a.sbeg[sid + 1] - b0);
+        slot0 = a.sslot0[sid];
     }
+    // the wavefront runs to its longest stream
+    int Cmax = C;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Cmax = max(Cmax, __builtin_amdgcn_readlane(C, s * LS));
+    Cmax = __builtin_amdgcn_readfirstlane(Cmax);
     const uint8_t *sr = a.sres + b0;
-    const int steps = C + 63;
-    const int steps8 = (steps + 7) & ~7;
+    const int steps_s = C + LS - 1;                  // this stream's steps
+    const int steps8 = (Cmax + LS - 1 + 7) & ~7;     // the wavefront's steps (whole tiles)
+    const int G = (steps_s + 7) >> 3;                // this stream's tiles per pass
     for (int pass = 0; pass < a.passes; ++pass) {
         const int row0 = pass * SPAN;
         __syncthreads();
         if (P16) {
             int16_t *p16 = reinterpret_cast<int16_t *>(prof);
-            for (int x = tid; x < nprow * 512; x += nthreads) {
-                const int r = x >> 9, l = (x >> 3) & 63, tt = x & 7;
+            constexpr int PER = 8 * W;               // halves per (residue, lane)
+            for (int x = tid; x < nprow * LS * PER; x += nthreads) {
+                const int r = x / (LS * PER), l = (x / PER) & (LS - 1), tt = x % PER;
                 const int i = row0 + l * R + tt;
                 int v = -32768;
                 if (r < a.alpha && tt < R && i < a.m) v = (int)a.mat[(a.center[i] & 31) * a.alpha + r] + goe;
@@ -198,13 +212,12 @@ sw_stream_kernel(StreamArgs a) {
             }
         }
         __syncthreads();
-        if (!active) continue;
-        const int myrow = row0 + lane * R;
-        const int *pbase = prof + lane * R;
-        const int2 *bin = (pass > 0) ? a.bound + a.sbbase[sid] + (int64_t)(pass - 1) * C : nullptr;
-        int2 *bout = (pass + 1 < a.passes) ? a.bound + a.sbbase[sid] + (int64_t)pass * C : nullptr;
-        const int G = (steps + 7) >> 3;
-        uint32_t *cw = TB ? a.codes + a.scbase[sid] + (int64_t)pass * G * 512 + lane * 8 : nullptr;
+        if (wave * NS >= a.nstreams) continue;   // no stream of this wavefront is active
+        const int myrow = row0 + ll * R;
+        const int *pbase = prof + ll * R;
+        const int2 *bin = (pass > 0 && active) ? a.bound + a.sbbase[sid] + (int64_t)(pass - 1) * C : nullptr;
+        int2 *bout = (pass + 1 < a.passes && active) ? a.bound + a.sbbase[sid] + (int64_t)pass * C : nullptr;
+        uint32_t *cw = (TB && active) ? a.codes + a.scbase[sid] + (int64_t)pass * G * LS * 8 * W + ll * 8 * W : nullptr;
         // staged residue codes are already clamped to the profile rows; the
         // first-column flag moves to bit 31 (so the profile index shifts it out)
         const int padc = P16 ? a.alpha : kPad;
@@ -218,29 +231,34 @@ sw_stream_kernel(StreamArgs a) {
             int botg = -goe, botf = 0;   // this lane's bottom row values (last step)
             int diag0 = -goe;            // Hg(myrow-1, j-1) for row 0
             int rcur = padc;             // staged residue of this lane's column
-            int rbuf = padc;             // staged residues of columns kb .. kb+63 across lanes
+            int rbuf = padc;             // staged residues of columns kb .. kb+LS-1 of the stream
             int2 bbuf = make_int2(-goe, 0);
             int pl = -1;                 // this lane's pair index within the stream
             // lane's best cell in the current pair: first column with its max H
             int bh = 0, bcol = 0, bk = 0, kflag = 0;
             auto publish = [&]() __attribute__((always_inline)) {
-                if (pl >= 0 && bh > 0) {
+                if (active && pl >= 0 && bh > 0) {
                     BestCell b{bh, bk - kflag + 1, myrow + (31 - (bcol & 31))};
                     atomicMax(a.keys + slot0 + pl, cell_key(b, ENDC));
                 }
             };
             for (int k8 = 0; k8 < steps8; k8 += 8) {
-                if ((k8 & 63) == 0) {
-                    const int kk = k8 + lane;
+                if ((k8 & (LS - 1)) == 0) {
+                    const int kk = k8 + ll;
                     rbuf = (kk < C) ? conv((int)sr[kk]) : padc;
                     if (HB && bin) bbuf = (kk < C) ? bin[kk] : make_int2(-goe, 0);
                 }
 #pragma unroll
                 for (int u = 0; u < 8; ++u) {
                     const int k = k8 + u;
-                    const int rl = (k8 & 63) + u;   // wave-uniform
-                    const int rin = __builtin_amdgcn_readlane(rbuf, rl);
-                    rcur = __builtin_amdgcn_update_dpp(rin, rcur, 0x138, 0xf, 0xf, false);
+                    const int rl = (k8 & (LS - 1)) + u;   // wave-uniform
+                    rcur = __builtin_amdgcn_update_dpp(__builtin_amdgcn_readlane(rbuf, rl), rcur, 0x138, 0xf, 0xf,
+                                                       false);
+#pragma unroll
+                    for (int s = 1; s < NS; ++s) {   // the first lane of stream s takes its column directly
+                        const int rs = __builtin_amdgcn_readlane(rbuf, s * LS + rl);
+                        rcur = lane == s * LS ? rs : rcur;
+                    }
                     int upg, upf;
                     if (HB) {
                         int tg = -goe, tf = 0;
@@ -250,9 +268,24 @@ sw_stream_kernel(StreamArgs a) {
                         }
                         upg = __builtin_amdgcn_update_dpp(tg, botg, 0x138, 0xf, 0xf, false);
                         upf = __builtin_amdgcn_update_dpp(tf, botf, 0x138, 0xf, 0xf, false);
+#pragma unroll
+                        for (int s = 1; s < NS; ++s) {
+                            int sg = -goe, sf = 0;
+                            if (bin) {
+                                sg = __builtin_amdgcn_readlane(bbuf.x, s * LS + rl);
+                                sf = __builtin_amdgcn_readlane(bbuf.y, s * LS + rl);
+                            }
+                            upg = lane == s * LS ? sg : upg;
+                            upf = lane == s * LS ? sf : upf;
+                        }
                     } else {
                         upg = __builtin_amdgcn_update_dpp(-goe, botg, 0x138, 0xf, 0xf, false);
                         upf = __builtin_amdgcn_mov_dpp(botf, 0x138, 0xf, 0xf, true);   // lane 0: 0
+#pragma unroll
+                        for (int s = 1; s < NS; ++s) {
+                            upg = lane == s * LS ? -goe : upg;
+                            upf = lane == s * LS ? 0 : upf;
+                        }
                     }
                     if (rcur < 0) {
                         // leave the previous pair, enter the next one at its column 1
@@ -270,23 +303,33 @@ sw_stream_kernel(StreamArgs a) {
                     diag0 = upg;
                     int p[R];
                     if (P16) {
-                        const uint4 q = reinterpret_cast<const uint4 *>(prof)[((uint32_t)rcur << 6) + lane];
-                        const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
+                        constexpr int LG = LS == 64 ? 6 : (LS == 32 ? 5 : 4);
+                        const uint4 *pq = reinterpret_cast<const uint4 *>(prof) + (((uint32_t)rcur << LG) + ll) * W;
 #pragma unroll
-                        for (int t = 0; t < R; ++t)
-                            p[t] = (t & 1) ? ((int)qw[t >> 1] >> 16) : (int)(int16_t)(qw[t >> 1] & 0xffffu);
+                        for (int w = 0; w < W; ++w) {
+                            const uint4 q = pq[w];
+                            const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                            for (int t = 8 * w; t < R && t < 8 * w + 8; ++t) {
+                                const int h = t - 8 * w;
+                                p[t] = (h & 1) ? ((int)qw[h >> 1] >> 16) : (int)(int16_t)(qw[h >> 1] & 0xffffu);
+                            }
+                        }
                     } else {
                         const int *prow = pbase + (rcur & 31) * SPAN;
 #pragma unroll
                         for (int t = 0; t < R; ++t) p[t] = prow[t];
                     }
-                    uint32_t word = 0;
+                    uint32_t word[W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) word[w] = 0;
                     int colkey = 0, hm = 0;
 #pragma unroll
                     for (int t = 0; t < R; t += 2) {
-                        const int h0 = sw_cell<TB>(hg[t], e[t], diag, upg, upf, p[t], ge, goe, word);
+                        const int h0 = sw_cell<TB>(hg[t], e[t], diag, upg, upf, p[t], ge, goe, word[t >> 3]);
                         if (t + 1 < R) {
-                            const int h1 = sw_cell<TB>(hg[t + 1], e[t + 1], diag, upg, upf, p[t + 1], ge, goe, word);
+                            const int h1 = sw_cell<TB>(hg[t + 1], e[t + 1], diag, upg, upf, p[t + 1], ge, goe,
+                                                       word[(t + 1) >> 3]);
                             if (ENDC) colkey = vmax3(colkey, (h0 << 5) | (31 - t), (h1 << 5) | (30 - t));
                             else hm = vmax3(hm, h0, h1);
                         } else {
@@ -296,10 +339,13 @@ sw_stream_kernel(StreamArgs a) {
                     }
                     botg = upg;
                     botf = upf;
-                    if (TB) stage[64 * u] = word;
+                    if (TB) {
+#pragma unroll
+                        for (int w = 0; w < W; ++w) stage[64 * (u * W + w)] = word[w];
+                    }
                     if (HB && bout) {
-                        const int K = k - lane;   // stream column of this lane
-                        if (lane == 63 && K >= 0 && K < C) bout[K] = make_int2(botg, botf);
+                        const int K = k - ll;   // stream column of this lane
+                        if (ll == LS - 1 && K >= 0 && K < C) bout[K] = make_int2(botg, botf);
                     }
                     if (ENDC) {
                         const int ch = colkey >> 5;
@@ -311,15 +357,17 @@ sw_stream_kernel(StreamArgs a) {
                         bh = max(bh, hm);
                     }
                 }
-                if (TB) {
-                    uint4 *dst = reinterpret_cast<uint4 *>(cw + (int64_t)(k8 >> 3) * 512);
-                    dst[0] = make_uint4(stage[0], stage[64], stage[128], stage[192]);
-                    dst[1] = make_uint4(stage[256], stage[320], stage[384], stage[448]);
+                if (TB && cw && k8 < steps_s) {
+                    uint4 *dst = reinterpret_cast<uint4 *>(cw + (int64_t)(k8 >> 3) * LS * 8 * W);
+#pragma unroll
+                    for (int v = 0; v < 2 * W; ++v)
+                        dst[v] = make_uint4(stage[64 * (4 * v)], stage[64 * (4 * v + 1)], stage[64 * (4 * v + 2)],
+                                            stage[64 * (4 * v + 3)]);
                 }
             }
             publish();   // the stream's last pair
         };
-        if (bin || bout) run(std::true_type{});
+        if (pass > 0 || pass + 1 < a.passes) run(std::true_type{});
         else run(std::false_type{});
     }
 }
@@ -592,6 +640,8 @@ struct WalkArgs {
     const int32_t *slot0;     // [nstreams]
     const int64_t *scb;       // [nstreams] code word base
     int nstreams;
+    int lg_ls;                // log2 of the lanes per stream (wavefront layout)
+    int W;                    // code words per step (wavefront layout)
 };
 
 constexpr int kWalkCenterLds = 8192;   // centers up to this length are staged in LDS
@@ -605,7 +655,7 @@ constexpr int kWalkCenterLds = 8192;   // centers up to this length are staged i
 template <bool STRIP, bool CEN_LDS>
 __global__ void __launch_bounds__(64)
 walk_kernel(WalkArgs a) {
-    __shared__ uint32_t cache[4][8][64];
+    __shared__ uint32_t cache[4][16][64];
     __shared__ uint32_t swin[16][64];
     __shared__ int8_t smat[32 * 32];
     __shared__ uint8_t scen[kWalkCenterLds];
@@ -655,26 +705,34 @@ walk_kernel(WalkArgs a) {
         }
         base = a.scb[lo];
         ccol = (int)(a.slot_col[w] - a.sbeg[lo]);
-        stride = (int)(a.sbeg[lo + 1] - a.sbeg[lo]) + 63;
+        stride = (int)(a.sbeg[lo + 1] - a.sbeg[lo]) + (1 << a.lg_ls) - 1;
     }
     constexpr bool strip = STRIP;
     const int R = strip ? 16 : a.R;
     const int G = strip ? (stride + 3) >> 2 : (stride + 7) >> 3;   // groups per pass / strip
+    // wavefront layout: LS lanes per stream, W words (8 steps x W words per chunk)
+    const int lg = strip ? 6 : a.lg_ls, LSm = (1 << lg) - 1;
+    const int W = strip ? 1 : a.W;
+    const int n0 = min(R, 8);           // rows in the first word of a step
     int i = i1, j = j1;
-    // row decomposition of i-1: block (pass*64 + lane, or strip) and row t in block
+    // row decomposition of i-1: block (pass*LS + lane, or strip) and row t in block
     int blk = 0, t = 0;
     {
         const int row = i - 1;
         if (strip) { blk = row >> 4; t = row & 15; }
-        else { const int span = 64 * R, ps = row / span, rr = row - ps * span; blk = ps * 64 + rr / R; t = rr % R; }
+        else {
+            const int span = R << lg, ps = row / span, rr = row - ps * span;
+            blk = (ps << lg) + rr / R;
+            t = rr % R;
+        }
     }
     // chunk (block b, group g): group of 4 columns (strip) or 8 wavefront steps
     auto grp_of = [&](int b, int jj) __attribute__((always_inline)) -> int {
-        return strip ? (jj - 1) >> 2 : (ccol + jj - 1 + (b & 63)) >> 3;
+        return strip ? (jj - 1) >> 2 : (ccol + jj - 1 + (b & LSm)) >> 3;
     };
     auto chunk_addr = [&](int b, int g) __attribute__((always_inline)) -> int64_t {
         return strip ? base + (((int64_t)b * G + g) * 64 + ccol) * 8
-                     : base + (((int64_t)(b >> 6) * G + g) * 64 + (b & 63)) * 8;
+                     : base + ((((int64_t)(b >> lg) * G + g) << lg) + (b & LSm)) * 8 * W;
     };
     int tb0 = -1, tg0 = -1, tb1 = -1, tg1 = -1, tb2 = -1, tg2 = -1, tb3 = -1, tg3 = -1;
     int state = 0;              // 0 = H, 1 = E, 2 = F
@@ -702,8 +760,11 @@ walk_kernel(WalkArgs a) {
             const int sl = h0 ? 0 : (h1 ? 1 : (h2 ? 2 : 3));
             int wi, sh;
             if (strip) { wi = ((j - 1) & 3) * 2 + (t >> 3); sh = 4 * (7 - (t & 7)); }
-            else { wi = (ccol + j - 1 + (blk & 63)) & 7; sh = 4 * (R - 1 - t); }
-            const uint32_t nib = (cache[sl][wi & 7][lane] >> (sh & 31)) & 15u;
+            else {
+                wi = ((ccol + j - 1 + (blk & LSm)) & 7) * W + (t >> 3);
+                sh = t < 8 ? 4 * (n0 - 1 - t) : 4 * (R - 1 - t);
+            }
+            const uint32_t nib = (cache[sl][wi & 15][lane] >> (sh & 31)) & 15u;
             const int gq = (int)(so + j - 1 - swb);
             const int gqc = min(max(gq, 0), 63);
             const int ic = min(max(i - 1, 0), m - 1);
@@ -793,27 +854,42 @@ walk_kernel(WalkArgs a) {
         const int64_t ad1 = g0 >= 1 ? chunk_addr(blk, g0 - 1) : ad0;
         const int64_t ad2 = g2 >= 0 ? chunk_addr(blk - 1, g2) : ad0;
         const int64_t ad3 = g2 >= 1 ? chunk_addr(blk - 1, g2 - 1) : ad0;
-        const uint4 c0l = *reinterpret_cast<const uint4 *>(a.codes + ad0);
-        const uint4 c0h = *reinterpret_cast<const uint4 *>(a.codes + ad0 + 4);
-        const uint4 c1l = *reinterpret_cast<const uint4 *>(a.codes + ad1);
-        const uint4 c1h = *reinterpret_cast<const uint4 *>(a.codes + ad1 + 4);
-        const uint4 c2l = *reinterpret_cast<const uint4 *>(a.codes + ad2);
-        const uint4 c2h = *reinterpret_cast<const uint4 *>(a.codes + ad2 + 4);
-        const uint4 c3l = *reinterpret_cast<const uint4 *>(a.codes + ad3);
-        const uint4 c3h = *reinterpret_cast<const uint4 *>(a.codes + ad3 + 4);
+        uint4 cq[4][4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) cq[0][h] = cq[1][h] = cq[2][h] = cq[3][h] = make_uint4(0, 0, 0, 0);
+        {
+            const uint4 *q0 = reinterpret_cast<const uint4 *>(a.codes + ad0);
+            const uint4 *q1 = reinterpret_cast<const uint4 *>(a.codes + ad1);
+            const uint4 *q2 = reinterpret_cast<const uint4 *>(a.codes + ad2);
+            const uint4 *q3 = reinterpret_cast<const uint4 *>(a.codes + ad3);
+            cq[0][0] = q0[0]; cq[0][1] = q0[1];
+            cq[1][0] = q1[0]; cq[1][1] = q1[1];
+            cq[2][0] = q2[0]; cq[2][1] = q2[1];
+            cq[3][0] = q3[0]; cq[3][1] = q3[1];
+            if (W == 2) {
+                cq[0][2] = q0[2]; cq[0][3] = q0[3];
+                cq[1][2] = q1[2]; cq[1][3] = q1[3];
+                cq[2][2] = q2[2]; cq[2][3] = q2[3];
+                cq[3][2] = q3[2]; cq[3][3] = q3[3];
+            }
+        }
         swin[0][lane] = s0.x; swin[1][lane] = s0.y; swin[2][lane] = s0.z; swin[3][lane] = s0.w;
         swin[4][lane] = s1.x; swin[5][lane] = s1.y; swin[6][lane] = s1.z; swin[7][lane] = s1.w;
         swin[8][lane] = s2.x; swin[9][lane] = s2.y; swin[10][lane] = s2.z; swin[11][lane] = s2.w;
         swin[12][lane] = s3.x; swin[13][lane] = s3.y; swin[14][lane] = s3.z; swin[15][lane] = s3.w;
         swb = nswb;
-        cache[0][0][lane] = c0l.x; cache[0][1][lane] = c0l.y; cache[0][2][lane] = c0l.z; cache[0][3][lane] = c0l.w;
-        cache[0][4][lane] = c0h.x; cache[0][5][lane] = c0h.y; cache[0][6][lane] = c0h.z; cache[0][7][lane] = c0h.w;
-        cache[1][0][lane] = c1l.x; cache[1][1][lane] = c1l.y; cache[1][2][lane] = c1l.z; cache[1][3][lane] = c1l.w;
-        cache[1][4][lane] = c1h.x; cache[1][5][lane] = c1h.y; cache[1][6][lane] = c1h.z; cache[1][7][lane] = c1h.w;
-        cache[2][0][lane] = c2l.x; cache[2][1][lane] = c2l.y; cache[2][2][lane] = c2l.z; cache[2][3][lane] = c2l.w;
-        cache[2][4][lane] = c2h.x; cache[2][5][lane] = c2h.y; cache[2][6][lane] = c2h.z; cache[2][7][lane] = c2h.w;
-        cache[3][0][lane] = c3l.x; cache[3][1][lane] = c3l.y; cache[3][2][lane] = c3l.z; cache[3][3][lane] = c3l.w;
-        cache[3][4][lane] = c3h.x; cache[3][5][lane] = c3h.y; cache[3][6][lane] = c3h.z; cache[3][7][lane] = c3h.w;
+#pragma unroll
+        for (int c = 0; c < 4; ++c) {
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                if (h < 2 || W == 2) {
+                    cache[c][4 * h + 0][lane] = cq[c][h].x;
+                    cache[c][4 * h + 1][lane] = cq[c][h].y;
+                    cache[c][4 * h + 2][lane] = cq[c][h].z;
+                    cache[c][4 * h + 3][lane] = cq[c][h].w;
+                }
+            }
+        }
         tb0 = blk; tg0 = g0;
         tb1 = g0 >= 1 ? blk : -1; tg1 = g0 - 1;
         tb2 = g2 >= 0 ? blk - 1 : -1; tg2 = g2;

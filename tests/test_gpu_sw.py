@@ -1,6 +1,8 @@
 """GPU parity: SW scores, end/start cells and center-star vectors, bit-exact
 against the oracle, through the C ABI.  Both kernels (one pair per lane, one
-pair per wavefront) are checked on every case."""
+pair per wavefront stream of 64, 32 or 16 lanes) are checked on every case."""
+import os
+
 import numpy as np
 import pytest
 
@@ -10,7 +12,7 @@ from paper_1704_00878_amd import synth
 
 pytestmark = pytest.mark.gpu
 
-ROUTES = ["intra", "inter"]
+ROUTES = ["intra", "intra32", "intra16", "inter"]
 
 
 @pytest.fixture(scope="module")
@@ -28,15 +30,21 @@ def ctx(H):
 
 
 def _route(H, name):
-    return H.HALIGN_ROUTE_INTRA if name == "intra" else H.HALIGN_ROUTE_INTER
+    return H.HALIGN_ROUTE_INTER if name == "inter" else H.HALIGN_ROUTE_INTRA
 
 
 def _run(H, ctx, sc, seqs, center_codes, route, traceback=True):
     import torch
     ds = H.DeviceSeqs(seqs)
     cen = torch.from_numpy(np.ascontiguousarray(center_codes, dtype=np.uint8)).cuda()
-    out = H.sw_batch(ctx, sc, ds, 0, traceback=traceback, route=_route(H, route), center_seq=cen)
-    torch.cuda.synchronize()
+    lanes = {"intra32": "32", "intra16": "16"}.get(route)
+    if lanes:
+        os.environ["HALIGN_STREAM_LANES"] = lanes
+    try:
+        out = H.sw_batch(ctx, sc, ds, 0, traceback=traceback, route=_route(H, route), center_seq=cen)
+        torch.cuda.synchronize()
+    finally:
+        os.environ.pop("HALIGN_STREAM_LANES", None)
     m = len(center_codes)
     res = dict(score=out["score"].cpu().numpy(), cells=out["cells"].cpu().numpy())
     if traceback:
@@ -137,8 +145,9 @@ def test_small_alphabet_ties(H, ctx):
             _compare(got, S, go, ge, center, seqs)
 
 
+@pytest.mark.parametrize("lanes", ["intra", "intra32", "intra16"])
 @pytest.mark.parametrize("streams", [1, 2, 5])
-def test_stream_packing(H, ctx, streams, monkeypatch):
+def test_stream_packing(H, ctx, streams, lanes, monkeypatch):
     """Many pairs per wavefront: pair boundaries inside a stream reset the
     state exactly; empty and 1-residue sequences sit between long ones."""
     monkeypatch.setenv("HALIGN_MAX_STREAMS", str(streams))
@@ -152,7 +161,7 @@ def test_stream_packing(H, ctx, streams, monkeypatch):
     ss = synth.SeqSet.from_list(seqs)
     sc = H.Scoring()
     for center in (base.seq(0), rng.integers(0, 20, size=700).astype(np.uint8)):
-        got = _run(H, ctx, sc, ss, center, "intra")
+        got = _run(H, ctx, sc, ss, center, lanes)
         _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, center, ss)
 
 
