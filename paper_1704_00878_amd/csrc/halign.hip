@@ -747,9 +747,11 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
         best->LS = it->second[3];
         return HALIGN_OK;
     }
-    // the batch itself, or a strided sample that keeps the length mix and,
-    // through the stream count, the number of pairs per stream
-    const int ns = std::min(N, 65536);
+    // the batch itself (up to 4e10 cells: a few tens of ms per candidate), or a
+    // strided sample of 65,536 pairs that keeps the length mix and, through the
+    // stream count, the number of pairs per stream
+    const double bcells = (double)m * (double)(sq->offsets_host[N] - sq->offsets_host[0]);
+    const int ns = bcells <= 4e10 ? N : std::min(N, 65536);
     std::vector<int32_t> sample(ns);
     for (int q = 0; q < ns; ++q) sample[q] = (int32_t)((int64_t)q * N / ns);
     int R0 = 8, p0 = 1;
