@@ -102,7 +102,7 @@ def counter_record(kernel: str, workload: str):
     return None
 
 
-def learned_report(H, ctx, sc, workload: str, anchors: int, epochs: int):
+def learned_report(H, ctx, sc, workload: str, anchors: int, partners: int, epochs: int, ema: float):
     """Learned center on a family set: the exhaustive center (all pairs,
     score-only) against the trained proposer's judged top-16, with the MSA of
     each and its avg SP.  Also the untrained network, 16 random candidates and
@@ -130,8 +130,9 @@ def learned_report(H, ctx, sc, workload: str, anchors: int, epochs: int):
     log(f"bench: exact center {c_exact} in {t_exact:.2f} s ({pair_cells / t_exact / 1e9:.0f} GCUPS score-only)")
     prop = H.Proposer(seed=1)
     losses, t_train = timed(lambda: H.halign_train_proposer(ctx, sc, ds, prop, anchors=anchors, batch=1024,
-                                                            epochs=epochs, lr=1e-3, seed=7))
-    log(f"bench: trained on {anchors * 64} pairs x {epochs} epochs in {t_train:.2f} s, loss {losses[0]:.4f} -> "
+                                                            epochs=epochs, lr=1e-3, seed=7, ema=ema,
+                                                            partners=partners))
+    log(f"bench: trained on {anchors * partners} pairs x {epochs} epochs in {t_train:.2f} s, loss {losses[0]:.4f} -> "
         f"{losses[-1]:.4f}")
     (c_learned, cand), t_prop = timed(lambda: H.halign_center_learned(ctx, sc, ds, prop, 16))
     c_untrained, _ = H.halign_center_learned(ctx, sc, ds, H.Proposer(seed=1), 16)
@@ -156,7 +157,8 @@ def learned_report(H, ctx, sc, workload: str, anchors: int, epochs: int):
         "workload": f"{workload}: {N} seqs, len {int(L.min())}-{int(L.max())}",
         "exact_center_s": round(t_exact, 3), "exact_pairs": npairs, "exact_cells": float(pair_cells),
         "exact_gcups": round(pair_cells / t_exact / 1e9, 1),
-        "train_s": round(t_train, 3), "train_pairs": anchors * 64, "epochs": epochs,
+        "train_s": round(t_train, 3), "train_pairs": anchors * partners, "anchors": anchors, "epochs": epochs,
+        "ema": ema,
         "loss_first_last": [round(losses[0], 5), round(losses[-1], 5)],
         "propose_judge_s": round(t_prop, 4), "candidates": [int(x) for x in cand],
         "sp_ratio_exact_over_learned": round(res["exact"]["avg_sp"] / res["learned"]["avg_sp"], 5),
@@ -180,8 +182,10 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy")
     ap.add_argument("--learned", default="learned50k", help="family set for the learned-center report "
                     "('none' skips it)")
-    ap.add_argument("--anchors", type=int, default=3125, help="training anchors (64 partners each)")
-    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--anchors", type=int, default=50000, help="training anchors")
+    ap.add_argument("--partners", type=int, default=4, help="training partners per anchor")
+    ap.add_argument("--epochs", type=int, default=16)
+    ap.add_argument("--ema", type=float, default=0.0, help="parameter average decay (0: off)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
@@ -320,7 +324,7 @@ def main():
 
     learned = None
     if args.learned != "none":
-        learned = learned_report(H, ctx, sc, args.learned, args.anchors, args.epochs)
+        learned = learned_report(H, ctx, sc, args.learned, args.anchors, args.partners, args.epochs, args.ema)
 
     out = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,

@@ -244,9 +244,12 @@ int halign_topk_center(halign_ctx *ctx, const float *E, int32_t nrows, int32_t k
                        int32_t *top, void *stream);
 
 /* Trainer.  Parameters (device): fp32 masters and their bf16 copies, updated
- * in place.  Training pairs: `anchors` random sequences, each with 64 random
- * partners (seeded), targets SW(a, b) / 100 from halign_sw_pairs; `epochs`
- * passes of Adam over them in batches of `batch` pairs.  loss_host[e] gets
+ * in place.  Training pairs: `anchors` random sequences, each with
+ * `partners` random partners (1..64, 0 = 64; seeded), targets SW(a, b) / 100
+ * from halign_sw_pairs (which scores 64 partners per anchor); `epochs`
+ * passes of Adam over them in batches of `batch` pairs.  With 0 < ema < 1 an
+ * exponential moving average of the parameters (decay `ema` per step, started
+ * from the initial parameters) replaces them at the end.  loss_host[e] gets
  * the mean batch loss of epoch e (synchronises). */
 typedef struct {
     float *W1, *b1, *W2, *b2;     /* fp32 masters */
@@ -258,6 +261,8 @@ typedef struct {
     int32_t epochs;
     float lr;
     uint64_t seed;
+    float ema;                    /* 0: off */
+    int32_t partners;             /* per anchor, 1..64 (0: 64) */
 } halign_train_opts;
 int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
                           const halign_train_opts *opts, const halign_params *params,

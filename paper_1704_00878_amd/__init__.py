@@ -60,7 +60,8 @@ class _Params(ctypes.Structure):
 
 class _TrainOpts(ctypes.Structure):
     _fields_ = [("anchors", ctypes.c_int32), ("batch", ctypes.c_int32), ("epochs", ctypes.c_int32),
-                ("lr", ctypes.c_float), ("seed", ctypes.c_uint64)]
+                ("lr", ctypes.c_float), ("seed", ctypes.c_uint64), ("ema", ctypes.c_float),
+                ("partners", ctypes.c_int32)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -422,8 +423,9 @@ def halign_topk_center(ctx: Context, E, nrows: int, k: int, u, top, stream=None)
 
 
 def halign_train_proposer(ctx: Context, sc: Scoring, seqs: DeviceSeqs, prop: Proposer, anchors: int,
-                          batch: int = 1024, epochs: int = 4, lr: float = 1e-3, seed: int = 7, stream=None):
-    opts = _TrainOpts(anchors, batch, epochs, lr, seed)
+                          batch: int = 1024, epochs: int = 4, lr: float = 1e-3, seed: int = 7, ema: float = 0.0,
+                          partners: int = 64, stream=None):
+    opts = _TrainOpts(anchors, batch, epochs, lr, seed, ema, partners)
     pr = prop.params()
     losses = (ctypes.c_float * epochs)()
     _check(lib().halign_train_proposer(ctx.h, sc.ref, seqs.ref, ctypes.byref(opts), ctypes.byref(pr), losses,

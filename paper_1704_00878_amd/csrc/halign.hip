@@ -1715,13 +1715,16 @@ int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halig
         return fail(HALIGN_E_INVALID, "need N >= 2 and positive anchors, batch, epochs");
     hipStream_t st = (hipStream_t)stream;
     HCHK(hipSetDevice(ctx->device));
-    // training pairs: anchors with 64 partners each (never the anchor itself)
+    // training pairs: anchors with `partners` partners each (never the anchor
+    // itself); the score kernel takes 64 partners per anchor, of which the
+    // first `partners` are used
     uint64_t rs = opts->seed;
     const int A = opts->anchors;
-    const int P = A * 64;
-    std::vector<int32_t> anc(A), par(P);
+    const int PA = (opts->partners > 0 && opts->partners < 64) ? opts->partners : 64;
+    const int P = A * PA;
+    std::vector<int32_t> anc(A), par((size_t)A * 64);
     for (int q = 0; q < A; ++q) anc[q] = (int32_t)(splitmix(rs) % (uint64_t)N);
-    for (int q = 0; q < P; ++q) {
+    for (size_t q = 0; q < (size_t)A * 64; ++q) {
         int32_t b;
         do { b = (int32_t)(splitmix(rs) % (uint64_t)N); } while (b == anc[q / 64]);
         par[q] = b;
@@ -1732,20 +1735,23 @@ int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halig
     const int nsteps = steps_per_epoch * opts->epochs;
     size_t off = 0;
     auto take = [&](size_t bytes) { size_t r = off; off = (off + bytes + 255) & ~size_t(255); return r; };
-    const size_t o_score = take(4 * (size_t)P), o_tgt = take(4 * (size_t)P), o_idx = take(4 * (size_t)nsteps * 2 * B),
+    const size_t o_score = take(4 * (size_t)A * 64), o_tgt = take(4 * (size_t)A * 64),
+                 o_idx = take(4 * (size_t)nsteps * 2 * B),
                  o_tix = take(4 * (size_t)nsteps * B), o_tb = take(4 * (size_t)B), o_loss = take(4 * (size_t)nsteps),
                  o_X = take(2 * (size_t)N * hk::kFeat), o_Xb = take(2 * (size_t)2 * B * hk::kFeat),
                  o_Z = take(4 * (size_t)2 * B * hk::kHid), o_Hb = take(2 * (size_t)2 * B * hk::kHid),
                  o_E = take(4 * (size_t)2 * B * hk::kEmb), o_dE = take(4 * (size_t)2 * B * hk::kEmb),
                  o_g = take(4 * (size_t)(hk::kFeat * hk::kHid + hk::kHid + hk::kHid * hk::kEmb + hk::kEmb)),
                  o_m = take(4 * (size_t)(hk::kFeat * hk::kHid + hk::kHid + hk::kHid * hk::kEmb + hk::kEmb)),
-                 o_v = take(4 * (size_t)(hk::kFeat * hk::kHid + hk::kHid + hk::kHid * hk::kEmb + hk::kEmb));
+                 o_v = take(4 * (size_t)(hk::kFeat * hk::kHid + hk::kHid + hk::kHid * hk::kEmb + hk::kEmb)),
+                 o_e = take(4 * (size_t)(hk::kFeat * hk::kHid + hk::kHid + hk::kHid * hk::kEmb + hk::kEmb));
     RCHK(grow(ctx, ctx->mlp[6], off));
     char *w = (char *)ctx->mlp[6].p;
     int32_t *score = (int32_t *)(w + o_score);
     float *tgt = (float *)(w + o_tgt);
     RCHK(halign_sw_pairs(ctx, sc, seqs, anc.data(), A, par.data(), score, stream));
-    hipLaunchKernelGGL(hk::scale_targets_kernel, dim3((P + 255) / 256), dim3(256), 0, st, (const int32_t *)score, P, tgt);
+    hipLaunchKernelGGL(hk::scale_targets_kernel, dim3((A * 64 + 255) / 256), dim3(256), 0, st, (const int32_t *)score,
+                       A * 64, tgt);
     HCHK(hipGetLastError());
     // batch index lists for every step (rows of X_all for a then b, and target slots)
     {
@@ -1757,9 +1763,10 @@ int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halig
                 const int step = e * steps_per_epoch + s;
                 for (int r = 0; r < B; ++r) {
                     const int q = order[s * B + r];
-                    hidx[(size_t)step * 2 * B + r] = anc[q / 64];
-                    hidx[(size_t)step * 2 * B + B + r] = par[q];
-                    htix[(size_t)step * B + r] = q;
+                    const int slot = (q / PA) * 64 + q % PA;
+                    hidx[(size_t)step * 2 * B + r] = anc[q / PA];
+                    hidx[(size_t)step * 2 * B + B + r] = par[slot];
+                    htix[(size_t)step * B + r] = slot;
                 }
             }
         }
@@ -1781,6 +1788,21 @@ int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halig
     float *Z = (float *)(w + o_Z), *E = (float *)(w + o_E), *dE = (float *)(w + o_dE), *tb = (float *)(w + o_tb);
     float *loss = (float *)(w + o_loss);
     halign_model md{pr->W1b, pr->b1, pr->W2b, pr->b2};
+    // parameter average (starts from the initial parameters)
+    const bool use_ema = opts->ema > 0.f && opts->ema < 1.f;
+    float *ema = (float *)(w + o_e);
+    float *eW1 = ema, *eb1 = ema + nW1, *eW2 = eb1 + hk::kHid, *eb2 = eW2 + nW2;
+    if (use_ema) {
+        HCHK(hipMemcpyAsync(eW1, pr->W1, 4 * (size_t)nW1, hipMemcpyDeviceToDevice, st));
+        HCHK(hipMemcpyAsync(eb1, pr->b1, 4 * (size_t)hk::kHid, hipMemcpyDeviceToDevice, st));
+        HCHK(hipMemcpyAsync(eW2, pr->W2, 4 * (size_t)nW2, hipMemcpyDeviceToDevice, st));
+        HCHK(hipMemcpyAsync(eb2, pr->b2, 4 * (size_t)hk::kEmb, hipMemcpyDeviceToDevice, st));
+    }
+    auto ema_step = [&](const float *p, float *e, int64_t n) -> int {
+        hipLaunchKernelGGL(hk::ema_kernel, dim3(grid_for(n, 256, 2048)), dim3(256), 0, st, p, e, n, opts->ema);
+        HCHK(hipGetLastError());
+        return HALIGN_OK;
+    };
     for (int step = 0; step < nsteps; ++step) {
         const int32_t *ix = (const int32_t *)(w + o_idx) + (size_t)step * 2 * B;
         const int32_t *tx = (const int32_t *)(w + o_tix) + (size_t)step * B;
@@ -1796,6 +1818,23 @@ int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halig
         RCHK(halign_adam_step(pr->b1, gb1, mb1, vb1, nullptr, hk::kHid, lr, 0.9f, 0.999f, 1e-8f, step + 1, stream));
         RCHK(halign_adam_step(pr->W2, gW2, mW2, vW2, pr->W2b, nW2, lr, 0.9f, 0.999f, 1e-8f, step + 1, stream));
         RCHK(halign_adam_step(pr->b2, gb2, mb2, vb2, nullptr, hk::kEmb, lr, 0.9f, 0.999f, 1e-8f, step + 1, stream));
+        if (use_ema) {
+            RCHK(ema_step(pr->W1, eW1, nW1));
+            RCHK(ema_step(pr->b1, eb1, hk::kHid));
+            RCHK(ema_step(pr->W2, eW2, nW2));
+            RCHK(ema_step(pr->b2, eb2, hk::kEmb));
+        }
+    }
+    if (use_ema) {   // the averaged parameters become the model
+        HCHK(hipMemcpyAsync(pr->W1, eW1, 4 * (size_t)nW1, hipMemcpyDeviceToDevice, st));
+        HCHK(hipMemcpyAsync(pr->b1, eb1, 4 * (size_t)hk::kHid, hipMemcpyDeviceToDevice, st));
+        HCHK(hipMemcpyAsync(pr->W2, eW2, 4 * (size_t)nW2, hipMemcpyDeviceToDevice, st));
+        HCHK(hipMemcpyAsync(pr->b2, eb2, 4 * (size_t)hk::kEmb, hipMemcpyDeviceToDevice, st));
+        hipLaunchKernelGGL(hk::f32_to_bf16_kernel, dim3(grid_for(nW1, 256, 2048)), dim3(256), 0, st,
+                           (const float *)pr->W1, pr->W1b, nW1);
+        hipLaunchKernelGGL(hk::f32_to_bf16_kernel, dim3(grid_for(nW2, 256, 2048)), dim3(256), 0, st,
+                           (const float *)pr->W2, pr->W2b, nW2);
+        HCHK(hipGetLastError());
     }
     if (loss_host) {
         std::vector<float> hl(nsteps);

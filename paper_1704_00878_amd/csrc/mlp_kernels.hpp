@@ -238,6 +238,12 @@ __global__ void adam_kernel(float *p, const float *gr, float *m, float *v, uint1
     }
 }
 
+// exponential moving average of parameters: e = d * e + (1 - d) * p
+__global__ void ema_kernel(const float *p, float *e, int64_t n, float d) {
+    for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
+        e[x] = d * e[x] + (1.f - d) * p[x];
+}
+
 __global__ void f32_to_bf16_kernel(const float *src, uint16_t *dst, int64_t n) {
     for (int64_t x = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; x < n; x += (int64_t)gridDim.x * blockDim.x)
         dst[x] = f2bf(src[x]);

@@ -170,6 +170,24 @@ def test_training_reduces_loss(H, ctx):
     assert losses[-1] < 0.5 * losses[0], losses
 
 
+def test_training_parameter_average(H, ctx):
+    """With one Adam step, the averaged parameters are d * p0 + (1 - d) * p1,
+    where p1 is what the same step gives without averaging."""
+    seqs = synth.generate("learned50k", n_seqs=300, seed=12)
+    ds = H.DeviceSeqs(seqs)
+    d = 0.75
+    p0 = H.Proposer(seed=3)
+    init = [x.cpu().numpy().astype(np.float64) for x in (p0.W1, p0.b1, p0.W2, p0.b2)]
+    plain = H.Proposer(seed=3)
+    H.halign_train_proposer(ctx, H.Scoring(), ds, plain, anchors=4, batch=256, epochs=1, lr=1e-2, seed=5)
+    avg = H.Proposer(seed=3)
+    H.halign_train_proposer(ctx, H.Scoring(), ds, avg, anchors=4, batch=256, epochs=1, lr=1e-2, seed=5, ema=d)
+    for x0, x1, xa in zip(init, (plain.W1, plain.b1, plain.W2, plain.b2), (avg.W1, avg.b1, avg.W2, avg.b2)):
+        ref = d * x0 + (1 - d) * x1.cpu().numpy().astype(np.float64)
+        assert np.allclose(xa.cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
+    assert (avg.W1b.cpu().numpy().view(np.uint16) == mlp.bf16_bits(avg.W1.cpu().numpy())).all()
+
+
 def test_learned_center_gain(H, ctx):
     """What the trained proposer gains (a 4,000-sequence draw of the learned50k
     family set): its judged top-16 center reaches >= 99% of the exact center's
