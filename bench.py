@@ -79,10 +79,11 @@ def cpu_baseline(seqs, center: int, budget_s: float = 20.0):
                       f"({cells:.3e} cells, {dt:.1f} s, one thread per core)"}
 
 
-def counter_record(kernel: str, workload: str):
+def counter_record(kernel: str, workload: str, plan: dict):
     """HBM counters of the forward kernel taken with rocprofv3 --pmc on this
-    workload, from the profiles/ summaries; None unless they were taken on the
-    kernel source as it is now (sha256 of csrc/sw_kernels.hpp)."""
+    workload and plan (rows per lane, lanes per stream), from the profiles/
+    summaries; None unless they were taken on the kernel source as it is now
+    (sha256 of csrc/sw_kernels.hpp)."""
     import glob
     import hashlib
     import re
@@ -97,7 +98,8 @@ def counter_record(kernel: str, workload: str):
                 rec = json.loads(m.group(1))
             except ValueError:
                 continue
-            if rec.get("kernel") == kernel and rec.get("workload") == workload and rec.get("source_sha256") == sha:
+            if (rec.get("kernel") == kernel and rec.get("workload") == workload and rec.get("source_sha256") == sha
+                    and rec.get("R") == plan.get("R") and rec.get("lanes") == plan.get("lanes")):
                 return rec
     return None
 
@@ -140,11 +142,11 @@ def learned_report(H, ctx, sc, workload: str, anchors: int, partners: int, epoch
     c_random = int(max(rand, key=lambda i: (S[i], -i)))
 
     def msa_of(c):
+        H.halign_msa(ctx, sc, ds, c)   # warm: plans (and tunes) this center length once
         (msa, _), dt = timed(lambda: H.halign_msa(ctx, sc, ds, c))
         sp = H.halign_sp_score(sc, msa)[0] / npairs
         return dt, sp, int(msa.shape[1])
 
-    H.halign_msa(ctx, sc, ds, c_learned)          # warm the buffers
     res = {}
     for name, c in (("exact", c_exact), ("learned", c_learned), ("untrained", c_untrained),
                     ("random16", c_random), ("seq0", 0)):
@@ -279,7 +281,9 @@ def main():
         torch.cuda.synchronize()
         log(f"bench: calibration copy of {nb} bytes x3 done")
 
-    # per-pair launches: same kernels, one pair per call, no batching
+    # per-pair launches: same kernels, one pair per call, no batching (default
+    # plan: tuning a one-pair batch would only add the tuner's own runs)
+    ctx.set_autotune(False)
     rng = np.random.default_rng(0)
     pick = rng.choice(seqs.n, size=min(max(args.perpair, 1), seqs.n), replace=False)
     singles = [H.DeviceSeqs(seqs.subset([int(k)]), "cuda:0") for k in pick]
@@ -299,7 +303,7 @@ def main():
     # dominant kernel roofline: integer VALU, fixed op model
     achieved = cells * OPS_PER_CELL_TB / (fwd_ms * 1e-3) / 1e12
     kname = "sw_stream_kernel" if st["route"] == 0 else "sw_inter_kernel"
-    rec = counter_record(kname, args.workload)
+    rec = counter_record(kname, args.workload, plan)
     traffic = clock = None
     if rec is not None:
         traffic = int(rec["fetch_kib"] * 1024 * rec["fetch_factor"] + rec["write_kib"] * 1024 * rec["write_factor"])
@@ -322,6 +326,7 @@ def main():
         cpu = cpu_baseline(seqs, center)
         log(f"bench: oracle {cpu['value']:.3f} GCUPS on {cpu['cores']} threads")
 
+    ctx.set_autotune(not args.no_autotune)
     learned = None
     if args.learned != "none":
         learned = learned_report(H, ctx, sc, args.learned, args.anchors, args.partners, args.epochs, args.ema)
