@@ -1255,8 +1255,12 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const 
     while (ch > 1024 && (size_t)wpb * wave_bytes(ch) > lim) ch = ((ch / 2) + 15) & ~15;
     while (wpb > 1 && (size_t)wpb * wave_bytes(ch) > lim) --wpb;
     if ((size_t)wpb * wave_bytes(ch) > lim) return fail(HALIGN_E_UNSUPPORTED, "center length %d too long for row emission", m);
-    hk::RowsArgs ra{seqs->residues, seqs->offsets, N, m, ins, aligned, aw, G, col, width, ch, (int)wave_bytes(ch), msa};
-    const size_t lds = (size_t)wpb * wave_bytes(ch);
+    if (width >= ((int64_t)1 << 31)) return fail(HALIGN_E_UNSUPPORTED, "MSA width %lld", (long long)width);
+    const size_t gcb = 8 * (size_t)m1;
+    const int gc_lds = (size_t)wpb * wave_bytes(ch) + gcb <= lim ? 1 : 0;
+    hk::RowsArgs ra{seqs->residues, seqs->offsets, N, m, ins, aligned, aw, G, col, width, ch, (int)wave_bytes(ch),
+                    gc_lds, msa};
+    const size_t lds = (size_t)wpb * wave_bytes(ch) + (gc_lds ? gcb : 0);
     const int per_cu = std::max(1, std::min(8, (int)(ctx->lds_max / lds)));
     const int grid = std::max(1, std::min((N + wpb - 1) / wpb, ctx->num_cu * per_cu));
     hipLaunchKernelGGL(hk::rows_kernel, dim3(grid), dim3(64 * wpb), lds, st, ra);

@@ -136,6 +136,7 @@ struct RowsArgs {
     int64_t width;
     int ch;                   // columns per chunk (multiple of 16)
     int wave_bytes;           // LDS bytes per wavefront region
+    int gc_lds;               // (col, G) staged in LDS for the workgroup (after the wave regions)
     uint8_t *msa;             // [nrows][width]
 };
 
@@ -152,6 +153,14 @@ __global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
     const size_t bo = (4 * (size_t)m1 + (((size_t)m1 * 2 + 3) & ~(size_t)3) + 4 * (size_t)a.aw + 15) & ~(size_t)15;
     uint8_t *buf = reinterpret_cast<uint8_t *>(wsh + bo);                     // [ch + 16], 16-byte aligned
     uint4 *buf16 = reinterpret_cast<uint4 *>(buf);
+    int2 *gcl = reinterpret_cast<int2 *>(reinterpret_cast<char *>(lds_rows) + (size_t)wpb * a.wave_bytes);
+    if (a.gc_lds) {
+        for (int p = tid; p < m1; p += blockDim.x) gcl[p] = make_int2((int)a.col[p], a.G[p]);
+        __syncthreads();
+    }
+    auto colg = [&](int p) __attribute__((always_inline)) -> int2 {
+        return a.gc_lds ? gcl[p] : make_int2((int)a.col[p], a.G[p]);
+    };
     const int per = (m1 + 63) / 64;
     const int lo = min(m1, lane * per), hi = min(m1, lo + per);
     for (int k = blockIdx.x * wpb + wid; k < a.nrows; k += gridDim.x * wpb) {
@@ -185,15 +194,27 @@ __global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
             const int nw = (a0 + len + 15) >> 4;
             for (int q = lane; q < nw; q += 64) buf16[q] = make_uint4(~0u, ~0u, ~0u, ~0u);
             __builtin_amdgcn_wave_barrier();
-            for (int q = lane; q < n; q += 64) {
-                int l = 0, h = m;   // last block whose start is <= q
+            // each lane places a contiguous run of residues: one binary search
+            // for the block of its first residue, then a short forward walk
+            // (a new search when it would cross more than a few empty blocks)
+            const int per_r = (n + 63) >> 6;
+            const int q0 = min(n, lane * per_r), q1 = min(n, q0 + per_r);
+            auto search = [&](int q, int l) __attribute__((always_inline)) {   // last block with start <= q
+                int h = m;
                 while (l < h) {
                     const int mid = (l + h + 1) >> 1;
                     if (spos[mid] <= q) l = mid;
                     else h = mid - 1;
                 }
+                return l;
+            };
+            int l = q0 < q1 ? search(q0, 0) : 0;
+            for (int q = q0; q < q1; ++q) {
+                for (int st = 0; st < 4 && l < m && spos[l + 1] <= q; ++st) ++l;
+                if (l < m && spos[l + 1] <= q) l = search(q, l);
                 const int tq = q - spos[l];
-                const int64_t dest = a.col[l] + (tq < (int)sins[l] ? tq : a.G[l]);
+                const int2 cg = colg(l);
+                const int dest = cg.x + (tq < (int)sins[l] ? tq : cg.y);
                 if (dest >= x0 && dest < x0 + len) buf[a0 + (int)(dest - x0)] = s[q];
             }
             __builtin_amdgcn_wave_barrier();

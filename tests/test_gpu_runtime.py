@@ -25,10 +25,14 @@ def _host(H, out, m):
             H.aligned_to_bool(out["aligned"].cpu().numpy(), m))
 
 
-def test_graph_replays_match_eager(H):
+@pytest.mark.parametrize("lanes", [None, "16"])
+def test_graph_replays_match_eager(H, lanes, monkeypatch):
     """Several replays, with eager work and synchronisations in between, each
-    equal to the oracle; a changed argument is captured anew."""
+    equal to the oracle; a changed argument is captured anew.  Also with
+    16-lane streams."""
     import torch
+    if lanes:
+        monkeypatch.setenv("HALIGN_STREAM_LANES", lanes)
     ctx = H.Context(0)
     sc = H.Scoring()
     seqs = synth.generate("plain64", n_seqs=300, seed=31)
