@@ -64,19 +64,25 @@ def cpu_baseline(seqs, center: int, budget_s: float = 20.0):
         except Exception as e:  # pragma: no cover
             err.append(e)
 
-    ths = [threading.Thread(target=work, args=(p,)) for p in parts]
+    # whole passes over the sample until about 2 s of wall time have run
+    reps = 0
     t = time.perf_counter()
-    for th in ths:
-        th.start()
-    for th in ths:
-        th.join()
-    dt = time.perf_counter() - t
-    if err:
-        raise err[0]
-    cells = m * int(sample.residues.size)
+    while True:
+        ths = [threading.Thread(target=work, args=(p,)) for p in parts]
+        for th in ths:
+            th.start()
+        for th in ths:
+            th.join()
+        reps += 1
+        dt = time.perf_counter() - t
+        if err:
+            raise err[0]
+        if dt >= 2.0 or nsamp < seqs.n:
+            break
+    cells = m * int(sample.residues.size) * reps
     return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": len(parts), "kind": "oracle",
-            "sample": f"SW+traceback of the first {nsamp} of {seqs.n} sequences against the center "
-                      f"({cells:.3e} cells, {dt:.1f} s, one thread per core)"}
+            "sample": f"SW+traceback of the first {nsamp} of {seqs.n} sequences against the center, "
+                      f"{reps} pass(es) ({cells:.3e} cells, {dt:.1f} s, one thread per core)"}
 
 
 def counter_record(kernel: str, workload: str, plan: dict):
