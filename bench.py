@@ -110,7 +110,8 @@ def counter_record(kernel: str, workload: str, plan: dict):
     return None
 
 
-def learned_report(H, ctx, sc, workload: str, anchors: int, partners: int, epochs: int, ema: float):
+def learned_report(H, ctx, sc, workload: str, anchors: int, partners: int, epochs: int, ema: float,
+                   nseqs: int = 0):
     """Learned center on a family set: the exhaustive center (all pairs,
     score-only) against the trained proposer's judged top-16, with the MSA of
     each and its avg SP.  Also the untrained network, 16 random candidates and
@@ -118,7 +119,7 @@ def learned_report(H, ctx, sc, workload: str, anchors: int, partners: int, epoch
     import torch
     from paper_1704_00878_amd import synth
     log(f"bench: learned center on {workload}")
-    seqs = synth.generate(workload)
+    seqs = synth.generate(workload, n_seqs=nseqs) if nseqs > 0 else synth.generate(workload)
     ds = H.DeviceSeqs(seqs, "cuda:0")
     N = seqs.n
     L = seqs.lengths().astype(np.float64)
@@ -190,6 +191,7 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true", help="also run a 256 MiB device copy")
     ap.add_argument("--learned", default="learned50k", help="family set for the learned-center report "
                     "('none' skips it)")
+    ap.add_argument("--learned-n", type=int, default=0, help="first N sequences of the family set (0: all)")
     ap.add_argument("--anchors", type=int, default=50000, help="training anchors")
     ap.add_argument("--partners", type=int, default=4, help="training partners per anchor")
     ap.add_argument("--epochs", type=int, default=16)
@@ -335,7 +337,8 @@ def main():
     ctx.set_autotune(not args.no_autotune)
     learned = None
     if args.learned != "none":
-        learned = learned_report(H, ctx, sc, args.learned, args.anchors, args.partners, args.epochs, args.ema)
+        learned = learned_report(H, ctx, sc, args.learned, args.anchors, args.partners, args.epochs, args.ema,
+                                 args.learned_n)
 
     out = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,

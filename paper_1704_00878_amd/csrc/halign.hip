@@ -23,6 +23,8 @@
 #include "../../include/halign.h"
 #include "msa_kernels.hpp"
 #include "sw_kernels.hpp"
+#include "strip_kernels.hpp"
+#include "walk_kernels.hpp"
 #include "mlp_kernels.hpp"
 
 namespace {
@@ -290,6 +292,12 @@ void launch_stream(int R, int LS, const hk::StreamArgs &a, bool tb, bool endc, b
         case 15: launch_stream_R<15>(LS, a, tb, endc, p16, grid, lds, st); break;
         default: launch_stream_R<16>(LS, a, tb, endc, p16, grid, lds, st); break;
     }
+}
+
+// Boundary-row columns per strip-kernel lane: the longest sequence rounded
+// up to whole prefetch blocks.
+int64_t strip_cols(int nmax_all) {
+    return ((int64_t)std::max(1, nmax_all) + hk::kB - 1) / hk::kB * hk::kB;
 }
 
 void launch_inter(const hk::InterArgs &a, bool tb, bool endc, int grid, hipStream_t st) {
@@ -600,7 +608,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         } else {
             const int slots = ctx->num_cu * 16;
             const int grid = std::max(1, std::min(ngroups, slots));
-            RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * std::max(1, nmax_all) * 8));
+            RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * strip_cols(nmax_all) * 8));
             RCHK(launch_fill((uint32_t *)counter, 0u, 1, st));
             RCHK(record(ctx, ctx->ev[0], st));
             hk::InterArgs a{};
@@ -622,7 +630,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             a.codes = tb ? (uint32_t *)ctx->codes.p : nullptr;
             a.gcode_base = (const int64_t *)(dplan + o_gcb);
             a.bound = (int2 *)ctx->bound.p;
-            a.bstride = (int64_t)64 * std::max(1, nmax_all);
+            a.bstride = (int64_t)64 * strip_cols(nmax_all);
             launch_inter(a, tb, endc, grid, st);
             HCHK(hipGetLastError());
             RCHK(record(ctx, ctx->ev[1], st));
@@ -1293,7 +1301,7 @@ static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, 
     const int64_t *oh = sq->offsets_host;
     for (int k = 0; k < sq->n; ++k) nmax_all = std::max(nmax_all, (int)(oh[k + 1] - oh[k]));
     const int grid = std::max(1, std::min(ng, ctx->num_cu * 16));
-    RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * std::max(1, nmax_all) * 8));
+    RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * strip_cols(nmax_all) * 8));
     RCHK(grow(ctx, ctx->counter, 256));
     RCHK(launch_fill((uint32_t *)ctx->counter.p, 0u, 1, st));
     hk::InterArgs a{};
@@ -1314,7 +1322,7 @@ static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, 
     a.counter = (int *)ctx->counter.p;
     a.score = score;
     a.bound = (int2 *)ctx->bound.p;
-    a.bstride = (int64_t)64 * std::max(1, nmax_all);
+    a.bstride = (int64_t)64 * strip_cols(nmax_all);
     ctx->last_stats[0] = 0;
     RCHK(record(ctx, ctx->ev[0], st));
     launch_inter(a, false, false, grid, st);

@@ -1,0 +1,256 @@
+// Strip kernel (one pair per lane) for gfx950: the score and traceback
+// forward pass of many pairs against per-group centers.  Shares the
+// recurrence, register form, traceback code and end-cell rule of the
+// wavefront kernel (sw_kernels.hpp).
+#pragma once
+#include "sw_kernels.hpp"
+
+namespace hk {
+
+// ---------------------------------------------------------------------------
+// Inter-task kernel: one pair per lane, 64 pairs per wavefront (one wave per
+// workgroup, persistent over groups).  Lane-private state is a strip of T=16
+// center rows; the wave sweeps j over the group's longest sequence, strip by
+// strip.  The strip's profile (32 x 16 int32, stride 20) is rebuilt in LDS per
+// strip from the group's center, so a group may use the batch center or any
+// sequence of the set as its center (center selection, training targets).
+// Strip boundaries (Hg, F* of the strip's last row for every j) go through a
+// per-workgroup scratch row, read with agent-scope loads so that no stale L1
+// line is seen.
+//
+// Codes: u64 (two u32 words: rows 0-7, 8-15; row t nibble at 4*(7 - t%8))
+// per (strip s, column j, lane), tiled so that a lane's 4 consecutive columns
+// share 32 bytes: with G = ceil(nmax/4),
+//   codes[gbase + ((s*G + (j-1)/4)*64 + lane)*8 + ((j-1)%4)*2 + half].
+// ---------------------------------------------------------------------------
+constexpr int kT = 16;
+constexpr int kPS = kT + 4;  // LDS row stride of the strip profile
+constexpr int kB = 4;        // columns per prefetch block (the 4 columns of a code chunk)
+constexpr int kFMask = (1 << 27) - 1;  // F* bits of a strip boundary cell (residue code above)
+
+struct InterArgs {
+    const int8_t *mat;
+    int alpha;
+    const uint8_t *center;    // batch center (mode 0)
+    int m;
+    const uint8_t *res;
+    const int64_t *off;
+    int mode;                 // 0 batch, 1 all pairs (a < b), 2 anchored groups
+    const int32_t *order;     // mode 0: 64 * ngroups pair ids (-1 = empty lane)
+    const int32_t *gnmax;     // mode 0: per group longest sequence (code layout)
+    const int32_t *gcen;      // mode 1: center position in perm; mode 2: center seq id
+    const int32_t *gb0;       // modes 1/2: first partner position in perm
+    const int32_t *perm;      // modes 1/2: sequence ids sorted by length
+    int nseq;
+    const int32_t *gslot;     // mode 2: sums slot of the group's center
+    int64_t *sums;            // modes 1/2: integer score sums (atomic adds)
+    int ngroups;
+    int ge, goe;
+    int *counter;
+    int32_t *score;           // mode 0: per pair id; mode 2: per lane slot (optional)
+    int32_t *endcell;
+    uint32_t *codes;
+    const int64_t *gcode_base;// per group (u32 words)
+    int2 *bound;              // per workgroup slot: bstride int2
+    int64_t bstride;          // >= 64 * (max nmax rounded up to kB)
+};
+
+__device__ __forceinline__ int2 load_agent(const int2 *p) {
+    uint64_t v = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
+                                   __HIP_MEMORY_SCOPE_AGENT);
+    return make_int2((int)(uint32_t)v, (int)(uint32_t)(v >> 32));
+}
+
+template <bool TB, bool ENDC>
+__global__ void __launch_bounds__(64)
+sw_inter_kernel(InterArgs a) {
+    __shared__ int prof[kAlphaMax * kPS];
+    __shared__ uint32_t stage_all[64 * 8];
+    __shared__ int8_t smat[kAlphaMax * kAlphaMax];
+    const int lane = threadIdx.x;
+    for (int x = lane; x < kAlphaMax * kAlphaMax; x += 64) {
+        const int r = x >> 5, q = x & 31;
+        smat[x] = (r < a.alpha && q < a.alpha) ? a.mat[r * a.alpha + q] : (int8_t)0;
+    }
+    int2 *bnd = a.bound + (int64_t)blockIdx.x * a.bstride;
+    const int ge = a.ge, goe = a.goe;
+    __shared__ int s_next;
+    for (;;) {
+        // fetch the next group: one atomic by lane 0, broadcast through LDS
+        __syncthreads();
+        if (lane == 0) s_next = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int g = __builtin_amdgcn_readfirstlane(s_next);
+        if (g >= a.ngroups) break;
+        int pid = -1;       // output slot (mode 0: pair id)
+        int sid = -1;       // sequence of this lane
+        const uint8_t *cen = a.center;
+        int m = a.m;
+        int cid = -1;
+        if (a.mode == 0) {
+            pid = a.order[(int64_t)g * 64 + lane];
+            sid = pid;
+        } else {
+            const int bpos = a.gb0[g] + lane;
+            cid = a.mode == 1 ? a.perm[a.gcen[g]] : a.gcen[g];
+            if (bpos < a.nseq) {
+                sid = a.perm[bpos];
+                pid = g * 64 + lane;          // output slot; a self pair scores 0
+                if (sid == cid) sid = -1;
+            }
+            cen = a.res + a.off[cid];
+            m = (int)(a.off[cid + 1] - a.off[cid]);
+        }
+        const int64_t so = sid >= 0 ? a.off[sid] : 0;
+        const int n = sid >= 0 ? (int)(a.off[sid + 1] - so) : 0;
+        const uint8_t *s = a.res + so;
+        // prefetch base: the set's first residue for an empty lane (a group
+        // that runs any column holds at least one residue)
+        const uint8_t *sq = n > 0 ? s : a.res;
+        int nmax = n;
+        if (a.mode == 0) {
+            nmax = a.gnmax[g];
+        } else {
+#pragma unroll
+            for (int sh = 1; sh < 64; sh <<= 1) nmax = max(nmax, __shfl_xor(nmax, sh));
+        }
+        m = __builtin_amdgcn_readfirstlane(m);        // same in every lane
+        nmax = __builtin_amdgcn_readfirstlane(nmax);  // same in every lane
+        const int nstrips = (m + kT - 1) / kT;
+        const int G = (nmax + 3) >> 2;
+        uint32_t *cw = TB ? a.codes + a.gcode_base[g] + lane * 8 : nullptr;
+        uint32_t *stage = stage_all + lane * 8;
+        BestCell best{0, 0x7fffffff, 0x7fffffff};
+        int hmax = 0;
+        for (int st = 0; st < nstrips; ++st) {
+            const int i0 = st * kT;
+            __syncthreads();
+            for (int x = lane; x < kAlphaMax * kT; x += 64) {
+                const int r = x / kT, t = x - r * kT;
+                int v = kNegProf;
+                if (r < a.alpha && i0 + t < m) v = (int)smat[(cen[i0 + t] & 31) * 32 + r] + goe;
+                prof[r * kPS + t] = v;
+            }
+            __syncthreads();
+            int hg[kT], e[kT];
+#pragma unroll
+            for (int t = 0; t < kT; ++t) { hg[t] = -goe; e[t] = 0; }
+            int diag0 = -goe;
+            // The first strip reads residues from the lane's sequence and
+            // leaves each column's code in its boundary cell (bits 27-31 of
+            // F*, which stays below 2^23 for lengths < 65536 and |scores| <
+            // 128); later strips get residue and boundary in one load.  A
+            // block of kB columns is fetched one block ahead into the other of
+            // two buffers, so the load latency overlaps a block of cells.  The
+            // loads are unconditional (indexes clamped into the lane's
+            // sequence and the group's boundary row) and so is the boundary
+            // store, which keeps the wait counts exact across blocks.  Every
+            // block is whole: columns past nmax (up to nmaxp, a multiple of kB)
+            // are padding columns as for a lane's columns past n, whose cells
+            // stay below an earlier cell of the lane and never win the end cell.
+            const int nlast = max(n - 1, 0);
+            const int nmaxp = (nmax + kB - 1) / kB * kB;
+            auto strip = [&](auto first_tag) {
+                constexpr bool FIRST = decltype(first_tag)::value;
+                auto fetch = [&](int j0, int2 (&bq)[kB]) {
+#pragma unroll
+                    for (int b = 0; b < kB; ++b) {
+                        const int j = min(j0 + b, nmaxp);
+                        if (FIRST) bq[b].x = (int)sq[min(j - 1, nlast)];
+                        else bq[b] = load_agent(bnd + (int64_t)(j - 1) * 64 + lane);
+                    }
+                };
+                auto block = [&](int j0, const int2 (&bc)[kB]) {
+#pragma unroll
+                    for (int b = 0; b < kB; ++b) {
+                        const int j = j0 + b;
+                        int upg, upf, r;
+                        if (FIRST) {
+                            upg = -goe;
+                            upf = 0;
+                            r = (j <= n) ? (bc[b].x & 31) : kPad;
+                        } else {
+                            upg = bc[b].x;
+                            upf = bc[b].y & kFMask;
+                            r = (int)((uint32_t)bc[b].y >> 27);
+                        }
+                        int diag = diag0;
+                        diag0 = upg;
+                        const int *prow = prof + r * kPS;
+                        int p[kT];
+#pragma unroll
+                        for (int t = 0; t < kT; ++t) p[t] = prow[t];
+                        uint32_t w0 = 0, w1 = 0;
+                        int colkey = 0;
+#pragma unroll
+                        for (int t = 0; t < kT; t += 2) {
+                            const int h0 = sw_cell<TB>(hg[t], e[t], diag, upg, upf, p[t], ge, goe,
+                                                       t < 8 ? w0 : w1);
+                            const int h1 = sw_cell<TB>(hg[t + 1], e[t + 1], diag, upg, upf, p[t + 1], ge, goe,
+                                                       t < 8 ? w0 : w1);
+                            if (ENDC) colkey = vmax3(colkey, (h0 << 5) | (31 - t), (h1 << 5) | (30 - t));
+                            else hmax = vmax3(hmax, h0, h1);
+                        }
+                        bnd[(int64_t)(j - 1) * 64 + lane] = make_int2(upg, upf | (r << 27));
+                        if (TB) {
+                            stage[2 * b] = w0;
+                            stage[2 * b + 1] = w1;
+                            if (b == kB - 1) {
+                                const uint4 lo = *reinterpret_cast<const uint4 *>(stage);
+                                const uint4 hi = *reinterpret_cast<const uint4 *>(stage + 4);
+                                uint4 *dst = reinterpret_cast<uint4 *>(cw + ((int64_t)st * G + ((j - 1) >> 2)) * 512);
+                                dst[0] = lo;
+                                dst[1] = hi;
+                            }
+                        }
+                        if (ENDC) {
+                            // later strips hold larger i: on equal H they win only with a smaller j
+                            const int ch = colkey >> 5;
+                            if (ch > 0 && (ch > best.h || (ch == best.h && j < best.j))) {
+                                best.h = ch;
+                                best.j = j;
+                                best.i = i0 + (31 - (colkey & 31));
+                            }
+                        }
+                    }
+                };
+                int2 bA[kB], bB[kB];
+                fetch(1, bA);
+                for (int j0 = 1; j0 <= nmaxp; j0 += 2 * kB) {
+                    fetch(j0 + kB, bB);
+                    block(j0, bA);
+                    if (j0 + kB > nmaxp) break;
+                    fetch(j0 + 2 * kB, bA);
+                    block(j0 + kB, bB);
+                }
+            };
+            if (nmax > 0) {
+                if (st == 0) strip(std::true_type{});
+                else strip(std::false_type{});
+            }
+        }
+        if (ENDC) hmax = best.h;
+        if (a.mode == 0) {
+            if (pid >= 0) {
+                a.score[pid] = hmax;
+                if (ENDC && a.endcell) {
+                    a.endcell[2 * pid] = best.h > 0 ? best.i + 1 : 0;
+                    a.endcell[2 * pid + 1] = best.h > 0 ? best.j : 0;
+                }
+            }
+        } else {
+            const int v = sid >= 0 ? hmax : 0;
+            if (a.score && pid >= 0) a.score[pid] = v;
+            if (a.mode == 1 && sid >= 0) atomicAdd(reinterpret_cast<unsigned long long *>(a.sums + sid), (unsigned long long)v);
+            int tot = v;
+#pragma unroll
+            for (int sh = 1; sh < 64; sh <<= 1) tot += __shfl_xor(tot, sh);
+            if (lane == 0) {
+                const int slot = a.mode == 1 ? cid : a.gslot[g];
+                atomicAdd(reinterpret_cast<unsigned long long *>(a.sums + slot), (unsigned long long)(int64_t)tot);
+            }
+        }
+    }
+}
+
+}  // namespace hk
