@@ -1277,10 +1277,25 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const 
 }
 
 // Center selection -----------------------------------------------------------
+// The packed 16-bit score-only strip kernel applies when no H can reach 2^14:
+// max S times the longest sequence stays below 16000 (gap costs small).
+// HALIGN_STRIP32=1 keeps the 32-bit kernel (tests of both paths).
+static bool strip16_ok(const Scoring &S, const halign_seqs *sq) {
+    const char *e = getenv("HALIGN_STRIP32");
+    if (e && atoi(e) != 0) return false;
+    int smax = 0;
+    for (int x = 0; x < S.alpha * S.alpha; ++x) smax = std::max(smax, (int)S.hmat[x]);
+    int64_t lmax = 0;
+    for (int k = 0; k < sq->n; ++k) lmax = std::max(lmax, sq->offsets_host[k + 1] - sq->offsets_host[k]);
+    return S.goe <= 4096 && S.ge <= 4096 && (int64_t)smax * lmax + S.goe < 16000;
+}
+
+// Groups: one center, 64 partners (32-bit kernel) or 128 (16-bit kernel).
 static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, int mode,
                       const std::vector<int32_t> &gcen, const std::vector<int32_t> &gb0,
                       const std::vector<int32_t> &perm, const std::vector<int32_t> &gslot, int64_t *sums,
-                      int32_t *score, hipStream_t st, int nperm = -1) {
+                      int32_t *score, hipStream_t st, int nperm = -1, bool p16 = false) {
+    if (p16 && (score || mode == 0)) return fail(HALIGN_E_INVALID, "16-bit strip kernel: score-only center selection");
     const int ng = (int)gcen.size();
     if (ng == 0) return HALIGN_OK;
     PlanBuilder pb;
@@ -1301,7 +1316,7 @@ static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, 
     const int64_t *oh = sq->offsets_host;
     for (int k = 0; k < sq->n; ++k) nmax_all = std::max(nmax_all, (int)(oh[k + 1] - oh[k]));
     const int grid = std::max(1, std::min(ng, ctx->num_cu * 16));
-    RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * strip_cols(nmax_all) * 8));
+    RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * strip_cols(nmax_all) * (p16 ? 16 : 8)));
     RCHK(grow(ctx, ctx->counter, 256));
     RCHK(launch_fill((uint32_t *)ctx->counter.p, 0u, 1, st));
     hk::InterArgs a{};
@@ -1325,7 +1340,8 @@ static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, 
     a.bstride = (int64_t)64 * strip_cols(nmax_all);
     ctx->last_stats[0] = 0;
     RCHK(record(ctx, ctx->ev[0], st));
-    launch_inter(a, false, false, grid, st);
+    if (p16) hipLaunchKernelGGL(hk::sw_inter16_kernel, dim3(grid), dim3(64), 0, st, a);
+    else launch_inter(a, false, false, grid, st);
     HCHK(hipGetLastError());
     RCHK(record(ctx, ctx->ev[1], st));
     RCHK(record(ctx, ctx->ev[2], st));
@@ -1371,15 +1387,17 @@ int halign_center_exact(halign_ctx *ctx, const halign_scoring *sc, const halign_
     RCHK(validate_now(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
     RCHK(launch_fill((uint32_t *)sums, 0u, 2 * (int64_t)N, st));
     std::vector<int32_t> perm = length_perm(seqs), gcen, gb0, gslot;
+    const bool p16 = strip16_ok(S, seqs);
+    const int step = p16 ? 128 : 64;
     // all pairs a' < b' in length order: the longer sequence is the lane's,
     // the shorter one the group's center
     for (int a = 0; a < N; ++a)
-        for (int b = a + 1; b < N; b += 64) {
+        for (int b = a + 1; b < N; b += step) {
             gcen.push_back(a);
             gb0.push_back(b);
         }
     if (gcen.size() > (size_t)INT32_MAX / 64) return fail(HALIGN_E_UNSUPPORTED, "too many pairs");
-    RCHK(run_groups(ctx, S, seqs, 1, gcen, gb0, perm, gslot, sums, nullptr, st));
+    RCHK(run_groups(ctx, S, seqs, 1, gcen, gb0, perm, gslot, sums, nullptr, st, -1, p16));
     if (center_host) RCHK(argmax_sums(ctx, sums, nullptr, N, center_host, st));
     return HALIGN_OK;
 }
@@ -1402,13 +1420,15 @@ int halign_center_judge(halign_ctx *ctx, const halign_scoring *sc, const halign_
     RCHK(validate_now(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
     RCHK(launch_fill((uint32_t *)sums, 0u, 2 * (int64_t)ncand, st));
     std::vector<int32_t> perm = length_perm(seqs), gcen, gb0, gslot;
+    const bool p16 = strip16_ok(S, seqs);
+    const int step = p16 ? 128 : 64;
     for (int q = 0; q < ncand; ++q)
-        for (int b = 0; b < N; b += 64) {
+        for (int b = 0; b < N; b += step) {
             gcen.push_back(hc[q]);
             gb0.push_back(b);
             gslot.push_back(q);
         }
-    RCHK(run_groups(ctx, S, seqs, 2, gcen, gb0, perm, gslot, sums, nullptr, st));
+    RCHK(run_groups(ctx, S, seqs, 2, gcen, gb0, perm, gslot, sums, nullptr, st, -1, p16));
     if (center_host) RCHK(argmax_sums(ctx, sums, hc.data(), ncand, center_host, st));
     return HALIGN_OK;
 }

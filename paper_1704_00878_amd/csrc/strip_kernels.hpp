@@ -253,4 +253,185 @@ sw_inter_kernel(InterArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Packed 16-bit score-only strip kernel (center selection: modes 1 and 2).
+// Each lane scores two pairs of the group at once, pair A (partner gb0+lane)
+// in the low and pair B (partner gb0+64+lane) in the high half of every
+// register, with v_pk_* 16-bit integer ops: a group holds 128 partners.
+// E and F are carried unclamped (they never fall below -(go+ge), since
+// E(i,j) >= H(i,j-1) - goe), and H = max(H(i-1,j-1) + S, E, F, 0):
+//   eext = e - ge; en = max(eext, Hg); fext = F - ge; fn = max(fext, Hg_up);
+//   hd = Hg_diag + P; h = max(max(hd, en), max(fn, 0)); Hg = h - goe
+// that is 10 packed ops per two cells with the running maximum.  The host
+// uses this kernel only when every H stays below 2^14 (max S * longest
+// sequence < 16000), so that no value wraps and a padding profile entry of
+// -2^14 can never be a source.  The profile (int16 [r][16]) of the two
+// lanes' residues is interleaved into (A, B) pairs with v_perm_b32.
+// Strip boundaries per lane and column: packed Hg and packed F (int2) and the
+// two residue codes (uint16), written by every strip and read by the next one
+// with agent-scope loads (as in the 32-bit kernel).
+// ---------------------------------------------------------------------------
+typedef short pk16 __attribute__((ext_vector_type(2)));
+constexpr int kNegProf16 = -(1 << 14);
+
+__device__ __forceinline__ pk16 as_pk(uint32_t x) { return __builtin_bit_cast(pk16, x); }
+__device__ __forceinline__ uint32_t as_u(pk16 x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ pk16 pmax(pk16 a, pk16 b) { return __builtin_elementwise_max(a, b); }
+
+__global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
+sw_inter16_kernel(InterArgs a) {
+    __shared__ uint32_t prof[kAlphaMax * 8];   // int16 [r][16], 8 words per residue
+    __shared__ int8_t smat[kAlphaMax * kAlphaMax];
+    __shared__ int s_next;
+    const int lane = threadIdx.x;
+    for (int x = lane; x < kAlphaMax * kAlphaMax; x += 64) {
+        const int r = x >> 5, q = x & 31;
+        smat[x] = (r < a.alpha && q < a.alpha) ? a.mat[r * a.alpha + q] : (int8_t)0;
+    }
+    // per workgroup: int2 (packed Hg, packed F) per lane and column, then the
+    // lane's two residue codes (uint16) per column
+    int2 *bnd = reinterpret_cast<int2 *>(reinterpret_cast<int4 *>(a.bound) + (int64_t)blockIdx.x * a.bstride);
+    uint16_t *bres = reinterpret_cast<uint16_t *>(bnd + a.bstride);
+    const pk16 ge2 = pk16{(short)a.ge, (short)a.ge};
+    const pk16 goe2 = pk16{(short)a.goe, (short)a.goe};
+    const pk16 zero2 = pk16{0, 0};
+    const pk16 init2 = pk16{(short)-a.goe, (short)-a.goe};
+    for (;;) {
+        __syncthreads();
+        if (lane == 0) s_next = atomicAdd(a.counter, 1);
+        __syncthreads();
+        const int g = __builtin_amdgcn_readfirstlane(s_next);
+        if (g >= a.ngroups) break;
+        const int cid = a.mode == 1 ? a.perm[a.gcen[g]] : a.gcen[g];
+        const int pa = a.gb0[g] + lane, pbp = pa + 64;
+        int sa = pa < a.nseq ? a.perm[pa] : -1;
+        int sb = pbp < a.nseq ? a.perm[pbp] : -1;
+        sa = sa == cid ? -1 : sa;   // a self pair scores 0
+        sb = sb == cid ? -1 : sb;
+        const uint8_t *cen = a.res + a.off[cid];
+        const int m = __builtin_amdgcn_readfirstlane((int)(a.off[cid + 1] - a.off[cid]));
+        const int64_t soa = sa >= 0 ? a.off[sa] : 0, sob = sb >= 0 ? a.off[sb] : 0;
+        const int na = sa >= 0 ? (int)(a.off[sa + 1] - soa) : 0;
+        const int nb = sb >= 0 ? (int)(a.off[sb + 1] - sob) : 0;
+        // prefetch bases: the set's first residue for an empty lane (a group
+        // that runs any column holds at least one residue)
+        const uint8_t *qa = na > 0 ? a.res + soa : a.res;
+        const uint8_t *qb = nb > 0 ? a.res + sob : a.res;
+        int nmax = max(na, nb);
+#pragma unroll
+        for (int sh = 1; sh < 64; sh <<= 1) nmax = max(nmax, __shfl_xor(nmax, sh));
+        nmax = __builtin_amdgcn_readfirstlane(nmax);
+        const int nstrips = (m + kT - 1) / kT;
+        const int nmaxp = (nmax + kB - 1) / kB * kB;
+        const int la = max(na - 1, 0), lb = max(nb - 1, 0);
+        pk16 hmax = zero2;
+        for (int st = 0; st < nstrips && nmax > 0; ++st) {
+            const int i0 = st * kT;
+            __syncthreads();
+            for (int x = lane; x < kAlphaMax * 8; x += 64) {
+                const int r = x >> 3, t = 2 * (x & 7);
+                int v0 = kNegProf16, v1 = kNegProf16;
+                if (r < a.alpha && i0 + t < m) v0 = (int)smat[(cen[i0 + t] & 31) * 32 + r] + a.goe;
+                if (r < a.alpha && i0 + t + 1 < m) v1 = (int)smat[(cen[i0 + t + 1] & 31) * 32 + r] + a.goe;
+                prof[x] = (uint32_t)(v0 & 0xffff) | ((uint32_t)v1 << 16);
+            }
+            __syncthreads();
+            pk16 hg[kT], e[kT];
+#pragma unroll
+            for (int t = 0; t < kT; ++t) { hg[t] = init2; e[t] = init2; }
+            pk16 diag0 = init2;
+            auto strip = [&](auto first_tag) {
+                constexpr bool FIRST = decltype(first_tag)::value;
+                auto fetch = [&](int j0, int4 (&bq)[kB]) __attribute__((always_inline)) {
+#pragma unroll
+                    for (int b = 0; b < kB; ++b) {
+                        const int j = min(j0 + b, nmaxp);
+                        if (FIRST) {
+                            bq[b].x = (int)qa[min(j - 1, la)];
+                            bq[b].y = (int)qb[min(j - 1, lb)];
+                        } else {
+                            const int2 v = load_agent(bnd + (int64_t)(j - 1) * 64 + lane);
+                            const uint32_t rw = __hip_atomic_load(
+                                reinterpret_cast<const uint32_t *>(bres + (int64_t)(j - 1) * 64 + (lane & ~1)),
+                                __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                            bq[b] = make_int4(v.x, v.y, (int)(rw >> (16 * (lane & 1))), 0);
+                        }
+                    }
+                };
+                auto block = [&](int j0, const int4 (&bc)[kB]) {
+#pragma unroll
+                    for (int b = 0; b < kB; ++b) {
+                        const int j = j0 + b;
+                        pk16 upg, upf;
+                        int ra, rb;
+                        if (FIRST) {
+                            upg = init2;
+                            upf = init2;
+                            ra = (j <= na) ? (bc[b].x & 31) : kPad;
+                            rb = (j <= nb) ? (bc[b].y & 31) : kPad;
+                        } else {
+                            upg = as_pk((uint32_t)bc[b].x);
+                            upf = as_pk((uint32_t)bc[b].y);
+                            ra = bc[b].z & 255;
+                            rb = (bc[b].z >> 8) & 255;
+                        }
+                        pk16 diag = diag0;
+                        diag0 = upg;
+                        const uint4 *pa4 = reinterpret_cast<const uint4 *>(prof + ra * 8);
+                        const uint4 *pb4 = reinterpret_cast<const uint4 *>(prof + rb * 8);
+                        const uint4 a0 = pa4[0], a1 = pa4[1], b0 = pb4[0], b1 = pb4[1];
+                        const uint32_t wa[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
+                        const uint32_t wb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+#pragma unroll
+                        for (int k = 0; k < 8; ++k) {
+#pragma unroll
+                            for (int h = 0; h < 2; ++h) {
+                                const int t = 2 * k + h;
+                                const pk16 p = as_pk(__builtin_amdgcn_perm(wb[k], wa[k], h ? 0x07060302u : 0x05040100u));
+                                const pk16 en = pmax(e[t] - ge2, hg[t]);
+                                const pk16 fn = pmax(upf - ge2, upg);
+                                const pk16 hd = diag + p;
+                                const pk16 hh = pmax(pmax(hd, en), pmax(fn, zero2));
+                                hmax = pmax(hmax, hh);
+                                diag = hg[t];
+                                hg[t] = hh - goe2;
+                                e[t] = en;
+                                upg = hg[t];
+                                upf = fn;
+                            }
+                        }
+                        bnd[(int64_t)(j - 1) * 64 + lane] = make_int2((int)as_u(upg), (int)as_u(upf));
+                        bres[(int64_t)(j - 1) * 64 + lane] = (uint16_t)(ra | (rb << 8));
+                    }
+                };
+                int4 bA[kB], bB[kB];
+                fetch(1, bA);
+                for (int j0 = 1; j0 <= nmaxp; j0 += 2 * kB) {
+                    fetch(j0 + kB, bB);
+                    block(j0, bA);
+                    if (j0 + kB > nmaxp) break;
+                    fetch(j0 + 2 * kB, bA);
+                    block(j0 + kB, bB);
+                }
+            };
+            if (st == 0) strip(std::true_type{});
+            else strip(std::false_type{});
+        }
+        const uint32_t hm = as_u(hmax);
+        const int va = sa >= 0 ? (int)(hm & 0xffff) : 0;
+        const int vb = sb >= 0 ? (int)(hm >> 16) : 0;
+        if (a.mode == 1) {
+            if (sa >= 0) atomicAdd(reinterpret_cast<unsigned long long *>(a.sums + sa), (unsigned long long)va);
+            if (sb >= 0) atomicAdd(reinterpret_cast<unsigned long long *>(a.sums + sb), (unsigned long long)vb);
+        }
+        int tot = va + vb;
+#pragma unroll
+        for (int sh = 1; sh < 64; sh <<= 1) tot += __shfl_xor(tot, sh);
+        if (lane == 0) {
+            const int slot = a.mode == 1 ? cid : a.gslot[g];
+            atomicAdd(reinterpret_cast<unsigned long long *>(a.sums + slot), (unsigned long long)(int64_t)tot);
+        }
+    }
+}
+
 }  // namespace hk

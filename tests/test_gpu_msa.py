@@ -111,7 +111,33 @@ def test_merge_and_rows_calls(H, ctx):
     assert (msa.cpu().numpy() == ref["msa"]).all()
 
 
-def test_center_exact(H, ctx):
+# center selection runs the packed 16-bit strip kernel when scores fit, else
+# the 32-bit one; HALIGN_STRIP32=1 forces the 32-bit kernel
+STRIPS = [None, "1"]
+
+
+@pytest.fixture(params=STRIPS, ids=["strip16", "strip32"])
+def strip(request, monkeypatch):
+    if request.param:
+        monkeypatch.setenv("HALIGN_STRIP32", request.param)
+    else:
+        monkeypatch.delenv("HALIGN_STRIP32", raising=False)
+    return request.param
+
+
+def _mixed_set(n, seed):
+    """Family sequences plus an empty one, a 1-residue one and a lone
+    unrelated one: spans several 128-partner groups and 16-row strips."""
+    base = synth.generate("plain64", n_seqs=n, seed=seed)
+    rng = np.random.default_rng(seed)
+    extra = [np.zeros(0, np.uint8), np.array([4], np.uint8), rng.integers(0, 20, 97).astype(np.uint8)]
+    seqs = [base.seq(k) for k in range(base.n)]
+    for q, x in enumerate(extra):
+        seqs.insert(37 * q + 5, x)
+    return synth.SeqSet.from_list(seqs)
+
+
+def test_center_exact(H, ctx, strip):
     import torch
     seqs = synth.generate("plain64", n_seqs=24, seed=9)
     best, sums = oracle.center_exact(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets)
@@ -131,7 +157,47 @@ def test_center_exact_plain64_and_msa(H, ctx):
     assert (got == ref["msa"]).all()
 
 
-def test_center_judge(H, ctx):
+def test_center_exact_groups(H, ctx, strip):
+    import torch
+    seqs = _mixed_set(200, 12)
+    best, sums = oracle.center_exact(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets)
+    ds = H.DeviceSeqs(seqs)
+    d = torch.empty(seqs.n, dtype=torch.int64, device="cuda")
+    c = H.halign_center_exact(ctx, H.Scoring(), ds, d)
+    assert c == best
+    assert (d.cpu().numpy() == sums).all()
+
+
+def test_center_judge_groups(H, ctx, strip):
+    import torch
+    seqs = _mixed_set(200, 13)
+    cand = [5, 0, 42, 79, 150, 202, 6]   # includes the empty (5) and 1-residue (42) sequences
+    jb, js = oracle.center_judge(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets, cand)
+    ds = H.DeviceSeqs(seqs)
+    ct = torch.tensor(cand, dtype=torch.int32, device="cuda")
+    d = torch.empty(len(cand), dtype=torch.int64, device="cuda")
+    c = H.halign_center_judge(ctx, H.Scoring(), ds, ct, d)
+    assert c == jb
+    assert (d.cpu().numpy() == js).all()
+
+
+def test_center_exact_long_falls_back(H, ctx):
+    """11 x 1500 >= 16000: the 16-bit bound fails and the 32-bit kernel runs."""
+    import torch
+    rng = np.random.default_rng(3)
+    root = rng.integers(0, 20, 1500).astype(np.uint8)
+    mut = root.copy()
+    mut[rng.integers(0, 1500, 200)] = rng.integers(0, 20, 200).astype(np.uint8)
+    seqs = synth.SeqSet.from_list([root, mut, root[:700], rng.integers(0, 20, 300).astype(np.uint8)])
+    best, sums = oracle.center_exact(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets)
+    ds = H.DeviceSeqs(seqs)
+    d = torch.empty(seqs.n, dtype=torch.int64, device="cuda")
+    c = H.halign_center_exact(ctx, H.Scoring(), ds, d)
+    assert c == best
+    assert (d.cpu().numpy() == sums).all()
+
+
+def test_center_judge(H, ctx, strip):
     import torch
     seqs = synth.generate("plain64", n_seqs=40, seed=4)
     cand = [5, 0, 17, 39, 22]
