@@ -85,18 +85,32 @@ def cpu_baseline(seqs, center: int, budget_s: float = 20.0):
                       f"{reps} pass(es) ({cells:.3e} cells, {dt:.1f} s, one thread per core)"}
 
 
+# kernel -> the sources its counter records are tied to
+KERNEL_SOURCES = {"sw_stream_kernel": ["sw_kernels.hpp"],
+                  "sw_stream16_kernel": ["stream16_kernels.hpp", "sw_kernels.hpp", "strip_kernels.hpp"]}
+
+
+def kernel_source_sha(kernel: str):
+    """sha256 over the kernel's source files (concatenated), or None."""
+    import hashlib
+    h = hashlib.sha256()
+    try:
+        for f in KERNEL_SOURCES.get(kernel, []):
+            h.update(open(os.path.join(ROOT, "paper_1704_00878_amd", "csrc", f), "rb").read())
+    except OSError:
+        return None
+    return h.hexdigest() if kernel in KERNEL_SOURCES else None
+
+
 def counter_record(kernel: str, workload: str, plan: dict):
     """HBM counters of the forward kernel taken with rocprofv3 --pmc on this
     workload and plan (rows per lane, lanes per stream), from the profiles/
     summaries; None unless they were taken on the kernel source as it is now
-    (sha256 of csrc/sw_kernels.hpp)."""
+    (sha256 of its source files)."""
     import glob
-    import hashlib
     import re
-    src = os.path.join(ROOT, "paper_1704_00878_amd", "csrc", "sw_kernels.hpp")
-    try:
-        sha = hashlib.sha256(open(src, "rb").read()).hexdigest()
-    except OSError:
+    sha = kernel_source_sha(kernel)
+    if sha is None:
         return None
     for path in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
         for m in re.finditer(r"<!-- record (\{.*?\}) -->", open(path).read()):
@@ -338,7 +352,8 @@ def main():
 
     # dominant kernel roofline: integer VALU, fixed op model
     achieved = cells * OPS_PER_CELL_TB / (fwd_ms * 1e-3) / 1e12
-    kname = "sw_stream_kernel" if st["route"] == 0 else "sw_inter_kernel"
+    kname = ("sw_stream16_kernel" if plan.get("packed") else "sw_stream_kernel") if st["route"] == 0 \
+        else "sw_inter_kernel"
     rec = counter_record(kname, args.workload, plan)
     traffic = clock = None
     if rec is not None:

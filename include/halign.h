@@ -115,14 +115,16 @@ int  halign_ctx_last_stats(const halign_ctx *ctx, int64_t *stats_host /*[4]: cel
  * bucket of (center length, batch size, mean length, traceback) times the
  * candidate plans -- wavefront streams of 64 lanes with R or R+1 center rows
  * per lane and one or two streams per resident wave slot, streams of 32 or 16
- * lanes with up to 16 rows per lane, or the one-pair-per-lane kernel -- on
- * the batch (a strided sample of 65,536 pairs for batches above 4e10 cells,
- * with the stream count scaled to keep the pairs per stream) in the call's
- * own mode,
- * and keeps the fastest; results do not depend on the plan.
+ * lanes with up to 16 rows per lane, the same in packed 16-bit arithmetic
+ * with two streams per lane group (traceback only, when no score can reach
+ * 2^14), or the one-pair-per-lane kernel -- on the batch (a strided sample of
+ * 65,536 pairs for batches above 4e10 cells, with the stream count scaled to
+ * keep the pairs per stream) in the call's own mode, and keeps the fastest;
+ * results do not depend on the plan.
  * HALIGN_TUNE_CACHE=<path> persists choices (malformed lines are ignored).
  * halign_ctx_last_plan reports {route, R, streams multiplier, lanes per
- * stream} of the last call (route -1 / R 0: defaults).  HALIGN_PROGRESS=1 prints one line on
+ * stream, packed (0/1: whether the last batch ran the packed kernel)} of the
+ * last call (route -1 / R 0: defaults).  HALIGN_PROGRESS=1 prints one line on
  * stderr as each chunk of a chunked batch completes. */
 int  halign_ctx_set_autotune(halign_ctx *ctx, int enable);
 /* halign_msa runs its pairwise batch with HALIGN_GRAPH when enabled (the
@@ -130,7 +132,7 @@ int  halign_ctx_set_autotune(halign_ctx *ctx, int enable);
  * replays. */
 int  halign_ctx_set_graph(halign_ctx *ctx, int enable);
 int  halign_ctx_graph_launches(const halign_ctx *ctx, int64_t *n_host);
-int  halign_ctx_last_plan(const halign_ctx *ctx, int32_t *plan_host /*[4]*/);
+int  halign_ctx_last_plan(const halign_ctx *ctx, int32_t *plan_host /*[5]*/);
 
 /* ---- step a1: encode ASCII to residue codes (upper/lower case; U->C,
  * O->K, other letters -> X).  ascii and codes may alias. */

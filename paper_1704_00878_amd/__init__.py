@@ -219,9 +219,9 @@ class Context:
         _check(lib().halign_ctx_set_autotune(self.h, 1 if on else 0))
 
     def last_plan(self):
-        a = (ctypes.c_int32 * 4)()
+        a = (ctypes.c_int32 * 5)()
         _check(lib().halign_ctx_last_plan(self.h, a))
-        return dict(route=a[0], R=a[1], streams=a[2], lanes=a[3])
+        return dict(route=a[0], R=a[1], streams=a[2], lanes=a[3], packed=a[4])
 
     def set_graph(self, on: bool):
         _check(lib().halign_ctx_set_graph(self.h, 1 if on else 0))

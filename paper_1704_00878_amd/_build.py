@@ -9,7 +9,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB_PATH = os.path.join(HERE, "libhalign.so")
 SOURCES = ["halign.hip"]
-DEPS = ["halign.hip", "sw_kernels.hpp", "strip_kernels.hpp", "walk_kernels.hpp", "msa_kernels.hpp", "mlp_kernels.hpp"]
+DEPS = ["halign.hip", "sw_kernels.hpp", "strip_kernels.hpp", "walk_kernels.hpp", "stream16_kernels.hpp", "msa_kernels.hpp", "mlp_kernels.hpp"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 

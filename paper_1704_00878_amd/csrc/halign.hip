@@ -25,6 +25,7 @@
 #include "sw_kernels.hpp"
 #include "strip_kernels.hpp"
 #include "walk_kernels.hpp"
+#include "stream16_kernels.hpp"
 #include "mlp_kernels.hpp"
 
 namespace {
@@ -71,6 +72,7 @@ struct halign_ctx {
     size_t cap = 0;          // workspace cap for codes + boundary rows (0 = none)
     int num_cu = 256;
     size_t lds_max = 65536;
+    int last_pk = 0;          // the last batch ran the packed 16-bit wavefront kernel
     // device scratch
     DevBuf codes, bound, plan, counter, pairbuf, msabuf, spbuf, sbuf;
     DevBuf mlp[10];          // learned-center scratch (features, activations, gradients, moments)
@@ -95,8 +97,8 @@ struct halign_ctx {
     int64_t graph_launches = 0;
     int autotune = 0;         // 1: tune route / rows per lane / stream count per bucket
     int progress = 0;         // 1: a line on stderr after each chunk of a chunked batch
-    std::array<int, 4> last_tune = {-1, 0, 1, 64};
-    std::map<std::string, std::array<int, 4>> tuned;   // bucket -> {route, R, stream multiplier, lanes per stream}
+    std::array<int, 5> last_tune = {-1, 0, 1, 64, 0};
+    std::map<std::string, std::array<int, 5>> tuned;   // bucket -> {route, R, stream multiplier, lanes per stream, packed}
     std::string tune_file;    // optional cache file (HALIGN_TUNE_CACHE)
     int *flag_host = nullptr; // pinned: largest residue code of the last validated call
     int flag_alpha = 0;       // alphabet that value is checked against (0 = nothing pending)
@@ -294,6 +296,38 @@ void launch_stream(int R, int LS, const hk::StreamArgs &a, bool tb, bool endc, b
     }
 }
 
+// Packed 16-bit wavefront kernel (traceback with end cells only): 32- and
+// 16-lane streams, R = 2..16.
+bool stream16_supported(int R, int LS) { return (LS == 32 || LS == 16) && R >= 2 && R <= 16; }
+
+template <int R>
+void launch_stream16_R(int LS, const hk::StreamArgs &a, int grid, size_t lds, hipStream_t st) {
+    if constexpr (R >= 2) {
+        if (LS == 32) hipLaunchKernelGGL((hk::sw_stream16_kernel<R, 32>), dim3(grid), dim3(512), lds, st, a);
+        else hipLaunchKernelGGL((hk::sw_stream16_kernel<R, 16>), dim3(grid), dim3(512), lds, st, a);
+    }
+}
+
+void launch_stream16(int R, int LS, const hk::StreamArgs &a, int grid, size_t lds, hipStream_t st) {
+    switch (R) {
+        case 2: launch_stream16_R<2>(LS, a, grid, lds, st); break;
+        case 3: launch_stream16_R<3>(LS, a, grid, lds, st); break;
+        case 4: launch_stream16_R<4>(LS, a, grid, lds, st); break;
+        case 5: launch_stream16_R<5>(LS, a, grid, lds, st); break;
+        case 6: launch_stream16_R<6>(LS, a, grid, lds, st); break;
+        case 7: launch_stream16_R<7>(LS, a, grid, lds, st); break;
+        case 8: launch_stream16_R<8>(LS, a, grid, lds, st); break;
+        case 9: launch_stream16_R<9>(LS, a, grid, lds, st); break;
+        case 10: launch_stream16_R<10>(LS, a, grid, lds, st); break;
+        case 11: launch_stream16_R<11>(LS, a, grid, lds, st); break;
+        case 12: launch_stream16_R<12>(LS, a, grid, lds, st); break;
+        case 13: launch_stream16_R<13>(LS, a, grid, lds, st); break;
+        case 14: launch_stream16_R<14>(LS, a, grid, lds, st); break;
+        case 15: launch_stream16_R<15>(LS, a, grid, lds, st); break;
+        default: launch_stream16_R<16>(LS, a, grid, lds, st); break;
+    }
+}
+
 // Boundary-row columns per strip-kernel lane: the longest sequence rounded
 // up to whole prefetch blocks.
 int64_t strip_cols(int nmax_all) {
@@ -325,6 +359,7 @@ struct Tune {
     int smul = 1;     // streams per resident wave slot
     double scale = 1; // stream count scale (a sample keeps the batch's pairs per stream)
     int LS = 0;       // lanes per stream (0: 64)
+    int pk = 0;       // 1: packed 16-bit wavefront kernel (two streams per lane group)
 };
 
 int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq,
@@ -382,18 +417,31 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             passes = ps;
         }
     }
+    // packed 16-bit wavefront kernel: asked for by the tuner (or the test knob
+    // HALIGN_STREAM_PACK=1 with the lanes knob), traceback with end cells only,
+    // and only when no H can reach 2^14 and the gap costs are small
+    bool pk = false;
+    {
+        const char *e = getenv("HALIGN_STREAM_PACK");
+        const bool want = tune.R > 0 ? tune.pk > 0 : (e && atoi(e) != 0);
+        const bool fits = p16 && tb && endc && (int64_t)smax * std::min(m, nlong) < 16000 && S.goe <= 256 &&
+                          S.ge <= 256;
+        pk = want && fits && route == kRouteIntra && stream16_supported(R, LS);
+    }
     const int W = (R + 7) / 8, NS = 64 / LS;
+    const int WQ = pk ? (R + 3) / 4 : W;   // code words per step
     const size_t prof_bytes =
         p16 ? (size_t)(S.alpha + 1) * LS * 16 * W : (size_t)hk::kAlphaMax * LS * R * 4;
-    const size_t lds_stream = prof_bytes + (tb ? (size_t)8 * 512 * 4 * W : 0);
+    const size_t lds_stream = prof_bytes + (tb ? (pk ? (size_t)8 * 256 * 4 * WQ : (size_t)8 * 512 * 4 * W) : 0);
     if (route == kRouteIntra && lds_stream > ctx->lds_max) route = kRouteInter;
     ctx->last_stats[2] = route;
+    ctx->last_pk = pk ? 1 : 0;
 
     // chunk the pairs so that codes + boundary rows fit the cap
     const size_t cap = ctx->cap ? ctx->cap : (size_t)1 << 62;
     std::vector<std::pair<int, int>> chunks;  // [lo, hi) in pids
     const size_t intra_bytes =
-        (tb ? (size_t)passes * LS * 4 * W * ((size_t)sum_len + (size_t)(LS + 8) * (size_t)np) : 0) +
+        (tb ? (size_t)passes * LS * 4 * WQ * ((size_t)sum_len + (size_t)(LS + 8) * (size_t)np) : 0) +
         (size_t)(passes - 1) * 8 * (size_t)sum_len;
     if (route == kRouteIntra && intra_bytes <= cap) {
         chunks.push_back({0, np});
@@ -406,7 +454,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             size_t b = 0;
             bool boundary = true;
             if (route == kRouteIntra) {
-                b = (tb ? (size_t)passes * (n + LS + 8) * LS * 4 * W : 0) + (size_t)(passes - 1) * n * 8;
+                b = (tb ? (size_t)passes * (n + LS + 8) * LS * 4 * WQ : 0) + (size_t)(passes - 1) * n * 8;
             } else {
                 boundary = (x - lo) % 64 == 0;
                 b = (boundary && tb) ? (size_t)nst * ((n + 3) / 4) * 512 * 4 : 0;  // group charged by its longest
@@ -453,7 +501,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             for (int x = hi - 1; x >= lo && plen[x] == 0; --x) ++nonempty;
             nonempty = cn - nonempty;   // empty pairs sort last
             const int wg_per_cu = std::max(1, std::min(4, (int)(ctx->lds_max / lds_stream)));
-            const int resident = ctx->num_cu * wg_per_cu * 8 * NS * std::max(1, tune.smul);
+            const int resident = ctx->num_cu * wg_per_cu * 8 * NS * std::max(1, tune.smul) * (pk ? 2 : 1);
             nstreams = std::max(1, std::min(nonempty, (int)std::max(1.0, resident * tune.scale)));
             if (const char *e = getenv("HALIGN_MAX_STREAMS")) {   // test knob: many pairs per stream
                 const int cap_s = atoi(e);
@@ -510,6 +558,19 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                 col += scols[s];
                 h_scb[s] = (int64_t)code_words;
                 h_sbb[s] = (int64_t)bound_elems;
+                if (pk) {
+                    // stream pair (s, s+1) shares the tiles and boundary rows of a
+                    // lane group, sized by the longer stream
+                    if (s & 1) {
+                        h_scb[s] = h_scb[s - 1];
+                        h_sbb[s] = h_sbb[s - 1];
+                        continue;
+                    }
+                    const int64_t cq = std::max(scols[s], s + 1 < nstreams ? scols[s + 1] : (int64_t)0);
+                    if (tb) code_words += (size_t)passes * ((cq + LS - 1 + 7) / 8) * LS * 8 * WQ;
+                    if (passes > 1) bound_elems += (size_t)(passes - 1) * cq;
+                    continue;
+                }
                 if (tb) code_words += (size_t)passes * ((scols[s] + LS - 1 + 7) / 8) * LS * 8 * W;
                 if (passes > 1) bound_elems += (size_t)(passes - 1) * scols[s];
             }
@@ -597,7 +658,8 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             a.scbase = (const int64_t *)(dplan + o_scb);
             a.bound = (int2 *)ctx->bound.p;
             a.sbbase = (const int64_t *)(dplan + o_sbb);
-            launch_stream(R, LS, a, tb, endc, p16, ((nstreams + NS - 1) / NS + 7) / 8, lds_stream, st);
+            if (pk) launch_stream16(R, LS, a, (((nstreams + 1) / 2 + NS - 1) / NS + 7) / 8, lds_stream, st);
+            else launch_stream(R, LS, a, tb, endc, p16, ((nstreams + NS - 1) / NS + 7) / 8, lds_stream, st);
             HCHK(hipGetLastError());
             RCHK(record(ctx, ctx->ev[1], st));
             hipLaunchKernelGGL(hk::decode_keys_kernel, dim3(grid_for(nslots, 256, 1 << 30)), dim3(256), 0, st,
@@ -665,7 +727,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             w.ccol = strip_plan ? (const int32_t *)(dplan + o_ccol) : nullptr;
             w.R = R;
             w.lg_ls = LS == 64 ? 6 : (LS == 32 ? 5 : 4);
-            w.W = W;
+            w.W = WQ;
             w.kind = route == kRouteIntra ? 0 : 1;
             w.cells = out.cells;
             w.ins = out.ins;
@@ -676,11 +738,16 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             const dim3 wg(grid_for(cn, 64, 1 << 30));
             const bool cl = m <= hk::kWalkCenterLds;
             if (route == kRouteIntra) {
-                if (cl) hipLaunchKernelGGL((hk::walk_kernel<false, true>), wg, dim3(64), 0, st, w);
-                else hipLaunchKernelGGL((hk::walk_kernel<false, false>), wg, dim3(64), 0, st, w);
+                if (pk) {
+                    if (cl) hipLaunchKernelGGL((hk::walk_kernel<false, true, true>), wg, dim3(64), 0, st, w);
+                    else hipLaunchKernelGGL((hk::walk_kernel<false, false, true>), wg, dim3(64), 0, st, w);
+                } else {
+                    if (cl) hipLaunchKernelGGL((hk::walk_kernel<false, true, false>), wg, dim3(64), 0, st, w);
+                    else hipLaunchKernelGGL((hk::walk_kernel<false, false, false>), wg, dim3(64), 0, st, w);
+                }
             } else {
-                if (cl) hipLaunchKernelGGL((hk::walk_kernel<true, true>), wg, dim3(64), 0, st, w);
-                else hipLaunchKernelGGL((hk::walk_kernel<true, false>), wg, dim3(64), 0, st, w);
+                if (cl) hipLaunchKernelGGL((hk::walk_kernel<true, true, false>), wg, dim3(64), 0, st, w);
+                else hipLaunchKernelGGL((hk::walk_kernel<true, false, false>), wg, dim3(64), 0, st, w);
             }
             HCHK(hipGetLastError());
         }
@@ -728,18 +795,21 @@ void tune_load(halign_ctx *ctx) {
     while (std::getline(f, line)) {
         std::istringstream s(line);
         std::string key;
-        int r = -1, R = -1, sm = -1, ls = 64;
+        int r = -1, R = -1, sm = -1, ls = 64, pk = 0;
         if (!(s >> key >> r >> R >> sm)) continue;              // malformed: ignored
         if (!(s >> ls)) ls = 64;                                // lines without the lane count
-        if (r < 0 || r > 1 || R < 0 || R > 16 || sm < 1 || sm > 4 || (ls != 64 && ls != 32 && ls != 16)) continue;
-        ctx->tuned[key] = {r, R, sm, ls};
+        if (!(s >> pk)) pk = 0;                                 // lines without the packed flag
+        if (r < 0 || r > 1 || R < 0 || R > 16 || sm < 1 || sm > 4 || (ls != 64 && ls != 32 && ls != 16) || pk < 0 ||
+            pk > 1)
+            continue;
+        ctx->tuned[key] = {r, R, sm, ls, pk};
     }
 }
 
-void tune_save(halign_ctx *ctx, const std::string &key, const std::array<int, 4> &v) {
+void tune_save(halign_ctx *ctx, const std::string &key, const std::array<int, 5> &v) {
     if (ctx->tune_file.empty()) return;
     std::ofstream f(ctx->tune_file, std::ios::app);
-    if (f) f << key << " " << v[0] << " " << v[1] << " " << v[2] << " " << v[3] << "\n";
+    if (f) f << key << " " << v[0] << " " << v[1] << " " << v[2] << " " << v[3] << " " << v[4] << "\n";
 }
 
 int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq, bool tb,
@@ -753,6 +823,7 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
         best->R = it->second[1];
         best->smul = it->second[2];
         best->LS = it->second[3];
+        best->pk = it->second[4];
         return HALIGN_OK;
     }
     // the batch itself (up to 4e10 cells: a few tens of ms per candidate), or a
@@ -775,6 +846,9 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
         const int ps = std::max(1, (m + ls * 16 - 1) / (ls * 16));
         const int r = std::max(2, (m + ls * ps - 1) / (ls * ps));
         cands.push_back({kRouteIntra, r, 1, scale, ls});
+        // the packed 16-bit kernel on the same geometry (run_batch falls back to
+        // the 32-bit one where it does not apply)
+        if (tb && endc) cands.push_back({kRouteIntra, r, 1, scale, ls, 1});
     }
     cands.push_back({kRouteInter, 0, 1, scale, 64});
     // the forward kernels are timed in the same traceback mode as the call
@@ -793,7 +867,7 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
         }
     }
     best->scale = 1;
-    const std::array<int, 4> v = {best->route, best->R, best->smul, best->LS > 0 ? best->LS : 64};
+    const std::array<int, 5> v = {best->route, best->R, best->smul, best->LS > 0 ? best->LS : 64, best->pk};
     ctx->tuned[key] = v;
     tune_save(ctx, key, v);
     return HALIGN_OK;
@@ -988,7 +1062,7 @@ int halign_ctx_set_autotune(halign_ctx *ctx, int enable) {
 
 int halign_ctx_last_plan(const halign_ctx *ctx, int32_t *plan_host) {
     if (!ctx || !plan_host) return fail(HALIGN_E_INVALID, "NULL argument");
-    for (int i = 0; i < 4; ++i) plan_host[i] = ctx->last_tune[i];
+    for (int i = 0; i < 5; ++i) plan_host[i] = ctx->last_tune[i];
     return HALIGN_OK;
 }
 
@@ -1083,7 +1157,7 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
         out.gskip = gskip;
     }
     RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st, tune, prep));
-    ctx->last_tune = {tune.route, tune.R, tune.smul, tune.LS > 0 ? tune.LS : 64};
+    ctx->last_tune = {tune.route, tune.R, tune.smul, tune.LS > 0 ? tune.LS : 64, ctx->last_pk};
     if (!tb && cells) {
         // score-only with cells: report the end cell as (0, 0, i1, j1)
         hipLaunchKernelGGL(hk::endcell_to_cells_kernel, dim3(grid_for(N, 256)), dim3(256), 0, st,

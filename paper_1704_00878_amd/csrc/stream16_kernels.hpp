@@ -1,0 +1,304 @@
+// Packed 16-bit wavefront kernel for gfx950: the traceback forward pass of
+// the wavefront kernel (sw_kernels.hpp) with two streams per lane group.
+// Lane group g of a wavefront runs stream 2q (A) in the low and stream 2q+1
+// (B) in the high half of every register, q = wave * NS + g, with v_pk_* 16-bit
+// integer ops.  The lane group's columns are the longer stream's; the other
+// half runs padding columns after its last pair.
+//
+// Recurrence as in the 16-bit strip kernel (E and F unclamped, floor at 0 on
+// F): 10 packed ops per two cells.  The host uses this kernel only when no H
+// can reach 2^14 (max S * min(m, longest sequence) < 16000, go + ge <= 256),
+// so no value or difference wraps and a padding profile entry of -2^14 is
+// never a source.  The four flags of a cell are the signs of four packed
+// differences: one v_pk_lshrrev_b16 moves both signs to bits 0 and 16 and one
+// v_lshl_or_b32 pushes them into a word that collects 16 flags per half (4
+// rows), so WQ = ceil(R/4) words per step hold both pairs: word q holds rows
+// 4q.. of the lane, row t at bit 16*half + 4*(n_q - 1 - (t - 4q)) with n_q rows
+// in word q.  Tiles and the step-to-column rule are the wavefront kernel's
+// with WQ words per step; each lane stages 4 steps in LDS and stores them as
+// half a tile.  Flags from unclamped E and F equal the clamped kernels' on
+// every cell the walk visits.
+//
+// End cells: both halves unpack H into 32-bit keys (H << 5 | 31 - t), as in
+// the 32-bit kernel, per pair.
+#pragma once
+#include "sw_kernels.hpp"
+#include "strip_kernels.hpp"
+
+namespace hk {
+
+typedef unsigned short pku16 __attribute__((ext_vector_type(2)));
+
+// one v_lshl_or_b32 per push (written out: the compiler would otherwise merge
+// consecutive pushes into wider shifts and three-way ORs, which cost more)
+__device__ __forceinline__ uint32_t push2(uint32_t w, pk16 d) {
+    const pku16 s = __builtin_bit_cast(pku16, d) >> pku16{15, 15};
+    uint32_t r;
+    asm("v_lshl_or_b32 %0, %1, 1, %2" : "=v"(r) : "v"(w), "v"(__builtin_bit_cast(uint32_t, s)));
+    return r;
+}
+
+template <int R, int LS>
+__global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
+sw_stream16_kernel(StreamArgs a) {
+    static_assert(LS == 32 || LS == 16, "lanes per stream");
+    static_assert(R >= 2 && R <= 16, "rows per lane");
+    constexpr int W = (R + 7) / 8;           // profile uint4 per (residue, lane)
+    constexpr int WQ = (R + 3) / 4;          // code words per step (both halves)
+    constexpr int NS = 64 / LS;              // lane groups per wavefront
+    constexpr int SPAN = LS * R;             // rows per pass
+    constexpr int LG = LS == 32 ? 5 : 4;
+    extern __shared__ int prof[];   // profile, then code staging [8 waves][4 steps][WQ][64 lanes]
+    const int nprow = a.alpha + 1;
+    const int prof_words = nprow * LS * 4 * W;
+    uint32_t *stage = reinterpret_cast<uint32_t *>(prof + prof_words) + (threadIdx.x >> 6) * 256 * WQ +
+                      (threadIdx.x & 63);
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int ll = lane & (LS - 1);
+    const int nthreads = blockDim.x;
+    const int goe = a.goe;
+    const int wave = __builtin_amdgcn_readfirstlane(blockIdx.x * (nthreads >> 6) + (tid >> 6));
+    const int q = wave * NS + lane / LS;     // lane group's stream pair
+    const int sA = 2 * q, sB = 2 * q + 1;
+    const bool actA = sA < a.nstreams, actB = sB < a.nstreams;
+    int64_t bA = 0, bB = 0;
+    int CA = 0, CB = 0, slotA = 0, slotB = 0;
+    if (actA) {
+        bA = a.sbeg[sA];
+        CA = (int)(a.sbeg[sA + 1] - bA);
+        slotA = a.sslot0[sA];
+    }
+    if (actB) {
+        bB = a.sbeg[sB];
+        CB = (int)(a.sbeg[sB + 1] - bB);
+        slotB = a.sslot0[sB];
+    }
+    const int C = max(CA, CB);
+    int Cmax = C;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) Cmax = max(Cmax, __builtin_amdgcn_readlane(C, s * LS));
+    Cmax = __builtin_amdgcn_readfirstlane(Cmax);
+    const uint8_t *srA = a.sres + bA, *srB = a.sres + bB;
+    const int steps_s = C + LS - 1;
+    const int steps8 = (Cmax + LS - 1 + 7) & ~7;
+    const int G = (steps_s + 7) >> 3;
+    const pk16 init2 = pk16{(short)-goe, (short)-goe};
+    const uint32_t init2u = as_u(init2);
+    const pk16 ge2 = pk16{(short)a.ge, (short)a.ge};
+    const pk16 goe2 = pk16{(short)goe, (short)goe};
+    const pk16 zero2 = pk16{0, 0};
+    const int padc = a.alpha;
+    const int padrc = padc | (padc << 16);
+    for (int pass = 0; pass < a.passes; ++pass) {
+        const int row0 = pass * SPAN;
+        __syncthreads();
+        {
+            int16_t *p16 = reinterpret_cast<int16_t *>(prof);
+            constexpr int PER = 8 * W;
+            for (int x = tid; x < nprow * LS * PER; x += nthreads) {
+                const int r = x / (LS * PER), l = (x / PER) & (LS - 1), tt = x % PER;
+                const int i = row0 + l * R + tt;
+                int v = kNegProf16;
+                if (r < a.alpha && tt < R && i < a.m) v = (int)a.mat[(a.center[i] & 31) * a.alpha + r] + goe;
+                p16[x] = (int16_t)v;
+            }
+        }
+        __syncthreads();
+        if (2 * wave * NS >= a.nstreams) continue;   // no stream of this wavefront is active
+        const int myrow = row0 + ll * R;
+        const int2 *bin = (pass > 0 && actA) ? a.bound + a.sbbase[sA] + (int64_t)(pass - 1) * C : nullptr;
+        int2 *bout = (pass + 1 < a.passes && actA) ? a.bound + a.sbbase[sA] + (int64_t)pass * C : nullptr;
+        uint32_t *cw = actA ? a.codes + a.scbase[sA] + (int64_t)pass * G * LS * 8 * WQ + ll * 8 * WQ : nullptr;
+        auto run = [&](auto hb_tag) __attribute__((always_inline)) {
+            constexpr bool HB = decltype(hb_tag)::value;
+            pk16 hg[R], e[R];
+#pragma unroll
+            for (int t = 0; t < R; ++t) { hg[t] = init2; e[t] = init2; }
+            uint32_t botg = init2u, botf = init2u;
+            uint32_t diag0 = init2u;
+            int rcur = padrc, rbuf = padrc;
+            int2 bbuf = make_int2((int)init2u, (int)init2u);
+            int plA = -1, plB = -1;
+            int bhA = 0, bcolA = 0, bkA = 0, kfA = 0;
+            int bhB = 0, bcolB = 0, bkB = 0, kfB = 0;
+            auto publishA = [&]() __attribute__((always_inline)) {
+                if (actA && plA >= 0 && bhA > 0) {
+                    BestCell b{bhA, bkA - kfA + 1, myrow + (31 - (bcolA & 31))};
+                    atomicMax(a.keys + slotA + plA, cell_key(b, true));
+                }
+            };
+            auto publishB = [&]() __attribute__((always_inline)) {
+                if (actB && plB >= 0 && bhB > 0) {
+                    BestCell b{bhB, bkB - kfB + 1, myrow + (31 - (bcolB & 31))};
+                    atomicMax(a.keys + slotB + plB, cell_key(b, true));
+                }
+            };
+            for (int k8 = 0; k8 < steps8; k8 += 8) {
+                if ((k8 & (LS - 1)) == 0) {
+                    const int kk = k8 + ll;
+                    const int ra = kk < CA ? (int)srA[kk] : padc;
+                    const int rb = kk < CB ? (int)srB[kk] : padc;
+                    rbuf = ra | (rb << 16);
+                    if (HB && bin) bbuf = kk < C ? bin[kk] : make_int2((int)init2u, (int)init2u);
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int k = k8 + u;
+                    const int rl = (k8 & (LS - 1)) + u;   // wave-uniform
+                    rcur = __builtin_amdgcn_update_dpp(__builtin_amdgcn_readlane(rbuf, rl), rcur, 0x138, 0xf, 0xf,
+                                                       false);
+#pragma unroll
+                    for (int s = 1; s < NS; ++s) {
+                        const int rs = __builtin_amdgcn_readlane(rbuf, s * LS + rl);
+                        rcur = lane == s * LS ? rs : rcur;
+                    }
+                    uint32_t upgu, upfu;
+                    if (HB) {
+                        int tg = (int)init2u, tf = (int)init2u;
+                        if (bin) {
+                            tg = __builtin_amdgcn_readlane(bbuf.x, rl);
+                            tf = __builtin_amdgcn_readlane(bbuf.y, rl);
+                        }
+                        upgu = (uint32_t)__builtin_amdgcn_update_dpp(tg, (int)botg, 0x138, 0xf, 0xf, false);
+                        upfu = (uint32_t)__builtin_amdgcn_update_dpp(tf, (int)botf, 0x138, 0xf, 0xf, false);
+#pragma unroll
+                        for (int s = 1; s < NS; ++s) {
+                            int sg = (int)init2u, sf = (int)init2u;
+                            if (bin) {
+                                sg = __builtin_amdgcn_readlane(bbuf.x, s * LS + rl);
+                                sf = __builtin_amdgcn_readlane(bbuf.y, s * LS + rl);
+                            }
+                            upgu = lane == s * LS ? (uint32_t)sg : upgu;
+                            upfu = lane == s * LS ? (uint32_t)sf : upfu;
+                        }
+                    } else {
+                        upgu = (uint32_t)__builtin_amdgcn_update_dpp((int)init2u, (int)botg, 0x138, 0xf, 0xf, false);
+                        upfu = (uint32_t)__builtin_amdgcn_update_dpp((int)init2u, (int)botf, 0x138, 0xf, 0xf, false);
+#pragma unroll
+                        for (int s = 1; s < NS; ++s) {
+                            upgu = lane == s * LS ? init2u : upgu;
+                            upfu = lane == s * LS ? init2u : upfu;
+                        }
+                    }
+                    if (rcur & 0x00800080) {
+                        // a pair starts in one half or both: publish the pair left
+                        // behind and reset that half to the column-0 boundary
+                        const bool fA = (rcur & 0x80) != 0, fB = (rcur & 0x800000) != 0;
+                        if (fA) {
+                            publishA();
+                            ++plA;
+                            bhA = 0;
+                            bcolA = 0;
+                            bkA = k;
+                            kfA = k;
+                        }
+                        if (fB) {
+                            publishB();
+                            ++plB;
+                            bhB = 0;
+                            bcolB = 0;
+                            bkB = k;
+                            kfB = k;
+                        }
+                        const uint32_t msk = (fA ? 0xffffu : 0u) | (fB ? 0xffff0000u : 0u);
+#pragma unroll
+                        for (int t = 0; t < R; ++t) {
+                            hg[t] = as_pk((init2u & msk) | (as_u(hg[t]) & ~msk));
+                            e[t] = as_pk((init2u & msk) | (as_u(e[t]) & ~msk));
+                        }
+                        diag0 = (init2u & msk) | (diag0 & ~msk);
+                    }
+                    pk16 upg = as_pk(upgu), upf = as_pk(upfu);
+                    pk16 diag = as_pk(diag0);
+                    diag0 = upgu;
+                    const int ra = rcur & 0x7f, rb = (rcur >> 16) & 0x7f;
+                    const uint4 *pa = reinterpret_cast<const uint4 *>(prof) + (((uint32_t)ra << LG) + ll) * W;
+                    const uint4 *pb = reinterpret_cast<const uint4 *>(prof) + (((uint32_t)rb << LG) + ll) * W;
+                    uint32_t wa[4 * W], wb[4 * W];
+#pragma unroll
+                    for (int w = 0; w < W; ++w) {
+                        const uint4 x = pa[w], y = pb[w];
+                        wa[4 * w] = x.x; wa[4 * w + 1] = x.y; wa[4 * w + 2] = x.z; wa[4 * w + 3] = x.w;
+                        wb[4 * w] = y.x; wb[4 * w + 1] = y.y; wb[4 * w + 2] = y.z; wb[4 * w + 3] = y.w;
+                    }
+                    uint32_t word[WQ];
+#pragma unroll
+                    for (int w = 0; w < WQ; ++w) word[w] = 0;
+                    int ckA = 0, ckB = 0, kpA = 0, kpB = 0;
+#pragma unroll
+                    for (int t = 0; t < R; ++t) {
+                        const pk16 p = as_pk(__builtin_amdgcn_perm(wb[t >> 1], wa[t >> 1],
+                                                                   (t & 1) ? 0x07060302u : 0x05040100u));
+                        const pk16 eext = e[t] - ge2;
+                        const pk16 en = pmax(eext, hg[t]);
+                        const pk16 fext = upf - ge2;
+                        const pk16 fn = pmax(fext, upg);
+                        const pk16 hd = diag + p;
+                        const pk16 h = pmax(pmax(hd, en), pmax(fn, zero2));
+                        uint32_t wd = word[t >> 2];
+                        wd = push2(wd, upg - fext);   // fext
+                        wd = push2(wd, hg[t] - eext); // eext
+                        wd = push2(wd, en - h);       // note
+                        wd = push2(wd, hd - h);       // notd
+                        word[t >> 2] = wd;
+                        const uint32_t hu = as_u(h);
+                        const int kA = (int)((hu & 0xffffu) << 5) | (31 - t);
+                        const int kB = (int)((hu >> 16) << 5) | (31 - t);
+                        if (t & 1) {
+                            ckA = vmax3(ckA, kpA, kA);
+                            ckB = vmax3(ckB, kpB, kB);
+                        } else if (t == R - 1) {
+                            ckA = max(ckA, kA);
+                            ckB = max(ckB, kB);
+                        } else {
+                            kpA = kA;
+                            kpB = kB;
+                        }
+                        diag = hg[t];
+                        hg[t] = h - goe2;
+                        e[t] = en;
+                        upg = hg[t];
+                        upf = fn;
+                    }
+                    botg = as_u(upg);
+                    botf = as_u(upf);
+#pragma unroll
+                    for (int w = 0; w < WQ; ++w) stage[64 * ((u & 3) * WQ + w)] = word[w];
+                    if ((u & 3) == 3 && cw && k8 < steps_s) {
+                        // half a tile (4 steps, 16*WQ bytes of the lane's 32*WQ)
+                        uint4 *dst = reinterpret_cast<uint4 *>(cw + (int64_t)(k8 >> 3) * LS * 8 * WQ) + (u >> 2) * WQ;
+#pragma unroll
+                        for (int v = 0; v < WQ; ++v)
+                            dst[v] = make_uint4(stage[64 * (4 * v)], stage[64 * (4 * v + 1)], stage[64 * (4 * v + 2)],
+                                                stage[64 * (4 * v + 3)]);
+                    }
+                    if (HB && bout) {
+                        const int K = k - ll;
+                        if (ll == LS - 1 && K >= 0 && K < C) bout[K] = make_int2((int)botg, (int)botf);
+                    }
+                    {
+                        const int ch = ckA >> 5;
+                        const bool up = ch > bhA;
+                        bcolA = up ? ckA : bcolA;
+                        bkA = up ? k : bkA;
+                        bhA = max(bhA, ch);
+                    }
+                    {
+                        const int ch = ckB >> 5;
+                        const bool up = ch > bhB;
+                        bcolB = up ? ckB : bcolB;
+                        bkB = up ? k : bkB;
+                        bhB = max(bhB, ch);
+                    }
+                }
+            }
+            publishA();
+            publishB();
+        };
+        if (pass > 0 || pass + 1 < a.passes) run(std::true_type{});
+        else run(std::false_type{});
+    }
+}
+
+}  // namespace hk

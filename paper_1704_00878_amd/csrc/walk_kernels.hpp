@@ -65,10 +65,12 @@ constexpr int kWalkCenterLds = 8192;   // centers up to this length are staged i
 // (and refreshes the sequence window), in one round trip.  Lanes advance
 // through their cached data until each misses or ends, so that one memory
 // round trip serves the misses of every lane of the wavefront.
-template <bool STRIP, bool CEN_LDS>
+template <bool STRIP, bool CEN_LDS, bool PK>
 __global__ void __launch_bounds__(64)
 walk_kernel(WalkArgs a) {
-    __shared__ uint32_t cache[4][16][64];
+    constexpr int CW = PK ? 32 : 16;   // words per cached chunk (8 steps x W, W <= 4 packed, <= 2 otherwise)
+    constexpr int HQ = CW / 4;
+    __shared__ uint32_t cache[4][CW][64];
     __shared__ uint32_t swin[16][64];
     __shared__ int8_t smat[32 * 32];
     __shared__ uint8_t scen[kWalkCenterLds];
@@ -104,6 +106,7 @@ walk_kernel(WalkArgs a) {
     }
     const int i1 = a.endcell[2 * pid], j1 = a.endcell[2 * pid + 1];
     int64_t base;
+    int half = 0;   // packed wavefront layout: the stream's half of each code word
     int ccol, stride;
     if (STRIP) {
         base = a.cbase[pid];
@@ -118,7 +121,13 @@ walk_kernel(WalkArgs a) {
         }
         base = a.scb[lo];
         ccol = (int)(a.slot_col[w] - a.sbeg[lo]);
-        stride = (int)(a.sbeg[lo + 1] - a.sbeg[lo]) + (1 << a.lg_ls) - 1;
+        int cs = (int)(a.sbeg[lo + 1] - a.sbeg[lo]);
+        if (PK) {   // the stream pair shares the longer stream's tiles
+            const int o = lo ^ 1;
+            if (o < a.nstreams) cs = max(cs, (int)(a.sbeg[o + 1] - a.sbeg[o]));
+            half = lo & 1;
+        }
+        stride = cs + (1 << a.lg_ls) - 1;
     }
     constexpr bool strip = STRIP;
     const int R = strip ? 16 : a.R;
@@ -174,10 +183,15 @@ walk_kernel(WalkArgs a) {
             int wi, sh;
             if (strip) { wi = ((j - 1) & 3) * 2 + (t >> 3); sh = 4 * (7 - (t & 7)); }
             else {
-                wi = ((ccol + j - 1 + (blk & LSm)) & 7) * W + (t >> 3);
-                sh = t < 8 ? 4 * (n0 - 1 - t) : 4 * (R - 1 - t);
+                if (PK) {
+                    wi = ((ccol + j - 1 + (blk & LSm)) & 7) * W + (t >> 2);
+                    sh = 16 * half + 4 * (min(4, R - (t & ~3)) - 1 - (t & 3));
+                } else {
+                    wi = ((ccol + j - 1 + (blk & LSm)) & 7) * W + (t >> 3);
+                    sh = t < 8 ? 4 * (n0 - 1 - t) : 4 * (R - 1 - t);
+                }
             }
-            const uint32_t nib = (cache[sl][wi & 15][lane] >> (sh & 31)) & 15u;
+            const uint32_t nib = (cache[sl][wi & (CW - 1)][lane] >> (sh & 31)) & 15u;
             const int gq = (int)(so + j - 1 - swb);
             const int gqc = min(max(gq, 0), 63);
             const int ic = min(max(i - 1, 0), m - 1);
@@ -267,9 +281,9 @@ walk_kernel(WalkArgs a) {
         const int64_t ad1 = g0 >= 1 ? chunk_addr(blk, g0 - 1) : ad0;
         const int64_t ad2 = g2 >= 0 ? chunk_addr(blk - 1, g2) : ad0;
         const int64_t ad3 = g2 >= 1 ? chunk_addr(blk - 1, g2 - 1) : ad0;
-        uint4 cq[4][4];
+        uint4 cq[4][HQ];
 #pragma unroll
-        for (int h = 0; h < 4; ++h) cq[0][h] = cq[1][h] = cq[2][h] = cq[3][h] = make_uint4(0, 0, 0, 0);
+        for (int h = 0; h < HQ; ++h) cq[0][h] = cq[1][h] = cq[2][h] = cq[3][h] = make_uint4(0, 0, 0, 0);
         {
             const uint4 *q0 = reinterpret_cast<const uint4 *>(a.codes + ad0);
             const uint4 *q1 = reinterpret_cast<const uint4 *>(a.codes + ad1);
@@ -279,7 +293,16 @@ walk_kernel(WalkArgs a) {
             cq[1][0] = q1[0]; cq[1][1] = q1[1];
             cq[2][0] = q2[0]; cq[2][1] = q2[1];
             cq[3][0] = q3[0]; cq[3][1] = q3[1];
-            if (W == 2) {
+            if (PK) {
+#pragma unroll
+                for (int h = 2; h < HQ; ++h)
+                    if (h < 2 * W) {
+                        cq[0][h] = q0[h];
+                        cq[1][h] = q1[h];
+                        cq[2][h] = q2[h];
+                        cq[3][h] = q3[h];
+                    }
+            } else if (W == 2) {
                 cq[0][2] = q0[2]; cq[0][3] = q0[3];
                 cq[1][2] = q1[2]; cq[1][3] = q1[3];
                 cq[2][2] = q2[2]; cq[2][3] = q2[3];
@@ -294,8 +317,8 @@ walk_kernel(WalkArgs a) {
 #pragma unroll
         for (int c = 0; c < 4; ++c) {
 #pragma unroll
-            for (int h = 0; h < 4; ++h) {
-                if (h < 2 || W == 2) {
+            for (int h = 0; h < HQ; ++h) {
+                if (h < 2 || (PK ? h < 2 * W : W == 2)) {
                     cache[c][4 * h + 0][lane] = cq[c][h].x;
                     cache[c][4 * h + 1][lane] = cq[c][h].y;
                     cache[c][4 * h + 2][lane] = cq[c][h].z;
