@@ -25,14 +25,16 @@ def _host(H, out, m):
             H.aligned_to_bool(out["aligned"].cpu().numpy(), m))
 
 
-@pytest.mark.parametrize("lanes", [None, "16"])
+@pytest.mark.parametrize("lanes", [None, "16", "pack16"])
 def test_graph_replays_match_eager(H, lanes, monkeypatch):
     """Several replays, with eager work and synchronisations in between, each
     equal to the oracle; a changed argument is captured anew.  Also with
-    16-lane streams."""
+    16-lane streams and with the packed 16-bit kernel on them."""
     import torch
     if lanes:
-        monkeypatch.setenv("HALIGN_STREAM_LANES", lanes)
+        monkeypatch.setenv("HALIGN_STREAM_LANES", lanes.replace("pack", ""))
+    if lanes and lanes.startswith("pack"):
+        monkeypatch.setenv("HALIGN_STREAM_PACK", "1")
     ctx = H.Context(0)
     sc = H.Scoring()
     seqs = synth.generate("plain64", n_seqs=300, seed=31)
