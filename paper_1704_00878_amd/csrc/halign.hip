@@ -8,7 +8,6 @@
 
 #include <algorithm>
 #include <fstream>
-#include <functional>
 #include <map>
 #include <sstream>
 #include <cstdarg>
@@ -364,7 +363,7 @@ struct Tune {
 
 int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq,
               const std::vector<int32_t> &pids_in, bool tb, bool endc, int route, const BatchOut &out,
-              hipStream_t st, const Tune &tune = Tune(), const std::function<int()> &after_forward = nullptr) {
+              hipStream_t st, const Tune &tune = Tune()) {
     const int64_t *oh = sq->offsets_host;
     const int N = sq->n;
     const int np = (int)pids_in.size();
@@ -666,7 +665,6 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                                (const unsigned long long *)keys, (const int32_t *)(dplan + o_spid), nslots, out.score,
                                endc ? out.endcell : (int32_t *)nullptr);
             HCHK(hipGetLastError());
-            if (ci == 0 && after_forward) RCHK(after_forward());
         } else {
             const int slots = ctx->num_cu * 16;
             const int grid = std::max(1, std::min(ngroups, slots));
@@ -696,7 +694,6 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             launch_inter(a, tb, endc, grid, st);
             HCHK(hipGetLastError());
             RCHK(record(ctx, ctx->ev[1], st));
-            if (ci == 0 && after_forward) RCHK(after_forward());
         }
         ++launches;
         if (tb) {
@@ -1109,10 +1106,13 @@ int halign_encode(const uint8_t *ascii, int64_t len, uint8_t *codes, void *strea
 // The launch sequence of halign_sw_batch (validation, plan, forward, walk).
 static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *center, int32_t m,
                           const halign_seqs *seqs, uint32_t flags, int32_t *score, int32_t *cells, uint16_t *ins,
-                          uint32_t *aligned, void *stream, int32_t *G = nullptr, int gskip = -1) {
+                          uint32_t *aligned, void *stream, int32_t *G = nullptr, int gskip = -1,
+                          bool checked = false) {
     if (!ctx) return fail(HALIGN_E_INVALID, "ctx is NULL");
-    RCHK(check_scoring(sc));
-    RCHK(check_seqs(seqs));
+    if (!checked) {   // halign_msa has checked both already
+        RCHK(check_scoring(sc));
+        RCHK(check_seqs(seqs));
+    }
     if (m <= 0 || !center) return fail(HALIGN_E_INVALID, "empty center");
     if (m >= 65536) return fail(HALIGN_E_UNSUPPORTED, "center length %d >= 65536", m);
     if (!score && seqs->n > 0) return fail(HALIGN_E_INVALID, "score is NULL");
@@ -1134,10 +1134,10 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
         BatchOut tout{score, cells, endcell, ins, aligned};
         RCHK(autotune(ctx, S, center, m, seqs, tb, endc, tout, st, &tune));
     }
-    // the code check and the zeroing of the outputs go in behind the first
-    // forward launch (the forward kernels read codes masked to 5 bits, and the
-    // outputs are first written by the walk), so the GPU starts on the DP as
-    // soon as the plan is ready
+    // the code check and the zeroing of the outputs go in before the host
+    // plans the batch, so these small kernels run while the host works (the
+    // forward kernels read codes masked to 5 bits, the check is read after the
+    // batch, and the outputs are first written by the walk)
     auto prep = [&]() -> int {
         RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], center, m, st));
         if (tb) {
@@ -1156,7 +1156,8 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
         out.G = G;
         out.gskip = gskip;
     }
-    RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st, tune, prep));
+    RCHK(prep());
+    RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st, tune));
     ctx->last_tune = {tune.route, tune.R, tune.smul, tune.LS > 0 ? tune.LS : 64, ctx->last_pk};
     if (!tb && cells) {
         // score-only with cells: report the end cell as (0, 0, i1, j1)
@@ -1193,9 +1194,10 @@ uint64_t fnv(uint64_t h, const void *p, size_t n) {
 // (pointers, sizes, offsets, scoring) stay the same.
 static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8_t *center, int32_t m,
                           const halign_seqs *seqs, uint32_t flags, int32_t *score, int32_t *cells, uint16_t *ins,
-                          uint32_t *aligned, void *stream, int32_t *G = nullptr, int gskip = -1) {
+                          uint32_t *aligned, void *stream, int32_t *G = nullptr, int gskip = -1,
+                          bool checked = false) {
     if (!(flags & HALIGN_GRAPH))
-        return sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream, G, gskip);
+        return sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream, G, gskip, checked);
     if (!ctx || !sc || !seqs || !sc->matrix_host || !seqs->offsets_host)
         return sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream, G, gskip);
     hipStream_t st = (hipStream_t)stream;
@@ -1611,7 +1613,7 @@ int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seq
     const uint8_t *cen = seqs->residues + oh[c];
     // the walk max-merges every pair's insertion counts into G (the center's own are all zero)
     RCHK(sw_batch_async(ctx, sc, cen, m, seqs, HALIGN_TRACEBACK | (ctx->use_graph ? HALIGN_GRAPH : 0u), score, cells,
-                        ins, al, stream, G, c));
+                        ins, al, stream, G, c, true));
     hipLaunchKernelGGL(hk::center_row_kernel, dim3(1), dim3(256), 0, st, ins, al, c, m, aw);
     HCHK(hipGetLastError());
     int64_t width = 0;
