@@ -19,8 +19,14 @@
 // half a tile.  Flags from unclamped E and F equal the clamped kernels' on
 // every cell the walk visits.
 //
-// End cells: both halves unpack H into 32-bit keys (H << 5 | 31 - t), as in
-// the 32-bit kernel, per pair.
+// End cells stay packed: per step one v_pk_max_i16 per row gives the step
+// maximum of each half, its sign against the running best gives a 16-bit
+// mask per half, and where it is set the step and the lane's rows are
+// copied (v_bfi_b32).  The first step that reaches the best H is the
+// smallest column, and at publication the smallest row of that step holding
+// the best H completes the key (max H, then min j, then min i per lane).
+// This needs R more registers; above R = 11 both halves unpack H into 32-bit
+// keys (H << 5 | 31 - t) per row instead, as the 32-bit kernel does.
 #pragma once
 #include "sw_kernels.hpp"
 #include "strip_kernels.hpp"
@@ -38,11 +44,22 @@ __device__ __forceinline__ uint32_t push2(uint32_t w, pk16 d) {
     return r;
 }
 
+// bitwise select m ? x : y (written out: with a mask known to be whole
+// halves, the compiler would select per half with compares instead)
+__device__ __forceinline__ uint32_t bfi(uint32_t m, uint32_t x, uint32_t y) {
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(x), "v"(y));
+    return r;
+}
+
 template <int R, int LS>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 sw_stream16_kernel(StreamArgs a) {
     static_assert(LS == 32 || LS == 16, "lanes per stream");
     static_assert(R >= 2 && R <= 16, "rows per lane");
+    // packed end cells need R more registers: up to R = 11 they fit the
+    // 128 of four waves per SIMD
+    constexpr bool SNAP = R <= 11;
     constexpr int W = (R + 7) / 8;           // profile uint4 per (residue, lane)
     constexpr int WQ = (R + 3) / 4;          // code words per step (both halves)
     constexpr int NS = 64 / LS;              // lane groups per wavefront
@@ -120,16 +137,42 @@ sw_stream16_kernel(StreamArgs a) {
             int rcur = padrc, rbuf = padrc;
             int2 bbuf = make_int2((int)init2u, (int)init2u);
             int plA = -1, plB = -1;
-            int bhA = 0, bcolA = 0, bkA = 0, kfA = 0;
-            int bhB = 0, bcolB = 0, bkB = 0, kfB = 0;
+            // running end cell of the current pair, per half.  SNAP: the best
+            // H, the step (mod 2^16) that first reached it and the lane's rows
+            // (as H - go - ge) at that step, the row resolved at publication.
+            // Otherwise 32-bit keys (H << 5 | 31 - t) per step.
+            pk16 bh = zero2;
+            uint32_t bk = 0;
+            pk16 hs[SNAP ? R : 1];
+#pragma unroll
+            for (int t = 0; t < (SNAP ? R : 1); ++t) hs[t] = init2;
+            int bhA = 0, bcolA = 0, bkA = 0;
+            int bhB = 0, bcolB = 0, bkB = 0;
+            int kfA = 0, kfB = 0;
+            auto publish = [&](int h, int kf, int sh, int slot, int pl) __attribute__((always_inline)) {
+                int t0 = 0;
+#pragma unroll
+                for (int t = R - 1; t >= 0; --t)
+                    if ((int)(short)(as_u(hs[SNAP ? t : 0]) >> sh) == h - goe) t0 = t;
+                // j - 1 < 2^16 for every cell of a pair, so the low 16 bits of
+                // the step difference are the column
+                BestCell b{h, (int)(((bk >> sh) - (uint32_t)kf) & 0xffffu) + 1, myrow + t0};
+                atomicMax(a.keys + slot + pl, cell_key(b, true));
+            };
             auto publishA = [&]() __attribute__((always_inline)) {
-                if (actA && plA >= 0 && bhA > 0) {
+                if constexpr (SNAP) {
+                    const int h = (int)(as_u(bh) & 0xffffu);
+                    if (actA && plA >= 0 && h > 0) publish(h, kfA, 0, slotA, plA);
+                } else if (actA && plA >= 0 && bhA > 0) {
                     BestCell b{bhA, bkA - kfA + 1, myrow + (31 - (bcolA & 31))};
                     atomicMax(a.keys + slotA + plA, cell_key(b, true));
                 }
             };
             auto publishB = [&]() __attribute__((always_inline)) {
-                if (actB && plB >= 0 && bhB > 0) {
+                if constexpr (SNAP) {
+                    const int h = (int)(as_u(bh) >> 16);
+                    if (actB && plB >= 0 && h > 0) publish(h, kfB, 16, slotB, plB);
+                } else if (actB && plB >= 0 && bhB > 0) {
                     BestCell b{bhB, bkB - kfB + 1, myrow + (31 - (bcolB & 31))};
                     atomicMax(a.keys + slotB + plB, cell_key(b, true));
                 }
@@ -188,20 +231,21 @@ sw_stream16_kernel(StreamArgs a) {
                         if (fA) {
                             publishA();
                             ++plA;
+                            kfA = k;
                             bhA = 0;
                             bcolA = 0;
                             bkA = k;
-                            kfA = k;
                         }
                         if (fB) {
                             publishB();
                             ++plB;
+                            kfB = k;
                             bhB = 0;
                             bcolB = 0;
                             bkB = k;
-                            kfB = k;
                         }
                         const uint32_t msk = (fA ? 0xffffu : 0u) | (fB ? 0xffff0000u : 0u);
+                        bh = as_pk(as_u(bh) & ~msk);
 #pragma unroll
                         for (int t = 0; t < R; ++t) {
                             hg[t] = as_pk((init2u & msk) | (as_u(hg[t]) & ~msk));
@@ -225,6 +269,7 @@ sw_stream16_kernel(StreamArgs a) {
                     uint32_t word[WQ];
 #pragma unroll
                     for (int w = 0; w < WQ; ++w) word[w] = 0;
+                    pk16 sm = zero2;   // step maximum over the lane's rows, per half
                     int ckA = 0, ckB = 0, kpA = 0, kpB = 0;
 #pragma unroll
                     for (int t = 0; t < R; ++t) {
@@ -242,18 +287,22 @@ sw_stream16_kernel(StreamArgs a) {
                         wd = push2(wd, en - h);       // note
                         wd = push2(wd, hd - h);       // notd
                         word[t >> 2] = wd;
-                        const uint32_t hu = as_u(h);
-                        const int kA = (int)((hu & 0xffffu) << 5) | (31 - t);
-                        const int kB = (int)((hu >> 16) << 5) | (31 - t);
-                        if (t & 1) {
-                            ckA = vmax3(ckA, kpA, kA);
-                            ckB = vmax3(ckB, kpB, kB);
-                        } else if (t == R - 1) {
-                            ckA = max(ckA, kA);
-                            ckB = max(ckB, kB);
+                        if constexpr (SNAP) {
+                            sm = t == 0 ? h : pmax(sm, h);
                         } else {
-                            kpA = kA;
-                            kpB = kB;
+                            const uint32_t hu = as_u(h);
+                            const int kA = (int)((hu & 0xffffu) << 5) | (31 - t);
+                            const int kB = (int)((hu >> 16) << 5) | (31 - t);
+                            if (t & 1) {
+                                ckA = vmax3(ckA, kpA, kA);
+                                ckB = vmax3(ckB, kpB, kB);
+                            } else if (t == R - 1) {
+                                ckA = max(ckA, kA);
+                                ckB = max(ckB, kB);
+                            } else {
+                                kpA = kA;
+                                kpB = kB;
+                            }
                         }
                         diag = hg[t];
                         hg[t] = h - goe2;
@@ -277,19 +326,29 @@ sw_stream16_kernel(StreamArgs a) {
                         const int K = k - ll;
                         if (ll == LS - 1 && K >= 0 && K < C) bout[K] = make_int2((int)botg, (int)botf);
                     }
-                    {
-                        const int ch = ckA >> 5;
-                        const bool up = ch > bhA;
-                        bcolA = up ? ckA : bcolA;
-                        bkA = up ? k : bkA;
-                        bhA = max(bhA, ch);
-                    }
-                    {
-                        const int ch = ckB >> 5;
-                        const bool up = ch > bhB;
-                        bcolB = up ? ckB : bcolB;
-                        bkB = up ? k : bkB;
-                        bhB = max(bhB, ch);
+                    if constexpr (SNAP) {
+                        // 0xffff in each half whose step maximum beats its best
+                        const uint32_t imp = as_u((bh - sm) >> pk16{15, 15});
+                        bh = pmax(bh, sm);
+                        const uint32_t kw = (uint32_t)(k & 0xffff) * 0x10001u;
+                        bk = bfi(imp, kw, bk);
+#pragma unroll
+                        for (int t = 0; t < R; ++t) hs[t] = as_pk(bfi(imp, as_u(hg[t]), as_u(hs[t])));
+                    } else {
+                        {
+                            const int ch = ckA >> 5;
+                            const bool up = ch > bhA;
+                            bcolA = up ? ckA : bcolA;
+                            bkA = up ? k : bkA;
+                            bhA = max(bhA, ch);
+                        }
+                        {
+                            const int ch = ckB >> 5;
+                            const bool up = ch > bhB;
+                            bcolB = up ? ckB : bcolB;
+                            bkB = up ? k : bkB;
+                            bhB = max(bhB, ch);
+                        }
                     }
                 }
             }
