@@ -10,11 +10,14 @@
 // can reach 2^14 (max S * min(m, longest sequence) < 16000, go + ge <= 256),
 // so no value or difference wraps and a padding profile entry of -2^14 is
 // never a source.  The four flags of a cell are the signs of four packed
-// differences: one v_pk_lshrrev_b16 moves both signs to bits 0 and 16 and one
-// v_lshl_or_b32 pushes them into a word that collects 16 flags per half (4
-// rows), so WQ = ceil(R/4) words per step hold both pairs: word q holds rows
-// 4q.. of the lane, row t at bit 16*half + 4*(n_q - 1 - (t - 4q)) with n_q rows
-// in word q.  Tiles and the step-to-column rule are the wavefront kernel's
+// differences.  v_perm_b32 with byte selectors 8..11 turns the signs of two
+// packed differences into four 0x00/0xff bytes, one per flag and half, so
+// two perms give all eight flags of a row pair, and two v_bfi_b32 with
+// constant masks drop them into their bits of a word that holds 4 rows of
+// both pairs: WQ = ceil(R/4) words per step, word q holding rows 4q.. of the
+// lane.  Row t (k = t mod 4) of half h: byte h holds notd at bit 2k and note
+// at bit 2k + 1, byte 2 + h holds eext at bit 2k and fext at bit 2k + 1.
+// Tiles and the step-to-column rule are the wavefront kernel's
 // with WQ words per step; each lane stages 4 steps in LDS and stores them as
 // half a tile.  Flags from unclamped E and F equal the clamped kernels' on
 // every cell the walk visits.
@@ -35,20 +38,18 @@ namespace hk {
 
 typedef unsigned short pku16 __attribute__((ext_vector_type(2)));
 
-// one v_lshl_or_b32 per push (written out: the compiler would otherwise merge
-// consecutive pushes into wider shifts and three-way ORs, which cost more)
-__device__ __forceinline__ uint32_t push2(uint32_t w, pk16 d) {
-    const pku16 s = __builtin_bit_cast(pku16, d) >> pku16{15, 15};
-    uint32_t r;
-    asm("v_lshl_or_b32 %0, %1, 1, %2" : "=v"(r) : "v"(w), "v"(__builtin_bit_cast(uint32_t, s)));
-    return r;
-}
-
 // bitwise select m ? x : y (written out: with a mask known to be whole
 // halves, the compiler would select per half with compares instead)
 __device__ __forceinline__ uint32_t bfi(uint32_t m, uint32_t x, uint32_t y) {
     uint32_t r;
     asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(x), "v"(y));
+    return r;
+}
+
+// the same with a wave-uniform mask in an SGPR
+__device__ __forceinline__ uint32_t bfi_s(uint32_t m, uint32_t x, uint32_t y) {
+    uint32_t r;
+    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "s"(m), "v"(x), "v"(y));
     return r;
 }
 
@@ -281,11 +282,13 @@ sw_stream16_kernel(StreamArgs a) {
                         const pk16 fn = pmax(fext, upg);
                         const pk16 hd = diag + p;
                         const pk16 h = pmax(pmax(hd, en), pmax(fn, zero2));
+                        // bytes (notd A, notd B, eext A, eext B) and (note A, note B, fext A, fext B)
+                        const uint32_t f0 = __builtin_amdgcn_perm(as_u(hg[t] - eext), as_u(hd - h), 0x0b0a0908u);
+                        const uint32_t f1 = __builtin_amdgcn_perm(as_u(upg - fext), as_u(en - h), 0x0b0a0908u);
+                        const uint32_t m0 = 0x01010101u << (2 * (t & 3)), m1 = m0 << 1;
                         uint32_t wd = word[t >> 2];
-                        wd = push2(wd, upg - fext);   // fext
-                        wd = push2(wd, hg[t] - eext); // eext
-                        wd = push2(wd, en - h);       // note
-                        wd = push2(wd, hd - h);       // notd
+                        wd = bfi_s(m0, f0, wd);
+                        wd = bfi_s(m1, f1, wd);
                         word[t >> 2] = wd;
                         if constexpr (SNAP) {
                             sm = t == 0 ? h : pmax(sm, h);

@@ -185,13 +185,16 @@ walk_kernel(WalkArgs a) {
             else {
                 if (PK) {
                     wi = ((ccol + j - 1 + (blk & LSm)) & 7) * W + (t >> 2);
-                    sh = 16 * half + 4 * (min(4, R - (t & ~3)) - 1 - (t & 3));
+                    sh = 8 * half + 2 * (t & 3);
                 } else {
                     wi = ((ccol + j - 1 + (blk & LSm)) & 7) * W + (t >> 3);
                     sh = t < 8 ? 4 * (n0 - 1 - t) : 4 * (R - 1 - t);
                 }
             }
-            const uint32_t nib = (cache[sl][wi & (CW - 1)][lane] >> (sh & 31)) & 15u;
+            const uint32_t cword = cache[sl][wi & (CW - 1)][lane];
+            // notd, note, eext, fext in bits 0-3 (packed layout: two bit pairs 16 apart)
+            const uint32_t nib = PK ? ((cword >> (sh & 15)) & 3u) | (((cword >> ((sh & 15) + 16)) & 3u) << 2)
+                                    : (cword >> (sh & 31)) & 15u;
             const int gq = (int)(so + j - 1 - swb);
             const int gqc = min(max(gq, 0), 63);
             const int ic = min(max(i - 1, 0), m - 1);

@@ -150,6 +150,50 @@ def test_small_alphabet_ties(H, ctx):
             _compare(got, S, go, ge, center, seqs)
 
 
+@pytest.mark.parametrize("route,m", [("pack32", 330), ("pack32", 420), ("pack16", 170), ("pack16", 420),
+                                     ("intra32", 330), ("intra16", 420)])
+@pytest.mark.parametrize("streams", [0, 3])
+def test_small_alphabet_ties_long_centers(H, ctx, route, m, streams, monkeypatch):
+    """Ties on centers that give 10 to 14 rows per lane (both end-cell
+    trackings of the packed kernel, one and two passes), with one pair per
+    stream and with many pairs per stream."""
+    if streams:
+        monkeypatch.setenv("HALIGN_MAX_STREAMS", str(streams))
+    rng = np.random.default_rng(m + streams)
+    S = np.array([[2, -1], [-1, 2]], np.int8)
+    center = rng.integers(0, 2, size=m).astype(np.uint8)
+    seqs = [rng.integers(0, 2, size=int(rng.integers(0, 300))).astype(np.uint8) for _ in range(60)]
+    seqs += [center.copy(), center[m // 3:].copy(), np.zeros(0, np.uint8)]
+    ss = synth.SeqSet.from_list(seqs)
+    for go, ge in [(1, 1), (0, 1)]:
+        sc = H.Scoring(S, go, ge)
+        got = _run(H, ctx, sc, ss, center, route)
+        if route.startswith("pack"):
+            assert ctx.last_plan()["packed"] == 1
+        _compare(got, S, go, ge, center, ss)
+
+
+@pytest.mark.parametrize("route", ["pack32", "pack16"])
+def test_packed_step_count_past_16_bits(H, ctx, route, monkeypatch):
+    """One stream of about 80,000 columns: the packed kernel keeps the step of
+    each end cell modulo 2^16, which must still give every column."""
+    monkeypatch.setenv("HALIGN_MAX_STREAMS", "1")
+    rng = np.random.default_rng(11)
+    center = rng.integers(0, 20, size=150).astype(np.uint8)
+    seqs = []
+    for k in range(300):
+        s = rng.integers(0, 20, size=int(rng.integers(200, 330))).astype(np.uint8)
+        p = int(rng.integers(0, len(s) - 60))
+        s[p:p + 60] = center[40:100]   # an end cell far into the pair
+        seqs.append(s)
+    ss = synth.SeqSet.from_list(seqs)
+    assert int(ss.offsets[-1]) > 70000
+    sc = H.Scoring()
+    got = _run(H, ctx, sc, ss, center, route)
+    assert ctx.last_plan()["packed"] == 1
+    _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, center, ss)
+
+
 @pytest.mark.parametrize("lanes", ["intra", "intra32", "intra16", "pack32", "pack16"])
 @pytest.mark.parametrize("streams", [1, 2, 5])
 def test_stream_packing(H, ctx, streams, lanes, monkeypatch):
