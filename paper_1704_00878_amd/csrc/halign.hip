@@ -418,12 +418,12 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
     }
     // packed 16-bit wavefront kernel: asked for by the tuner (or the test knob
     // HALIGN_STREAM_PACK=1 with the lanes knob), traceback with end cells only,
-    // and only when no H can reach 2^14 and the gap costs are small
+    // and only when every H stays below 15000 and the gap costs are small
     bool pk = false;
     {
         const char *e = getenv("HALIGN_STREAM_PACK");
         const bool want = tune.R > 0 ? tune.pk > 0 : (e && atoi(e) != 0);
-        const bool fits = p16 && tb && endc && (int64_t)smax * std::min(m, nlong) < 16000 && S.goe <= 256 &&
+        const bool fits = p16 && tb && endc && (int64_t)smax * std::min(m, nlong) < 15000 && S.goe <= 256 &&
                           S.ge <= 256;
         pk = want && fits && route == kRouteIntra && stream16_supported(R, LS);
     }

@@ -6,10 +6,11 @@
 // half runs padding columns after its last pair.
 //
 // Recurrence as in the 16-bit strip kernel (E and F unclamped, floor at 0 on
-// F): 10 packed ops per two cells.  The host uses this kernel only when no H
-// can reach 2^14 (max S * min(m, longest sequence) < 16000, go + ge <= 256),
-// so no value or difference wraps and a padding profile entry of -2^14 is
-// never a source.  The four flags of a cell are the signs of four packed
+// F), on values held plus a bias so that H = max(diagonal, E, max(F, 0)) is
+// one v_pk_maximum3_f16 on their bit patterns: 9 packed ops per two cells.
+// The host uses this kernel only when every H stays below 15000 (max S *
+// min(m, longest sequence) < 15000, go + ge <= 256), so no value or
+// difference wraps and a padding profile entry is never a source.  The four flags of a cell are the signs of four packed
 // differences.  v_perm_b32 with byte selectors 8..11 turns the signs of two
 // packed differences into four 0x00/0xff bytes, one per flag and half, so
 // two perms give all eight flags of a row pair, and two v_bfi_b32 with
@@ -37,6 +38,24 @@
 namespace hk {
 
 typedef unsigned short pku16 __attribute__((ext_vector_type(2)));
+
+// Biased 16-bit values: every H, E, F and H - go - ge is held plus kBias16,
+// which keeps each operand of the three-way maximum a non-negative 16-bit
+// pattern below 0x7c00 (a finite non-negative half), whose order as a half
+// is its order as an integer.  The host bound H < 15000 gives values in
+// [kBias16 - 512, kBias16 + 15000); a padding entry of kPadProf16 makes H - go
+// - ge + pad below kBias16, so it never wins against the floor, and at least
+// 0.
+constexpr int kBias16 = 15616;
+constexpr int kPadProf16 = -15360;
+
+// max(a, b, c) per half with one v_pk_maximum3_f16 (operands as above)
+__device__ __forceinline__ pk16 max3h(pk16 a, pk16 b, pk16 c) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 r = __builtin_elementwise_maximum(
+        __builtin_elementwise_maximum(__builtin_bit_cast(h2, a), __builtin_bit_cast(h2, b)), __builtin_bit_cast(h2, c));
+    return __builtin_bit_cast(pk16, r);
+}
 
 // bitwise select m ? x : y (written out: with a mask known to be whole
 // halves, the compiler would select per half with compares instead)
@@ -101,11 +120,12 @@ sw_stream16_kernel(StreamArgs a) {
     const int steps_s = C + LS - 1;
     const int steps8 = (Cmax + LS - 1 + 7) & ~7;
     const int G = (steps_s + 7) >> 3;
-    const pk16 init2 = pk16{(short)-goe, (short)-goe};
+    const pk16 init2 = pk16{(short)(kBias16 - goe), (short)(kBias16 - goe)};   // -go - ge, biased
     const uint32_t init2u = as_u(init2);
     const pk16 ge2 = pk16{(short)a.ge, (short)a.ge};
     const pk16 goe2 = pk16{(short)goe, (short)goe};
     const pk16 zero2 = pk16{0, 0};
+    const pk16 bias2 = pk16{(short)kBias16, (short)kBias16};   // 0, biased
     const int padc = a.alpha;
     const int padrc = padc | (padc << 16);
     for (int pass = 0; pass < a.passes; ++pass) {
@@ -117,7 +137,7 @@ sw_stream16_kernel(StreamArgs a) {
             for (int x = tid; x < nprow * LS * PER; x += nthreads) {
                 const int r = x / (LS * PER), l = (x / PER) & (LS - 1), tt = x % PER;
                 const int i = row0 + l * R + tt;
-                int v = kNegProf16;
+                int v = kPadProf16;
                 if (r < a.alpha && tt < R && i < a.m) v = (int)a.mat[(a.center[i] & 31) * a.alpha + r] + goe;
                 p16[x] = (int16_t)v;
             }
@@ -157,24 +177,24 @@ sw_stream16_kernel(StreamArgs a) {
                     if ((int)(short)(as_u(hs[SNAP ? t : 0]) >> sh) == h - goe) t0 = t;
                 // j - 1 < 2^16 for every cell of a pair, so the low 16 bits of
                 // the step difference are the column
-                BestCell b{h, (int)(((bk >> sh) - (uint32_t)kf) & 0xffffu) + 1, myrow + t0};
+                BestCell b{h - kBias16, (int)(((bk >> sh) - (uint32_t)kf) & 0xffffu) + 1, myrow + t0};
                 atomicMax(a.keys + slot + pl, cell_key(b, true));
             };
             auto publishA = [&]() __attribute__((always_inline)) {
                 if constexpr (SNAP) {
                     const int h = (int)(as_u(bh) & 0xffffu);
-                    if (actA && plA >= 0 && h > 0) publish(h, kfA, 0, slotA, plA);
-                } else if (actA && plA >= 0 && bhA > 0) {
-                    BestCell b{bhA, bkA - kfA + 1, myrow + (31 - (bcolA & 31))};
+                    if (actA && plA >= 0 && h > kBias16) publish(h, kfA, 0, slotA, plA);
+                } else if (actA && plA >= 0 && bhA > kBias16) {
+                    BestCell b{bhA - kBias16, bkA - kfA + 1, myrow + (31 - (bcolA & 31))};
                     atomicMax(a.keys + slotA + plA, cell_key(b, true));
                 }
             };
             auto publishB = [&]() __attribute__((always_inline)) {
                 if constexpr (SNAP) {
                     const int h = (int)(as_u(bh) >> 16);
-                    if (actB && plB >= 0 && h > 0) publish(h, kfB, 16, slotB, plB);
-                } else if (actB && plB >= 0 && bhB > 0) {
-                    BestCell b{bhB, bkB - kfB + 1, myrow + (31 - (bcolB & 31))};
+                    if (actB && plB >= 0 && h > kBias16) publish(h, kfB, 16, slotB, plB);
+                } else if (actB && plB >= 0 && bhB > kBias16) {
+                    BestCell b{bhB - kBias16, bkB - kfB + 1, myrow + (31 - (bcolB & 31))};
                     atomicMax(a.keys + slotB + plB, cell_key(b, true));
                 }
             };
@@ -270,7 +290,8 @@ sw_stream16_kernel(StreamArgs a) {
                     uint32_t word[WQ];
 #pragma unroll
                     for (int w = 0; w < WQ; ++w) word[w] = 0;
-                    pk16 sm = zero2;   // step maximum over the lane's rows, per half
+                    pk16 sm = bias2;   // step maximum over the lane's rows, per half
+                    pk16 hprev = bias2;
                     int ckA = 0, ckB = 0, kpA = 0, kpB = 0;
 #pragma unroll
                     for (int t = 0; t < R; ++t) {
@@ -281,7 +302,7 @@ sw_stream16_kernel(StreamArgs a) {
                         const pk16 fext = upf - ge2;
                         const pk16 fn = pmax(fext, upg);
                         const pk16 hd = diag + p;
-                        const pk16 h = pmax(pmax(hd, en), pmax(fn, zero2));
+                        const pk16 h = max3h(hd, en, pmax(fn, bias2));
                         // bytes (notd A, notd B, eext A, eext B) and (note A, note B, fext A, fext B)
                         const uint32_t f0 = __builtin_amdgcn_perm(as_u(hg[t] - eext), as_u(hd - h), 0x0b0a0908u);
                         const uint32_t f1 = __builtin_amdgcn_perm(as_u(upg - fext), as_u(en - h), 0x0b0a0908u);
@@ -291,7 +312,9 @@ sw_stream16_kernel(StreamArgs a) {
                         wd = bfi_s(m1, f1, wd);
                         word[t >> 2] = wd;
                         if constexpr (SNAP) {
-                            sm = t == 0 ? h : pmax(sm, h);
+                            if (t & 1) sm = max3h(sm, hprev, h);
+                            else if (t == R - 1) sm = pmax(sm, h);
+                            else hprev = h;
                         } else {
                             const uint32_t hu = as_u(h);
                             const int kA = (int)((hu & 0xffffu) << 5) | (31 - t);

@@ -194,6 +194,27 @@ def test_packed_step_count_past_16_bits(H, ctx, route, monkeypatch):
     _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, center, ss)
 
 
+@pytest.mark.parametrize("route", ["pack32", "pack16"])
+@pytest.mark.parametrize("m", [1050, 1363, 1364])
+def test_packed_scores_at_the_bound(H, ctx, route, m):
+    """Scores up to the packed kernel's bound (max S x min(m, longest) <
+    15000): a center of m tryptophans (S = 11) against itself and its parts
+    reaches H = 11 m, 14,993 at m = 1363; at m = 1364 the bound fails and the
+    32-bit kernel runs."""
+    w = 17   # W in the NCBI order
+    center = np.full(m, w, np.uint8)
+    rng = np.random.default_rng(m)
+    mixed = center.copy()
+    mixed[rng.integers(0, m, m // 10)] = rng.integers(0, 20, m // 10).astype(np.uint8)
+    ss = synth.SeqSet.from_list([center.copy(), center[m // 4:].copy(), mixed, np.zeros(0, np.uint8),
+                                 rng.integers(0, 20, 200).astype(np.uint8)])
+    sc = H.Scoring()
+    got = _run(H, ctx, sc, ss, center, route)
+    assert ctx.last_plan()["packed"] == (1 if 11 * m < 15000 else 0)
+    assert got["score"][0] == 11 * m
+    _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, center, ss)
+
+
 @pytest.mark.parametrize("lanes", ["intra", "intra32", "intra16", "pack32", "pack16"])
 @pytest.mark.parametrize("streams", [1, 2, 5])
 def test_stream_packing(H, ctx, streams, lanes, monkeypatch):
@@ -297,7 +318,7 @@ def test_invalid_arguments(H, ctx):
 
 def test_packed_kernel_selected(H, ctx, monkeypatch):
     """The packed routes run the packed 16-bit kernel, not a silent fallback;
-    above its bound (max S x length >= 16000) the 32-bit kernel takes over."""
+    above its bound (max S x length >= 15000) the 32-bit kernel takes over."""
     import torch
     monkeypatch.setenv("HALIGN_STREAM_LANES", "32")
     monkeypatch.setenv("HALIGN_STREAM_PACK", "1")
