@@ -116,8 +116,8 @@ int  halign_ctx_last_stats(const halign_ctx *ctx, int64_t *stats_host /*[4]: cel
  * candidate plans -- wavefront streams of 64 lanes with R or R+1 center rows
  * per lane and one or two streams per resident wave slot, streams of 32 or 16
  * lanes with up to 16 rows per lane, the same in packed 16-bit arithmetic
- * with two streams per lane group (traceback only, when no score can reach
- * 2^14), or the one-pair-per-lane kernel -- on the batch (a strided sample of
+ * with two streams per lane group (traceback only, when every score stays
+ * below 15000), or the one-pair-per-lane kernel -- on the batch (a strided sample of
  * 65,536 pairs for batches above 4e10 cells, with the stream count scaled to
  * keep the pairs per stream) in the call's own mode, and keeps the fastest;
  * results do not depend on the plan.
