@@ -5,9 +5,9 @@
 // integer ops.  The lane group's columns are the longer stream's; the other
 // half runs padding columns after its last pair.
 //
-// Recurrence as in the 16-bit strip kernel (E and F unclamped, floor at 0 on
-// F), on values held plus a bias so that H = max(diagonal, E, max(F, 0)) is
-// one v_pk_maximum3_f16 on their bit patterns: 9 packed ops per two cells.
+// Recurrence as in the 32-bit kernels (E* and F* clamped at 0), on values
+// held plus a bias so that each of E*, F* and H is one v_pk_maximum3_f16 on
+// their bit patterns: 8 packed ops per two cells.
 // The host uses this kernel only when every H stays below 15000 (max S *
 // min(m, longest sequence) < 15000, go + ge <= 256), so no value or
 // difference wraps and a padding profile entry is never a source.  The four flags of a cell are the signs of four packed
@@ -20,10 +20,10 @@
 // at bit 2k + 1, byte 2 + h holds eext at bit 2k and fext at bit 2k + 1.
 // Tiles and the step-to-column rule are the wavefront kernel's
 // with WQ words per step; each lane stages 4 steps in LDS and stores them as
-// half a tile.  Flags from unclamped E and F equal the clamped kernels' on
-// every cell the walk visits.
+// half a tile.  With E* and F* clamped as there, every flag equals the 32-bit
+// kernel's.
 //
-// End cells stay packed: per step one v_pk_max_i16 per row gives the step
+// End cells stay packed: per step one v_pk_maximum3_f16 per two rows gives the step
 // maximum of each half, its sign against the running best gives a 16-bit
 // mask per half, and where it is set the step and the lane's rows are
 // copied (v_bfi_b32).  The first step that reaches the best H is the
@@ -39,10 +39,10 @@ namespace hk {
 
 typedef unsigned short pku16 __attribute__((ext_vector_type(2)));
 
-// Biased 16-bit values: every H, E, F and H - go - ge is held plus kBias16,
-// which keeps each operand of the three-way maximum a non-negative 16-bit
-// pattern below 0x7c00 (a finite non-negative half), whose order as a half
-// is its order as an integer.  The host bound H < 15000 gives values in
+// Biased 16-bit values: every H, E*, F* and H - go - ge is held plus
+// kBias16, which keeps each operand of the three-way maxima a non-negative
+// 16-bit pattern below 0x7c00 (a finite non-negative half), whose order as a
+// half is its order as an integer.  The host bound H < 15000 gives values in
 // [kBias16 - 512, kBias16 + 15000); a padding entry of kPadProf16 makes H - go
 // - ge + pad below kBias16, so it never wins against the floor, and at least
 // 0.
@@ -298,11 +298,11 @@ sw_stream16_kernel(StreamArgs a) {
                         const pk16 p = as_pk(__builtin_amdgcn_perm(wb[t >> 1], wa[t >> 1],
                                                                    (t & 1) ? 0x07060302u : 0x05040100u));
                         const pk16 eext = e[t] - ge2;
-                        const pk16 en = pmax(eext, hg[t]);
+                        const pk16 en = max3h(eext, hg[t], bias2);   // E* = max(E, 0)
                         const pk16 fext = upf - ge2;
-                        const pk16 fn = pmax(fext, upg);
+                        const pk16 fn = max3h(fext, upg, bias2);     // F* = max(F, 0)
                         const pk16 hd = diag + p;
-                        const pk16 h = max3h(hd, en, pmax(fn, bias2));
+                        const pk16 h = max3h(hd, en, fn);
                         // bytes (notd A, notd B, eext A, eext B) and (note A, note B, fext A, fext B)
                         const uint32_t f0 = __builtin_amdgcn_perm(as_u(hg[t] - eext), as_u(hd - h), 0x0b0a0908u);
                         const uint32_t f1 = __builtin_amdgcn_perm(as_u(upg - fext), as_u(en - h), 0x0b0a0908u);
