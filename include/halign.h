@@ -184,8 +184,9 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m,
  * Exact: sums[i] = sum_{j != i} SW(seq i, seq j) (int64), center = argmax,
  * ties to the lowest index (Methods: the center is the sequence most similar
  * to the others).  *center_host is written (synchronises).
- * Both calls score pairs in packed 16-bit arithmetic when no score can reach
- * 2^14 (max matrix entry x longest sequence < 16000), else in 32-bit; the
+ * Both calls score pairs in packed 16-bit arithmetic when every score stays
+ * below 15000 (max matrix entry x longest sequence + go + ge < 15000, go + ge
+ * and ge at most 256), else in 32-bit; the
  * sums are the same either way.  HALIGN_STRIP32=1 forces the 32-bit kernel. */
 int halign_center_exact(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
                         int64_t *sums, int32_t *center_host, void *stream);

@@ -1353,8 +1353,9 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const 
 }
 
 // Center selection -----------------------------------------------------------
-// The packed 16-bit score-only strip kernel applies when no H can reach 2^14:
-// max S times the longest sequence stays below 16000 (gap costs small).
+// The packed 16-bit score-only strip kernel applies when every H stays below
+// 15000: max S times the longest sequence (plus go + ge) stays below 15000,
+// and go + ge <= 256.
 // HALIGN_STRIP32=1 keeps the 32-bit kernel (tests of both paths).
 static bool strip16_ok(const Scoring &S, const halign_seqs *sq) {
     const char *e = getenv("HALIGN_STRIP32");
@@ -1363,7 +1364,7 @@ static bool strip16_ok(const Scoring &S, const halign_seqs *sq) {
     for (int x = 0; x < S.alpha * S.alpha; ++x) smax = std::max(smax, (int)S.hmat[x]);
     int64_t lmax = 0;
     for (int k = 0; k < sq->n; ++k) lmax = std::max(lmax, sq->offsets_host[k + 1] - sq->offsets_host[k]);
-    return S.goe <= 4096 && S.ge <= 4096 && (int64_t)smax * lmax + S.goe < 16000;
+    return S.goe <= 256 && S.ge <= 256 && (int64_t)smax * lmax + S.goe < 15000;
 }
 
 // Groups: one center, 64 partners (32-bit kernel) or 128 (16-bit kernel).

@@ -258,25 +258,44 @@ sw_inter_kernel(InterArgs a) {
 // Each lane scores two pairs of the group at once, pair A (partner gb0+lane)
 // in the low and pair B (partner gb0+64+lane) in the high half of every
 // register, with v_pk_* 16-bit integer ops: a group holds 128 partners.
-// E and F are carried unclamped (they never fall below -(go+ge), since
-// E(i,j) >= H(i,j-1) - goe), and H = max(H(i-1,j-1) + S, E, F, 0):
-//   eext = e - ge; en = max(eext, Hg); fext = F - ge; fn = max(fext, Hg_up);
-//   hd = Hg_diag + P; h = max(max(hd, en), max(fn, 0)); Hg = h - goe
-// that is 10 packed ops per two cells with the running maximum.  The host
-// uses this kernel only when every H stays below 2^14 (max S * longest
-// sequence < 16000), so that no value wraps and a padding profile entry of
-// -2^14 can never be a source.  The profile (int16 [r][16]) of the two
-// lanes' residues is interleaved into (A, B) pairs with v_perm_b32.
+// E* and F* are clamped at 0 as in the 32-bit kernel, and all values are
+// biased (below) so that each three-way maximum is one v_pk_maximum3_f16:
+//   eext = e - ge; en = max(eext, Hg, 0); fext = F - ge; fn = max(fext, Hg_up, 0);
+//   hd = Hg_diag + P; h = max(hd, en, fn); Hg = h - goe
+// that is 8 packed ops per two cells plus half a maximum for the running
+// maximum.  The host uses this kernel only when every H stays below 15000
+// (max S * longest sequence + go + ge < 15000), so that no biased value
+// leaves [0, 0x7c00) and a padding profile entry can never be a source.  The
+// profile (int16 [r][16]) of the two lanes' residues is interleaved into
+// (A, B) pairs with v_perm_b32.
 // Strip boundaries per lane and column: packed Hg and packed F (int2) and the
 // two residue codes (uint16), written by every strip and read by the next one
 // with agent-scope loads (as in the 32-bit kernel).
 // ---------------------------------------------------------------------------
 typedef short pk16 __attribute__((ext_vector_type(2)));
-constexpr int kNegProf16 = -(1 << 14);
 
 __device__ __forceinline__ pk16 as_pk(uint32_t x) { return __builtin_bit_cast(pk16, x); }
 __device__ __forceinline__ uint32_t as_u(pk16 x) { return __builtin_bit_cast(uint32_t, x); }
 __device__ __forceinline__ pk16 pmax(pk16 a, pk16 b) { return __builtin_elementwise_max(a, b); }
+
+// Biased 16-bit values: every H, E*, F* and H - go - ge is held plus
+// kBias16, which keeps each operand of the three-way maxima a non-negative
+// 16-bit pattern below 0x7c00 (a finite non-negative half), whose order as a
+// half is its order as an integer.  The host bound H < 15000 gives values in
+// [kBias16 - 512, kBias16 + 15000); a padding entry of kPadProf16 makes H - go
+// - ge + pad below kBias16, so it never wins against the floor, and at least
+// 0.
+constexpr int kBias16 = 15616;
+constexpr int kPadProf16 = -15360;
+
+// max(a, b, c) per half with one v_pk_maximum3_f16 (operands as above)
+__device__ __forceinline__ pk16 max3h(pk16 a, pk16 b, pk16 c) {
+    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+    const h2 r = __builtin_elementwise_maximum(
+        __builtin_elementwise_maximum(__builtin_bit_cast(h2, a), __builtin_bit_cast(h2, b)), __builtin_bit_cast(h2, c));
+    return __builtin_bit_cast(pk16, r);
+}
+
 
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 sw_inter16_kernel(InterArgs a) {
@@ -294,8 +313,8 @@ sw_inter16_kernel(InterArgs a) {
     uint16_t *bres = reinterpret_cast<uint16_t *>(bnd + a.bstride);
     const pk16 ge2 = pk16{(short)a.ge, (short)a.ge};
     const pk16 goe2 = pk16{(short)a.goe, (short)a.goe};
-    const pk16 zero2 = pk16{0, 0};
-    const pk16 init2 = pk16{(short)-a.goe, (short)-a.goe};
+    const pk16 bias2 = pk16{(short)kBias16, (short)kBias16};             // 0, biased
+    const pk16 init2 = pk16{(short)(kBias16 - a.goe), (short)(kBias16 - a.goe)};   // -go - ge, biased
     for (;;) {
         __syncthreads();
         if (lane == 0) s_next = atomicAdd(a.counter, 1);
@@ -324,13 +343,13 @@ sw_inter16_kernel(InterArgs a) {
         const int nstrips = (m + kT - 1) / kT;
         const int nmaxp = (nmax + kB - 1) / kB * kB;
         const int la = max(na - 1, 0), lb = max(nb - 1, 0);
-        pk16 hmax = zero2;
+        pk16 hmax = bias2;
         for (int st = 0; st < nstrips && nmax > 0; ++st) {
             const int i0 = st * kT;
             __syncthreads();
             for (int x = lane; x < kAlphaMax * 8; x += 64) {
                 const int r = x >> 3, t = 2 * (x & 7);
-                int v0 = kNegProf16, v1 = kNegProf16;
+                int v0 = kPadProf16, v1 = kPadProf16;
                 if (r < a.alpha && i0 + t < m) v0 = (int)smat[(cen[i0 + t] & 31) * 32 + r] + a.goe;
                 if (r < a.alpha && i0 + t + 1 < m) v1 = (int)smat[(cen[i0 + t + 1] & 31) * 32 + r] + a.goe;
                 prof[x] = (uint32_t)(v0 & 0xffff) | ((uint32_t)v1 << 16);
@@ -382,17 +401,19 @@ sw_inter16_kernel(InterArgs a) {
                         const uint4 a0 = pa4[0], a1 = pa4[1], b0 = pb4[0], b1 = pb4[1];
                         const uint32_t wa[8] = {a0.x, a0.y, a0.z, a0.w, a1.x, a1.y, a1.z, a1.w};
                         const uint32_t wb[8] = {b0.x, b0.y, b0.z, b0.w, b1.x, b1.y, b1.z, b1.w};
+                        pk16 hh0 = bias2;
 #pragma unroll
                         for (int k = 0; k < 8; ++k) {
 #pragma unroll
                             for (int h = 0; h < 2; ++h) {
                                 const int t = 2 * k + h;
                                 const pk16 p = as_pk(__builtin_amdgcn_perm(wb[k], wa[k], h ? 0x07060302u : 0x05040100u));
-                                const pk16 en = pmax(e[t] - ge2, hg[t]);
-                                const pk16 fn = pmax(upf - ge2, upg);
+                                const pk16 en = max3h(e[t] - ge2, hg[t], bias2);
+                                const pk16 fn = max3h(upf - ge2, upg, bias2);
                                 const pk16 hd = diag + p;
-                                const pk16 hh = pmax(pmax(hd, en), pmax(fn, zero2));
-                                hmax = pmax(hmax, hh);
+                                const pk16 hh = max3h(hd, en, fn);
+                                if (h) hmax = max3h(hmax, hh0, hh);
+                                else hh0 = hh;
                                 diag = hg[t];
                                 hg[t] = hh - goe2;
                                 e[t] = en;
@@ -418,8 +439,8 @@ sw_inter16_kernel(InterArgs a) {
             else strip(std::false_type{});
         }
         const uint32_t hm = as_u(hmax);
-        const int va = sa >= 0 ? (int)(hm & 0xffff) : 0;
-        const int vb = sb >= 0 ? (int)(hm >> 16) : 0;
+        const int va = sa >= 0 ? (int)(hm & 0xffff) - kBias16 : 0;
+        const int vb = sb >= 0 ? (int)(hm >> 16) - kBias16 : 0;
         if (a.mode == 1) {
             if (sa >= 0) atomicAdd(reinterpret_cast<unsigned long long *>(a.sums + sa), (unsigned long long)va);
             if (sb >= 0) atomicAdd(reinterpret_cast<unsigned long long *>(a.sums + sb), (unsigned long long)vb);

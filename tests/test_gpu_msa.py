@@ -182,7 +182,7 @@ def test_center_judge_groups(H, ctx, strip):
 
 
 def test_center_exact_long_falls_back(H, ctx):
-    """11 x 1500 >= 16000: the 16-bit bound fails and the 32-bit kernel runs."""
+    """11 x 1500 >= 15000: the 16-bit bound fails and the 32-bit kernel runs."""
     import torch
     rng = np.random.default_rng(3)
     root = rng.integers(0, 20, 1500).astype(np.uint8)
@@ -195,6 +195,25 @@ def test_center_exact_long_falls_back(H, ctx):
     c = H.halign_center_exact(ctx, H.Scoring(), ds, d)
     assert c == best
     assert (d.cpu().numpy() == sums).all()
+
+
+def test_center_exact_at_the_bound(H, ctx, strip):
+    """Scores up to the 16-bit kernel's bound (max S x longest + go + ge <
+    15000): tryptophan runs of 1362 residues (S = 11) score 14,982 against
+    each other, with mutated copies, a shorter run and an unrelated sequence."""
+    import torch
+    rng = np.random.default_rng(5)
+    w = np.full(1362, 17, np.uint8)   # W in the NCBI order
+    mut = w.copy()
+    mut[rng.integers(0, 1362, 100)] = rng.integers(0, 20, 100).astype(np.uint8)
+    seqs = synth.SeqSet.from_list([w, mut, w.copy(), w[:900].copy(), rng.integers(0, 20, 400).astype(np.uint8)])
+    best, sums = oracle.center_exact(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets)
+    ds = H.DeviceSeqs(seqs)
+    d = torch.empty(seqs.n, dtype=torch.int64, device="cuda")
+    c = H.halign_center_exact(ctx, H.Scoring(), ds, d)
+    assert c == best
+    assert (d.cpu().numpy() == sums).all()
+    assert sums[0] >= 2 * 14982
 
 
 def test_center_judge(H, ctx, strip):
