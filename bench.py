@@ -241,8 +241,8 @@ def main():
     ap.add_argument("--ema", type=float, default=0.0, help="parameter average decay (0: off)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU design "
-              "is described in DESIGN.md and is not built.", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no "
+              "multi-GPU path (pairs would shard over GPUs; that is a design, not code).", file=sys.stderr)
         sys.exit(2)
 
     import torch
