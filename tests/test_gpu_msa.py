@@ -256,15 +256,23 @@ def test_sp_score_random(H):
     assert spb == oracle.sp_blosum(synth.BLOSUM62, 1, a)
 
 
-def test_batch20k_full_size(H, ctx):
-    """The benchmark's workload and launch configuration: every row restores
-    its input, G and the width follow from the vectors, and 300 sampled pairs
-    equal the oracle bit for bit."""
+@pytest.mark.parametrize("plan", ["default", "packed"])
+def test_batch20k_full_size(H, ctx, plan, monkeypatch):
+    """The benchmark's workload and launch configuration (the plan its tuner
+    picks: the packed 16-bit kernel with 10 rows per lane on 32-lane streams;
+    and the untuned default): every row restores its input, G and the width
+    follow from the vectors, and 300 sampled pairs equal the oracle bit for
+    bit."""
     import torch
+    if plan == "packed":
+        monkeypatch.setenv("HALIGN_STREAM_LANES", "32")
+        monkeypatch.setenv("HALIGN_STREAM_PACK", "1")
     seqs = synth.generate("batch20k")
     ds = H.DeviceSeqs(seqs)
     sc = H.Scoring()
     out = H.sw_batch(ctx, sc, ds, 0, traceback=True)
+    if plan == "packed":   # 32-lane streams of ceil(311 / 32) = 10 rows, packed
+        assert ctx.last_plan()["packed"] == 1
     msa, c = H.halign_msa(ctx, sc, ds, 0)
     torch.cuda.synchronize()
     score = out["score"].cpu().numpy()
