@@ -2,42 +2,41 @@
 // the wavefront kernel (sw_kernels.hpp) with two streams per lane group.
 // Lane group g of a wavefront runs stream 2q (A) in the low and stream 2q+1
 // (B) in the high half of every register, q = wave * NS + g, with v_pk_* 16-bit
-// integer ops.  The lane group's columns are the longer stream's; the other
-// half runs padding columns after its last pair.
+// ops.  The lane group's columns are the longer stream's; the other half runs
+// padding columns after its last pair.
 //
 // Recurrence as in the 32-bit kernels (E* and F* clamped at 0), on values
 // held plus a bias so that each of E*, F* and H is one v_pk_maximum3_f16 on
-// their bit patterns: 8 packed ops per two cells.
-// The host uses this kernel only when every H stays below 15000 (max S *
-// min(m, longest sequence) < 15000, go + ge <= 256), so no value or
-// difference wraps and a padding profile entry is never a source.  The four flags of a cell are the signs of four packed
-// differences.  v_perm_b32 with byte selectors 8..11 turns the signs of two
-// packed differences into four 0x00/0xff bytes, one per flag and half, so
-// two perms give all eight flags of a row pair, and two v_bfi_b32 with
-// constant masks drop them into their bits of a word that holds 4 rows of
-// both pairs: WQ = ceil(R/4) words per step, word q holding rows 4q.. of the
-// lane.  Row t (k = t mod 4) of half h: byte h holds notd at bit 2k and note
-// at bit 2k + 1, byte 2 + h holds eext at bit 2k and fext at bit 2k + 1.
-// Tiles and the step-to-column rule are the wavefront kernel's
-// with WQ words per step; each lane stages 4 steps in LDS and stores them as
-// half a tile.  With E* and F* clamped as there, every flag equals the 32-bit
-// kernel's.
+// their bit patterns: 8 packed ops per two cells.  The host uses this kernel
+// only when every H stays below 15000 (max S * min(m, longest sequence) <
+// 15000, go + ge <= 256), so no value or difference wraps and a padding
+// profile entry is never a source.
 //
-// End cells stay packed: per step one v_pk_maximum3_f16 per two rows gives the step
-// maximum of each half, its sign against the running best gives a 16-bit
-// mask per half, and where it is set the step and the lane's rows are
-// copied (v_bfi_b32).  The first step that reaches the best H is the
-// smallest column, and at publication the smallest row of that step holding
-// the best H completes the key (max H, then min j, then min i per lane).
-// This needs R more registers; above R = 11 both halves unpack H into 32-bit
-// keys (H << 5 | 31 - t) per row instead, as the 32-bit kernel does.
+// The four flags of a cell are the signs of four packed differences.
+// v_perm_b32 with byte selectors 8..11 turns the signs of two packed
+// differences into four 0x00/0xff bytes, one per flag and half, so two perms
+// give all eight flags of a row pair, and two v_bfi_b32 with constant masks
+// drop them into their bits of a word that holds 4 rows of both pairs:
+// WQ = ceil(R/4) words per step, word q holding rows 4q.. of the lane.  Row t
+// (k = t mod 4) of half h: byte h holds notd at bit 2k and note at bit 2k + 1,
+// byte 2 + h holds eext at bit 2k and fext at bit 2k + 1.  Tiles and the
+// step-to-column rule are the wavefront kernel's with WQ words per step; each
+// lane stages 4 steps in LDS and stores them as half a tile.  With E* and F*
+// clamped as there, every flag equals the 32-bit kernel's.
+//
+// End cells stay packed: per step one v_pk_maximum3_f16 per two rows gives
+// the step maximum of each half, its sign against the running best gives a
+// 16-bit mask per half, and where it is set the step and the lane's rows are
+// copied (v_bfi_b32).  The first step that reaches the best H is the smallest
+// column, and at publication the smallest row of that step holding the best H
+// completes the key (max H, then min j, then min i per lane).  This needs R
+// more registers; above R = 11 both halves unpack H into 32-bit keys
+// (H << 5 | 31 - t) per row instead, as the 32-bit kernel does.
 #pragma once
 #include "sw_kernels.hpp"
 #include "strip_kernels.hpp"
 
 namespace hk {
-
-typedef unsigned short pku16 __attribute__((ext_vector_type(2)));
 
 // bitwise select m ? x : y (written out: with a mask known to be whole
 // halves, the compiler would select per half with compares instead)
