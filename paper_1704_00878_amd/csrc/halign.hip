@@ -482,12 +482,13 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         size_t code_words = 0, bound_elems = 0;
         int nmax_all = 0;
         nmax_all = plen[lo];
-        // strip route: per-pid walk descriptors and the walk list (the
-        // wavefront route's walk reads the per-slot and per-stream plan)
+        // strip route: the walk list and its walk descriptors, both in walk
+        // order (the wavefront route's walk reads the per-slot and per-stream
+        // plan)
         const bool strip_plan = route != kRouteIntra;
-        const size_t o_cbase = strip_plan ? pb.add(sizeof(int64_t) * N) : 0,
-                     o_cstr = strip_plan ? pb.add(sizeof(int32_t) * N) : 0,
-                     o_ccol = strip_plan ? pb.add(sizeof(int32_t) * N) : 0,
+        const size_t o_cbase = strip_plan ? pb.add(sizeof(int64_t) * cn) : 0,
+                     o_cstr = strip_plan ? pb.add(sizeof(int32_t) * cn) : 0,
+                     o_ccol = strip_plan ? pb.add(sizeof(int32_t) * cn) : 0,
                      o_walk = strip_plan ? pb.add(sizeof(int32_t) * cn) : 0;
         size_t o_sbeg = 0, o_slot0 = 0, o_scb = 0, o_sbb = 0, o_spid = 0, o_scol = 0;
         size_t o_order = 0, o_gnmax = 0, o_gcb = 0;
@@ -600,18 +601,17 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                 int nmax = 0;
                 for (int l = 0; l < 64; ++l) {
                     const int x = lo + g * 64 + l;
-                    const int pid = x < hi ? pids[x] : -1;
-                    h_order[g * 64 + l] = pid;
-                    if (pid >= 0) nmax = std::max(nmax, len(pid));
+                    h_order[g * 64 + l] = x < hi ? pids[x] : -1;
+                    if (x < hi) nmax = std::max(nmax, plen[x]);
                 }
                 h_gnmax[g] = nmax;
                 h_gcb[g] = (int64_t)code_words;
-                for (int l = 0; l < 64; ++l) {
-                    const int pid = h_order[g * 64 + l];
-                    if (pid < 0) continue;
-                    h_cbase[pid] = (int64_t)code_words;
-                    h_ccol[pid] = l;
-                    h_cstr[pid] = nmax;
+                // walk entry q = g * 64 + l is the pair in lane l of group g
+                for (int l = 0; l < 64 && lo + g * 64 + l < hi; ++l) {
+                    const int q = g * 64 + l;
+                    h_cbase[q] = (int64_t)code_words;
+                    h_ccol[q] = l;
+                    h_cstr[q] = nmax;
                 }
                 if (tb) code_words += (size_t)nst * ((nmax + 3) / 4) * 512;
             }

@@ -32,9 +32,9 @@ struct WalkArgs {
     const int32_t *endcell;   // [N][2]
     const uint32_t *codes;
     // layout per pair id: kind 0 = wavefront (R rows/lane), 1 = strip (16 rows)
-    const int64_t *cbase;     // word base of the stream / group
-    const int32_t *ccol;      // wavefront: first stream column of the pair; strip: lane in group
-    const int32_t *cstride;   // wavefront: steps per pass (C+63); strip: nmax of the group
+    const int64_t *cbase;     // strip, per walk entry: word base of the group
+    const int32_t *ccol;      // strip, per walk entry: lane in the group
+    const int32_t *cstride;   // strip, per walk entry: nmax of the group
     int R;                    // wavefront rows per lane
     int kind;
     int32_t *cells;           // [N][4]
@@ -109,9 +109,9 @@ walk_kernel(WalkArgs a) {
     int half = 0;   // packed wavefront layout: the stream's half of each code word
     int ccol, stride;
     if (STRIP) {
-        base = a.cbase[pid];
-        ccol = a.ccol[pid];
-        stride = a.cstride[pid];
+        base = a.cbase[w];
+        ccol = a.ccol[w];
+        stride = a.cstride[w];
     } else {   // stream of slot w: the last s with slot0[s] <= w
         int lo = 0, hi = a.nstreams - 1;
         while (lo < hi) {
