@@ -490,7 +490,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                      o_cstr = strip_plan ? pb.add(sizeof(int32_t) * cn) : 0,
                      o_ccol = strip_plan ? pb.add(sizeof(int32_t) * cn) : 0,
                      o_walk = strip_plan ? pb.add(sizeof(int32_t) * cn) : 0;
-        size_t o_sbeg = 0, o_slot0 = 0, o_scb = 0, o_sbb = 0, o_spid = 0, o_scol = 0;
+        size_t o_sbeg = 0, o_slot0 = 0, o_scb = 0, o_sbb = 0, o_spid = 0, o_scol = 0, o_sstr = 0;
         size_t o_order = 0, o_gnmax = 0, o_gcb = 0;
         int nstreams = 0, nslots = 0, ngroups = 0;
         int64_t total_cols = 0;
@@ -514,6 +514,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             o_sbb = pb.add(sizeof(int64_t) * nstreams);
             o_spid = pb.add(sizeof(int32_t) * nslots);
             o_scol = pb.add(sizeof(int64_t) * nslots);
+            o_sstr = pb.add(sizeof(int32_t) * nslots);
         } else {
             ngroups = (cn + 63) / 64;
             o_order = pb.add(sizeof(int32_t) * (size_t)ngroups * 64);
@@ -535,6 +536,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             int64_t *h_sbb = (int64_t *)(hs + o_sbb);
             int32_t *h_spid = (int32_t *)(hs + o_spid);
             int64_t *h_scol = (int64_t *)(hs + o_scol);
+            int32_t *h_sstr = (int32_t *)(hs + o_sstr);   // stream of each slot (for the walk)
             // stream of each non-empty pair (snake order), then slots grouped by stream
             std::vector<int32_t> scount(nstreams, 0), sfill(nstreams, 0);
             std::vector<int64_t> scols(nstreams, 0);
@@ -584,11 +586,13 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                 if (s < 0) {
                     h_spid[eslot] = pid;
                     h_scol[eslot] = 0;
+                    h_sstr[eslot] = 0;
                     ++eslot;
                     continue;
                 }
                 const int q = h_slot0[s] + sfill[s]++;
                 h_spid[q] = pid;
+                h_sstr[q] = s;
                 h_scol[q] = h_sbeg[s] + spos[s];
                 spos[s] += plen[lo + x];
             }
@@ -711,6 +715,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                 w.slot_col = (const int64_t *)(dplan + o_scol);
                 w.sbeg = (const int64_t *)(dplan + o_sbeg);
                 w.slot0 = (const int32_t *)(dplan + o_slot0);
+                w.slot_stream = (const int32_t *)(dplan + o_sstr);
                 w.scb = (const int64_t *)(dplan + o_scb);
                 w.nstreams = nstreams;
             }

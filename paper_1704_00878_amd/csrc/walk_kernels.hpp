@@ -51,6 +51,7 @@ struct WalkArgs {
     const int64_t *slot_col;
     const int64_t *sbeg;      // [nstreams + 1]
     const int32_t *slot0;     // [nstreams]
+    const int32_t *slot_stream;   // [slots] the stream s of each slot
     const int64_t *scb;       // [nstreams] code word base
     int nstreams;
     int lg_ls;                // log2 of the lanes per stream (wavefront layout)
@@ -112,13 +113,8 @@ walk_kernel(WalkArgs a) {
         base = a.cbase[w];
         ccol = a.ccol[w];
         stride = a.cstride[w];
-    } else {   // stream of slot w: the last s with slot0[s] <= w
-        int lo = 0, hi = a.nstreams - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (a.slot0[mid] <= w) lo = mid;
-            else hi = mid - 1;
-        }
+    } else {   // stream of slot w
+        const int lo = a.slot_stream[w];
         base = a.scb[lo];
         ccol = (int)(a.slot_col[w] - a.sbeg[lo]);
         int cs = (int)(a.sbeg[lo + 1] - a.sbeg[lo]);
