@@ -494,12 +494,12 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         size_t o_order = 0, o_gnmax = 0, o_gcb = 0;
         int nstreams = 0, nslots = 0, ngroups = 0;
         int64_t total_cols = 0;
+        int nonempty = 0;   // pairs [0, nonempty) of the chunk are non-empty: empty pairs sort last
+        for (int x = hi - 1; x >= lo && plen[x] == 0; --x) ++nonempty;
+        nonempty = cn - nonempty;
         if (route == kRouteIntra) {
             // streams: snake-deal the (longest first) non-empty pairs over the
             // resident waves so that every stream has about the same columns
-            int nonempty = 0;
-            for (int x = hi - 1; x >= lo && plen[x] == 0; --x) ++nonempty;
-            nonempty = cn - nonempty;   // empty pairs sort last
             const int wg_per_cu = std::max(1, std::min(4, (int)(ctx->lds_max / lds_stream)));
             const int resident = ctx->num_cu * wg_per_cu * 8 * NS * std::max(1, tune.smul) * (pk ? 2 : 1);
             nstreams = std::max(1, std::min(nonempty, (int)std::max(1.0, resident * tune.scale)));
@@ -537,18 +537,16 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             int32_t *h_spid = (int32_t *)(hs + o_spid);
             int64_t *h_scol = (int64_t *)(hs + o_scol);
             int32_t *h_sstr = (int32_t *)(hs + o_sstr);   // stream of each slot (for the walk)
-            // stream of each non-empty pair (snake order), then slots grouped by stream
-            std::vector<int32_t> scount(nstreams, 0), sfill(nstreams, 0);
+            // pairs and columns of each stream (snake order), then slots grouped by stream
+            // (the k-th non-empty pair, k = r * nstreams + q, goes to stream q in
+            // even rounds r and nstreams - 1 - q in odd ones)
+            std::vector<int32_t> scount(nstreams, 0);
             std::vector<int64_t> scols(nstreams, 0);
-            std::vector<int32_t> sof(cn, -1);
             int r = 0, q = 0;   // round and position of the next non-empty pair
-            for (int x = 0; x < cn; ++x) {
-                const int n = plen[lo + x];
-                if (n == 0) continue;
+            for (int x = 0; x < nonempty; ++x) {
                 const int s = (r & 1) ? nstreams - 1 - q : q;
-                sof[x] = s;
                 scount[s]++;
-                scols[s] += n;
+                scols[s] += plen[lo + x];
                 if (++q == nstreams) { q = 0; ++r; }
             }
             int slot = 0;
@@ -578,23 +576,22 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             }
             h_sbeg[nstreams] = col;
             total_cols = col;
-            std::vector<int64_t> spos(nstreams, 0);   // column within stream
-            int eslot = slot;                         // empty pairs after the streamed ones
-            for (int x = 0; x < cn; ++x) {
-                const int pid = pids[lo + x];
-                const int s = sof[x];
-                if (s < 0) {
-                    h_spid[eslot] = pid;
-                    h_scol[eslot] = 0;
-                    h_sstr[eslot] = 0;
-                    ++eslot;
-                    continue;
+            // slots stream by stream (sequential writes): the pl-th pair of
+            // stream s is non-empty pair pl * nstreams + (pl odd ? nstreams - 1 - s : s)
+            for (int s = 0; s < nstreams; ++s) {
+                int64_t c = h_sbeg[s];
+                for (int pl = 0, qs = h_slot0[s]; pl < scount[s]; ++pl, ++qs) {
+                    const int x = pl * nstreams + ((pl & 1) ? nstreams - 1 - s : s);
+                    h_spid[qs] = pids[lo + x];
+                    h_scol[qs] = c;
+                    h_sstr[qs] = s;
+                    c += plen[lo + x];
                 }
-                const int q = h_slot0[s] + sfill[s]++;
-                h_spid[q] = pid;
-                h_sstr[q] = s;
-                h_scol[q] = h_sbeg[s] + spos[s];
-                spos[s] += plen[lo + x];
+            }
+            for (int x = nonempty; x < cn; ++x) {   // empty pairs after the streamed ones
+                h_spid[x] = pids[lo + x];
+                h_scol[x] = 0;
+                h_sstr[x] = 0;
             }
         } else {
             int32_t *h_order = (int32_t *)(hs + o_order);
