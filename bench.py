@@ -88,7 +88,7 @@ def cpu_baseline(seqs, center: int, budget_s: float = 20.0):
 
 # kernel -> the sources its counter records are tied to
 KERNEL_SOURCES = {"sw_stream_kernel": ["sw_kernels.hpp"],
-                  "sw_stream16_kernel": ["stream16_kernels.hpp", "sw_kernels.hpp", "strip_kernels.hpp"]}
+                  "sw_stream16_kernel": ["stream16_kernels.hpp", "sw_kernels.hpp", "pk16.hpp"]}
 
 
 def kernel_source_sha(kernel: str):

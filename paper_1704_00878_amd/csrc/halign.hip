@@ -20,11 +20,11 @@
 #include <vector>
 
 #include "../../include/halign.h"
+#include "launch.hpp"
 #include "msa_kernels.hpp"
-#include "sw_kernels.hpp"
+#include "plan_kernels.hpp"
 #include "strip_kernels.hpp"
 #include "walk_kernels.hpp"
-#include "stream16_kernels.hpp"
 #include "mlp_kernels.hpp"
 
 namespace {
@@ -47,6 +47,11 @@ int fail(int code, const char *fmt, ...) {
         if (e_ != hipSuccess)                                                        \
             return fail(HALIGN_E_DEVICE, "%s failed: %s", #expr, hipGetErrorString(e_)); \
     } while (0)
+
+using hk::launch_stream;
+using hk::launch_stream16;
+using hk::stream16_supported;
+using hk::stream_supported;
 
 #define RCHK(expr)                 \
     do {                           \
@@ -238,93 +243,6 @@ void pick_geom(int m, int *R, int *passes) {
     const int p = std::max(1, (m + 511) / 512);
     *passes = p;
     *R = std::max(1, std::min(8, (m + 64 * p - 1) / (64 * p)));
-}
-
-template <int R, int LS, bool P16>
-void launch_stream_RLP(const hk::StreamArgs &a, bool tb, bool endc, int grid, size_t lds, hipStream_t st) {
-    if (tb)
-        hipLaunchKernelGGL((hk::sw_stream_kernel<R, LS, true, true, P16>), dim3(grid), dim3(512), lds, st, a);
-    else if (endc)
-        hipLaunchKernelGGL((hk::sw_stream_kernel<R, LS, false, true, P16>), dim3(grid), dim3(512), lds, st, a);
-    else
-        hipLaunchKernelGGL((hk::sw_stream_kernel<R, LS, false, false, P16>), dim3(grid), dim3(512), lds, st, a);
-}
-
-// instantiated geometries: 64-lane streams with R = 1..8 (int16 or int32
-// profile); 32- and 16-lane streams with R = 2..16 (int16 profile)
-bool stream_supported(int R, int LS, bool p16) {
-    if (LS == 64) return R >= 1 && R <= 8;
-    return (LS == 32 || LS == 16) && p16 && R >= 2 && R <= 16;
-}
-
-template <int R>
-void launch_stream_R(int LS, const hk::StreamArgs &a, bool tb, bool endc, bool p16, int grid, size_t lds,
-                     hipStream_t st) {
-    if constexpr (R <= 8) {
-        if (LS == 64) {
-            if (p16) launch_stream_RLP<R, 64, true>(a, tb, endc, grid, lds, st);
-            else launch_stream_RLP<R, 64, false>(a, tb, endc, grid, lds, st);
-            return;
-        }
-    }
-    if constexpr (R >= 2) {
-        if (LS == 32) launch_stream_RLP<R, 32, true>(a, tb, endc, grid, lds, st);
-        else launch_stream_RLP<R, 16, true>(a, tb, endc, grid, lds, st);
-    }
-}
-
-void launch_stream(int R, int LS, const hk::StreamArgs &a, bool tb, bool endc, bool p16, int grid, size_t lds,
-                   hipStream_t st) {
-    switch (R) {
-        case 1: launch_stream_R<1>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 2: launch_stream_R<2>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 3: launch_stream_R<3>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 4: launch_stream_R<4>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 5: launch_stream_R<5>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 6: launch_stream_R<6>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 7: launch_stream_R<7>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 8: launch_stream_R<8>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 9: launch_stream_R<9>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 10: launch_stream_R<10>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 11: launch_stream_R<11>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 12: launch_stream_R<12>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 13: launch_stream_R<13>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 14: launch_stream_R<14>(LS, a, tb, endc, p16, grid, lds, st); break;
-        case 15: launch_stream_R<15>(LS, a, tb, endc, p16, grid, lds, st); break;
-        default: launch_stream_R<16>(LS, a, tb, endc, p16, grid, lds, st); break;
-    }
-}
-
-// Packed 16-bit wavefront kernel (traceback with end cells only): 32- and
-// 16-lane streams, R = 2..16.
-bool stream16_supported(int R, int LS) { return (LS == 32 || LS == 16) && R >= 2 && R <= 16; }
-
-template <int R>
-void launch_stream16_R(int LS, const hk::StreamArgs &a, int grid, size_t lds, hipStream_t st) {
-    if constexpr (R >= 2) {
-        if (LS == 32) hipLaunchKernelGGL((hk::sw_stream16_kernel<R, 32>), dim3(grid), dim3(512), lds, st, a);
-        else hipLaunchKernelGGL((hk::sw_stream16_kernel<R, 16>), dim3(grid), dim3(512), lds, st, a);
-    }
-}
-
-void launch_stream16(int R, int LS, const hk::StreamArgs &a, int grid, size_t lds, hipStream_t st) {
-    switch (R) {
-        case 2: launch_stream16_R<2>(LS, a, grid, lds, st); break;
-        case 3: launch_stream16_R<3>(LS, a, grid, lds, st); break;
-        case 4: launch_stream16_R<4>(LS, a, grid, lds, st); break;
-        case 5: launch_stream16_R<5>(LS, a, grid, lds, st); break;
-        case 6: launch_stream16_R<6>(LS, a, grid, lds, st); break;
-        case 7: launch_stream16_R<7>(LS, a, grid, lds, st); break;
-        case 8: launch_stream16_R<8>(LS, a, grid, lds, st); break;
-        case 9: launch_stream16_R<9>(LS, a, grid, lds, st); break;
-        case 10: launch_stream16_R<10>(LS, a, grid, lds, st); break;
-        case 11: launch_stream16_R<11>(LS, a, grid, lds, st); break;
-        case 12: launch_stream16_R<12>(LS, a, grid, lds, st); break;
-        case 13: launch_stream16_R<13>(LS, a, grid, lds, st); break;
-        case 14: launch_stream16_R<14>(LS, a, grid, lds, st); break;
-        case 15: launch_stream16_R<15>(LS, a, grid, lds, st); break;
-        default: launch_stream16_R<16>(LS, a, grid, lds, st); break;
-    }
 }
 
 // Boundary-row columns per strip-kernel lane: the longest sequence rounded

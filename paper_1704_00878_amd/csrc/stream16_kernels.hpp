@@ -34,24 +34,9 @@
 // (H << 5 | 31 - t) per row instead, as the 32-bit kernel does.
 #pragma once
 #include "sw_kernels.hpp"
-#include "strip_kernels.hpp"
+#include "pk16.hpp"
 
 namespace hk {
-
-// bitwise select m ? x : y (written out: with a mask known to be whole
-// halves, the compiler would select per half with compares instead)
-__device__ __forceinline__ uint32_t bfi(uint32_t m, uint32_t x, uint32_t y) {
-    uint32_t r;
-    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "v"(m), "v"(x), "v"(y));
-    return r;
-}
-
-// the same with a wave-uniform mask in an SGPR
-__device__ __forceinline__ uint32_t bfi_s(uint32_t m, uint32_t x, uint32_t y) {
-    uint32_t r;
-    asm("v_bfi_b32 %0, %1, %2, %3" : "=v"(r) : "s"(m), "v"(x), "v"(y));
-    return r;
-}
 
 template <int R, int LS>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))

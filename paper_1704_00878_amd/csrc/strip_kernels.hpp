@@ -4,6 +4,7 @@
 // wavefront kernel (sw_kernels.hpp).
 #pragma once
 #include "sw_kernels.hpp"
+#include "pk16.hpp"
 
 namespace hk {
 
@@ -272,31 +273,6 @@ sw_inter_kernel(InterArgs a) {
 // two residue codes (uint16), written by every strip and read by the next one
 // with agent-scope loads (as in the 32-bit kernel).
 // ---------------------------------------------------------------------------
-typedef short pk16 __attribute__((ext_vector_type(2)));
-
-__device__ __forceinline__ pk16 as_pk(uint32_t x) { return __builtin_bit_cast(pk16, x); }
-__device__ __forceinline__ uint32_t as_u(pk16 x) { return __builtin_bit_cast(uint32_t, x); }
-__device__ __forceinline__ pk16 pmax(pk16 a, pk16 b) { return __builtin_elementwise_max(a, b); }
-
-// Biased 16-bit values: every H, E*, F* and H - go - ge is held plus
-// kBias16, which keeps each operand of the three-way maxima a non-negative
-// 16-bit pattern below 0x7c00 (a finite non-negative half), whose order as a
-// half is its order as an integer.  The host bound H < 15000 gives values in
-// [kBias16 - 512, kBias16 + 15000); a padding entry of kPadProf16 makes H - go
-// - ge + pad below kBias16, so it never wins against the floor, and at least
-// 0.
-constexpr int kBias16 = 15616;
-constexpr int kPadProf16 = -15360;
-
-// max(a, b, c) per half with one v_pk_maximum3_f16 (operands as above)
-__device__ __forceinline__ pk16 max3h(pk16 a, pk16 b, pk16 c) {
-    typedef _Float16 h2 __attribute__((ext_vector_type(2)));
-    const h2 r = __builtin_elementwise_maximum(
-        __builtin_elementwise_maximum(__builtin_bit_cast(h2, a), __builtin_bit_cast(h2, b)), __builtin_bit_cast(h2, c));
-    return __builtin_bit_cast(pk16, r);
-}
-
-
 __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 sw_inter16_kernel(InterArgs a) {
     __shared__ uint32_t prof[kAlphaMax * 8];   // int16 [r][16], 8 words per residue
