@@ -37,35 +37,47 @@ def log(msg):
 
 def cpu_baseline(seqs, center: int, budget_s: float = 20.0):
     """The oracle, unchanged, on a bounded sample of the same workload: SW with
-    traceback of sequences against the center, split over host threads (each
-    thread runs the single-threaded routine on its own slice)."""
+    traceback of sequences against the center.  Timed on one thread (the
+    oracle's own single-core rate) and on one thread per host core (up to 16,
+    each running the single-threaded routine on its own slice)."""
     import oracle
     from paper_1704_00878_amd import synth
-    cores = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else (os.cpu_count() or 1)
-    cores = max(1, min(cores, 16))
+    host_cores = os.cpu_count() or 1
+    usable = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else host_cores
+    threads = max(1, min(usable, 16))
     c = seqs.seq(center)
     m = len(c)
     lens = seqs.lengths()
-    # size the sample from a short single-thread probe
+    cum = np.cumsum(lens) * m
+
+    def run(sub):
+        oracle.sw_batch(synth.BLOSUM62, synth.GAP_OPEN, synth.GAP_EXTEND, c, sub.residues, sub.offsets)
+
+    # one core: whole passes over a prefix of the set for about 3 s
     probe = seqs.subset(range(min(40, seqs.n)))
     t = time.perf_counter()
-    oracle.sw_batch(synth.BLOSUM62, synth.GAP_OPEN, synth.GAP_EXTEND, c, probe.residues, probe.offsets)
+    run(probe)
     rate1 = m * probe.residues.size / max(time.perf_counter() - t, 1e-6)
-    want_cells = rate1 * cores * budget_s
-    cum = np.cumsum(lens) * m
-    nsamp = int(min(seqs.n, max(cores, np.searchsorted(cum, want_cells))))
+    n1 = int(min(seqs.n, max(1, np.searchsorted(cum, rate1 * 3.0))))
+    one = seqs.subset(range(n1))
+    t = time.perf_counter()
+    run(one)
+    dt1 = time.perf_counter() - t
+    gcups1 = m * int(one.residues.size) / dt1 / 1e9
+    # all threads: about budget_s of CPU work, whole passes until 2 s of wall time
+    want_cells = rate1 * threads * budget_s
+    nsamp = int(min(seqs.n, max(threads, np.searchsorted(cum, want_cells))))
     sample = seqs.subset(range(nsamp))
-    slices = np.array_split(np.arange(nsamp), cores)
+    slices = np.array_split(np.arange(nsamp), threads)
     parts = [sample.subset(sl) for sl in slices if len(sl)]
     err = []
 
     def work(p):
         try:
-            oracle.sw_batch(synth.BLOSUM62, synth.GAP_OPEN, synth.GAP_EXTEND, c, p.residues, p.offsets)
+            run(p)
         except Exception as e:  # pragma: no cover
             err.append(e)
 
-    # whole passes over the sample until about 2 s of wall time have run
     reps = 0
     t = time.perf_counter()
     while True:
@@ -82,8 +94,10 @@ def cpu_baseline(seqs, center: int, budget_s: float = 20.0):
             break
     cells = m * int(sample.residues.size) * reps
     return {"value": cells / dt / 1e9, "unit": "GCUPS", "cores": len(parts), "kind": "oracle",
-            "sample": f"SW+traceback of the first {nsamp} of {seqs.n} sequences against the center, "
-                      f"{reps} pass(es) ({cells:.3e} cells, {dt:.1f} s, one thread per core)"}
+            "host_cores": host_cores, "usable_cores": usable, "value_one_core": round(gcups1, 4),
+            "sample": f"SW+traceback against the center: one thread on the first {n1} sequences "
+                      f"({m * int(one.residues.size):.3e} cells, {dt1:.1f} s); {len(parts)} threads on the "
+                      f"first {nsamp} of {seqs.n} sequences, {reps} pass(es) ({cells:.3e} cells, {dt:.1f} s)"}
 
 
 # kernel -> the sources its counter records are tied to

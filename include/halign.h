@@ -133,6 +133,11 @@ int  halign_ctx_set_autotune(halign_ctx *ctx, int enable);
 int  halign_ctx_set_graph(halign_ctx *ctx, int enable);
 int  halign_ctx_graph_launches(const halign_ctx *ctx, int64_t *n_host);
 int  halign_ctx_last_plan(const halign_ctx *ctx, int32_t *plan_host /*[5]*/);
+/* Failure injection for tests of error handling: chunk c (0-based) of the
+ * next halign_sw_batch on this ctx fails with HALIGN_E_DEVICE before its
+ * launch (the call returns the error; the ctx stays usable and a repeated
+ * call gives the full result). */
+int  halign_debug_fail_chunk(halign_ctx *ctx, int c);
 
 /* ---- step a1: encode ASCII to residue codes (upper/lower case; U->C,
  * O->K, other letters -> X).  ascii and codes may alias. */
@@ -190,6 +195,16 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m,
  * sums are the same either way.  HALIGN_STRIP32=1 forces the 32-bit kernel. */
 int halign_center_exact(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
                         int64_t *sums, int32_t *center_host, void *stream);
+/* Group tiling of halign_center_exact (host only, no device needed): all
+ * pairs a < b of n positions (in length order) fall into *ngroups_host groups
+ * of one center position and `step` consecutive partner positions (64 for
+ * the 32-bit kernel, 128 for the packed one), numbered in closed form, so
+ * the search holds O(n) host data.  With g >= 0, group g is decoded into its
+ * center position and first partner position (partners [p0, p0 + step),
+ * those not above the center position are idle).  A caller sharding the
+ * exhaustive search over devices can split [0, *ngroups_host). */
+int halign_exact_tiling(int64_t n, int32_t step, int64_t g, int64_t *ngroups_host, int64_t *center_pos_host,
+                        int64_t *partner0_host);
 /* Exact judge restricted to candidates cand[ncand] (device): sums[q] =
  * sum_{j != cand[q]} SW(seq cand[q], seq j); *center_host = the candidate
  * with the largest sum, ties to the lowest sequence index. */
@@ -238,6 +253,9 @@ int halign_pair_loss(halign_ctx *ctx, const float *E, const float *target, int32
 int halign_mlp_backward(halign_ctx *ctx, const halign_model *model, const uint16_t *X, int32_t nrows,
                         const float *Z, const uint16_t *Hb, const float *dE,
                         float *dW1, float *db1, float *dW2, float *db2, void *stream);
+
+/* bf16 copy (round to nearest even) of n fp32 values: dst[i] = bf16 bits of src[i]. */
+int halign_f32_to_bf16(const float *src, uint16_t *dst, int64_t n, void *stream);
 
 /* Adam (bias-corrected, step t >= 1) on fp32 master weights p[n] with
  * gradient g and moments m, v; writes the bf16 copy pb when non-NULL. */

@@ -63,6 +63,8 @@ def lib():
         for fn in ("orc_sp_pairs", "orc_sp_columns"):
             getattr(L, fn).argtypes = [P, I, ctypes.c_int64]
             getattr(L, fn).restype = ctypes.c_int64
+        L.orc_encode.argtypes = [P, ctypes.c_int64, P]
+        L.orc_encode.restype = None
         L.orc_sp_blosum.argtypes = [P, I, I, P, I, ctypes.c_int64]
         L.orc_sp_blosum.restype = ctypes.c_int64
         _lib = L
@@ -87,6 +89,15 @@ def _check(r: int) -> int:
     if r < 0:
         raise ValueError(f"oracle error {r}")
     return r
+
+
+def encode(text) -> np.ndarray:
+    """Protein text (str or bytes) -> residue codes."""
+    raw = np.frombuffer(text.encode() if isinstance(text, str) else bytes(text), dtype=np.uint8).copy()
+    out = np.zeros(len(raw), np.uint8)
+    if len(raw):
+        lib().orc_encode(_p(raw), len(raw), _p(out))
+    return out
 
 
 def sw(S, go: int, ge: int, c, s, want_ops: bool = False):

@@ -36,6 +36,28 @@ enum { ORC_OK = 0, ORC_EINVAL = -1, ORC_ENOMEM = -2 };
 static int imax(int a, int b) { return a > b ? a : b; }
 
 /* ------------------------------------------------------------------------
+ * Encoding of protein text into residue codes (the sequences the Methods
+ * section distributes are protein letters): code = position of the letter in
+ * the NCBI order ARNDCQEGHILKMFPSTWYVBZX* (upper or lower case); the rare
+ * residues U (selenocysteine) and O (pyrrolysine) take the codes of C and K;
+ * every other byte is X.  A plain search of the order string per byte.
+ * ---------------------------------------------------------------------- */
+void orc_encode(const uint8_t *ascii, int64_t len, uint8_t *codes)
+{
+    static const char order[] = "ARNDCQEGHILKMFPSTWYVBZX*";
+    for (int64_t x = 0; x < len; x++) {
+        int ch = ascii[x];
+        if (ch >= 'a' && ch <= 'z') ch = ch - 'a' + 'A';
+        if (ch == 'U') ch = 'C';
+        if (ch == 'O') ch = 'K';
+        int code = 22;                       /* X */
+        for (int k = 0; k < 24; k++)
+            if (order[k] == ch) { code = k; break; }
+        codes[x] = (uint8_t)code;
+    }
+}
+
+/* ------------------------------------------------------------------------
  * Literal eq. 2 (Methods, Smith-Waterman section) with an arbitrary gap
  * weight table W[1..], O(m n (m + n)).  Returns the best score; fills the
  * full H matrix ((m+1) x (n+1), row-major) when H is non-NULL.

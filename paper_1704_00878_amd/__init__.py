@@ -101,6 +101,8 @@ def lib():
         "halign_mlp_forward": ([P, P, P, I, P, P, P, P], I),
         "halign_pair_loss": ([P, P, P, I, P, P, P], I),
         "halign_mlp_backward": ([P, P, P, I, P, P, P, P, P, P, P, P], I),
+        "halign_f32_to_bf16": ([P, P, I64, P], I),
+        "halign_exact_tiling": ([I64, I, I64, P, P, P], I),
         "halign_adam_step": ([P, P, P, P, P, I64, ctypes.c_float, ctypes.c_float, ctypes.c_float,
                               ctypes.c_float, I, P], I),
         "halign_topk_center": ([P, P, I, I, P, P, P], I),
@@ -117,10 +119,6 @@ def lib():
         fn.restype = res
     _lib = L
     return L
-
-
-def exported_symbols() -> list:
-    return [n for n in ("halign_ctx_create", "halign_ctx_destroy", "halign_last_error")]
 
 
 def _check(rc: int):
@@ -376,11 +374,8 @@ class Proposer:
         self.refresh_bf16()
 
     def refresh_bf16(self):
-        import torch
         for src, dst in ((self.W1, self.W1b), (self.W2, self.W2b)):
-            u = src.contiguous().view(torch.int32).to(torch.int64) & 0xFFFFFFFF
-            r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) & 0xFFFF
-            dst.copy_(r.to(torch.int32).to(torch.int16))
+            halign_f32_to_bf16(src, dst)
 
     def model(self):
         m = _Model(self.W1b.data_ptr(), self.b1.data_ptr(), self.W2b.data_ptr(), self.b2.data_ptr())
@@ -411,6 +406,19 @@ def halign_mlp_backward(ctx: Context, prop: Proposer, X, nrows: int, Z, Hb, dE, 
     m = prop.model()
     _check(lib().halign_mlp_backward(ctx.h, ctypes.byref(m), _ptr(X), nrows, _ptr(Z), _ptr(Hb), _ptr(dE),
                                      _ptr(dW1), _ptr(db1), _ptr(dW2), _ptr(db2), _stream(stream)))
+
+
+def halign_f32_to_bf16(src, dst, stream=None):
+    assert src.is_contiguous() and dst.is_contiguous() and src.numel() == dst.numel()
+    _check(lib().halign_f32_to_bf16(_ptr(src), _ptr(dst), src.numel(), _stream(stream)))
+
+
+def halign_exact_tiling(n: int, step: int, g: int = -1):
+    """Group count of the exhaustive center's tiling and, for g >= 0, the
+    (center position, first partner position) of group g (host only)."""
+    ng, a, b0 = ctypes.c_int64(0), ctypes.c_int64(-1), ctypes.c_int64(-1)
+    _check(lib().halign_exact_tiling(n, step, g, ctypes.byref(ng), ctypes.byref(a), ctypes.byref(b0)))
+    return (int(ng.value), int(a.value), int(b0.value)) if g >= 0 else int(ng.value)
 
 
 def halign_adam_step(p, g, m, v, pb, lr, b1, b2, eps, t, stream=None):

@@ -80,12 +80,17 @@ struct halign_ctx {
     // device scratch
     DevBuf codes, bound, plan, counter, pairbuf, msabuf, spbuf, sbuf;
     DevBuf mlp[10];          // learned-center scratch (features, activations, gradients, moments)
-    // pinned host staging for plans
+    // pinned host staging for plans: regions are taken in order within a
+    // call (stage_off, plan_off) and never reused before the call ends, so the
+    // copies of a captured graph each read their own region
     HostBuf stage;
+    size_t stage_off = 0, plan_off = 0;
     hipEvent_t ev_stage = nullptr;
     bool stage_pending = false;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    float last_ms[3] = {0, 0, 0};
+    // timing of the last call: one (start, forward end, walk end) event
+    // triple per forward launch (chunk, route or graph replay)
+    std::vector<std::array<hipEvent_t, 3>> tev;
+    int ntev = 0;
     int64_t last_stats[4] = {0, 0, 0, 0};
     int fault_chunk = -1;    // test hook: chunk index whose first launch reports failure
     bool capturing = false;   // a hipGraph capture of halign_sw_batch is in progress
@@ -163,14 +168,73 @@ int stage_wait(halign_ctx *ctx) {
     return HALIGN_OK;
 }
 
-int stage_grow(halign_ctx *ctx, size_t bytes) {
+// Start of a call: the previous call's copies have left the pinned stage,
+// whose regions are then taken from its start again; the timing triples
+// restart too.
+int stage_begin(halign_ctx *ctx) {
     RCHK(stage_wait(ctx));
-    if (bytes <= ctx->stage.cap) return HALIGN_OK;
-    if (ctx->stage.p) HCHK(hipHostFree(ctx->stage.p));
-    ctx->stage.p = nullptr;
-    size_t want = std::max(bytes, ctx->stage.cap * 2);
-    HCHK(hipHostMalloc(&ctx->stage.p, want, hipHostMallocDefault));
-    ctx->stage.cap = want;
+    ctx->stage_off = 0;
+    ctx->plan_off = 0;
+    ctx->ntev = 0;
+    return HALIGN_OK;
+}
+
+// `bytes` of the pinned stage, after the regions this call took already.
+int stage_host(halign_ctx *ctx, size_t bytes, char **host) {
+    const size_t o = (ctx->stage_off + 255) & ~size_t(255);
+    if (o + bytes > ctx->stage.cap) {
+        if (ctx->capturing) return fail(HALIGN_E_UNSUPPORTED, "plan staging outgrew its buffer under graph capture");
+        RCHK(stage_wait(ctx));   // the regions taken so far have been copied
+        if (ctx->stage.p) HCHK(hipHostFree(ctx->stage.p));
+        ctx->stage.p = nullptr;
+        ctx->stage.cap = 0;
+        const size_t want = std::max<size_t>(2 * (o + bytes), 1 << 16);
+        HCHK(hipHostMalloc(&ctx->stage.p, want, hipHostMallocDefault));
+        ctx->stage.cap = want;
+    }
+    *host = (char *)ctx->stage.p + o;
+    ctx->stage_off = o + bytes;
+    return HALIGN_OK;
+}
+
+// `bytes` of the device plan buffer, after the regions this call took already
+// (a larger buffer replaces it only once the stream has drained).
+int plan_dev(halign_ctx *ctx, size_t bytes, hipStream_t st, char **dev) {
+    const size_t o = (ctx->plan_off + 255) & ~size_t(255);
+    if (o + bytes > ctx->plan.cap) {
+        if (ctx->capturing) return fail(HALIGN_E_UNSUPPORTED, "plan outgrew its buffer under graph capture");
+        if (ctx->plan.p) HCHK(hipStreamSynchronize(st));
+        RCHK(grow(ctx, ctx->plan, 2 * (o + bytes)));
+    }
+    *dev = (char *)ctx->plan.p + o;
+    ctx->plan_off = o + bytes;
+    return HALIGN_OK;
+}
+
+// The next timing triple of this call (created on first use).
+int tev_next(halign_ctx *ctx, std::array<hipEvent_t, 3> **out) {
+    if (ctx->ntev == (int)ctx->tev.size()) {
+        std::array<hipEvent_t, 3> t{};
+        for (auto &e : t) HCHK(hipEventCreate(&e));
+        ctx->tev.push_back(t);
+    }
+    *out = &ctx->tev[ctx->ntev++];
+    return HALIGN_OK;
+}
+
+// Forward and walk time (ms) summed over the triples of the last call
+// (synchronises on the last one).
+int tev_sum(halign_ctx *ctx, float *fwd, float *walk) {
+    *fwd = *walk = 0.f;
+    if (ctx->ntev == 0) return HALIGN_OK;
+    HCHK(hipEventSynchronize(ctx->tev[ctx->ntev - 1][2]));
+    for (int q = 0; q < ctx->ntev; ++q) {
+        float f = 0.f, w = 0.f;
+        HCHK(hipEventElapsedTime(&f, ctx->tev[q][0], ctx->tev[q][1]));
+        HCHK(hipEventElapsedTime(&w, ctx->tev[q][1], ctx->tev[q][2]));
+        *fwd += f;
+        *walk += w;
+    }
     return HALIGN_OK;
 }
 
@@ -385,13 +449,12 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         }
         chunks.push_back({lo, np});
     }
-    ctx->last_stats[3] = (int64_t)chunks.size();
+    ctx->last_stats[3] += (int64_t)chunks.size();
     const int64_t cells_total = (int64_t)m * sum_len;
-    ctx->last_stats[0] = cells_total;
+    ctx->last_stats[0] += cells_total;
     RCHK(grow(ctx, ctx->counter, 256));
-    int *counter = (int *)ctx->counter.p;
+    unsigned long long *counter = (unsigned long long *)ctx->counter.p;
 
-    float fwd_ms = 0.f, walk_ms = 0.f;
     int64_t launches = 0;
     for (size_t ci = 0; ci < chunks.size(); ++ci) {
         const int lo = chunks[ci].first, hi = chunks[ci].second;
@@ -439,8 +502,8 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             o_gnmax = pb.add(sizeof(int32_t) * ngroups);
             o_gcb = pb.add(sizeof(int64_t) * ngroups);
         }
-        RCHK(stage_grow(ctx, pb.total));
-        char *hs = (char *)ctx->stage.p;
+        char *hs = nullptr;
+        RCHK(stage_host(ctx, pb.total, &hs));
         int32_t *h_walk = (int32_t *)(hs + o_walk);
         int64_t *h_cbase = (int64_t *)(hs + o_cbase);
         int32_t *h_cstr = (int32_t *)(hs + o_cstr);
@@ -535,11 +598,13 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                 if (tb) code_words += (size_t)nst * ((nmax + 3) / 4) * 512;
             }
         }
-        RCHK(grow(ctx, ctx->plan, pb.total));
-        char *dplan = (char *)ctx->plan.p;
+        char *dplan = nullptr;
+        RCHK(plan_dev(ctx, pb.total, st, &dplan));
         HCHK(hipMemcpyAsync(dplan, hs, pb.total, hipMemcpyHostToDevice, st));
         RCHK(record(ctx, ctx->ev_stage, st));
         ctx->stage_pending = true;
+        std::array<hipEvent_t, 3> *tv = nullptr;
+        RCHK(tev_next(ctx, &tv));
 
         if (tb) RCHK(grow(ctx, ctx->codes, std::max<size_t>(4, code_words * 4)));
         if (ctx->fault_chunk == (int)ci) {
@@ -558,7 +623,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                                (const int32_t *)(dplan + o_spid), (const int64_t *)(dplan + o_scol), nslots,
                                p16 ? S.alpha : 31, sres);
             HCHK(hipGetLastError());
-            RCHK(record(ctx, ctx->ev[0], st));
+            RCHK(record(ctx, (*tv)[0], st));
             hk::StreamArgs a{};
             a.mat = S.dmat;
             a.alpha = S.alpha;
@@ -579,7 +644,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             if (pk) launch_stream16(R, LS, a, (((nstreams + 1) / 2 + NS - 1) / NS + 7) / 8, lds_stream, st);
             else launch_stream(R, LS, a, tb, endc, p16, ((nstreams + NS - 1) / NS + 7) / 8, lds_stream, st);
             HCHK(hipGetLastError());
-            RCHK(record(ctx, ctx->ev[1], st));
+            RCHK(record(ctx, (*tv)[1], st));
             hipLaunchKernelGGL(hk::decode_keys_kernel, dim3(grid_for(nslots, 256, 1 << 30)), dim3(256), 0, st,
                                (const unsigned long long *)keys, (const int32_t *)(dplan + o_spid), nslots, out.score,
                                endc ? out.endcell : (int32_t *)nullptr);
@@ -588,8 +653,8 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             const int slots = ctx->num_cu * 16;
             const int grid = std::max(1, std::min(ngroups, slots));
             RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * strip_cols(nmax_all) * 8));
-            RCHK(launch_fill((uint32_t *)counter, 0u, 1, st));
-            RCHK(record(ctx, ctx->ev[0], st));
+            RCHK(launch_fill((uint32_t *)counter, 0u, 2, st));
+            RCHK(record(ctx, (*tv)[0], st));
             hk::InterArgs a{};
             a.mat = S.dmat;
             a.alpha = S.alpha;
@@ -612,7 +677,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             a.bstride = (int64_t)64 * strip_cols(nmax_all);
             launch_inter(a, tb, endc, grid, st);
             HCHK(hipGetLastError());
-            RCHK(record(ctx, ctx->ev[1], st));
+            RCHK(record(ctx, (*tv)[1], st));
         }
         ++launches;
         if (tb) {
@@ -668,27 +733,20 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             }
             HCHK(hipGetLastError());
         }
-        RCHK(record(ctx, ctx->ev[2], st));
-        if (chunks.size() > 1 && !ctx->capturing) {
-            HCHK(hipEventSynchronize(ctx->ev[2]));
+        RCHK(record(ctx, (*tv)[2], st));
+        if (ctx->progress && chunks.size() > 1 && !ctx->capturing) {
+            // progress lines wait for each chunk; otherwise the host plans the
+            // next chunk while this one runs
+            HCHK(hipEventSynchronize((*tv)[2]));
             float f = 0, w2 = 0;
-            HCHK(hipEventElapsedTime(&f, ctx->ev[0], ctx->ev[1]));
-            HCHK(hipEventElapsedTime(&w2, ctx->ev[1], ctx->ev[2]));
-            fwd_ms += f;
-            walk_ms += w2;
-            if (ctx->progress)
-                fprintf(stderr, "halign: chunk %d/%d done (%d pairs, forward %.1f ms, walk %.1f ms)\n", (int)ci + 1,
-                        (int)chunks.size(), cn, f, w2), fflush(stderr);
+            HCHK(hipEventElapsedTime(&f, (*tv)[0], (*tv)[1]));
+            HCHK(hipEventElapsedTime(&w2, (*tv)[1], (*tv)[2]));
+            fprintf(stderr, "halign: chunk %d/%d done (%d pairs, forward %.1f ms, walk %.1f ms)\n", (int)ci + 1,
+                    (int)chunks.size(), cn, f, w2);
+            fflush(stderr);
         }
     }
-    ctx->last_stats[1] = launches;
-    if (chunks.size() > 1) {
-        ctx->last_ms[0] = fwd_ms;
-        ctx->last_ms[1] = walk_ms;
-        ctx->last_ms[2] = -1.f;
-    } else {
-        ctx->last_ms[2] = 0.f;
-    }
+    ctx->last_stats[1] += launches;
     return HALIGN_OK;
 }
 
@@ -774,9 +832,14 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
     for (const Tune &c : cands) {
         float ms = 0.f;
         for (int rep = 0; rep < 2; ++rep) {
+            // every candidate run starts the stage and the timing triples anew
+            // (the previous run has synchronised)
+            ctx->stage_off = ctx->plan_off = 0;
+            ctx->ntev = 0;
             RCHK(run_batch(ctx, S, center, m, sq, sample, tb, endc, c.route, out, st, c));
-            HCHK(hipEventSynchronize(ctx->ev[1]));
-            HCHK(hipEventElapsedTime(&ms, ctx->ev[0], ctx->ev[1]));
+            float wk = 0.f;
+            RCHK(tev_sum(ctx, &ms, &wk));
+            RCHK(stage_wait(ctx));
         }
         if (ms < best_ms) {
             best_ms = ms;
@@ -790,8 +853,10 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
     return HALIGN_OK;
 }
 
+// The first staging step of every call: starts the call's stage regions.
 int upload_matrix(halign_ctx *ctx, const halign_scoring *sc, hipStream_t st, Scoring *S) {
     const size_t bytes = (size_t)sc->alphabet * sc->alphabet;
+    RCHK(stage_begin(ctx));
     if (ctx->capturing) {   // the device copy from the uncaptured run is kept by the graph
         S->dmat = (const int8_t *)ctx->spbuf.p;
         S->hmat = sc->matrix_host;
@@ -801,9 +866,10 @@ int upload_matrix(halign_ctx *ctx, const halign_scoring *sc, hipStream_t st, Sco
         return HALIGN_OK;
     }
     RCHK(grow(ctx, ctx->spbuf, 4096));
-    RCHK(stage_grow(ctx, 4096));
-    memcpy(ctx->stage.p, sc->matrix_host, bytes);
-    HCHK(hipMemcpyAsync(ctx->spbuf.p, ctx->stage.p, bytes, hipMemcpyHostToDevice, st));
+    char *hs = nullptr;
+    RCHK(stage_host(ctx, bytes, &hs));
+    memcpy(hs, sc->matrix_host, bytes);
+    HCHK(hipMemcpyAsync(ctx->spbuf.p, hs, bytes, hipMemcpyHostToDevice, st));
     RCHK(record(ctx, ctx->ev_stage, st));
     ctx->stage_pending = true;
     S->dmat = (const int8_t *)ctx->spbuf.p;
@@ -898,9 +964,6 @@ int halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out) 
                                                              : prop.sharedMemPerBlock;
         if (prop.sharedMemPerBlock && prop.sharedMemPerBlock < ctx->lds_max) ctx->lds_max = prop.sharedMemPerBlock;
     }
-    for (auto &e : ctx->ev) {
-        if (hipEventCreate(&e) != hipSuccess) { halign_ctx_destroy(ctx); return fail(HALIGN_E_DEVICE, "event create"); }
-    }
     if (hipHostMalloc((void **)&ctx->flag_host, 64, hipHostMallocDefault) != hipSuccess) {
         halign_ctx_destroy(ctx);
         return fail(HALIGN_E_DEVICE, "pinned allocation");
@@ -925,8 +988,8 @@ void halign_ctx_destroy(halign_ctx *ctx) {
         if (b.p) (void)hipFree(b.p);
     if (ctx->stage.p) (void)hipHostFree(ctx->stage.p);
     if (ctx->flag_host) (void)hipHostFree(ctx->flag_host);
-    for (auto &e : ctx->ev)
-        if (e) (void)hipEventDestroy(e);
+    for (auto &t : ctx->tev)
+        for (auto &e : t) (void)hipEventDestroy(e);
     if (ctx->ev_stage) (void)hipEventDestroy(ctx->ev_stage);
     delete ctx;
 }
@@ -939,16 +1002,8 @@ int halign_ctx_workspace_bytes(const halign_ctx *ctx, size_t *bytes_host) {
 
 int halign_ctx_last_timings(halign_ctx *ctx, float *ms_host) {
     if (!ctx || !ms_host) return fail(HALIGN_E_INVALID, "NULL argument");
-    if (ctx->last_ms[2] == 0.f) {
-        HCHK(hipEventSynchronize(ctx->ev[2]));
-        HCHK(hipEventElapsedTime(&ms_host[0], ctx->ev[0], ctx->ev[1]));
-        HCHK(hipEventElapsedTime(&ms_host[1], ctx->ev[1], ctx->ev[2]));
-        ms_host[2] = ms_host[0] + ms_host[1];
-    } else {
-        ms_host[0] = ctx->last_ms[0];
-        ms_host[1] = ctx->last_ms[1];
-        ms_host[2] = ms_host[0] + ms_host[1];
-    }
+    RCHK(tev_sum(ctx, &ms_host[0], &ms_host[1]));
+    ms_host[2] = ms_host[0] + ms_host[1];
     return HALIGN_OK;
 }
 
@@ -983,8 +1038,8 @@ int halign_ctx_last_plan(const halign_ctx *ctx, int32_t *plan_host) {
     return HALIGN_OK;
 }
 
-// test hook (not part of the public header): make chunk `c` of the next
-// halign_sw_batch fail before its launch.
+// Failure injection (declared in halign.h): chunk `c` of the next
+// halign_sw_batch fails before its launch.
 int halign_debug_fail_chunk(halign_ctx *ctx, int c) {
     if (!ctx) return fail(HALIGN_E_INVALID, "NULL ctx");
     ctx->fault_chunk = c;
@@ -1053,7 +1108,9 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
     if (want_tune) {
         BatchOut tout{score, cells, endcell, ins, aligned};
         RCHK(autotune(ctx, S, center, m, seqs, tb, endc, tout, st, &tune));
+        RCHK(stage_begin(ctx));   // the tuner's runs have synchronised
     }
+    for (auto &v : ctx->last_stats) v = 0;
     // the code check and the zeroing of the outputs go in before the host
     // plans the batch, so these small kernels run while the host works (the
     // forward kernels read codes masked to 5 bits, the check is read after the
@@ -1132,17 +1189,22 @@ static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8
     if (seqs->n >= 0) key = fnv(key, seqs->offsets_host, sizeof(int64_t) * ((size_t)seqs->n + 1));
     if (ctx->gent.exec && ctx->gent.key == key) {
         HCHK(hipSetDevice(ctx->device));
-        RCHK(record(ctx, ctx->ev[0], st));
+        RCHK(stage_begin(ctx));
+        std::array<hipEvent_t, 3> *tv = nullptr;
+        RCHK(tev_next(ctx, &tv));
+        RCHK(record(ctx, (*tv)[0], st));
         HCHK(hipGraphLaunch(ctx->gent.exec, st));
-        RCHK(record(ctx, ctx->ev[1], st));
-        RCHK(record(ctx, ctx->ev[2], st));
-        ctx->last_ms[2] = 0.f;
+        RCHK(record(ctx, (*tv)[1], st));
+        RCHK(record(ctx, (*tv)[2], st));
         ctx->flag_alpha = sc->alphabet;   // the graph copies the code check into flag_host
         ctx->graph_launches++;
         return HALIGN_OK;
     }
     // first call: run it, then capture the same sequence for later calls
     RCHK(sw_batch_body(ctx, sc, center, m, seqs, flags, score, cells, ins, aligned, stream, G, gskip));
+    // the captured run writes its plans into the stage from its start again:
+    // the copies of the run above must have read it first
+    RCHK(stage_wait(ctx));
     const int pending = ctx->flag_alpha;
     graph_drop(ctx);
     if (!ctx->cap_stream) HCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
@@ -1288,34 +1350,40 @@ static bool strip16_ok(const Scoring &S, const halign_seqs *sq) {
 }
 
 // Groups: one center, 64 partners (32-bit kernel) or 128 (16-bit kernel).
-static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, int mode,
+// Mode 1 (all pairs a < b of `perm`, in length order): the groups follow the
+// closed-form triangular tiling of tiling.hpp, ngroups = tri_groups(N, step),
+// with no per-group arrays.  Mode 2 (anchored groups): gcen, gb0 and gslot
+// list the groups.
+static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, int mode, int64_t ngroups,
                       const std::vector<int32_t> &gcen, const std::vector<int32_t> &gb0,
                       const std::vector<int32_t> &perm, const std::vector<int32_t> &gslot, int64_t *sums,
                       int32_t *score, hipStream_t st, int nperm = -1, bool p16 = false) {
     if (p16 && (score || mode == 0)) return fail(HALIGN_E_INVALID, "16-bit strip kernel: score-only center selection");
-    const int ng = (int)gcen.size();
-    if (ng == 0) return HALIGN_OK;
+    if (ngroups <= 0) return HALIGN_OK;
+    const size_t ng2 = mode == 2 ? (size_t)ngroups : 1;
     PlanBuilder pb;
-    const size_t o_gcen = pb.add(4 * (size_t)ng), o_gb0 = pb.add(4 * (size_t)ng),
-                 o_perm = pb.add(4 * perm.size()), o_gslot = pb.add(4 * std::max<size_t>(1, gslot.size()));
-    RCHK(stage_grow(ctx, pb.total));
-    char *hs = (char *)ctx->stage.p;
-    memcpy(hs + o_gcen, gcen.data(), 4 * (size_t)ng);
-    memcpy(hs + o_gb0, gb0.data(), 4 * (size_t)ng);
+    const size_t o_gcen = pb.add(4 * ng2), o_gb0 = pb.add(4 * ng2), o_perm = pb.add(4 * perm.size()),
+                 o_gslot = pb.add(4 * ng2);
+    char *hs = nullptr;
+    RCHK(stage_host(ctx, pb.total, &hs));
+    if (mode == 2) {
+        memcpy(hs + o_gcen, gcen.data(), 4 * ng2);
+        memcpy(hs + o_gb0, gb0.data(), 4 * ng2);
+        memcpy(hs + o_gslot, gslot.data(), 4 * ng2);
+    }
     memcpy(hs + o_perm, perm.data(), 4 * perm.size());
-    if (!gslot.empty()) memcpy(hs + o_gslot, gslot.data(), 4 * gslot.size());
-    RCHK(grow(ctx, ctx->plan, pb.total));
-    char *dplan = (char *)ctx->plan.p;
+    char *dplan = nullptr;
+    RCHK(plan_dev(ctx, pb.total, st, &dplan));
     HCHK(hipMemcpyAsync(dplan, hs, pb.total, hipMemcpyHostToDevice, st));
     RCHK(record(ctx, ctx->ev_stage, st));
     ctx->stage_pending = true;
     int nmax_all = 0;
     const int64_t *oh = sq->offsets_host;
     for (int k = 0; k < sq->n; ++k) nmax_all = std::max(nmax_all, (int)(oh[k + 1] - oh[k]));
-    const int grid = std::max(1, std::min(ng, ctx->num_cu * 16));
+    const int grid = (int)std::max<int64_t>(1, std::min<int64_t>(ngroups, (int64_t)ctx->num_cu * 16));
     RCHK(grow(ctx, ctx->bound, (size_t)grid * 64 * strip_cols(nmax_all) * (p16 ? 16 : 8)));
     RCHK(grow(ctx, ctx->counter, 256));
-    RCHK(launch_fill((uint32_t *)ctx->counter.p, 0u, 1, st));
+    RCHK(launch_fill((uint32_t *)ctx->counter.p, 0u, 2, st));
     hk::InterArgs a{};
     a.mat = S.dmat;
     a.alpha = S.alpha;
@@ -1328,21 +1396,22 @@ static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, 
     a.nseq = nperm >= 0 ? nperm : sq->n;
     a.gslot = (const int32_t *)(dplan + o_gslot);
     a.sums = sums;
-    a.ngroups = ng;
+    a.ngroups = ngroups;
     a.ge = S.ge;
     a.goe = S.goe;
-    a.counter = (int *)ctx->counter.p;
+    a.counter = (unsigned long long *)ctx->counter.p;
     a.score = score;
     a.bound = (int2 *)ctx->bound.p;
     a.bstride = (int64_t)64 * strip_cols(nmax_all);
     ctx->last_stats[0] = 0;
-    RCHK(record(ctx, ctx->ev[0], st));
+    std::array<hipEvent_t, 3> *tv = nullptr;
+    RCHK(tev_next(ctx, &tv));
+    RCHK(record(ctx, (*tv)[0], st));
     if (p16) hipLaunchKernelGGL(hk::sw_inter16_kernel, dim3(grid), dim3(64), 0, st, a);
     else launch_inter(a, false, false, grid, st);
     HCHK(hipGetLastError());
-    RCHK(record(ctx, ctx->ev[1], st));
-    RCHK(record(ctx, ctx->ev[2], st));
-    ctx->last_ms[2] = 0.f;
+    RCHK(record(ctx, (*tv)[1], st));
+    RCHK(record(ctx, (*tv)[2], st));
     return HALIGN_OK;
 }
 
@@ -1370,6 +1439,17 @@ static int argmax_sums(halign_ctx *ctx, const int64_t *sums, const int32_t *cand
     return HALIGN_OK;
 }
 
+int halign_exact_tiling(int64_t n, int32_t step, int64_t g, int64_t *ngroups_host, int64_t *center_pos_host,
+                        int64_t *partner0_host) {
+    if (n < 0 || step < 1 || !ngroups_host) return fail(HALIGN_E_INVALID, "bad arguments");
+    const int64_t ng = hk::tri_groups(n, step);
+    *ngroups_host = ng;
+    if (g < 0) return HALIGN_OK;
+    if (g >= ng || !center_pos_host || !partner0_host) return fail(HALIGN_E_INVALID, "group %lld of %lld", (long long)g, (long long)ng);
+    hk::tri_group(g, n, step, center_pos_host, partner0_host);
+    return HALIGN_OK;
+}
+
 int halign_center_exact(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, int64_t *sums,
                         int32_t *center_host, void *stream) {
     if (!ctx || !sums) return fail(HALIGN_E_INVALID, "bad arguments");
@@ -1383,18 +1463,13 @@ int halign_center_exact(halign_ctx *ctx, const halign_scoring *sc, const halign_
     RCHK(upload_matrix(ctx, sc, st, &S));
     RCHK(validate_now(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
     RCHK(launch_fill((uint32_t *)sums, 0u, 2 * (int64_t)N, st));
-    std::vector<int32_t> perm = length_perm(seqs), gcen, gb0, gslot;
+    // all pairs a' < b' in length order: the longer sequence is the lane's,
+    // the shorter one the group's center; the groups are numbered in closed
+    // form (tiling.hpp), so the host holds O(N) plan data
+    std::vector<int32_t> perm = length_perm(seqs), none;
     const bool p16 = strip16_ok(S, seqs);
     const int step = p16 ? 128 : 64;
-    // all pairs a' < b' in length order: the longer sequence is the lane's,
-    // the shorter one the group's center
-    for (int a = 0; a < N; ++a)
-        for (int b = a + 1; b < N; b += step) {
-            gcen.push_back(a);
-            gb0.push_back(b);
-        }
-    if (gcen.size() > (size_t)INT32_MAX / 64) return fail(HALIGN_E_UNSUPPORTED, "too many pairs");
-    RCHK(run_groups(ctx, S, seqs, 1, gcen, gb0, perm, gslot, sums, nullptr, st, -1, p16));
+    RCHK(run_groups(ctx, S, seqs, 1, hk::tri_groups(N, step), none, none, perm, none, sums, nullptr, st, -1, p16));
     if (center_host) RCHK(argmax_sums(ctx, sums, nullptr, N, center_host, st));
     return HALIGN_OK;
 }
@@ -1425,7 +1500,7 @@ int halign_center_judge(halign_ctx *ctx, const halign_scoring *sc, const halign_
             gb0.push_back(b);
             gslot.push_back(q);
         }
-    RCHK(run_groups(ctx, S, seqs, 2, gcen, gb0, perm, gslot, sums, nullptr, st, -1, p16));
+    RCHK(run_groups(ctx, S, seqs, 2, (int64_t)gcen.size(), gcen, gb0, perm, gslot, sums, nullptr, st, -1, p16));
     if (center_host) RCHK(argmax_sums(ctx, sums, hc.data(), ncand, center_host, st));
     return HALIGN_OK;
 }
@@ -1461,7 +1536,7 @@ int halign_sw_pairs(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs
     RCHK(launch_fill((uint32_t *)sums, 0u, 2 * (int64_t)nanchors, st));
     halign_seqs sq2 = *seqs;
     sq2.n = N;
-    RCHK(run_groups(ctx, S, &sq2, 2, gcen, gb0, perm, gslot, sums, score, st, (int)np));
+    RCHK(run_groups(ctx, S, &sq2, 2, (int64_t)gcen.size(), gcen, gb0, perm, gslot, sums, score, st, (int)np));
     return HALIGN_OK;
 }
 
@@ -1682,6 +1757,15 @@ int halign_mlp_backward(halign_ctx *ctx, const halign_model *model, const uint16
     c.C = dW1; c.ldc = hk::kHid;
     if (nrows > 0) RCHK((gemm<true, false, 0>(c, st)));
     else RCHK(launch_fill((uint32_t *)dW1, 0u, (int64_t)hk::kFeat * hk::kHid, st));
+    return HALIGN_OK;
+}
+
+int halign_f32_to_bf16(const float *src, uint16_t *dst, int64_t n, void *stream) {
+    if (n < 0 || (n > 0 && (!src || !dst))) return fail(HALIGN_E_INVALID, "bad arguments");
+    if (n == 0) return HALIGN_OK;
+    hipLaunchKernelGGL(hk::f32_to_bf16_kernel, dim3(grid_for(n, 256, 8192)), dim3(256), 0, (hipStream_t)stream, src,
+                       dst, n);
+    HCHK(hipGetLastError());
     return HALIGN_OK;
 }
 

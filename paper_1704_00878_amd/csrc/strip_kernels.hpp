@@ -5,6 +5,7 @@
 #pragma once
 #include "sw_kernels.hpp"
 #include "pk16.hpp"
+#include "tiling.hpp"
 
 namespace hk {
 
@@ -39,15 +40,15 @@ struct InterArgs {
     int mode;                 // 0 batch, 1 all pairs (a < b), 2 anchored groups
     const int32_t *order;     // mode 0: 64 * ngroups pair ids (-1 = empty lane)
     const int32_t *gnmax;     // mode 0: per group longest sequence (code layout)
-    const int32_t *gcen;      // mode 1: center position in perm; mode 2: center seq id
-    const int32_t *gb0;       // modes 1/2: first partner position in perm
-    const int32_t *perm;      // modes 1/2: sequence ids sorted by length
+    const int32_t *gcen;      // mode 2: center seq id per group
+    const int32_t *gb0;       // mode 2: first partner position in perm per group
+    const int32_t *perm;      // modes 1/2: sequence ids (mode 1: sorted by length)
     int nseq;
     const int32_t *gslot;     // mode 2: sums slot of the group's center
     int64_t *sums;            // modes 1/2: integer score sums (atomic adds)
-    int ngroups;
+    int64_t ngroups;          // mode 1: tri_groups(nseq, partners per group), largest first
     int ge, goe;
-    int *counter;
+    unsigned long long *counter;   // next group (zeroed before the launch)
     int32_t *score;           // mode 0: per pair id; mode 2: per lane slot (optional)
     int32_t *endcell;
     uint32_t *codes;
@@ -55,6 +56,13 @@ struct InterArgs {
     int2 *bound;              // per workgroup slot: bstride int2
     int64_t bstride;          // >= 64 * (max nmax rounded up to kB)
 };
+
+// a wave-uniform 64-bit value (read from LDS by every lane) in SGPRs
+__device__ __forceinline__ int64_t uniform64(unsigned long long v) {
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)v);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+    return (int64_t)(((uint64_t)hi << 32) | lo);
+}
 
 __device__ __forceinline__ int2 load_agent(const int2 *p) {
     uint64_t v = __hip_atomic_load(reinterpret_cast<const uint64_t *>(p), __ATOMIC_RELAXED,
@@ -75,13 +83,13 @@ sw_inter_kernel(InterArgs a) {
     }
     int2 *bnd = a.bound + (int64_t)blockIdx.x * a.bstride;
     const int ge = a.ge, goe = a.goe;
-    __shared__ int s_next;
+    __shared__ unsigned long long s_next;
     for (;;) {
         // fetch the next group: one atomic by lane 0, broadcast through LDS
         __syncthreads();
-        if (lane == 0) s_next = atomicAdd(a.counter, 1);
+        if (lane == 0) s_next = atomicAdd(a.counter, 1ull);
         __syncthreads();
-        const int g = __builtin_amdgcn_readfirstlane(s_next);
+        const int64_t g = uniform64(s_next);
         if (g >= a.ngroups) break;
         int pid = -1;       // output slot (mode 0: pair id)
         int sid = -1;       // sequence of this lane
@@ -89,14 +97,21 @@ sw_inter_kernel(InterArgs a) {
         int m = a.m;
         int cid = -1;
         if (a.mode == 0) {
-            pid = a.order[(int64_t)g * 64 + lane];
+            pid = a.order[g * 64 + lane];
             sid = pid;
         } else {
-            const int bpos = a.gb0[g] + lane;
-            cid = a.mode == 1 ? a.perm[a.gcen[g]] : a.gcen[g];
-            if (bpos < a.nseq) {
+            int64_t apos = -1, b0;
+            if (a.mode == 1) {
+                tri_group(a.ngroups - 1 - g, a.nseq, 64, &apos, &b0);
+                cid = a.perm[apos];
+            } else {
+                b0 = a.gb0[g];
+                cid = a.gcen[g];
+            }
+            const int64_t bpos = b0 + lane;
+            if (bpos < a.nseq && bpos > apos) {
                 sid = a.perm[bpos];
-                pid = g * 64 + lane;          // output slot; a self pair scores 0
+                pid = (int)(g * 64 + lane);   // output slot (mode 2); a self pair scores 0
                 if (sid == cid) sid = -1;
             }
             cen = a.res + a.off[cid];
@@ -277,7 +292,7 @@ __global__ void __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(4)))
 sw_inter16_kernel(InterArgs a) {
     __shared__ uint32_t prof[kAlphaMax * 8];   // int16 [r][16], 8 words per residue
     __shared__ int8_t smat[kAlphaMax * kAlphaMax];
-    __shared__ int s_next;
+    __shared__ unsigned long long s_next;
     const int lane = threadIdx.x;
     for (int x = lane; x < kAlphaMax * kAlphaMax; x += 64) {
         const int r = x >> 5, q = x & 31;
@@ -293,14 +308,22 @@ sw_inter16_kernel(InterArgs a) {
     const pk16 init2 = pk16{(short)(kBias16 - a.goe), (short)(kBias16 - a.goe)};   // -go - ge, biased
     for (;;) {
         __syncthreads();
-        if (lane == 0) s_next = atomicAdd(a.counter, 1);
+        if (lane == 0) s_next = atomicAdd(a.counter, 1ull);
         __syncthreads();
-        const int g = __builtin_amdgcn_readfirstlane(s_next);
+        const int64_t g = uniform64(s_next);
         if (g >= a.ngroups) break;
-        const int cid = a.mode == 1 ? a.perm[a.gcen[g]] : a.gcen[g];
-        const int pa = a.gb0[g] + lane, pbp = pa + 64;
-        int sa = pa < a.nseq ? a.perm[pa] : -1;
-        int sb = pbp < a.nseq ? a.perm[pbp] : -1;
+        int64_t apos = -1, b0;
+        int cid;
+        if (a.mode == 1) {
+            tri_group(a.ngroups - 1 - g, a.nseq, 128, &apos, &b0);
+            cid = a.perm[apos];
+        } else {
+            b0 = a.gb0[g];
+            cid = a.gcen[g];
+        }
+        const int64_t pa = b0 + lane, pbp = pa + 64;
+        int sa = (pa < a.nseq && pa > apos) ? a.perm[pa] : -1;
+        int sb = (pbp < a.nseq && pbp > apos) ? a.perm[pbp] : -1;
         sa = sa == cid ? -1 : sa;   // a self pair scores 0
         sb = sb == cid ? -1 : sb;
         const uint8_t *cen = a.res + a.off[cid];

@@ -14,7 +14,9 @@ configurable length distributions.
 """
 from __future__ import annotations
 
+import concurrent.futures
 import dataclasses
+import os
 from typing import Callable, Sequence
 
 import numpy as np
@@ -128,7 +130,13 @@ class SeqSet:
         return SeqSet(res.astype(np.uint8), offs)
 
     def subset(self, idx: Sequence[int]) -> "SeqSet":
-        return SeqSet.from_list([self.seq(int(k)) for k in idx])
+        """The sequences idx, in that order (one gather)."""
+        idx = np.asarray(idx, dtype=np.int64).reshape(-1)
+        lens = self.offsets[idx + 1] - self.offsets[idx]
+        offs = np.zeros(len(idx) + 1, dtype=np.int64)
+        np.cumsum(lens, out=offs[1:])
+        pos = np.arange(offs[-1], dtype=np.int64) + np.repeat(self.offsets[idx] - offs[:-1], lens)
+        return SeqSet(self.residues[pos].astype(np.uint8), offs)
 
 
 # ---------------------------------------------------------------------------
@@ -260,11 +268,21 @@ def generate(cfg: FamilyConfig | str, n_seqs: int | None = None, seed: int | Non
     np.cumsum(root_lens, out=root_off[1:])
     nchunks = max(1, (n_seqs + _CHUNK - 1) // _CHUNK)
     kids = ss.spawn(nchunks)
-    parts, offs, base = [], [np.zeros(1, np.int64)], 0
-    for c in range(nchunks):
+
+    def chunk(c):
         n = min(_CHUNK, n_seqs - c * _CHUNK)
-        out, off = _generate_chunk(np.random.Generator(np.random.PCG64(kids[c])), cfg, n, roots, root_off,
-                                   root_lens)
+        return _generate_chunk(np.random.Generator(np.random.PCG64(kids[c])), cfg, n, roots, root_off, root_lens)
+
+    # chunks draw from their own seed streams, so they are generated in
+    # parallel (numpy releases the GIL) and concatenated in order
+    workers = max(1, min(nchunks, 8, os.cpu_count() or 1))
+    if workers > 1:
+        with concurrent.futures.ThreadPoolExecutor(workers) as ex:
+            results = list(ex.map(chunk, range(nchunks)))
+    else:
+        results = [chunk(c) for c in range(nchunks)]
+    parts, offs, base = [], [np.zeros(1, np.int64)], 0
+    for out, off in results:
         parts.append(out)
         offs.append(off[1:] + base)
         base += int(off[-1])

@@ -66,6 +66,49 @@ def test_graph_replays_match_eager(H, lanes, monkeypatch):
     ctx.close()
 
 
+@pytest.mark.parametrize("route", ["intra", "pack16", "inter"])
+def test_graph_replays_in_chunks(H, route, monkeypatch):
+    """A workspace cap that splits the batch into chunks, captured into one
+    graph: every chunk keeps its own plan region, so every replay (with eager
+    work and synchronisations in between) equals the oracle."""
+    import torch
+    if route == "pack16":
+        monkeypatch.setenv("HALIGN_STREAM_LANES", "16")
+        monkeypatch.setenv("HALIGN_STREAM_PACK", "1")
+    ctx = H.Context(0, workspace_cap=1_000_000)
+    sc = H.Scoring()
+    seqs = synth.generate("plain64", n_seqs=300, seed=32)
+    ds = H.DeviceSeqs(seqs)
+    ref = _ref(seqs, 0)
+    rt = H.HALIGN_ROUTE_INTER if route == "inter" else H.HALIGN_ROUTE_INTRA
+    out = H.sw_batch(ctx, sc, ds, 0, graph=True, route=rt)
+    torch.cuda.synchronize()
+    assert ctx.last_stats()["chunks"] >= 2
+    for g, r in zip(_host(H, out, out["m"]), ref):
+        assert (g == r).all()
+    for rep in range(3):
+        for k in out:
+            if hasattr(out[k], "fill_"):
+                out[k].fill_(-7)
+        torch.cuda.synchronize()
+        H.sw_batch(ctx, sc, ds, 0, graph=True, route=rt, out=out)
+        torch.cuda.synchronize()
+        for g, r in zip(_host(H, out, out["m"]), ref):
+            assert (g == r).all(), rep
+        other = H.sw_batch(ctx, sc, ds, 7, route=rt)   # eager call in between
+        torch.cuda.synchronize()
+        assert (other["score"].cpu().numpy() == _ref(seqs, 7)[0]).all()
+    assert ctx.graph_launches() == 3
+    # the end-to-end MSA with graph replay on the same capped ctx
+    ctx.set_graph(True)
+    mref = oracle.msa(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets, 0)
+    for _ in range(3):
+        msa, _c = H.halign_msa(ctx, sc, ds, 0)
+        torch.cuda.synchronize()
+        assert (msa.cpu().numpy() == mref["msa"]).all()
+    ctx.close()
+
+
 def test_msa_with_graph(H):
     import torch
     ctx = H.Context(0)
@@ -111,10 +154,14 @@ def test_autotune_is_exact(H, tmp_path, monkeypatch):
 
 
 def test_encode(H):
+    """Every byte value, and a long text spanning several workgroups, against
+    the oracle's encoding."""
     import torch
-    text = "ARNDCQEGHILKMFPSTWYVBZX*arndUOJ-"
-    a = torch.tensor(list(text.encode()), dtype=torch.uint8, device="cuda")
-    c = torch.empty_like(a)
-    H.halign_encode(a, c)
-    torch.cuda.synchronize()
-    assert (c.cpu().numpy() == synth.encode(text)).all()
+    rng = np.random.default_rng(4)
+    for raw in (bytes(range(256)) + b"ARNDCQEGHILKMFPSTWYVBZX*arndUOJ-",
+                bytes(rng.integers(0, 256, 1_000_003, dtype=np.uint8))):
+        a = torch.tensor(list(raw), dtype=torch.uint8, device="cuda")
+        c = torch.empty_like(a)
+        H.halign_encode(a, c)
+        torch.cuda.synchronize()
+        assert (c.cpu().numpy() == oracle.encode(raw)).all()

@@ -22,7 +22,7 @@ CSRC = os.path.join(ROOT, "paper_1704_00878_amd", "csrc")
 
 
 def _constants():
-    src = open(os.path.join(CSRC, "strip_kernels.hpp")).read()
+    src = open(os.path.join(CSRC, "pk16.hpp")).read()
     bias = int(re.search(r"constexpr int kBias16 = (-?\d+);", src).group(1))
     pad = int(re.search(r"constexpr int kPadProf16 = (-?\d+);", src).group(1))
     host = open(os.path.join(CSRC, "halign.hip")).read()

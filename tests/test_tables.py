@@ -54,6 +54,25 @@ def test_encode_decode():
     assert synth.decode([0, 255, 17]) == "A-W"
 
 
+def test_oracle_encode_hand_codes():
+    """The oracle's encoding against codes written out by hand from the NCBI
+    order A R N D C Q E G H I L K M F P S T W Y V B Z X * (0..23)."""
+    import oracle
+    oracle.build(force=False)
+    got = oracle.encode("MKTAYIAKQR")
+    assert list(got) == [12, 11, 16, 0, 18, 9, 0, 11, 5, 1]
+    got = oracle.encode("wyv*bzx")                    # lower case and the last letters
+    assert list(got) == [17, 18, 19, 23, 20, 21, 22]
+    got = oracle.encode("UuOo")                        # U -> C (4), O -> K (11)
+    assert list(got) == [4, 4, 11, 11]
+    got = oracle.encode(b"J-1 \x00\xff.")              # everything else -> X (22)
+    assert list(got) == [22] * 7
+    assert list(oracle.encode(b"")) == []
+    ascii7 = bytes(range(128))
+    assert (oracle.encode(ascii7) == synth.encode(ascii7.decode("ascii"))).all()
+    assert (oracle.encode(bytes(range(128, 256))) == 22).all()
+
+
 def test_generator_deterministic_and_shaped():
     a = synth.generate("plain64")
     b = synth.generate("plain64")
