@@ -38,6 +38,50 @@
 
 namespace hk {
 
+// DPP controls (gfx9 family): shifts within 16-lane rows, the whole-wave
+// shift, and the broadcast of lane 15 of each row to the next row.
+constexpr int kDppRowShl = 0x100;   // + n: lane l reads lane l + n of its row
+constexpr int kDppRowShr1 = 0x111;  // lane l reads lane l - 1 of its row
+constexpr int kDppRowBcast15 = 0x142;
+
+// LDS dwords of a profile entry (n <= 4 of the uint4 at p)
+template <int N>
+__device__ __forceinline__ void lds_words(const uint4 *p, uint32_t *d) {
+    if constexpr (N >= 4) {
+        const uint4 x = *p;
+        d[0] = x.x; d[1] = x.y; d[2] = x.z; d[3] = x.w;
+    } else if constexpr (N == 3) {
+        const uint3 x = *reinterpret_cast<const uint3 *>(p);
+        d[0] = x.x; d[1] = x.y; d[2] = x.z;
+    } else if constexpr (N == 2) {
+        const uint2 x = *reinterpret_cast<const uint2 *>(p);
+        d[0] = x.x; d[1] = x.y;
+    } else {
+        d[0] = *reinterpret_cast<const uint32_t *>(p);
+    }
+}
+
+// A stream's next column enters at its first lane and every other lane takes
+// its left neighbour's: lane l of each stream gets x[l - 1], the first lane of
+// each stream gets head (both wave-uniform patterns, three DPP moves at most).
+template <int LS>
+__device__ __forceinline__ int stream_shift(int x, int head) {
+    if constexpr (LS == 16) {
+        return __builtin_amdgcn_update_dpp(head, x, kDppRowShr1, 0xf, 0xf, false);
+    } else {   // 32 lanes: rows 1 and 3 continue rows 0 and 2
+        const int t = __builtin_amdgcn_update_dpp(head, x, kDppRowBcast15, 0xa, 0xf, false);
+        return __builtin_amdgcn_update_dpp(t, x, kDppRowShr1, 0xf, 0xf, false);
+    }
+}
+
+// lane l of each 16-lane row takes x[l + U] (the first lane of each stream
+// takes the value of lane U of its stream)
+template <int U>
+__device__ __forceinline__ int row_take(int x) {
+    if constexpr (U == 0) return x;
+    else return __builtin_amdgcn_update_dpp(x, x, kDppRowShl + U, 0xf, 0xf, false);
+}
+
 template <int R, int LS>
 __global__ void __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(4)))
 sw_stream16_kernel(StreamArgs a) {
@@ -47,15 +91,21 @@ sw_stream16_kernel(StreamArgs a) {
     // 128 of four waves per SIMD
     constexpr bool SNAP = R <= 11;
     constexpr int W = (R + 7) / 8;           // profile uint4 per (residue, lane)
+    constexpr int NW = (R + 1) / 2;          // profile dwords a step reads per stream
     constexpr int WQ = (R + 3) / 4;          // code words per step (both halves)
     constexpr int NS = 64 / LS;              // lane groups per wavefront
     constexpr int SPAN = LS * R;             // rows per pass
     constexpr int LG = LS == 32 ? 5 : 4;
-    extern __shared__ int prof[];   // profile, then code staging [8 waves][4 steps][WQ][64 lanes]
+    // profile int16 [residue][w][lane][8]: lane l's rows 8w..8w+7 of residue r
+    // at uint4 (r * W + w) * LS + l, so the lanes of a read touch consecutive
+    // 16-byte slots whatever residue each one reads (no bank conflicts);
+    // then the code staging [8 waves][4 steps][WQ][64 lanes]
+    extern __shared__ int prof[];
     const int nprow = a.alpha + 1;
     const int prof_words = nprow * LS * 4 * W;
     uint32_t *stage = reinterpret_cast<uint32_t *>(prof + prof_words) + (threadIdx.x >> 6) * 256 * WQ +
                       (threadIdx.x & 63);
+    const uint4 *prof4 = reinterpret_cast<const uint4 *>(prof) + (threadIdx.x & (LS - 1));
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int ll = lane & (LS - 1);
@@ -94,14 +144,28 @@ sw_stream16_kernel(StreamArgs a) {
     const pk16 bias2 = pk16{(short)kBias16, (short)kBias16};   // 0, biased
     const int padc = a.alpha;
     const int padrc = padc | (padc << 16);
+    // residues of the stream columns k0 + ll (A, B), for the first 8 lanes
+    // of each stream (the heads of steps k0 .. k0 + 7); padding outside.
+    // They are combined (A | B << 16) only where used, a block later, so the
+    // loads are not waited for here.
+    auto residues = [&](int k0) __attribute__((always_inline)) {
+        const int kk = k0 + ll;
+        int ra = padc, rb = padc;
+        if (ll < 8) {
+            if (kk < CA) ra = (int)srA[kk];
+            if (kk < CB) rb = (int)srB[kk];
+        }
+        return make_int2(ra, rb);
+    };
+    auto pair_code = [](int2 r) __attribute__((always_inline)) { return r.x | (r.y << 16); };
     for (int pass = 0; pass < a.passes; ++pass) {
         const int row0 = pass * SPAN;
         __syncthreads();
         {
             int16_t *p16 = reinterpret_cast<int16_t *>(prof);
-            constexpr int PER = 8 * W;
-            for (int x = tid; x < nprow * LS * PER; x += nthreads) {
-                const int r = x / (LS * PER), l = (x / PER) & (LS - 1), tt = x % PER;
+            for (int x = tid; x < nprow * W * LS * 8; x += nthreads) {
+                const int r = x / (W * LS * 8), w = (x / (LS * 8)) % W, l = (x >> 3) & (LS - 1);
+                const int tt = 8 * w + (x & 7);
                 const int i = row0 + l * R + tt;
                 int v = kPadProf16;
                 if (r < a.alpha && tt < R && i < a.m) v = (int)a.mat[(a.center[i] & 31) * a.alpha + r] + goe;
@@ -116,13 +180,41 @@ sw_stream16_kernel(StreamArgs a) {
         uint32_t *cw = actA ? a.codes + a.scbase[sA] + (int64_t)pass * G * LS * 8 * WQ + ll * 8 * WQ : nullptr;
         auto run = [&](auto hb_tag) __attribute__((always_inline)) {
             constexpr bool HB = decltype(hb_tag)::value;
+            // boundary rows of the previous pass (Hg, F*) of the stream columns
+            // k0 + ll for the first 8 lanes of each stream
+            auto bounds = [&](int k0) __attribute__((always_inline)) {
+                const int kk = k0 + ll;
+                int2 v = make_int2((int)init2u, (int)init2u);
+                if (HB && bin && ll < 8 && kk < C) v = bin[kk];
+                return v;
+            };
             pk16 hg[R], e[R];
 #pragma unroll
             for (int t = 0; t < R; ++t) { hg[t] = init2; e[t] = init2; }
             uint32_t botg = init2u, botf = init2u;
             uint32_t diag0 = init2u;
-            int rcur = padrc, rbuf = padrc;
-            int2 bbuf = make_int2((int)init2u, (int)init2u);
+            // residues and boundary values of the current 8-step block and of
+            // the next one (loaded a block ahead, so no step waits on memory)
+            int rbuf = pair_code(residues(0));
+            int2 rnext = residues(8);
+            int2 bbuf = bounds(0), bnext = bounds(8);
+            // the residue pair of this lane's column at the current step, and
+            // the profile words it selects (read one step ahead)
+            int rcur = stream_shift<LS>(padrc, rbuf);
+            uint32_t wa[NW], wb[NW];
+            auto prof_read = [&](int rc, uint32_t (&da)[NW], uint32_t (&db)[NW]) __attribute__((always_inline)) {
+                const uint32_t ra = __builtin_amdgcn_ubfe((uint32_t)rc, 0, 7);
+                const uint32_t rb = __builtin_amdgcn_ubfe((uint32_t)rc, 16, 7);
+                const uint4 *pa = prof4 + ((ra * W) << LG);
+                const uint4 *pb = prof4 + ((rb * W) << LG);
+                lds_words<(NW < 4 ? NW : 4)>(pa, da);
+                lds_words<(NW < 4 ? NW : 4)>(pb, db);
+                if constexpr (NW > 4) {
+                    lds_words<NW - 4>(pa + LS, da + 4);
+                    lds_words<NW - 4>(pb + LS, db + 4);
+                }
+            };
+            prof_read(rcur, wa, wb);
             int plA = -1, plB = -1;
             // running end cell of the current pair, per half.  SNAP: the best
             // H, the step (mod 2^16) that first reached it and the lane's rows
@@ -164,185 +256,162 @@ sw_stream16_kernel(StreamArgs a) {
                     atomicMax(a.keys + slotB + plB, cell_key(b, true));
                 }
             };
-            for (int k8 = 0; k8 < steps8; k8 += 8) {
-                if ((k8 & (LS - 1)) == 0) {
-                    const int kk = k8 + ll;
-                    const int ra = kk < CA ? (int)srA[kk] : padc;
-                    const int rb = kk < CB ? (int)srB[kk] : padc;
-                    rbuf = ra | (rb << 16);
-                    if (HB && bin) bbuf = kk < C ? bin[kk] : make_int2((int)init2u, (int)init2u);
+            auto step = [&](auto u_tag, int k8) __attribute__((always_inline)) {
+                constexpr int u = decltype(u_tag)::value;
+                const int k = k8 + u;
+                // the next step's residues and profile words, issued first
+                const int rnx = stream_shift<LS>(rcur, u < 7 ? row_take<(u + 1) & 7>(rbuf) : pair_code(rnext));
+                uint32_t na[NW], nb[NW];
+                prof_read(rnx, na, nb);
+                uint32_t upgu, upfu;
+                if (HB) {
+                    upgu = (uint32_t)stream_shift<LS>((int)botg, row_take<u>(bbuf.x));
+                    upfu = (uint32_t)stream_shift<LS>((int)botf, row_take<u>(bbuf.y));
+                } else {
+                    upgu = (uint32_t)stream_shift<LS>((int)botg, (int)init2u);
+                    upfu = (uint32_t)stream_shift<LS>((int)botf, (int)init2u);
                 }
-#pragma unroll
-                for (int u = 0; u < 8; ++u) {
-                    const int k = k8 + u;
-                    const int rl = (k8 & (LS - 1)) + u;   // wave-uniform
-                    rcur = __builtin_amdgcn_update_dpp(__builtin_amdgcn_readlane(rbuf, rl), rcur, 0x138, 0xf, 0xf,
-                                                       false);
-#pragma unroll
-                    for (int s = 1; s < NS; ++s) {
-                        const int rs = __builtin_amdgcn_readlane(rbuf, s * LS + rl);
-                        rcur = lane == s * LS ? rs : rcur;
+                if (rcur & 0x00800080) {
+                    // a pair starts in one half or both: publish the pair left
+                    // behind and reset that half to the column-0 boundary
+                    const bool fA = (rcur & 0x80) != 0, fB = (rcur & 0x800000) != 0;
+                    if (fA) {
+                        publishA();
+                        ++plA;
+                        kfA = k;
+                        bhA = 0;
+                        bcolA = 0;
+                        bkA = k;
                     }
-                    uint32_t upgu, upfu;
-                    if (HB) {
-                        int tg = (int)init2u, tf = (int)init2u;
-                        if (bin) {
-                            tg = __builtin_amdgcn_readlane(bbuf.x, rl);
-                            tf = __builtin_amdgcn_readlane(bbuf.y, rl);
-                        }
-                        upgu = (uint32_t)__builtin_amdgcn_update_dpp(tg, (int)botg, 0x138, 0xf, 0xf, false);
-                        upfu = (uint32_t)__builtin_amdgcn_update_dpp(tf, (int)botf, 0x138, 0xf, 0xf, false);
-#pragma unroll
-                        for (int s = 1; s < NS; ++s) {
-                            int sg = (int)init2u, sf = (int)init2u;
-                            if (bin) {
-                                sg = __builtin_amdgcn_readlane(bbuf.x, s * LS + rl);
-                                sf = __builtin_amdgcn_readlane(bbuf.y, s * LS + rl);
-                            }
-                            upgu = lane == s * LS ? (uint32_t)sg : upgu;
-                            upfu = lane == s * LS ? (uint32_t)sf : upfu;
-                        }
-                    } else {
-                        upgu = (uint32_t)__builtin_amdgcn_update_dpp((int)init2u, (int)botg, 0x138, 0xf, 0xf, false);
-                        upfu = (uint32_t)__builtin_amdgcn_update_dpp((int)init2u, (int)botf, 0x138, 0xf, 0xf, false);
-#pragma unroll
-                        for (int s = 1; s < NS; ++s) {
-                            upgu = lane == s * LS ? init2u : upgu;
-                            upfu = lane == s * LS ? init2u : upfu;
-                        }
+                    if (fB) {
+                        publishB();
+                        ++plB;
+                        kfB = k;
+                        bhB = 0;
+                        bcolB = 0;
+                        bkB = k;
                     }
-                    if (rcur & 0x00800080) {
-                        // a pair starts in one half or both: publish the pair left
-                        // behind and reset that half to the column-0 boundary
-                        const bool fA = (rcur & 0x80) != 0, fB = (rcur & 0x800000) != 0;
-                        if (fA) {
-                            publishA();
-                            ++plA;
-                            kfA = k;
-                            bhA = 0;
-                            bcolA = 0;
-                            bkA = k;
-                        }
-                        if (fB) {
-                            publishB();
-                            ++plB;
-                            kfB = k;
-                            bhB = 0;
-                            bcolB = 0;
-                            bkB = k;
-                        }
-                        const uint32_t msk = (fA ? 0xffffu : 0u) | (fB ? 0xffff0000u : 0u);
-                        bh = as_pk(as_u(bh) & ~msk);
-#pragma unroll
-                        for (int t = 0; t < R; ++t) {
-                            hg[t] = as_pk((init2u & msk) | (as_u(hg[t]) & ~msk));
-                            e[t] = as_pk((init2u & msk) | (as_u(e[t]) & ~msk));
-                        }
-                        diag0 = (init2u & msk) | (diag0 & ~msk);
-                    }
-                    pk16 upg = as_pk(upgu), upf = as_pk(upfu);
-                    pk16 diag = as_pk(diag0);
-                    diag0 = upgu;
-                    const int ra = rcur & 0x7f, rb = (rcur >> 16) & 0x7f;
-                    const uint4 *pa = reinterpret_cast<const uint4 *>(prof) + (((uint32_t)ra << LG) + ll) * W;
-                    const uint4 *pb = reinterpret_cast<const uint4 *>(prof) + (((uint32_t)rb << LG) + ll) * W;
-                    uint32_t wa[4 * W], wb[4 * W];
-#pragma unroll
-                    for (int w = 0; w < W; ++w) {
-                        const uint4 x = pa[w], y = pb[w];
-                        wa[4 * w] = x.x; wa[4 * w + 1] = x.y; wa[4 * w + 2] = x.z; wa[4 * w + 3] = x.w;
-                        wb[4 * w] = y.x; wb[4 * w + 1] = y.y; wb[4 * w + 2] = y.z; wb[4 * w + 3] = y.w;
-                    }
-                    uint32_t word[WQ];
-#pragma unroll
-                    for (int w = 0; w < WQ; ++w) word[w] = 0;
-                    pk16 sm = bias2;   // step maximum over the lane's rows, per half
-                    pk16 hprev = bias2;
-                    int ckA = 0, ckB = 0, kpA = 0, kpB = 0;
+                    const uint32_t msk = (fA ? 0xffffu : 0u) | (fB ? 0xffff0000u : 0u);
+                    bh = as_pk(as_u(bh) & ~msk);
 #pragma unroll
                     for (int t = 0; t < R; ++t) {
-                        const pk16 p = as_pk(__builtin_amdgcn_perm(wb[t >> 1], wa[t >> 1],
-                                                                   (t & 1) ? 0x07060302u : 0x05040100u));
-                        const pk16 eext = e[t] - ge2;
-                        const pk16 en = max3h(eext, hg[t], bias2);   // E* = max(E, 0)
-                        const pk16 fext = upf - ge2;
-                        const pk16 fn = max3h(fext, upg, bias2);     // F* = max(F, 0)
-                        const pk16 hd = diag + p;
-                        const pk16 h = max3h(hd, en, fn);
-                        // bytes (notd A, notd B, eext A, eext B) and (note A, note B, fext A, fext B)
-                        const uint32_t f0 = __builtin_amdgcn_perm(as_u(hg[t] - eext), as_u(hd - h), 0x0b0a0908u);
-                        const uint32_t f1 = __builtin_amdgcn_perm(as_u(upg - fext), as_u(en - h), 0x0b0a0908u);
-                        const uint32_t m0 = 0x01010101u << (2 * (t & 3)), m1 = m0 << 1;
-                        uint32_t wd = word[t >> 2];
-                        wd = bfi_s(m0, f0, wd);
-                        wd = bfi_s(m1, f1, wd);
-                        word[t >> 2] = wd;
-                        if constexpr (SNAP) {
-                            if (t & 1) sm = max3h(sm, hprev, h);
-                            else if (t == R - 1) sm = pmax(sm, h);
-                            else hprev = h;
-                        } else {
-                            const uint32_t hu = as_u(h);
-                            const int kA = (int)((hu & 0xffffu) << 5) | (31 - t);
-                            const int kB = (int)((hu >> 16) << 5) | (31 - t);
-                            if (t & 1) {
-                                ckA = vmax3(ckA, kpA, kA);
-                                ckB = vmax3(ckB, kpB, kB);
-                            } else if (t == R - 1) {
-                                ckA = max(ckA, kA);
-                                ckB = max(ckB, kB);
-                            } else {
-                                kpA = kA;
-                                kpB = kB;
-                            }
-                        }
-                        diag = hg[t];
-                        hg[t] = h - goe2;
-                        e[t] = en;
-                        upg = hg[t];
-                        upf = fn;
+                        hg[t] = as_pk((init2u & msk) | (as_u(hg[t]) & ~msk));
+                        e[t] = as_pk((init2u & msk) | (as_u(e[t]) & ~msk));
                     }
-                    botg = as_u(upg);
-                    botf = as_u(upf);
+                    diag0 = (init2u & msk) | (diag0 & ~msk);
+                }
+                pk16 upg = as_pk(upgu), upf = as_pk(upfu);
+                pk16 diag = as_pk(diag0);
+                diag0 = upgu;
+                uint32_t word[WQ];
 #pragma unroll
-                    for (int w = 0; w < WQ; ++w) stage[64 * ((u & 3) * WQ + w)] = word[w];
-                    if ((u & 3) == 3 && cw && k8 < steps_s) {
-                        // half a tile (4 steps, 16*WQ bytes of the lane's 32*WQ)
-                        uint4 *dst = reinterpret_cast<uint4 *>(cw + (int64_t)(k8 >> 3) * LS * 8 * WQ) + (u >> 2) * WQ;
+                for (int w = 0; w < WQ; ++w) word[w] = 0;
+                pk16 sm = bias2;   // step maximum over the lane's rows, per half
+                pk16 hprev = bias2;
+                int ckA = 0, ckB = 0, kpA = 0, kpB = 0;
 #pragma unroll
-                        for (int v = 0; v < WQ; ++v)
-                            dst[v] = make_uint4(stage[64 * (4 * v)], stage[64 * (4 * v + 1)], stage[64 * (4 * v + 2)],
-                                                stage[64 * (4 * v + 3)]);
-                    }
-                    if (HB && bout) {
-                        const int K = k - ll;
-                        if (ll == LS - 1 && K >= 0 && K < C) bout[K] = make_int2((int)botg, (int)botf);
-                    }
+                for (int t = 0; t < R; ++t) {
+                    const pk16 p = as_pk(__builtin_amdgcn_perm(wb[t >> 1], wa[t >> 1],
+                                                               (t & 1) ? 0x07060302u : 0x05040100u));
+                    const pk16 eext = e[t] - ge2;
+                    const pk16 en = max3h(eext, hg[t], bias2);   // E* = max(E, 0)
+                    const pk16 fext = upf - ge2;
+                    const pk16 fn = max3h(fext, upg, bias2);     // F* = max(F, 0)
+                    const pk16 hd = diag + p;
+                    const pk16 h = max3h(hd, en, fn);
+                    // bytes (notd A, notd B, eext A, eext B) and (note A, note B, fext A, fext B)
+                    const uint32_t f0 = __builtin_amdgcn_perm(as_u(hg[t] - eext), as_u(hd - h), 0x0b0a0908u);
+                    const uint32_t f1 = __builtin_amdgcn_perm(as_u(upg - fext), as_u(en - h), 0x0b0a0908u);
+                    const uint32_t m0 = 0x01010101u << (2 * (t & 3)), m1 = m0 << 1;
+                    uint32_t wd = word[t >> 2];
+                    wd = bfi_s(m0, f0, wd);
+                    wd = bfi_s(m1, f1, wd);
+                    word[t >> 2] = wd;
                     if constexpr (SNAP) {
-                        // 0xffff in each half whose step maximum beats its best
-                        const uint32_t imp = as_u((bh - sm) >> pk16{15, 15});
-                        bh = pmax(bh, sm);
-                        const uint32_t kw = (uint32_t)(k & 0xffff) * 0x10001u;
-                        bk = bfi(imp, kw, bk);
-#pragma unroll
-                        for (int t = 0; t < R; ++t) hs[t] = as_pk(bfi(imp, as_u(hg[t]), as_u(hs[t])));
+                        if (t & 1) sm = max3h(sm, hprev, h);
+                        else if (t == R - 1) sm = pmax(sm, h);
+                        else hprev = h;
                     } else {
-                        {
-                            const int ch = ckA >> 5;
-                            const bool up = ch > bhA;
-                            bcolA = up ? ckA : bcolA;
-                            bkA = up ? k : bkA;
-                            bhA = max(bhA, ch);
+                        const uint32_t hu = as_u(h);
+                        const int kA = (int)((hu & 0xffffu) << 5) | (31 - t);
+                        const int kB = (int)((hu >> 16) << 5) | (31 - t);
+                        if (t & 1) {
+                            ckA = vmax3(ckA, kpA, kA);
+                            ckB = vmax3(ckB, kpB, kB);
+                        } else if (t == R - 1) {
+                            ckA = max(ckA, kA);
+                            ckB = max(ckB, kB);
+                        } else {
+                            kpA = kA;
+                            kpB = kB;
                         }
-                        {
-                            const int ch = ckB >> 5;
-                            const bool up = ch > bhB;
-                            bcolB = up ? ckB : bcolB;
-                            bkB = up ? k : bkB;
-                            bhB = max(bhB, ch);
-                        }
+                    }
+                    diag = hg[t];
+                    hg[t] = h - goe2;
+                    e[t] = en;
+                    upg = hg[t];
+                    upf = fn;
+                }
+                botg = as_u(upg);
+                botf = as_u(upf);
+#pragma unroll
+                for (int w = 0; w < WQ; ++w) stage[64 * ((u & 3) * WQ + w)] = word[w];
+                if ((u & 3) == 3 && cw && k8 < steps_s) {
+                    // half a tile (4 steps, 16*WQ bytes of the lane's 32*WQ)
+                    uint4 *dst = reinterpret_cast<uint4 *>(cw + (int64_t)(k8 >> 3) * LS * 8 * WQ) + (u >> 2) * WQ;
+#pragma unroll
+                    for (int v = 0; v < WQ; ++v)
+                        dst[v] = make_uint4(stage[64 * (4 * v)], stage[64 * (4 * v + 1)], stage[64 * (4 * v + 2)],
+                                            stage[64 * (4 * v + 3)]);
+                }
+                if (HB && bout) {
+                    const int K = k - ll;
+                    if (ll == LS - 1 && K >= 0 && K < C) bout[K] = make_int2((int)botg, (int)botf);
+                }
+                if constexpr (SNAP) {
+                    // 0xffff in each half whose step maximum beats its best
+                    const uint32_t imp = as_u((bh - sm) >> pk16{15, 15});
+                    bh = pmax(bh, sm);
+                    const uint32_t kw = (uint32_t)(k & 0xffff) * 0x10001u;
+                    bk = bfi(imp, kw, bk);
+#pragma unroll
+                    for (int t = 0; t < R; ++t) hs[t] = as_pk(bfi(imp, as_u(hg[t]), as_u(hs[t])));
+                } else {
+                    {
+                        const int ch = ckA >> 5;
+                        const bool up = ch > bhA;
+                        bcolA = up ? ckA : bcolA;
+                        bkA = up ? k : bkA;
+                        bhA = max(bhA, ch);
+                    }
+                    {
+                        const int ch = ckB >> 5;
+                        const bool up = ch > bhB;
+                        bcolB = up ? ckB : bcolB;
+                        bkB = up ? k : bkB;
+                        bhB = max(bhB, ch);
                     }
                 }
+                rcur = rnx;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) {
+                    wa[w] = na[w];
+                    wb[w] = nb[w];
+                }
+            };
+            for (int k8 = 0; k8 < steps8; k8 += 8) {
+                step(std::integral_constant<int, 0>{}, k8);
+                step(std::integral_constant<int, 1>{}, k8);
+                step(std::integral_constant<int, 2>{}, k8);
+                step(std::integral_constant<int, 3>{}, k8);
+                step(std::integral_constant<int, 4>{}, k8);
+                step(std::integral_constant<int, 5>{}, k8);
+                step(std::integral_constant<int, 6>{}, k8);
+                step(std::integral_constant<int, 7>{}, k8);
+                rbuf = pair_code(rnext);
+                bbuf = bnext;
+                rnext = residues(k8 + 16);
+                bnext = bounds(k8 + 16);
             }
             publishA();
             publishB();
