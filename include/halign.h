@@ -163,6 +163,24 @@ int halign_sw_batch(halign_ctx *ctx, const halign_scoring *sc,
                     int32_t *score, int32_t *cells, uint16_t *ins, uint32_t *aligned,
                     void *stream);
 
+/* For callers that cannot allocate memory (code under hipGraph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): the score-only form
+ * of halign_sw_batch (HALIGN_SCORE_ONLY, end cells through `cells`) without a
+ * context and without any allocation, host or device.  Outputs as in
+ * halign_sw_batch: score[N] and, when cells != NULL, cells[N][4] =
+ * (0, 0, i1, j1).  Pairs run one per lane in input order (no length sort).
+ * Scratch: one static device array of HALIGN_NOALLOC_SCRATCH_BYTES per GPU
+ * (held from the library's first use of that GPU until the process ends);
+ * the longest sequence may use at most that many bytes of strip boundary
+ * rows per workgroup (512 bytes per residue, rounded up to 4 residues), which
+ * covers every length the library supports; beyond that HALIGN_E_UNSUPPORTED.
+ * Residue codes are not checked (codes >= alphabet give unspecified scores,
+ * never out-of-bounds accesses).  Every call on a GPU shares that GPU's
+ * array: calls that overlap on one GPU (two streams, two threads) race. */
+#define HALIGN_NOALLOC_SCRATCH_BYTES (64u << 20)
+int halign_sw_score_noalloc(const halign_scoring *sc, const uint8_t *center, int32_t m,
+                            const halign_seqs *seqs, int32_t *score, int32_t *cells, void *stream);
+
 /* Score-only SW of anchored pairs (center selection, training targets):
  * score[64*q + l] = SW(seq anchors_host[q], seq partners_host[64*q + l]) for
  * q < nanchors, l < 64.  Index arrays are HOST arrays; score is device. */

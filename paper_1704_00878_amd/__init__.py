@@ -92,6 +92,7 @@ def lib():
         "halign_ctx_graph_launches": ([P, P], I),
         "halign_encode": ([P, I64, P, P], I),
         "halign_sw_batch": ([P, P, P, I, P, U32, P, P, P, P, P], I),
+        "halign_sw_score_noalloc": ([P, P, I, P, P, P, P], I),
         "halign_sw_pairs": ([P, P, P, P, I, P, P, P], I),
         "halign_merge": ([P, P, I, I, P, P, P, P], I),
         "halign_emit_rows": ([P, P, I, P, P, P, P, I64, P, P], I),
@@ -246,6 +247,12 @@ def halign_sw_batch(ctx: Context, sc: Scoring, center_t, m: int, seqs: DeviceSeq
                                                                   else center_t.data_ptr()),
                                  m, seqs.ref, flags, _ptr(score), _ptr(cells), _ptr(ins), _ptr(aligned),
                                  _stream(stream)))
+
+
+def halign_sw_score_noalloc(sc: Scoring, center_t, m: int, seqs: DeviceSeqs, score, cells=None, stream=None):
+    _check(lib().halign_sw_score_noalloc(sc.ref, ctypes.c_void_p(center_t if isinstance(center_t, int)
+                                                                 else center_t.data_ptr()),
+                                         m, seqs.ref, _ptr(score), _ptr(cells), _stream(stream)))
 
 
 def halign_sw_pairs(ctx: Context, sc: Scoring, seqs: DeviceSeqs, anchors: np.ndarray,

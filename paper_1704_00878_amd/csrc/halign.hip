@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <array>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -29,15 +30,15 @@
 
 namespace {
 
-thread_local std::string g_err;
+// message of the last failure on this thread (a fixed buffer: reporting an
+// error allocates nothing)
+thread_local char g_err[512];
 
 int fail(int code, const char *fmt, ...) {
-    char buf[512];
     va_list ap;
     va_start(ap, fmt);
-    vsnprintf(buf, sizeof buf, fmt, ap);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
     va_end(ap);
-    g_err = buf;
     return code;
 }
 
@@ -936,7 +937,7 @@ int route_of(uint32_t flags, int m, int N) {
 // ===========================================================================
 extern "C" {
 
-const char *halign_last_error(void) { return g_err.c_str(); }
+const char *halign_last_error(void) { return g_err; }
 
 int halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out) {
     if (!out) return fail(HALIGN_E_INVALID, "out is NULL");
@@ -1126,14 +1127,14 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
         }
         return HALIGN_OK;
     };
-    std::vector<int32_t> pids(N);
-    std::iota(pids.begin(), pids.end(), 0);
     BatchOut out{score, cells, endcell, ins, aligned};
     if (tb && G) {
         out.G = G;
         out.gskip = gskip;
     }
     RCHK(prep());
+    std::vector<int32_t> pids(N);
+    std::iota(pids.begin(), pids.end(), 0);
     RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st, tune));
     ctx->last_tune = {tune.route, tune.R, tune.smul, tune.LS > 0 ? tune.LS : 64, ctx->last_pk};
     if (!tb && cells) {
@@ -1537,6 +1538,110 @@ int halign_sw_pairs(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs
     halign_seqs sq2 = *seqs;
     sq2.n = N;
     RCHK(run_groups(ctx, S, &sq2, 2, (int64_t)gcen.size(), gcen, gb0, perm, gslot, sums, score, st, (int)np));
+    return HALIGN_OK;
+}
+
+}  // extern "C"
+
+// ---------------------------------------------------------------------------
+// Allocation-free score-only batch: its scratch (matrix copy, work counter,
+// strip boundary rows) is one static device array per GPU.  In host code the
+// array's name only stands for the symbol; its device address on the current
+// GPU comes from hipGetSymbolAddress, taken once per device and kept.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = HALIGN_NOALLOC_SCRATCH_BYTES;
+constexpr size_t kScratchHead = 4096;   // matrix copy at 0, work counter at 2048, boundary rows after
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+struct ScratchSlot {
+    void *ptr = nullptr;
+    int num_cu = 0;
+};
+constexpr int kMaxDevices = 64;
+ScratchSlot g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// the current device's copy of `scratch` (address and compute-unit count)
+int scratch_of_device(int dev, ScratchSlot *out) {
+    if (dev < 0 || dev >= kMaxDevices) return fail(HALIGN_E_UNSUPPORTED, "device %d", dev);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    ScratchSlot &s = g_scratch[dev];
+    if (!s.ptr) {
+        void *p = nullptr;
+        HCHK(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        int cu = 0;
+        HCHK(hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev));
+        s.num_cu = std::max(1, cu);
+        s.ptr = p;
+    }
+    *out = s;
+    return HALIGN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int halign_sw_score_noalloc(const halign_scoring *sc, const uint8_t *center, int32_t m, const halign_seqs *seqs,
+                            int32_t *score, int32_t *cells, void *stream) {
+    RCHK(check_scoring(sc));
+    RCHK(check_seqs(seqs));
+    if (m <= 0 || !center) return fail(HALIGN_E_INVALID, "empty center");
+    if (m >= 65536) return fail(HALIGN_E_UNSUPPORTED, "center length %d >= 65536", m);
+    const int N = seqs->n;
+    if (N == 0) return HALIGN_OK;
+    if (!score) return fail(HALIGN_E_INVALID, "score is NULL");
+    int dev = 0;
+    HCHK(hipGetDevice(&dev));
+    ScratchSlot sl;
+    RCHK(scratch_of_device(dev, &sl));
+    const int64_t *oh = seqs->offsets_host;
+    int nmax_all = 0;
+    for (int k = 0; k < N; ++k) nmax_all = std::max(nmax_all, (int)(oh[k + 1] - oh[k]));
+    // boundary rows: 64 lanes x the longest sequence (whole prefetch blocks) per workgroup
+    const int64_t bstride = (int64_t)64 * strip_cols(nmax_all);
+    const size_t per_wg = (size_t)bstride * sizeof(int2);
+    const size_t avail = kScratchBytes - kScratchHead;
+    if (per_wg > avail)
+        return fail(HALIGN_E_UNSUPPORTED,
+                    "longest sequence %d needs %zu bytes of scratch per workgroup; the static scratch holds %zu",
+                    nmax_all, per_wg, avail);
+    const int64_t ngroups = ((int64_t)N + 63) / 64;
+    const int grid = (int)std::max<int64_t>(
+        1, std::min<int64_t>({ngroups, (int64_t)sl.num_cu * 16, (int64_t)(avail / per_wg)}));
+    hipStream_t st = (hipStream_t)stream;
+    unsigned char *base = (unsigned char *)sl.ptr;
+    hk::MatrixArg mat{};
+    memcpy(mat.v, sc->matrix_host, (size_t)sc->alphabet * sc->alphabet);
+    hipLaunchKernelGGL(hk::matrix_copy_kernel, dim3(1), dim3(256), 0, st, mat, sc->alphabet * sc->alphabet,
+                       (int8_t *)base);
+    HCHK(hipGetLastError());
+    // the work counter starts at zero on every call (the array keeps the last call's contents)
+    RCHK(launch_fill((uint32_t *)(base + 2048), 0u, 2, st));
+    hk::InterArgs a{};
+    a.mat = (const int8_t *)base;
+    a.alpha = sc->alphabet;
+    a.center = center;
+    a.m = m;
+    a.res = seqs->residues;
+    a.off = seqs->offsets;
+    a.mode = 0;
+    a.order = nullptr;
+    a.gnmax = nullptr;
+    a.nseq = N;
+    a.ngroups = ngroups;
+    a.ge = sc->gap_extend;
+    a.goe = sc->gap_open + sc->gap_extend;
+    a.counter = (unsigned long long *)(base + 2048);
+    a.score = score;
+    a.endcell = nullptr;
+    a.cells4 = reinterpret_cast<int4 *>(cells);
+    a.bound = (int2 *)(base + kScratchHead);
+    a.bstride = bstride;
+    launch_inter(a, false, cells != nullptr, grid, st);
+    HCHK(hipGetLastError());
     return HALIGN_OK;
 }
 

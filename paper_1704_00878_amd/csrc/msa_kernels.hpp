@@ -23,6 +23,16 @@ __global__ void fill_u16_kernel(uint16_t *p, uint16_t v, int64_t n) {
         p[x] = v;
 }
 
+// A substitution matrix passed by value (kernel argument), copied into device
+// memory by one workgroup: no host staging buffer is involved.
+struct MatrixArg {
+    int8_t v[32 * 32];
+};
+
+__global__ void matrix_copy_kernel(MatrixArg mat, int n, int8_t *dst) {
+    for (int x = threadIdx.x; x < n; x += blockDim.x) dst[x] = mat.v[x];
+}
+
 // Score-only calls that ask for cells report (0, 0, i1, j1).
 __global__ void endcell_to_cells_kernel(const int32_t *endcell, int n, int32_t *cells) {
     const int k = blockIdx.x * blockDim.x + threadIdx.x;

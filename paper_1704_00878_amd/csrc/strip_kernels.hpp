@@ -38,8 +38,8 @@ struct InterArgs {
     const uint8_t *res;
     const int64_t *off;
     int mode;                 // 0 batch, 1 all pairs (a < b), 2 anchored groups
-    const int32_t *order;     // mode 0: 64 * ngroups pair ids (-1 = empty lane)
-    const int32_t *gnmax;     // mode 0: per group longest sequence (code layout)
+    const int32_t *order;     // mode 0: 64 * ngroups pair ids (-1 = empty lane); NULL: pair 64g + lane
+    const int32_t *gnmax;     // mode 0: per group longest sequence (code layout); NULL: from the lanes
     const int32_t *gcen;      // mode 2: center seq id per group
     const int32_t *gb0;       // mode 2: first partner position in perm per group
     const int32_t *perm;      // modes 1/2: sequence ids (mode 1: sorted by length)
@@ -50,7 +50,8 @@ struct InterArgs {
     int ge, goe;
     unsigned long long *counter;   // next group (zeroed before the launch)
     int32_t *score;           // mode 0: per pair id; mode 2: per lane slot (optional)
-    int32_t *endcell;
+    int32_t *endcell;         // mode 0: (i1, j1) per pair id (optional)
+    int4 *cells4;             // mode 0 score-only: (0, 0, i1, j1) per pair id (optional)
     uint32_t *codes;
     const int64_t *gcode_base;// per group (u32 words)
     int2 *bound;              // per workgroup slot: bstride int2
@@ -97,7 +98,7 @@ sw_inter_kernel(InterArgs a) {
         int m = a.m;
         int cid = -1;
         if (a.mode == 0) {
-            pid = a.order[g * 64 + lane];
+            pid = a.order ? a.order[g * 64 + lane] : (g * 64 + lane < a.nseq ? (int)(g * 64 + lane) : -1);
             sid = pid;
         } else {
             int64_t apos = -1, b0;
@@ -124,7 +125,7 @@ sw_inter_kernel(InterArgs a) {
         // that runs any column holds at least one residue)
         const uint8_t *sq = n > 0 ? s : a.res;
         int nmax = n;
-        if (a.mode == 0) {
+        if (a.mode == 0 && a.gnmax) {
             nmax = a.gnmax[g];
         } else {
 #pragma unroll
@@ -253,6 +254,8 @@ sw_inter_kernel(InterArgs a) {
                     a.endcell[2 * pid] = best.h > 0 ? best.i + 1 : 0;
                     a.endcell[2 * pid + 1] = best.h > 0 ? best.j : 0;
                 }
+                if (ENDC && a.cells4)
+                    a.cells4[pid] = make_int4(0, 0, best.h > 0 ? best.i + 1 : 0, best.h > 0 ? best.j : 0);
             }
         } else {
             const int v = sid >= 0 ? hmax : 0;
