@@ -302,6 +302,10 @@ struct Scoring {
 // ---------------------------------------------------------------------------
 enum Route { kRouteIntra = 0, kRouteInter = 1 };
 
+// pairs longer than this (sequence residues) run on the wavefront kernel even
+// in a batch that runs one pair per lane
+constexpr int kLongPair = 1000;
+
 // Rows per lane and passes of the wavefront kernel: passes = ceil(m / 512),
 // R = ceil(m / (64 * passes)) <= 8, so a pass holds 64*R >= m/passes rows.
 void pick_geom(int m, int *R, int *passes) {
@@ -1133,9 +1137,22 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
         out.gskip = gskip;
     }
     RCHK(prep());
-    std::vector<int32_t> pids(N);
-    std::iota(pids.begin(), pids.end(), 0);
-    RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route_of(flags, m, N), out, st, tune));
+    // Routing by pair length: when the batch as a whole runs one pair per lane
+    // (the route the caller did not force), pairs longer than kLongPair
+    // residues run on the wavefront kernel, one pair per stream, in a launch
+    // of their own; the rest keep the strip kernel.  Both write the same
+    // outputs, each at its own pair ids.
+    const int route = tune.route >= 0 ? tune.route : route_of(flags, m, N);
+    std::vector<int32_t> pids, longp;
+    pids.reserve(N);
+    const int64_t *oh = seqs->offsets_host;
+    const bool split = route == kRouteInter && (flags & (3u << 4)) == HALIGN_ROUTE_AUTO;
+    for (int k = 0; k < N; ++k) {
+        if (split && oh[k + 1] - oh[k] > kLongPair) longp.push_back(k);
+        else pids.push_back(k);
+    }
+    if (!longp.empty()) RCHK(run_batch(ctx, S, center, m, seqs, longp, tb, endc, kRouteIntra, out, st));
+    RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route, out, st, tune));
     ctx->last_tune = {tune.route, tune.R, tune.smul, tune.LS > 0 ? tune.LS : 64, ctx->last_pk};
     if (!tb && cells) {
         // score-only with cells: report the end cell as (0, 0, i1, j1)

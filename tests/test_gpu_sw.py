@@ -250,6 +250,42 @@ def test_profile_int32_path(H, ctx, m, monkeypatch):
     _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, center, seqs)
 
 
+@pytest.mark.parametrize("traceback", [True, False])
+def test_long_pairs_leave_the_strip_route(H, ctx, traceback, monkeypatch):
+    """A batch on the one-pair-per-lane route (chosen here through the route
+    knob; by default it is the route of batches of 262,144 pairs and more):
+    its pairs longer than 1,000 residues run on the wavefront kernel in a
+    launch of their own, the rest on the strip kernel, and every pair equals
+    the oracle."""
+    import torch
+    monkeypatch.setenv("HALIGN_ROUTE", "inter")
+    rng = np.random.default_rng(77)
+    center = rng.integers(0, 20, size=300).astype(np.uint8)
+    base = synth.generate("plain64", n_seqs=120, seed=78)
+    seqs = [base.seq(k) for k in range(base.n)]
+    for L in (1000, 1001, 1200, 2000):               # long pairs holding the center
+        s = rng.integers(0, 20, size=L).astype(np.uint8)
+        p = int(rng.integers(0, L - 300))
+        s[p:p + 300] = center
+        seqs.insert(int(rng.integers(0, len(seqs))), s)
+    seqs.insert(7, rng.integers(0, 20, size=1500).astype(np.uint8))   # long and unrelated
+    seqs.insert(9, np.zeros(0, np.uint8))
+    ss = synth.SeqSet.from_list(seqs)
+    ds = H.DeviceSeqs(ss)
+    sc = H.Scoring()
+    cen = torch.from_numpy(center).cuda()
+    out = H.sw_batch(ctx, sc, ds, 0, traceback=traceback, center_seq=cen)
+    torch.cuda.synchronize()
+    st = ctx.last_stats()
+    assert st["route"] == 1 and st["launches"] >= 2
+    got = dict(score=out["score"].cpu().numpy(), cells=out["cells"].cpu().numpy())
+    if traceback:
+        got["ins"] = out["ins"].cpu().numpy().view(np.uint16)
+        got["aligned"] = H.aligned_to_bool(out["aligned"].cpu().numpy(), len(center))
+    _compare(got, sc.matrix, sc.gap_open, sc.gap_extend, center, ss, traceback=traceback)
+    assert (got["score"][[k for k in range(ss.n) if ss.lengths()[k] in (1001, 1200, 2000)]] >= 300 * 4).all()
+
+
 def test_deterministic_repeat(H, ctx):
     seqs = synth.generate("plain64")
     sc = H.Scoring()
