@@ -140,7 +140,7 @@ def counter_record(kernel: str, workload: str, plan: dict):
 
 
 def learned_report(H, ctx, sc, workload: str, anchors: int, partners: int, epochs: int, ema: float,
-                   nseqs: int = 0, exact: bool = True):
+                   nseqs: int = 0, exact: bool = True, prejudge=(256, 16384)):
     """Learned center on a family set: the exhaustive center (all pairs,
     score-only) against the trained proposer's judged top-16, with the MSA of
     each and its avg SP.  Also the untrained network, 16 random candidates and
@@ -186,8 +186,11 @@ def learned_report(H, ctx, sc, workload: str, anchors: int, partners: int, epoch
                                                             partners=partners))
     log(f"bench: trained on {anchors * partners} pairs x {epochs} epochs in {t_train:.2f} s, loss {losses[0]:.4f} -> "
         f"{losses[-1]:.4f}")
+    ctx.set_prejudge(0, 0)
+    c_plain, _ = H.halign_center_learned(ctx, sc, ds, prop, 16)   # top-16 by u judged directly
+    ctx.set_prejudge(*prejudge)
     (c_learned, cand), t_prop = timed(lambda: H.halign_center_learned(ctx, sc, ds, prop, 16))
-    log(f"bench: learned center {c_learned}: propose + judge {t_prop * 1e3:.1f} ms")
+    log(f"bench: learned center {c_learned}: propose + pre-judge + judge {t_prop * 1e3:.1f} ms")
     c_untrained, _ = H.halign_center_learned(ctx, sc, ds, H.Proposer(seed=1), 16)
     rand = np.random.default_rng(0).choice(N, 16, replace=False)
     if S is not None:
@@ -205,7 +208,8 @@ def learned_report(H, ctx, sc, workload: str, anchors: int, partners: int, epoch
     res = {}
     ref_name = "exact" if exact else "learned"
     centers = ((("exact", c_exact),) if exact else ()) + (
-        ("learned", c_learned), ("untrained", c_untrained), ("random16", c_random), ("seq0", 0))
+        ("learned", c_learned), ("learned_top16_only", c_plain), ("untrained", c_untrained), ("random16", c_random),
+        ("seq0", 0))
     ref = objective(c_exact if exact else c_learned)
     for name, c in centers:
         dt, sp, w = msa_of(c)
@@ -221,6 +225,7 @@ def learned_report(H, ctx, sc, workload: str, anchors: int, partners: int, epoch
         "exact_cells": float(pair_cells),
         "exact_gcups": round(pair_cells / t_exact / 1e9, 1) if exact else None,
         "train_s": round(t_train, 3), "train_pairs": anchors * partners, "anchors": anchors, "epochs": epochs,
+        "prejudge": {"candidates": prejudge[0], "partners": prejudge[1]},
         "ema": ema,
         "loss_first_last": [round(losses[0], 5), round(losses[-1], 5)],
         "propose_judge_s": round(t_prop, 4), "candidates": [int(x) for x in cand],
@@ -250,8 +255,10 @@ def main():
     ap.add_argument("--learned-n", type=int, default=0, help="first N sequences of the family set (0: all)")
     ap.add_argument("--no-exact", action="store_true", help="learned report without the exhaustive center")
     ap.add_argument("--anchors", type=int, default=50000, help="training anchors")
-    ap.add_argument("--partners", type=int, default=4, help="training partners per anchor")
-    ap.add_argument("--epochs", type=int, default=16)
+    ap.add_argument("--partners", type=int, default=64, help="training partners per anchor")
+    ap.add_argument("--epochs", type=int, default=1)
+    ap.add_argument("--prejudge", type=int, nargs=2, default=(256, 16384), metavar=("CANDIDATES", "PARTNERS"),
+                    help="pre-judge of the learned center (0 0: off)")
     ap.add_argument("--ema", type=float, default=0.0, help="parameter average decay (0: off)")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -398,7 +405,7 @@ def main():
     learned = None
     if args.learned != "none":
         learned = learned_report(H, ctx, sc, args.learned, args.anchors, args.partners, args.epochs, args.ema,
-                                 args.learned_n, not args.no_exact)
+                                 args.learned_n, not args.no_exact, tuple(args.prejudge))
 
     out = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,

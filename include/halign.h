@@ -125,7 +125,8 @@ int  halign_ctx_last_stats(const halign_ctx *ctx, int64_t *stats_host /*[4]: cel
  * halign_ctx_last_plan reports {route, R, streams multiplier, lanes per
  * stream, packed (0/1: whether the last batch ran the packed kernel)} of the
  * last call (route -1 / R 0: defaults).  HALIGN_PROGRESS=1 prints one line on
- * stderr as each chunk of a chunked batch completes. */
+ * stderr as each chunk of a chunked batch completes; HALIGN_HOST_TIMING=1 one
+ * line per halign_msa call with the host time (us) between its stages. */
 int  halign_ctx_set_autotune(halign_ctx *ctx, int enable);
 /* halign_msa runs its pairwise batch with HALIGN_GRAPH when enabled (the
  * batch is planned and captured once, then replayed); graph_launches counts
@@ -223,6 +224,18 @@ int halign_center_exact(halign_ctx *ctx, const halign_scoring *sc, const halign_
  * exhaustive search over devices can split [0, *ngroups_host). */
 int halign_exact_tiling(int64_t n, int32_t step, int64_t g, int64_t *ngroups_host, int64_t *center_pos_host,
                         int64_t *partner0_host);
+/* The judge over a partner sample: sums[q] = sum over the listed partners
+ * (host array, npartners entries, sequence indices; a candidate scores 0
+ * against itself) of SW(seq cand[q], partner); *center_host (optional) = the
+ * candidate with the largest sum, ties to the lowest sequence index.  The
+ * same partners for every candidate, so differences between candidates are
+ * estimated with the sampling noise of the partners shared. */
+int halign_center_judge_sample(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+                               const int32_t *cand, int32_t ncand, const int32_t *partners_host, int32_t npartners,
+                               int64_t *sums, int32_t *center_host, void *stream);
+/* Pre-judge of halign_center_learned: candidates (0 = off, at most 256) and
+ * partners of the sample. */
+int  halign_ctx_set_prejudge(halign_ctx *ctx, int candidates, int partners);
 /* Exact judge restricted to candidates cand[ncand] (device): sums[q] =
  * sum_{j != cand[q]} SW(seq cand[q], seq j); *center_host = the candidate
  * with the largest sum, ties to the lowest sequence index. */
@@ -263,6 +276,15 @@ int halign_mlp_forward(halign_ctx *ctx, const halign_model *model, const uint16_
  * (fp32, 2*npairs x EMB) and loss_out[0] (device fp32). */
 int halign_pair_loss(halign_ctx *ctx, const float *E, const float *target, int32_t npairs,
                      float *dE, float *loss_out, void *stream);
+
+/* halign_pair_loss plus a term on groups of `group` consecutive pairs (1..64,
+ * dividing npairs; 0 = none): loss += lam * mean over groups of (mean of
+ * pred - target over the group)^2, the squared bias of a group's
+ * predictions.  With a group per anchor (all partners of one sequence), the
+ * term trains the mean prediction of each sequence against its partners,
+ * the quantity the candidate score u_i sums. */
+int halign_pair_loss_grouped(halign_ctx *ctx, const float *E, const float *target, int32_t npairs, int32_t group,
+                             float lam, float *dE, float *loss_out, void *stream);
 
 /* Backward of halign_mlp_forward for dE (Z and Hb from the same forward):
  * dW1 (fp32 FEAT x HID), db1 (HID), dW2 (fp32 HID x EMB), db2 (EMB).  The
@@ -305,6 +327,9 @@ typedef struct {
     uint64_t seed;
     float ema;                    /* 0: off */
     int32_t partners;             /* per anchor, 1..64 (0: 64) */
+    float group_weight;           /* > 0: batches of whole anchors and the
+                                     per-anchor term of halign_pair_loss_grouped
+                                     with this weight (0: plain pair loss) */
 } halign_train_opts;
 int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
                           const halign_train_opts *opts, const halign_params *params,
@@ -312,7 +337,11 @@ int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halig
 
 /* Learned center: featurize and embed every sequence, take the top k by u,
  * judge them exactly; *center_host = the best candidate (synchronises).
- * cand_host (optional, k entries) receives the candidates. */
+ * cand_host (optional, k entries) receives the candidates.  With a pre-judge
+ * set on the ctx (halign_ctx_set_prejudge), the top `candidates` (> k) by u
+ * are first scored against a common sample of `partners` sequences (evenly
+ * spaced indices; halign_center_judge_sample) and the k best of that sample
+ * are the ones judged exactly. */
 int halign_center_learned(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
                           const halign_model *model, int32_t k, int32_t *cand_host,
                           int32_t *center_host, void *stream);

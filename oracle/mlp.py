@@ -61,14 +61,22 @@ def forward(X, W1, b1, W2, b2, round_h: bool = True):
     return z, h, e
 
 
-def pair_loss(E, target):
-    """Loss and dL/dE for pairs (r, r + P)."""
+def pair_loss(E, target, group: int = 0, lam: float = 0.0):
+    """Loss and dL/dE for pairs (r, r + P): the mean squared error of the
+    predictions e_a . e_b, plus (group > 0) lam times the mean over groups of
+    `group` consecutive pairs of the squared mean error of the group."""
     P = len(target)
     a, b = E[:P], E[P:2 * P]
     pred = (a * b).sum(axis=1)
     diff = pred - target
     loss = float((diff ** 2).mean())
     g = 2.0 * diff / P
+    if group > 0:
+        assert P % group == 0
+        G = P // group
+        gm = diff.reshape(G, group).mean(axis=1)
+        loss += lam * float((gm ** 2).mean())
+        g = g + np.repeat(2.0 * lam * gm / (G * group), group)
     dE = np.zeros_like(E)
     dE[:P] = g[:, None] * b
     dE[P:2 * P] = g[:, None] * a

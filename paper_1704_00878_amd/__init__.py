@@ -61,7 +61,7 @@ class _Params(ctypes.Structure):
 class _TrainOpts(ctypes.Structure):
     _fields_ = [("anchors", ctypes.c_int32), ("batch", ctypes.c_int32), ("epochs", ctypes.c_int32),
                 ("lr", ctypes.c_float), ("seed", ctypes.c_uint64), ("ema", ctypes.c_float),
-                ("partners", ctypes.c_int32)]
+                ("partners", ctypes.c_int32), ("group_weight", ctypes.c_float)]
 
 
 _ALLOC_FN = ctypes.CFUNCTYPE(ctypes.c_void_p, ctypes.c_size_t, ctypes.c_void_p)
@@ -98,9 +98,12 @@ def lib():
         "halign_emit_rows": ([P, P, I, P, P, P, P, I64, P, P], I),
         "halign_center_exact": ([P, P, P, P, P, P], I),
         "halign_center_judge": ([P, P, P, P, I, P, P, P], I),
+        "halign_center_judge_sample": ([P, P, P, P, I, P, I, P, P, P], I),
+        "halign_ctx_set_prejudge": ([P, ctypes.c_int, ctypes.c_int], I),
         "halign_featurize": ([P, P, I, P, P], I),
         "halign_mlp_forward": ([P, P, P, I, P, P, P, P], I),
         "halign_pair_loss": ([P, P, P, I, P, P, P], I),
+        "halign_pair_loss_grouped": ([P, P, P, I, I, ctypes.c_float, P, P, P], I),
         "halign_mlp_backward": ([P, P, P, I, P, P, P, P, P, P, P, P], I),
         "halign_f32_to_bf16": ([P, P, I64, P], I),
         "halign_exact_tiling": ([I64, I, I64, P, P, P], I),
@@ -230,6 +233,9 @@ class Context:
         _check(lib().halign_ctx_graph_launches(self.h, ctypes.byref(v)))
         return int(v.value)
 
+    def set_prejudge(self, candidates: int, partners: int):
+        _check(lib().halign_ctx_set_prejudge(self.h, candidates, partners))
+
     def fail_chunk(self, c: int):
         _check(lib().halign_debug_fail_chunk(self.h, c))
 
@@ -286,6 +292,15 @@ def halign_center_judge(ctx: Context, sc: Scoring, seqs: DeviceSeqs, cand, sums,
     c = ctypes.c_int32(-1)
     _check(lib().halign_center_judge(ctx.h, sc.ref, seqs.ref, _ptr(cand), cand.numel(), _ptr(sums),
                                      ctypes.byref(c), _stream(stream)))
+    return int(c.value)
+
+
+def halign_center_judge_sample(ctx: Context, sc: Scoring, seqs: DeviceSeqs, cand, partners: np.ndarray, sums,
+                               stream=None) -> int:
+    c = ctypes.c_int32(-1)
+    pa = np.ascontiguousarray(partners, dtype=np.int32)
+    _check(lib().halign_center_judge_sample(ctx.h, sc.ref, seqs.ref, _ptr(cand), cand.numel(), pa.ctypes.data,
+                                            len(pa), _ptr(sums), ctypes.byref(c), _stream(stream)))
     return int(c.value)
 
 
@@ -409,6 +424,11 @@ def halign_pair_loss(ctx: Context, E, target, npairs: int, dE, loss, stream=None
     _check(lib().halign_pair_loss(ctx.h, _ptr(E), _ptr(target), npairs, _ptr(dE), _ptr(loss), _stream(stream)))
 
 
+def halign_pair_loss_grouped(ctx: Context, E, target, npairs: int, group: int, lam: float, dE, loss, stream=None):
+    _check(lib().halign_pair_loss_grouped(ctx.h, _ptr(E), _ptr(target), npairs, group, lam, _ptr(dE), _ptr(loss),
+                                          _stream(stream)))
+
+
 def halign_mlp_backward(ctx: Context, prop: Proposer, X, nrows: int, Z, Hb, dE, dW1, db1, dW2, db2, stream=None):
     m = prop.model()
     _check(lib().halign_mlp_backward(ctx.h, ctypes.byref(m), _ptr(X), nrows, _ptr(Z), _ptr(Hb), _ptr(dE),
@@ -439,8 +459,8 @@ def halign_topk_center(ctx: Context, E, nrows: int, k: int, u, top, stream=None)
 
 def halign_train_proposer(ctx: Context, sc: Scoring, seqs: DeviceSeqs, prop: Proposer, anchors: int,
                           batch: int = 1024, epochs: int = 4, lr: float = 1e-3, seed: int = 7, ema: float = 0.0,
-                          partners: int = 64, stream=None):
-    opts = _TrainOpts(anchors, batch, epochs, lr, seed, ema, partners)
+                          partners: int = 64, group_weight: float = 0.0, stream=None):
+    opts = _TrainOpts(anchors, batch, epochs, lr, seed, ema, partners, group_weight)
     pr = prop.params()
     losses = (ctypes.c_float * epochs)()
     _check(lib().halign_train_proposer(ctx.h, sc.ref, seqs.ref, ctypes.byref(opts), ctypes.byref(pr), losses,

@@ -15,6 +15,7 @@
 #include <cstdlib>
 #include <cstring>
 #include <array>
+#include <chrono>
 #include <mutex>
 #include <numeric>
 #include <string>
@@ -110,11 +111,42 @@ struct halign_ctx {
     std::array<int, 5> last_tune = {-1, 0, 1, 64, 0};
     std::map<std::string, std::array<int, 5>> tuned;   // bucket -> {route, R, stream multiplier, lanes per stream, packed}
     std::string tune_file;    // optional cache file (HALIGN_TUNE_CACHE)
-    int *flag_host = nullptr; // pinned: largest residue code of the last validated call
+    int *flag_host = nullptr; // pinned: (tag << 8 | largest residue code) of the last validated call
+    uint32_t vtag = 0;        // tag of the last eager code check
+    uint32_t check_tag = 0;   // tag validate_check expects (0 after a graph replay)
     int flag_alpha = 0;       // alphabet that value is checked against (0 = nothing pending)
+    // HALIGN_HOST_TIMING=1: host time between labelled points of each
+    // halign_msa call, one line on stderr per call
+    int host_timing = 0;
+    std::vector<std::pair<const char *, double>> hmarks;
+    // learned center: pre-judge of the top prejudge_cand candidates by u
+    // against prejudge_part common partners (0: off)
+    int prejudge_cand = 0, prejudge_part = 0;
+    // host planning scratch, kept between calls (no allocation per call)
+    std::vector<int32_t> h_pids, h_plen, h_cnt, h_sof, h_head, h_nxt, h_scount, h_cur, h_split;
+    std::vector<int64_t> h_scols;
+    // the last tuned-plan lookup, by its integer key
+    int64_t tkey[4] = {-1, -1, -1, -1};
+    std::array<int, 5> tval = {-1, 0, 1, 64, 0};
 };
 
 namespace {
+
+void hmark(halign_ctx *ctx, const char *label) {
+    if (!ctx->host_timing) return;
+    const double us =
+        std::chrono::duration<double, std::micro>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    ctx->hmarks.push_back({label, us});
+}
+
+void hmark_print(halign_ctx *ctx) {
+    if (!ctx->host_timing || ctx->hmarks.size() < 2) return;
+    fprintf(stderr, "halign host us:");
+    for (size_t q = 1; q < ctx->hmarks.size(); ++q)
+        fprintf(stderr, " %s %.1f", ctx->hmarks[q].first, ctx->hmarks[q].second - ctx->hmarks[q - 1].second);
+    fprintf(stderr, " (total %.1f)\n", ctx->hmarks.back().second - ctx->hmarks.front().second);
+    ctx->hmarks.clear();
+}
 
 int grow(halign_ctx *ctx, DevBuf &b, size_t bytes) {
     if (bytes <= b.cap) return HALIGN_OK;
@@ -348,36 +380,47 @@ struct Tune {
     int pk = 0;       // 1: packed 16-bit wavefront kernel (two streams per lane group)
 };
 
+// pairs_in: the pair ids of the batch (NULL: 0 .. np-1).
 int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq,
-              const std::vector<int32_t> &pids_in, bool tb, bool endc, int route, const BatchOut &out,
-              hipStream_t st, const Tune &tune = Tune()) {
+              const int32_t *pids_in, int np, bool tb, bool endc, int route, const BatchOut &out, hipStream_t st,
+              const Tune &tune = Tune()) {
     const int64_t *oh = sq->offsets_host;
     const int N = sq->n;
-    const int np = (int)pids_in.size();
     if (np == 0) return HALIGN_OK;
-    auto len = [&](int pid) { return (int)(oh[pid + 1] - oh[pid]); };
+    auto pid_of = [&](int x) { return pids_in ? pids_in[x] : x; };
     // longest first (counting sort on length, stable); plen[x] = length of
     // pids[x], so that later passes read lengths in order
-    std::vector<int32_t> pids(np), plen(np);
+    if ((int)ctx->h_pids.size() < np) {
+        ctx->h_pids.resize(np);
+        ctx->h_plen.resize(np);
+    }
+    int32_t *pids = ctx->h_pids.data(), *plen = ctx->h_plen.data();
     int64_t sum_len = 0;
     {
-        std::vector<int32_t> lin(np);
         int maxlen = 0;
         for (int x = 0; x < np; ++x) {
-            lin[x] = len(pids_in[x]);
-            maxlen = std::max(maxlen, lin[x]);
-            sum_len += lin[x];
+            const int p = pid_of(x);
+            maxlen = std::max(maxlen, (int)(oh[p + 1] - oh[p]));
         }
-        std::vector<int32_t> cnt(maxlen + 2, 0);
-        for (int x = 0; x < np; ++x) cnt[maxlen - lin[x]]++;
+        std::vector<int32_t> &cnt = ctx->h_cnt;
+        cnt.assign(maxlen + 2, 0);
+        for (int x = 0; x < np; ++x) {
+            const int p = pid_of(x);
+            const int L = (int)(oh[p + 1] - oh[p]);
+            cnt[maxlen - L]++;
+            sum_len += L;
+        }
         int acc = 0;
         for (auto &c : cnt) { const int v = c; c = acc; acc += v; }
         for (int x = 0; x < np; ++x) {
-            const int q = cnt[maxlen - lin[x]]++;
-            pids[q] = pids_in[x];
-            plen[q] = lin[x];
+            const int p = pid_of(x);
+            const int L = (int)(oh[p + 1] - oh[p]);
+            const int q = cnt[maxlen - L]++;
+            pids[q] = p;
+            plen[q] = L;
         }
     }
+    hmark(ctx, "sort");
     const int aw = (m + 31) / 32;
     // int16 profile when every score and profile entry fits in 16 bits:
     // max score <= max(S) * min(m, longest sequence)
@@ -483,10 +526,16 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
         int nonempty = 0;   // pairs [0, nonempty) of the chunk are non-empty: empty pairs sort last
         for (int x = hi - 1; x >= lo && plen[x] == 0; --x) ++nonempty;
         nonempty = cn - nonempty;
+        const char *deal_env = getenv("HALIGN_DEAL");   // test knob: snake dealing
+        const bool deal_lpt = !(deal_env && !strcmp(deal_env, "snake"));
         if (route == kRouteIntra) {
             // streams: snake-deal the (longest first) non-empty pairs over the
             // resident waves so that every stream has about the same columns
-            const int wg_per_cu = std::max(1, std::min(4, (int)(ctx->lds_max / lds_stream)));
+            // resident workgroups per CU: by LDS, and by registers (the packed
+            // kernel and the 32-bit one with R > 6 hold four waves per SIMD,
+            // the 32-bit one with R <= 6 six)
+            const int waves_simd = (pk || R > 6) ? 4 : 6;
+            const int wg_per_cu = std::max(1, std::min({4, (int)(ctx->lds_max / lds_stream), waves_simd * 4 / 8}));
             const int resident = ctx->num_cu * wg_per_cu * 8 * NS * std::max(1, tune.smul) * (pk ? 2 : 1);
             nstreams = std::max(1, std::min(nonempty, (int)std::max(1.0, resident * tune.scale)));
             if (const char *e = getenv("HALIGN_MAX_STREAMS")) {   // test knob: many pairs per stream
@@ -523,18 +572,52 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             int32_t *h_spid = (int32_t *)(hs + o_spid);
             int64_t *h_scol = (int64_t *)(hs + o_scol);
             int32_t *h_sstr = (int32_t *)(hs + o_sstr);   // stream of each slot (for the walk)
-            // pairs and columns of each stream (snake order), then slots grouped by stream
-            // (the k-th non-empty pair, k = r * nstreams + q, goes to stream q in
-            // even rounds r and nstreams - 1 - q in odd ones)
-            std::vector<int32_t> scount(nstreams, 0);
-            std::vector<int64_t> scols(nstreams, 0);
-            int r = 0, q = 0;   // round and position of the next non-empty pair
-            for (int x = 0; x < nonempty; ++x) {
-                const int s = (r & 1) ? nstreams - 1 - q : q;
-                scount[s]++;
-                scols[s] += plen[lo + x];
-                if (++q == nstreams) { q = 0; ++r; }
+            // pairs and columns of each stream, then slots grouped by stream.
+            // Snake dealing: the k-th non-empty pair, k = r * nstreams + q, goes
+            // to stream q in even rounds r and nstreams - 1 - q in odd ones.
+            // Least-loaded dealing: each pair (longest first) goes to the stream
+            // with the fewest columns so far (a bucket queue on the column
+            // count, whose minimum only grows), so streams end within one pair
+            // length of each other.
+            std::vector<int32_t> &scount = ctx->h_scount;
+            std::vector<int64_t> &scols = ctx->h_scols;
+            scount.assign(nstreams, 0);
+            scols.assign(nstreams, 0);
+            std::vector<int32_t> &sof = ctx->h_sof;   // least-loaded dealing: stream of each non-empty pair
+            int64_t sum_ne = 0;
+            for (int x = 0; x < nonempty; ++x) sum_ne += plen[lo + x];
+            const int64_t maxload = (nonempty > 0 ? sum_ne / nstreams + plen[lo] : 0) + 1;
+            const bool lpt = deal_lpt && maxload <= ((int64_t)1 << 22);
+            hmark(ctx, "p_setup");
+            if (lpt) {
+                if ((int)sof.size() < nonempty) sof.resize(nonempty);
+                std::vector<int32_t> &head = ctx->h_head, &nxt = ctx->h_nxt;
+                head.assign(maxload + 1, -1);
+                if ((int)nxt.size() < nstreams) nxt.resize(nstreams);
+                for (int s2 = 0; s2 < nstreams; ++s2) nxt[s2] = s2 + 1 < nstreams ? s2 + 1 : -1;
+                head[0] = 0;
+                int64_t minp = 0;
+                for (int x = 0; x < nonempty; ++x) {
+                    while (head[minp] < 0) ++minp;
+                    const int s2 = head[minp];
+                    head[minp] = nxt[s2];
+                    sof[x] = s2;
+                    scount[s2]++;
+                    scols[s2] += plen[lo + x];
+                    const int64_t l2 = minp + plen[lo + x];
+                    nxt[s2] = head[l2];
+                    head[l2] = s2;
+                }
+            } else {
+                int r = 0, q = 0;   // round and position of the next non-empty pair
+                for (int x = 0; x < nonempty; ++x) {
+                    const int s2 = (r & 1) ? nstreams - 1 - q : q;
+                    scount[s2]++;
+                    scols[s2] += plen[lo + x];
+                    if (++q == nstreams) { q = 0; ++r; }
+                }
             }
+            hmark(ctx, "p_deal");
             int slot = 0;
             int64_t col = 0;
             for (int s = 0; s < nstreams; ++s) {
@@ -562,16 +645,37 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             }
             h_sbeg[nstreams] = col;
             total_cols = col;
-            // slots stream by stream (sequential writes): the pl-th pair of
-            // stream s is non-empty pair pl * nstreams + (pl odd ? nstreams - 1 - s : s)
-            for (int s = 0; s < nstreams; ++s) {
-                int64_t c = h_sbeg[s];
-                for (int pl = 0, qs = h_slot0[s]; pl < scount[s]; ++pl, ++qs) {
-                    const int x = pl * nstreams + ((pl & 1) ? nstreams - 1 - s : s);
-                    h_spid[qs] = pids[lo + x];
-                    h_scol[qs] = c;
-                    h_sstr[qs] = s;
-                    c += plen[lo + x];
+            hmark(ctx, "p_streams");
+            if (lpt) {
+                // slots of each stream in dealing order (longest first): the
+                // pairs are sorted by stream in host memory first, so that the
+                // pinned plan is written sequentially
+                std::vector<int32_t> &cur = ctx->h_cur, &ord = ctx->h_nxt;
+                cur.assign(h_slot0, h_slot0 + nstreams);
+                if ((int)ord.size() < nonempty) ord.resize(nonempty);
+                for (int x = 0; x < nonempty; ++x) ord[cur[sof[x]]++] = x;
+                for (int s2 = 0, qs = 0; s2 < nstreams; ++s2) {
+                    int64_t c = h_sbeg[s2];
+                    for (int pl = 0; pl < scount[s2]; ++pl, ++qs) {
+                        const int x = ord[qs];
+                        h_spid[qs] = pids[lo + x];
+                        h_scol[qs] = c;
+                        h_sstr[qs] = s2;
+                        c += plen[lo + x];
+                    }
+                }
+            } else {
+                // slots stream by stream (sequential writes): the pl-th pair of
+                // stream s is non-empty pair pl * nstreams + (pl odd ? nstreams - 1 - s : s)
+                for (int s = 0; s < nstreams; ++s) {
+                    int64_t c = h_sbeg[s];
+                    for (int pl = 0, qs = h_slot0[s]; pl < scount[s]; ++pl, ++qs) {
+                        const int x = pl * nstreams + ((pl & 1) ? nstreams - 1 - s : s);
+                        h_spid[qs] = pids[lo + x];
+                        h_scol[qs] = c;
+                        h_sstr[qs] = s;
+                        c += plen[lo + x];
+                    }
                 }
             }
             for (int x = nonempty; x < cn; ++x) {   // empty pairs after the streamed ones
@@ -603,6 +707,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
                 if (tb) code_words += (size_t)nst * ((nmax + 3) / 4) * 512;
             }
         }
+        hmark(ctx, "plan");
         char *dplan = nullptr;
         RCHK(plan_dev(ctx, pb.total, st, &dplan));
         HCHK(hipMemcpyAsync(dplan, hs, pb.total, hipMemcpyHostToDevice, st));
@@ -623,10 +728,9 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             unsigned long long *keys = (unsigned long long *)ctx->sbuf.p;
             uint8_t *sres = (uint8_t *)ctx->sbuf.p + keys_b;
             if (passes > 1) RCHK(grow(ctx, ctx->bound, std::max<size_t>(8, bound_elems * 8)));
-            RCHK(launch_fill((uint32_t *)keys, 0u, 2 * (int64_t)nslots, st));
             hipLaunchKernelGGL(hk::stage_stream_kernel, dim3(nslots), dim3(128), 0, st, sq->residues, sq->offsets,
                                (const int32_t *)(dplan + o_spid), (const int64_t *)(dplan + o_scol), nslots,
-                               p16 ? S.alpha : 31, sres);
+                               p16 ? S.alpha : 31, sres, keys);
             HCHK(hipGetLastError());
             RCHK(record(ctx, (*tv)[0], st));
             hk::StreamArgs a{};
@@ -739,6 +843,7 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             HCHK(hipGetLastError());
         }
         RCHK(record(ctx, (*tv)[2], st));
+        hmark(ctx, "launch");
         if (ctx->progress && chunks.size() > 1 && !ctx->capturing) {
             // progress lines wait for each chunk; otherwise the host plans the
             // next chunk while this one runs
@@ -792,20 +897,33 @@ void tune_save(halign_ctx *ctx, const std::string &key, const std::array<int, 5>
     if (f) f << key << " " << v[0] << " " << v[1] << " " << v[2] << " " << v[3] << " " << v[4] << "\n";
 }
 
+// *ran: whether candidate plans were run (the stage is then drained).
 int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, const halign_seqs *sq, bool tb,
-             bool endc, const BatchOut &out, hipStream_t st, Tune *best) {
+             bool endc, const BatchOut &out, hipStream_t st, Tune *best, bool *ran) {
+    *ran = false;
     const int N = sq->n;
     const int mean = N > 0 ? (int)((sq->offsets_host[N] - sq->offsets_host[0]) / N) : 0;
+    auto apply = [&](const std::array<int, 5> &v) {
+        best->route = v[0];
+        best->R = v[1];
+        best->smul = v[2];
+        best->LS = v[3];
+        best->pk = v[4];
+    };
+    const int64_t ik[4] = {m, N, mean, tb ? 1 : 0};
+    if (std::equal(ik, ik + 4, ctx->tkey)) {   // same bucket as the last call: no string key
+        apply(ctx->tval);
+        return HALIGN_OK;
+    }
     const std::string key = tune_key(m, N, mean, tb);
     auto it = ctx->tuned.find(key);
     if (it != ctx->tuned.end()) {
-        best->route = it->second[0];
-        best->R = it->second[1];
-        best->smul = it->second[2];
-        best->LS = it->second[3];
-        best->pk = it->second[4];
+        apply(it->second);
+        std::copy(ik, ik + 4, ctx->tkey);
+        ctx->tval = it->second;
         return HALIGN_OK;
     }
+    *ran = true;
     // the batch itself (up to 4e10 cells: a few tens of ms per candidate), or a
     // strided sample of 65,536 pairs that keeps the length mix and, through the
     // stream count, the number of pairs per stream
@@ -841,7 +959,7 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
             // (the previous run has synchronised)
             ctx->stage_off = ctx->plan_off = 0;
             ctx->ntev = 0;
-            RCHK(run_batch(ctx, S, center, m, sq, sample, tb, endc, c.route, out, st, c));
+            RCHK(run_batch(ctx, S, center, m, sq, sample.data(), (int)sample.size(), tb, endc, c.route, out, st, c));
             float wk = 0.f;
             RCHK(tev_sum(ctx, &ms, &wk));
             RCHK(stage_wait(ctx));
@@ -855,6 +973,8 @@ int autotune(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, co
     const std::array<int, 5> v = {best->route, best->R, best->smul, best->LS > 0 ? best->LS : 64, best->pk};
     ctx->tuned[key] = v;
     tune_save(ctx, key, v);
+    std::copy(ik, ik + 4, ctx->tkey);
+    ctx->tval = v;
     return HALIGN_OK;
 }
 
@@ -892,14 +1012,28 @@ int upload_matrix(halign_ctx *ctx, const halign_scoring *sc, hipStream_t st, Sco
 int validate_codes(halign_ctx *ctx, int alpha, const uint8_t *res, int64_t nres, const uint8_t *center, int m,
                    hipStream_t st) {
     RCHK(grow(ctx, ctx->counter, 256));
-    int *flag = (int *)ctx->counter.p + 8;
-    RCHK(launch_fill((uint32_t *)flag, 0u, 1, st));
-    if (nres > 0)
-        hipLaunchKernelGGL(hk::maxcode_kernel, dim3(grid_for((nres + 15) / 16, 256, 1024)), dim3(256), 0, st, res,
-                           nres, flag);
-    if (center && m > 0)
-        hipLaunchKernelGGL(hk::maxcode_kernel, dim3(1), dim3(256), 0, st, center, (int64_t)m, flag);
-    HCHK(hipGetLastError());
+    uint32_t *flag = (uint32_t *)ctx->counter.p + 8;
+    // the flag holds (call tag << 8 | largest code) and is raised with
+    // atomicMax: a larger tag per call replaces the last call's value without
+    // a clearing launch (cleared once when the 24-bit tag wraps).  A captured
+    // graph clears the flag itself and uses tag 0 on every replay.
+    uint32_t tag = 0;
+    if (ctx->capturing) {
+        RCHK(launch_fill(flag, 0u, 1, st));
+    } else {
+        if (++ctx->vtag >= (1u << 24)) {
+            RCHK(launch_fill(flag, 0u, 1, st));
+            ctx->vtag = 1;
+        }
+        tag = ctx->vtag;
+    }
+    ctx->check_tag = tag;
+    const int64_t n1 = nres > 0 ? nres : 0, n2 = (center && m > 0) ? m : 0;
+    if (n1 + n2 > 0) {
+        hipLaunchKernelGGL(hk::maxcode_kernel, dim3(grid_for((n1 + 15) / 16 + 1, 256, 1024)), dim3(256), 0, st, res, n1,
+                           center, n2, tag << 8, flag);
+        HCHK(hipGetLastError());
+    }
     HCHK(hipMemcpyAsync(ctx->flag_host, flag, 4, hipMemcpyDeviceToHost, st));
     ctx->flag_alpha = alpha;
     return HALIGN_OK;
@@ -908,7 +1042,8 @@ int validate_codes(halign_ctx *ctx, int alpha, const uint8_t *res, int64_t nres,
 // Call after the stream has synchronised past validate_codes().
 int validate_check(halign_ctx *ctx) {
     if (!ctx->flag_alpha) return HALIGN_OK;
-    const int h = *ctx->flag_host, alpha = ctx->flag_alpha;
+    const uint32_t v = (uint32_t)*ctx->flag_host;
+    const int h = (v >> 8) == ctx->check_tag ? (int)(v & 0xffu) : 0, alpha = ctx->flag_alpha;
     ctx->flag_alpha = 0;
     if (h >= alpha) return fail(HALIGN_E_INVALID, "residue code %d >= alphabet %d", h, alpha);
     return HALIGN_OK;
@@ -960,6 +1095,7 @@ int halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out) 
     }
     if (const char *e = getenv("HALIGN_AUTOTUNE")) ctx->autotune = atoi(e) != 0;
     if (const char *e = getenv("HALIGN_PROGRESS")) ctx->progress = atoi(e) != 0;
+    if (const char *e = getenv("HALIGN_HOST_TIMING")) ctx->host_timing = atoi(e) != 0;
     if (const char *e = getenv("HALIGN_TUNE_CACHE")) ctx->tune_file = e;
     tune_load(ctx);
     hipDeviceProp_t prop;
@@ -1028,6 +1164,13 @@ int halign_ctx_set_graph(halign_ctx *ctx, int enable) {
 int halign_ctx_graph_launches(const halign_ctx *ctx, int64_t *n_host) {
     if (!ctx || !n_host) return fail(HALIGN_E_INVALID, "NULL argument");
     *n_host = ctx->graph_launches;
+    return HALIGN_OK;
+}
+
+int halign_ctx_set_prejudge(halign_ctx *ctx, int candidates, int partners) {
+    if (!ctx || candidates < 0 || candidates > 256 || partners < 0) return fail(HALIGN_E_INVALID, "bad arguments");
+    ctx->prejudge_cand = candidates;
+    ctx->prejudge_part = partners;
     return HALIGN_OK;
 }
 
@@ -1108,27 +1251,38 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
     const bool endc = tb || cells != nullptr;
     RCHK(grow(ctx, ctx->pairbuf, (size_t)N * 8 + 256));
     int32_t *endcell = (int32_t *)ctx->pairbuf.p;
+    hmark(ctx, "upload");
     Tune tune;
     const bool want_tune = ctx->autotune && (flags & (3u << 4)) == HALIGN_ROUTE_AUTO;
     if (want_tune) {
         BatchOut tout{score, cells, endcell, ins, aligned};
-        RCHK(autotune(ctx, S, center, m, seqs, tb, endc, tout, st, &tune));
-        RCHK(stage_begin(ctx));   // the tuner's runs have synchronised
+        bool ran = false;
+        RCHK(autotune(ctx, S, center, m, seqs, tb, endc, tout, st, &tune, &ran));
+        if (ran) RCHK(stage_begin(ctx));   // the tuner's runs have synchronised
     }
     for (auto &v : ctx->last_stats) v = 0;
+    hmark(ctx, "tune");
     // the code check and the zeroing of the outputs go in before the host
     // plans the batch, so these small kernels run while the host works (the
     // forward kernels read codes masked to 5 bits, the check is read after the
     // batch, and the outputs are first written by the walk)
     auto prep = [&]() -> int {
-        RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], center, m, st));
         if (tb) {
-            hipLaunchKernelGGL(hk::fill_u16_kernel, dim3(grid_for((int64_t)N * (m + 1), 256, 4096)), dim3(256), 0,
-                               st, ins, (uint16_t)0, (int64_t)N * (m + 1));
+            // ins (as 32-bit words; an odd trailing uint16 on its own), aligned
+            // and G zeroed in one launch
+            hk::ZeroArgs z{};
+            const int64_t nins = (int64_t)N * (m + 1);
+            z.p[0] = reinterpret_cast<uint32_t *>(ins);
+            z.n[0] = nins / 2;
+            z.p[1] = aligned;
+            z.n[1] = (int64_t)N * ((m + 31) / 32);
+            z.p[2] = reinterpret_cast<uint32_t *>(G);
+            z.n[2] = G ? (int64_t)m + 1 : 0;
+            z.tail16 = (nins & 1) ? ins + (nins - 1) : nullptr;
+            hipLaunchKernelGGL(hk::zero_kernel, dim3(grid_for(z.n[0] + z.n[1], 256, 4096)), dim3(256), 0, st, z);
             HCHK(hipGetLastError());
-            RCHK(launch_fill(aligned, 0u, (int64_t)N * ((m + 31) / 32), st));
-            if (G) RCHK(launch_fill((uint32_t *)G, 0u, (int64_t)m + 1, st));
         }
+        RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], center, m, st));
         return HALIGN_OK;
     };
     BatchOut out{score, cells, endcell, ins, aligned};
@@ -1137,22 +1291,29 @@ static int sw_batch_body(halign_ctx *ctx, const halign_scoring *sc, const uint8_
         out.gskip = gskip;
     }
     RCHK(prep());
+    hmark(ctx, "prep");
     // Routing by pair length: when the batch as a whole runs one pair per lane
     // (the route the caller did not force), pairs longer than kLongPair
     // residues run on the wavefront kernel, one pair per stream, in a launch
     // of their own; the rest keep the strip kernel.  Both write the same
     // outputs, each at its own pair ids.
     const int route = tune.route >= 0 ? tune.route : route_of(flags, m, N);
-    std::vector<int32_t> pids, longp;
-    pids.reserve(N);
     const int64_t *oh = seqs->offsets_host;
     const bool split = route == kRouteInter && (flags & (3u << 4)) == HALIGN_ROUTE_AUTO;
-    for (int k = 0; k < N; ++k) {
-        if (split && oh[k + 1] - oh[k] > kLongPair) longp.push_back(k);
-        else pids.push_back(k);
+    int nlong = 0;
+    if (split)
+        for (int k = 0; k < N; ++k) nlong += oh[k + 1] - oh[k] > kLongPair;
+    if (nlong == 0) {
+        RCHK(run_batch(ctx, S, center, m, seqs, nullptr, N, tb, endc, route, out, st, tune));
+    } else {
+        // long pairs first in the id list, then the rest
+        std::vector<int32_t> &ids = ctx->h_split;
+        ids.resize(N);
+        int a = 0, b = nlong;
+        for (int k = 0; k < N; ++k) ids[oh[k + 1] - oh[k] > kLongPair ? a++ : b++] = k;
+        RCHK(run_batch(ctx, S, center, m, seqs, ids.data(), nlong, tb, endc, kRouteIntra, out, st));
+        RCHK(run_batch(ctx, S, center, m, seqs, ids.data() + nlong, N - nlong, tb, endc, route, out, st, tune));
     }
-    if (!longp.empty()) RCHK(run_batch(ctx, S, center, m, seqs, longp, tb, endc, kRouteIntra, out, st));
-    RCHK(run_batch(ctx, S, center, m, seqs, pids, tb, endc, route, out, st, tune));
     ctx->last_tune = {tune.route, tune.R, tune.smul, tune.LS > 0 ? tune.LS : 64, ctx->last_pk};
     if (!tb && cells) {
         // score-only with cells: report the end cell as (0, 0, i1, j1)
@@ -1215,6 +1376,7 @@ static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8
         RCHK(record(ctx, (*tv)[1], st));
         RCHK(record(ctx, (*tv)[2], st));
         ctx->flag_alpha = sc->alphabet;   // the graph copies the code check into flag_host
+        ctx->check_tag = 0;               // with tag 0
         ctx->graph_launches++;
         return HALIGN_OK;
     }
@@ -1224,6 +1386,7 @@ static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8
     // the copies of the run above must have read it first
     RCHK(stage_wait(ctx));
     const int pending = ctx->flag_alpha;
+    const uint32_t pending_tag = ctx->check_tag;
     graph_drop(ctx);
     if (!ctx->cap_stream) HCHK(hipStreamCreateWithFlags(&ctx->cap_stream, hipStreamNonBlocking));
     HCHK(hipStreamBeginCapture(ctx->cap_stream, hipStreamCaptureModeRelaxed));
@@ -1234,6 +1397,7 @@ static int sw_batch_async(halign_ctx *ctx, const halign_scoring *sc, const uint8
     hipGraph_t g = nullptr;
     const hipError_t ec = hipStreamEndCapture(ctx->cap_stream, &g);
     ctx->flag_alpha = pending;
+    ctx->check_tag = pending_tag;
     if (rc != HALIGN_OK) {
         if (g) (void)hipGraphDestroy(g);
         return rc;
@@ -1492,35 +1656,76 @@ int halign_center_exact(halign_ctx *ctx, const halign_scoring *sc, const halign_
     return HALIGN_OK;
 }
 
-int halign_center_judge(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, const int32_t *cand,
-                        int32_t ncand, int64_t *sums, int32_t *center_host, void *stream) {
-    if (!ctx || !sums || !cand || ncand <= 0) return fail(HALIGN_E_INVALID, "bad arguments");
-    RCHK(check_scoring(sc));
-    RCHK(check_seqs(seqs));
+}  // extern "C"
+
+// Sums of scores of candidates hc[q] against a partner list (NULL: every
+// sequence), center = the candidate with the largest sum, ties to the lower
+// sequence index.
+static int judge_impl(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+                      const std::vector<int32_t> &hc, const int32_t *partners_host, int32_t npart, int64_t *sums,
+                      int32_t *center_host, hipStream_t st) {
     const int N = seqs->n;
-    HCHK(hipSetDevice(ctx->device));
-    hipStream_t st = (hipStream_t)stream;
-    std::vector<int32_t> hc(ncand);
-    HCHK(hipMemcpyAsync(hc.data(), cand, 4 * (size_t)ncand, hipMemcpyDeviceToHost, st));
-    HCHK(hipStreamSynchronize(st));
+    const int ncand = (int)hc.size();
     for (int q = 0; q < ncand; ++q)
         if (hc[q] < 0 || hc[q] >= N) return fail(HALIGN_E_INVALID, "candidate %d out of range", hc[q]);
     Scoring S;
     RCHK(upload_matrix(ctx, sc, st, &S));
     RCHK(validate_now(ctx, sc->alphabet, seqs->residues, seqs->offsets_host[N], nullptr, 0, st));
     RCHK(launch_fill((uint32_t *)sums, 0u, 2 * (int64_t)ncand, st));
-    std::vector<int32_t> perm = length_perm(seqs), gcen, gb0, gslot;
+    std::vector<int32_t> perm, gcen, gb0, gslot;
+    if (partners_host) {   // partners in length order, as for all sequences
+        perm.assign(partners_host, partners_host + npart);
+        const int64_t *oh = seqs->offsets_host;
+        std::stable_sort(perm.begin(), perm.end(),
+                         [&](int32_t x, int32_t y) { return (oh[x + 1] - oh[x]) < (oh[y + 1] - oh[y]); });
+    } else {
+        perm = length_perm(seqs);
+    }
+    const int np = (int)perm.size();
     const bool p16 = strip16_ok(S, seqs);
     const int step = p16 ? 128 : 64;
     for (int q = 0; q < ncand; ++q)
-        for (int b = 0; b < N; b += step) {
+        for (int b = 0; b < np; b += step) {
             gcen.push_back(hc[q]);
             gb0.push_back(b);
             gslot.push_back(q);
         }
-    RCHK(run_groups(ctx, S, seqs, 2, (int64_t)gcen.size(), gcen, gb0, perm, gslot, sums, nullptr, st, -1, p16));
+    RCHK(run_groups(ctx, S, seqs, 2, (int64_t)gcen.size(), gcen, gb0, perm, gslot, sums, nullptr, st, np, p16));
     if (center_host) RCHK(argmax_sums(ctx, sums, hc.data(), ncand, center_host, st));
     return HALIGN_OK;
+}
+
+extern "C" {
+
+int halign_center_judge(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, const int32_t *cand,
+                        int32_t ncand, int64_t *sums, int32_t *center_host, void *stream) {
+    if (!ctx || !sums || !cand || ncand <= 0) return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_scoring(sc));
+    RCHK(check_seqs(seqs));
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> hc(ncand);
+    HCHK(hipMemcpyAsync(hc.data(), cand, 4 * (size_t)ncand, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    return judge_impl(ctx, sc, seqs, hc, nullptr, 0, sums, center_host, st);
+}
+
+int halign_center_judge_sample(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+                               const int32_t *cand, int32_t ncand, const int32_t *partners_host, int32_t npartners,
+                               int64_t *sums, int32_t *center_host, void *stream) {
+    if (!ctx || !sums || !cand || ncand <= 0 || npartners < 0 || (npartners > 0 && !partners_host))
+        return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_scoring(sc));
+    RCHK(check_seqs(seqs));
+    const int N = seqs->n;
+    for (int q = 0; q < npartners; ++q)
+        if (partners_host[q] < 0 || partners_host[q] >= N) return fail(HALIGN_E_INVALID, "partner out of range");
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    std::vector<int32_t> hc(ncand);
+    HCHK(hipMemcpyAsync(hc.data(), cand, 4 * (size_t)ncand, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    return judge_impl(ctx, sc, seqs, hc, partners_host, npartners, sums, center_host, st);
 }
 
 int halign_sw_pairs(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, const int32_t *anchors_host,
@@ -1692,8 +1897,11 @@ int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seq
                const halign_model *model, halign_alloc_fn alloc, void *user, uint8_t **msa, int64_t *width_host,
                int32_t *center_out_host, void *stream) {
     if (!ctx || !alloc || !msa || !width_host) return fail(HALIGN_E_INVALID, "bad arguments");
+    ctx->hmarks.clear();
+    hmark(ctx, "start");
     RCHK(check_scoring(sc));
     RCHK(check_seqs(seqs));
+    hmark(ctx, "checks");
     const int N = seqs->n;
     if (N <= 0) return fail(HALIGN_E_INVALID, "empty set");
     HCHK(hipSetDevice(ctx->device));
@@ -1735,11 +1943,16 @@ int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seq
     hipLaunchKernelGGL(hk::center_row_kernel, dim3(1), dim3(256), 0, st, ins, al, c, m, aw);
     HCHK(hipGetLastError());
     int64_t width = 0;
+    hmark(ctx, "batch");
     RCHK(merge_offsets(ctx, G, m + 1, col, &width, st));   // synchronises
+    hmark(ctx, "sync");
     RCHK(validate_check(ctx));
     uint8_t *out = (uint8_t *)alloc((size_t)N * (size_t)width, user);
     if (!out && width > 0) return fail(HALIGN_E_NOMEM, "allocator returned NULL for %lld bytes", (long long)(N * width));
+    hmark(ctx, "alloc");
     RCHK(halign_emit_rows(ctx, seqs, m, ins, al, G, col, width, out, stream));
+    hmark(ctx, "rows");
+    hmark_print(ctx);
     *msa = out;
     *width_host = width;
     if (center_out_host) *center_out_host = c;
@@ -1837,6 +2050,30 @@ int halign_pair_loss(halign_ctx *ctx, const float *E, const float *target, int32
         HCHK(hipGetLastError());
     }
     hipLaunchKernelGGL(hk::mean_kernel, dim3(1), dim3(256), 0, st, (const float *)sq, npairs, loss_out);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
+}
+
+int halign_pair_loss_grouped(halign_ctx *ctx, const float *E, const float *target, int32_t npairs, int32_t group,
+                             float lam, float *dE, float *loss_out, void *stream) {
+    if (group <= 0) return halign_pair_loss(ctx, E, target, npairs, dE, loss_out, stream);
+    if (!ctx || npairs < 0 || group > 64 || npairs % group != 0 ||
+        (npairs > 0 && (!E || !target || !dE || !loss_out)))
+        return fail(HALIGN_E_INVALID, "bad arguments (1 <= group <= 64 dividing npairs)");
+    hipStream_t st = (hipStream_t)stream;
+    const int G = npairs / group;
+    const size_t b_sq = ((size_t)npairs * 4 + 255) & ~size_t(255), b_g = ((size_t)G * 4 + 255) & ~size_t(255);
+    RCHK(grow(ctx, ctx->mlp[0], b_sq + b_g + (size_t)2 * npairs * hk::kEmb * 2 + 512));
+    float *sq = (float *)ctx->mlp[0].p;
+    float *gsq = (float *)((char *)ctx->mlp[0].p + b_sq);
+    uint16_t *dEb = (uint16_t *)((char *)ctx->mlp[0].p + b_sq + b_g);
+    if (G > 0) {
+        hipLaunchKernelGGL(hk::pair_group_loss_kernel, dim3(G), dim3(64), 0, st, E, target, npairs, group, lam, dE,
+                           dEb, sq, gsq);
+        HCHK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(hk::mean2_kernel, dim3(1), dim3(256), 0, st, (const float *)sq, npairs, (const float *)gsq, G,
+                       lam, loss_out);
     HCHK(hipGetLastError());
     return HALIGN_OK;
 }
@@ -1964,8 +2201,11 @@ int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halig
         do { b = (int32_t)(splitmix(rs) % (uint64_t)N); } while (b == anc[q / 64]);
         par[q] = b;
     }
+    // with a group weight, a batch holds whole anchors (all PA partners of
+    // each), and the loss adds the squared mean error of each anchor's pairs
+    const bool grouped = opts->group_weight > 0.f;
     // scratch layout in mlp[6]: scores, targets, batch index lists, X_all
-    const int B = std::min(opts->batch, P);
+    const int B = grouped ? std::max(1, std::min(opts->batch, P) / PA) * PA : std::min(opts->batch, P);
     const int steps_per_epoch = P / B;
     const int nsteps = steps_per_epoch * opts->epochs;
     size_t off = 0;
@@ -1992,8 +2232,15 @@ int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halig
     {
         std::vector<int32_t> order(P), hidx((size_t)nsteps * 2 * B), htix((size_t)nsteps * B);
         for (int q = 0; q < P; ++q) order[q] = q;
+        std::vector<int32_t> aord(A);
+        for (int q = 0; q < A; ++q) aord[q] = q;
         for (int e = 0; e < opts->epochs; ++e) {
-            for (int q = P - 1; q > 0; --q) std::swap(order[q], order[(int)(splitmix(rs) % (uint64_t)(q + 1))]);
+            if (grouped) {   // shuffled anchors, each with its partners in order
+                for (int q = A - 1; q > 0; --q) std::swap(aord[q], aord[(int)(splitmix(rs) % (uint64_t)(q + 1))]);
+                for (int q = 0; q < P; ++q) order[q] = aord[q / PA] * PA + q % PA;
+            } else {
+                for (int q = P - 1; q > 0; --q) std::swap(order[q], order[(int)(splitmix(rs) % (uint64_t)(q + 1))]);
+            }
             for (int s = 0; s < steps_per_epoch; ++s) {
                 const int step = e * steps_per_epoch + s;
                 for (int r = 0; r < B; ++r) {
@@ -2046,7 +2293,7 @@ int halign_train_proposer(halign_ctx *ctx, const halign_scoring *sc, const halig
         hipLaunchKernelGGL(hk::gather_f32_kernel, dim3((B + 255) / 256), dim3(256), 0, st, (const float *)tgt, tx, B, tb);
         HCHK(hipGetLastError());
         RCHK(halign_mlp_forward(ctx, &md, Xb, 2 * B, Z, Hb, E, stream));
-        RCHK(halign_pair_loss(ctx, E, tb, B, dE, loss + step, stream));
+        RCHK(halign_pair_loss_grouped(ctx, E, tb, B, grouped ? PA : 0, opts->group_weight, dE, loss + step, stream));
         RCHK(halign_mlp_backward(ctx, &md, Xb, 2 * B, Z, Hb, dE, gW1, gb1, gW2, gb2, stream));
         const float lr = opts->lr;
         RCHK(halign_adam_step(pr->W1, gW1, mW1, vW1, pr->W1b, nW1, lr, 0.9f, 0.999f, 1e-8f, step + 1, stream));
@@ -2114,7 +2361,33 @@ int halign_center_learned(halign_ctx *ctx, const halign_scoring *sc, const halig
         RCHK(halign_mlp_forward(ctx, model, X, nr, nullptr, Hb, E + (size_t)r0 * hk::kEmb, stream));
     }
     int32_t *top = (int32_t *)(w + o_top);
-    RCHK(halign_topk_center(ctx, E, N, kk, (float *)(w + o_u), top, stream));
+    const int kp = std::min(std::min(ctx->prejudge_cand, 256), N);
+    const int np = std::min(ctx->prejudge_part, N);
+    if (kp > kk && np > 0) {
+        // pre-judge: the top kp by u, scored against a common sample of np
+        // partners (evenly spaced indices); the kk best of that sample go on
+        RCHK(grow(ctx, ctx->mlp[8], 12 * (size_t)kp + 512));
+        int32_t *wide = (int32_t *)ctx->mlp[8].p;
+        int64_t *wsum = (int64_t *)((char *)ctx->mlp[8].p + ((4 * (size_t)kp + 255) & ~size_t(255)));
+        RCHK(halign_topk_center(ctx, E, N, kp, (float *)(w + o_u), wide, stream));
+        std::vector<int32_t> part(np), hw(kp), order(kp);
+        for (int q = 0; q < np; ++q) part[q] = (int32_t)((int64_t)q * N / np);
+        RCHK(halign_center_judge_sample(ctx, sc, seqs, wide, kp, part.data(), np, wsum, nullptr, stream));
+        std::vector<int64_t> hs(kp);
+        HCHK(hipMemcpyAsync(hw.data(), wide, 4 * (size_t)kp, hipMemcpyDeviceToHost, st));
+        HCHK(hipMemcpyAsync(hs.data(), wsum, 8 * (size_t)kp, hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+            return hs[x] > hs[y] || (hs[x] == hs[y] && hw[x] < hw[y]);
+        });
+        std::vector<int32_t> sel(kk);
+        for (int q = 0; q < kk; ++q) sel[q] = hw[order[q]];
+        HCHK(hipMemcpyAsync(top, sel.data(), 4 * (size_t)kk, hipMemcpyHostToDevice, st));
+        HCHK(hipStreamSynchronize(st));
+    } else {
+        RCHK(halign_topk_center(ctx, E, N, kk, (float *)(w + o_u), top, stream));
+    }
     int32_t c = -1;
     RCHK(halign_center_judge(ctx, sc, seqs, top, kk, (int64_t *)(w + o_sums), &c, stream));
     if (cand_host) {

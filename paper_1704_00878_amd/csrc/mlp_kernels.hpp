@@ -222,6 +222,63 @@ __global__ void __launch_bounds__(256) mean_kernel(const float *v, int n, float 
     }
 }
 
+// Pair loss with a per-group term: groups of K consecutive pairs (K <= 64,
+// one wavefront per group), loss = mean(diff^2) + lam * mean over groups of
+// (mean diff of the group)^2.  dpred = 2 diff / P + 2 lam gmean / (G K).
+__global__ void __launch_bounds__(64) pair_group_loss_kernel(const float *E, const float *target, int P, int K,
+                                                             float lam, float *dE, uint16_t *dEb, float *sq,
+                                                             float *gsq) {
+    const int g = blockIdx.x, l = threadIdx.x;
+    const int G = P / K;
+    const int r = g * K + l;
+    float diff = 0.f, pred = 0.f;
+    const float *a = E + (int64_t)r * kEmb, *b = E + (int64_t)(r + P) * kEmb;
+    if (l < K) {
+        for (int d = 0; d < kEmb; ++d) pred += a[d] * b[d];
+        diff = pred - target[r];
+        sq[r] = diff * diff;
+    }
+    float sum = diff;   // fixed-order tree over the wavefront
+    for (int sh = 32; sh > 0; sh >>= 1) sum += __shfl_xor(sum, sh);
+    const float gm = sum / (float)K;
+    if (l == 0) gsq[g] = gm * gm;
+    if (l >= K) return;
+    const float gsc = 2.f * diff / (float)P + 2.f * lam * gm / ((float)G * (float)K);
+    float *da = dE + (int64_t)r * kEmb, *db = dE + (int64_t)(r + P) * kEmb;
+    uint16_t *dab = dEb + (int64_t)r * kEmb, *dbb = dEb + (int64_t)(r + P) * kEmb;
+    for (int d = 0; d < kEmb; ++d) {
+        const float ga = gsc * b[d], gb = gsc * a[d];
+        da[d] = ga;
+        db[d] = gb;
+        dab[d] = f2bf(ga);
+        dbb[d] = f2bf(gb);
+    }
+}
+
+// out[0] = mean(v[0..n)) + lam * mean(w[0..m)), each sum in a fixed order.
+__global__ void __launch_bounds__(256) mean2_kernel(const float *v, int n, const float *w, int m, float lam,
+                                                    float *out) {
+    __shared__ float part[256];
+    float res = 0.f;
+    for (int which = 0; which < 2; ++which) {
+        const float *x = which ? w : v;
+        const int c = which ? m : n;
+        float s = 0.f;
+        const int per = (c + 255) / 256;
+        const int lo = min(c, (int)threadIdx.x * per), hi = min(c, lo + per);
+        for (int q = lo; q < hi; ++q) s += x[q];
+        part[threadIdx.x] = s;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float t = 0.f;
+            for (int q = 0; q < 256; ++q) t += part[q];
+            res += (which ? lam : 1.f) * (c > 0 ? t / (float)c : 0.f);
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) out[0] = res;
+}
+
 // Adam with bias correction on fp32 masters; optional bf16 copy.
 __global__ void adam_kernel(float *p, const float *gr, float *m, float *v, uint16_t *pb, int64_t n, float lr,
                             float b1, float b2, float eps, float c1, float c2) {

@@ -40,33 +40,57 @@ __global__ void endcell_to_cells_kernel(const int32_t *endcell, int n, int32_t *
     reinterpret_cast<int4 *>(cells)[k] = make_int4(0, 0, endcell[2 * k], endcell[2 * k + 1]);
 }
 
-// Largest residue code in [p, p + n) -> *out (atomicMax; *out zeroed before).
-// 16-byte loads where aligned, one atomic per workgroup.
-__global__ void __launch_bounds__(256) maxcode_kernel(const uint8_t *p, int64_t n, int *out) {
-    __shared__ int red[4];
+// Largest code in [p, p + n) and [q, q + nq), raised into *out as
+// (tag | code) with atomicMax (one atomic per workgroup).  16-byte loads where
+// aligned.
+__device__ __forceinline__ int maxcode_range(const uint8_t *p, int64_t n, int64_t tid, int64_t stride) {
     int mx = 0;
     const int64_t head = min<int64_t>(n, (int64_t)((16 - ((uintptr_t)p & 15)) & 15));
-    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     for (int64_t x = tid; x < head; x += stride) mx = max(mx, (int)p[x]);
     const int64_t nv = (n - head) >> 4;
     const uint4 *pv = reinterpret_cast<const uint4 *>(p + head);
     for (int64_t x = tid; x < nv; x += stride) {
-        const uint4 q = pv[x];
-        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+        const uint4 v = pv[x];
+        const uint32_t w[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
         for (int y = 0; y < 4; ++y)
             mx = max(mx, max(max((int)(w[y] & 255), (int)((w[y] >> 8) & 255)),
                              max((int)((w[y] >> 16) & 255), (int)(w[y] >> 24))));
     }
     for (int64_t x = head + (nv << 4) + tid; x < n; x += stride) mx = max(mx, (int)p[x]);
+    return mx;
+}
+
+__global__ void __launch_bounds__(256) maxcode_kernel(const uint8_t *p, int64_t n, const uint8_t *q, int64_t nq,
+                                                      uint32_t tag, uint32_t *out) {
+    __shared__ int red[4];
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int mx = n > 0 ? maxcode_range(p, n, tid, stride) : 0;
+    if (nq > 0) mx = max(mx, maxcode_range(q, nq, tid, stride));
     for (int sh = 32; sh > 0; sh >>= 1) mx = max(mx, __shfl_xor(mx, sh));
     if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
     __syncthreads();
     if (threadIdx.x == 0) {
         const int b = max(max(red[0], red[1]), max(red[2], red[3]));
-        if (b > 0) atomicMax(out, b);
+        atomicMax(out, tag | (uint32_t)b);
     }
+}
+
+// Zero up to three word ranges (and one trailing uint16) in one launch.
+struct ZeroArgs {
+    uint32_t *p[3];
+    int64_t n[3];
+    uint16_t *tail16;
+};
+
+__global__ void zero_kernel(ZeroArgs z) {
+    const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+#pragma unroll
+    for (int r = 0; r < 3; ++r)
+        for (int64_t x = tid; x < z.n[r]; x += stride) z.p[r][x] = 0u;
+    if (tid == 0 && z.tail16) *z.tail16 = 0;
 }
 
 // ASCII -> residue code through a 256-entry table.

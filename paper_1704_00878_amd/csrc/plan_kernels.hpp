@@ -21,11 +21,14 @@ __global__ void decode_keys_kernel(const unsigned long long *keys, const int32_t
 }
 
 // Stage the residues of every stream: sres[sbase + c0(q) + x] = s_q[x], with
-// kFirstCol on x = 0.  One workgroup per pair slot.
+// kFirstCol on x = 0, and clear the slot's end-cell key.  One workgroup per
+// pair slot.
 __global__ void stage_stream_kernel(const uint8_t *res, const int64_t *off, const int32_t *slot_pid,
-                                    const int64_t *slot_col, int nslots, int clamp, uint8_t *sres) {
+                                    const int64_t *slot_col, int nslots, int clamp, uint8_t *sres,
+                                    unsigned long long *keys) {
     const int q = blockIdx.x;
     if (q >= nslots) return;
+    if (threadIdx.x == 0) keys[q] = 0ull;
     const int pid = slot_pid[q];
     const int64_t so = off[pid];
     const int n = (int)(off[pid + 1] - so);

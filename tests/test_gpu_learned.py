@@ -92,8 +92,12 @@ def test_forward(H, ctx, nrows):
 
 
 @pytest.mark.parametrize("npairs", [32, 37, 100])
-def test_loss_and_backward(H, ctx, npairs):
+@pytest.mark.parametrize("grouped", [False, True])
+def test_loss_and_backward(H, ctx, npairs, grouped):
+    """Pair loss (and the per-group term, groups of 16, 37 or 25 pairs) and the
+    backward against the oracle."""
     import torch
+    group = {32: 16, 37: 37, 100: 25}[npairs] if grouped else 0
     nrows = 2 * npairs
     seqs, X, prop = _setup(H, nrows, seed=3)
     Z = torch.empty((nrows, H.HID), dtype=torch.float32, device="cuda")
@@ -104,7 +108,10 @@ def test_loss_and_backward(H, ctx, npairs):
     tgt = torch.from_numpy(rng.normal(size=npairs).astype(np.float32)).cuda()
     dE = torch.empty_like(E)
     loss = torch.empty(1, dtype=torch.float32, device="cuda")
-    H.halign_pair_loss(ctx, E, tgt, npairs, dE, loss)
+    if group:
+        H.halign_pair_loss_grouped(ctx, E, tgt, npairs, group, 0.5, dE, loss)
+    else:
+        H.halign_pair_loss(ctx, E, tgt, npairs, dE, loss)
     dW1 = torch.empty((H.FEAT, H.HID), dtype=torch.float32, device="cuda")
     db1 = torch.empty(H.HID, dtype=torch.float32, device="cuda")
     dW2 = torch.empty((H.HID, H.EMB), dtype=torch.float32, device="cuda")
@@ -112,7 +119,7 @@ def test_loss_and_backward(H, ctx, npairs):
     H.halign_mlp_backward(ctx, prop, X, nrows, Z, Hb, dE, dW1, db1, dW2, db2)
     torch.cuda.synchronize()
     Ef = E.cpu().numpy().astype(np.float64)
-    L, dE_ref = mlp.pair_loss(Ef, tgt.cpu().numpy().astype(np.float64))
+    L, dE_ref = mlp.pair_loss(Ef, tgt.cpu().numpy().astype(np.float64), group=group, lam=0.5)
     assert abs(loss.item() - L) <= 1e-4 * max(1.0, abs(L))
     close(dE.cpu().numpy(), dE_ref)
     Xf = bits_to_f(X)

@@ -229,6 +229,24 @@ def test_center_judge(H, ctx, strip):
     assert (d.cpu().numpy() == js).all()
 
 
+def test_center_judge_sample(H, ctx, strip):
+    """Sums over a common partner sample (a candidate against itself scores 0),
+    against the oracle's pairwise scores."""
+    import torch
+    seqs = synth.generate("plain64", n_seqs=40, seed=14)
+    cand = [5, 0, 17, 39]
+    partners = [3, 5, 9, 17, 30, 39, 0, 22]
+    ds = H.DeviceSeqs(seqs)
+    ct = torch.tensor(cand, dtype=torch.int32, device="cuda")
+    d = torch.empty(len(cand), dtype=torch.int64, device="cuda")
+    c = H.halign_center_judge_sample(ctx, H.Scoring(), ds, ct, np.array(partners), d)
+    want = [sum(0 if p == a else oracle.sw_score(synth.BLOSUM62, 11, 1, seqs.seq(a), seqs.seq(p)) for p in partners)
+            for a in cand]
+    assert list(d.cpu().numpy()) == want
+    best = max(range(len(cand)), key=lambda q: (want[q], -cand[q]))
+    assert c == cand[best]
+
+
 def test_sw_pairs(H, ctx):
     import torch
     seqs = synth.generate("plain64", n_seqs=50, seed=6)

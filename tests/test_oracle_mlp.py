@@ -45,6 +45,34 @@ def _loss(X, W1, b1, W2, b2, t):
     return mlp.pair_loss(E, t)[0]
 
 
+def test_grouped_loss_matches_central_differences():
+    """The per-group mean-error term: dL/dE against FP64 central differences
+    of the loss itself, and a hand case (two groups of two pairs)."""
+    rng = np.random.default_rng(4)
+    P, G, Em = 12, 3, 5
+    E = rng.normal(size=(2 * P, Em))
+    t = rng.normal(size=P)
+    lam = 0.7
+    L, dE = mlp.pair_loss(E, t, group=G, lam=lam)
+    eps = 1e-6
+    num = np.zeros_like(E)
+    for idx in np.ndindex(E.shape):
+        old = E[idx]
+        E[idx] = old + eps
+        lp = mlp.pair_loss(E, t, group=G, lam=lam)[0]
+        E[idx] = old - eps
+        lm = mlp.pair_loss(E, t, group=G, lam=lam)[0]
+        E[idx] = old
+        num[idx] = (lp - lm) / (2 * eps)
+    assert np.abs(num - dE).max() <= 1e-6 * max(1.0, np.abs(num).max())
+    # hand case: predictions 1, 2, 3, 4 (e_a = [p], e_b = [1]) against 0:
+    # MSE = 30 / 4; group means 1.5 and 3.5, their mean square (2.25 + 12.25) / 2
+    E2 = np.array([[1.0], [2.0], [3.0], [4.0], [1.0], [1.0], [1.0], [1.0]])
+    L2, _ = mlp.pair_loss(E2, np.zeros(4), group=2, lam=2.0)
+    assert abs(L2 - (7.5 + 2.0 * 7.25)) < 1e-12
+    assert mlp.pair_loss(E2, np.zeros(4))[0] == 7.5
+
+
 def test_backward_matches_central_differences():
     rng = np.random.default_rng(0)
     X, W1, b1, W2, b2, t = _tiny(rng)
