@@ -826,19 +826,25 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             w.aw = aw;
             w.G = out.G;
             w.gskip = out.gskip;
-            const dim3 wg(grid_for(cn, 64, 1 << 30));
+            // cached chunk shape: about as many rows (NB blocks of R rows) as
+            // columns (NG chunk columns of 8 or 4), NB * NG = 16
+            const int wR = route == kRouteIntra ? R : 16;
+            w.rmagic = wR >= 2 ? (uint32_t)((((uint64_t)1 << 32) + wR - 1) / wR) : 0u;
+            w.lg_nb = route == kRouteIntra ? (wR >= 4 ? 2 : (wR >= 2 ? 3 : 4)) : 1;
+            const dim3 wg(grid_for(cn, hk::kWalkPairs, 1 << 30));
             const bool cl = m <= hk::kWalkCenterLds;
+            const size_t wlds = hk::walk_lds_bytes(route == kRouteIntra ? WQ : 1, m, cl);
             if (route == kRouteIntra) {
                 if (pk) {
-                    if (cl) hipLaunchKernelGGL((hk::walk_kernel<false, true, true>), wg, dim3(64), 0, st, w);
-                    else hipLaunchKernelGGL((hk::walk_kernel<false, false, true>), wg, dim3(64), 0, st, w);
+                    if (cl) hipLaunchKernelGGL((hk::walk_kernel<false, true, true>), wg, dim3(256), wlds, st, w);
+                    else hipLaunchKernelGGL((hk::walk_kernel<false, false, true>), wg, dim3(256), wlds, st, w);
                 } else {
-                    if (cl) hipLaunchKernelGGL((hk::walk_kernel<false, true, false>), wg, dim3(64), 0, st, w);
-                    else hipLaunchKernelGGL((hk::walk_kernel<false, false, false>), wg, dim3(64), 0, st, w);
+                    if (cl) hipLaunchKernelGGL((hk::walk_kernel<false, true, false>), wg, dim3(256), wlds, st, w);
+                    else hipLaunchKernelGGL((hk::walk_kernel<false, false, false>), wg, dim3(256), wlds, st, w);
                 }
             } else {
-                if (cl) hipLaunchKernelGGL((hk::walk_kernel<true, true, false>), wg, dim3(64), 0, st, w);
-                else hipLaunchKernelGGL((hk::walk_kernel<true, false, false>), wg, dim3(64), 0, st, w);
+                if (cl) hipLaunchKernelGGL((hk::walk_kernel<true, true, false>), wg, dim3(256), wlds, st, w);
+                else hipLaunchKernelGGL((hk::walk_kernel<true, false, false>), wg, dim3(256), wlds, st, w);
             }
             HCHK(hipGetLastError());
         }

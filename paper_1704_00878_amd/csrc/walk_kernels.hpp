@@ -1,5 +1,5 @@
-// Traceback walk for gfx950: one lane per pair over the 4-bit codes written
-// by the wavefront kernel (sw_kernels.hpp) or the strip kernel
+// Traceback walk for gfx950: one 16-lane DPP row per pair over the 4-bit codes
+// written by the wavefront kernel (sw_kernels.hpp) or the strip kernel
 // (strip_kernels.hpp), emitting the center-star vector of each pair.
 #pragma once
 #include "sw_kernels.hpp"
@@ -7,16 +7,28 @@
 namespace hk {
 
 // ---------------------------------------------------------------------------
-// Traceback walk: one lane per pair.  From the end cell, in state H: stop when
-// the running value is 0, else take the diagonal if notd is clear, else the
-// horizontal gap if note is clear, else the vertical gap; in a gap state,
-// extend while the ext bit is set (open wins ties).  The running value is
-// H (or the gap value) of the current cell, kept exactly from the score.
-// Emits the center-star vector: ins[k][0..m], aligned bits, cells.
+// Traceback walk.  From the end cell, in state H: stop when the running value
+// is 0, else take the diagonal if notd is clear, else the horizontal gap if
+// note is clear, else the vertical gap; in a gap state, extend while the ext
+// bit is set (open wins ties).  The running value is H (or the gap value) of
+// the current cell, kept exactly from the score.  Emits the center-star
+// vector: ins[k][0..m], aligned bits, cells.
 //
-// Code words arrive in 32-byte chunks (8 steps of one lane of the wavefront
-// layout, or 4 columns of one lane of the strip layout) held in a two-entry
-// per-lane LDS cache, so a diagonal run costs one line fetch per chunk.
+// A path is a chain of runs: diagonal runs in H, horizontal runs in E and
+// vertical runs in F.  Sixteen lanes (one DPP row) serve one pair: lane k
+// looks at the k-th cell ahead along the current run, so one iteration
+// decides up to sixteen moves.  The first lane whose cell ends the run (a
+// stop, a gap, the end of a gap, missing data) is found with a ballot; the
+// score change over the diagonal cells before it is a row prefix sum.
+//
+// Code words arrive in chunks: 8 steps of one lane of the wavefront layout
+// (R rows x 8 columns) or 4 columns of one lane of the strip layout (16 rows
+// x 4 columns).  Each pair caches 16 chunks in LDS, direct mapped by (block
+// mod NB, chunk column mod NG), NB * NG = 16.  On a miss the pair's lanes load,
+// one chunk each, the NB blocks at and above the current one times the NG
+// chunk columns at and left of where the path (diagonal, or straight up in a
+// vertical gap) meets each block, with a 64-byte window of the sequence, in
+// one round trip.
 // ---------------------------------------------------------------------------
 struct WalkArgs {
     const int8_t *mat;
@@ -36,6 +48,7 @@ struct WalkArgs {
     const int32_t *ccol;      // strip, per walk entry: lane in the group
     const int32_t *cstride;   // strip, per walk entry: nmax of the group
     int R;                    // wavefront rows per lane
+    uint32_t rmagic;          // ceil(2^32 / R) for R >= 2: row / R = umulhi(row, rmagic) for rows < 2^16
     int kind;
     int32_t *cells;           // [N][4]
     uint16_t *ins;            // [N][m+1] (zeroed)
@@ -56,53 +69,77 @@ struct WalkArgs {
     int nstreams;
     int lg_ls;                // log2 of the lanes per stream (wavefront layout)
     int W;                    // code words per step (wavefront layout)
+    int lg_nb;                // log2 of NB, the cached blocks per pair (NG = 16 / NB)
 };
 
 constexpr int kWalkCenterLds = 8192;   // centers up to this length are staged in LDS
+constexpr int kWalkPairs = 16;         // pairs per 256-thread workgroup (16 lanes each)
+constexpr int kWalkSlots = 16;         // cached code chunks per pair
 
-// One lane per pair.  Each lane keeps four 32-byte code chunks and a 64-byte
-// window of its sequence in LDS: on a miss it loads the chunk it needs, the
-// one to its left and the two that a diagonal path meets in the block above
-// (and refreshes the sequence window), in one round trip.  Lanes advance
-// through their cached data until each misses or ends, so that one memory
-// round trip serves the misses of every lane of the wavefront.
+// LDS bytes of one workgroup: substitution table, sequence windows, chunk
+// tags, chunk cache (8 * W words per chunk), and the center if staged
+__host__ __device__ inline size_t walk_lds_bytes(int W, int m, bool cen_lds) {
+    return 1024 + kWalkPairs * 64 + kWalkPairs * kWalkSlots * 8 +
+           (size_t)kWalkPairs * kWalkSlots * 8 * W * 4 + (cen_lds ? (size_t)((m + 15) & ~15) : 0);
+}
+
+// inclusive prefix sum over the 16 lanes of a DPP row
+__device__ inline int row_prefix16(int x) {
+    x += __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, false);   // row_shr:1
+    x += __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, false);   // row_shr:2
+    x += __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, false);   // row_shr:4
+    x += __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, false);   // row_shr:8
+    return x;
+}
+
+// Reasons a run ends at a cell (the first that holds): the walk stops there,
+// the codes are bad, the cell's chunk is not cached, the sequence window does
+// not hold its residue (diagonal moves only), the move out of the cell is not
+// the run's own (a gap from H), the gap ends (E or F).
+enum : int { kRunFin = 1, kRunBad = 2, kRunMiss = 3, kRunSmiss = 4, kRunTurn = 5, kRunEnd = 6 };
+
 template <bool STRIP, bool CEN_LDS, bool PK>
-__global__ void __launch_bounds__(64)
+__global__ void __launch_bounds__(256)
 walk_kernel(WalkArgs a) {
-    constexpr int CW = PK ? 32 : 16;   // words per cached chunk (8 steps x W, W <= 4 packed, <= 2 otherwise)
-    constexpr int HQ = CW / 4;
-    __shared__ uint32_t cache[4][CW][64];
-    __shared__ uint32_t swin[16][64];
-    __shared__ int8_t smat[32 * 32];
-    __shared__ uint8_t scen[kWalkCenterLds];
-    const int lane = threadIdx.x;
+    extern __shared__ uint32_t wlds[];
+    const int W = STRIP ? 1 : a.W;
+    const int cws = 8 * W;                 // words per cached chunk
+    int8_t *smat = reinterpret_cast<int8_t *>(wlds);
+    uint32_t *swin_all = wlds + 256;                                    // [pairs][16] words
+    int2 *ctag_all = reinterpret_cast<int2 *>(wlds + 256 + kWalkPairs * 16);   // [pairs][slots]
+    uint32_t *cache_all = wlds + 256 + kWalkPairs * 16 + kWalkPairs * kWalkSlots * 2;
+    uint8_t *scen = reinterpret_cast<uint8_t *>(cache_all + kWalkPairs * kWalkSlots * cws);
     const int m = a.m;
-    constexpr bool cen_lds = CEN_LDS;
-    for (int x = lane; x < 1024; x += 64) {
+    for (int x = threadIdx.x; x < 1024; x += 256) {
         const int r = x >> 5, q = x & 31;
         smat[x] = (r < a.alpha && q < a.alpha) ? a.mat[r * a.alpha + q] : (int8_t)0;
     }
-    if (cen_lds)
-        for (int x = lane; x < m; x += 64) scen[x] = a.center[x] & 31;
+    if (CEN_LDS)
+        for (int x = threadIdx.x; x < m; x += 256) scen[x] = a.center[x] & 31;
+    ctag_all[threadIdx.x] = make_int2(-1, -1);   // 256 = pairs x slots
     __syncthreads();
-    const int w = blockIdx.x * 64 + lane;
+    const int gp = threadIdx.x >> 4;       // pair of the workgroup
+    const int k = threadIdx.x & 15;        // lane of the pair's row
+    const int gbase = threadIdx.x & 48;    // the row's first lane in the wavefront
+    const int w = blockIdx.x * kWalkPairs + gp;
     if (w >= a.npairs) return;
+    uint32_t *win = swin_all + gp * 16;
+    int2 *ctag = ctag_all + gp * kWalkSlots;
+    uint32_t *ccache = cache_all + gp * kWalkSlots * cws;
     const int pid = STRIP ? a.pids[w] : a.slot_pid[w];
     const int64_t so = a.off[pid];
     const int n = (int)(a.off[pid + 1] - so);
-    // window of residue bytes [swb, swb + 64) of the residue array, read as
-    // four aligned 16-byte chunks that each hold a byte at or below the
-    // position in use (so no read leaves the array's last page)
-    int64_t swb = -1024;
     uint16_t *ins = a.ins + (int64_t)pid * (m + 1);
     uint32_t *al = a.aligned + (int64_t)pid * a.aw;
     int v = a.score[pid];
     int4 *cp = reinterpret_cast<int4 *>(a.cells) + pid;
     int32_t *gmax = (a.G && pid != a.gskip) ? a.G : nullptr;
     if (v <= 0) {
-        ins[0] = (uint16_t)n;
-        if (gmax && n > 0) atomicMax(gmax, n);
-        *cp = make_int4(0, 0, 0, 0);
+        if (k == 0) {
+            ins[0] = (uint16_t)n;
+            if (gmax && n > 0) atomicMax(gmax, n);
+            *cp = make_int4(0, 0, 0, 0);
+        }
         return;
     }
     const int i1 = a.endcell[2 * pid], j1 = a.endcell[2 * pid + 1];
@@ -127,209 +164,200 @@ walk_kernel(WalkArgs a) {
     }
     constexpr bool strip = STRIP;
     const int R = strip ? 16 : a.R;
-    const int G = strip ? (stride + 3) >> 2 : (stride + 7) >> 3;   // groups per pass / strip
-    // wavefront layout: LS lanes per stream, W words (8 steps x W words per chunk)
+    const uint32_t rmagic = a.rmagic;
+    const int G = strip ? (stride + 3) >> 2 : (stride + 7) >> 3;   // chunk columns per block row
     const int lg = strip ? 6 : a.lg_ls, LSm = (1 << lg) - 1;
-    const int W = strip ? 1 : a.W;
     const int n0 = min(R, 8);           // rows in the first word of a step
-    int i = i1, j = j1;
-    // row decomposition of i-1: block (pass*LS + lane, or strip) and row t in block
-    int blk = 0, t = 0;
-    {
-        const int row = i - 1;
-        if (strip) { blk = row >> 4; t = row & 15; }
+    const int lgnb = a.lg_nb, lgng = 4 - lgnb, nbm = (1 << lgnb) - 1, ngm = (1 << lgng) - 1;
+    // row -> (block, row in block); block = pass * LS + lane (wavefront) or strip
+    auto split_row = [&](int row, int &b, int &t) __attribute__((always_inline)) {
+        if (strip) { b = row >> 4; t = row & 15; }
         else {
-            const int span = R << lg, ps = row / span, rr = row - ps * span;
-            blk = (ps << lg) + rr / R;
-            t = rr % R;
+            b = R == 1 ? row : (int)__umulhi((uint32_t)row, rmagic);
+            t = row - b * R;
         }
-    }
-    // chunk (block b, group g): group of 4 columns (strip) or 8 wavefront steps
-    auto grp_of = [&](int b, int jj) __attribute__((always_inline)) -> int {
-        return strip ? (jj - 1) >> 2 : (ccol + jj - 1 + (b & LSm)) >> 3;
+    };
+    // chunk column of (block b, column col)
+    auto grp_of = [&](int b, int col) __attribute__((always_inline)) -> int {
+        return strip ? col >> 2 : (ccol + col + (b & LSm)) >> 3;
     };
     auto chunk_addr = [&](int b, int g) __attribute__((always_inline)) -> int64_t {
         return strip ? base + (((int64_t)b * G + g) * 64 + ccol) * 8
                      : base + ((((int64_t)(b >> lg) * G + g) << lg) + (b & LSm)) * 8 * W;
     };
-    int tb0 = -1, tg0 = -1, tb1 = -1, tg1 = -1, tb2 = -1, tg2 = -1, tb3 = -1, tg3 = -1;
+    int i = i1, j = j1;
     int state = 0;              // 0 = H, 1 = E, 2 = F
-    int run = 0;                // pending insertions at row i
+    int run = 0;                // horizontal moves of the open insertion run
     int insrow = -1, inssum = 0;
     int curw = -1;              // aligned word being accumulated
     uint32_t bits = 0;
-    // stores found inside the stepping loop wait in one pending slot each and
-    // are issued between rounds, so the loop itself touches only LDS
-    int pw = -1, pir = -1, piv = 0;
-    uint32_t pb = 0;
+    int64_t swb = 0;
+    int qoff = -(1 << 30);      // so - swb once a window is loaded
     bool bad = (i1 < 1 || i1 > m || j1 < 1 || j1 > n);
     bool fin = false;
-    int guard = 0;
     // a path has at most m + n steps; the guard keeps a corrupted code
     // stream from reading outside the matrix or looping
-    while (!bad && !fin) {
-        bool smiss = false;
-        bool cmiss = false;
-        while (true) {
-            // everything about the current cell, then one exit test
-            const int grp = grp_of(blk, j);
-            const bool h0 = tb0 == blk && tg0 == grp, h1 = tb1 == blk && tg1 == grp;
-            const bool h2 = tb2 == blk && tg2 == grp, h3 = tb3 == blk && tg3 == grp;
-            const int sl = h0 ? 0 : (h1 ? 1 : (h2 ? 2 : 3));
+    int guard = 0;
+    const int glim = m + n + 2;
+    for (;;) {
+        if (__ballot(!bad && !fin) == 0) break;
+        // why the pair left the iteration loop: 0 still in it, else a kRun*
+        // reason; 7 done before the round
+        int why = (bad || fin) ? 7 : 0;
+        for (;;) {
+            // ---- the cell of lane k: k moves ahead along the current run
+            const int ci = i - (state != 1 ? k : 0), cj = j - (state != 2 ? k : 0);
+            const int row = max(ci - 1, 0), col = max(cj - 1, 0);
+            int b, t;
+            split_row(row, b, t);
+            const int g = grp_of(b, col);
+            const int slot = (g & ngm) | ((b & nbm) << lgng);
             int wi, sh;
-            if (strip) { wi = ((j - 1) & 3) * 2 + (t >> 3); sh = 4 * (7 - (t & 7)); }
+            if (strip) { wi = (col & 3) * 2 + (t >> 3); sh = 4 * (7 - (t & 7)); }
             else {
-                if (PK) {
-                    wi = ((ccol + j - 1 + (blk & LSm)) & 7) * W + (t >> 2);
-                    sh = 8 * half + 2 * (t & 3);
-                } else {
-                    wi = ((ccol + j - 1 + (blk & LSm)) & 7) * W + (t >> 3);
-                    sh = t < 8 ? 4 * (n0 - 1 - t) : 4 * (R - 1 - t);
-                }
+                const int st8 = (ccol + col + (b & LSm)) & 7;
+                if (PK) { wi = st8 * W + (t >> 2); sh = 8 * half + 2 * (t & 3); }
+                else { wi = st8 * W + (t >> 3); sh = t < 8 ? 4 * (n0 - 1 - t) : 4 * (R - 1 - t); }
             }
-            const uint32_t cword = cache[sl][wi & (CW - 1)][lane];
+            const uint32_t cword = ccache[slot * cws + wi];
+            const int2 tg = ctag[slot];
+            const int gq = qoff + col;
+            const int gqc = min(max(gq, 0), 63);
+            const int ic = min(row, m - 1);
+            const int cr = CEN_LDS ? (int)scen[ic] : (int)(a.center[ic] & 31);
+            const int sr = (int)((win[gqc >> 2] >> (8 * (gqc & 3))) & 31u);
+            int sd = (int)smat[cr * 32 + sr];
+            // read for every lane and iteration: no branch guards the reads
+            asm volatile("" : "+v"(sd));
             // notd, note, eext, fext in bits 0-3 (packed layout: two bit pairs 16 apart)
             const uint32_t nib = PK ? ((cword >> (sh & 15)) & 3u) | (((cword >> ((sh & 15) + 16)) & 3u) << 2)
                                     : (cword >> (sh & 31)) & 15u;
-            const int gq = (int)(so + j - 1 - swb);
-            const int gqc = min(max(gq, 0), 63);
-            const int ic = min(max(i - 1, 0), m - 1);
-            const int cr = cen_lds ? (int)scen[ic] : (int)(a.center[ic] & 31);
-            const int sr = (int)((swin[gqc >> 2][lane] >> (8 * (gqc & 3))) & 31u);
-            const int sd = (int)smat[cr * 32 + sr];
-            const bool stop = state == 0 && v == 0;
-            const bool badc = guard > m + n + 2 || i < 1 || j < 1;
-            const bool miss = !(h0 || h1 || h2 || h3);
-            // the move out of this cell: diagonal, horizontal (E) or vertical
-            // (F); a switch from H into E or F moves in the same step
-            const bool dm = state == 0 && !(nib & 1u);
-            const bool hm = state == 1 || (state == 0 && (nib & 3u) == 1u);
-            const bool sm = dm && (gq < 0 || gq >= 64);
-            const bool ext = hm ? (nib & 4u) != 0 : (nib & 8u) != 0;
-            const bool fa = dm && curw >= 0 && ((i - 1) >> 5) != curw && pw >= 0;
-            const bool fi = hm && !ext && insrow >= 0 && insrow != i && pir >= 0;
-            if (stop || badc || miss || sm || fa || fi) {
-                fin = stop;
-                bad = !stop && badc;
-                cmiss = !stop && !badc && miss;
-                smiss = !stop && !badc && !miss && sm;
-                break;
+            const int hit = (tg.x == b) & (tg.y == g);
+            const int cbad = (ci < 1) | (cj < 1) | (guard + k > glim);
+            // score change over the diagonal cells before this one
+            const int pre = row_prefix16(sd) - sd;
+            int reason;
+            if (state == 0) {
+                const int dg = (int)(~nib & 1u);
+                reason = (v - pre == 0) ? kRunFin : cbad ? kRunBad : !hit ? kRunMiss
+                       : !dg ? kRunTurn : ((unsigned)gq >= 64u) ? kRunSmiss : 0;
+            } else {
+                const int ext = (int)(nib >> (state == 1 ? 2 : 3)) & 1;
+                reason = cbad ? kRunBad : !hit ? kRunMiss : !ext ? kRunEnd : 0;
             }
-            ++guard;
-            v += dm ? -sd : (ext ? a.ge : a.goe);
-            if (dm) {
-                const int p = i - 1;
-                if ((p >> 5) != curw) {
-                    if (curw >= 0) { pw = curw; pb = bits; }
-                    curw = p >> 5;
-                    bits = 0;
-                }
-                bits |= 1u << (p & 31);
-            }
-            run += hm ? 1 : 0;
-            if (hm && !ext) {   // the insertion run ends: it belongs to slot i
-                if (insrow == i) {
-                    inssum += run;
-                } else {
-                    if (insrow >= 0) { pir = insrow; piv = inssum; }
-                    insrow = i;
-                    inssum = run;
-                }
-                run = 0;
-            }
-            state = dm ? 0 : (ext ? (hm ? 1 : 2) : 0);
-            const bool di = !hm, dj = hm || dm;
-            i -= di ? 1 : 0;
-            j -= dj ? 1 : 0;
-            const bool wrap = di && t == 0;
-            t = wrap ? R - 1 : t - (di ? 1 : 0);
-            blk -= wrap ? 1 : 0;
-        }
-        if (pw >= 0) { al[pw] = pb; pw = -1; }
-        if (pir >= 0) {
-            ins[pir] = (uint16_t)piv;
-            if (gmax) atomicMax(gmax + pir, piv);
-            pir = -1;
-        }
-        if (bad || fin) break;
-        if (!cmiss && !smiss) continue;   // the loop stopped only to issue stores
-        // the sequence window: moved when it no longer holds the 16 residues
-        // at and below j - 1; reloaded with every code miss (one round trip)
-        const int64_t gs = so + j - 1;
-        int64_t nswb = swb;
-        if (smiss || gs - 15 < swb || gs >= swb + 64) {
-            nswb = (gs & ~(int64_t)15) - 48;
-            if (nswb < 0) nswb = 0;
-        }
-        const uint4 *src = reinterpret_cast<const uint4 *>(a.res + nswb);
-        const uint4 s0 = src[0], s1 = src[1], s2 = src[2], s3 = src[3];
-        if (smiss) {
-            swin[0][lane] = s0.x; swin[1][lane] = s0.y; swin[2][lane] = s0.z; swin[3][lane] = s0.w;
-            swin[4][lane] = s1.x; swin[5][lane] = s1.y; swin[6][lane] = s1.z; swin[7][lane] = s1.w;
-            swin[8][lane] = s2.x; swin[9][lane] = s2.y; swin[10][lane] = s2.z; swin[11][lane] = s2.w;
-            swin[12][lane] = s3.x; swin[13][lane] = s3.y; swin[14][lane] = s3.z; swin[15][lane] = s3.w;
-            swb = nswb;
-            continue;
-        }
-        // miss at (blk, grp(j)): load it, its left neighbour, and the two
-        // chunks of the block above where a diagonal path enters it
-        const int g0 = grp_of(blk, j);
-        const int jn = j - (t + 1);
-        const int g2 = (blk >= 1 && jn >= 1) ? grp_of(blk - 1, jn) : -1;
-        const int64_t ad0 = chunk_addr(blk, g0);
-        const int64_t ad1 = g0 >= 1 ? chunk_addr(blk, g0 - 1) : ad0;
-        const int64_t ad2 = g2 >= 0 ? chunk_addr(blk - 1, g2) : ad0;
-        const int64_t ad3 = g2 >= 1 ? chunk_addr(blk - 1, g2 - 1) : ad0;
-        uint4 cq[4][HQ];
-#pragma unroll
-        for (int h = 0; h < HQ; ++h) cq[0][h] = cq[1][h] = cq[2][h] = cq[3][h] = make_uint4(0, 0, 0, 0);
-        {
-            const uint4 *q0 = reinterpret_cast<const uint4 *>(a.codes + ad0);
-            const uint4 *q1 = reinterpret_cast<const uint4 *>(a.codes + ad1);
-            const uint4 *q2 = reinterpret_cast<const uint4 *>(a.codes + ad2);
-            const uint4 *q3 = reinterpret_cast<const uint4 *>(a.codes + ad3);
-            cq[0][0] = q0[0]; cq[0][1] = q0[1];
-            cq[1][0] = q1[0]; cq[1][1] = q1[1];
-            cq[2][0] = q2[0]; cq[2][1] = q2[1];
-            cq[3][0] = q3[0]; cq[3][1] = q3[1];
-            if (PK) {
-#pragma unroll
-                for (int h = 2; h < HQ; ++h)
-                    if (h < 2 * W) {
-                        cq[0][h] = q0[h];
-                        cq[1][h] = q1[h];
-                        cq[2][h] = q2[h];
-                        cq[3][h] = q3[h];
+            // ---- the first lane of the row that ends the run
+            const unsigned long long fm = __ballot(reason != 0);
+            const uint32_t rb = (uint32_t)(fm >> gbase) & 0xffffu;
+            const int r = __builtin_ctz(rb | 0x10000u);
+            const int q = min(r, 15);
+            const uint32_t pk = ((uint32_t)(pre + 0x8000) & 0xffffu) | ((uint32_t)(sd & 0xff) << 16) |
+                                (nib << 24) | ((uint32_t)reason << 28);
+            const uint32_t got = (uint32_t)__builtin_amdgcn_ds_bpermute((gbase + q) << 2, (int)pk);
+            const int preq = (int)(got & 0xffffu) - 0x8000;
+            const int sdq = (int)(int8_t)(got >> 16);
+            const uint32_t nibq = (got >> 24) & 15u;
+            const int rq = r < 16 ? (int)(got >> 28) : 0;
+            if (why == 0) {
+                // ---- r moves of the run
+                if (state == 0) {
+                    if (r > 0) {
+                        // aligned bits of center positions i - r .. i - 1
+                        const int hi = i - 1, lo = i - r;
+                        const int wh = hi >> 5, wlo = lo >> 5;
+                        if (wh != curw) {
+                            if (curw >= 0 && k == 0) al[curw] = bits;
+                            curw = wh;
+                            bits = 0;
+                        }
+                        bits |= (0xffffffffu >> (31 - (hi & 31))) & (0xffffffffu << (wlo == wh ? (lo & 31) : 0));
+                        if (wlo != wh) {
+                            if (k == 0) al[wh] = bits;
+                            curw = wlo;
+                            bits = 0xffffffffu << (lo & 31);
+                        }
                     }
-            } else if (W == 2) {
-                cq[0][2] = q0[2]; cq[0][3] = q0[3];
-                cq[1][2] = q1[2]; cq[1][3] = q1[3];
-                cq[2][2] = q2[2]; cq[2][3] = q2[3];
-                cq[3][2] = q3[2]; cq[3][3] = q3[3];
-            }
-        }
-        swin[0][lane] = s0.x; swin[1][lane] = s0.y; swin[2][lane] = s0.z; swin[3][lane] = s0.w;
-        swin[4][lane] = s1.x; swin[5][lane] = s1.y; swin[6][lane] = s1.z; swin[7][lane] = s1.w;
-        swin[8][lane] = s2.x; swin[9][lane] = s2.y; swin[10][lane] = s2.z; swin[11][lane] = s2.w;
-        swin[12][lane] = s3.x; swin[13][lane] = s3.y; swin[14][lane] = s3.z; swin[15][lane] = s3.w;
-        swb = nswb;
-#pragma unroll
-        for (int c = 0; c < 4; ++c) {
-#pragma unroll
-            for (int h = 0; h < HQ; ++h) {
-                if (h < 2 || (PK ? h < 2 * W : W == 2)) {
-                    cache[c][4 * h + 0][lane] = cq[c][h].x;
-                    cache[c][4 * h + 1][lane] = cq[c][h].y;
-                    cache[c][4 * h + 2][lane] = cq[c][h].z;
-                    cache[c][4 * h + 3][lane] = cq[c][h].w;
+                    v -= preq + (r == 16 ? sdq : 0);
+                    i -= r;
+                    j -= r;
+                } else {
+                    v += r * a.ge;
+                    if (state == 1) { j -= r; run += r; } else i -= r;
+                }
+                guard += r;
+                // ---- the move out of cell r when the run ends there
+                if (rq == kRunTurn || rq == kRunEnd) {
+                    const bool hm = state == 1 || (state == 0 && (nibq & 3u) == 1u);
+                    const bool ext = rq == kRunTurn && ((hm ? (nibq >> 2) : (nibq >> 3)) & 1u);
+                    v += ext ? a.ge : a.goe;
+                    ++guard;
+                    state = ext ? (hm ? 1 : 2) : 0;
+                    if (hm) {
+                        --j;
+                        ++run;
+                        if (!ext) {   // the insertion run ends: it belongs to slot i
+                            if (insrow == i) inssum += run;
+                            else {
+                                if (insrow >= 0 && k == 0) {
+                                    ins[insrow] = (uint16_t)inssum;
+                                    if (gmax) atomicMax(gmax + insrow, inssum);
+                                }
+                                insrow = i;
+                                inssum = run;
+                            }
+                            run = 0;
+                        }
+                    } else {
+                        --i;
+                    }
+                } else if (rq != 0) {
+                    why = rq;
                 }
             }
+            if (__ballot(why == 0) == 0) break;
         }
-        tb0 = blk; tg0 = g0;
-        tb1 = g0 >= 1 ? blk : -1; tg1 = g0 - 1;
-        tb2 = g2 >= 0 ? blk - 1 : -1; tg2 = g2;
-        tb3 = g2 >= 1 ? blk - 1 : -1; tg3 = g2 - 1;
+        if (why == 7) continue;
+        fin = why == kRunFin;
+        bad = why == kRunBad;
+        if (why != kRunMiss && why != kRunSmiss) continue;
+        // ---- refill: lane k loads chunk (block b0 - qb, column gq0 - u), k = qb * NG + u
+        const int row0 = i - 1, col0 = j - 1;
+        int b0, t0;
+        split_row(row0, b0, t0);
+        const int qb = k >> lgng, u = k & ngm;
+        const int bq = b0 - qb;
+        const int cq = (state == 2 || qb == 0) ? col0 : max(col0 - (t0 + 1) - (qb - 1) * R, 0);
+        const int gg = grp_of(max(bq, 0), cq) - u;
+        const bool ok = bq >= 0 && gg >= 0;
+        const int slot = (gg & ngm) | ((bq & nbm) << lgng);
+        const int64_t gs = so + col0;
+        int64_t nswb = (gs & ~(int64_t)15) - 48;
+        if (nswb < 0) nswb = 0;
+        // 16 lanes x 4 bytes, none past the aligned 16-byte chunk that holds
+        // residue gs (dwords above it repeat that chunk's last one; the path
+        // never reads columns right of j - 1)
+        const uint32_t wv = *reinterpret_cast<const uint32_t *>(
+            a.res + min(nswb + 4 * k, (gs & ~(int64_t)15) + 12));
+        uint4 cq4[8];
+#pragma unroll
+        for (int h = 0; h < 8; ++h) cq4[h] = make_uint4(0, 0, 0, 0);
+        if (ok) {
+            const uint4 *src = reinterpret_cast<const uint4 *>(a.codes + chunk_addr(bq, gg));
+#pragma unroll
+            for (int h = 0; h < 8; ++h)
+                if (h < 2 * W) cq4[h] = src[h];
+        }
+        win[k] = wv;
+        swb = nswb;
+        qoff = (int)(so - swb);
+        if (ok) {
+            uint4 *dst = reinterpret_cast<uint4 *>(ccache + slot * cws);
+#pragma unroll
+            for (int h = 0; h < 8; ++h)
+                if (h < 2 * W) dst[h] = cq4[h];
+        }
+        ctag[slot] = ok ? make_int2(bq, gg) : make_int2(-1, -1);
     }
+    if (k != 0) return;
     if (bad) {
         *cp = make_int4(-1, -1, -1, -1);
         return;
