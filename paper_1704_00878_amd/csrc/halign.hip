@@ -1542,6 +1542,8 @@ static bool strip16_ok(const Scoring &S, const halign_seqs *sq) {
 // closed-form triangular tiling of tiling.hpp, ngroups = tri_groups(N, step),
 // with no per-group arrays.  Mode 2 (anchored groups): gcen, gb0 and gslot
 // list the groups.
+constexpr int64_t kGroupSlice = (int64_t)1 << 21;   // all-pairs groups per launch
+
 static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, int mode, int64_t ngroups,
                       const std::vector<int32_t> &gcen, const std::vector<int32_t> &gb0,
                       const std::vector<int32_t> &perm, const std::vector<int32_t> &gslot, int64_t *sums,
@@ -1595,9 +1597,24 @@ static int run_groups(halign_ctx *ctx, const Scoring &S, const halign_seqs *sq, 
     std::array<hipEvent_t, 3> *tv = nullptr;
     RCHK(tev_next(ctx, &tv));
     RCHK(record(ctx, (*tv)[0], st));
-    if (p16) hipLaunchKernelGGL(hk::sw_inter16_kernel, dim3(grid), dim3(64), 0, st, a);
-    else launch_inter(a, false, false, grid, st);
-    HCHK(hipGetLastError());
+    // all pairs run in launches of at most kGroupSlice groups (a few seconds
+    // each at the largest sets), so that no single kernel runs for minutes
+    int64_t slice = mode == 1 ? kGroupSlice : ngroups;
+    if (const char *e = getenv("HALIGN_GROUP_SLICE"))   // test knob: many small launches
+        if (mode == 1 && atoll(e) > 0) slice = atoll(e);
+    a.gtotal = ngroups;
+    for (int64_t g0 = 0; g0 < ngroups; g0 += slice) {
+        a.gfirst = g0;
+        a.ngroups = std::min(slice, ngroups - g0);
+        if (g0 > 0) RCHK(launch_fill((uint32_t *)ctx->counter.p, 0u, 2, st));
+        if (p16) hipLaunchKernelGGL(hk::sw_inter16_kernel, dim3(grid), dim3(64), 0, st, a);
+        else launch_inter(a, false, false, grid, st);
+        HCHK(hipGetLastError());
+        if (ctx->progress && ngroups > slice && !ctx->capturing) {
+            HCHK(hipStreamSynchronize(st));
+            fprintf(stderr, "halign: all-pairs groups %lld / %lld\n", (long long)(g0 + a.ngroups), (long long)ngroups);
+        }
+    }
     RCHK(record(ctx, (*tv)[1], st));
     RCHK(record(ctx, (*tv)[2], st));
     return HALIGN_OK;

@@ -46,7 +46,9 @@ struct InterArgs {
     int nseq;
     const int32_t *gslot;     // mode 2: sums slot of the group's center
     int64_t *sums;            // modes 1/2: integer score sums (atomic adds)
-    int64_t ngroups;          // mode 1: tri_groups(nseq, partners per group), largest first
+    int64_t ngroups;          // groups of this launch
+    int64_t gfirst, gtotal;   // mode 1: this launch runs groups gfirst .. gfirst + ngroups - 1 of the
+                              // gtotal = tri_groups(nseq, partners per group), largest first
     int ge, goe;
     unsigned long long *counter;   // next group (zeroed before the launch)
     int32_t *score;           // mode 0: per pair id; mode 2: per lane slot (optional)
@@ -103,7 +105,7 @@ sw_inter_kernel(InterArgs a) {
         } else {
             int64_t apos = -1, b0;
             if (a.mode == 1) {
-                tri_group(a.ngroups - 1 - g, a.nseq, 64, &apos, &b0);
+                tri_group(a.gtotal - 1 - (a.gfirst + g), a.nseq, 64, &apos, &b0);
                 cid = a.perm[apos];
             } else {
                 b0 = a.gb0[g];
@@ -318,7 +320,7 @@ sw_inter16_kernel(InterArgs a) {
         int64_t apos = -1, b0;
         int cid;
         if (a.mode == 1) {
-            tri_group(a.ngroups - 1 - g, a.nseq, 128, &apos, &b0);
+            tri_group(a.gtotal - 1 - (a.gfirst + g), a.nseq, 128, &apos, &b0);
             cid = a.perm[apos];
         } else {
             b0 = a.gb0[g];

@@ -168,6 +168,19 @@ def test_center_exact_groups(H, ctx, strip):
     assert (d.cpu().numpy() == sums).all()
 
 
+def test_center_exact_sliced(H, ctx, strip, monkeypatch):
+    """All pairs in launches of 3 groups each (a counter reset between them)."""
+    import torch
+    monkeypatch.setenv("HALIGN_GROUP_SLICE", "3")
+    seqs = _mixed_set(200, 14)
+    best, sums = oracle.center_exact(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets)
+    ds = H.DeviceSeqs(seqs)
+    d = torch.empty(seqs.n, dtype=torch.int64, device="cuda")
+    c = H.halign_center_exact(ctx, H.Scoring(), ds, d)
+    assert c == best
+    assert (d.cpu().numpy() == sums).all()
+
+
 def test_center_judge_groups(H, ctx, strip):
     import torch
     seqs = _mixed_set(200, 13)
