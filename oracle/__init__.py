@@ -65,6 +65,8 @@ def lib():
             getattr(L, fn).restype = ctypes.c_int64
         L.orc_encode.argtypes = [P, ctypes.c_int64, P]
         L.orc_encode.restype = None
+        L.orc_column_profile.argtypes = [P, I, ctypes.c_int64, I, P]
+        L.orc_column_profile.restype = I
         L.orc_sp_blosum.argtypes = [P, I, I, P, I, ctypes.c_int64]
         L.orc_sp_blosum.restype = ctypes.c_int64
         _lib = L
@@ -231,6 +233,16 @@ def sp_pairs(msa_rows: np.ndarray) -> int:
 def sp_columns(msa_rows: np.ndarray) -> int:
     a = _u8(msa_rows)
     return int(lib().orc_sp_columns(_p(a), a.shape[0], a.shape[1]))
+
+
+def column_profile(msa_rows: np.ndarray, alpha: int) -> np.ndarray:
+    """int32 [width][alpha + 1]: residue counts per column, gaps last."""
+    a = _u8(msa_rows)
+    out = np.zeros((a.shape[1], alpha + 1), np.int32)
+    r = lib().orc_column_profile(_p(a), a.shape[0], a.shape[1], alpha, _p(out))
+    if r != 0:
+        raise ValueError("byte outside the alphabet and not a gap")
+    return out
 
 
 def avg_sp(msa_rows: np.ndarray) -> float:

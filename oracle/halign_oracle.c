@@ -415,6 +415,24 @@ int64_t orc_sp_columns(const uint8_t *msa, int nseq, int64_t width)
     return total;
 }
 
+/* Column profile (Results, datasets section: the per-column counts from which
+ * the avg SP of an alignment follows): out[x * (alpha + 1) + a] = number of
+ * rows whose column x holds residue code a (a < alpha); slot alpha counts the
+ * gaps.  Returns 0, or -1 if a byte is neither a residue code below alpha nor
+ * the gap code. */
+int orc_column_profile(const uint8_t *msa, int nseq, int64_t width, int alpha, int32_t *out)
+{
+    memset(out, 0, sizeof(int32_t) * (size_t)width * (size_t)(alpha + 1));
+    for (int a = 0; a < nseq; a++)
+        for (int64_t x = 0; x < width; x++) {
+            uint8_t u = msa[(size_t)a * width + x];
+            if (u == ORC_GAP) out[x * (alpha + 1) + alpha]++;
+            else if (u < alpha) out[x * (alpha + 1) + u]++;
+            else return -1;
+        }
+    return 0;
+}
+
 /* BLOSUM column SP: S for residue pairs, -ge per residue/gap pair, 0 gap/gap. */
 int64_t orc_sp_blosum(const int8_t *S, int alpha, int ge, const uint8_t *msa, int nseq, int64_t width)
 {

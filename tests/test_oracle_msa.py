@@ -128,3 +128,45 @@ def test_center_ties_lowest_index():
     assert best == 0 and len(set(sums.tolist())) == 1
     jb, _ = oracle.center_judge(B62, GO, GE, seqs.residues, seqs.offsets, [2, 1])
     assert jb == 1
+
+
+def _sp_from_profile(P, S, ge):
+    """Both SP scores from column counts: residue pairs by the matrix (or +1
+    when they differ), residue-gap pairs +2 (or -ge), gap-gap pairs 0."""
+    alpha = P.shape[1] - 1
+    res, gap = P[:, :alpha].astype(np.int64), P[:, alpha].astype(np.int64)
+    r = res.sum(1)
+    sp = int(((r * (r - 1) // 2) - (res * (res - 1) // 2).sum(1) + 2 * gap * r).sum())
+    pairs = res[:, :, None] * res[:, None, :] - np.einsum("xa,ab->xab", res, np.eye(alpha, dtype=np.int64))
+    bl = int((pairs * S[:alpha, :alpha].astype(np.int64)[None]).sum() // 2 - ge * (gap * r).sum())
+    return sp, bl
+
+
+def test_column_profile_hand():
+    G = 255
+    a = np.array([[0, 1, G, 2],
+                  [0, G, G, 2],
+                  [3, 1, 1, 2]], np.uint8)
+    P = oracle.column_profile(a, 4)
+    assert P.tolist() == [[2, 0, 0, 1, 0],
+                          [0, 2, 0, 0, 1],
+                          [0, 1, 0, 0, 2],
+                          [0, 0, 3, 0, 0]]
+    with pytest.raises(ValueError):
+        oracle.column_profile(np.array([[4]], np.uint8), 4)
+
+
+def test_column_profile_pins_sp():
+    """Counts per column sum to the rows; SP and BLOSUM SP taken from the
+    profile equal the explicit pair loops (a slot or column mix-up breaks the
+    BLOSUM sum, whose matrix entries differ per residue)."""
+    rng = np.random.default_rng(21)
+    B62 = np.asarray(synth.BLOSUM62, np.int8)
+    for n, w in ((2, 1), (7, 13), (40, 57)):
+        a = rng.integers(0, 24, (n, w)).astype(np.uint8)
+        a[rng.random((n, w)) < 0.3] = 255
+        P = oracle.column_profile(a, 24)
+        assert (P.sum(1) == n).all()
+        sp, bl = _sp_from_profile(P, B62, 1)
+        assert sp == oracle.sp_pairs(a)
+        assert bl == oracle.sp_blosum(B62, 1, a)
