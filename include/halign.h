@@ -365,6 +365,17 @@ int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seq
 int halign_sp_score(const halign_scoring *sc, const uint8_t *msa, int32_t n, int64_t width,
                     int64_t *out_host, void *stream);
 
+/* Column profile of an MSA (Results: the per-column counts that avg SP is a
+ * function of).  msa: device uint8 [n][width], residue codes below alphabet
+ * or HALIGN_GAP (255).  profile: device int32 [width][alphabet + 1],
+ * caller-owned, overwritten: profile[x][a] = rows whose column x holds code a,
+ * profile[x][alphabet] = gaps in column x.  1 <= alphabet <= 32.  Reads the
+ * MSA once, in coalesced row segments (suited to 1e6 rows).  Synchronises;
+ * HALIGN_E_INVALID if a byte is neither a code below alphabet nor the gap
+ * (profile contents then unspecified). */
+int halign_column_profile(const uint8_t *msa, int32_t n, int64_t width, int32_t alphabet,
+                          int32_t *profile, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

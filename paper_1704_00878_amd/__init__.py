@@ -114,6 +114,7 @@ def lib():
         "halign_center_learned": ([P, P, P, P, I, P, P, P], I),
         "halign_msa": ([P, P, P, I, P, _ALLOC_FN, P, P, P, P, P], I),
         "halign_sp_score": ([P, P, I, I64, P, P], I),
+        "halign_column_profile": ([P, I, I64, I, P, P], I),
     }
     for name, (args, res) in sig.items():
         if not hasattr(L, name):
@@ -309,6 +310,16 @@ def halign_sp_score(sc: Scoring, msa, stream=None):
     n, w = (msa.shape[0], msa.shape[1]) if msa.dim() == 2 else (0, 0)
     _check(lib().halign_sp_score(sc.ref, _ptr(msa), n, w, out, _stream(stream)))
     return int(out[0]), int(out[1])
+
+
+def halign_column_profile(msa, alphabet: int = 24, out=None, stream=None):
+    """int32 [W, alphabet + 1] device tensor: residue counts per MSA column, gaps last."""
+    import torch
+    n, w = (msa.shape[0], msa.shape[1]) if msa.dim() == 2 else (0, 0)
+    if out is None:
+        out = torch.empty((w, alphabet + 1), dtype=torch.int32, device=msa.device)
+    _check(lib().halign_column_profile(_ptr(msa), n, w, alphabet, _ptr(out), _stream(stream)))
+    return out
 
 
 def halign_msa(ctx: Context, sc: Scoring, seqs: DeviceSeqs, center: int, model=None, stream=None, out=None):

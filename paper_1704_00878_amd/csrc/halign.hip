@@ -1890,27 +1890,112 @@ int halign_sw_score_noalloc(const halign_scoring *sc, const uint8_t *center, int
     return HALIGN_OK;
 }
 
+}  // extern "C"
+
+// Column profile into prof, *dbad raised on a byte that is neither a residue
+// code below alpha nor the gap.  Rows are split into slabs (at most
+// kProfMaxSlab rows, for 16-bit partial counts) so that the grid has a few
+// thousand workgroups; the slabs' counts meet in a second pass, not in
+// atomics (many workgroups adding into the same profile line serialise).
+// part: at least column_profile_part_bytes() bytes of device scratch.
+static void column_profile_shape(int32_t n, int64_t width, int64_t *ncb, int64_t *nslab, int *slab) {
+    if (n <= 0 || width <= 0) {   // nothing to count
+        *ncb = *nslab = 0;
+        *slab = 1;
+        return;
+    }
+    *ncb = (width + hk::kProfCols - 1) / hk::kProfCols;
+    int64_t ns = std::max<int64_t>((n + hk::kProfMaxSlab - 1) / hk::kProfMaxSlab,
+                                   std::min<int64_t>((3072 + *ncb - 1) / *ncb, (n + 255) / 256));
+    int sl = (int)((n + ns - 1) / std::max<int64_t>(ns, 1));
+    if (const char *e = getenv("HALIGN_PROFILE_SLAB"))   // test knob: rows per slab
+        if (atoi(e) > 0) sl = std::min(atoi(e), hk::kProfMaxSlab);
+    *slab = std::max(sl, 1);
+    *nslab = (n + *slab - 1) / *slab;
+}
+
+static size_t column_profile_part_bytes(int32_t n, int64_t width, int32_t alpha) {
+    int64_t ncb, nslab;
+    int slab;
+    column_profile_shape(n, width, &ncb, &nslab, &slab);
+    return (size_t)nslab * (size_t)width * (size_t)(alpha + 1) * 2;
+}
+
+static int column_profile_launch(const uint8_t *msa, int32_t n, int64_t width, int32_t alpha, int32_t *prof,
+                                 uint16_t *part, int *dbad, hipStream_t st) {
+    const int nsym = alpha + 1;
+    if (n <= 0 || width <= 0) return launch_fill((uint32_t *)prof, 0u, width * nsym, st);
+    int64_t ncb, nslab;
+    int slab;
+    column_profile_shape(n, width, &ncb, &nslab, &slab);
+    if (ncb > 0x7fffffff || nslab > 65535) return fail(HALIGN_E_UNSUPPORTED, "%d x %lld MSA", n, (long long)width);
+    hipLaunchKernelGGL(hk::colprof_kernel, dim3((unsigned)ncb, (unsigned)nslab), dim3(256),
+                       (size_t)(alpha + 3) * 256 * 4, st, msa, n, width, alpha, slab, part, dbad);
+    HCHK(hipGetLastError());
+    const int64_t nelem = width * nsym;
+    hipLaunchKernelGGL(hk::colprof_sum_kernel, dim3((unsigned)((nelem + 255) / 256)), dim3(256), 0, st,
+                       (const uint16_t *)part, (int)nslab, nelem, prof);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
+}
+
+extern "C" {
+
+int halign_column_profile(const uint8_t *msa, int32_t n, int64_t width, int32_t alphabet, int32_t *profile,
+                          void *stream) {
+    if (n < 0 || width < 0 || alphabet < 1 || alphabet > 32 || (width > 0 && !profile) ||
+        (n > 0 && width > 0 && !msa))
+        return fail(HALIGN_E_INVALID, "bad arguments");
+    hipStream_t st = (hipStream_t)stream;
+    int *dbad = nullptr;
+    HCHK(hipMalloc(&dbad, 256 + column_profile_part_bytes(n, width, alphabet)));
+    int rc = launch_fill((uint32_t *)dbad, 0u, 1, st);
+    if (rc == HALIGN_OK)
+        rc = column_profile_launch(msa, n, width, alphabet, profile, (uint16_t *)((char *)dbad + 256), dbad, st);
+    int hbad = 0;
+    if (rc == HALIGN_OK && hipMemcpyAsync(&hbad, dbad, 4, hipMemcpyDeviceToHost, st) != hipSuccess)
+        rc = fail(HALIGN_E_DEVICE, "profile flag copy");
+    if (rc == HALIGN_OK && hipStreamSynchronize(st) != hipSuccess) rc = fail(HALIGN_E_DEVICE, "profile sync");
+    (void)hipFree(dbad);
+    if (rc != HALIGN_OK) return rc;
+    if (hbad) return fail(HALIGN_E_INVALID, "MSA byte neither a residue code below %d nor the gap", alphabet);
+    return HALIGN_OK;
+}
+
 int halign_sp_score(const halign_scoring *sc, const uint8_t *msa, int32_t n, int64_t width, int64_t *out_host,
                     void *stream) {
     RCHK(check_scoring(sc));
     if (!out_host || n < 0 || width < 0 || (n > 0 && width > 0 && !msa)) return fail(HALIGN_E_INVALID, "bad arguments");
     hipStream_t st = (hipStream_t)stream;
-    int8_t *dmat = nullptr;
-    unsigned long long *dout = nullptr;
-    HCHK(hipMalloc(&dmat, 1024));
-    HCHK(hipMalloc(&dout, 16));
-    HCHK(hipMemcpyAsync(dmat, sc->matrix_host, (size_t)sc->alphabet * sc->alphabet, hipMemcpyHostToDevice, st));
-    RCHK(launch_fill((uint32_t *)dout, 0u, 4, st));
-    if (n > 0 && width > 0) {
-        hipLaunchKernelGGL(hk::sp_kernel, dim3((unsigned)((width + 127) / 128)), dim3(128), 0, st, msa, n, width,
-                           (const int8_t *)dmat, sc->alphabet, sc->gap_extend, dout);
-        HCHK(hipGetLastError());
+    const int alpha = sc->alphabet;
+    // one allocation: matrix (1 KiB), sums (16 B), flag, profile
+    const size_t prof_b = ((size_t)std::max<int64_t>(width, 1) * (alpha + 1) * 4 + 255) & ~(size_t)255;
+    char *buf = nullptr;
+    HCHK(hipMalloc(&buf, 2048 + prof_b + column_profile_part_bytes(n, width, alpha)));
+    int8_t *dmat = (int8_t *)buf;
+    unsigned long long *dout = (unsigned long long *)(buf + 1024);
+    int *dbad = (int *)(buf + 1040);
+    int32_t *prof = (int32_t *)(buf + 2048);
+    int rc = HALIGN_OK;
+    unsigned long long h[2] = {0, 0};
+    int hbad = 0;
+    if (hipMemcpyAsync(dmat, sc->matrix_host, (size_t)alpha * alpha, hipMemcpyHostToDevice, st) != hipSuccess)
+        rc = fail(HALIGN_E_DEVICE, "matrix copy");
+    if (rc == HALIGN_OK) rc = launch_fill((uint32_t *)dout, 0u, 5, st);   // sums and flag
+    if (rc == HALIGN_OK)
+        rc = column_profile_launch(msa, n, width, alpha, prof, (uint16_t *)(buf + 2048 + prof_b), dbad, st);
+    if (rc == HALIGN_OK && n > 0 && width > 0) {
+        hipLaunchKernelGGL(hk::sp_profile_kernel, dim3((unsigned)((width + 255) / 256)), dim3(256), 0, st, prof,
+                           width, alpha, (const int8_t *)dmat, sc->gap_extend, dout);
+        if (hipGetLastError() != hipSuccess) rc = fail(HALIGN_E_DEVICE, "sp_profile_kernel launch");
     }
-    unsigned long long h[2];
-    HCHK(hipMemcpyAsync(h, dout, 16, hipMemcpyDeviceToHost, st));
-    HCHK(hipStreamSynchronize(st));
-    HCHK(hipFree(dmat));
-    HCHK(hipFree(dout));
+    if (rc == HALIGN_OK && (hipMemcpyAsync(h, dout, 16, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                            hipMemcpyAsync(&hbad, dbad, 4, hipMemcpyDeviceToHost, st) != hipSuccess ||
+                            hipStreamSynchronize(st) != hipSuccess))
+        rc = fail(HALIGN_E_DEVICE, "sp result copy");
+    (void)hipFree(buf);
+    if (rc != HALIGN_OK) return rc;
+    if (hbad) return fail(HALIGN_E_INVALID, "MSA byte neither a residue code below %d nor the gap", alpha);
     out_host[0] = (int64_t)h[0];
     out_host[1] = (int64_t)h[1];
     return HALIGN_OK;

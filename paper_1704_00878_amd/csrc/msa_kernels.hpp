@@ -267,41 +267,109 @@ __global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
     }
 }
 
-// avg SP numerator and BLOSUM column SP over an N x W MSA, one thread per
-// column; counts per residue code kept in LDS.  out[0] += sum over columns of
-// (pairs of different residues) + 2*(residue-gap pairs); out[1] += BLOSUM SP.
-__global__ void __launch_bounds__(128)
-sp_kernel(const uint8_t *msa, int n, int64_t width, const int8_t *mat, int alpha, int ge,
-          unsigned long long *out) {
-    __shared__ int cnt[128][33];
+constexpr int kProfCols = 256;      // columns per workgroup (one per lane)
+constexpr int kProfMaxSlab = 65535; // rows per workgroup (16-bit partial counts)
+constexpr int kProfRows = 32;       // rows loaded per pass
+
+// rows of one column into the lane's LDS counters (stride 256 words): bin 0
+// gaps, 1 + a for residue code a, top = alpha + 1 anything else; EDGE: a lane
+// past the last column (in == false) reads the last column and counts into
+// bin top + 1, which is discarded, so the row loop has no branch
+template <bool EDGE>
+__device__ __forceinline__ void colprof_rows(const uint8_t *p, int64_t width, int rows, uint32_t *lc, uint32_t top,
+                                             bool in) {
+    auto count = [&](uint32_t b) __attribute__((always_inline)) {
+        uint32_t bin = min((b + 1u) & 255u, top);
+        if (EDGE) bin = in ? bin : top + 1u;
+        atomicAdd(lc + bin * 256, 1u);
+    };
+    int r = 0;
+    for (; r + kProfRows <= rows; r += kProfRows, p += kProfRows * width) {
+        uint32_t v[kProfRows];
+#pragma unroll
+        for (int u = 0; u < kProfRows; ++u) v[u] = p[u * width];
+#pragma unroll
+        for (int u = 0; u < kProfRows; ++u) count(v[u]);
+    }
+    for (; r < rows; ++r, p += width) count(*p);
+}
+
+// Column profile of an N x W MSA, first pass: workgroup (x, y) counts the
+// bytes of columns 256 x .. 256 x + 255 over the rows of slab y.  Lane t owns
+// column 256 x + t, so each byte load of a wavefront covers 64 consecutive
+// bytes of a row; 32 rows are loaded before they are counted.  The lane's
+// counters sit in LDS (word bin * 256 + t, no barrier needed): bin 0 counts
+// gaps, bin 1 + a residue code a, bin alpha + 1 any other byte (which raises
+// *bad).  The slab's counts go, without atomics, to part[y][column][slot]
+// (uint16; slot a < alpha a residue code, slot alpha the gaps), written in
+// contiguous runs.  A lane past the last column reads the last column and
+// counts into a discarded bin, so the row loop has no branch.
+__global__ void __launch_bounds__(256)
+colprof_kernel(const uint8_t *msa, int n, int64_t width, int alpha, int slab, uint16_t *part, int *bad) {
+    extern __shared__ uint32_t pcnt[];
+    const int nbin = alpha + 3;
+    const int t = threadIdx.x;
+    uint32_t *lc = pcnt + t;
+    for (int x = 0; x < nbin; ++x) lc[x * 256] = 0;
+    const int64_t cb = (int64_t)blockIdx.x * kProfCols;
+    const bool in = cb + t < width;
+    const int r0 = blockIdx.y * slab;
+    const int r1 = min(n, r0 + slab);
+    const uint8_t *p = msa + (int64_t)r0 * width + (in ? cb + t : width - 1);
+    if (cb + kProfCols <= width) colprof_rows<false>(p, width, r1 - r0, lc, (uint32_t)alpha + 1u, true);
+    else colprof_rows<true>(p, width, r1 - r0, lc, (uint32_t)alpha + 1u, in);
+    if (in && lc[(alpha + 1) * 256] != 0) atomicOr(bad, 1);
+    __syncthreads();
+    // slab counts out: element e of the workgroup's run is (column e / nsym, slot e % nsym)
+    const int nsym = alpha + 1;
+    const int64_t ncols = min((int64_t)kProfCols, width - cb);
+    uint16_t *dst = part + ((int64_t)blockIdx.y * width + cb) * nsym;
+    for (int e = t; e < ncols * nsym; e += 256) {
+        const int c = e / nsym, slot = e - c * nsym;
+        dst[e] = (uint16_t)pcnt[(slot == alpha ? 0 : slot + 1) * 256 + c];
+    }
+}
+
+// Second pass: profile[e] = sum over slabs of part[slab][e], e < width * nsym.
+__global__ void __launch_bounds__(256)
+colprof_sum_kernel(const uint16_t *part, int nslab, int64_t nelem, int32_t *prof) {
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= nelem) return;
+    int32_t s = 0;
+    for (int y = 0; y < nslab; ++y) s += part[(int64_t)y * nelem + e];
+    prof[e] = s;
+}
+
+// avg SP numerator and BLOSUM column SP from a column profile, one thread
+// per column: out[0] += (pairs of different residues) + 2 * (residue-gap
+// pairs); out[1] += sum of S over residue pairs - ge * (residue-gap pairs).
+__global__ void __launch_bounds__(256)
+sp_profile_kernel(const int32_t *prof, int64_t width, int alpha, const int8_t *mat, int ge,
+                  unsigned long long *out) {
     __shared__ int smat[32][32];
     const int tid = threadIdx.x;
-    for (int x = tid; x < 1024; x += 128) {
+    for (int x = tid; x < 1024; x += 256) {
         const int a = x >> 5, b = x & 31;
         smat[a][b] = (a < alpha && b < alpha) ? mat[a * alpha + b] : 0;
     }
-    const int64_t x = (int64_t)blockIdx.x * 128 + tid;
-    for (int c = 0; c < 33; ++c) cnt[tid][c] = 0;
     __syncthreads();
-    if (x < width) {
-        for (int k = 0; k < n; ++k) {
-            const int b = msa[(int64_t)k * width + x];
-            cnt[tid][b == kGap ? 32 : (b & 31)]++;
-        }
-        const int64_t g = cnt[tid][32], r = n - g;
-        int64_t same = 0, bl = 0;
-        for (int a = 0; a < 32; ++a) {
-            const int64_t ca = cnt[tid][a];
-            if (!ca) continue;
-            same += ca * (ca - 1) / 2;
-            bl += ca * (ca - 1) / 2 * smat[a][a];
-            for (int b = a + 1; b < 32; ++b) bl += ca * (int64_t)cnt[tid][b] * smat[a][b];
-        }
-        const int64_t sp = (r * (r - 1) / 2 - same) + 2 * g * r;
-        bl -= (int64_t)ge * g * r;
-        atomicAdd(out, (unsigned long long)sp);
-        atomicAdd(out + 1, (unsigned long long)bl);
+    const int64_t x = (int64_t)blockIdx.x * 256 + tid;
+    if (x >= width) return;
+    const int32_t *c = prof + x * (alpha + 1);
+    const int64_t g = c[alpha];
+    int64_t r = 0, same = 0, bl = 0;
+    for (int a = 0; a < alpha; ++a) {
+        const int64_t ca = c[a];
+        if (!ca) continue;
+        r += ca;
+        same += ca * (ca - 1) / 2;
+        bl += ca * (ca - 1) / 2 * smat[a][a];
+        for (int b = a + 1; b < alpha; ++b) bl += ca * (int64_t)c[b] * smat[a][b];
     }
+    const int64_t sp = (r * (r - 1) / 2 - same) + 2 * g * r;
+    bl -= (int64_t)ge * g * r;
+    atomicAdd(out, (unsigned long long)sp);
+    atomicAdd(out + 1, (unsigned long long)bl);
 }
 
 }  // namespace hk

@@ -56,3 +56,18 @@ def msa(S, go: int, ge: int, seqs, center: int, threads: int | None = None):
     G, col, W = oracle.merge(ins)
     rows = oracle.rows(seqs.residues, seqs.offsets, ins, al, G, W)
     return dict(score=score, cells=cells, ins=ins, aligned=al, G=G, col=col, width=W, msa=rows)
+
+
+def sp_from_profile(P, S, ge: int):
+    """(avg SP numerator, BLOSUM SP) from a column profile [W][alpha + 1]:
+    residue pairs score +1 when different (or S), residue-gap pairs +2 (or
+    -ge), gap-gap pairs 0."""
+    alpha = P.shape[1] - 1
+    res, gap = P[:, :alpha].astype(np.int64), P[:, alpha].astype(np.int64)
+    r = res.sum(1)
+    sp = int(((r * (r - 1) // 2) - (res * (res - 1) // 2).sum(1) + 2 * gap * r).sum())
+    S64 = np.asarray(S, np.int64)[:alpha, :alpha]
+    cross = np.einsum("xa,ab,xb->", res, S64, res)          # ordered pairs, self pairs included
+    diag = (res * np.diag(S64)[None]).sum()                  # self pairs
+    bl = int((cross - diag) // 2 - ge * (gap * r).sum())
+    return sp, bl

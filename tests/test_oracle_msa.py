@@ -4,6 +4,7 @@ import pytest
 
 import oracle
 from golden_cases import load, row_text
+from oracle_par import sp_from_profile
 from paper_1704_00878_amd import synth
 
 B62 = synth.BLOSUM62
@@ -130,18 +131,6 @@ def test_center_ties_lowest_index():
     assert jb == 1
 
 
-def _sp_from_profile(P, S, ge):
-    """Both SP scores from column counts: residue pairs by the matrix (or +1
-    when they differ), residue-gap pairs +2 (or -ge), gap-gap pairs 0."""
-    alpha = P.shape[1] - 1
-    res, gap = P[:, :alpha].astype(np.int64), P[:, alpha].astype(np.int64)
-    r = res.sum(1)
-    sp = int(((r * (r - 1) // 2) - (res * (res - 1) // 2).sum(1) + 2 * gap * r).sum())
-    pairs = res[:, :, None] * res[:, None, :] - np.einsum("xa,ab->xab", res, np.eye(alpha, dtype=np.int64))
-    bl = int((pairs * S[:alpha, :alpha].astype(np.int64)[None]).sum() // 2 - ge * (gap * r).sum())
-    return sp, bl
-
-
 def test_column_profile_hand():
     G = 255
     a = np.array([[0, 1, G, 2],
@@ -167,6 +156,6 @@ def test_column_profile_pins_sp():
         a[rng.random((n, w)) < 0.3] = 255
         P = oracle.column_profile(a, 24)
         assert (P.sum(1) == n).all()
-        sp, bl = _sp_from_profile(P, B62, 1)
+        sp, bl = sp_from_profile(P, B62, 1)
         assert sp == oracle.sp_pairs(a)
         assert bl == oracle.sp_blosum(B62, 1, a)
