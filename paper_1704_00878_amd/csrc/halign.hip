@@ -833,7 +833,8 @@ int run_batch(halign_ctx *ctx, const Scoring &S, const uint8_t *center, int m, c
             w.lg_nb = route == kRouteIntra ? (wR >= 4 ? 2 : (wR >= 2 ? 3 : 4)) : 1;
             const dim3 wg(grid_for(cn, hk::kWalkPairs, 1 << 30));
             const bool cl = m <= hk::kWalkCenterLds;
-            const size_t wlds = hk::walk_lds_bytes(route == kRouteIntra ? WQ : 1, m, cl);
+            w.glds = (out.G && m < hk::kWalkGLds) ? 1 : 0;
+            const size_t wlds = hk::walk_lds_bytes(route == kRouteIntra ? WQ : 1, m, cl, w.glds != 0);
             if (route == kRouteIntra) {
                 if (pk) {
                     if (cl) hipLaunchKernelGGL((hk::walk_kernel<false, true, true>), wg, dim3(256), wlds, st, w);
