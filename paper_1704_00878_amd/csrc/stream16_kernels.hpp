@@ -44,20 +44,21 @@ constexpr int kDppRowShl = 0x100;   // + n: lane l reads lane l + n of its row
 constexpr int kDppRowShr1 = 0x111;  // lane l reads lane l - 1 of its row
 constexpr int kDppRowBcast15 = 0x142;
 
-// LDS dwords of a profile entry (n <= 4 of the uint4 at p)
+// N (<= 4) LDS dwords of a profile entry at p (16-byte aligned for N >= 3,
+// 8-byte aligned for N = 2)
 template <int N>
-__device__ __forceinline__ void lds_words(const uint4 *p, uint32_t *d) {
+__device__ __forceinline__ void lds_words(const uint32_t *p, uint32_t *d) {
     if constexpr (N >= 4) {
-        const uint4 x = *p;
+        const uint4 x = *reinterpret_cast<const uint4 *>(p);
         d[0] = x.x; d[1] = x.y; d[2] = x.z; d[3] = x.w;
     } else if constexpr (N == 3) {
-        const uint3 x = *reinterpret_cast<const uint3 *>(p);
+        const uint4 x = *reinterpret_cast<const uint4 *>(p);
         d[0] = x.x; d[1] = x.y; d[2] = x.z;
     } else if constexpr (N == 2) {
         const uint2 x = *reinterpret_cast<const uint2 *>(p);
         d[0] = x.x; d[1] = x.y;
     } else {
-        d[0] = *reinterpret_cast<const uint32_t *>(p);
+        d[0] = *p;
     }
 }
 
@@ -90,22 +91,28 @@ sw_stream16_kernel(StreamArgs a) {
     // packed end cells need R more registers: up to R = 11 they fit the
     // 128 of four waves per SIMD
     constexpr bool SNAP = R <= 11;
-    constexpr int W = (R + 7) / 8;           // profile uint4 per (residue, lane)
     constexpr int NW = (R + 1) / 2;          // profile dwords a step reads per stream
+    // profile planes per residue: rows 0..7 (NA dwords per lane, lane stride
+    // SA dwords), then rows 8..R-1 (NB dwords, stride SB); strides of 1, 2 or 4
+    // dwords keep the lanes of one read on distinct banks
+    constexpr int NA = NW < 4 ? NW : 4, NB = NW - NA;
+    constexpr int SA = NA == 3 ? 4 : NA, SB = NB == 3 ? 4 : NB;
+    constexpr int PRW = LS * (SA + SB);      // profile dwords per residue
     constexpr int WQ = (R + 3) / 4;          // code words per step (both halves)
     constexpr int NS = 64 / LS;              // lane groups per wavefront
     constexpr int SPAN = LS * R;             // rows per pass
     constexpr int LG = LS == 32 ? 5 : 4;
-    // profile int16 [residue][w][lane][8]: lane l's rows 8w..8w+7 of residue r
-    // at uint4 (r * W + w) * LS + l, so the lanes of a read touch consecutive
-    // 16-byte slots whatever residue each one reads (no bank conflicts);
-    // then the code staging [8 waves][4 steps][WQ][64 lanes]
+    // profile int16 per residue r (PRW dwords): plane A [lane][SA dwords] holds
+    // lane l's rows 0..7 (two rows per dword), plane B [lane][SB dwords] its
+    // rows 8..R-1, so the lanes of a read touch consecutive slots whatever
+    // residue each one reads; then the code staging [8 waves][4 steps][WQ][64 lanes]
     extern __shared__ int prof[];
     const int nprow = a.alpha + 1;
-    const int prof_words = nprow * LS * 4 * W;
+    const int prof_words = nprow * PRW;
     uint32_t *stage = reinterpret_cast<uint32_t *>(prof + prof_words) + (threadIdx.x >> 6) * 256 * WQ +
                       (threadIdx.x & 63);
-    const uint4 *prof4 = reinterpret_cast<const uint4 *>(prof) + (threadIdx.x & (LS - 1));
+    const uint32_t *profA = reinterpret_cast<const uint32_t *>(prof) + (threadIdx.x & (LS - 1)) * SA;
+    const uint32_t *profB = reinterpret_cast<const uint32_t *>(prof) + LS * SA + (threadIdx.x & (LS - 1)) * SB;
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int ll = lane & (LS - 1);
@@ -163,9 +170,12 @@ sw_stream16_kernel(StreamArgs a) {
         __syncthreads();
         {
             int16_t *p16 = reinterpret_cast<int16_t *>(prof);
-            for (int x = tid; x < nprow * W * LS * 8; x += nthreads) {
-                const int r = x / (W * LS * 8), w = (x / (LS * 8)) % W, l = (x >> 3) & (LS - 1);
-                const int tt = 8 * w + (x & 7);
+            for (int x = tid; x < nprow * PRW * 2; x += nthreads) {
+                // int16 x of residue r: plane A (lane l, row tt < 8) or plane B
+                const int r = x / (PRW * 2), y = x - r * (PRW * 2);
+                int l, tt;
+                if (y < LS * SA * 2) { l = y / (SA * 2); tt = y - l * (SA * 2); }
+                else { const int z = y - LS * SA * 2; l = z / (SB * 2); tt = 8 + z - l * (SB * 2); }
                 const int i = row0 + l * R + tt;
                 int v = kPadProf16;
                 if (r < a.alpha && tt < R && i < a.m) v = (int)a.mat[(a.center[i] & 31) * a.alpha + r] + goe;
@@ -205,13 +215,11 @@ sw_stream16_kernel(StreamArgs a) {
             auto prof_read = [&](int rc, uint32_t (&da)[NW], uint32_t (&db)[NW]) __attribute__((always_inline)) {
                 const uint32_t ra = __builtin_amdgcn_ubfe((uint32_t)rc, 0, 7);
                 const uint32_t rb = __builtin_amdgcn_ubfe((uint32_t)rc, 16, 7);
-                const uint4 *pa = prof4 + ((ra * W) << LG);
-                const uint4 *pb = prof4 + ((rb * W) << LG);
-                lds_words<(NW < 4 ? NW : 4)>(pa, da);
-                lds_words<(NW < 4 ? NW : 4)>(pb, db);
-                if constexpr (NW > 4) {
-                    lds_words<NW - 4>(pa + LS, da + 4);
-                    lds_words<NW - 4>(pb + LS, db + 4);
+                lds_words<NA>(profA + ra * PRW, da);
+                lds_words<NA>(profA + rb * PRW, db);
+                if constexpr (NB > 0) {
+                    lds_words<NB>(profB + ra * PRW, da + NA);
+                    lds_words<NB>(profB + rb * PRW, db + NA);
                 }
             };
             prof_read(rcur, wa, wb);
