@@ -112,6 +112,8 @@ struct halign_ctx {
     std::map<std::string, std::array<int, 5>> tuned;   // bucket -> {route, R, stream multiplier, lanes per stream, packed}
     std::string tune_file;    // optional cache file (HALIGN_TUNE_CACHE)
     int *flag_host = nullptr; // pinned: (tag << 8 | largest residue code) of the last validated call
+    int64_t *mail_host = nullptr, *mail_dev = nullptr;   // coherent pinned mailbox: width, sequence number
+    int64_t mail_seq = 0;
     uint32_t vtag = 0;        // tag of the last eager code check
     uint32_t check_tag = 0;   // tag validate_check expects (0 after a graph replay)
     int flag_alpha = 0;       // alphabet that value is checked against (0 = nothing pending)
@@ -1116,6 +1118,15 @@ int halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out) 
         halign_ctx_destroy(ctx);
         return fail(HALIGN_E_DEVICE, "pinned allocation");
     }
+    // the width mailbox; without it the width comes back by a copy and a
+    // stream synchronisation
+    if (hipHostMalloc((void **)&ctx->mail_host, 64, hipHostMallocMapped | hipHostMallocCoherent) == hipSuccess) {
+        ctx->mail_host[0] = ctx->mail_host[1] = 0;
+        if (hipHostGetDevicePointer((void **)&ctx->mail_dev, ctx->mail_host, 0) != hipSuccess) ctx->mail_dev = nullptr;
+    } else {
+        ctx->mail_host = nullptr;
+        (void)hipGetLastError();
+    }
     if (hipEventCreateWithFlags(&ctx->ev_stage, hipEventDisableTiming) != hipSuccess) {
         halign_ctx_destroy(ctx);
         return fail(HALIGN_E_DEVICE, "event create");
@@ -1136,6 +1147,7 @@ void halign_ctx_destroy(halign_ctx *ctx) {
         if (b.p) (void)hipFree(b.p);
     if (ctx->stage.p) (void)hipHostFree(ctx->stage.p);
     if (ctx->flag_host) (void)hipHostFree(ctx->flag_host);
+    if (ctx->mail_host) (void)hipHostFree(ctx->mail_host);
     for (auto &t : ctx->tev)
         for (auto &e : t) (void)hipEventDestroy(e);
     if (ctx->ev_stage) (void)hipEventDestroy(ctx->ev_stage);
@@ -1453,9 +1465,29 @@ static int merge_offsets(halign_ctx *ctx, const int32_t *G, int m1, int64_t *col
                          hipStream_t st) {
     RCHK(grow(ctx, ctx->spbuf, 4096));
     int64_t *dwidth = (int64_t *)((char *)ctx->spbuf.p + 2048);
-    hipLaunchKernelGGL(hk::merge_scan_kernel, dim3(1), dim3(1024), 0, st, G, m1, col, dwidth);
+    const bool mail = width_host && ctx->mail_dev && !ctx->capturing;
+    const int64_t seq = mail ? ++ctx->mail_seq : 0;
+    hipLaunchKernelGGL(hk::merge_scan_kernel, dim3(1), dim3(1024), 0, st, G, m1, col, dwidth,
+                       mail ? ctx->mail_dev : nullptr, seq);
     HCHK(hipGetLastError());
-    if (width_host) {
+    if (mail) {
+        // spin on the mailbox (the kernel's release store of seq follows the
+        // width); now and then ask the stream whether it failed or finished
+        volatile int64_t *mb = ctx->mail_host;
+        for (uint64_t it = 1;; ++it) {
+            if (mb[1] == seq) break;
+            if ((it & 4095) == 0) {
+                const hipError_t q = hipStreamQuery(st);
+                if (q == hipSuccess) {
+                    if (mb[1] == seq) break;
+                    return fail(HALIGN_E_DEVICE, "merge scan finished without its width");
+                }
+                if (q != hipErrorNotReady) return fail(HALIGN_E_DEVICE, "%s", hipGetErrorString(q));
+            }
+        }
+        __atomic_thread_fence(__ATOMIC_ACQUIRE);
+        *width_host = mb[0];
+    } else if (width_host) {
         HCHK(hipMemcpyAsync(width_host, dwidth, 8, hipMemcpyDeviceToHost, st));
         HCHK(hipStreamSynchronize(st));
     }

@@ -127,7 +127,11 @@ __global__ void merge_max_kernel(const uint16_t *ins, int n, int m1, int32_t *G)
 }
 
 // col[p] = sum_{q<p} (G[q] + 1); width = m + sum G.  One workgroup of 1024.
-__global__ void __launch_bounds__(1024) merge_scan_kernel(const int32_t *G, int m1, int64_t *col, int64_t *width) {
+// mail (optional, host memory mapped for the device): mail[0] = width, then
+// mail[1] = seq with a system-scope release, so a host spinning on mail[1]
+// reads the width without a stream synchronisation
+__global__ void __launch_bounds__(1024) merge_scan_kernel(const int32_t *G, int m1, int64_t *col, int64_t *width,
+                                                          int64_t *mail, int64_t seq) {
     __shared__ int64_t part[1024];
     const int tid = threadIdx.x;
     const int per = (m1 + 1023) / 1024;
@@ -144,7 +148,13 @@ __global__ void __launch_bounds__(1024) merge_scan_kernel(const int32_t *G, int 
     }
     int64_t acc = tid > 0 ? part[tid - 1] : 0;
     for (int p = lo; p < hi; ++p) { col[p] = acc; acc += G[p] + 1; }
-    if (tid == 1023) *width = part[1023] - 1;
+    if (tid == 1023) {
+        *width = part[1023] - 1;
+        if (mail) {
+            __hip_atomic_store(mail, part[1023] - 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+            __hip_atomic_store(mail + 1, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+    }
 }
 
 // Rows: one wavefront per row, up to four wavefronts per workgroup, each
