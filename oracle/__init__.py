@@ -65,6 +65,14 @@ def lib():
             getattr(L, fn).restype = ctypes.c_int64
         L.orc_encode.argtypes = [P, ctypes.c_int64, P]
         L.orc_encode.restype = None
+        L.orc_nuc_matches.argtypes = [P, I, P, I, I, P, P, I]
+        L.orc_nuc_matches.restype = I
+        L.orc_nuc_chain.argtypes = [P, P, I, I, P]
+        L.orc_nuc_chain.restype = I
+        L.orc_nuc_align.argtypes = [P, I, I, I, I, P, I, P, I, P, P, P, P]
+        L.orc_nuc_align.restype = I
+        L.orc_nuc_msa.argtypes = [P, I, I, I, I, P, P, I, P, P, P, P, P, P]
+        L.orc_nuc_msa.restype = I
         L.orc_column_profile.argtypes = [P, I, ctypes.c_int64, I, P]
         L.orc_column_profile.restype = I
         L.orc_sp_blosum.argtypes = [P, I, I, P, I, ctypes.c_int64]
@@ -254,3 +262,60 @@ def sp_blosum(S, ge: int, msa_rows: np.ndarray) -> int:
     S = _mat(S)
     a = _u8(msa_rows)
     return int(lib().orc_sp_blosum(_p(S), S.shape[0], ge, _p(a), a.shape[0], a.shape[1]))
+
+
+# ---------------------------------------------------------------------------
+# Nucleotide center star (trie section): segments, matches, anchor chain,
+# global alignment of the unmatched stretches
+# ---------------------------------------------------------------------------
+def nuc_matches(c, s, k: int):
+    """(q, p) arrays: every match of an indexed center segment in s, by p."""
+    c, s = _u8(c), _u8(s)
+    cap = len(s) + 1
+    mq = np.zeros(cap, np.int32)
+    mp = np.zeros(cap, np.int32)
+    a = _check(lib().orc_nuc_matches(_p(c), len(c), _p(s), len(s), k, _p(mq), _p(mp), cap))
+    return mq[:a].copy(), mp[:a].copy()
+
+
+def nuc_chain(mq, mp, k: int) -> np.ndarray:
+    """Indices of the anchor chain among the matches (mq, mp)."""
+    mq = np.ascontiguousarray(mq, np.int32)
+    mp = np.ascontiguousarray(mp, np.int32)
+    ch = np.zeros(max(1, len(mq)), np.int32)
+    n = _check(lib().orc_nuc_chain(_p(mq), _p(mp), len(mq), k, _p(ch)))
+    return ch[:n].copy()
+
+
+def nuc_align(S, go: int, ge: int, k: int, c, s):
+    """Pairwise nucleotide center-star alignment: dict(score, ins, aligned, anchors)."""
+    S = _mat(S)
+    c, s = _u8(c), _u8(s)
+    m = len(c)
+    ins = np.zeros(m + 1, np.uint16)
+    al = np.zeros(max(m, 1), np.uint8)
+    sc = ctypes.c_int32(0)
+    na = ctypes.c_int32(0)
+    _check(lib().orc_nuc_align(_p(S), S.shape[0], go, ge, k, _p(c), m, _p(s), len(s), ctypes.byref(sc), _p(ins),
+                               _p(al), ctypes.byref(na)))
+    return dict(score=int(sc.value), ins=ins, aligned=al[:m].copy(), anchors=int(na.value))
+
+
+def nuc_msa(S, go: int, ge: int, k: int, residues, offsets):
+    """Nucleotide MSA with sequence 0 as the center: dict of every stage's output."""
+    S = _mat(S)
+    res = _u8(residues)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    N = len(off) - 1
+    m = int(off[1] - off[0])
+    score = np.zeros(N, np.int32)
+    ins = np.zeros((N, m + 1), np.uint16)
+    al = np.zeros((N, max(m, 1)), np.uint8)
+    G = np.zeros(m + 1, np.int32)
+    col = np.zeros(m + 1, np.int64)
+    W = ctypes.c_int64(0)
+    _check(lib().orc_nuc_msa(_p(S), S.shape[0], go, ge, k, _p(res), _p(off), N, _p(score), _p(ins), _p(al), _p(G),
+                             _p(col), ctypes.byref(W)))
+    al = al[:, :m].copy()
+    msa_rows = rows(res, off, ins, al, G, int(W.value))
+    return dict(score=score, ins=ins, aligned=al, G=G, col=col, width=int(W.value), msa=msa_rows)

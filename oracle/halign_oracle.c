@@ -447,3 +447,280 @@ int64_t orc_sp_blosum(const int8_t *S, int alpha, int ge, const uint8_t *msa, in
             }
     return total;
 }
+
+/* ========================================================================
+ * Nucleotide center star (Methods, "Trie trees method for similar
+ * nucleotide sequences"): the first sequence is the center; a trie of the
+ * center's segments with failure links finds the segments that recur in
+ * each sequence; those matched segments are kept as they are and only the
+ * unmatched stretches between them are aligned.
+ *
+ * Readings of the paper (it gives no parameters):
+ *  - Segments: the center is cut into consecutive segments of k residues
+ *    (segment q covers c[q*k, q*k + k)); a segment is indexed when it holds
+ *    only codes 0..3 (A, C, G, T) and no other indexed segment has the same
+ *    string.  The trailing partial segment is never indexed.
+ *  - Matches: every (q, p) with s[p, p + k) equal to indexed segment q (the
+ *    trie with failure links, Aho-Corasick, reports them in order of p;
+ *    a byte >= 4 in s returns the automaton to its root).
+ *  - Anchors: a chain of matches strictly increasing in q with
+ *    p_next >= p + k, of the largest size.  best[i] = 1 + max best[j] over
+ *    earlier matches j (p_j + k <= p_i, q_j < q_i); the predecessor of i is,
+ *    among those j with best[j] = best[i] - 1, the one with the smallest
+ *    (q_j, p_j); the chain ends at the match with the largest best, ties to
+ *    the smallest (q, p).
+ *  - Between anchors (and before the first and after the last), the center
+ *    stretch and the sequence stretch are aligned end to end with affine
+ *    gaps (Gotoh's global form, W_k = go + ge*k, the same traceback
+ *    priorities as the local alignment: diagonal, then s residue against a
+ *    gap, then center residue against a gap; a gap is followed back to the
+ *    shortest length reaching the value).
+ *  - Output: the same center-star vector as the protein path (ins[m+1]
+ *    slots, aligned[m]), so the merge and the rows are unchanged; score =
+ *    sum of S over the anchors' residues plus the stretches' global scores.
+ * ====================================================================== */
+
+/* Trie (goto function over codes 0..3) of the indexed segments with failure
+ * links; node 0 is the root.  out[v] = segment ending at node v, or -1. */
+typedef struct { int32_t *go; int32_t *fail; int32_t *out; int nn; } orc_trie;
+
+static void orc_trie_free(orc_trie *t) { free(t->go); free(t->fail); free(t->out); }
+
+/* Indexed segments of c: idx[q] = 1 when segment q is indexed. */
+static int orc_nuc_index(const uint8_t *c, int m, int k, uint8_t *idx)
+{
+    const int ns = k > 0 ? m / k : 0;
+    for (int q = 0; q < ns; q++) {
+        idx[q] = 1;
+        for (int t = 0; t < k; t++) if (c[q * k + t] > 3) { idx[q] = 0; break; }
+    }
+    for (int q = 0; q < ns; q++) {
+        if (!idx[q]) continue;
+        for (int r = q + 1; r < ns; r++)
+            if (idx[r] && memcmp(c + q * k, c + r * k, (size_t)k) == 0) {
+                /* a repeated segment string is dropped everywhere */
+                for (int x = r; x < ns; x++)
+                    if (x != q && memcmp(c + q * k, c + x * k, (size_t)k) == 0) idx[x] = 2;
+                idx[q] = 2;
+                break;
+            }
+    }
+    for (int q = 0; q < ns; q++) if (idx[q] == 2) idx[q] = 0;
+    return ns;
+}
+
+static int orc_trie_build(const uint8_t *c, int m, int k, orc_trie *t)
+{
+    const int ns = k > 0 ? m / k : 0;
+    uint8_t *idx = (uint8_t *)calloc((size_t)ns + 1, 1);
+    const int cap = ns * k + 1;
+    t->go = (int32_t *)malloc(sizeof(int32_t) * 4 * (size_t)cap);
+    t->fail = (int32_t *)calloc((size_t)cap, sizeof(int32_t));
+    t->out = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    int32_t *queue = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    if (!idx || !t->go || !t->fail || !t->out || !queue) {
+        free(idx); free(queue); orc_trie_free(t); return ORC_ENOMEM;
+    }
+    orc_nuc_index(c, m, k, idx);
+    for (int v = 0; v < cap; v++) { t->out[v] = -1; for (int a = 0; a < 4; a++) t->go[4 * v + a] = -1; }
+    int nn = 1;
+    for (int q = 0; q < ns; q++) {
+        if (!idx[q]) continue;
+        int v = 0;
+        for (int d = 0; d < k; d++) {
+            int a = c[q * k + d];
+            if (t->go[4 * v + a] < 0) t->go[4 * v + a] = nn++;
+            v = t->go[4 * v + a];
+        }
+        t->out[v] = q;
+    }
+    /* failure links by breadth-first order; missing edges become the
+     * failure target's edges (the goto function of the automaton) */
+    int head = 0, tail = 0;
+    for (int a = 0; a < 4; a++) {
+        int u = t->go[a];
+        if (u < 0) t->go[a] = 0;
+        else { t->fail[u] = 0; queue[tail++] = u; }
+    }
+    while (head < tail) {
+        int v = queue[head++];
+        for (int a = 0; a < 4; a++) {
+            int u = t->go[4 * v + a];
+            if (u < 0) { t->go[4 * v + a] = t->go[4 * t->fail[v] + a]; continue; }
+            t->fail[u] = t->go[4 * t->fail[v] + a];
+            queue[tail++] = u;
+        }
+    }
+    t->nn = nn;
+    free(idx); free(queue);
+    return ORC_OK;
+}
+
+/* All matches (q, p) of the indexed center segments in s, in order of p.
+ * Returns the number of matches (at most cap are written), or an error. */
+int orc_nuc_matches(const uint8_t *c, int m, const uint8_t *s, int n, int k,
+                    int32_t *mq, int32_t *mp, int cap)
+{
+    if (k < 1 || m < 0 || n < 0) return ORC_EINVAL;
+    orc_trie t;
+    int r = orc_trie_build(c, m, k, &t);
+    if (r < 0) return r;
+    int v = 0, cnt = 0;
+    for (int j = 0; j < n; j++) {
+        if (s[j] > 3) { v = 0; continue; }
+        v = t.go[4 * v + s[j]];
+        /* all segments have length k, so only the node itself can end one
+         * (a shorter suffix along the failure chain is never a segment) */
+        if (t.out[v] >= 0) {
+            if (cnt < cap) { mq[cnt] = t.out[v]; mp[cnt] = j - k + 1; }
+            cnt++;
+        }
+    }
+    orc_trie_free(&t);
+    return cnt;
+}
+
+/* Anchor chain over matches (mq, mp) in order of p (the reading above).
+ * chain[] receives the chosen match indices in increasing order; returns
+ * the chain length. */
+int orc_nuc_chain(const int32_t *mq, const int32_t *mp, int a, int k, int32_t *chain)
+{
+    if (a <= 0) return 0;
+    int32_t *best = (int32_t *)malloc(sizeof(int32_t) * (size_t)a);
+    int32_t *pred = (int32_t *)malloc(sizeof(int32_t) * (size_t)a);
+    if (!best || !pred) { free(best); free(pred); return ORC_ENOMEM; }
+    for (int i = 0; i < a; i++) {
+        int b = 0;
+        for (int j = 0; j < i; j++)
+            if (mp[j] + k <= mp[i] && mq[j] < mq[i] && best[j] > b) b = best[j];
+        best[i] = b + 1;
+        pred[i] = -1;
+        for (int j = 0; j < i; j++) {
+            if (mp[j] + k > mp[i] || mq[j] >= mq[i] || best[j] != b) continue;
+            if (pred[i] < 0 || mq[j] < mq[pred[i]] || (mq[j] == mq[pred[i]] && mp[j] < mp[pred[i]])) pred[i] = j;
+        }
+    }
+    int e = 0;
+    for (int i = 1; i < a; i++)
+        if (best[i] > best[e] || (best[i] == best[e] && (mq[i] < mq[e] || (mq[i] == mq[e] && mp[i] < mp[e])))) e = i;
+    const int len = best[e];
+    for (int x = len - 1, i = e; x >= 0; x--, i = pred[i]) chain[x] = i;
+    free(best); free(pred);
+    return len;
+}
+
+/* Global affine alignment of c[0, mc) against s[0, nc) (Gotoh, end to end):
+ * H(0,0) = 0, H(i,0) = F(i,0) = -(go + ge*i), H(0,j) = E(0,j) = -(go + ge*j).
+ * Writes the moves into the center-star vector at center offset cb and
+ * returns the score. */
+static int orc_global(const int8_t *S, int alpha, int go, int ge, const uint8_t *c, int mc, const uint8_t *s,
+                      int nc, int cb, uint16_t *ins, uint8_t *aligned, int *err)
+{
+    const size_t ld = (size_t)nc + 1, sz = ((size_t)mc + 1) * ld;
+    int32_t *H = (int32_t *)malloc(sizeof(int32_t) * sz);
+    int32_t *E = (int32_t *)malloc(sizeof(int32_t) * sz);
+    int32_t *F = (int32_t *)malloc(sizeof(int32_t) * sz);
+    if (!H || !E || !F) { free(H); free(E); free(F); *err = ORC_ENOMEM; return 0; }
+    const int goe = go + ge;
+    H[0] = 0; E[0] = ORC_NEG; F[0] = ORC_NEG;
+    for (int j = 1; j <= nc; j++) { H[j] = -(go + ge * j); E[j] = H[j]; F[j] = ORC_NEG; }
+    for (int i = 1; i <= mc; i++) {
+        int32_t *Hi = H + (size_t)i * ld, *Ei = E + (size_t)i * ld, *Fi = F + (size_t)i * ld;
+        const int32_t *Hu = Hi - ld, *Fu = Fi - ld;
+        Hi[0] = -(go + ge * i); Ei[0] = ORC_NEG; Fi[0] = Hi[0];
+        for (int j = 1; j <= nc; j++) {
+            int e = imax(Ei[j - 1] - ge, Hi[j - 1] - goe);
+            int f = imax(Fu[j] - ge, Hu[j] - goe);
+            int h = imax(Hu[j - 1] + S[c[i - 1] * alpha + s[j - 1]], imax(e, f));
+            Ei[j] = e; Fi[j] = f; Hi[j] = h;
+        }
+    }
+    const int score = H[(size_t)mc * ld + nc];
+    int i = mc, j = nc;
+    enum { ST_H, ST_E, ST_F } st = ST_H;
+    while (i > 0 || j > 0) {
+        const size_t at = (size_t)i * ld + j;
+        if (st == ST_H) {
+            if (i > 0 && j > 0 && H[at] == H[at - ld - 1] + S[c[i - 1] * alpha + s[j - 1]]) {
+                aligned[cb + i - 1] = 1;
+                i--; j--;
+            } else if (H[at] == E[at]) {
+                st = ST_E;
+            } else {
+                st = ST_F;
+            }
+        } else if (st == ST_E) {
+            ins[cb + i] += 1;   /* s_j after c_{cb+i}: slot cb + i */
+            int ext = j > 1 && E[at - 1] - ge > H[at - 1] - goe;
+            j--;
+            if (!ext) st = ST_H;
+        } else {
+            int ext = i > 1 && F[at - ld] - ge > H[at - ld] - goe;
+            i--;
+            if (!ext) st = ST_H;
+        }
+    }
+    free(H); free(E); free(F);
+    return score;
+}
+
+/* Pairwise nucleotide center-star alignment of s against center c.
+ * ins[m+1], aligned[m] (zeroed here); *nanchors (may be NULL) receives the
+ * chain length.  Returns 0 and the score in *score, or a negative error. */
+int orc_nuc_align(const int8_t *S, int alpha, int go, int ge, int k,
+                  const uint8_t *c, int m, const uint8_t *s, int n,
+                  int32_t *score, uint16_t *ins, uint8_t *aligned, int32_t *nanchors)
+{
+    if (k < 1 || m < 0 || n < 0 || alpha < 5) return ORC_EINVAL;
+    for (int i = 0; i < m; i++) if (c[i] >= alpha) return ORC_EINVAL;
+    for (int j = 0; j < n; j++) if (s[j] >= alpha) return ORC_EINVAL;
+    memset(ins, 0, sizeof(uint16_t) * ((size_t)m + 1));
+    memset(aligned, 0, (size_t)m);
+    const int cap = n + 1;
+    int32_t *mq = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    int32_t *mp = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    int32_t *ch = (int32_t *)malloc(sizeof(int32_t) * (size_t)cap);
+    if (!mq || !mp || !ch) { free(mq); free(mp); free(ch); return ORC_ENOMEM; }
+    int a = orc_nuc_matches(c, m, s, n, k, mq, mp, cap);
+    int len = a < 0 ? a : orc_nuc_chain(mq, mp, a, k, ch);
+    if (len < 0) { free(mq); free(mp); free(ch); return len; }
+    int total = 0, err = 0, ci = 0, sj = 0;   /* next unaligned center / sequence position */
+    for (int x = 0; x <= len && !err; x++) {
+        const int qc = x < len ? mq[ch[x]] * k : m;   /* stretch ends at the anchor (or the ends) */
+        const int ps = x < len ? mp[ch[x]] : n;
+        total += orc_global(S, alpha, go, ge, c + ci, qc - ci, s + sj, ps - sj, ci, ins, aligned, &err);
+        if (x < len) {
+            for (int t = 0; t < k; t++) {
+                aligned[qc + t] = 1;
+                total += S[c[qc + t] * alpha + s[ps + t]];
+            }
+            ci = qc + k;
+            sj = ps + k;
+        }
+    }
+    free(mq); free(mp); free(ch);
+    if (err) return err;
+    if (nanchors) *nanchors = len;
+    *score = total;
+    return ORC_OK;
+}
+
+/* Nucleotide MSA with sequence 0 as the center: every pair's vectors, then
+ * the merge (the center's own row is the gapped center). */
+int orc_nuc_msa(const int8_t *S, int alpha, int go, int ge, int k,
+                const uint8_t *res, const int64_t *off, int nseq,
+                int32_t *score, uint16_t *ins, uint8_t *aligned,
+                int32_t *G, int64_t *col, int64_t *width)
+{
+    if (nseq < 1) return ORC_EINVAL;
+    const uint8_t *c = res + off[0];
+    const int m = (int)(off[1] - off[0]);
+    for (int x = 0; x < nseq; x++) {
+        int r = orc_nuc_align(S, alpha, go, ge, k, c, m, res + off[x], (int)(off[x + 1] - off[x]),
+                              score + x, ins + (size_t)x * (m + 1), aligned + (size_t)x * m, NULL);
+        if (r < 0) return r;
+    }
+    memset(ins, 0, sizeof(uint16_t) * ((size_t)m + 1));
+    memset(aligned, 1, (size_t)m);
+    return orc_merge(ins, nseq, m, G, col, width);
+}

@@ -295,3 +295,76 @@ def random_set(rng: np.random.Generator, n_seqs: int, lo: int, hi: int,
     """Unrelated iid sequences with uniform lengths (edge-case tests)."""
     lens = rng.integers(lo, hi + 1, size=n_seqs)
     return SeqSet.from_list([rng.integers(0, alphabet, size=int(L)).astype(np.uint8) for L in lens])
+
+
+# ---------------------------------------------------------------------------
+# Nucleotide sets (the trie section's workload: similar genomes)
+# ---------------------------------------------------------------------------
+NUC_ALPHABET = "ACGTN"            # codes 0..4; N is never part of an anchor
+# BLASTN-style scores (the paper names none): +2 match, -3 mismatch, -1 for
+# any pair with N; gaps W_k = 5 + 2k
+NUC_MATRIX = np.array([[2 if (a == b and a < 4) else (-1 if (a == 4 or b == 4) else -3) for b in range(5)]
+                       for a in range(5)], dtype=np.int8)
+NUC_MATRIX.setflags(write=False)
+NUC_GAP_OPEN = 5
+NUC_GAP_EXTEND = 2
+NUC_K = 16                        # center segment length of the trie
+
+
+@dataclasses.dataclass(frozen=True)
+class DnaConfig:
+    name: str
+    n_seqs: int
+    root_len: int
+    p_sub: float
+    p_indel: float
+    p_n: float
+    seed: int
+
+
+DNA_CONFIGS = {
+    # 672 human mitochondrial genomes (Table 1: lengths 16,556-16,579) and the
+    # 100x replication; stand-ins: one random root, low divergence
+    "dna672": DnaConfig("dna672", 672, 16569, 0.003, 0.0002, 0.0, SEED_BASE + 10),
+    "dna67k": DnaConfig("dna67k", 67_200, 16569, 0.003, 0.0002, 0.0, SEED_BASE + 11),
+    # small, more divergent set with a few N codes (tests)
+    "dna_small": DnaConfig("dna_small", 48, 1500, 0.02, 0.004, 0.001, SEED_BASE + 12),
+}
+
+
+def generate_dna(cfg: DnaConfig | str, n_seqs: int | None = None, seed: int | None = None) -> SeqSet:
+    """Similar nucleotide sequences: one uniform ACGT root; each sequence
+    copies it with substitutions (probability p_sub, to a different base),
+    then indels starting at each position with probability p_indel (half
+    insertions of uniform bases before the position, half deletions),
+    geometric(0.5) lengths, then N codes at rate p_n.  Sequence 0 is a copy
+    like the others (it becomes the center)."""
+    if isinstance(cfg, str):
+        cfg = DNA_CONFIGS[cfg]
+    n_seqs = cfg.n_seqs if n_seqs is None else n_seqs
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(cfg.seed if seed is None else seed)))
+    root = rng.integers(0, 4, cfg.root_len).astype(np.uint8)
+    L = cfg.root_len
+    seqs = []
+    for _ in range(n_seqs):
+        b = root.copy()
+        hit = np.nonzero(rng.random(L) < cfg.p_sub)[0]
+        b[hit] = (b[hit] + rng.integers(1, 4, len(hit))) % 4
+        ev = np.nonzero(rng.random(L) < cfg.p_indel)[0]
+        is_ins = rng.random(len(ev)) < 0.5
+        elen = rng.geometric(0.5, size=len(ev))
+        keep = np.ones(L, bool)
+        for pos, ln in zip(ev[~is_ins], elen[~is_ins]):
+            keep[pos:pos + ln] = False
+        parts, last = [], 0
+        for pos, ln in zip(ev[is_ins], elen[is_ins]):
+            parts.append(b[last:pos][keep[last:pos]])
+            if keep[pos]:
+                parts.append(rng.integers(0, 4, int(ln)).astype(np.uint8))
+            last = pos
+        parts.append(b[last:][keep[last:]])
+        x = np.concatenate(parts).astype(np.uint8)
+        if cfg.p_n > 0:
+            x[rng.random(len(x)) < cfg.p_n] = 4
+        seqs.append(x)
+    return SeqSet.from_list(seqs)
