@@ -357,6 +357,34 @@ int halign_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seq
                halign_alloc_fn alloc, void *user,
                uint8_t **msa, int64_t *width_host, int32_t *center_out_host, void *stream);
 
+/* ---- nucleotide center star (Methods, trie section) -------------------------
+ * Similar nucleotide sequences: the center's segments of k bases (segment q =
+ * center[q*k, q*k + k), codes 0..3 = A C G T only, and no other such segment
+ * with the same string) are found in every sequence (the paper's trie with
+ * failure links reports every occurrence; here a hash table of the packed
+ * segments gives the same set), the largest chain of matches increasing in q
+ * with non-overlapping positions p (p_next >= p + k) becomes the anchors
+ * (predecessor and end chosen by the smallest (q, p) among equals), and the
+ * stretches before, between and after the anchors are aligned end to end with
+ * affine gaps W_k = gap_open + gap_extend*k (Gotoh's global form, traceback
+ * priorities as for the local alignment).  Codes >= 4 never join an anchor.
+ * alphabet >= 5; 1 <= k <= 32.
+ * score: device int32 [N] (anchor residues' scores plus the stretches' global
+ * scores); ins [N][m+1], aligned [N][(m+31)/32] as in halign_sw_batch; G:
+ * optional device int32 [m+1], the merge (max of ins over all sequences but
+ * the center).  Scratch lives in the ctx; the call synchronises (the match
+ * counts and stretch sizes size it). */
+int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+                     int32_t center, int32_t k, int32_t *score, uint16_t *ins, uint32_t *aligned,
+                     int32_t *G, void *stream);
+
+/* Nucleotide MSA with the given center (the paper takes the first sequence):
+ * halign_nuc_align, the center's own row, the merge and the rows, as
+ * halign_msa does for proteins.  score: device int32 [N]. */
+int halign_nuc_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs,
+                   int32_t center, int32_t k, int32_t *score, halign_alloc_fn alloc, void *user,
+                   uint8_t **msa, int64_t *width_host, void *stream);
+
 /* ---- evaluation (Results: avg SP) ------------------------------------------
  * out_host[0] = sum over row pairs and columns of: 1 for two different
  * residues, 2 for a residue against a gap, 0 otherwise (avg SP = out/C(N,2));

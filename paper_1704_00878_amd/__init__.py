@@ -113,6 +113,8 @@ def lib():
         "halign_train_proposer": ([P, P, P, P, P, P, P], I),
         "halign_center_learned": ([P, P, P, P, I, P, P, P], I),
         "halign_msa": ([P, P, P, I, P, _ALLOC_FN, P, P, P, P, P], I),
+        "halign_nuc_align": ([P, P, P, I, I, P, P, P, P, P], I),
+        "halign_nuc_msa": ([P, P, P, I, I, P, _ALLOC_FN, P, P, P, P], I),
         "halign_sp_score": ([P, P, I, I64, P, P], I),
         "halign_column_profile": ([P, I, I64, I, P, P], I),
     }
@@ -347,6 +349,34 @@ def halign_msa(ctx: Context, sc: Scoring, seqs: DeviceSeqs, center: int, model=N
     W = int(width.value)
     t = keep["t"][: seqs.n * W].view(seqs.n, W)
     return t, int(cout.value)
+
+
+def halign_nuc_align(ctx: Context, sc: Scoring, seqs: DeviceSeqs, center: int, k: int, score, ins, aligned, G=None,
+                     stream=None):
+    _check(lib().halign_nuc_align(ctx.h, sc.ref, seqs.ref, center, k, _ptr(score), _ptr(ins), _ptr(aligned), _ptr(G),
+                                  _stream(stream)))
+
+
+def halign_nuc_msa(ctx: Context, sc: Scoring, seqs: DeviceSeqs, k: int, center: int = 0, stream=None, out=None):
+    """Nucleotide center-star MSA (trie section).  Returns (msa uint8 [N, W], score int32 [N])."""
+    import torch
+    keep = {}
+
+    def _alloc(nbytes, user):
+        if out is not None and out.dtype == torch.uint8 and out.is_contiguous() and out.numel() >= nbytes:
+            keep["t"] = out.view(-1)
+        else:
+            keep["t"] = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=f"cuda:{ctx.device}")
+        return keep["t"].data_ptr()
+
+    cb = _ALLOC_FN(_alloc)
+    score = torch.empty(seqs.n, dtype=torch.int32, device=f"cuda:{ctx.device}")
+    out_ptr = ctypes.c_void_p()
+    width = ctypes.c_int64(0)
+    _check(lib().halign_nuc_msa(ctx.h, sc.ref, seqs.ref, center, k, _ptr(score), cb, None, ctypes.byref(out_ptr),
+                                ctypes.byref(width), _stream(stream)))
+    W = int(width.value)
+    return keep["t"][: seqs.n * W].view(seqs.n, W), score
 
 
 # ---------------------------------------------------------------------------

@@ -27,6 +27,7 @@
 #include "plan_kernels.hpp"
 #include "strip_kernels.hpp"
 #include "walk_kernels.hpp"
+#include "nuc_kernels.hpp"
 #include "mlp_kernels.hpp"
 
 namespace {
@@ -113,6 +114,7 @@ struct halign_ctx {
     std::string tune_file;    // optional cache file (HALIGN_TUNE_CACHE)
     int *flag_host = nullptr; // pinned: (tag << 8 | largest residue code) of the last validated call
     int64_t *mail_host = nullptr, *mail_dev = nullptr;   // coherent pinned mailbox: width, sequence number
+    DevBuf nuctab, nucscr, nucdp;   // nucleotide path: segment table, matches and chains, stretch scratch
     int64_t mail_seq = 0;
     uint32_t vtag = 0;        // tag of the last eager code check
     uint32_t check_tag = 0;   // tag validate_check expects (0 after a graph replay)
@@ -1141,7 +1143,8 @@ void halign_ctx_destroy(halign_ctx *ctx) {
     (void)hipDeviceSynchronize();
     graph_drop(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
-    for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf, &ctx->sbuf})
+    for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf,
+                      &ctx->sbuf, &ctx->nuctab, &ctx->nucscr, &ctx->nucdp})
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : ctx->mlp)
         if (b.p) (void)hipFree(b.p);
@@ -2536,6 +2539,206 @@ int halign_center_learned(halign_ctx *ctx, const halign_scoring *sc, const halig
         HCHK(hipStreamSynchronize(st));
     }
     *center_host = c;
+    return HALIGN_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Nucleotide center star (trie section)
+// ===========================================================================
+namespace {
+
+uint32_t nuc_hash_host(unsigned long long key, int lg_t) {
+    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - lg_t));
+}
+
+// exclusive sums of n int64 values (+ add each) into out; *total_host
+int scan_i64(halign_ctx *ctx, const int64_t *in, int n, int64_t add, int64_t *out, int64_t *total_host,
+             hipStream_t st) {
+    RCHK(grow(ctx, ctx->spbuf, 4096));
+    int64_t *dtot = (int64_t *)((char *)ctx->spbuf.p + 2048 + 64);
+    hipLaunchKernelGGL(hk::scan_i64_kernel, dim3(1), dim3(1024), 0, st, in, n, add, out, dtot);
+    HCHK(hipGetLastError());
+    HCHK(hipMemcpyAsync(total_host, dtot, 8, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    return HALIGN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, int32_t center, int32_t k,
+                     int32_t *score, uint16_t *ins, uint32_t *aligned, int32_t *G, void *stream) {
+    if (!ctx || !score || !ins || !aligned) return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_scoring(sc));
+    RCHK(check_seqs(seqs));
+    if (sc->alphabet < 5) return fail(HALIGN_E_UNSUPPORTED, "nucleotide alphabet needs codes 0..4 (A C G T other)");
+    if (k < 1 || k > 32) return fail(HALIGN_E_UNSUPPORTED, "segment length %d outside 1..32", k);
+    const int N = seqs->n;
+    if (center < 0 || center >= N) return fail(HALIGN_E_INVALID, "center %d of %d", center, N);
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t *oh = seqs->offsets_host;
+    const int m = (int)(oh[center + 1] - oh[center]);
+    const uint8_t *dc = seqs->residues + oh[center];
+    Scoring S;
+    RCHK(upload_matrix(ctx, sc, st, &S));
+    RCHK(validate_now(ctx, sc->alphabet, seqs->residues, oh[N], nullptr, 0, st));
+    // the center's segments, on the host: segment q (k codes 0..3) is indexed
+    // when no other such segment has the same string
+    std::vector<uint8_t> c(m);
+    if (m > 0) {
+        HCHK(hipMemcpyAsync(c.data(), dc, m, hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+    }
+    const int nsg = m / k;
+    std::vector<unsigned long long> key(nsg);
+    std::vector<int32_t> segscore(std::max(nsg, 1), 0);
+    std::vector<uint8_t> clean(nsg, 1);
+    for (int q = 0; q < nsg; ++q) {
+        unsigned long long kk = 0;
+        for (int t = 0; t < k; ++t) {
+            const int b = c[q * k + t];
+            if (b > 3) clean[q] = 0;
+            kk = (kk << 2) | (unsigned long long)(b & 3);
+            segscore[q] += sc->matrix_host[b * sc->alphabet + b];
+        }
+        key[q] = kk;
+    }
+    std::map<unsigned long long, int> seen;
+    for (int q = 0; q < nsg; ++q)
+        if (clean[q]) seen[key[q]]++;
+    int nidx = 0;
+    for (int q = 0; q < nsg; ++q)
+        if (clean[q] && seen[key[q]] == 1) ++nidx;
+    int lg_t = 6;
+    while ((1 << lg_t) < 2 * nidx) ++lg_t;
+    const int T = 1 << lg_t;
+    std::vector<unsigned long long> tkey(T, 0);
+    std::vector<int32_t> tseg(T, -1);
+    for (int q = 0; q < nsg; ++q) {
+        if (!clean[q] || seen[key[q]] != 1) continue;
+        uint32_t h = nuc_hash_host(key[q], lg_t);
+        while (tseg[h] >= 0) h = (h + 1) & (T - 1);
+        tkey[h] = key[q];
+        tseg[h] = q;
+    }
+    // device: table, scores, per-sequence counters
+    const size_t o_tk = 0, o_ts = o_tk + 8 * (size_t)T, o_ss = o_ts + 4 * (size_t)T,
+                 o_nm = (o_ss + 4 * segscore.size() + 255) & ~(size_t)255, o_w = o_nm + 4 * (size_t)N + 256,
+                 o_mo = o_w + 8 * (size_t)N, o_nc = o_mo + 8 * (size_t)N, o_rl = o_nc + 4 * (size_t)N + 256,
+                 o_cl = o_rl + 8 * (size_t)N, o_ro = o_cl + 8 * (size_t)N, o_co = o_ro + 8 * (size_t)N,
+                 tab_bytes = o_co + 8 * (size_t)N;
+    RCHK(grow(ctx, ctx->nuctab, tab_bytes));
+    char *tb = (char *)ctx->nuctab.p;
+    HCHK(hipMemcpyAsync(tb + o_tk, tkey.data(), 8 * (size_t)T, hipMemcpyHostToDevice, st));
+    HCHK(hipMemcpyAsync(tb + o_ts, tseg.data(), 4 * (size_t)T, hipMemcpyHostToDevice, st));
+    HCHK(hipMemcpyAsync(tb + o_ss, segscore.data(), 4 * segscore.size(), hipMemcpyHostToDevice, st));
+    const int aw = (m + 31) / 32;
+    {   // zero the vectors (ins as words plus an odd tail) and G
+        const int64_t n16 = (int64_t)N * (m + 1);
+        hk::ZeroArgs z{};
+        z.p[0] = (uint32_t *)ins;
+        z.n[0] = n16 / 2;
+        z.p[1] = aligned;
+        z.n[1] = (int64_t)N * aw;
+        z.p[2] = (uint32_t *)G;
+        z.n[2] = G ? m + 1 : 0;
+        z.tail16 = (n16 & 1) ? ins + (n16 - 1) : nullptr;
+        hipLaunchKernelGGL(hk::zero_kernel, dim3(grid_for(z.n[0] + z.n[1], 256, 4096)), dim3(256), 0, st, z);
+        HCHK(hipGetLastError());
+    }
+    hk::NucArgs a{};
+    a.res = seqs->residues;
+    a.off = seqs->offsets;
+    a.nseq = N;
+    a.center = dc;
+    a.m = m;
+    a.k = k;
+    a.tkey = (const unsigned long long *)(tb + o_tk);
+    a.tseg = (const int32_t *)(tb + o_ts);
+    a.lg_t = lg_t;
+    a.segscore = (const int32_t *)(tb + o_ss);
+    a.mat = S.dmat;
+    a.alpha = S.alpha;
+    a.go = S.goe - S.ge;
+    a.ge = S.ge;
+    a.nmatch = (int32_t *)(tb + o_nm);
+    a.score = score;
+    a.ins = ins;
+    a.aligned = aligned;
+    a.aw = aw;
+    a.G = G;
+    a.gskip = center;
+    const dim3 grid((unsigned)((N + 255) / 256));
+    hipLaunchKernelGGL(hk::nuc_count_kernel, grid, dim3(256), 0, st, a);
+    HCHK(hipGetLastError());
+    // matches: moff[x] = sum of counts before x; chain table adds one entry per sequence
+    hipLaunchKernelGGL(hk::widen_kernel, grid, dim3(256), 0, st, (const int32_t *)(tb + o_nm), N, (int64_t *)(tb + o_w));
+    int64_t nmt = 0;
+    RCHK(scan_i64(ctx, (const int64_t *)(tb + o_w), N, 0, (int64_t *)(tb + o_mo), &nmt, st));
+    const size_t s_mq = 0, s_mp = s_mq + 4 * (size_t)nmt, s_mb = s_mp + 4 * (size_t)nmt,
+                 s_pr = s_mb + 4 * (size_t)nmt, s_tl = s_pr + 4 * (size_t)nmt,
+                 scr_bytes = s_tl + 4 * ((size_t)nmt + N) + 256;
+    RCHK(grow(ctx, ctx->nucscr, scr_bytes));
+    char *sb = (char *)ctx->nucscr.p;
+    a.moff = (const int64_t *)(tb + o_mo);
+    a.mq = (int32_t *)(sb + s_mq);
+    a.mp = (int32_t *)(sb + s_mp);
+    a.mbest = (int32_t *)(sb + s_mb);
+    a.mpred = (int32_t *)(sb + s_pr);
+    a.tails = (int32_t *)(sb + s_tl);
+    a.nchain = (int32_t *)(tb + o_nc);
+    a.rowlen = (int64_t *)(tb + o_rl);
+    a.codelen = (int64_t *)(tb + o_cl);
+    hipLaunchKernelGGL(hk::nuc_chain_kernel, grid, dim3(256), 0, st, a);
+    HCHK(hipGetLastError());
+    int64_t nrow = 0, ncode = 0;
+    RCHK(scan_i64(ctx, a.rowlen, N, 0, (int64_t *)(tb + o_ro), &nrow, st));
+    RCHK(scan_i64(ctx, a.codelen, N, 0, (int64_t *)(tb + o_co), &ncode, st));
+    const size_t d_ro = 0, d_co = (8 * (size_t)nrow + 255) & ~(size_t)255, dp_bytes = d_co + 4 * (size_t)ncode + 256;
+    RCHK(grow(ctx, ctx->nucdp, dp_bytes));
+    a.rowoff = (const int64_t *)(tb + o_ro);
+    a.codeoff = (const int64_t *)(tb + o_co);
+    a.rows = (int2 *)((char *)ctx->nucdp.p + d_ro);
+    a.codes = (uint32_t *)((char *)ctx->nucdp.p + d_co);
+    hipLaunchKernelGGL(hk::nuc_align_kernel, grid, dim3(256), 0, st, a);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
+}
+
+int halign_nuc_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs *seqs, int32_t center, int32_t k,
+                   int32_t *score, halign_alloc_fn alloc, void *user, uint8_t **msa, int64_t *width_host,
+                   void *stream) {
+    if (!ctx || !alloc || !msa || !width_host || !score) return fail(HALIGN_E_INVALID, "bad arguments");
+    RCHK(check_seqs(seqs));
+    const int N = seqs->n;
+    if (center < 0 || center >= N) return fail(HALIGN_E_INVALID, "center %d of %d", center, N);
+    hipStream_t st = (hipStream_t)stream;
+    const int m = (int)(seqs->offsets_host[center + 1] - seqs->offsets_host[center]);
+    const int aw = (m + 31) / 32;
+    // vectors, G, col in the ctx's MSA scratch
+    const size_t o_ins = 0, o_al = (2 * (size_t)N * (m + 1) + 255) & ~(size_t)255,
+                 o_g = o_al + ((4 * (size_t)N * aw + 255) & ~(size_t)255), o_col = o_g + ((4 * (size_t)(m + 1) + 255) & ~(size_t)255),
+                 bytes = o_col + 8 * (size_t)(m + 1);
+    RCHK(grow(ctx, ctx->msabuf, bytes));
+    char *mb = (char *)ctx->msabuf.p;
+    uint16_t *ins = (uint16_t *)(mb + o_ins);
+    uint32_t *al = (uint32_t *)(mb + o_al);
+    int32_t *G = (int32_t *)(mb + o_g);
+    int64_t *col = (int64_t *)(mb + o_col);
+    RCHK(halign_nuc_align(ctx, sc, seqs, center, k, score, ins, al, G, stream));
+    hipLaunchKernelGGL(hk::center_row_kernel, dim3(1), dim3(256), 0, st, ins, al, center, m, aw);
+    HCHK(hipGetLastError());
+    int64_t width = 0;
+    RCHK(merge_offsets(ctx, G, m + 1, col, &width, st));
+    uint8_t *out = (uint8_t *)alloc((size_t)N * (size_t)width, user);
+    if (!out && width > 0) return fail(HALIGN_E_NOMEM, "allocator returned NULL for %lld bytes", (long long)(N * width));
+    RCHK(halign_emit_rows(ctx, seqs, m, ins, al, G, col, width, out, stream));
+    *msa = out;
+    *width_host = width;
     return HALIGN_OK;
 }
 
