@@ -79,6 +79,7 @@ struct halign_ctx {
     size_t cap = 0;          // workspace cap for codes + boundary rows (0 = none)
     int num_cu = 256;
     size_t lds_max = 65536;
+    size_t lds_cu = 65536;      // LDS of a CU: what one workgroup may take with the attribute set
     int last_pk = 0;          // the last batch ran the packed 16-bit wavefront kernel
     // device scratch
     DevBuf codes, bound, plan, counter, pairbuf, msabuf, spbuf, sbuf;
@@ -1115,6 +1116,15 @@ int halign_ctx_create(int device, size_t workspace_cap_bytes, halign_ctx **out) 
         ctx->lds_max = prop.maxSharedMemoryPerMultiProcessor ? prop.maxSharedMemoryPerMultiProcessor
                                                              : prop.sharedMemPerBlock;
         if (prop.sharedMemPerBlock && prop.sharedMemPerBlock < ctx->lds_max) ctx->lds_max = prop.sharedMemPerBlock;
+        // row emission of long centers takes up to the CU's LDS in one workgroup
+        const size_t cu = prop.maxSharedMemoryPerMultiProcessor;
+        if (cu > ctx->lds_max &&
+            hipFuncSetAttribute((const void *)hk::rows_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)cu) ==
+                hipSuccess)
+            ctx->lds_cu = cu;
+        else
+            ctx->lds_cu = ctx->lds_max;
+        (void)hipGetLastError();
     }
     if (hipHostMalloc((void **)&ctx->flag_host, 64, hipHostMallocDefault) != hipSuccess) {
         halign_ctx_destroy(ctx);
@@ -1536,7 +1546,7 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const 
     // LDS per wavefront: (m+1) block starts and counts, the aligned bits and
     // a chunk of ch columns
     const int m1 = m + 1, aw = (m + 31) / 32;
-    const size_t lim = std::min<size_t>(ctx->lds_max, 64 * 1024);
+    size_t lim = std::min<size_t>(ctx->lds_max, 64 * 1024);
     auto wave_bytes = [&](int ch) {
         const size_t head = (4 * (size_t)m1 + (((size_t)m1 * 2 + 3) & ~(size_t)3) + 4 * (size_t)aw + 15) & ~(size_t)15;
         return head + (size_t)ch + 32;
@@ -1544,6 +1554,7 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const 
     int ch = (int)std::min<int64_t>(8192, (width + 15) & ~(int64_t)15), wpb = hk::kWaveRows;
     while (ch > 1024 && (size_t)wpb * wave_bytes(ch) > lim) ch = ((ch / 2) + 15) & ~15;
     while (wpb > 1 && (size_t)wpb * wave_bytes(ch) > lim) --wpb;
+    if ((size_t)wpb * wave_bytes(ch) > lim && wave_bytes(ch) <= ctx->lds_cu) lim = ctx->lds_cu;   // long centers
     if ((size_t)wpb * wave_bytes(ch) > lim) return fail(HALIGN_E_UNSUPPORTED, "center length %d too long for row emission", m);
     if (width >= ((int64_t)1 << 31)) return fail(HALIGN_E_UNSUPPORTED, "MSA width %lld", (long long)width);
     const size_t gcb = 8 * (size_t)m1;
@@ -2549,21 +2560,31 @@ int halign_center_learned(halign_ctx *ctx, const halign_scoring *sc, const halig
 // ===========================================================================
 namespace {
 
-uint32_t nuc_hash_host(unsigned long long key, int lg_t) {
-    return (uint32_t)((key * 0x9E3779B97F4A7C15ull) >> (64 - lg_t));
-}
-
-// exclusive sums of n int64 values (+ add each) into out; *total_host
-int scan_i64(halign_ctx *ctx, const int64_t *in, int n, int64_t add, int64_t *out, int64_t *total_host,
-             hipStream_t st) {
-    RCHK(grow(ctx, ctx->spbuf, 4096));
-    int64_t *dtot = (int64_t *)((char *)ctx->spbuf.p + 2048 + 64);
-    hipLaunchKernelGGL(hk::scan_i64_kernel, dim3(1), dim3(1024), 0, st, in, n, add, out, dtot);
-    HCHK(hipGetLastError());
-    HCHK(hipMemcpyAsync(total_host, dtot, 8, hipMemcpyDeviceToHost, st));
+// exclusive sums of n int64 values (+ add each) into out, the total into
+// *total_dev (device, may be out + n) and *total_host
+int scan_i64(halign_ctx *ctx, const int64_t *in, int64_t n, int64_t add, int64_t *out, int64_t *total_dev,
+             int64_t *total_host, hipStream_t st) {
+    if (n <= hk::kScanTile) {
+        hipLaunchKernelGGL(hk::scan_i64_kernel, dim3(1), dim3(1024), 0, st, in, (int)n, add, out, total_dev);
+        HCHK(hipGetLastError());
+    } else {
+        const int64_t nt = (n + hk::kScanTile - 1) / hk::kScanTile;
+        if (nt > 0x7fffffff) return fail(HALIGN_E_UNSUPPORTED, "scan of %lld values", (long long)n);
+        RCHK(grow(ctx, ctx->sbuf, 16 * (size_t)nt + 256));
+        int64_t *part = (int64_t *)ctx->sbuf.p, *poff = part + nt;
+        hipLaunchKernelGGL(hk::scan_tile_kernel, dim3((unsigned)nt), dim3(1024), 0, st, in, n, add, out, part);
+        hipLaunchKernelGGL(hk::scan_i64_kernel, dim3(1), dim3(1024), 0, st, (const int64_t *)part, (int)nt,
+                           (int64_t)0, poff, total_dev);
+        hipLaunchKernelGGL(hk::scan_add_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, out, n,
+                           (const int64_t *)poff);
+        HCHK(hipGetLastError());
+    }
+    HCHK(hipMemcpyAsync(total_host, total_dev, 8, hipMemcpyDeviceToHost, st));
     HCHK(hipStreamSynchronize(st));
     return HALIGN_OK;
 }
+
+size_t al256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 }  // namespace
 
@@ -2620,22 +2641,30 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
     std::vector<int32_t> tseg(T, -1);
     for (int q = 0; q < nsg; ++q) {
         if (!clean[q] || seen[key[q]] != 1) continue;
-        uint32_t h = nuc_hash_host(key[q], lg_t);
+        uint32_t h = hk::nuc_hash(key[q], lg_t);
         while (tseg[h] >= 0) h = (h + 1) & (T - 1);
         tkey[h] = key[q];
         tseg[h] = q;
     }
-    // device: table, scores, per-sequence counters
-    const size_t o_tk = 0, o_ts = o_tk + 8 * (size_t)T, o_ss = o_ts + 4 * (size_t)T,
-                 o_nm = (o_ss + 4 * segscore.size() + 255) & ~(size_t)255, o_w = o_nm + 4 * (size_t)N + 256,
-                 o_mo = o_w + 8 * (size_t)N, o_nc = o_mo + 8 * (size_t)N, o_rl = o_nc + 4 * (size_t)N + 256,
-                 o_cl = o_rl + 8 * (size_t)N, o_ro = o_cl + 8 * (size_t)N, o_co = o_ro + 8 * (size_t)N,
-                 tab_bytes = o_co + 8 * (size_t)N;
+    // scan chunks: sequence x covers the match starts 0 .. n - k in chunks
+    std::vector<int64_t> cbase(N + 1, 0);
+    for (int x = 0; x < N; ++x) {
+        const int64_t w = std::max<int64_t>(0, oh[x + 1] - oh[x] - k + 1);
+        cbase[x + 1] = cbase[x] + (w + hk::kNucChunk - 1) / hk::kNucChunk;
+    }
+    const int64_t nchunk = cbase[N];
+    // device tables: segment table, segment scores, chunk bases, two totals,
+    // and per chunk: counts (int32), the same widened, offsets (nchunk + 1)
+    const size_t o_tk = 0, o_ts = al256(8 * (size_t)T), o_ss = o_ts + al256(4 * (size_t)T),
+                 o_cb = o_ss + al256(4 * segscore.size()), o_tot = o_cb + al256(8 * (size_t)(N + 1)),
+                 o_cc = o_tot + 256, o_cw = o_cc + al256(4 * (size_t)nchunk + 4),
+                 o_co = o_cw + al256(8 * (size_t)nchunk + 8), tab_bytes = o_co + al256(8 * (size_t)(nchunk + 1));
     RCHK(grow(ctx, ctx->nuctab, tab_bytes));
     char *tb = (char *)ctx->nuctab.p;
     HCHK(hipMemcpyAsync(tb + o_tk, tkey.data(), 8 * (size_t)T, hipMemcpyHostToDevice, st));
     HCHK(hipMemcpyAsync(tb + o_ts, tseg.data(), 4 * (size_t)T, hipMemcpyHostToDevice, st));
     HCHK(hipMemcpyAsync(tb + o_ss, segscore.data(), 4 * segscore.size(), hipMemcpyHostToDevice, st));
+    HCHK(hipMemcpyAsync(tb + o_cb, cbase.data(), 8 * (size_t)(N + 1), hipMemcpyHostToDevice, st));
     const int aw = (m + 31) / 32;
     {   // zero the vectors (ins as words plus an odd tail) and G
         const int64_t n16 = (int64_t)N * (m + 1);
@@ -2665,46 +2694,68 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
     a.alpha = S.alpha;
     a.go = S.goe - S.ge;
     a.ge = S.ge;
-    a.nmatch = (int32_t *)(tb + o_nm);
+    a.cbase = (const int64_t *)(tb + o_cb);
+    a.nchunk = nchunk;
+    a.ccount = (int32_t *)(tb + o_cc);
+    a.cmoff = (const int64_t *)(tb + o_co);
     a.score = score;
     a.ins = ins;
     a.aligned = aligned;
     a.aw = aw;
     a.G = G;
     a.gskip = center;
-    const dim3 grid((unsigned)((N + 255) / 256));
-    hipLaunchKernelGGL(hk::nuc_count_kernel, grid, dim3(256), 0, st, a);
-    HCHK(hipGetLastError());
-    // matches: moff[x] = sum of counts before x; chain table adds one entry per sequence
-    hipLaunchKernelGGL(hk::widen_kernel, grid, dim3(256), 0, st, (const int32_t *)(tb + o_nm), N, (int64_t *)(tb + o_w));
+    int64_t *dtot = (int64_t *)(tb + o_tot);
+    const unsigned cgrid = (unsigned)std::max<int64_t>(1, (nchunk + 255) / 256);
+    if (nchunk > 0) {
+        hipLaunchKernelGGL(hk::nuc_count_kernel, dim3(cgrid), dim3(256), 0, st, a);
+        HCHK(hipGetLastError());
+        hipLaunchKernelGGL(hk::widen_kernel, dim3(cgrid), dim3(256), 0, st, (const int32_t *)a.ccount, (int)nchunk,
+                           (int64_t *)(tb + o_cw));
+        HCHK(hipGetLastError());
+    }
     int64_t nmt = 0;
-    RCHK(scan_i64(ctx, (const int64_t *)(tb + o_w), N, 0, (int64_t *)(tb + o_mo), &nmt, st));
-    const size_t s_mq = 0, s_mp = s_mq + 4 * (size_t)nmt, s_mb = s_mp + 4 * (size_t)nmt,
-                 s_pr = s_mb + 4 * (size_t)nmt, s_tl = s_pr + 4 * (size_t)nmt,
-                 scr_bytes = s_tl + 4 * ((size_t)nmt + N) + 256;
+    int64_t *cm = (int64_t *)(tb + o_co);
+    RCHK(scan_i64(ctx, (const int64_t *)(tb + o_cw), nchunk, 0, cm, cm + nchunk, &nmt, st));
+    // per match (4 x int32) and per slot (matches + N): chain table, stretch
+    // descriptor, sequence, sizes and their offsets (+ a total each)
+    const int64_t nslot = nmt + N;
+    const size_t m_q = 0, m_p = al256(4 * (size_t)nmt), m_b = m_p + al256(4 * (size_t)nmt),
+                 m_r = m_b + al256(4 * (size_t)nmt), s_tl = m_r + al256(4 * (size_t)nmt),
+                 s_d = s_tl + al256(4 * (size_t)nslot), s_x = s_d + al256(16 * (size_t)nslot),
+                 s_r = s_x + al256(4 * (size_t)nslot), s_c = s_r + al256(8 * (size_t)nslot),
+                 s_ro = s_c + al256(8 * (size_t)nslot), s_co = s_ro + al256(8 * (size_t)nslot + 8),
+                 scr_bytes = s_co + al256(8 * (size_t)nslot + 8);
     RCHK(grow(ctx, ctx->nucscr, scr_bytes));
     char *sb = (char *)ctx->nucscr.p;
-    a.moff = (const int64_t *)(tb + o_mo);
-    a.mq = (int32_t *)(sb + s_mq);
-    a.mp = (int32_t *)(sb + s_mp);
-    a.mbest = (int32_t *)(sb + s_mb);
-    a.mpred = (int32_t *)(sb + s_pr);
+    a.mq = (int32_t *)(sb + m_q);
+    a.mp = (int32_t *)(sb + m_p);
+    a.mbest = (int32_t *)(sb + m_b);
+    a.mpred = (int32_t *)(sb + m_r);
     a.tails = (int32_t *)(sb + s_tl);
-    a.nchain = (int32_t *)(tb + o_nc);
-    a.rowlen = (int64_t *)(tb + o_rl);
-    a.codelen = (int64_t *)(tb + o_cl);
-    hipLaunchKernelGGL(hk::nuc_chain_kernel, grid, dim3(256), 0, st, a);
+    a.sdesc = (int4 *)(sb + s_d);
+    a.sseq = (int32_t *)(sb + s_x);
+    a.srow = (int64_t *)(sb + s_r);
+    a.scode = (int64_t *)(sb + s_c);
+    a.nslot = nslot;
+    if (nchunk > 0) {
+        hipLaunchKernelGGL(hk::nuc_store_kernel, dim3(cgrid), dim3(256), 0, st, a);
+        HCHK(hipGetLastError());
+    }
+    const unsigned sgrid = (unsigned)((N + 255) / 256);
+    hipLaunchKernelGGL(hk::nuc_chain_kernel, dim3(sgrid), dim3(256), 0, st, a);
     HCHK(hipGetLastError());
+    // stretch scratch: row buffers and codes, one region per stretch
     int64_t nrow = 0, ncode = 0;
-    RCHK(scan_i64(ctx, a.rowlen, N, 0, (int64_t *)(tb + o_ro), &nrow, st));
-    RCHK(scan_i64(ctx, a.codelen, N, 0, (int64_t *)(tb + o_co), &ncode, st));
-    const size_t d_ro = 0, d_co = (8 * (size_t)nrow + 255) & ~(size_t)255, dp_bytes = d_co + 4 * (size_t)ncode + 256;
+    int64_t *ro = (int64_t *)(sb + s_ro), *co = (int64_t *)(sb + s_co);
+    RCHK(scan_i64(ctx, a.srow, nslot, 0, ro, dtot, &nrow, st));
+    RCHK(scan_i64(ctx, a.scode, nslot, 0, co, dtot + 1, &ncode, st));
+    const size_t d_co = al256(8 * (size_t)nrow), dp_bytes = d_co + al256(4 * (size_t)ncode);
     RCHK(grow(ctx, ctx->nucdp, dp_bytes));
-    a.rowoff = (const int64_t *)(tb + o_ro);
-    a.codeoff = (const int64_t *)(tb + o_co);
-    a.rows = (int2 *)((char *)ctx->nucdp.p + d_ro);
+    a.srowoff = ro;
+    a.scodeoff = co;
+    a.rows = (int2 *)ctx->nucdp.p;
     a.codes = (uint32_t *)((char *)ctx->nucdp.p + d_co);
-    hipLaunchKernelGGL(hk::nuc_align_kernel, grid, dim3(256), 0, st, a);
+    hipLaunchKernelGGL(hk::nuc_stretch_kernel, dim3((unsigned)((nslot + 255) / 256)), dim3(256), 0, st, a);
     HCHK(hipGetLastError());
     return HALIGN_OK;
 }

@@ -233,33 +233,37 @@ __global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
         __builtin_amdgcn_wave_barrier();
         uint8_t *row = a.msa + (int64_t)k * width;
         const int a0 = (int)((uintptr_t)row & 15);
+        // each lane places a contiguous run of residues: one binary search
+        // for the block of its first residue, then a short forward walk (a new
+        // search when it would cross more than a few empty blocks).  Columns
+        // grow with the residue index, so over the chunks of the row each
+        // lane's cursor only moves forward.
+        const int per_r = (n + 63) >> 6;
+        const int q0 = min(n, lane * per_r), q1 = min(n, q0 + per_r);
+        auto search = [&](int q, int l) __attribute__((always_inline)) {   // last block with start <= q
+            int h = m;
+            while (l < h) {
+                const int mid = (l + h + 1) >> 1;
+                if (spos[mid] <= q) l = mid;
+                else h = mid - 1;
+            }
+            return l;
+        };
+        int l = q0 < q1 ? search(q0, 0) : 0;
+        int qc = q0;
         for (int64_t x0 = 0; x0 < width; x0 += a.ch) {
             const int len = (int)min<int64_t>(a.ch, width - x0);
             const int nw = (a0 + len + 15) >> 4;
             for (int q = lane; q < nw; q += 64) buf16[q] = make_uint4(~0u, ~0u, ~0u, ~0u);
             __builtin_amdgcn_wave_barrier();
-            // each lane places a contiguous run of residues: one binary search
-            // for the block of its first residue, then a short forward walk
-            // (a new search when it would cross more than a few empty blocks)
-            const int per_r = (n + 63) >> 6;
-            const int q0 = min(n, lane * per_r), q1 = min(n, q0 + per_r);
-            auto search = [&](int q, int l) __attribute__((always_inline)) {   // last block with start <= q
-                int h = m;
-                while (l < h) {
-                    const int mid = (l + h + 1) >> 1;
-                    if (spos[mid] <= q) l = mid;
-                    else h = mid - 1;
-                }
-                return l;
-            };
-            int l = q0 < q1 ? search(q0, 0) : 0;
-            for (int q = q0; q < q1; ++q) {
-                for (int st = 0; st < 4 && l < m && spos[l + 1] <= q; ++st) ++l;
-                if (l < m && spos[l + 1] <= q) l = search(q, l);
-                const int tq = q - spos[l];
+            for (; qc < q1; ++qc) {
+                for (int st = 0; st < 4 && l < m && spos[l + 1] <= qc; ++st) ++l;
+                if (l < m && spos[l + 1] <= qc) l = search(qc, l);
+                const int tq = qc - spos[l];
                 const int2 cg = colg(l);
                 const int dest = cg.x + (tq < (int)sins[l] ? tq : cg.y);
-                if (dest >= x0 && dest < x0 + len) buf[a0 + (int)(dest - x0)] = s[q];
+                if (dest >= x0 + len) break;   // a later chunk's column
+                buf[a0 + (int)(dest - x0)] = s[qc];
             }
             __builtin_amdgcn_wave_barrier();
             // copy out: LDS byte a0 + c holds column x0 + c

@@ -97,3 +97,13 @@ def test_mito_like_subset(H, ctx):
     sc, ins, al, G = _vectors(H, ctx, seqs, 0, synth.NUC_K)
     wsc, wins, wal = _oracle_pairs(seqs, 0, synth.NUC_K)
     assert (sc == wsc).all() and (ins == wins).all() and (al == wal).all()
+
+
+def test_msa_long_center(H, ctx):
+    """A 16.5 kb center: the rows need more LDS than 64 KiB per workgroup."""
+    seqs = synth.generate_dna("dna672", n_seqs=12, seed=5)
+    ref = oracle.nuc_msa(NM, GO, GE, synth.NUC_K, seqs.residues, seqs.offsets)
+    msa, score = H.halign_nuc_msa(ctx, H.Scoring(NM, GO, GE), H.DeviceSeqs(seqs), synth.NUC_K)
+    assert msa.shape[1] == ref["width"]
+    assert (msa.cpu().numpy() == ref["msa"]).all()
+    assert (score.cpu().numpy() == ref["score"]).all()
