@@ -238,6 +238,46 @@ def learned_report(H, ctx, sc, workload: str, anchors: int, partners: int, epoch
     return out
 
 
+def nucleotide_report(H, ctx, workload: str, reps: int, cpu_seqs: int):
+    """The trie section's nucleotide center star on a DNA set: MSA time with
+    the sequences resident; with cpu_seqs > 0 its CPU baseline, the oracle's
+    pairwise routine on one host thread over the first cpu_seqs sequences."""
+    import torch
+    from paper_1704_00878_amd import synth
+    seqs = synth.generate_dna(workload)
+    ds = H.DeviceSeqs(seqs)
+    sc = H.Scoring(synth.NUC_MATRIX, synth.NUC_GAP_OPEN, synth.NUC_GAP_EXTEND)
+    k = synth.NUC_K
+    log(f"bench: nucleotide center star on {workload} ({seqs.n} seqs)")
+    msa, score = H.halign_nuc_msa(ctx, sc, ds, k)   # warm-up
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        msa, score = H.halign_nuc_msa(ctx, sc, ds, k, out=msa)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    ms = 1e3 * float(np.median(ts))
+    sp = H.halign_sp_score(sc, msa)[0] / (seqs.n * (seqs.n - 1) / 2)
+    log(f"bench: nucleotide MSA {ms:.2f} ms (width {msa.shape[1]})")
+    cpu = None
+    if cpu_seqs > 0:
+        import oracle
+        nc = min(cpu_seqs, seqs.n)
+        c = seqs.seq(0)
+        t = time.perf_counter()
+        for x in range(nc):
+            oracle.nuc_align(synth.NUC_MATRIX, synth.NUC_GAP_OPEN, synth.NUC_GAP_EXTEND, k, c, seqs.seq(x))
+        dt = time.perf_counter() - t
+        bases = float(seqs.offsets[nc])
+        cpu = {"value": round(bases / dt, 1), "unit": "bases/s", "cores": 1, "kind": "oracle",
+               "sample": f"pairwise vectors of the first {nc} of {seqs.n} sequences against sequence 0 "
+                         f"({dt:.2f} s; no merge or rows)"}
+    return {"workload": f"{workload}: {seqs.n} seqs, {int(seqs.offsets[-1])} bases, center seq 0, k {k}",
+            "msa_ms": round(ms, 3), "width": int(msa.shape[1]), "avg_sp": round(sp, 4),
+            "bases_per_s": round(float(seqs.offsets[-1]) / (ms / 1e3), 1), "cpu_baseline": cpu}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -254,6 +294,8 @@ def main():
                     "('none' skips it)")
     ap.add_argument("--learned-n", type=int, default=0, help="first N sequences of the family set (0: all)")
     ap.add_argument("--no-exact", action="store_true", help="learned report without the exhaustive center")
+    ap.add_argument("--nucleotide", default="dna672", help="DNA set for the nucleotide center-star report "
+                    "(none: skip)")
     ap.add_argument("--anchors", type=int, default=50000, help="training anchors")
     ap.add_argument("--partners", type=int, default=64, help="training partners per anchor")
     ap.add_argument("--epochs", type=int, default=1)
@@ -401,6 +443,10 @@ def main():
         cpu = cpu_baseline(seqs, center)
         log(f"bench: oracle {cpu['value']:.3f} GCUPS on {cpu['cores']} threads")
 
+    nuc = None
+    if args.nucleotide != "none":
+        nuc = nucleotide_report(H, ctx, args.nucleotide, 5, 0 if args.no_cpu else 200)
+
     ctx.set_autotune(not args.no_autotune)
     learned = None
     if args.learned != "none":
@@ -425,6 +471,7 @@ def main():
         "avg_sp": round(sp / npairs, 3), "msa_s": round(ms_step / 1e3, 6),
         "graph_replay": graph,
         "learned_center": learned,
+        "nucleotide": nuc,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
