@@ -1548,7 +1548,8 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const 
     const int m1 = m + 1, aw = (m + 31) / 32;
     size_t lim = std::min<size_t>(ctx->lds_max, 64 * 1024);
     auto wave_bytes = [&](int ch) {
-        const size_t head = (4 * (size_t)m1 + (((size_t)m1 * 2 + 3) & ~(size_t)3) + 4 * (size_t)aw + 15) & ~(size_t)15;
+        const size_t h2 = ((size_t)m1 * 2 + 3) & ~(size_t)3;
+        const size_t head = (2 * h2 + 4 * (size_t)aw + 15) & ~(size_t)15;
         return head + (size_t)ch + 32;
     };
     int ch = (int)std::min<int64_t>(8192, (width + 15) & ~(int64_t)15), wpb = hk::kWaveRows;
@@ -1557,7 +1558,9 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const 
     if ((size_t)wpb * wave_bytes(ch) > lim && wave_bytes(ch) <= ctx->lds_cu) lim = ctx->lds_cu;   // long centers
     if ((size_t)wpb * wave_bytes(ch) > lim) return fail(HALIGN_E_UNSUPPORTED, "center length %d too long for row emission", m);
     if (width >= ((int64_t)1 << 31)) return fail(HALIGN_E_UNSUPPORTED, "MSA width %lld", (long long)width);
-    const size_t gcb = 8 * (size_t)m1;
+    const size_t gcb = 4 * (size_t)(m1 + 1);
+    if ((size_t)wpb * wave_bytes(ch) + gcb > lim && (size_t)wpb * wave_bytes(ch) + gcb <= ctx->lds_cu)
+        lim = ctx->lds_cu;   // the column table in LDS too
     const int gc_lds = (size_t)wpb * wave_bytes(ch) + gcb <= lim ? 1 : 0;
     hk::RowsArgs ra{seqs->residues, seqs->offsets, N, m, ins, aligned, aw, G, col, width, ch, (int)wave_bytes(ch),
                     gc_lds, msa};
@@ -2741,8 +2744,13 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
         hipLaunchKernelGGL(hk::nuc_store_kernel, dim3(cgrid), dim3(256), 0, st, a);
         HCHK(hipGetLastError());
     }
-    const unsigned sgrid = (unsigned)((N + 255) / 256);
-    hipLaunchKernelGGL(hk::nuc_chain_kernel, dim3(sgrid), dim3(256), 0, st, a);
+    // LDS sized for twice the mean match count (a power of two, 64 ..
+    // kChainLdsMax), so several workgroups share a CU; a sequence with more
+    // matches is chained in the global arrays
+    int cap = 64;
+    while (cap < hk::kChainLdsMax && (int64_t)cap * N < 2 * nmt) cap *= 2;
+    a.chain_cap = cap;
+    hipLaunchKernelGGL(hk::nuc_chain_kernel, dim3((unsigned)N), dim3(64), hk::nuc_chain_lds_bytes(cap), st, a);
     HCHK(hipGetLastError());
     // stretch scratch: row buffers and codes, one region per stretch
     int64_t nrow = 0, ncode = 0;

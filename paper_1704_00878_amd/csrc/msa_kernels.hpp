@@ -180,7 +180,7 @@ struct RowsArgs {
     int64_t width;
     int ch;                   // columns per chunk (multiple of 16)
     int wave_bytes;           // LDS bytes per wavefront region
-    int gc_lds;               // (col, G) staged in LDS for the workgroup (after the wave regions)
+    int gc_lds;               // col staged in LDS for the workgroup (after the wave regions)
     uint8_t *msa;             // [nrows][width]
 };
 
@@ -190,20 +190,28 @@ __global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
     const int wpb = blockDim.x >> 6;
     const int m = a.m, m1 = m + 1;
     const int64_t width = a.width;
+    // per wavefront: block starts in the sequence (uint16: lengths < 65536),
+    // insertion counts, aligned bits, then the row chunk
+    const size_t h2 = ((size_t)m1 * 2 + 3) & ~(size_t)3;
     char *wsh = reinterpret_cast<char *>(lds_rows) + (size_t)wid * a.wave_bytes;
-    int *spos = reinterpret_cast<int *>(wsh);                                  // [m1]
-    uint16_t *sins = reinterpret_cast<uint16_t *>(wsh + 4 * (size_t)m1);        // [m1]
-    uint32_t *abit = reinterpret_cast<uint32_t *>(wsh + 4 * (size_t)m1 + (((size_t)m1 * 2 + 3) & ~(size_t)3));
-    const size_t bo = (4 * (size_t)m1 + (((size_t)m1 * 2 + 3) & ~(size_t)3) + 4 * (size_t)a.aw + 15) & ~(size_t)15;
+    uint16_t *spos = reinterpret_cast<uint16_t *>(wsh);                         // [m1]
+    uint16_t *sins = reinterpret_cast<uint16_t *>(wsh + h2);                   // [m1]
+    uint32_t *abit = reinterpret_cast<uint32_t *>(wsh + 2 * h2);
+    const size_t bo = (2 * h2 + 4 * (size_t)a.aw + 15) & ~(size_t)15;
     uint8_t *buf = reinterpret_cast<uint8_t *>(wsh + bo);                     // [ch + 16], 16-byte aligned
     uint4 *buf16 = reinterpret_cast<uint4 *>(buf);
-    int2 *gcl = reinterpret_cast<int2 *>(reinterpret_cast<char *>(lds_rows) + (size_t)wpb * a.wave_bytes);
+    // the workgroup's column table: col[p] for p <= m and width + 1 after
+    // it, so block p's gap count is col[p + 1] - col[p] - 1
+    int *gcl = reinterpret_cast<int *>(reinterpret_cast<char *>(lds_rows) + (size_t)wpb * a.wave_bytes);
     if (a.gc_lds) {
-        for (int p = tid; p < m1; p += blockDim.x) gcl[p] = make_int2((int)a.col[p], a.G[p]);
+        for (int p = tid; p <= m1; p += blockDim.x) gcl[p] = p < m1 ? (int)a.col[p] : (int)(width + 1);
         __syncthreads();
     }
     auto colg = [&](int p) __attribute__((always_inline)) -> int2 {
-        return a.gc_lds ? gcl[p] : make_int2((int)a.col[p], a.G[p]);
+        return a.gc_lds ? make_int2(gcl[p], gcl[p + 1] - gcl[p] - 1) : make_int2((int)a.col[p], a.G[p]);
+    };
+    auto colv = [&](int p) __attribute__((always_inline)) -> int64_t {   // col[p], p <= m
+        return a.gc_lds ? (int64_t)gcl[p] : a.col[p];
     };
     const int per = (m1 + 63) / 64;
     const int lo = min(m1, lane * per), hi = min(m1, lo + per);
@@ -214,8 +222,34 @@ __global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
         const uint16_t *ir = a.ins + (int64_t)k * m1;
         const uint32_t *ar = a.aligned + (int64_t)k * a.aw;
         __builtin_amdgcn_wave_barrier();   // the previous row is done with this region
-        for (int q = lane; q < a.aw; q += 64) abit[q] = ar[q];
-        for (int p = lane; p < m1; p += 64) sins[p] = ir[p];
+        // staged with 8 loads in flight per lane (a long center's counts are
+        // hundreds of loads per lane)
+        for (int q0 = 0; q0 < a.aw; q0 += 512) {
+            uint32_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + 64 * u + lane;
+                v[u] = q < a.aw ? ar[q] : 0u;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int q = q0 + 64 * u + lane;
+                if (q < a.aw) abit[q] = v[u];
+            }
+        }
+        for (int p0 = 0; p0 < m1; p0 += 512) {
+            uint16_t v[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = p0 + 64 * u + lane;
+                v[u] = p < m1 ? ir[p] : (uint16_t)0;
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int p = p0 + 64 * u + lane;
+                if (p < m1) sins[p] = v[u];
+            }
+        }
         __builtin_amdgcn_wave_barrier();
         int sum = 0;
         for (int p = lo; p < hi; ++p)
@@ -227,21 +261,31 @@ __global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
         }
         int acc = inc - sum;
         for (int p = lo; p < hi; ++p) {
-            spos[p] = acc;
+            spos[p] = (uint16_t)acc;
             acc += (int)sins[p] + ((p < m) ? (int)((abit[p >> 5] >> (p & 31)) & 1u) : 0);
         }
         __builtin_amdgcn_wave_barrier();
         uint8_t *row = a.msa + (int64_t)k * width;
         const int a0 = (int)((uintptr_t)row & 15);
-        // each lane places a contiguous run of residues: one binary search
-        // for the block of its first residue, then a short forward walk (a new
-        // search when it would cross more than a few empty blocks).  Columns
-        // grow with the residue index, so over the chunks of the row each
-        // lane's cursor only moves forward.
-        const int per_r = (n + 63) >> 6;
-        const int q0 = min(n, lane * per_r), q1 = min(n, q0 + per_r);
-        auto search = [&](int q, int l) __attribute__((always_inline)) {   // last block with start <= q
-            int h = m;
+        // Residues are split over the lanes chunk by chunk.  Columns grow with
+        // the residue index, so a chunk of columns [x0, x1) holds the residues
+        // first_at(x0) .. first_at(x1) - 1; first_at(x) is found from block p,
+        // the last with col[p] <= x: block p's residues before column x are its
+        // first min(x - col[p], ins[p]) (its insertions sit at col[p] + t, its
+        // aligned residue at col[p + 1] - 1).  Each lane then places a
+        // contiguous run of that range: one binary search for the block of its
+        // first residue (within the chunk's blocks), then a short forward walk.
+        auto first_at = [&](int64_t x, int &pblk) __attribute__((always_inline)) -> int {
+            int l0 = pblk, h0 = m;   // col[pblk] <= x
+            while (l0 < h0) {
+                const int mid = (l0 + h0 + 1) >> 1;
+                if (colv(mid) <= x) l0 = mid;
+                else h0 = mid - 1;
+            }
+            pblk = l0;
+            return (int)spos[l0] + (int)min<int64_t>(x - colv(l0), (int64_t)sins[l0]);
+        };
+        auto search = [&](int q, int l, int h) __attribute__((always_inline)) {   // last block in [l, h] with start <= q
             while (l < h) {
                 const int mid = (l + h + 1) >> 1;
                 if (spos[mid] <= q) l = mid;
@@ -249,21 +293,24 @@ __global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
             }
             return l;
         };
-        int l = q0 < q1 ? search(q0, 0) : 0;
-        int qc = q0;
+        int qa = 0, pa = 0;   // the chunk's first residue and its block
         for (int64_t x0 = 0; x0 < width; x0 += a.ch) {
             const int len = (int)min<int64_t>(a.ch, width - x0);
+            int pb = pa;
+            const int qb = x0 + len >= width ? n : first_at(x0 + len, pb);
             const int nw = (a0 + len + 15) >> 4;
             for (int q = lane; q < nw; q += 64) buf16[q] = make_uint4(~0u, ~0u, ~0u, ~0u);
             __builtin_amdgcn_wave_barrier();
-            for (; qc < q1; ++qc) {
-                for (int st = 0; st < 4 && l < m && spos[l + 1] <= qc; ++st) ++l;
-                if (l < m && spos[l + 1] <= qc) l = search(qc, l);
-                const int tq = qc - spos[l];
+            const int pc = (qb - qa + 63) >> 6;
+            const int r0 = min(qb, qa + lane * pc), r1 = min(qb, r0 + pc);
+            int l = r0 < r1 ? search(r0, pa, x0 + len >= width ? m : pb) : 0;
+            for (int q = r0; q < r1; ++q) {
+                for (int st = 0; st < 4 && l < m && spos[l + 1] <= q; ++st) ++l;
+                if (l < m && spos[l + 1] <= q) l = search(q, l, m);
+                const int tq = q - spos[l];
                 const int2 cg = colg(l);
-                const int dest = cg.x + (tq < (int)sins[l] ? tq : cg.y);
-                if (dest >= x0 + len) break;   // a later chunk's column
-                buf[a0 + (int)(dest - x0)] = s[qc];
+                const int64_t dest = cg.x + (tq < (int)sins[l] ? tq : cg.y);
+                if (dest >= x0 && dest < x0 + len) buf[a0 + (int)(dest - x0)] = s[q];
             }
             __builtin_amdgcn_wave_barrier();
             // copy out: LDS byte a0 + c holds column x0 + c
@@ -277,6 +324,8 @@ __global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
                 }
             }
             __builtin_amdgcn_wave_barrier();
+            qa = qb;
+            pa = pb;
         }
     }
 }

@@ -8,9 +8,10 @@
 // set of occurrences comes from a hash table of the segments' 2-bit packed
 // strings (one probe per position of the sequence); the table sits in LDS.
 //
-// One lane per sequence throughout: sequences are many and their work is
-// sequential (a scan, a chain, small dynamic programs), so lanes, not
-// cooperative tiles, carry the parallelism.
+// Lanes, not cooperative tiles, carry the parallelism: sequences are many and
+// their work is sequential (a scan, a chain, small dynamic programs).  The
+// scan takes one lane per chunk of match starts, the chain one workgroup per
+// sequence (its matches staged in LDS), each stretch one lane.
 #pragma once
 #include <hip/hip_runtime.h>
 #include <stdint.h>
@@ -56,6 +57,7 @@ struct NucArgs {
     int aw;
     int32_t *G;               // optional merge: max of ins over the sequences
     int gskip;                // sequence kept out of G
+    int chain_cap;            // matches per sequence chained in LDS (<= kChainLdsMax)
 };
 
 constexpr int kNucChunk = 256;   // match starts per scan lane
@@ -170,46 +172,37 @@ __global__ void __launch_bounds__(256) nuc_store_kernel(NucArgs a) {
     });
 }
 
-// Third pass, one lane per sequence: the anchor chain over its matches (in
-// order of p).  A match is inserted into the chain table once p_i >= p_j + k
-// for the match i being queried; tails[L] is the inserted match of chain
-// length L with the smallest (q, p) (q increases with L).  A query takes the
-// longest L whose tail has q < q_i: best = L + 1, predecessor = tails[L].
-// Then the anchors (aligned bits, scores) and one stretch per slot: before the
-// first anchor, between anchors, after the last.
-__global__ void __launch_bounds__(256) nuc_chain_kernel(NucArgs a) {
-    const int x = blockIdx.x * blockDim.x + threadIdx.x;
-    if (x >= a.nseq) return;
-    const int n = (int)(a.off[x + 1] - a.off[x]);
-    const int k = a.k, m = a.m;
-    const int64_t mb = a.cmoff[a.cbase[x]];
-    const int cnt = (int)(a.cmoff[a.cbase[x + 1]] - mb);
-    const int32_t *mq = a.mq + mb, *mp = a.mp + mb;
-    int32_t *mbest = a.mbest + mb, *mpred = a.mpred + mb;
-    const int64_t sb = mb + x;   // this sequence's slots: sb .. sb + cnt
-    int32_t *tails = a.tails + sb;
+// Third pass: the anchor chain over a sequence's matches (in order of p).  A
+// match is inserted into the chain table once p_i >= p_j + k for the match i
+// being queried; tails[L] is the inserted match of chain length L with the
+// smallest (q, p) (q increases with L).  A query takes the longest L whose
+// tail has q < q_i: best = L + 1, predecessor = tails[L].  Sequential in the
+// matches; returns L with the chain in tails[0 .. L-1].
+template <typename TM, typename TI>
+__device__ __forceinline__ int nuc_chain_seq(const TM *mq, const TM *mp, TI *mbest, TI *mpred, TI *tails, int cnt,
+                                             int k) {
     int L = 0, ins_next = 0;
     int lastq = -1;   // q of tails[L]
     auto insert = [&](int j) __attribute__((always_inline)) {
-        const int bj = mbest[j];
-        const int qj = mq[j];
+        const int bj = (int)mbest[j];
+        const int qj = (int)mq[j];
         if (bj > L) {
-            tails[bj] = j;
+            tails[bj] = (TI)j;
             L = bj;
             lastq = qj;
-        } else if (qj < mq[tails[bj]]) {
-            tails[bj] = j;
+        } else if (qj < (int)mq[tails[bj]]) {
+            tails[bj] = (TI)j;
             if (bj == L) lastq = qj;
         }
     };
-    int qn = cnt > 0 ? mq[0] : 0, pn = cnt > 0 ? mp[0] : 0;
+    int qn = cnt > 0 ? (int)mq[0] : 0, pn = cnt > 0 ? (int)mp[0] : 0;
     for (int i = 0; i < cnt; ++i) {
         const int q = qn, p = pn;
         if (i + 1 < cnt) {   // the next match's fields, loaded a match ahead
-            qn = mq[i + 1];
-            pn = mp[i + 1];
+            qn = (int)mq[i + 1];
+            pn = (int)mp[i + 1];
         }
-        while (ins_next < i && mp[ins_next] + k <= p) insert(ins_next++);
+        while (ins_next < i && (int)mp[ins_next] + k <= p) insert(ins_next++);
         int lq = 0;
         if (L > 0 && lastq < q) {
             lq = L;
@@ -217,56 +210,102 @@ __global__ void __launch_bounds__(256) nuc_chain_kernel(NucArgs a) {
             int lo = 1, hi = L;   // largest l in [1, L] with q(tails[l]) < q
             while (lo <= hi) {
                 const int mid = (lo + hi) >> 1;
-                if (mq[tails[mid]] < q) { lq = mid; lo = mid + 1; }
+                if ((int)mq[tails[mid]] < q) { lq = mid; lo = mid + 1; }
                 else hi = mid - 1;
             }
         }
-        mbest[i] = lq + 1;
-        mpred[i] = lq > 0 ? tails[lq] : -1;
+        mbest[i] = (TI)(lq + 1);
+        mpred[i] = (TI)(lq > 0 ? (int)tails[lq] : 0);   // unused for lq = 0
     }
     while (ins_next < cnt) insert(ins_next++);
     // the chain, in order, into tails[0 .. L-1] (tails[L] is its last match)
-    int e = L > 0 ? tails[L] : -1;
+    int e = L > 0 ? (int)tails[L] : 0;
     for (int t = L - 1; t >= 0; --t) {
-        tails[t] = e;
-        e = mpred[e];
+        tails[t] = (TI)e;
+        e = (int)mpred[e];
     }
-    // anchors: aligned bits (word by word) and scores; stretches per slot
+    return L;
+}
+
+constexpr int kChainLdsMax = 4096;   // matches of a sequence chained in LDS at most
+
+// LDS of the chain kernel for cap matches: five 16-bit arrays
+inline size_t nuc_chain_lds_bytes(int cap) { return (size_t)2 * (5 * (size_t)cap + 1); }
+
+// One 64-lane workgroup per sequence.  A sequence with at most a.chain_cap
+// matches has them staged in LDS (q, p < 65536 as 16-bit fields) and chained
+// there by lane 0; a larger one is chained by lane 0 in the global arrays.
+// Then the lanes share the slots: the anchors (aligned bits, scores) and one
+// stretch per slot (before the first anchor, between anchors, after the last;
+// slots past the chain get an empty descriptor).
+__global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
+    extern __shared__ uint16_t chain_lds[];
+    const int cap = a.chain_cap;
+    uint16_t *lq = chain_lds, *lp = lq + cap, *lbest = lp + cap, *lpred = lbest + cap, *ltails = lpred + cap;
+    __shared__ int sh_L, sh_total;
+    const int x = blockIdx.x, lane = threadIdx.x;
+    const int n = (int)(a.off[x + 1] - a.off[x]);
+    const int k = a.k, m = a.m;
+    const int64_t mb = a.cmoff[a.cbase[x]];
+    const int cnt = (int)(a.cmoff[a.cbase[x + 1]] - mb);
+    const int32_t *mq = a.mq + mb, *mp = a.mp + mb;
+    const int64_t sb = mb + x;   // this sequence's slots: sb .. sb + cnt
+    int32_t *tails = a.tails + sb;
+    const bool inl = cnt <= cap;
+    if (inl) {
+        for (int i = lane; i < cnt; i += 64) {
+            lq[i] = (uint16_t)mq[i];
+            lp[i] = (uint16_t)mp[i];
+        }
+    }
+    if (lane == 0) sh_total = 0;
+    __syncthreads();
+    if (lane == 0)
+        sh_L = inl ? nuc_chain_seq(lq, lp, lbest, lpred, ltails, cnt, k)
+                   : nuc_chain_seq(mq, mp, a.mbest + mb, a.mpred + mb, tails, cnt, k);
+    __syncthreads();
+    const int L = sh_L;
+    auto anchor = [&](int t) __attribute__((always_inline)) -> int {   // match index of anchor t < L
+        return inl ? (int)ltails[t] : tails[t];
+    };
+    auto qof = [&](int j) __attribute__((always_inline)) -> int { return inl ? (int)lq[j] : mq[j]; };
+    auto pof = [&](int j) __attribute__((always_inline)) -> int { return inl ? (int)lp[j] : mp[j]; };
     uint32_t *al = a.aligned + (int64_t)x * a.aw;
-    int total = 0, ci = 0, sj = 0;
-    int curw = -1;
-    uint32_t bits = 0;
-    for (int t = 0; t <= cnt; ++t) {
+    int part = 0;
+    for (int t = lane; t <= cnt; t += 64) {
         if (t > L) {
             a.sdesc[sb + t] = make_int4(0, -1, 0, 0);
             a.srow[sb + t] = 0;
             a.scode[sb + t] = 0;
             continue;
         }
-        const int qc = t < L ? mq[tails[t]] * k : m;
-        const int ps = t < L ? mp[tails[t]] : n;
+        int ci = 0, sj = 0;   // just past the previous anchor
+        if (t > 0) {
+            const int jp = anchor(t - 1);
+            ci = qof(jp) * k + k;
+            sj = pof(jp) + k;
+        }
+        const int jt = t < L ? anchor(t) : 0;
+        const int qc = t < L ? qof(jt) * k : m;
+        const int ps = t < L ? pof(jt) : n;
         const int dc = qc - ci, ds = ps - sj;
         a.sdesc[sb + t] = make_int4(ci, dc, sj, ds);
         a.sseq[sb + t] = x;
         a.srow[sb + t] = ds + 1;
         a.scode[sb + t] = (int64_t)dc * ((ds + 7) >> 3);
         if (t < L) {
-            for (int u = 0; u < k; ++u) {
-                const int pp = qc + u;
-                if ((pp >> 5) != curw) {
-                    if (curw >= 0) atomicOr(al + curw, bits);
-                    curw = pp >> 5;
-                    bits = 0;
-                }
-                bits |= 1u << (pp & 31);
+            // center positions qc .. qc + k - 1 aligned
+            for (int w = qc >> 5; w <= (qc + k - 1) >> 5; ++w) {
+                const int b0 = max(qc, w << 5) - (w << 5), b1 = min(qc + k, (w + 1) << 5) - (w << 5);
+                const uint32_t bits = (b1 - b0 == 32) ? ~0u : (((1u << (b1 - b0)) - 1u) << b0);
+                atomicOr(al + w, bits);
             }
-            total += a.segscore[mq[tails[t]]];
-            ci = qc + k;
-            sj = ps + k;
+            part += a.segscore[qof(jt)];
         }
     }
-    if (curw >= 0) atomicOr(al + curw, bits);
-    a.score[x] = total;
+    atomicAdd(&sh_total, part);
+    __syncthreads();
+    if (lane == 0) a.score[x] = sh_total;
 }
 
 // Fourth pass, one lane per stretch: the stretch aligned end to end (Gotoh's
