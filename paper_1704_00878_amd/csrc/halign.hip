@@ -118,6 +118,7 @@ struct halign_ctx {
     DevBuf nuctab, nucscr, nucdp;   // nucleotide path: segment table, matches and chains, stretch scratch
     int64_t mail_seq = 0;
     uint32_t vtag = 0;        // tag of the last eager code check
+    uint32_t *vflag = nullptr;   // the flag word those tags were raised in (cleared when it changes)
     uint32_t check_tag = 0;   // tag validate_check expects (0 after a graph replay)
     int flag_alpha = 0;       // alphabet that value is checked against (0 = nothing pending)
     // HALIGN_HOST_TIMING=1: host time between labelled points of each
@@ -1033,11 +1034,14 @@ int validate_codes(halign_ctx *ctx, int alpha, const uint8_t *res, int64_t nres,
     if (ctx->capturing) {
         RCHK(launch_fill(flag, 0u, 1, st));
     } else {
-        if (++ctx->vtag >= (1u << 24)) {
+        // a buffer not yet cleared here (new, or swapped in) holds stale
+        // bytes that would outrank or mimic a tag: clear it first
+        if (ctx->vflag != flag || ctx->vtag + 1 >= (1u << 24)) {
             RCHK(launch_fill(flag, 0u, 1, st));
-            ctx->vtag = 1;
+            ctx->vflag = flag;
+            ctx->vtag = 0;
         }
-        tag = ctx->vtag;
+        tag = ++ctx->vtag;
     }
     ctx->check_tag = tag;
     const int64_t n1 = nres > 0 ? nres : 0, n2 = (center && m > 0) ? m : 0;
@@ -2660,7 +2664,7 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
     // and per chunk: counts (int32), the same widened, offsets (nchunk + 1)
     const size_t o_tk = 0, o_ts = al256(8 * (size_t)T), o_ss = o_ts + al256(4 * (size_t)T),
                  o_cb = o_ss + al256(4 * segscore.size()), o_tot = o_cb + al256(8 * (size_t)(N + 1)),
-                 o_cc = o_tot + 256, o_cw = o_cc + al256(4 * (size_t)nchunk + 4),
+                 o_lc = o_tot + 128, o_cc = o_tot + 256, o_cw = o_cc + al256(4 * (size_t)nchunk + 4),
                  o_co = o_cw + al256(8 * (size_t)nchunk + 8), tab_bytes = o_co + al256(8 * (size_t)(nchunk + 1));
     RCHK(grow(ctx, ctx->nuctab, tab_bytes));
     char *tb = (char *)ctx->nuctab.p;
@@ -2678,6 +2682,8 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
         z.n[1] = (int64_t)N * aw;
         z.p[2] = (uint32_t *)G;
         z.n[2] = G ? m + 1 : 0;
+        z.p[3] = (uint32_t *)(tb + o_lc);   // the stretch list counts
+        z.n[3] = 2;
         z.tail16 = (n16 & 1) ? ins + (n16 - 1) : nullptr;
         hipLaunchKernelGGL(hk::zero_kernel, dim3(grid_for(z.n[0] + z.n[1], 256, 4096)), dim3(256), 0, st, z);
         HCHK(hipGetLastError());
@@ -2722,12 +2728,14 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
     // per match (4 x int32) and per slot (matches + N): chain table, stretch
     // descriptor, sequence, sizes and their offsets (+ a total each)
     const int64_t nslot = nmt + N;
+    if (nslot >= ((int64_t)1 << 31)) return fail(HALIGN_E_UNSUPPORTED, "%lld segment matches", (long long)nmt);
     const size_t m_q = 0, m_p = al256(4 * (size_t)nmt), m_b = m_p + al256(4 * (size_t)nmt),
                  m_r = m_b + al256(4 * (size_t)nmt), s_tl = m_r + al256(4 * (size_t)nmt),
                  s_d = s_tl + al256(4 * (size_t)nslot), s_x = s_d + al256(16 * (size_t)nslot),
                  s_r = s_x + al256(4 * (size_t)nslot), s_c = s_r + al256(8 * (size_t)nslot),
                  s_ro = s_c + al256(8 * (size_t)nslot), s_co = s_ro + al256(8 * (size_t)nslot + 8),
-                 scr_bytes = s_co + al256(8 * (size_t)nslot + 8);
+                 s_sl = s_co + al256(8 * (size_t)nslot + 8), s_bl = s_sl + al256(4 * (size_t)nslot),
+                 scr_bytes = s_bl + al256(4 * (size_t)nslot);
     RCHK(grow(ctx, ctx->nucscr, scr_bytes));
     char *sb = (char *)ctx->nucscr.p;
     a.mq = (int32_t *)(sb + m_q);
@@ -2740,6 +2748,9 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
     a.srow = (int64_t *)(sb + s_r);
     a.scode = (int64_t *)(sb + s_c);
     a.nslot = nslot;
+    a.slist = (int32_t *)(sb + s_sl);
+    a.blist = (int32_t *)(sb + s_bl);
+    a.lcount = (int32_t *)(tb + o_lc);
     if (nchunk > 0) {
         hipLaunchKernelGGL(hk::nuc_store_kernel, dim3(cgrid), dim3(256), 0, st, a);
         HCHK(hipGetLastError());
@@ -2763,7 +2774,12 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
     a.scodeoff = co;
     a.rows = (int2 *)ctx->nucdp.p;
     a.codes = (uint32_t *)((char *)ctx->nucdp.p + d_co);
-    hipLaunchKernelGGL(hk::nuc_stretch_kernel, dim3((unsigned)((nslot + 255) / 256)), dim3(256), 0, st, a);
+    // the stretches: lists sized on the device, grids bounded by the slots
+    const int sgrid = (int)std::max<int64_t>(1, std::min<int64_t>((nslot + 255) / 256, (int64_t)ctx->num_cu * 8));
+    hipLaunchKernelGGL(hk::nuc_stretch_small_kernel, dim3(sgrid), dim3(256), 0, st, a);
+    HCHK(hipGetLastError());
+    const int wgrid = (int)std::max<int64_t>(1, std::min<int64_t>(nslot, (int64_t)ctx->num_cu * 16));
+    hipLaunchKernelGGL(hk::nuc_stretch_wave_kernel, dim3(wgrid), dim3(64), 0, st, a);
     HCHK(hipGetLastError());
     return HALIGN_OK;
 }

@@ -77,10 +77,10 @@ __global__ void __launch_bounds__(256) maxcode_kernel(const uint8_t *p, int64_t 
     }
 }
 
-// Zero up to three word ranges (and one trailing uint16) in one launch.
+// Zero up to four word ranges (and one trailing uint16) in one launch.
 struct ZeroArgs {
-    uint32_t *p[3];
-    int64_t n[3];
+    uint32_t *p[4];
+    int64_t n[4];
     uint16_t *tail16;
 };
 
@@ -88,7 +88,7 @@ __global__ void zero_kernel(ZeroArgs z) {
     const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
 #pragma unroll
-    for (int r = 0; r < 3; ++r)
+    for (int r = 0; r < 4; ++r)
         for (int64_t x = tid; x < z.n[r]; x += stride) z.p[r][x] = 0u;
     if (tid == 0 && z.tail16) *z.tail16 = 0;
 }

@@ -46,7 +46,7 @@ struct NucArgs {
     int32_t *tails;
     int4 *sdesc;              // per slot: center start, center length (-1: none), sequence start, its length
     int32_t *sseq;            // per slot: the sequence
-    int64_t *srow, *scode;    // per slot: row buffer entries, code words
+    int64_t *srow, *scode;    // per slot: boundary entries (wide stretches), code words
     const int64_t *srowoff, *scodeoff;
     int64_t nslot;
     int2 *rows;
@@ -58,9 +58,14 @@ struct NucArgs {
     int32_t *G;               // optional merge: max of ins over the sequences
     int gskip;                // sequence kept out of G
     int chain_cap;            // matches per sequence chained in LDS (<= kChainLdsMax)
+    // non-empty stretches: slots of the narrow ones (one lane each) and the
+    // wide ones (one wavefront each); lcount[0], lcount[1] their counts (zeroed)
+    int32_t *slist, *blist;
+    int32_t *lcount;
 };
 
 constexpr int kNucChunk = 256;   // match starts per scan lane
+constexpr int kNucSmallW = 32;   // stretches at most this many columns wide: one lane, the row in registers
 
 // The table's hash of a packed segment (the host fills the table with it).
 __host__ __device__ __forceinline__ uint32_t nuc_hash(unsigned long long key, int lg_t) {
@@ -271,27 +276,38 @@ __global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
     auto qof = [&](int j) __attribute__((always_inline)) -> int { return inl ? (int)lq[j] : mq[j]; };
     auto pof = [&](int j) __attribute__((always_inline)) -> int { return inl ? (int)lp[j] : mp[j]; };
     uint32_t *al = a.aligned + (int64_t)x * a.aw;
+    const uint64_t below = (1ull << lane) - 1ull;   // lanes under this one
     int part = 0;
-    for (int t = lane; t <= cnt; t += 64) {
-        if (t > L) {
-            a.sdesc[sb + t] = make_int4(0, -1, 0, 0);
-            a.srow[sb + t] = 0;
-            a.scode[sb + t] = 0;
-            continue;
-        }
+    for (int t0 = 0; t0 <= L; t0 += 64) {   // the chain's slots: uniform trip count (ballots below)
+        const int t = t0 + lane;
+        const bool in = t <= L;
         int ci = 0, sj = 0;   // just past the previous anchor
-        if (t > 0) {
+        if (in && t > 0) {
             const int jp = anchor(t - 1);
             ci = qof(jp) * k + k;
             sj = pof(jp) + k;
         }
-        const int jt = t < L ? anchor(t) : 0;
+        const int jt = in && t < L ? anchor(t) : 0;
         const int qc = t < L ? qof(jt) * k : m;
         const int ps = t < L ? pof(jt) : n;
         const int dc = qc - ci, ds = ps - sj;
+        // non-empty stretches into the lane list (narrow) or the wavefront list
+        const bool work = in && (dc > 0 || ds > 0);
+        const bool wide = work && ds > kNucSmallW;
+        const uint64_t bs = __ballot(work && !wide), bw = __ballot(wide);
+        int os = 0, ow = 0;
+        if (lane == 0) {
+            if (bs) os = atomicAdd(a.lcount, __popcll(bs));
+            if (bw) ow = atomicAdd(a.lcount + 1, __popcll(bw));
+        }
+        os = __shfl(os, 0, 64);
+        ow = __shfl(ow, 0, 64);
+        if (work && !wide) a.slist[os + __popcll(bs & below)] = (int32_t)(sb + t);
+        if (wide) a.blist[ow + __popcll(bw & below)] = (int32_t)(sb + t);
+        if (!in) continue;
         a.sdesc[sb + t] = make_int4(ci, dc, sj, ds);
         a.sseq[sb + t] = x;
-        a.srow[sb + t] = ds + 1;
+        a.srow[sb + t] = wide ? dc + 1 : 0;   // the wavefront kernel's boundary column
         a.scode[sb + t] = (int64_t)dc * ((ds + 7) >> 3);
         if (t < L) {
             // center positions qc .. qc + k - 1 aligned
@@ -303,73 +319,41 @@ __global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
             part += a.segscore[qof(jt)];
         }
     }
+    for (int t = L + 1 + lane; t <= cnt; t += 64) {   // slots past the chain
+        a.sdesc[sb + t] = make_int4(0, -1, 0, 0);
+        a.srow[sb + t] = 0;
+        a.scode[sb + t] = 0;
+    }
     atomicAdd(&sh_total, part);
     __syncthreads();
     if (lane == 0) a.score[x] = sh_total;
 }
 
-// Fourth pass, one lane per stretch: the stretch aligned end to end (Gotoh's
-// global form, H(0,0) = 0, H(i,0) = F(i,0) = -(go + ge*i), H(0,j) = E(0,j) =
-// -(go + ge*j)), codes per cell (bit 0 diagonal not taken, 1 E not taken,
-// 2 E extended, 3 F extended), then the traceback with the local alignment's
-// priorities into the center-star vector.  Stretches of a sequence touch
-// disjoint insertion slots; aligned words and the score are shared (atomics).
-__global__ void __launch_bounds__(256) nuc_stretch_kernel(NucArgs a) {
-    __shared__ int8_t smat[32 * 32];
-    for (int x = threadIdx.x; x < 1024; x += blockDim.x) {
-        const int r = x >> 5, q = x & 31;
-        smat[x] = (r < a.alpha && q < a.alpha) ? a.mat[r * a.alpha + q] : (int8_t)0;
-    }
+// Fourth pass: each stretch aligned end to end (Gotoh's global form,
+// H(0,0) = 0, H(i,0) = -(go + ge*i), H(0,j) = -(go + ge*j), E(i,0) = F(0,j) =
+// -inf), codes per cell (bit 0 diagonal not taken, 1 E not taken, 2 E
+// extended, 3 F extended; eight cells per word, cw = ceil(ds / 8) words a
+// row), then the traceback with the local alignment's priorities into the
+// center-star vector.  Stretches of a sequence touch disjoint insertion slots;
+// aligned words and the score are shared (atomics).
+#define NUC_SMAT_SETUP                                                              \
+    __shared__ int8_t smat[32 * 32];                                                \
+    for (int x_ = threadIdx.x; x_ < 1024; x_ += blockDim.x) {                       \
+        const int r_ = x_ >> 5, q_ = x_ & 31;                                       \
+        smat[x_] = (r_ < a.alpha && q_ < a.alpha) ? a.mat[r_ * a.alpha + q_] : (int8_t)0; \
+    }                                                                               \
     __syncthreads();
-    const int64_t slot = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (slot >= a.nslot) return;
-    const int4 d = a.sdesc[slot];
-    const int dc = d.y;
-    if (dc < 0) return;
-    const int ci = d.x, sj = d.z, ds = d.w;
-    if (dc == 0 && ds == 0) return;   // adjacent anchors: nothing between them
-    const int x = a.sseq[slot];
-    const uint8_t *cc = a.center + ci, *ss = a.res + a.off[x] + sj;
-    const int m = a.m, go = a.go, ge = a.ge, goe = go + ge;
-    int2 *row = a.rows + a.srowoff[slot];
-    uint32_t *code0 = a.codes + a.scodeoff[slot];
-    uint16_t *ins = a.ins + (int64_t)x * (m + 1);
+
+// The traceback from (dc, ds) to (0, 0) over a stretch's codes: diagonal
+// steps mark center positions aligned, E steps count residues into the
+// insertion slot after their center position (a slot's count is written once,
+// with the merge's running max).
+__device__ __forceinline__ void nuc_traceback(const NucArgs &a, int x, int ci, int dc, int ds, const uint32_t *code0) {
+    const int cw = (ds + 7) >> 3;
+    uint16_t *ins = a.ins + (int64_t)x * (a.m + 1);
     uint32_t *al = a.aligned + (int64_t)x * a.aw;
     int32_t *gmax = (a.G && x != a.gskip) ? a.G : nullptr;
-    const int cw = (ds + 7) >> 3;   // code words per row
-    // forward: the row buffer holds (H, F) of the row above
-    for (int j = 0; j <= ds; ++j) row[j] = make_int2(j == 0 ? 0 : -(go + ge * j), kNucNeg);
-    for (int i = 1; i <= dc; ++i) {
-        const int cr = cc[i - 1] * 32;
-        int hdiag = row[0].x;
-        int hleft = -(go + ge * i), eleft = kNucNeg;
-        row[0] = make_int2(hleft, hleft);
-        uint32_t *crow = code0 + (int64_t)(i - 1) * cw;
-        uint32_t word = 0;
-        int2 upn = ds >= 1 ? row[1] : make_int2(0, 0);
-        for (int j = 1; j <= ds; ++j) {
-            const int2 up = upn;
-            if (j < ds) upn = row[j + 1];   // a cell ahead
-            const int e = max(eleft - ge, hleft - goe);
-            const int f = max(up.y - ge, up.x - goe);
-            const int dd = hdiag + smat[cr + ss[j - 1]];
-            const int h = max(dd, max(e, f));
-            const uint32_t nib = (uint32_t)(h != dd) | ((uint32_t)(h != e) << 1) |
-                                 ((uint32_t)(eleft - ge > hleft - goe) << 2) |
-                                 ((uint32_t)(up.y - ge > up.x - goe) << 3);
-            word |= nib << (4 * ((j - 1) & 7));
-            if (((j - 1) & 7) == 7 || j == ds) {
-                crow[(j - 1) >> 3] = word;
-                word = 0;
-            }
-            hdiag = up.x;
-            row[j] = make_int2(h, f);
-            hleft = h;
-            eleft = e;
-        }
-    }
-    atomicAdd(a.score + x, row[ds].x);   // H(dc, ds): the last row written (row 0 when dc = 0)
-    // traceback from (dc, ds) to (0, 0)
+    const int go = a.go;
     int i = dc, j = ds, st = 0;   // 0 H, 1 E, 2 F
     int sl = -1, scount = 0;
     int curw = -1;
@@ -423,6 +407,181 @@ __global__ void __launch_bounds__(256) nuc_stretch_kernel(NucArgs a) {
     if (curw >= 0) atomicOr(al + curw, bits);
 }
 
+// Stretches at most kNucSmallW columns wide, one lane each (over the list
+// a.slist[0 .. a.lcount[0])): the row of (H, F) sits in registers, the codes
+// go to the stretch's code region, then the lane's traceback reads them back.
+__global__ void __launch_bounds__(256) nuc_stretch_small_kernel(NucArgs a) {
+    NUC_SMAT_SETUP
+    const int ns = a.lcount[0];
+    const int go = a.go, ge = a.ge, goe = go + ge;
+    for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ns; base += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t li = base + threadIdx.x;
+        const bool act = li < ns;
+        const int64_t slot = act ? a.slist[li] : 0;
+        const int4 d = act ? a.sdesc[slot] : make_int4(0, 0, 0, 0);
+        const int ci = d.x, dc = d.y, sj = d.z, ds = d.w;
+        const int x = act ? a.sseq[slot] : 0;
+        // the widest stretch of the wavefront bounds the unrolled columns
+        int wmax = ds;
+        for (int o = 32; o >= 1; o >>= 1) wmax = max(wmax, __shfl_xor(wmax, o, 64));
+        wmax = __builtin_amdgcn_readfirstlane(wmax);
+        const uint8_t *cc = a.center + ci, *ss = a.res + a.off[x] + sj;
+        uint32_t *code0 = a.codes + a.scodeoff[slot];
+        const int cw = (ds + 7) >> 3;
+        uint32_t sw[kNucSmallW / 4];   // the stretch's residues, four per word
+#pragma unroll
+        for (int w = 0; w < kNucSmallW / 4; ++w) {
+            uint32_t v = 0;
+#pragma unroll
+            for (int b = 0; b < 4; ++b) {
+                const int jj = 4 * w + b;
+                if (jj < ds) v |= (uint32_t)ss[jj] << (8 * b);
+            }
+            sw[w] = v;
+        }
+        int H[kNucSmallW + 1], F[kNucSmallW + 1];
+#pragma unroll
+        for (int j = 0; j <= kNucSmallW; ++j) {
+            H[j] = j == 0 ? 0 : -(go + ge * j);
+            F[j] = kNucNeg;
+        }
+        int cnext = dc > 0 ? cc[0] : 0;
+        for (int i = 1; i <= dc; ++i) {
+            const int cr = cnext * 32;
+            if (i < dc) cnext = cc[i];   // a row ahead
+            int hdiag = H[0];
+            int hleft = -(go + ge * i), eleft = kNucNeg;
+            H[0] = hleft;
+            uint32_t *crow = code0 + (int64_t)(i - 1) * cw;
+            uint32_t word = 0;
+#pragma unroll
+            for (int j = 1; j <= kNucSmallW; ++j) {
+                if (j > wmax) continue;   // uniform: past the wavefront's widest stretch
+                const int e = max(eleft - ge, hleft - goe);
+                const int f = max(F[j] - ge, H[j] - goe);
+                const int dd = hdiag + smat[cr + ((sw[(j - 1) >> 2] >> (8 * ((j - 1) & 3))) & 255u)];
+                const int h = max(dd, max(e, f));
+                const uint32_t nib = (uint32_t)(h != dd) | ((uint32_t)(h != e) << 1) |
+                                     ((uint32_t)(eleft - ge > hleft - goe) << 2) |
+                                     ((uint32_t)(F[j] - ge > H[j] - goe) << 3);
+                word |= nib << (4 * ((j - 1) & 7));
+                if ((j & 7) == 0 || j == wmax) {
+                    if (((j - 1) >> 3) < cw) crow[(j - 1) >> 3] = word;
+                    word = 0;
+                }
+                hdiag = H[j];
+                H[j] = h;
+                F[j] = f;
+                hleft = h;
+                eleft = e;
+            }
+        }
+        int hend = H[0];   // H(dc, ds): the last row computed (row 0 when dc = 0)
+#pragma unroll
+        for (int j = 1; j <= kNucSmallW; ++j)
+            if (j == ds) hend = H[j];
+        if (act) {
+            atomicAdd(a.score + x, hend);
+            nuc_traceback(a, x, ci, dc, ds, code0);
+        }
+    }
+}
+
+// inclusive prefix max over the 64 lanes
+__device__ __forceinline__ int wave_prefix_max(int v, int lane) {
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int t = __shfl_up(v, d, 64);
+        if (lane >= d) v = max(v, t);
+    }
+    return v;
+}
+
+// Wider stretches, one wavefront each (over the list a.blist[0 ..
+// a.lcount[1])), in strips of 64 columns, lane L owning column 64 b + 1 + L of
+// strip b and keeping (H, F) of the row above in registers.  E along a row is a
+// max-plus scan: with Ht = max(D, F) and A(j) = Ht(i, j) + ge j,
+//   E(i, j) + ge j = max(E(i, jb) + ge jb, H(i, jb) + ge jb - go,
+//                        max over jb < j' < j of A(j') - go)
+// for the strip's left boundary jb (since E - ge >= E - go - ge, extending from
+// an E-derived H never beats the gap it continues).  The boundary column (H, E)
+// per row passes from strip to strip through the stretch's row region
+// (dc + 1 entries), 64 rows per coalesced load or store.
+__global__ void __launch_bounds__(64) nuc_stretch_wave_kernel(NucArgs a) {
+    NUC_SMAT_SETUP
+    const int lane = threadIdx.x;
+    const int nb = a.lcount[1];
+    const int go = a.go, ge = a.ge, goe = go + ge;
+    constexpr int kLow = -(1 << 30);
+    for (int li = blockIdx.x; li < nb; li += gridDim.x) {
+        const int64_t slot = a.blist[li];
+        const int4 d = a.sdesc[slot];
+        const int ci = d.x, dc = d.y, sj = d.z, ds = d.w;
+        const int x = a.sseq[slot];
+        const uint8_t *cc = a.center + ci, *ss = a.res + a.off[x] + sj;
+        int2 *bnd = a.rows + a.srowoff[slot];
+        uint32_t *code0 = a.codes + a.scodeoff[slot];
+        const int cw = (ds + 7) >> 3;
+        const int nstrip = (ds + 63) >> 6;
+        for (int b = 0; b < nstrip; ++b) {
+            const int jb = 64 * b;
+            const int j = jb + 1 + lane;
+            const bool inj = j <= ds;
+            const int sres = inj ? ss[j - 1] : 0;
+            int hp = -(go + ge * j), fp = kNucNeg;         // (H, F)(0, j)
+            int bh_prev = b == 0 ? 0 : -(go + ge * jb);    // H(0, jb)
+            for (int i0 = 1; i0 <= dc; i0 += 64) {
+                const int nr = min(64, dc - i0 + 1);
+                const int2 ld = (b > 0 && lane < nr) ? bnd[i0 + lane] : make_int2(0, 0);
+                const int crs = lane < nr ? cc[i0 - 1 + lane] : 0;
+                int2 out = make_int2(0, 0);
+                for (int r = 0; r < nr; ++r) {
+                    const int i = i0 + r;
+                    const int bh = b == 0 ? -(go + ge * i) : __shfl(ld.x, r, 64);   // H(i, jb)
+                    const int be = b == 0 ? kNucNeg : __shfl(ld.y, r, 64);          // E(i, jb)
+                    const int cr = __shfl(crs, r, 64) * 32;
+                    int hd = __shfl_up(hp, 1, 64);   // H(i-1, j-1)
+                    if (lane == 0) hd = bh_prev;
+                    const int dd = hd + smat[cr + sres];
+                    const int f = max(fp - ge, hp - goe);
+                    const int ht = max(dd, f);
+                    const int inc = wave_prefix_max(ht + ge * j, lane);
+                    int ex = __shfl_up(inc, 1, 64);
+                    if (lane == 0) ex = kLow;
+                    const int ehat = max(max(be + ge * jb, bh + ge * jb - go), ex - go);
+                    const int e = ehat - ge * j;
+                    const int h = max(ht, e);
+                    int el = __shfl_up(e, 1, 64), hl = __shfl_up(h, 1, 64);   // (E, H)(i, j-1)
+                    if (lane == 0) {
+                        el = be;
+                        hl = bh;
+                    }
+                    uint32_t nib = (uint32_t)(h != dd) | ((uint32_t)(h != e) << 1) |
+                                   ((uint32_t)(el - ge > hl - goe) << 2) | ((uint32_t)(fp - ge > hp - goe) << 3);
+                    if (!inj) nib = 0;
+                    uint32_t v = nib << (4 * (lane & 7));
+                    v |= __shfl_xor(v, 1, 64);
+                    v |= __shfl_xor(v, 2, 64);
+                    v |= __shfl_xor(v, 4, 64);
+                    const int w = 8 * b + (lane >> 3);
+                    if ((lane & 7) == 0 && w < cw) code0[(int64_t)(i - 1) * cw + w] = v;
+                    const int oh = __shfl(h, 63, 64), oe = __shfl(e, 63, 64);   // (H, E)(i, jb + 64)
+                    if (lane == r) out = make_int2(oh, oe);
+                    if (i == dc && j == ds) atomicAdd(a.score + x, h);   // H(dc, ds)
+                    bh_prev = bh;
+                    hp = h;
+                    fp = f;
+                }
+                if (b + 1 < nstrip && lane < nr) bnd[i0 + lane] = out;
+            }
+        }
+        if (dc == 0 && lane == 0) atomicAdd(a.score + x, -(go + ge * ds));   // H(0, ds)
+        __syncthreads();   // the codes, written by every lane, before lane 0 reads them
+        if (lane == 0) nuc_traceback(a, x, ci, dc, ds, code0);
+    }
+}
+
+#undef NUC_SMAT_SETUP
 #undef NUC_TABLE_SETUP
 
 // Exclusive prefix sums of n int64 values (one workgroup of 1024 lanes, each

@@ -107,3 +107,22 @@ def test_msa_long_center(H, ctx):
     assert msa.shape[1] == ref["width"]
     assert (msa.cpu().numpy() == ref["msa"]).all()
     assert (score.cpu().numpy() == ref["score"]).all()
+
+
+def test_stretch_widths(H, ctx):
+    """Stretches around the kernels' boundaries: up to 32 columns (one lane)
+    or wider (a wavefront, 64-column strips, 64-row boundary chunks), with
+    center spans of 0 .. 130 rows: a center region replaced by random bases."""
+    rng = np.random.default_rng(31)
+    c = rng.integers(0, 4, 1200).astype(np.uint8)
+    sizes = [0, 1, 15, 31, 32, 33, 47, 63, 64, 65, 96, 127, 129]
+    seqs = [c]
+    for h in sizes:
+        for w in sizes:
+            s0 = 160 + int(rng.integers(0, 16))
+            seqs.append(np.concatenate([c[:s0], rng.integers(0, 4, w).astype(np.uint8), c[s0 + h:]]))
+    seqs = synth.SeqSet.from_list(seqs)
+    sc, ins, al, G = _vectors(H, ctx, seqs, 0, 16)
+    wsc, wins, wal = _oracle_pairs(seqs, 0, 16)
+    assert (sc == wsc).all() and (ins == wins).all() and (al == wal).all()
+    assert (G == wins[1:].max(0)).all()
