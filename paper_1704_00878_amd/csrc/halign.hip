@@ -116,6 +116,7 @@ struct halign_ctx {
     int *flag_host = nullptr; // pinned: (tag << 8 | largest residue code) of the last validated call
     int64_t *mail_host = nullptr, *mail_dev = nullptr;   // coherent pinned mailbox: width, sequence number
     DevBuf nuctab, nucscr, nucdp;   // nucleotide path: segment table, matches and chains, stretch scratch
+    DevBuf rowck;                   // chunked rows: residues before each chunk of blocks, per row
     int64_t mail_seq = 0;
     uint32_t vtag = 0;        // tag of the last eager code check
     uint32_t *vflag = nullptr;   // the flag word those tags were raised in (cleared when it changes)
@@ -1158,7 +1159,7 @@ void halign_ctx_destroy(halign_ctx *ctx) {
     graph_drop(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf,
-                      &ctx->sbuf, &ctx->nuctab, &ctx->nucscr, &ctx->nucdp})
+                      &ctx->sbuf, &ctx->nuctab, &ctx->nucscr, &ctx->nucdp, &ctx->rowck})
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : ctx->mlp)
         if (b.p) (void)hipFree(b.p);
@@ -1547,9 +1548,31 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const 
     hipStream_t st = (hipStream_t)stream;
     const int N = seqs->n;
     if (N == 0 || width == 0) return HALIGN_OK;
+    const int m1 = m + 1, aw = (m + 31) / 32;
+    // long centers: tasks of (row, 256 blocks) after a per-row count pass
+    // (HALIGN_ROWS=chunk|lds picks a kernel for any center)
+    bool chunk_rows = m1 > hk::kRowsChunkMinBlocks;
+    if (const char *e = getenv("HALIGN_ROWS")) {
+        if (!strcmp(e, "chunk")) chunk_rows = true;
+        if (!strcmp(e, "lds")) chunk_rows = false;
+    }
+    if (chunk_rows) {
+        const int nck = (m1 + hk::kRowChunk - 1) / hk::kRowChunk;
+        RCHK(grow(ctx, ctx->rowck, 4 * (size_t)N * nck));
+        int32_t *ck = (int32_t *)ctx->rowck.p;
+        hk::RowsArgs ra{seqs->residues, seqs->offsets, N, m, ins, aligned, aw, G, col, width, 0, 0, 0, msa};
+        const int cgrid = std::max(1, std::min((N + 3) / 4, ctx->num_cu * 8));
+        hipLaunchKernelGGL(hk::rows_count_kernel, dim3(cgrid), dim3(256), 0, st, ra, ck, nck);
+        HCHK(hipGetLastError());
+        const int64_t ntask = (int64_t)N * nck;
+        const int egrid = (int)std::max<int64_t>(1, std::min<int64_t>((ntask + 3) / 4, (int64_t)ctx->num_cu * 8));
+        hipLaunchKernelGGL(hk::rows_chunk_kernel, dim3(egrid), dim3(256), 4 * (hk::kRowWin + 16), st, ra,
+                           (const int32_t *)ck, nck);
+        HCHK(hipGetLastError());
+        return HALIGN_OK;
+    }
     // LDS per wavefront: (m+1) block starts and counts, the aligned bits and
     // a chunk of ch columns
-    const int m1 = m + 1, aw = (m + 31) / 32;
     size_t lim = std::min<size_t>(ctx->lds_max, 64 * 1024);
     auto wave_bytes = [&](int ch) {
         const size_t h2 = ((size_t)m1 * 2 + 3) & ~(size_t)3;

@@ -330,6 +330,136 @@ __global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
     }
 }
 
+constexpr int kRowsChunkMinBlocks = 4096;   // centers with more blocks take the chunked row kernels
+constexpr int kRowChunk = 256;              // blocks per task, four per lane
+constexpr int kRowWin = 4096;               // LDS bytes of a task's column window
+
+// Chunked rows, first pass, one wavefront per row: ck[k][c] = residues of row
+// k before block c * kRowChunk (insertions plus aligned bits), lane L counting
+// blocks 4L .. 4L + 3 of each chunk (coalesced loads).
+__global__ void __launch_bounds__(256) rows_count_kernel(RowsArgs a, int32_t *ck, int nck) {
+    const int lane = threadIdx.x & 63;
+    const int wave = (int)((blockIdx.x * blockDim.x + threadIdx.x) >> 6);
+    const int nwave = (int)((gridDim.x * blockDim.x) >> 6);
+    const int m = a.m, m1 = m + 1;
+    for (int k = wave; k < a.nrows; k += nwave) {
+        const uint16_t *ir = a.ins + (int64_t)k * m1;
+        const uint32_t *ar = a.aligned + (int64_t)k * a.aw;
+        int run = 0;
+        for (int c = 0; c < nck; ++c) {
+            const int b = c * kRowChunk + 4 * lane;
+            int v = 0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                if (b + u < m1) v += (int)ir[b + u];
+            if (b < m) {   // blocks b .. b + 3 share an aligned word (b is a multiple of 4)
+                const uint32_t nb = (uint32_t)min(4, m - b);
+                v += __popc((ar[b >> 5] >> (b & 31)) & ((1u << nb) - 1u));
+            }
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+            if (lane == 0) ck[(int64_t)k * nck + c] = run;
+            run += v;
+        }
+    }
+}
+
+// Chunked rows, second pass: one wavefront per (row k, chunk c) task, lane L
+// owning blocks p = c * kRowChunk + 4L + u (u < 4).  Wave prefix sums over the
+// lanes give each lane its first residue (from ck) and first column (from
+// col[c * kRowChunk]); the chunk's columns are built in an LDS window of
+// kRowWin bytes at a time (filled with gaps, then each residue placed: block
+// p's insertion t at its column + t, its aligned residue at its column +
+// G[p]) and copied out with 16-byte stores, byte stores where a 16-byte word
+// is shared with a neighbouring chunk.  The window sits in LDS at the
+// output's misalignment, so aligned LDS words map onto aligned global words.
+__global__ void __launch_bounds__(256) rows_chunk_kernel(RowsArgs a, const int32_t *ck, int nck) {
+    extern __shared__ uint4 lds_rows[];
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    uint8_t *buf = reinterpret_cast<uint8_t *>(lds_rows) + wid * (kRowWin + 16);
+    uint4 *buf16 = reinterpret_cast<uint4 *>(buf);
+    const int m = a.m, m1 = m + 1;
+    const int64_t width = a.width;
+    const int64_t ntask = (int64_t)a.nrows * nck;
+    for (int64_t task = (int64_t)blockIdx.x * 4 + wid; task < ntask; task += (int64_t)gridDim.x * 4) {
+        const int k = (int)(task / nck), c = (int)(task - (int64_t)k * nck);
+        const int b = c * kRowChunk, bend = min(b + kRowChunk, m1);
+        const int64_t so = a.off[k];
+        const int n = (int)(a.off[k + 1] - so);
+        const uint8_t *s = a.res + so;
+        const uint16_t *ir = a.ins + (int64_t)k * m1;
+        const uint32_t *ar = a.aligned + (int64_t)k * a.aw;
+        const int p0 = b + 4 * lane;
+        int ni[4], gg[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            ni[u] = p0 + u < bend ? (int)ir[p0 + u] : 0;
+            gg[u] = p0 + u < bend ? a.G[p0 + u] : 0;
+        }
+        const uint32_t al4 = p0 < m ? (ar[p0 >> 5] >> (p0 & 31)) & ((1u << min(4, m - p0)) - 1u) : 0u;
+        int nres = 0, ncol = 0;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            nres += ni[u] + (int)((al4 >> u) & 1u);
+            ncol += p0 + u < bend ? gg[u] + (p0 + u < m ? 1 : 0) : 0;
+        }
+        int ir_ = nres, ic_ = ncol;   // inclusive prefix sums over the lanes
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t1 = __shfl_up(ir_, d, 64), t2 = __shfl_up(ic_, d, 64);
+            if (lane >= d) {
+                ir_ += t1;
+                ic_ += t2;
+            }
+        }
+        const int q0 = ck[task] + ir_ - nres;   // the lane's first residue
+        const int64_t colb = a.col[b];
+        const int64_t span = (bend < m1 ? a.col[bend] : width) - colb;
+        const int cl = ic_ - ncol;              // the lane's first column, relative to colb
+        uint8_t *row = a.msa + (int64_t)k * width;
+        const int a0 = (int)((uintptr_t)(row + colb) & 15);
+        for (int64_t x0 = 0; x0 < span; x0 += kRowWin) {
+            const int wl = (int)min<int64_t>(kRowWin, span - x0);
+            const int nw = (a0 + wl + 15) >> 4;
+            for (int q = lane; q < nw; q += 64) buf16[q] = make_uint4(~0u, ~0u, ~0u, ~0u);
+            __builtin_amdgcn_wave_barrier();
+            int cu = cl, qu = q0;
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (p0 + u < bend) {
+                    // insertions t at cu + t, for the t inside the window
+                    const int64_t t0 = max<int64_t>(0, x0 - cu), t1 = min<int64_t>(ni[u], x0 + wl - cu);
+                    for (int64_t t = t0; t < t1; ++t) {
+                        const int r = qu + (int)t;
+                        buf[a0 + (int)(cu + t - x0)] = r < n ? s[r] : (uint8_t)255;
+                    }
+                    qu += ni[u];
+                    if (p0 + u < m) {
+                        if ((al4 >> u) & 1u) {
+                            const int64_t pos = (int64_t)cu + gg[u] - x0;
+                            if (pos >= 0 && pos < wl) buf[a0 + (int)pos] = qu < n ? s[qu] : (uint8_t)255;
+                            ++qu;
+                        }
+                        cu += gg[u] + 1;
+                    } else {
+                        cu += gg[u];
+                    }
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+            uint8_t *dst = row + colb + x0 - a0;   // 16-byte aligned
+            for (int q = lane; q < nw; q += 64) {
+                const int b0 = 16 * q;
+                if (b0 >= a0 && b0 + 16 <= a0 + wl) {
+                    *reinterpret_cast<uint4 *>(dst + b0) = buf16[q];
+                } else {
+                    for (int e = max(b0, a0); e < min(b0 + 16, a0 + wl); ++e) dst[e] = buf[e];
+                }
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+    }
+}
+
 constexpr int kProfCols = 256;      // columns per workgroup (one per lane)
 constexpr int kProfMaxSlab = 65535; // rows per workgroup (16-bit partial counts)
 constexpr int kProfRows = 32;       // rows loaded per pass

@@ -87,6 +87,29 @@ def test_msa_wide_rows(H, ctx):
     assert (got == ref["msa"]).all()
 
 
+@pytest.mark.parametrize("kernel", ["chunk", "lds"])
+def test_rows_kernels(H, ctx, kernel, monkeypatch):
+    """Both row kernels on the same sets (each is the default for one range
+    of center lengths): the hand case, edge sets, wide rows, rows at every
+    alignment, a center longer than the lane kernel's threshold."""
+    monkeypatch.setenv("HALIGN_ROWS", kernel)
+    rng = np.random.default_rng(17)
+    base = synth.generate("plain64", n_seqs=12)
+    sets = [
+        synth.SeqSet.from_list([base.seq(0), np.zeros(0, np.uint8), base.seq(0), base.seq(3)[:5],
+                                rng.integers(0, 20, size=300).astype(np.uint8), base.seq(9)]),
+        synth.SeqSet.from_list([base.seq(1), rng.integers(0, 20, size=3000).astype(np.uint8)]
+                               + [base.seq(k % 12)[: 20 + 9 * k] for k in range(40)]),
+        synth.SeqSet.from_list([rng.integers(0, 20, size=5000).astype(np.uint8)]
+                               + [base.seq(k) for k in range(12)] + [np.zeros(0, np.uint8)]),
+    ]
+    for seqs in sets:
+        got, _ = _msa(H, ctx, seqs, 0)
+        ref = oracle.msa(synth.BLOSUM62, 11, 1, seqs.residues, seqs.offsets, 0)
+        assert got.shape == ref["msa"].shape
+        assert (got == ref["msa"]).all()
+
+
 def test_merge_and_rows_calls(H, ctx):
     """halign_merge and halign_emit_rows on oracle-made center-star vectors."""
     import torch

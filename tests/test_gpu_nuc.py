@@ -99,8 +99,11 @@ def test_mito_like_subset(H, ctx):
     assert (sc == wsc).all() and (ins == wins).all() and (al == wal).all()
 
 
-def test_msa_long_center(H, ctx):
-    """A 16.5 kb center: the rows need more LDS than 64 KiB per workgroup."""
+@pytest.mark.parametrize("kernel", ["chunk", "lds"])
+def test_msa_long_center(H, ctx, kernel, monkeypatch):
+    """A 16.5 kb center, with either row kernel (the LDS one needs more than
+    64 KiB per workgroup here)."""
+    monkeypatch.setenv("HALIGN_ROWS", kernel)
     seqs = synth.generate_dna("dna672", n_seqs=12, seed=5)
     ref = oracle.nuc_msa(NM, GO, GE, synth.NUC_K, seqs.residues, seqs.offsets)
     msa, score = H.halign_nuc_msa(ctx, H.Scoring(NM, GO, GE), H.DeviceSeqs(seqs), synth.NUC_K)
