@@ -2653,7 +2653,7 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
         for (int t = 0; t < k; ++t) {
             const int b = c[q * k + t];
             if (b > 3) clean[q] = 0;
-            kk = (kk << 2) | (unsigned long long)(b & 3);
+            kk |= (unsigned long long)(b & 3) << (2 * t);   // base t at bits 2t, 2t + 1
             segscore[q] += sc->matrix_host[b * sc->alphabet + b];
         }
         key[q] = kk;
@@ -2738,8 +2738,13 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
     a.gskip = center;
     int64_t *dtot = (int64_t *)(tb + o_tot);
     const unsigned cgrid = (unsigned)std::max<int64_t>(1, (nchunk + 255) / 256);
+    // wavefront scan: one chunk per wavefront, 16 per workgroup sharing the table
+    const unsigned wgrid_scan = (unsigned)std::max<int64_t>(1, std::min<int64_t>((nchunk + 15) / 16, (int64_t)ctx->num_cu * 3));
     if (nchunk > 0) {
-        hipLaunchKernelGGL(hk::nuc_count_kernel, dim3(cgrid), dim3(256), 0, st, a);
+        if (k <= hk::kNucWaveMaxK)
+            hipLaunchKernelGGL(hk::nuc_count_wave_kernel, dim3(wgrid_scan), dim3(1024), 0, st, a);
+        else
+            hipLaunchKernelGGL(hk::nuc_count_kernel, dim3(cgrid), dim3(256), 0, st, a);
         HCHK(hipGetLastError());
         hipLaunchKernelGGL(hk::widen_kernel, dim3(cgrid), dim3(256), 0, st, (const int32_t *)a.ccount, (int)nchunk,
                            (int64_t *)(tb + o_cw));
@@ -2775,7 +2780,10 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
     a.blist = (int32_t *)(sb + s_bl);
     a.lcount = (int32_t *)(tb + o_lc);
     if (nchunk > 0) {
-        hipLaunchKernelGGL(hk::nuc_store_kernel, dim3(cgrid), dim3(256), 0, st, a);
+        if (k <= hk::kNucWaveMaxK)
+            hipLaunchKernelGGL(hk::nuc_store_wave_kernel, dim3(wgrid_scan), dim3(1024), 0, st, a);
+        else
+            hipLaunchKernelGGL(hk::nuc_store_kernel, dim3(cgrid), dim3(256), 0, st, a);
         HCHK(hipGetLastError());
     }
     // LDS sized for twice the mean match count (a power of two, 64 ..
@@ -2784,7 +2792,7 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
     int cap = 64;
     while (cap < hk::kChainLdsMax && (int64_t)cap * N < 2 * nmt) cap *= 2;
     a.chain_cap = cap;
-    hipLaunchKernelGGL(hk::nuc_chain_kernel, dim3((unsigned)N), dim3(64), hk::nuc_chain_lds_bytes(cap), st, a);
+    hipLaunchKernelGGL(hk::nuc_chain_kernel, dim3((unsigned)N), dim3(64), hk::nuc_chain_lds_bytes(cap, aw), st, a);
     HCHK(hipGetLastError());
     // stretch scratch: row buffers and codes, one region per stretch
     int64_t nrow = 0, ncode = 0;

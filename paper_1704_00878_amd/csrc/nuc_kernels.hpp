@@ -26,8 +26,9 @@ struct NucArgs {
     int nseq;
     const uint8_t *center;    // the center's codes
     int m, k;
-    // segment table: T slots (power of two), key (2-bit packed string) and
-    // segment index (-1 = empty); segscore[q] = sum of S over segment q
+    // segment table: T slots (power of two), key (2-bit packed string, base
+    // t at bits 2t and 2t + 1) and segment index (-1 = empty); segscore[q] =
+    // sum of S over segment q
     const unsigned long long *tkey;
     const int32_t *tseg;
     int lg_t;
@@ -64,7 +65,7 @@ struct NucArgs {
     int32_t *lcount;
 };
 
-constexpr int kNucChunk = 256;   // match starts per scan lane
+constexpr int kNucChunk = 256;   // match starts per scan chunk
 constexpr int kNucSmallW = 32;   // stretches at most this many columns wide: one lane, the row in registers
 
 // The table's hash of a packed segment (the host fills the table with it).
@@ -128,7 +129,6 @@ __device__ __forceinline__ void nuc_scan_chunk(const NucArgs &a, const unsigned 
     const int n = (int)(a.off[x + 1] - so);
     const int k = a.k;
     const int p0 = c * kNucChunk, j1 = min(n, p0 + kNucChunk + k - 1);
-    const unsigned long long kmask = k >= 32 ? ~0ull : ((1ull << (2 * k)) - 1ull);
     const uintptr_t a0 = (uintptr_t)(a.res + so + p0);
     const uint32_t *w = reinterpret_cast<const uint32_t *>(a0 & ~(uintptr_t)3);
     const int sh0 = (int)(a0 & 3);
@@ -143,11 +143,149 @@ __device__ __forceinline__ void nuc_scan_chunk(const NucArgs &a, const unsigned 
             valid = 0;
             continue;
         }
-        key = ((key << 2) | b) & kmask;
+        key = (key >> 2) | ((unsigned long long)b << (2 * (k - 1)));   // base j - k + 1 + t at bits 2t
         if (++valid >= k) {
             const int q = nuc_lookup(tk, ts, a.lg_t, key);
             if (q >= 0) fn(q, j - k + 1);
         }
+    }
+}
+
+constexpr int kNucWaveMaxK = 29;   // the wavefront scan's window: k + 3 bases in 64 bits
+
+// The match starts p = p0 + 4 lane + r (r < 4) of chunk c of a sequence (its
+// residues at so, n of them), the
+// lanes of a wavefront sharing the chunk: returns q_r (the segment, or -1) in
+// q[r].  The chunk's bytes come in coalesced aligned words (one per lane, nine
+// more for the last k - 1 bases), are realigned to the chunk's start, turned
+// into 2-bit codes plus an invalid bit per base, and each lane gathers the
+// codes of its 32 bases (4 lane .. 4 lane + 31) from the next seven lanes.
+__device__ __forceinline__ void nuc_scan_wave(const NucArgs &a, const unsigned long long *tk, const int32_t *ts,
+                                              int64_t so, int n, int c, int lane, int q[4]) {
+    const int k = a.k;
+    const int p0 = c * kNucChunk;
+    const uint8_t *base = a.res + so;
+    const uintptr_t ad = (uintptr_t)(base + p0);
+    const uintptr_t A = ad & ~(uintptr_t)3;
+    const uint32_t sh = (uint32_t)(ad & 3);
+    const uintptr_t lim = (uintptr_t)(base + n);   // a word starting before it holds a byte of the sequence
+    const uint32_t d0 = A + 4 * (uintptr_t)lane < lim ? *reinterpret_cast<const uint32_t *>(A + 4 * lane) : 0u;
+    const uint32_t d1 =
+        (lane < 9 && A + 256 + 4 * (uintptr_t)lane < lim) ? *reinterpret_cast<const uint32_t *>(A + 256 + 4 * lane) : 0u;
+    // bytes p0 + 4 lane .. + 3 (e0) and p0 + 256 + 4 lane .. + 3 (e1, lanes < 8)
+    const uint32_t n0 = __shfl(d0, (lane + 1) & 63, 64), n1 = __shfl(d1, 0, 64), n1b = __shfl(d1, (lane + 1) & 63, 64);
+    const uint32_t e0 = (uint32_t)((((uint64_t)(lane < 63 ? n0 : n1) << 32) | d0) >> (8 * sh));
+    const uint32_t e1 = (uint32_t)((((uint64_t)n1b << 32) | d1) >> (8 * sh));
+    auto codes = [](uint32_t e) __attribute__((always_inline)) -> uint32_t {   // 2-bit codes | invalid bits << 8
+        uint32_t v = 0;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const uint32_t b = (e >> (8 * j)) & 255u;
+            v |= (b & 3u) << (2 * j);
+            v |= (uint32_t)(b > 3u) << (8 + j);
+        }
+        return v;
+    };
+    const uint32_t ca = codes(e0), cb = codes(e1);
+    uint64_t W = 0;   // base 4 lane + t at bits 2t
+    uint32_t V = 0;   // its invalid bit at bit t
+#pragma unroll
+    for (int d = 0; d < 8; ++d) {
+        const int src = lane + d;
+        const uint32_t va = __shfl(ca, src & 63, 64), vb = __shfl(cb, src & 63, 64);
+        const uint32_t v = src < 64 ? va : vb;
+        W |= (uint64_t)(v & 255u) << (8 * d);
+        V |= (v >> 8) << (4 * d);
+    }
+    const uint64_t kmask = (1ull << (2 * k)) - 1ull;
+    const uint32_t vmask = (1u << k) - 1u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int p = p0 + 4 * lane + r;
+        const bool ok = p + k <= n && ((V >> r) & vmask) == 0u;
+        q[r] = ok ? nuc_lookup(tk, ts, a.lg_t, (W >> (2 * r)) & kmask) : -1;
+    }
+}
+
+static_assert(kNucChunk == 4 * 64, "the wavefront scan takes four match starts per lane");
+
+// The wavefront's chunks [g, g1): an equal share of a.nchunk, contiguous so
+// that one search finds the first chunk's sequence and the rest follow it.
+__device__ __forceinline__ void nuc_wave_range(const NucArgs &a, int64_t &g, int64_t &g1) {
+    const int64_t nw = (int64_t)gridDim.x * (blockDim.x >> 6);
+    const int64_t w = (int64_t)blockIdx.x * (blockDim.x >> 6) + (threadIdx.x >> 6);
+    const int64_t per = (a.nchunk + nw - 1) / nw;
+    g = min(a.nchunk, w * per);
+    g1 = min(a.nchunk, g + per);
+}
+
+// First pass, wavefront form (k <= kNucWaveMaxK): matches per chunk.
+__global__ void __launch_bounds__(1024) nuc_count_wave_kernel(NucArgs a) {
+    NUC_TABLE_SETUP   // shared by the workgroup's 16 wavefronts
+    const int lane = threadIdx.x & 63;
+    int64_t g, g1;
+    nuc_wave_range(a, g, g1);
+    int x = 0, c = 0;
+    if (g < g1) nuc_chunk(a, g, x, c);
+    int64_t so = a.off[x], nb = a.cbase[x + 1];
+    int n = (int)(a.off[x + 1] - so);
+    for (; g < g1; ++g) {
+        if (g >= nb) {   // the next sequence with chunks
+            do ++x;
+            while (g >= a.cbase[x + 1]);
+            c = 0;
+            so = a.off[x];
+            n = (int)(a.off[x + 1] - so);
+            nb = a.cbase[x + 1];
+        }
+        int q[4];
+        nuc_scan_wave(a, tk, ts, so, n, c, lane, q);
+        int cnt = (q[0] >= 0) + (q[1] >= 0) + (q[2] >= 0) + (q[3] >= 0);
+#pragma unroll
+        for (int o = 32; o >= 1; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+        if (lane == 0) a.ccount[g] = cnt;
+        ++c;
+    }
+}
+
+// Second pass, wavefront form: the matches at their chunk's offset, in order
+// of p (lane by lane, then r).
+__global__ void __launch_bounds__(1024) nuc_store_wave_kernel(NucArgs a) {
+    NUC_TABLE_SETUP   // shared by the workgroup's 16 wavefronts
+    const int lane = threadIdx.x & 63;
+    int64_t g, g1;
+    nuc_wave_range(a, g, g1);
+    int x = 0, c = 0;
+    if (g < g1) nuc_chunk(a, g, x, c);
+    int64_t so = a.off[x], nb = a.cbase[x + 1];
+    int n = (int)(a.off[x + 1] - so);
+    for (; g < g1; ++g) {
+        if (g >= nb) {   // the next sequence with chunks
+            do ++x;
+            while (g >= a.cbase[x + 1]);
+            c = 0;
+            so = a.off[x];
+            n = (int)(a.off[x + 1] - so);
+            nb = a.cbase[x + 1];
+        }
+        int q[4];
+        nuc_scan_wave(a, tk, ts, so, n, c, lane, q);
+        const int cnt = (q[0] >= 0) + (q[1] >= 0) + (q[2] >= 0) + (q[3] >= 0);
+        int inc = cnt;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t;
+        }
+        int64_t at = a.cmoff[g] + inc - cnt;
+        const int p = c * kNucChunk + 4 * lane;
+#pragma unroll
+        for (int r = 0; r < 4; ++r)
+            if (q[r] >= 0) {
+                a.mq[at] = q[r];
+                a.mp[at] = p + r;
+                ++at;
+            }
+        ++c;
     }
 }
 
@@ -187,19 +325,10 @@ template <typename TM, typename TI>
 __device__ __forceinline__ int nuc_chain_seq(const TM *mq, const TM *mp, TI *mbest, TI *mpred, TI *tails, int cnt,
                                              int k) {
     int L = 0, ins_next = 0;
-    int lastq = -1;   // q of tails[L]
-    auto insert = [&](int j) __attribute__((always_inline)) {
-        const int bj = (int)mbest[j];
-        const int qj = (int)mq[j];
-        if (bj > L) {
-            tails[bj] = (TI)j;
-            L = bj;
-            lastq = qj;
-        } else if (qj < (int)mq[tails[bj]]) {
-            tails[bj] = (TI)j;
-            if (bj == L) lastq = qj;
-        }
-    };
+    int lastq = -1, lastj = 0;   // q and index of tails[L]
+    // the previous match's fields stay in registers: it is usually the next
+    // one inserted (matches lie about k apart in p)
+    int qprev = 0, pprev = 0, bprev = 0;
     int qn = cnt > 0 ? (int)mq[0] : 0, pn = cnt > 0 ? (int)mp[0] : 0;
     for (int i = 0; i < cnt; ++i) {
         const int q = qn, p = pn;
@@ -207,10 +336,30 @@ __device__ __forceinline__ int nuc_chain_seq(const TM *mq, const TM *mp, TI *mbe
             qn = (int)mq[i + 1];
             pn = (int)mp[i + 1];
         }
-        while (ins_next < i && (int)mp[ins_next] + k <= p) insert(ins_next++);
-        int lq = 0;
+        while (ins_next < i) {
+            const bool reg = ins_next == i - 1;
+            const int pj = reg ? pprev : (int)mp[ins_next];
+            if (pj + k > p) break;
+            const int j = ins_next++;
+            const int bj = reg ? bprev : (int)mbest[j];
+            const int qj = reg ? qprev : (int)mq[j];
+            if (bj > L) {
+                tails[bj] = (TI)j;
+                L = bj;
+                lastq = qj;
+                lastj = j;
+            } else if (qj < (int)mq[tails[bj]]) {
+                tails[bj] = (TI)j;
+                if (bj == L) {
+                    lastq = qj;
+                    lastj = j;
+                }
+            }
+        }
+        int lq = 0, pred = 0;   // pred unused for lq = 0
         if (L > 0 && lastq < q) {
             lq = L;
+            pred = lastj;
         } else {
             int lo = 1, hi = L;   // largest l in [1, L] with q(tails[l]) < q
             while (lo <= hi) {
@@ -218,11 +367,25 @@ __device__ __forceinline__ int nuc_chain_seq(const TM *mq, const TM *mp, TI *mbe
                 if ((int)mq[tails[mid]] < q) { lq = mid; lo = mid + 1; }
                 else hi = mid - 1;
             }
+            if (lq > 0) pred = (int)tails[lq];
         }
         mbest[i] = (TI)(lq + 1);
-        mpred[i] = (TI)(lq > 0 ? (int)tails[lq] : 0);   // unused for lq = 0
+        mpred[i] = (TI)pred;
+        qprev = q;
+        pprev = p;
+        bprev = lq + 1;
     }
-    while (ins_next < cnt) insert(ins_next++);
+    while (ins_next < cnt) {
+        const int j = ins_next++;
+        const int bj = (int)mbest[j];
+        const int qj = (int)mq[j];
+        if (bj > L) {
+            tails[bj] = (TI)j;
+            L = bj;
+        } else if (qj < (int)mq[tails[bj]]) {
+            tails[bj] = (TI)j;
+        }
+    }
     // the chain, in order, into tails[0 .. L-1] (tails[L] is its last match)
     int e = L > 0 ? (int)tails[L] : 0;
     for (int t = L - 1; t >= 0; --t) {
@@ -234,8 +397,9 @@ __device__ __forceinline__ int nuc_chain_seq(const TM *mq, const TM *mp, TI *mbe
 
 constexpr int kChainLdsMax = 4096;   // matches of a sequence chained in LDS at most
 
-// LDS of the chain kernel for cap matches: five 16-bit arrays
-inline size_t nuc_chain_lds_bytes(int cap) { return (size_t)2 * (5 * (size_t)cap + 1); }
+// LDS of the chain kernel for cap matches and aw aligned words: five 16-bit
+// arrays, then the words (4-byte aligned)
+inline size_t nuc_chain_lds_bytes(int cap, int aw) { return (size_t)2 * ((5 * (size_t)cap + 2) & ~(size_t)1) + 4 * (size_t)aw; }
 
 // One 64-lane workgroup per sequence.  A sequence with at most a.chain_cap
 // matches has them staged in LDS (q, p < 65536 as 16-bit fields) and chained
@@ -247,7 +411,7 @@ __global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
     extern __shared__ uint16_t chain_lds[];
     const int cap = a.chain_cap;
     uint16_t *lq = chain_lds, *lp = lq + cap, *lbest = lp + cap, *lpred = lbest + cap, *ltails = lpred + cap;
-    __shared__ int sh_L, sh_total;
+    __shared__ int sh_L;
     const int x = blockIdx.x, lane = threadIdx.x;
     const int n = (int)(a.off[x + 1] - a.off[x]);
     const int k = a.k, m = a.m;
@@ -263,58 +427,61 @@ __global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
             lp[i] = (uint16_t)mp[i];
         }
     }
-    if (lane == 0) sh_total = 0;
     __syncthreads();
-    if (lane == 0)
+    auto qof = [&](int j) __attribute__((always_inline)) -> int { return inl ? (int)lq[j] : mq[j]; };
+    auto pof = [&](int j) __attribute__((always_inline)) -> int { return inl ? (int)lp[j] : mp[j]; };
+    // When every match follows the one before it (q larger, p at least k
+    // further), all of them form the one chain of length cnt, which is then
+    // the longest: checked by all lanes, no sequential pass.
+    bool ok = true;
+    for (int i = lane; i + 1 < cnt; i += 64) ok = ok && qof(i + 1) > qof(i) && pof(i + 1) >= pof(i) + k;
+    const bool ident = __ballot(!ok) == 0;
+    if (lane == 0 && !ident)
         sh_L = inl ? nuc_chain_seq(lq, lp, lbest, lpred, ltails, cnt, k)
                    : nuc_chain_seq(mq, mp, a.mbest + mb, a.mpred + mb, tails, cnt, k);
     __syncthreads();
-    const int L = sh_L;
+    const int L = ident ? cnt : sh_L;
     auto anchor = [&](int t) __attribute__((always_inline)) -> int {   // match index of anchor t < L
-        return inl ? (int)ltails[t] : tails[t];
+        return ident ? t : (inl ? (int)ltails[t] : tails[t]);
     };
-    auto qof = [&](int j) __attribute__((always_inline)) -> int { return inl ? (int)lq[j] : mq[j]; };
-    auto pof = [&](int j) __attribute__((always_inline)) -> int { return inl ? (int)lp[j] : mp[j]; };
     uint32_t *al = a.aligned + (int64_t)x * a.aw;
+    uint32_t *lal = reinterpret_cast<uint32_t *>(chain_lds + ((5 * cap + 2) & ~1));   // [aw]: the aligned bits
+    for (int w = lane; w < a.aw; w += 64) lal[w] = 0u;
+    __syncthreads();
     const uint64_t below = (1ull << lane) - 1ull;   // lanes under this one
-    int part = 0;
-    for (int t0 = 0; t0 <= L; t0 += 64) {   // the chain's slots: uniform trip count (ballots below)
-        const int t = t0 + lane;
-        const bool in = t <= L;
-        int ci = 0, sj = 0;   // just past the previous anchor
-        if (in && t > 0) {
+    // slot t of the chain (t <= L): the stretch from just past anchor t - 1 to
+    // anchor t (or the ends)
+    auto stretch = [&](int t, int &ci, int &sj, int &dc, int &ds, int &jt) __attribute__((always_inline)) {
+        ci = 0;
+        sj = 0;
+        if (t > 0) {
             const int jp = anchor(t - 1);
             ci = qof(jp) * k + k;
             sj = pof(jp) + k;
         }
-        const int jt = in && t < L ? anchor(t) : 0;
-        const int qc = t < L ? qof(jt) * k : m;
-        const int ps = t < L ? pof(jt) : n;
-        const int dc = qc - ci, ds = ps - sj;
-        // non-empty stretches into the lane list (narrow) or the wavefront list
-        const bool work = in && (dc > 0 || ds > 0);
+        jt = t < L ? anchor(t) : 0;
+        dc = (t < L ? qof(jt) * k : m) - ci;
+        ds = (t < L ? pof(jt) : n) - sj;
+    };
+    int part = 0, nsm = 0, nwd = 0;
+    for (int t = lane; t <= L; t += 64) {
+        int ci, sj, dc, ds, jt;
+        stretch(t, ci, sj, dc, ds, jt);
+        const bool work = dc > 0 || ds > 0;
         const bool wide = work && ds > kNucSmallW;
-        const uint64_t bs = __ballot(work && !wide), bw = __ballot(wide);
-        int os = 0, ow = 0;
-        if (lane == 0) {
-            if (bs) os = atomicAdd(a.lcount, __popcll(bs));
-            if (bw) ow = atomicAdd(a.lcount + 1, __popcll(bw));
-        }
-        os = __shfl(os, 0, 64);
-        ow = __shfl(ow, 0, 64);
-        if (work && !wide) a.slist[os + __popcll(bs & below)] = (int32_t)(sb + t);
-        if (wide) a.blist[ow + __popcll(bw & below)] = (int32_t)(sb + t);
-        if (!in) continue;
+        nsm += work && !wide;
+        nwd += wide;
         a.sdesc[sb + t] = make_int4(ci, dc, sj, ds);
         a.sseq[sb + t] = x;
         a.srow[sb + t] = wide ? dc + 1 : 0;   // the wavefront kernel's boundary column
         a.scode[sb + t] = (int64_t)dc * ((ds + 7) >> 3);
         if (t < L) {
             // center positions qc .. qc + k - 1 aligned
+            const int qc = ci + dc;
             for (int w = qc >> 5; w <= (qc + k - 1) >> 5; ++w) {
                 const int b0 = max(qc, w << 5) - (w << 5), b1 = min(qc + k, (w + 1) << 5) - (w << 5);
                 const uint32_t bits = (b1 - b0 == 32) ? ~0u : (((1u << (b1 - b0)) - 1u) << b0);
-                atomicOr(al + w, bits);
+                atomicOr(lal + w, bits);
             }
             part += a.segscore[qof(jt)];
         }
@@ -324,9 +491,37 @@ __global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
         a.srow[sb + t] = 0;
         a.scode[sb + t] = 0;
     }
-    atomicAdd(&sh_total, part);
+    // the sequence's list entries: one global atomic per list, then the
+    // non-empty stretches in slot order (narrow: one lane each; wide: a
+    // wavefront each)
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) {
+        part += __shfl_xor(part, o, 64);
+        nsm += __shfl_xor(nsm, o, 64);
+        nwd += __shfl_xor(nwd, o, 64);
+    }
+    int os = 0, ow = 0;
+    if (lane == 0) {
+        a.score[x] = part;
+        if (nsm) os = atomicAdd(a.lcount, nsm);
+        if (nwd) ow = atomicAdd(a.lcount + 1, nwd);
+    }
+    os = __shfl(os, 0, 64);
+    ow = __shfl(ow, 0, 64);
+    for (int t0 = 0; t0 <= L; t0 += 64) {   // uniform trip count (ballots)
+        const int t = t0 + lane;
+        int ci = 0, sj = 0, dc = 0, ds = 0, jt = 0;
+        if (t <= L) stretch(t, ci, sj, dc, ds, jt);
+        const bool work = t <= L && (dc > 0 || ds > 0);
+        const bool wide = work && ds > kNucSmallW;
+        const uint64_t bs = __ballot(work && !wide), bw = __ballot(wide);
+        if (work && !wide) a.slist[os + __popcll(bs & below)] = (int32_t)(sb + t);
+        if (wide) a.blist[ow + __popcll(bw & below)] = (int32_t)(sb + t);
+        os += __popcll(bs);
+        ow += __popcll(bw);
+    }
     __syncthreads();
-    if (lane == 0) a.score[x] = sh_total;
+    for (int w = lane; w < a.aw; w += 64) al[w] = lal[w];   // the row was zeroed; stretches OR in later
 }
 
 // Fourth pass: each stretch aligned end to end (Gotoh's global form,
