@@ -1566,7 +1566,7 @@ int halign_emit_rows(halign_ctx *ctx, const halign_seqs *seqs, int32_t m, const 
         HCHK(hipGetLastError());
         const int64_t ntask = (int64_t)N * nck;
         const int egrid = (int)std::max<int64_t>(1, std::min<int64_t>((ntask + 3) / 4, (int64_t)ctx->num_cu * 8));
-        hipLaunchKernelGGL(hk::rows_chunk_kernel, dim3(egrid), dim3(256), 4 * (hk::kRowWin + 16), st, ra,
+        hipLaunchKernelGGL(hk::rows_chunk_kernel, dim3(egrid), dim3(256), 4 * hk::kRowWave, st, ra,
                            (const int32_t *)ck, nck);
         HCHK(hipGetLastError());
         return HALIGN_OK;

@@ -332,7 +332,9 @@ __global__ void __launch_bounds__(64 * kWaveRows) rows_kernel(RowsArgs a) {
 
 constexpr int kRowsChunkMinBlocks = 4096;   // centers with more blocks take the chunked row kernels
 constexpr int kRowChunk = 256;              // blocks per task, four per lane
-constexpr int kRowWin = 4096;               // LDS bytes of a task's column window
+constexpr int kRowWin = 2048;               // LDS bytes of a task's column window
+constexpr int kRowRes = 2048;               // LDS bytes of a task's residues (more: read from global memory)
+constexpr int kRowWave = kRowWin + 16 + kRowRes;   // LDS bytes per wavefront
 
 // Chunked rows, first pass, one wavefront per row: ck[k][c] = residues of row
 // k before block c * kRowChunk (insertions plus aligned bits), lane L counting
@@ -367,17 +369,19 @@ __global__ void __launch_bounds__(256) rows_count_kernel(RowsArgs a, int32_t *ck
 // Chunked rows, second pass: one wavefront per (row k, chunk c) task, lane L
 // owning blocks p = c * kRowChunk + 4L + u (u < 4).  Wave prefix sums over the
 // lanes give each lane its first residue (from ck) and first column (from
-// col[c * kRowChunk]); the chunk's columns are built in an LDS window of
-// kRowWin bytes at a time (filled with gaps, then each residue placed: block
-// p's insertion t at its column + t, its aligned residue at its column +
-// G[p]) and copied out with 16-byte stores, byte stores where a 16-byte word
-// is shared with a neighbouring chunk.  The window sits in LDS at the
+// col[c * kRowChunk]); the chunk's residues are staged in LDS (coalesced), and
+// its columns are built in an LDS window of kRowWin bytes at a time (filled
+// with gaps, then each residue placed: block p's insertion t at its column +
+// t, its aligned residue at its column + G[p]) and copied out with 16-byte
+// stores, byte stores where a 16-byte word is shared with a neighbouring
+// chunk.  The window sits in LDS at the
 // output's misalignment, so aligned LDS words map onto aligned global words.
 __global__ void __launch_bounds__(256) rows_chunk_kernel(RowsArgs a, const int32_t *ck, int nck) {
     extern __shared__ uint4 lds_rows[];
     const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    uint8_t *buf = reinterpret_cast<uint8_t *>(lds_rows) + wid * (kRowWin + 16);
+    uint8_t *buf = reinterpret_cast<uint8_t *>(lds_rows) + wid * kRowWave;
     uint4 *buf16 = reinterpret_cast<uint4 *>(buf);
+    uint8_t *rbuf = buf + kRowWin + 16;   // the task's residues
     const int m = a.m, m1 = m + 1;
     const int64_t width = a.width;
     const int64_t ntask = (int64_t)a.nrows * nck;
@@ -411,7 +415,30 @@ __global__ void __launch_bounds__(256) rows_chunk_kernel(RowsArgs a, const int32
                 ic_ += t2;
             }
         }
-        const int q0 = ck[task] + ir_ - nres;   // the lane's first residue
+        const int qt = ck[task];                // the chunk's first residue
+        const int q0 = qt + ir_ - nres;         // the lane's first residue
+        // the chunk's residues qt .. qt + ntot - 1 into LDS (eight loads in
+        // flight per lane), when they fit
+        const int ntot = __shfl(ir_, 63, 64);
+        const bool rl = ntot <= kRowRes;
+        if (rl) {
+            for (int i0 = 0; i0 < ntot; i0 += 512) {
+                uint8_t v[8];
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = i0 + 64 * u + lane;
+                    v[u] = i < ntot && qt + i < n ? s[qt + i] : (uint8_t)255;
+                }
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    const int i = i0 + 64 * u + lane;
+                    if (i < ntot) rbuf[i] = v[u];
+                }
+            }
+        }
+        auto resid = [&](int r) __attribute__((always_inline)) -> uint8_t {
+            return rl ? rbuf[r - qt] : (r < n ? s[r] : (uint8_t)255);
+        };
         const int64_t colb = a.col[b];
         const int64_t span = (bend < m1 ? a.col[bend] : width) - colb;
         const int cl = ic_ - ncol;              // the lane's first column, relative to colb
@@ -428,15 +455,12 @@ __global__ void __launch_bounds__(256) rows_chunk_kernel(RowsArgs a, const int32
                 if (p0 + u < bend) {
                     // insertions t at cu + t, for the t inside the window
                     const int64_t t0 = max<int64_t>(0, x0 - cu), t1 = min<int64_t>(ni[u], x0 + wl - cu);
-                    for (int64_t t = t0; t < t1; ++t) {
-                        const int r = qu + (int)t;
-                        buf[a0 + (int)(cu + t - x0)] = r < n ? s[r] : (uint8_t)255;
-                    }
+                    for (int64_t t = t0; t < t1; ++t) buf[a0 + (int)(cu + t - x0)] = resid(qu + (int)t);
                     qu += ni[u];
                     if (p0 + u < m) {
                         if ((al4 >> u) & 1u) {
                             const int64_t pos = (int64_t)cu + gg[u] - x0;
-                            if (pos >= 0 && pos < wl) buf[a0 + (int)pos] = qu < n ? s[qu] : (uint8_t)255;
+                            if (pos >= 0 && pos < wl) buf[a0 + (int)pos] = resid(qu);
                             ++qu;
                         }
                         cu += gg[u] + 1;
