@@ -2706,7 +2706,7 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
         z.p[2] = (uint32_t *)G;
         z.n[2] = G ? m + 1 : 0;
         z.p[3] = (uint32_t *)(tb + o_lc);   // the stretch list counts
-        z.n[3] = 2;
+        z.n[3] = 3;
         z.tail16 = (n16 & 1) ? ins + (n16 - 1) : nullptr;
         hipLaunchKernelGGL(hk::zero_kernel, dim3(grid_for(z.n[0] + z.n[1], 256, 4096)), dim3(256), 0, st, z);
         HCHK(hipGetLastError());

@@ -59,14 +59,17 @@ struct NucArgs {
     int32_t *G;               // optional merge: max of ins over the sequences
     int gskip;                // sequence kept out of G
     int chain_cap;            // matches per sequence chained in LDS (<= kChainLdsMax)
-    // non-empty stretches: slots of the narrow ones (one lane each) and the
-    // wide ones (one wavefront each); lcount[0], lcount[1] their counts (zeroed)
+    // non-empty stretches: slots of the narrow ones (one lane each; lcount[0]
+    // of at most kNucTinyW x kNucTinyW from the front of slist, lcount[2]
+    // others from its back, nslot entries) and the wide ones (one wavefront
+    // each; lcount[1] in blist); counts zeroed before the chain kernel
     int32_t *slist, *blist;
     int32_t *lcount;
 };
 
 constexpr int kNucChunk = 256;   // match starts per scan chunk
 constexpr int kNucSmallW = 32;   // stretches at most this many columns wide: one lane, the row in registers
+constexpr int kNucTinyW = 20;    // narrow stretches at most this size both ways are listed apart
 
 // The table's hash of a packed segment (the host fills the table with it).
 __host__ __device__ __forceinline__ uint32_t nuc_hash(unsigned long long key, int lg_t) {
@@ -463,13 +466,18 @@ __global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
         dc = (t < L ? qof(jt) * k : m) - ci;
         ds = (t < L ? pof(jt) : n) - sj;
     };
-    int part = 0, nsm = 0, nwd = 0;
+    // narrow stretches: up to kNucTinyW x kNucTinyW from the front of the
+    // lane list, the others from its back, so most wavefronts get stretches
+    // of one size
+    auto tiny = [&](int dc, int ds) __attribute__((always_inline)) { return dc <= kNucTinyW && ds <= kNucTinyW; };
+    int part = 0, nsm = 0, nwd = 0, nti = 0;
     for (int t = lane; t <= L; t += 64) {
         int ci, sj, dc, ds, jt;
         stretch(t, ci, sj, dc, ds, jt);
         const bool work = dc > 0 || ds > 0;
         const bool wide = work && ds > kNucSmallW;
-        nsm += work && !wide;
+        nti += work && !wide && tiny(dc, ds);
+        nsm += work && !wide && !tiny(dc, ds);
         nwd += wide;
         a.sdesc[sb + t] = make_int4(ci, dc, sj, ds);
         a.sseq[sb + t] = x;
@@ -499,24 +507,32 @@ __global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
         part += __shfl_xor(part, o, 64);
         nsm += __shfl_xor(nsm, o, 64);
         nwd += __shfl_xor(nwd, o, 64);
+        nti += __shfl_xor(nti, o, 64);
     }
-    int os = 0, ow = 0;
+    int os = 0, ow = 0, ot = 0;
     if (lane == 0) {
         a.score[x] = part;
-        if (nsm) os = atomicAdd(a.lcount, nsm);
+        if (nti) ot = atomicAdd(a.lcount, nti);
         if (nwd) ow = atomicAdd(a.lcount + 1, nwd);
+        if (nsm) os = atomicAdd(a.lcount + 2, nsm);
     }
+    ot = __shfl(ot, 0, 64);
     os = __shfl(os, 0, 64);
     ow = __shfl(ow, 0, 64);
+    int32_t *sback = a.slist + a.nslot - 1;   // the back of the lane list, filled downwards
     for (int t0 = 0; t0 <= L; t0 += 64) {   // uniform trip count (ballots)
         const int t = t0 + lane;
         int ci = 0, sj = 0, dc = 0, ds = 0, jt = 0;
         if (t <= L) stretch(t, ci, sj, dc, ds, jt);
         const bool work = t <= L && (dc > 0 || ds > 0);
         const bool wide = work && ds > kNucSmallW;
-        const uint64_t bs = __ballot(work && !wide), bw = __ballot(wide);
-        if (work && !wide) a.slist[os + __popcll(bs & below)] = (int32_t)(sb + t);
+        const bool ti = work && !wide && tiny(dc, ds);
+        const bool sm = work && !wide && !ti;
+        const uint64_t bt = __ballot(ti), bs = __ballot(sm), bw = __ballot(wide);
+        if (ti) a.slist[ot + __popcll(bt & below)] = (int32_t)(sb + t);
+        if (sm) sback[-(int64_t)(os + __popcll(bs & below))] = (int32_t)(sb + t);
         if (wide) a.blist[ow + __popcll(bw & below)] = (int32_t)(sb + t);
+        ot += __popcll(bt);
         os += __popcll(bs);
         ow += __popcll(bw);
     }
@@ -607,12 +623,12 @@ __device__ __forceinline__ void nuc_traceback(const NucArgs &a, int x, int ci, i
 // go to the stretch's code region, then the lane's traceback reads them back.
 __global__ void __launch_bounds__(256) nuc_stretch_small_kernel(NucArgs a) {
     NUC_SMAT_SETUP
-    const int ns = a.lcount[0];
+    const int nt = a.lcount[0], ns = nt + a.lcount[2];   // the front's entries, then the back's
     const int go = a.go, ge = a.ge, goe = go + ge;
     for (int64_t base = (int64_t)blockIdx.x * blockDim.x; base < ns; base += (int64_t)gridDim.x * blockDim.x) {
         const int64_t li = base + threadIdx.x;
         const bool act = li < ns;
-        const int64_t slot = act ? a.slist[li] : 0;
+        const int64_t slot = act ? a.slist[li < nt ? li : a.nslot - 1 - (li - nt)] : 0;
         const int4 d = act ? a.sdesc[slot] : make_int4(0, 0, 0, 0);
         const int ci = d.x, dc = d.y, sj = d.z, ds = d.w;
         const int x = act ? a.sseq[slot] : 0;
@@ -640,10 +656,22 @@ __global__ void __launch_bounds__(256) nuc_stretch_small_kernel(NucArgs a) {
             H[j] = j == 0 ? 0 : -(go + ge * j);
             F[j] = kNucNeg;
         }
-        int cnext = dc > 0 ? cc[0] : 0;
+        // the center's bases eight rows at a time, the next eight loaded a
+        // group ahead
+        auto load8 = [&](int i0) __attribute__((always_inline)) -> uint64_t {
+            uint64_t v = 0;
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                if (i0 + u < dc) v |= (uint64_t)cc[i0 + u] << (8 * u);
+            return v;
+        };
+        uint64_t cwin = load8(0), cnext = load8(8);
         for (int i = 1; i <= dc; ++i) {
-            const int cr = cnext * 32;
-            if (i < dc) cnext = cc[i];   // a row ahead
+            if (((i - 1) & 7) == 0 && i > 1) {
+                cwin = cnext;
+                cnext = load8(i + 7);
+            }
+            const int cr = (int)((cwin >> (8 * ((i - 1) & 7))) & 255u) * 32;
             int hdiag = H[0];
             int hleft = -(go + ge * i), eleft = kNucNeg;
             H[0] = hleft;
