@@ -296,6 +296,8 @@ def main():
     ap.add_argument("--no-exact", action="store_true", help="learned report without the exhaustive center")
     ap.add_argument("--nucleotide", default="dna672", help="DNA set for the nucleotide center-star report "
                     "(none: skip)")
+    ap.add_argument("--nucleotide-only", action="store_true",
+                    help="run only the nucleotide report and print it as one JSON line (profiling)")
     ap.add_argument("--anchors", type=int, default=50000, help="training anchors")
     ap.add_argument("--partners", type=int, default=64, help="training partners per anchor")
     ap.add_argument("--epochs", type=int, default=1)
@@ -316,6 +318,10 @@ def main():
         _build.build()
     assert torch.cuda.is_available()
     torch.cuda.set_device(0)
+    if args.nucleotide_only:
+        nuc = nucleotide_report(H, H.Context(0), args.nucleotide, args.steps, 0 if args.no_cpu else 200)
+        print(json.dumps({"nucleotide": nuc}), flush=True)
+        return
     log(f"bench: generating {args.workload}")
     seqs = synth.generate(args.workload)
     center = 0
