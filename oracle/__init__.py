@@ -23,10 +23,11 @@ _lib = None
 
 
 def build(force: bool = True) -> str:
-    """Compile the oracle with gcc (-O2, single-threaded, no SIMD intrinsics)."""
+    """Compile the oracle with gcc (-O2, single-threaded, no SIMD intrinsics, no
+    fused multiply-add: every double operation rounds on its own)."""
     if force or not os.path.exists(LIB_PATH):
         tmp = LIB_PATH + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-Wall",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared", "-Wall",
                                "-o", tmp, _SRC])
         os.replace(tmp, LIB_PATH)
     return LIB_PATH
@@ -77,6 +78,16 @@ def lib():
         L.orc_column_profile.restype = I
         L.orc_sp_blosum.argtypes = [P, I, I, P, I, ctypes.c_int64]
         L.orc_sp_blosum.restype = ctypes.c_int64
+        L.orc_pdist_counts.argtypes = [P, ctypes.c_int64, I, I, P, P]
+        L.orc_pdist_counts.restype = None
+        L.orc_pdist.argtypes = [P, ctypes.c_int64, I, I]
+        L.orc_pdist.restype = ctypes.c_double
+        L.orc_nj.argtypes = [P, I, P, P]
+        L.orc_nj.restype = I
+        L.orc_nj_clusters.argtypes = [P, I, ctypes.c_int64, P, P, P]
+        L.orc_nj_clusters.restype = I
+        L.orc_nj_tree.argtypes = [P, I, ctypes.c_int64, P, P, P]
+        L.orc_nj_tree.restype = I
         _lib = L
     return _lib
 
@@ -319,3 +330,60 @@ def nuc_msa(S, go: int, ge: int, k: int, residues, offsets):
     al = al[:, :m].copy()
     msa_rows = rows(res, off, ins, al, G, int(W.value))
     return dict(score=score, ins=ins, aligned=al, G=G, col=col, width=int(W.value), msa=msa_rows)
+
+
+# ---------------------------------------------------------------------------
+# Phylogeny from the MSA (NJ section, Fig. 4): p-distances, neighbour joining,
+# the sampled clustering and the merged tree
+# ---------------------------------------------------------------------------
+def pdist_counts(msa_rows: np.ndarray):
+    """(mism, comp) int64 N x N: mismatching and compared (both non-gap) columns."""
+    a = _u8(msa_rows)
+    n, w = a.shape
+    mism = np.zeros((n, n), np.int64)
+    comp = np.zeros((n, n), np.int64)
+    mm, cc = ctypes.c_int64(0), ctypes.c_int64(0)
+    for i in range(n):
+        for j in range(n):
+            lib().orc_pdist_counts(_p(a), w, i, j, ctypes.byref(mm), ctypes.byref(cc))
+            mism[i, j], comp[i, j] = mm.value, cc.value
+    return mism, comp
+
+
+def pdist(msa_rows: np.ndarray) -> np.ndarray:
+    """N x N p-distances (1 where two rows share no compared column)."""
+    a = _u8(msa_rows)
+    n, w = a.shape
+    return np.array([[lib().orc_pdist(_p(a), w, i, j) for j in range(n)] for i in range(n)])
+
+
+def nj(D: np.ndarray):
+    """Neighbour joining over D: (parent, blen) per node, leaves 0..n-1 first."""
+    D = np.ascontiguousarray(D, dtype=np.float64)
+    n = D.shape[0]
+    parent = np.zeros(max(2 * n, 3), np.int32)
+    blen = np.zeros(max(2 * n, 3), np.float64)
+    nn = _check(lib().orc_nj(_p(D), n, _p(parent), _p(blen)))
+    return parent[:nn].copy(), blen[:nn].copy()
+
+
+def nj_clusters(msa_rows: np.ndarray, perm):
+    """(label per row, seed row per cluster) of the sampled clustering."""
+    a = _u8(msa_rows)
+    n, w = a.shape
+    perm = np.ascontiguousarray(perm, np.int32)
+    label = np.zeros(n, np.int32)
+    seed = np.zeros(n, np.int32)
+    K = _check(lib().orc_nj_clusters(_p(a), n, w, _p(perm), _p(label), _p(seed)))
+    return label, seed[:K].copy()
+
+
+def nj_tree(msa_rows: np.ndarray, perm):
+    """The merged tree: (parent, blen) per node, rows 0..N-1 first."""
+    a = _u8(msa_rows)
+    n, w = a.shape
+    perm = np.ascontiguousarray(perm, np.int32)
+    parent = np.zeros(2 * n + 2, np.int32)
+    blen = np.zeros(2 * n + 2, np.float64)
+    nn = _check(lib().orc_nj_tree(_p(a), n, w, _p(perm), _p(parent), _p(blen)))
+    return parent[:nn].copy(), blen[:nn].copy()

@@ -724,3 +724,293 @@ int orc_nuc_msa(const int8_t *S, int alpha, int go, int ge, int k,
     memset(aligned, 1, (size_t)m);
     return orc_merge(ins, nseq, m, G, col, width);
 }
+
+/* ========================================================================
+ * Phylogeny from the MSA (Methods, "NJ method for constructing phylogenetic
+ * trees with Spark", Fig. 4): pairwise distances between MSA rows, a sampled
+ * clustering, neighbour joining (Saitou and Nei, the paper's ref. 22) inside
+ * each cluster and over the clusters, the cluster trees grafted onto the
+ * cluster-level tree.  Readings this section fixes (the paper names the steps
+ * and nothing more):
+ *  - Distance: the p-distance of two rows, mismatching columns over the
+ *    columns where both rows hold a residue (any byte but the gap byte); 1
+ *    when no column qualifies.
+ *  - Neighbour joining: with m active nodes, r_i = sum over active k of
+ *    d(i, k) (summed in slot order), Q(i, j) = (m - 2) d(i, j) - r_i - r_j;
+ *    the pair with the smallest Q is joined, ties to the smallest i, then j
+ *    (i < j); branch lengths d(i, j) / 2 + (r_i - r_j) / (2 (m - 2)) and
+ *    d(i, j) minus that; the new node takes slot i, slot j is dropped, and
+ *    d(u, k) = (d(i, k) + d(j, k) - d(i, j)) / 2.  Three nodes left join at a
+ *    centre with the three-point lengths; two at a centre with d / 2 each.
+ *    Negative lengths are kept.  Every step is an IEEE double operation in
+ *    the order written (no fused multiply-add).
+ *  - Tree layout: nodes 0 .. n-1 are the leaves, joins number the new nodes
+ *    n, n + 1, ... in order; parent[] and blen[] per node, the root (the last
+ *    centre, or the single leaf) has parent -1.
+ *  - Clustering: the sample is the first ceil(N / 10) entries of a given
+ *    permutation (the random draw is an input); every row is labelled with
+ *    its nearest sample row (ties to the earlier sample position).  Then, once
+ *    and in cluster order, a cluster of fewer than 3 rows is merged into the
+ *    cluster whose seed is nearest its own seed (ties to the lower cluster;
+ *    not when it is the only cluster); then, once, a cluster of more than
+ *    ceil(N / 10) rows is divided: its first ceil(size / 10) rows in
+ *    permutation order become seeds and its rows are relabelled among them.
+ *    Clusters are numbered by their seeds' sample order (divided ones in
+ *    place, in their new seeds' order); a cluster left empty (its seed went
+ *    to an identical earlier seed) is dropped.
+ *  - Merge: neighbour joining over each cluster's rows (slots in row order)
+ *    and over the clusters' seeds (the cluster-level tree); each cluster's
+ *    root replaces the cluster's leaf in the cluster-level tree (keeping that
+ *    leaf's branch length).  Node numbering: rows 0 .. N-1, then each
+ *    cluster's internal nodes (cluster order), then the cluster-level tree's
+ *    internal nodes.
+ * ------------------------------------------------------------------------ */
+
+/* p-distance counts of rows a and b of an MSA with w columns. */
+void orc_pdist_counts(const uint8_t *msa, int64_t w, int a, int b, int64_t *mism, int64_t *comp)
+{
+    const uint8_t *x = msa + (size_t)a * w, *y = msa + (size_t)b * w;
+    int64_t mm = 0, cc = 0;
+    for (int64_t c = 0; c < w; c++) {
+        if (x[c] != ORC_GAP && y[c] != ORC_GAP) {
+            cc++;
+            if (x[c] != y[c]) mm++;
+        }
+    }
+    *mism = mm;
+    *comp = cc;
+}
+
+double orc_pdist(const uint8_t *msa, int64_t w, int a, int b)
+{
+    int64_t mm, cc;
+    orc_pdist_counts(msa, w, a, b, &mm, &cc);
+    return cc > 0 ? (double)mm / (double)cc : 1.0;
+}
+
+/* Neighbour joining over the n x n distance matrix D (row-major, symmetric,
+ * zero diagonal; not modified).  parent and blen take the tree (2n - 2 nodes
+ * for n >= 3, 3 for n = 2, 1 for n = 1); returns the node count or < 0. */
+int orc_nj(const double *D, int n, int *parent, double *blen)
+{
+    if (n < 1) return ORC_EINVAL;
+    double *d = malloc(sizeof(double) * (size_t)n * n);
+    double *r = malloc(sizeof(double) * (size_t)n);
+    int *id = malloc(sizeof(int) * (size_t)n);
+    char *act = malloc((size_t)n);
+    if (!d || !r || !id || !act) { free(d); free(r); free(id); free(act); return ORC_ENOMEM; }
+    memcpy(d, D, sizeof(double) * (size_t)n * n);
+    for (int s = 0; s < n; s++) { id[s] = s; act[s] = 1; }
+    int next = n, m = n;
+    while (m > 3) {
+        for (int i = 0; i < n; i++) {
+            if (!act[i]) continue;
+            double sum = 0.0;
+            for (int k = 0; k < n; k++)
+                if (act[k]) sum += d[(size_t)i * n + k];
+            r[i] = sum;
+        }
+        double best = 0.0;
+        int bi = -1, bj = -1;
+        for (int i = 0; i < n; i++) {
+            if (!act[i]) continue;
+            for (int j = i + 1; j < n; j++) {
+                if (!act[j]) continue;
+                const double q = (double)(m - 2) * d[(size_t)i * n + j] - r[i] - r[j];
+                if (bi < 0 || q < best) { best = q; bi = i; bj = j; }
+            }
+        }
+        const double dij = d[(size_t)bi * n + bj];
+        const double li = 0.5 * dij + (r[bi] - r[bj]) / (2.0 * (double)(m - 2));
+        const double lj = dij - li;
+        const int u = next++;
+        parent[id[bi]] = u; blen[id[bi]] = li;
+        parent[id[bj]] = u; blen[id[bj]] = lj;
+        for (int k = 0; k < n; k++) {
+            if (!act[k] || k == bi || k == bj) continue;
+            const double v = (d[(size_t)bi * n + k] + d[(size_t)bj * n + k] - dij) * 0.5;
+            d[(size_t)bi * n + k] = v;
+            d[(size_t)k * n + bi] = v;
+        }
+        act[bj] = 0;
+        id[bi] = u;
+        m--;
+    }
+    int s[3], t = 0;
+    for (int i = 0; i < n && t < 3; i++)
+        if (act[i]) s[t++] = i;
+    if (m == 3) {
+        const double dab = d[(size_t)s[0] * n + s[1]], dac = d[(size_t)s[0] * n + s[2]],
+                     dbc = d[(size_t)s[1] * n + s[2]];
+        const int u = next++;
+        parent[id[s[0]]] = u; blen[id[s[0]]] = (dab + dac - dbc) * 0.5;
+        parent[id[s[1]]] = u; blen[id[s[1]]] = (dab + dbc - dac) * 0.5;
+        parent[id[s[2]]] = u; blen[id[s[2]]] = (dac + dbc - dab) * 0.5;
+        parent[u] = -1; blen[u] = 0.0;
+    } else if (m == 2) {
+        const double dab = d[(size_t)s[0] * n + s[1]];
+        const int u = next++;
+        parent[id[s[0]]] = u; blen[id[s[0]]] = dab * 0.5;
+        parent[id[s[1]]] = u; blen[id[s[1]]] = dab * 0.5;
+        parent[u] = -1; blen[u] = 0.0;
+    } else {
+        parent[id[s[0]]] = -1; blen[id[s[0]]] = 0.0;
+    }
+    free(d); free(r); free(id); free(act);
+    return next;
+}
+
+/* The clusters of the reading above: label[x] = cluster of row x; returns
+ * the cluster count K (seed[c] = the seed row of cluster c) or < 0. */
+int orc_nj_clusters(const uint8_t *msa, int nseq, int64_t w, const int32_t *perm, int32_t *label, int32_t *seed)
+{
+    if (nseq < 1) return ORC_EINVAL;
+    const int S = (nseq + 9) / 10;
+    int K = S;
+    for (int c = 0; c < S; c++) seed[c] = perm[c];
+    for (int x = 0; x < nseq; x++) {   /* nearest sample row */
+        double best = 0.0;
+        int bc = -1;
+        for (int c = 0; c < S; c++) {
+            const double dd = orc_pdist(msa, w, x, seed[c]);
+            if (bc < 0 || dd < best) { best = dd; bc = c; }
+        }
+        label[x] = bc;
+    }
+    int *size = calloc((size_t)nseq + 1, sizeof(int));
+    int *map = malloc(sizeof(int) * ((size_t)nseq + 1));
+    if (!size || !map) { free(size); free(map); return ORC_ENOMEM; }
+    for (int x = 0; x < nseq; x++) size[label[x]]++;
+    /* merge clusters of fewer than 3 rows into the cluster of the nearest
+     * seed, once, in cluster order (sizes update as clusters merge) */
+    for (int c = 0; c < K && K > 1; c++) {
+        if (size[c] == 0 || size[c] >= 3) continue;
+        double best = 0.0;
+        int bc = -1;
+        for (int e = 0; e < K; e++) {
+            if (e == c || size[e] == 0) continue;
+            const double dd = orc_pdist(msa, w, seed[c], seed[e]);
+            if (bc < 0 || dd < best) { best = dd; bc = e; }
+        }
+        if (bc < 0) continue;   /* the only cluster left */
+        for (int x = 0; x < nseq; x++)
+            if (label[x] == c) label[x] = bc;
+        size[bc] += size[c];
+        size[c] = 0;
+    }
+    /* renumber the clusters left (in order) */
+    int K2 = 0;
+    for (int c = 0; c < K; c++) map[c] = size[c] > 0 ? K2++ : -1;
+    for (int c = 0; c < K; c++)
+        if (map[c] >= 0) { seed[map[c]] = seed[c]; size[map[c]] = size[c]; }
+    for (int x = 0; x < nseq; x++) label[x] = map[label[x]];
+    K = K2;
+    /* divide clusters of more than ceil(N / 10) rows, once: the new clusters
+     * take the place of the divided one, in their seeds' order */
+    int32_t *nseed = malloc(sizeof(int32_t) * (size_t)nseq);
+    int32_t *nlab = malloc(sizeof(int32_t) * (size_t)nseq);
+    int *rank = malloc(sizeof(int) * (size_t)nseq);   /* position of each row in perm */
+    if (!nseed || !nlab || !rank) { free(size); free(map); free(nseed); free(nlab); free(rank); return ORC_ENOMEM; }
+    for (int t = 0; t < nseq; t++) rank[perm[t]] = t;
+    int NK = 0;
+    for (int c = 0; c < K; c++) {
+        if (size[c] <= S) {
+            for (int x = 0; x < nseq; x++)
+                if (label[x] == c) nlab[x] = NK;
+            nseed[NK++] = seed[c];
+            continue;
+        }
+        const int ns = (size[c] + 9) / 10;
+        const int base = NK;
+        for (int t = 0; t < nseq && NK - base < ns; t++)   /* the cluster's rows in permutation order */
+            if (label[perm[t]] == c) nseed[NK++] = perm[t];
+        for (int x = 0; x < nseq; x++) {
+            if (label[x] != c) continue;
+            double best = 0.0;
+            int bc = -1;
+            for (int e = base; e < NK; e++) {
+                const double dd = orc_pdist(msa, w, x, nseed[e]);
+                if (bc < 0 || dd < best) { best = dd; bc = e; }
+            }
+            nlab[x] = bc;
+        }
+    }
+    (void)rank;
+    /* a seed that an identical earlier seed took leaves its cluster empty:
+     * drop empty clusters, keeping the order */
+    for (int c = 0; c < NK; c++) size[c] = 0;
+    for (int x = 0; x < nseq; x++) size[nlab[x]]++;
+    K2 = 0;
+    for (int c = 0; c < NK; c++) map[c] = size[c] > 0 ? K2++ : -1;
+    for (int c = 0; c < NK; c++)
+        if (map[c] >= 0) seed[map[c]] = nseed[c];
+    for (int x = 0; x < nseq; x++) label[x] = map[nlab[x]];
+    free(size); free(map); free(nseed); free(nlab); free(rank);
+    return K2;
+}
+
+/* The whole tree: clusters, neighbour joining in each cluster and over the
+ * cluster seeds, the merge.  parent / blen have room for 2 N nodes; returns
+ * the node count (the root is the node with parent -1) or < 0. */
+int orc_nj_tree(const uint8_t *msa, int nseq, int64_t w, const int32_t *perm, int32_t *parent, double *blen)
+{
+    if (nseq < 1) return ORC_EINVAL;
+    int32_t *label = malloc(sizeof(int32_t) * (size_t)nseq);
+    int32_t *seed = malloc(sizeof(int32_t) * (size_t)nseq);
+    int *croot = malloc(sizeof(int) * (size_t)nseq);
+    if (!label || !seed || !croot) { free(label); free(seed); free(croot); return ORC_ENOMEM; }
+    const int K = orc_nj_clusters(msa, nseq, w, perm, label, seed);
+    if (K < 0) { free(label); free(seed); free(croot); return K; }
+    int next = nseq;
+    int *rows = malloc(sizeof(int) * (size_t)nseq);
+    int *lp = malloc(sizeof(int) * 2 * (size_t)nseq);
+    double *lb = malloc(sizeof(double) * 2 * (size_t)nseq);
+    double *D = NULL;
+    int err = (!rows || !lp || !lb) ? ORC_ENOMEM : ORC_OK;
+    for (int c = 0; c < K && !err; c++) {
+        int n = 0;
+        for (int x = 0; x < nseq; x++)
+            if (label[x] == c) rows[n++] = x;
+        free(D);
+        D = malloc(sizeof(double) * (size_t)n * n);
+        if (!D) { err = ORC_ENOMEM; break; }
+        for (int a = 0; a < n; a++)
+            for (int b = 0; b < n; b++)
+                D[(size_t)a * n + b] = a == b ? 0.0 : orc_pdist(msa, w, rows[a], rows[b]);
+        const int nn = orc_nj(D, n, lp, lb);
+        if (nn < 0) { err = nn; break; }
+        /* local node v: a leaf (v < n) is rows[v], an internal one next + v - n */
+        for (int v = 0; v < nn; v++) {
+            const int gv = v < n ? rows[v] : next + v - n;
+            const int pv = lp[v];
+            parent[gv] = pv < 0 ? -1 : (pv < n ? rows[pv] : next + pv - n);
+            blen[gv] = lb[v];
+            if (pv < 0) croot[c] = gv;
+        }
+        next += nn - n;
+    }
+    if (!err) {   /* the cluster-level tree over the seeds */
+        free(D);
+        D = malloc(sizeof(double) * (size_t)K * K);
+        if (!D) err = ORC_ENOMEM;
+        else {
+            for (int a = 0; a < K; a++)
+                for (int b = 0; b < K; b++)
+                    D[(size_t)a * K + b] = a == b ? 0.0 : orc_pdist(msa, w, seed[a], seed[b]);
+            const int nn = orc_nj(D, K, lp, lb);
+            if (nn < 0) err = nn;
+            else {
+                /* leaf c of this tree is cluster c's root; internal nodes follow */
+                for (int v = 0; v < nn; v++) {
+                    const int gv = v < K ? croot[v] : next + v - K;
+                    const int pv = lp[v];
+                    parent[gv] = pv < 0 ? -1 : (pv < K ? croot[pv] : next + pv - K);
+                    blen[gv] = pv < 0 ? 0.0 : lb[v];
+                }
+                next += nn - K;
+            }
+        }
+    }
+    free(D); free(rows); free(lp); free(lb); free(label); free(seed); free(croot);
+    return err ? err : next;
+}
