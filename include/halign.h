@@ -404,6 +404,50 @@ int halign_sp_score(const halign_scoring *sc, const uint8_t *msa, int32_t n, int
 int halign_column_profile(const uint8_t *msa, int32_t n, int64_t width, int32_t alphabet,
                           int32_t *profile, void *stream);
 
+/* ---- phylogeny (Methods, "NJ method for constructing phylogenetic trees
+ * with Spark", Fig. 4) -------------------------------------------------------
+ * p-distances between MSA rows: D[i * nb + j] = (columns where rows a_rows[i]
+ * and b_rows[j] differ and both hold a residue, i.e. neither is HALIGN_GAP)
+ * / (columns where both hold a residue), 1.0 where no column qualifies.
+ * msa: device uint8 [n][width]; a_rows, b_rows: device int32 row indices
+ * (NULL: rows 0 .. na-1, 0 .. nb-1); D: device double [na][nb]; mism, comp:
+ * device int32 [na][nb] (the two counts) or NULL.  The counts are exact and
+ * the quotient is one IEEE division.  Asynchronous on stream. */
+int halign_pdist(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width, const int32_t *a_rows,
+                 int32_t na, const int32_t *b_rows, int32_t nb, double *D, int32_t *mism, int32_t *comp,
+                 void *stream);
+
+/* Neighbour joining (Saitou and Nei) over the n x n device distance matrix D
+ * (symmetric, zero diagonal; not modified): with m active nodes, r_i = sum
+ * over active k of d(i, k) in slot order, Q(i, j) = (m - 2) d(i, j) - r_i -
+ * r_j; the smallest Q is joined (ties to the smallest i, then j, i < j) with
+ * lengths d(i, j) / 2 + (r_i - r_j) / (2 (m - 2)) and d(i, j) minus that; the
+ * new node takes slot i, d(u, k) = (d(i, k) + d(j, k) - d(i, j)) / 2.  Three
+ * nodes left meet at a centre (three-point lengths), two at a centre (d / 2
+ * each).  Every double operation rounds on its own, in that order.  Output:
+ * parent_host, blen_host (host, 2n + 1 entries): nodes 0 .. n-1 are the
+ * leaves, joins number n, n + 1, ...; the root has parent -1; *nodes = the
+ * node count.  Synchronises. */
+int halign_nj(halign_ctx *ctx, const double *D, int32_t n, int32_t *parent_host, double *blen_host,
+              int32_t *nodes, void *stream);
+
+/* The tree of an MSA (Fig. 4: sample, distances, clustering, per-cluster
+ * neighbour joining, merge).  perm_host: a permutation of 0 .. n-1 (the
+ * random draw; the sample is its first ceil(n / 10) rows).  Every row goes
+ * to its nearest sample row (ties to the earlier); then, once and in cluster
+ * order, a cluster of fewer than 3 rows joins the cluster whose seed is
+ * nearest its seed (ties to the lower cluster); then, once, a cluster of
+ * more than ceil(n / 10) rows is divided among its first ceil(size / 10) rows
+ * in permutation order (nearest, ties to the earlier); empty clusters are
+ * dropped.  Each cluster is joined (halign_nj over its rows in row order) and
+ * so are the clusters' seeds; each cluster's root replaces its leaf in the
+ * seeds' tree.  parent_host, blen_host: host, 2n + 2 entries; nodes 0 .. n-1
+ * are the rows, then each cluster's joins (cluster order), then the seeds'
+ * tree's joins; *nodes = the node count.  Scratch lives in the ctx (the
+ * distance matrices of the clusters and of the seeds).  Synchronises. */
+int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width, const int32_t *perm_host,
+                   int32_t *parent_host, double *blen_host, int32_t *nodes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -117,6 +117,9 @@ def lib():
         "halign_nuc_msa": ([P, P, P, I, I, P, _ALLOC_FN, P, P, P, P], I),
         "halign_sp_score": ([P, P, I, I64, P, P], I),
         "halign_column_profile": ([P, I, I64, I, P, P], I),
+        "halign_pdist": ([P, P, I, I64, P, I, P, I, P, P, P, P], I),
+        "halign_nj": ([P, P, I, P, P, P, P], I),
+        "halign_nj_tree": ([P, P, I, I64, P, P, P, P, P], I),
     }
     for name, (args, res) in sig.items():
         if not hasattr(L, name):
@@ -322,6 +325,83 @@ def halign_column_profile(msa, alphabet: int = 24, out=None, stream=None):
         out = torch.empty((w, alphabet + 1), dtype=torch.int32, device=msa.device)
     _check(lib().halign_column_profile(_ptr(msa), n, w, alphabet, _ptr(out), _stream(stream)))
     return out
+
+
+def halign_pdist(ctx: Context, msa, a_rows=None, b_rows=None, counts: bool = False, stream=None):
+    """p-distances between MSA rows (device uint8 [N, W]): float64 [na, nb]
+    device tensor (rows a_rows x b_rows, int32 device tensors; None: all
+    rows); with counts=True also the int32 mismatch and compared-column counts."""
+    import torch
+    n, w = msa.shape[0], msa.shape[1]
+    na = n if a_rows is None else a_rows.numel()
+    nb = n if b_rows is None else b_rows.numel()
+    dev = msa.device
+    D = torch.empty((na, nb), dtype=torch.float64, device=dev)
+    mm = torch.empty((na, nb), dtype=torch.int32, device=dev) if counts else None
+    cc = torch.empty((na, nb), dtype=torch.int32, device=dev) if counts else None
+    _check(lib().halign_pdist(ctx.h, _ptr(msa), n, w, _ptr(a_rows), na, _ptr(b_rows), nb, _ptr(D), _ptr(mm),
+                              _ptr(cc), _stream(stream)))
+    return (D, mm, cc) if counts else D
+
+
+def halign_nj(ctx: Context, D, stream=None):
+    """Neighbour joining over a float64 device distance matrix [n, n]:
+    (parent int32, blen float64) numpy arrays per node, leaves 0..n-1 first."""
+    n = D.shape[0]
+    parent = np.zeros(2 * n + 1, np.int32)
+    blen = np.zeros(2 * n + 1, np.float64)
+    nodes = ctypes.c_int32(0)
+    _check(lib().halign_nj(ctx.h, _ptr(D), n, parent.ctypes.data, blen.ctypes.data, ctypes.byref(nodes),
+                           _stream(stream)))
+    return parent[:nodes.value].copy(), blen[:nodes.value].copy()
+
+
+def halign_nj_tree(ctx: Context, msa, perm, stream=None):
+    """The tree of an MSA (device uint8 [N, W]) with the sample drawn by perm
+    (a permutation of 0..N-1): (parent int32, blen float64) numpy arrays per
+    node, rows 0..N-1 first."""
+    n, w = msa.shape[0], msa.shape[1]
+    perm = np.ascontiguousarray(perm, dtype=np.int32)
+    parent = np.zeros(2 * n + 2, np.int32)
+    blen = np.zeros(2 * n + 2, np.float64)
+    nodes = ctypes.c_int32(0)
+    _check(lib().halign_nj_tree(ctx.h, _ptr(msa), n, w, perm.ctypes.data, parent.ctypes.data, blen.ctypes.data,
+                                ctypes.byref(nodes), _stream(stream)))
+    return parent[:nodes.value].copy(), blen[:nodes.value].copy()
+
+
+def newick(parent, blen, names=None) -> str:
+    """Newick text of a (parent, blen) tree (leaves named by index unless names given)."""
+    nn = len(parent)
+    kids = [[] for _ in range(nn)]
+    root = -1
+    for v in range(nn):
+        if parent[v] < 0:
+            root = v
+        else:
+            kids[parent[v]].append(v)
+    out = []
+
+    def walk(v):   # iterative: deep trees
+        stack = [(v, 0)]
+        while stack:
+            x, k = stack.pop()
+            if k == 0 and kids[x]:
+                out.append("(")
+            if k < len(kids[x]):
+                if k > 0:
+                    out.append(",")
+                stack.append((x, k + 1))
+                stack.append((kids[x][k], 0))
+                continue
+            if kids[x]:
+                out.append(")")
+            else:
+                out.append(str(names[x]) if names is not None else str(x))
+            if parent[x] >= 0:
+                out.append(f":{blen[x]:.6g}")
+    walk(root)
+    return "".join(out) + ";"
 
 
 def halign_msa(ctx: Context, sc: Scoring, seqs: DeviceSeqs, center: int, model=None, stream=None, out=None):

@@ -28,6 +28,7 @@
 #include "strip_kernels.hpp"
 #include "walk_kernels.hpp"
 #include "nuc_kernels.hpp"
+#include "nj_kernels.hpp"
 #include "mlp_kernels.hpp"
 
 namespace {
@@ -117,6 +118,7 @@ struct halign_ctx {
     int64_t *mail_host = nullptr, *mail_dev = nullptr;   // coherent pinned mailbox: width, sequence number
     DevBuf nuctab, nucscr, nucdp;   // nucleotide path: segment table, matches and chains, stretch scratch
     DevBuf rowck;                   // chunked rows: residues before each chunk of blocks, per row
+    DevBuf njrows, njD, njS;        // phylogeny: row lists and group tables, distance matrices, join scratch
     int64_t mail_seq = 0;
     uint32_t vtag = 0;        // tag of the last eager code check
     uint32_t *vflag = nullptr;   // the flag word those tags were raised in (cleared when it changes)
@@ -1159,7 +1161,8 @@ void halign_ctx_destroy(halign_ctx *ctx) {
     graph_drop(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf,
-                      &ctx->sbuf, &ctx->nuctab, &ctx->nucscr, &ctx->nucdp, &ctx->rowck})
+                      &ctx->sbuf, &ctx->nuctab, &ctx->nucscr, &ctx->nucdp, &ctx->rowck,
+                      &ctx->njrows, &ctx->njD, &ctx->njS})
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : ctx->mlp)
         if (b.p) (void)hipFree(b.p);
@@ -2845,6 +2848,330 @@ int halign_nuc_msa(halign_ctx *ctx, const halign_scoring *sc, const halign_seqs 
     RCHK(halign_emit_rows(ctx, seqs, m, ins, al, G, col, width, out, stream));
     *msa = out;
     *width_host = width;
+    return HALIGN_OK;
+}
+
+}  // extern "C"
+
+// ===========================================================================
+// Phylogeny (NJ section, Fig. 4): p-distances, neighbour joining, the sampled
+// clustering and the merged tree
+// ===========================================================================
+namespace {
+
+inline size_t al256z(size_t b) { return (b + 255) & ~(size_t)255; }
+
+// Upload rows and the group table, then one pdist launch over every group's
+// tiles.  Synchronises the stream after the upload (the host vectors may go).
+int pdist_groups(halign_ctx *ctx, const uint8_t *msa, int64_t width, const std::vector<int32_t> &rows,
+                 std::vector<hk::PdGroup> &groups, double *D, int32_t *mism, int32_t *comp, hipStream_t st) {
+    int64_t tiles = 0;
+    for (auto &g : groups) {
+        g.tiles_b = (g.nb + hk::kPdTile - 1) / hk::kPdTile;
+        g.tile0 = tiles;
+        tiles += (int64_t)((g.na + hk::kPdTile - 1) / hk::kPdTile) * g.tiles_b;
+    }
+    if (tiles == 0) return HALIGN_OK;
+    if (tiles > 0x7fffffff) return fail(HALIGN_E_UNSUPPORTED, "%lld distance tiles", (long long)tiles);
+    const size_t o_g = al256z(4 * rows.size());
+    RCHK(grow(ctx, ctx->njrows, o_g + sizeof(hk::PdGroup) * groups.size()));
+    char *b = (char *)ctx->njrows.p;
+    if (!rows.empty()) HCHK(hipMemcpyAsync(b, rows.data(), 4 * rows.size(), hipMemcpyHostToDevice, st));
+    HCHK(hipMemcpyAsync(b + o_g, groups.data(), sizeof(hk::PdGroup) * groups.size(), hipMemcpyHostToDevice, st));
+    hk::PdArgs a{msa, width, (const int32_t *)b, (const hk::PdGroup *)(b + o_g), (int)groups.size(), D, mism, comp};
+    hipLaunchKernelGGL(hk::pdist_kernel, dim3((unsigned)tiles), dim3(256), 0, st, a);
+    HCHK(hipGetLastError());
+    HCHK(hipStreamSynchronize(st));
+    return HALIGN_OK;
+}
+
+// Neighbour joining over groups (each D at its d0 in dbase, modified); the
+// trees come back to the host: tree g at t0 = 2 * (sum of earlier n) + g.
+int nj_groups(halign_ctx *ctx, std::vector<hk::NjGroup> &groups, double *dbase, std::vector<int32_t> &parent,
+              std::vector<double> &blen, std::vector<int32_t> &nodes, hipStream_t st) {
+    int64_t ns = 0, nt = 0;
+    int nmax = 0;
+    for (auto &g : groups) {
+        g.s0 = ns;
+        g.t0 = nt;
+        ns += g.n;
+        nt += 2 * (int64_t)g.n + 1;
+        nmax = std::max(nmax, g.n);
+    }
+    const size_t G = groups.size();
+    const size_t o_r = 0, o_id = al256z(8 * ns), o_p = o_id + al256z(4 * ns), o_b = o_p + al256z(4 * nt),
+                 o_nd = o_b + al256z(8 * nt), o_g = o_nd + al256z(4 * G), o_act = o_g + al256z(sizeof(hk::NjGroup) * G),
+                 bytes = o_act + al256z(ns);
+    RCHK(grow(ctx, ctx->njS, bytes));
+    char *b = (char *)ctx->njS.p;
+    HCHK(hipMemcpyAsync(b + o_g, groups.data(), sizeof(hk::NjGroup) * G, hipMemcpyHostToDevice, st));
+    hk::NjArgs a{(const hk::NjGroup *)(b + o_g), dbase, (double *)(b + o_r), (uint8_t *)(b + o_act),
+                 (int32_t *)(b + o_id), (int32_t *)(b + o_p), (double *)(b + o_b), (int32_t *)(b + o_nd)};
+    const int bs = nmax > 2048 ? 1024 : nmax > 256 ? 512 : 256;
+    hipLaunchKernelGGL(hk::nj_kernel, dim3((unsigned)G), dim3(bs), 0, st, a);
+    HCHK(hipGetLastError());
+    parent.resize(nt);
+    blen.resize(nt);
+    nodes.resize(G);
+    HCHK(hipMemcpyAsync(parent.data(), b + o_p, 4 * nt, hipMemcpyDeviceToHost, st));
+    HCHK(hipMemcpyAsync(blen.data(), b + o_b, 8 * nt, hipMemcpyDeviceToHost, st));
+    HCHK(hipMemcpyAsync(nodes.data(), b + o_nd, 4 * G, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    return HALIGN_OK;
+}
+
+// labels[i] = nearest of the nb columns of D (na x nb, device), to the host
+int nearest_host(halign_ctx *ctx, const double *D, int na, int nb, std::vector<int32_t> &label, hipStream_t st) {
+    RCHK(grow(ctx, ctx->njS, al256z(4 * (size_t)na)));
+    int32_t *lab = (int32_t *)ctx->njS.p;
+    hipLaunchKernelGGL(hk::nearest_kernel, dim3((unsigned)((na + 255) / 256)), dim3(256), 0, st, D, (int64_t)nb, na,
+                       nb, lab);
+    HCHK(hipGetLastError());
+    label.resize(na);
+    HCHK(hipMemcpyAsync(label.data(), lab, 4 * (size_t)na, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    return HALIGN_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int halign_pdist(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width, const int32_t *a_rows, int32_t na,
+                 const int32_t *b_rows, int32_t nb, double *D, int32_t *mism, int32_t *comp, void *stream) {
+    if (!ctx || n < 0 || width < 0 || na < 0 || nb < 0 || ((int64_t)na * nb > 0 && (!D || (!msa && width > 0))))
+        return fail(HALIGN_E_INVALID, "bad arguments");
+    if ((!a_rows && na > n) || (!b_rows && nb > n)) return fail(HALIGN_E_INVALID, "row count above n");
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    if ((int64_t)na * nb == 0) return HALIGN_OK;
+    // the row lists: given ones copied into the ctx buffer behind an identity prefix
+    std::vector<int32_t> rows;
+    if (!a_rows || !b_rows) {
+        rows.resize(std::max(a_rows ? 0 : na, b_rows ? 0 : nb));
+        for (size_t x = 0; x < rows.size(); ++x) rows[x] = (int32_t)x;
+    }
+    const int64_t ida = (int64_t)rows.size();
+    std::vector<hk::PdGroup> groups(1);
+    hk::PdGroup &g = groups[0];
+    g.a0 = a_rows ? ida : 0;
+    g.b0 = b_rows ? ida + (a_rows ? na : 0) : 0;
+    g.na = na;
+    g.nb = nb;
+    g.o = 0;
+    g.ld = nb;
+    g.diag0 = 0;
+    rows.resize(ida + (a_rows ? na : 0) + (b_rows ? nb : 0));   // placeholders, filled on the device below
+    // upload the identity part with the table, then the given lists device to device
+    int64_t tiles = (int64_t)((na + hk::kPdTile - 1) / hk::kPdTile) * ((nb + hk::kPdTile - 1) / hk::kPdTile);
+    if (tiles > 0x7fffffff) return fail(HALIGN_E_UNSUPPORTED, "%lld distance tiles", (long long)tiles);
+    g.tiles_b = (nb + hk::kPdTile - 1) / hk::kPdTile;
+    g.tile0 = 0;
+    const size_t o_g = al256z(4 * rows.size());
+    RCHK(grow(ctx, ctx->njrows, o_g + sizeof(hk::PdGroup)));
+    char *b = (char *)ctx->njrows.p;
+    if (ida > 0) HCHK(hipMemcpyAsync(b, rows.data(), 4 * (size_t)ida, hipMemcpyHostToDevice, st));
+    if (a_rows) HCHK(hipMemcpyAsync(b + 4 * g.a0, a_rows, 4 * (size_t)na, hipMemcpyDeviceToDevice, st));
+    if (b_rows) HCHK(hipMemcpyAsync(b + 4 * g.b0, b_rows, 4 * (size_t)nb, hipMemcpyDeviceToDevice, st));
+    HCHK(hipMemcpyAsync(b + o_g, groups.data(), sizeof(hk::PdGroup), hipMemcpyHostToDevice, st));
+    hk::PdArgs a{msa, width, (const int32_t *)b, (const hk::PdGroup *)(b + o_g), 1, D, mism, comp};
+    hipLaunchKernelGGL(hk::pdist_kernel, dim3((unsigned)tiles), dim3(256), 0, st, a);
+    HCHK(hipGetLastError());
+    HCHK(hipStreamSynchronize(st));   // the host vectors above were copied from
+    return HALIGN_OK;
+}
+
+int halign_nj(halign_ctx *ctx, const double *D, int32_t n, int32_t *parent_host, double *blen_host, int32_t *nodes,
+              void *stream) {
+    if (!ctx || n < 1 || !D || !parent_host || !blen_host || !nodes) return fail(HALIGN_E_INVALID, "bad arguments");
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const size_t bytes = 8 * (size_t)n * n;
+    RCHK(grow(ctx, ctx->njD, bytes));
+    HCHK(hipMemcpyAsync(ctx->njD.p, D, bytes, hipMemcpyDeviceToDevice, st));
+    std::vector<hk::NjGroup> groups(1);
+    groups[0].n = n;
+    groups[0].d0 = 0;
+    std::vector<int32_t> parent, nd;
+    std::vector<double> blen;
+    RCHK(nj_groups(ctx, groups, (double *)ctx->njD.p, parent, blen, nd, st));
+    memcpy(parent_host, parent.data(), 4 * (size_t)nd[0]);
+    memcpy(blen_host, blen.data(), 8 * (size_t)nd[0]);
+    *nodes = nd[0];
+    return HALIGN_OK;
+}
+
+int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width, const int32_t *perm_host,
+                   int32_t *parent_host, double *blen_host, int32_t *nodes, void *stream) {
+    if (!ctx || n < 1 || width < 0 || (!msa && width > 0) || !perm_host || !parent_host || !blen_host || !nodes)
+        return fail(HALIGN_E_INVALID, "bad arguments");
+    {   // a permutation of 0 .. n-1
+        std::vector<char> seen(n, 0);
+        for (int t = 0; t < n; ++t) {
+            const int v = perm_host[t];
+            if (v < 0 || v >= n || seen[v]) return fail(HALIGN_E_INVALID, "perm is not a permutation of 0..%d", n - 1);
+            seen[v] = 1;
+        }
+    }
+    HCHK(hipSetDevice(ctx->device));
+    hipStream_t st = (hipStream_t)stream;
+    const int N = n, S = (N + 9) / 10;
+    std::vector<int32_t> seed(perm_host, perm_host + S);
+    // every row against the sample: nearest seed
+    std::vector<int32_t> label;
+    {
+        std::vector<int32_t> rows(N + S);
+        for (int x = 0; x < N; ++x) rows[x] = x;
+        for (int c = 0; c < S; ++c) rows[N + c] = seed[c];
+        std::vector<hk::PdGroup> gr(1);
+        gr[0] = hk::PdGroup{0, N, N, S, 0, S, 0, 0, 0};
+        RCHK(grow(ctx, ctx->njD, 8 * (size_t)N * S));
+        RCHK(pdist_groups(ctx, msa, width, rows, gr, (double *)ctx->njD.p, nullptr, nullptr, st));
+        RCHK(nearest_host(ctx, (const double *)ctx->njD.p, N, S, label, st));
+    }
+    int K = S;
+    std::vector<int> size(N + 1, 0);
+    for (int x = 0; x < N; ++x) size[label[x]]++;
+    // clusters of fewer than 3 rows join the cluster of the nearest seed
+    bool small = false;
+    for (int c = 0; c < K; ++c) small = small || (size[c] > 0 && size[c] < 3);
+    if (small && K > 1) {
+        std::vector<int32_t> rows(S);
+        for (int c = 0; c < S; ++c) rows[c] = seed[c];
+        std::vector<hk::PdGroup> gr(1);
+        gr[0] = hk::PdGroup{0, 0, S, S, 0, S, 0, 0, 0};
+        RCHK(grow(ctx, ctx->njD, 8 * (size_t)S * S));
+        RCHK(pdist_groups(ctx, msa, width, rows, gr, (double *)ctx->njD.p, nullptr, nullptr, st));
+        std::vector<double> drow(S);
+        for (int c = 0; c < K; ++c) {
+            if (size[c] == 0 || size[c] >= 3) continue;
+            HCHK(hipMemcpy(drow.data(), (const double *)ctx->njD.p + (size_t)c * S, 8 * (size_t)S,
+                           hipMemcpyDeviceToHost));
+            double best = 0.0;
+            int bc = -1;
+            for (int e = 0; e < K; ++e) {
+                if (e == c || size[e] == 0) continue;
+                if (bc < 0 || drow[e] < best) {
+                    best = drow[e];
+                    bc = e;
+                }
+            }
+            if (bc < 0) continue;
+            for (int x = 0; x < N; ++x)
+                if (label[x] == c) label[x] = bc;
+            size[bc] += size[c];
+            size[c] = 0;
+        }
+    }
+    {   // renumber the clusters left, in order
+        std::vector<int> map(K);
+        int K2 = 0;
+        for (int c = 0; c < K; ++c) map[c] = size[c] > 0 ? K2++ : -1;
+        for (int c = 0; c < K; ++c)
+            if (map[c] >= 0) {
+                seed[map[c]] = seed[c];
+                size[map[c]] = size[c];
+            }
+        for (int x = 0; x < N; ++x) label[x] = map[label[x]];
+        K = K2;
+    }
+    // clusters of more than ceil(N / 10) rows are divided, once
+    std::vector<int32_t> nseed, nlab(N);
+    for (int c = 0; c < K; ++c) {
+        if (size[c] <= S) {
+            for (int x = 0; x < N; ++x)
+                if (label[x] == c) nlab[x] = (int32_t)nseed.size();
+            nseed.push_back(seed[c]);
+            continue;
+        }
+        const int nsd = (size[c] + 9) / 10;
+        const int base = (int)nseed.size();
+        for (int t = 0; t < N && (int)nseed.size() - base < nsd; ++t)
+            if (label[perm_host[t]] == c) nseed.push_back(perm_host[t]);
+        std::vector<int32_t> rows, mem;
+        for (int x = 0; x < N; ++x)
+            if (label[x] == c) mem.push_back(x);
+        rows = mem;
+        rows.insert(rows.end(), nseed.begin() + base, nseed.end());
+        const int nm = (int)mem.size();
+        std::vector<hk::PdGroup> gr(1);
+        gr[0] = hk::PdGroup{0, nm, nm, nsd, 0, nsd, 0, 0, 0};
+        RCHK(grow(ctx, ctx->njD, 8 * (size_t)nm * nsd));
+        RCHK(pdist_groups(ctx, msa, width, rows, gr, (double *)ctx->njD.p, nullptr, nullptr, st));
+        std::vector<int32_t> lab;
+        RCHK(nearest_host(ctx, (const double *)ctx->njD.p, nm, nsd, lab, st));
+        for (int t = 0; t < nm; ++t) nlab[mem[t]] = base + lab[t];
+    }
+    {   // drop clusters left empty (a seed taken by an identical earlier one)
+        const int NK = (int)nseed.size();
+        std::vector<int> sz(NK, 0), map(NK);
+        for (int x = 0; x < N; ++x) sz[nlab[x]]++;
+        int K2 = 0;
+        for (int c = 0; c < NK; ++c) map[c] = sz[c] > 0 ? K2++ : -1;
+        seed.assign(K2, 0);
+        for (int c = 0; c < NK; ++c)
+            if (map[c] >= 0) seed[map[c]] = nseed[c];
+        for (int x = 0; x < N; ++x) label[x] = map[nlab[x]];
+        K = K2;
+    }
+    // distance matrices: each cluster over its rows (row order), then the seeds
+    std::vector<int32_t> rows;
+    std::vector<int64_t> coff(K + 1, 0);
+    std::vector<int> csize(K, 0);
+    for (int x = 0; x < N; ++x) csize[label[x]]++;
+    for (int c = 0; c < K; ++c) coff[c + 1] = coff[c] + csize[c];
+    rows.resize(N + K);
+    {
+        std::vector<int64_t> at(coff.begin(), coff.end() - 1);
+        for (int x = 0; x < N; ++x) rows[at[label[x]]++] = x;
+        for (int c = 0; c < K; ++c) rows[N + c] = seed[c];
+    }
+    std::vector<hk::PdGroup> gr(K + 1);
+    std::vector<hk::NjGroup> ng(K + 1);
+    int64_t dtot = 0;
+    for (int c = 0; c <= K; ++c) {
+        const int64_t r0 = c < K ? coff[c] : N;
+        const int sz = c < K ? csize[c] : K;
+        gr[c] = hk::PdGroup{r0, r0, sz, sz, dtot, sz, 1, 0, 0};
+        ng[c].n = sz;
+        ng[c].d0 = dtot;
+        dtot += (int64_t)sz * sz;
+    }
+    RCHK(grow(ctx, ctx->njD, 8 * (size_t)dtot));
+    RCHK(pdist_groups(ctx, msa, width, rows, gr, (double *)ctx->njD.p, nullptr, nullptr, st));
+    std::vector<int32_t> tp, tn;
+    std::vector<double> tb;
+    RCHK(nj_groups(ctx, ng, (double *)ctx->njD.p, tp, tb, tn, st));
+    // the merge, node numbering as documented
+    int next = N;
+    std::vector<int> croot(K);
+    for (int c = 0; c < K; ++c) {
+        const int nn = tn[c], sz = csize[c];
+        const int32_t *lp = tp.data() + ng[c].t0;
+        const double *lb = tb.data() + ng[c].t0;
+        const int32_t *mem = rows.data() + coff[c];
+        for (int v = 0; v < nn; ++v) {
+            const int gv = v < sz ? mem[v] : next + v - sz;
+            const int pv = lp[v];
+            parent_host[gv] = pv < 0 ? -1 : (pv < sz ? mem[pv] : next + pv - sz);
+            blen_host[gv] = lb[v];
+            if (pv < 0) croot[c] = gv;
+        }
+        next += nn - sz;
+    }
+    {
+        const int nn = tn[K];
+        const int32_t *lp = tp.data() + ng[K].t0;
+        const double *lb = tb.data() + ng[K].t0;
+        for (int v = 0; v < nn; ++v) {
+            const int gv = v < K ? croot[v] : next + v - K;
+            const int pv = lp[v];
+            parent_host[gv] = pv < 0 ? -1 : (pv < K ? croot[pv] : next + pv - K);
+            blen_host[gv] = pv < 0 ? 0.0 : lb[v];
+        }
+        next += nn - K;
+    }
+    *nodes = next;
     return HALIGN_OK;
 }
 

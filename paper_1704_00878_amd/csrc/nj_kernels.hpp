@@ -1,0 +1,308 @@
+// Phylogeny from the MSA for gfx950 (Methods, "NJ method for constructing
+// phylogenetic trees with Spark", Fig. 4): pairwise p-distances between MSA
+// rows, the nearest-seed labels of the sampled clustering, and neighbour
+// joining (Saitou and Nei) over distance matrices.
+//
+// Distances are integer counts (columns where both rows hold a residue, and
+// those of them that differ) turned into a double by one IEEE division, so
+// they are exact.  Neighbour joining does every double operation on its own
+// (the kernels turn floating-point contraction off, so no multiply and add
+// fuse) and in a fixed order (row sums in slot order), so the joins and
+// branch lengths are the same bits on any schedule of the lanes.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace hk {
+
+constexpr int kPdTile = 64;    // pairs per workgroup: 64 rows of A x 64 rows of B
+constexpr int kPdChunk = 64;   // columns staged per pass (16 words per row)
+constexpr int kPdStride = 17;  // LDS words per staged row (16 + 1: no bank conflicts between rows)
+
+// One group of pairs: rows rows[a0 + i] (i < na) against rows[b0 + j] (j <
+// nb); D[i * ld + j] (and the counts, when given) at out offset o.  diag0:
+// the group is square over the same rows and its diagonal is written as 0.
+struct PdGroup {
+    int64_t a0, b0;
+    int na, nb;
+    int64_t o, ld;
+    int diag0;
+    int tiles_b;      // ceil(nb / 64)
+    int64_t tile0;    // first tile of this group (prefix over groups)
+};
+
+struct PdArgs {
+    const uint8_t *msa;
+    int64_t width;
+    const int32_t *rows;
+    const PdGroup *groups;
+    int ngroups;
+    double *D;
+    int32_t *mism, *comp;   // optional
+};
+
+// bit 7 of each byte set when that byte of v is nonzero (no carries between bytes)
+__device__ __forceinline__ uint32_t nz_bytes(uint32_t v) {
+    return ((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v;
+}
+
+// A workgroup of 256 threads takes one 64 x 64 tile of a group's pairs; thread
+// (ty, tx) counts pairs (4 ty + i, 4 tx + j), i, j < 4.  Each pass stages 64
+// columns of the tile's 128 rows in LDS (gap bytes past the width or past the
+// group's rows, which count nowhere), then compares four columns per word:
+// both residues where neither byte is the gap (255), a mismatch where they
+// also differ.
+__global__ void __launch_bounds__(256) pdist_kernel(PdArgs a) {
+#pragma clang fp contract(off)
+    __shared__ uint32_t sa[kPdTile * kPdStride], sb[kPdTile * kPdStride];
+    // the group and tile of this workgroup
+    int lo = 0, hi = a.ngroups - 1;
+    const int64_t t = blockIdx.x;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (a.groups[mid].tile0 <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const PdGroup g = a.groups[lo];
+    const int64_t tl = t - g.tile0;
+    const int ta = (int)(tl / g.tiles_b), tb = (int)(tl - (int64_t)ta * g.tiles_b);
+    const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
+    // staging: thread tid loads 16 bytes of row (tid >> 2) of each operand
+    const int lr = tid >> 2, lb = 16 * (tid & 3);
+    const int ia = ta * kPdTile + lr, ib = tb * kPdTile + lr;
+    const uint8_t *pa = ia < g.na ? a.msa + (int64_t)a.rows[g.a0 + ia] * a.width : nullptr;
+    const uint8_t *pb = ib < g.nb ? a.msa + (int64_t)a.rows[g.b0 + ib] * a.width : nullptr;
+    uint32_t mm[4][4], cc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) mm[i][j] = cc[i][j] = 0u;
+    for (int64_t c0 = 0; c0 < a.width; c0 += kPdChunk) {
+        uint32_t wa[4], wb[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t va = 0, vb = 0;
+#pragma unroll
+            for (int y = 0; y < 4; ++y) {
+                const int64_t c = c0 + lb + 4 * q + y;
+                const uint32_t ba = (pa && c < a.width) ? pa[c] : 255u;
+                const uint32_t bb = (pb && c < a.width) ? pb[c] : 255u;
+                va |= ba << (8 * y);
+                vb |= bb << (8 * y);
+            }
+            wa[q] = va;
+            wb[q] = vb;
+        }
+        __syncthreads();   // the previous pass is done with the staged words
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            sa[lr * kPdStride + (lb >> 2) + q] = wa[q];
+            sb[lr * kPdStride + (lb >> 2) + q] = wb[q];
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int k = 0; k < kPdChunk / 4; ++k) {
+            uint32_t x[4], y[4], fx[4], fy[4];
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                x[i] = sa[(4 * ty + i) * kPdStride + k];
+                y[i] = sb[(4 * tx + i) * kPdStride + k];
+                fx[i] = nz_bytes(~x[i]) & 0x80808080u;   // not the gap
+                fy[i] = nz_bytes(~y[i]) & 0x80808080u;
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+#pragma unroll
+                for (int j = 0; j < 4; ++j) {
+                    const uint32_t both = fx[i] & fy[j];
+                    cc[i][j] += __popc(both);
+                    mm[i][j] += __popc(nz_bytes(x[i] ^ y[j]) & both);
+                }
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int r = ta * kPdTile + 4 * ty + i;
+        if (r >= g.na) continue;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+            const int s = tb * kPdTile + 4 * tx + j;
+            if (s >= g.nb) continue;
+            const int64_t o = g.o + (int64_t)r * g.ld + s;
+            double d = cc[i][j] > 0u ? (double)mm[i][j] / (double)cc[i][j] : 1.0;
+            if (g.diag0 && r == s) d = 0.0;
+            a.D[o] = d;
+            if (a.mism) a.mism[o] = (int32_t)mm[i][j];
+            if (a.comp) a.comp[o] = (int32_t)cc[i][j];
+        }
+    }
+}
+
+// label[i] = the first j with the smallest D[i * ld + j], j < nb (one lane per row).
+__global__ void __launch_bounds__(256) nearest_kernel(const double *D, int64_t ld, int na, int nb, int32_t *label) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= na) return;
+    const double *row = D + (int64_t)i * ld;
+    double best = row[0];
+    int bj = 0;
+    for (int j = 1; j < nb; ++j) {
+        const double v = row[j];
+        if (v < best) {
+            best = v;
+            bj = j;
+        }
+    }
+    label[i] = bj;
+}
+
+// One neighbour-joining problem: n x n matrix D (modified), tree out as
+// parent / blen over 2n nodes (leaves first), scratch r, act, id of n.
+struct NjGroup {
+    int n;
+    int64_t d0;     // offset of D in NjArgs::D
+    int64_t s0;     // offset of the n-entry scratch
+    int64_t t0;     // offset of the tree (2n + 1 entries)
+};
+
+struct NjArgs {
+    const NjGroup *groups;
+    double *D;
+    double *r;
+    uint8_t *act;
+    int32_t *id;
+    int32_t *parent;
+    double *blen;
+    int32_t *nodes;   // per group: node count
+};
+
+struct NjBest {
+    double q;
+    int i, j;
+};
+
+__device__ __forceinline__ bool nj_before(const NjBest &x, const NjBest &y) {   // x before y
+    if (y.i < 0) return x.i >= 0;
+    if (x.i < 0) return false;
+    if (x.q < y.q) return true;
+    if (y.q < x.q) return false;
+    return x.i < y.i || (x.i == y.i && x.j < y.j);
+}
+
+// One workgroup per problem: each join recomputes the row sums (one lane per
+// row, in slot order), finds the smallest Q (each lane its rows, then a
+// workgroup reduction in (Q, i, j) order), writes the two branch lengths and
+// updates row and column i for the new node.
+__global__ void __launch_bounds__(1024) nj_kernel(NjArgs a) {
+#pragma clang fp contract(off)
+    __shared__ NjBest red[32];
+    __shared__ int sh_i, sh_j;
+    const NjGroup g = a.groups[blockIdx.x];
+    const int n = g.n, tid = threadIdx.x, bs = blockDim.x;
+    double *D = a.D + g.d0;
+    double *r = a.r + g.s0;
+    uint8_t *act = a.act + g.s0;
+    int32_t *id = a.id + g.s0;
+    int32_t *parent = a.parent + g.t0;
+    double *blen = a.blen + g.t0;
+    for (int s = tid; s < n; s += bs) {
+        act[s] = 1;
+        id[s] = s;
+    }
+    __syncthreads();
+    int next = n, m = n;
+    while (m > 3) {
+        for (int i = tid; i < n; i += bs) {
+            if (!act[i]) continue;
+            double sum = 0.0;
+            const double *row = D + (int64_t)i * n;
+            for (int k = 0; k < n; ++k)
+                if (act[k]) sum = sum + row[k];
+            r[i] = sum;
+        }
+        __syncthreads();
+        const double f = (double)(m - 2);
+        NjBest b{0.0, -1, -1};
+        for (int i = tid; i < n; i += bs) {
+            if (!act[i]) continue;
+            const double ri = r[i];
+            const double *row = D + (int64_t)i * n;
+            for (int j = i + 1; j < n; ++j) {
+                if (!act[j]) continue;
+                const double q = f * row[j] - ri - r[j];
+                if (b.i < 0 || q < b.q) b = NjBest{q, i, j};
+            }
+        }
+        // the workgroup's first pair in (Q, i, j) order
+        for (int o = 32; o >= 1; o >>= 1) {
+            NjBest y{__shfl_xor(b.q, o, 64), __shfl_xor(b.i, o, 64), __shfl_xor(b.j, o, 64)};
+            if (nj_before(y, b)) b = y;
+        }
+        if ((tid & 63) == 0) red[tid >> 6] = b;
+        __syncthreads();
+        if (tid == 0) {
+            NjBest w = red[0];
+            for (int x = 1; x < (bs >> 6); ++x)
+                if (nj_before(red[x], w)) w = red[x];
+            const int bi = w.i, bj = w.j;
+            const double dij = D[(int64_t)bi * n + bj];
+            const double li = 0.5 * dij + (r[bi] - r[bj]) / (2.0 * f);
+            const double lj = dij - li;
+            parent[id[bi]] = next;
+            blen[id[bi]] = li;
+            parent[id[bj]] = next;
+            blen[id[bj]] = lj;
+            sh_i = bi;
+            sh_j = bj;
+        }
+        __syncthreads();
+        const int bi = sh_i, bj = sh_j;
+        const double dij = D[(int64_t)bi * n + bj];
+        for (int k = tid; k < n; k += bs) {
+            if (!act[k] || k == bi || k == bj) continue;
+            const double v = (D[(int64_t)bi * n + k] + D[(int64_t)bj * n + k] - dij) * 0.5;
+            D[(int64_t)bi * n + k] = v;
+            D[(int64_t)k * n + bi] = v;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            act[bj] = 0;
+            id[bi] = next;
+        }
+        ++next;
+        --m;
+        __syncthreads();
+    }
+    if (tid == 0) {
+        int s[3], c = 0;
+        for (int i = 0; i < n && c < 3; ++i)
+            if (act[i]) s[c++] = i;
+        if (m == 3) {
+            const double dab = D[(int64_t)s[0] * n + s[1]], dac = D[(int64_t)s[0] * n + s[2]],
+                         dbc = D[(int64_t)s[1] * n + s[2]];
+            parent[id[s[0]]] = next;
+            blen[id[s[0]]] = (dab + dac - dbc) * 0.5;
+            parent[id[s[1]]] = next;
+            blen[id[s[1]]] = (dab + dbc - dac) * 0.5;
+            parent[id[s[2]]] = next;
+            blen[id[s[2]]] = (dac + dbc - dab) * 0.5;
+            parent[next] = -1;
+            blen[next] = 0.0;
+            ++next;
+        } else if (m == 2) {
+            const double dab = D[(int64_t)s[0] * n + s[1]];
+            parent[id[s[0]]] = next;
+            blen[id[s[0]]] = dab * 0.5;
+            parent[id[s[1]]] = next;
+            blen[id[s[1]]] = dab * 0.5;
+            parent[next] = -1;
+            blen[next] = 0.0;
+            ++next;
+        } else {
+            parent[id[s[0]]] = -1;
+            blen[id[s[0]]] = 0.0;
+        }
+        a.nodes[blockIdx.x] = next;
+    }
+}
+
+}  // namespace hk

@@ -368,3 +368,10 @@ def generate_dna(cfg: DnaConfig | str, n_seqs: int | None = None, seed: int | No
             x[rng.random(len(x)) < cfg.p_n] = 4
         seqs.append(x)
     return SeqSet.from_list(seqs)
+
+
+def tree_permutation(n: int, seed: int | None = None) -> np.ndarray:
+    """The random draw of the tree stage: a seeded permutation of 0..n-1 (its
+    first ceil(n / 10) rows are the sample)."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(SEED_BASE + 20 if seed is None else seed)))
+    return rng.permutation(n).astype(np.int32)
