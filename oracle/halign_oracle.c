@@ -752,12 +752,15 @@ int orc_nuc_msa(const int8_t *S, int alpha, int go, int ge, int k,
  *    its nearest sample row (ties to the earlier sample position).  Then, once
  *    and in cluster order, a cluster of fewer than 3 rows is merged into the
  *    cluster whose seed is nearest its own seed (ties to the lower cluster;
- *    not when it is the only cluster); then, once, a cluster of more than
- *    ceil(N / 10) rows is divided: its first ceil(size / 10) rows in
- *    permutation order become seeds and its rows are relabelled among them.
+ *    not when it is the only cluster); then, until no cluster has more than
+ *    ceil(N / 10) rows ("divided ... until balanced construction"), each such
+ *    cluster is divided: its first ceil(size / 10) rows in permutation order
+ *    become seeds and its rows are relabelled among them (nearest, ties to
+ *    the earlier); when every row stays with one seed (near-identical rows),
+ *    it is cut into runs of ceil(N / 10) of its rows in permutation order.
  *    Clusters are numbered by their seeds' sample order (divided ones in
  *    place, in their new seeds' order); a cluster left empty (its seed went
- *    to an identical earlier seed) is dropped.
+ *    to an identical earlier seed) is dropped after each pass.
  *  - Merge: neighbour joining over each cluster's rows (slots in row order)
  *    and over the clusters' seeds (the cluster-level tree); each cluster's
  *    root replaces the cluster's leaf in the cluster-level tree (keeping that
@@ -905,48 +908,68 @@ int orc_nj_clusters(const uint8_t *msa, int nseq, int64_t w, const int32_t *perm
         if (map[c] >= 0) { seed[map[c]] = seed[c]; size[map[c]] = size[c]; }
     for (int x = 0; x < nseq; x++) label[x] = map[label[x]];
     K = K2;
-    /* divide clusters of more than ceil(N / 10) rows, once: the new clusters
-     * take the place of the divided one, in their seeds' order */
+    /* divide clusters of more than ceil(N / 10) rows until none is left: a
+     * cluster is replaced, in place, by the clusters of its first
+     * ceil(size / 10) rows in permutation order (its rows relabelled among
+     * them, nearest, ties to the earlier); when every row stays with one of
+     * them, by consecutive runs of ceil(N / 10) of its rows in permutation
+     * order instead; empty clusters are dropped after each pass */
     int32_t *nseed = malloc(sizeof(int32_t) * (size_t)nseq);
     int32_t *nlab = malloc(sizeof(int32_t) * (size_t)nseq);
-    int *rank = malloc(sizeof(int) * (size_t)nseq);   /* position of each row in perm */
-    if (!nseed || !nlab || !rank) { free(size); free(map); free(nseed); free(nlab); free(rank); return ORC_ENOMEM; }
-    for (int t = 0; t < nseq; t++) rank[perm[t]] = t;
-    int NK = 0;
-    for (int c = 0; c < K; c++) {
-        if (size[c] <= S) {
-            for (int x = 0; x < nseq; x++)
-                if (label[x] == c) nlab[x] = NK;
-            nseed[NK++] = seed[c];
-            continue;
-        }
-        const int ns = (size[c] + 9) / 10;
-        const int base = NK;
-        for (int t = 0; t < nseq && NK - base < ns; t++)   /* the cluster's rows in permutation order */
-            if (label[perm[t]] == c) nseed[NK++] = perm[t];
-        for (int x = 0; x < nseq; x++) {
-            if (label[x] != c) continue;
-            double best = 0.0;
-            int bc = -1;
-            for (int e = base; e < NK; e++) {
-                const double dd = orc_pdist(msa, w, x, nseed[e]);
-                if (bc < 0 || dd < best) { best = dd; bc = e; }
+    if (!nseed || !nlab) { free(size); free(map); free(nseed); free(nlab); return ORC_ENOMEM; }
+    for (;;) {
+        int big = 0;
+        for (int c = 0; c < K; c++) big |= size[c] > S;
+        if (!big) break;
+        int NK = 0;
+        for (int c = 0; c < K; c++) {
+            if (size[c] <= S) {
+                for (int x = 0; x < nseq; x++)
+                    if (label[x] == c) nlab[x] = NK;
+                nseed[NK++] = seed[c];
+                continue;
             }
-            nlab[x] = bc;
+            const int ns = (size[c] + 9) / 10;
+            const int base = NK;
+            for (int t = 0; t < nseq && NK - base < ns; t++)   /* the cluster's rows in permutation order */
+                if (label[perm[t]] == c) nseed[NK++] = perm[t];
+            int first = -1, split = 0;
+            for (int x = 0; x < nseq; x++) {
+                if (label[x] != c) continue;
+                double best = 0.0;
+                int bc = -1;
+                for (int e = base; e < NK; e++) {
+                    const double dd = orc_pdist(msa, w, x, nseed[e]);
+                    if (bc < 0 || dd < best) { best = dd; bc = e; }
+                }
+                nlab[x] = bc;
+                if (first < 0) first = bc;
+                else if (bc != first) split = 1;
+            }
+            if (!split) {   /* runs of S rows in permutation order */
+                NK = base;
+                int cnt = 0;
+                for (int t = 0; t < nseq; t++) {
+                    const int x = perm[t];
+                    if (label[x] != c) continue;
+                    if (cnt % S == 0) nseed[NK++] = x;
+                    nlab[x] = NK - 1;
+                    cnt++;
+                }
+            }
         }
+        /* drop empty clusters (a seed taken by an identical earlier seed), keeping the order */
+        for (int c = 0; c < NK; c++) size[c] = 0;
+        for (int x = 0; x < nseq; x++) size[nlab[x]]++;
+        K2 = 0;
+        for (int c = 0; c < NK; c++) map[c] = size[c] > 0 ? K2++ : -1;
+        for (int c = 0; c < NK; c++)
+            if (map[c] >= 0) { seed[map[c]] = nseed[c]; size[map[c]] = size[c]; }
+        for (int x = 0; x < nseq; x++) label[x] = map[nlab[x]];
+        K = K2;
     }
-    (void)rank;
-    /* a seed that an identical earlier seed took leaves its cluster empty:
-     * drop empty clusters, keeping the order */
-    for (int c = 0; c < NK; c++) size[c] = 0;
-    for (int x = 0; x < nseq; x++) size[nlab[x]]++;
-    K2 = 0;
-    for (int c = 0; c < NK; c++) map[c] = size[c] > 0 ? K2++ : -1;
-    for (int c = 0; c < NK; c++)
-        if (map[c] >= 0) seed[map[c]] = nseed[c];
-    for (int x = 0; x < nseq; x++) label[x] = map[nlab[x]];
-    free(size); free(map); free(nseed); free(nlab); free(rank);
-    return K2;
+    free(size); free(map); free(nseed); free(nlab);
+    return K;
 }
 
 /* The whole tree: clusters, neighbour joining in each cluster and over the

@@ -179,56 +179,85 @@ def _families(rng, fam_sizes, width=120, p=0.05):
     return np.array(rows, np.uint8)
 
 
+def _clusters(label, seed):
+    return [sorted(np.nonzero(label == c)[0].tolist()) for c in range(len(seed))]
+
+
 def test_clusters_hand_built():
     rng = np.random.default_rng(3)
-    # 30 rows in three families of 10; N = 30 -> 3 seeds, one per family
+    # 30 rows in three families of 10; N = 30 -> 3 seeds (one per family) and
+    # clusters of at most 3 rows.  Each family's cluster (10 rows) gets one
+    # new seed, its first row in permutation order, which takes every row:
+    # no split, so the family is cut into runs of 3 in permutation order.
     m = _families(rng, [10, 10, 10])
     perm = np.array([4, 15, 27] + [x for x in range(30) if x not in (4, 15, 27)], np.int32)
     label, seed = oracle.nj_clusters(m, perm)
-    # each family labelled with its own seed; 10 rows > ceil(30/10) = 3, so
-    # each cluster is divided among its first ceil(10/10) = 1 rows in perm
-    # order: the seed itself, i.e. the clusters stay
-    assert list(seed) == [4, 15, 27]
-    assert (label[:10] == 0).all() and (label[10:20] == 1).all() and (label[20:] == 2).all()
-    # seeds from one family only: the other two families fall into those
-    # clusters, which are then divided (each has more than 3 rows) among
-    # their first rows in permutation order; every cluster is non-empty and
-    # every seed (distinct rows) labelled with its own cluster
-    perm2 = np.array([0, 1, 2] + list(range(3, 30)), np.int32)
-    label2, seed2 = oracle.nj_clusters(m, perm2)
-    assert set(label2.tolist()) == set(range(len(seed2)))
-    assert all(label2[s] == c for c, s in enumerate(seed2))
-    assert len(seed2) > 3   # the divided clusters added seeds
+    assert list(seed) == [4, 2, 6, 9, 15, 12, 16, 19, 27, 22, 25, 29]
+    assert _clusters(label, seed) == [[0, 1, 4], [2, 3, 5], [6, 7, 8], [9], [10, 11, 15], [12, 13, 14],
+                                      [16, 17, 18], [19], [20, 21, 27], [22, 23, 24], [25, 26, 28], [29]]
     # a cluster of fewer than 3 rows is merged into the cluster of the
-    # nearest seed; the divide step (clusters over ceil(22/10) = 3 rows) then
-    # reseeds from the rows in permutation order (0, 12, 14, 1, 2, ...)
+    # nearest seed, then the divide passes (clusters over ceil(22/10) = 3
+    # rows) reseed from the rows in permutation order (0, 12, 14, 1, 2, ...)
     m3 = _families(rng, [12, 2, 8])    # N = 22 -> 3 seeds: rows 0 (A), 12 (B), 14 (C)
     perm3 = np.array([0, 12, 14] + [x for x in range(22) if x not in (0, 12, 14)], np.int32)
     label3, seed3 = oracle.nj_clusters(m3, perm3)
     D3 = oracle.pdist(m3)
-    A, B, C = list(range(12)), [12, 13], list(range(14, 22))
-    if D3[12, 0] <= D3[12, 14]:
-        # B joins A (14 rows: seeds 0 and 12, which split them back), C keeps seed 14
-        assert list(seed3) == [0, 12, 14]
-        assert (label3[A] == 0).all() and (label3[B] == 1).all() and (label3[C] == 2).all()
-    else:
-        # B joins C (10 rows: one seed, the first in permutation order, 12); A
-        # (12 rows) is divided between rows 0 and 1 by nearness, ties to 0
-        assert list(seed3) == [0, 1, 12]
-        assert (label3[B + C] == 2).all()
-        for x in A:
-            assert label3[x] == (0 if D3[x, 0] <= D3[x, 1] else 1)
+    assert D3[12, 0] < D3[12, 14]   # B joins A: A+B (14 rows, seed 0), C (8 rows, seed 14)
+    cl = _clusters(label3, seed3)
+    # A+B is divided between rows 0 and 12 (the first two in permutation
+    # order): B comes back out as its own cluster; C (one seed, 14, takes
+    # all) is cut into runs 14-16, 17-19, 20-21; A keeps dividing (its first
+    # rows in permutation order are 0, 1, 2, ...) until no part exceeds 3
+    assert [12, 13] in cl and [14, 15, 16] in cl and [17, 18, 19] in cl and [20, 21] in cl
+    a_parts = [c for c in cl if c[0] < 12]
+    assert sorted(x for c in a_parts for x in c) == list(range(12))
+    assert all(len(c) <= 3 for c in cl)
+    # seeds come in cluster order, each labelled with its own cluster
+    assert all(label3[s] == c for c, s in enumerate(seed3))
+
+
+def test_clusters_properties():
+    """On families with sub-families (where divisions split by nearness):
+    every cluster is non-empty and at most ceil(N / 10) rows, each seed is in
+    its own cluster, and the partition refines the first labelling (rows of
+    different nearest sample rows never share a cluster, merges aside)."""
+    rng = np.random.default_rng(12)
+    m = np.concatenate([_families(rng, [20, 20], p=0.02), _families(rng, [25, 15, 20], p=0.02)])
+    N = m.shape[0]
+    S = (N + 9) // 10
+    for rep in range(3):
+        perm = rng.permutation(N).astype(np.int32)
+        label, seed = oracle.nj_clusters(m, perm)
+        cl = _clusters(label, seed)
+        assert all(0 < len(c) <= S for c in cl)
+        assert all(label[s] == c for c, s in enumerate(seed))
+        D = oracle.pdist(m)
+        first = np.argmin(D[:, perm[:S]], axis=1)   # nearest sample row, ties to the earlier
+        sizes = np.bincount(first, minlength=S)
+        if (sizes[sizes > 0] >= 3).all():           # no merge happened: a refinement
+            for c in cl:
+                assert len(set(first[c].tolist())) == 1
 
 
 def test_nj_tree_small_is_plain_nj():
-    """N <= 10: one seed, one cluster, the tree is neighbour joining over all rows."""
+    """N <= 10: clusters hold at most ceil(N / 10) = 1 row, so every row is a
+    cluster, in permutation order (the one sample row takes every row, which
+    is then cut into runs of one); the tree is neighbour joining over the rows
+    taken in permutation order, its leaves mapped back to the rows."""
     rng = np.random.default_rng(8)
     for n in (1, 2, 3, 5, 10):
         m = _families(rng, [n])
         perm = rng.permutation(n).astype(np.int32)
         p, b = oracle.nj_tree(m, perm)
-        p2, b2 = oracle.nj(oracle.pdist(m))
-        assert (p == p2).all() and (b == b2).all()
+        D = oracle.pdist(m)
+        p2, b2 = oracle.nj(D[np.ix_(perm, perm)] * (1 - np.eye(n)))
+        node = lambda v: int(perm[v]) if v < n else v
+        want_p = np.zeros(len(p2), np.int32)
+        want_b = np.zeros(len(p2))
+        for v in range(len(p2)):
+            want_p[node(v)] = -1 if p2[v] < 0 else node(p2[v])
+            want_b[node(v)] = b2[v]
+        assert (p == want_p).all() and (b == want_b).all()
 
 
 def test_nj_tree_families_are_clades():
