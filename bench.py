@@ -278,6 +278,41 @@ def nucleotide_report(H, ctx, workload: str, reps: int, cpu_seqs: int):
             "bases_per_s": round(float(seqs.offsets[-1]) / (ms / 1e3), 1), "cpu_baseline": cpu}
 
 
+def phylogeny_report(H, ctx, workload: str, reps: int, cpu: bool):
+    """The NJ section's tree on the nucleotide MSA of a DNA set: halign_nj_tree
+    timed with the MSA resident; with cpu, its CPU baseline, the oracle's tree
+    of the same MSA on one host thread."""
+    import torch
+    from paper_1704_00878_amd import synth
+    seqs = synth.generate_dna(workload)
+    sc = H.Scoring(synth.NUC_MATRIX, synth.NUC_GAP_OPEN, synth.NUC_GAP_EXTEND)
+    msa, _ = H.halign_nuc_msa(ctx, sc, H.DeviceSeqs(seqs), synth.NUC_K)
+    perm = synth.tree_permutation(seqs.n)
+    log(f"bench: tree of the {workload} MSA ({seqs.n} x {msa.shape[1]}): warm-up call")
+    H.halign_nj_tree(ctx, msa, perm)   # warm-up
+    ts = []
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        parent, blen = H.halign_nj_tree(ctx, msa, perm)
+        ts.append(time.perf_counter() - t)
+    ms = 1e3 * float(np.median(ts))
+    log(f"bench: tree {ms:.2f} ms")
+    out = {"workload": f"{workload}: NJ tree of the {seqs.n} x {int(msa.shape[1])} nucleotide MSA, sample "
+                       f"{(seqs.n + 9) // 10} rows", "tree_ms": round(ms, 3), "nodes": int(len(parent)),
+           "rows_per_s": round(seqs.n / (ms / 1e3), 1), "cpu_baseline": None}
+    if cpu:
+        import oracle
+        host = msa.cpu().numpy()
+        t = time.perf_counter()
+        wp, wb = oracle.nj_tree(host, perm)
+        dt = time.perf_counter() - t
+        out["cpu_baseline"] = {"value": round(seqs.n / dt, 2), "unit": "rows/s", "cores": 1, "kind": "oracle",
+                               "sample": f"the whole tree of the same MSA on one host thread ({dt:.2f} s)",
+                               "equal": bool((wp == parent).all() and (wb == blen).all())}
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -298,6 +333,10 @@ def main():
                     "(none: skip)")
     ap.add_argument("--nucleotide-only", action="store_true",
                     help="run only the nucleotide report and print it as one JSON line (profiling)")
+    ap.add_argument("--tree", default="dna672", help="DNA set whose MSA the phylogeny report builds a tree of "
+                    "(none: skip)")
+    ap.add_argument("--tree-only", action="store_true",
+                    help="run only the phylogeny report and print it as one JSON line (profiling)")
     ap.add_argument("--anchors", type=int, default=50000, help="training anchors")
     ap.add_argument("--partners", type=int, default=64, help="training partners per anchor")
     ap.add_argument("--epochs", type=int, default=1)
@@ -321,6 +360,10 @@ def main():
     if args.nucleotide_only:
         nuc = nucleotide_report(H, H.Context(0), args.nucleotide, args.steps, 0 if args.no_cpu else 200)
         print(json.dumps({"nucleotide": nuc}), flush=True)
+        return
+    if args.tree_only:
+        tree = phylogeny_report(H, H.Context(0), args.tree, args.steps, not args.no_cpu)
+        print(json.dumps({"phylogeny": tree}), flush=True)
         return
     log(f"bench: generating {args.workload}")
     seqs = synth.generate(args.workload)
@@ -452,6 +495,9 @@ def main():
     nuc = None
     if args.nucleotide != "none":
         nuc = nucleotide_report(H, ctx, args.nucleotide, 5, 0 if args.no_cpu else 200)
+    tree = None
+    if args.tree != "none":
+        tree = phylogeny_report(H, ctx, args.tree, 3, not args.no_cpu)
 
     ctx.set_autotune(not args.no_autotune)
     learned = None
@@ -478,6 +524,7 @@ def main():
         "graph_replay": graph,
         "learned_center": learned,
         "nucleotide": nuc,
+        "phylogeny": tree,
     }
     print(json.dumps(out), flush=True)
     ctx.close()

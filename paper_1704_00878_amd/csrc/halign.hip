@@ -118,7 +118,7 @@ struct halign_ctx {
     int64_t *mail_host = nullptr, *mail_dev = nullptr;   // coherent pinned mailbox: width, sequence number
     DevBuf nuctab, nucscr, nucdp;   // nucleotide path: segment table, matches and chains, stretch scratch
     DevBuf rowck;                   // chunked rows: residues before each chunk of blocks, per row
-    DevBuf njrows, njD, njS;        // phylogeny: row lists and group tables, distance matrices, join scratch
+    DevBuf njrows, njD, njS, njacc; // phylogeny: row lists and group tables, distance matrices, join scratch, slice counts
     int64_t mail_seq = 0;
     uint32_t vtag = 0;        // tag of the last eager code check
     uint32_t *vflag = nullptr;   // the flag word those tags were raised in (cleared when it changes)
@@ -1162,7 +1162,7 @@ void halign_ctx_destroy(halign_ctx *ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf,
                       &ctx->sbuf, &ctx->nuctab, &ctx->nucscr, &ctx->nucdp, &ctx->rowck,
-                      &ctx->njrows, &ctx->njD, &ctx->njS})
+                      &ctx->njrows, &ctx->njD, &ctx->njS, &ctx->njacc})
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : ctx->mlp)
         if (b.p) (void)hipFree(b.p);
@@ -2861,6 +2861,34 @@ namespace {
 
 inline size_t al256z(size_t b) { return (b + 255) & ~(size_t)255; }
 
+// The distance launch: whole width per tile, or, when the tiles are too few
+// to fill the chip and the MSA is wide, column slices of at least 1,024
+// columns added atomically into zeroed counts and a finalize pass.  nout:
+// outputs the groups address (for the counts).
+int pdist_launch(halign_ctx *ctx, hk::PdArgs a, int64_t tiles, int64_t nout, hipStream_t st) {
+    int64_t nslice = 1;
+    if (tiles < 2048 && a.width > 2048)
+        nslice = std::min<int64_t>((a.width + 1023) / 1024, (2048 + tiles - 1) / tiles);
+    a.nslice = 1;
+    a.cslice = a.width;
+    a.acc = nullptr;
+    a.mode = 0;
+    if (nslice > 1) {
+        a.nslice = (int)nslice;
+        a.cslice = (((a.width + nslice - 1) / nslice) + hk::kPdChunk - 1) / hk::kPdChunk * hk::kPdChunk;
+        RCHK(grow(ctx, ctx->njacc, 8 * (size_t)nout));
+        a.acc = (int32_t *)ctx->njacc.p;
+        RCHK(launch_fill((uint32_t *)a.acc, 0u, 2 * nout, st));
+        a.mode = 1;
+        hipLaunchKernelGGL(hk::pdist_kernel, dim3((unsigned)(tiles * nslice)), dim3(256), 0, st, a);
+        HCHK(hipGetLastError());
+        a.mode = 2;
+    }
+    hipLaunchKernelGGL(hk::pdist_kernel, dim3((unsigned)tiles), dim3(256), 0, st, a);
+    HCHK(hipGetLastError());
+    return HALIGN_OK;
+}
+
 // Upload rows and the group table, then one pdist launch over every group's
 // tiles.  Synchronises the stream after the upload (the host vectors may go).
 int pdist_groups(halign_ctx *ctx, const uint8_t *msa, int64_t width, const std::vector<int32_t> &rows,
@@ -2878,9 +2906,11 @@ int pdist_groups(halign_ctx *ctx, const uint8_t *msa, int64_t width, const std::
     char *b = (char *)ctx->njrows.p;
     if (!rows.empty()) HCHK(hipMemcpyAsync(b, rows.data(), 4 * rows.size(), hipMemcpyHostToDevice, st));
     HCHK(hipMemcpyAsync(b + o_g, groups.data(), sizeof(hk::PdGroup) * groups.size(), hipMemcpyHostToDevice, st));
+    int64_t nout = 0;
+    for (auto &g : groups)
+        if (g.na > 0 && g.nb > 0) nout = std::max<int64_t>(nout, g.o + (int64_t)(g.na - 1) * g.ld + g.nb);
     hk::PdArgs a{msa, width, (const int32_t *)b, (const hk::PdGroup *)(b + o_g), (int)groups.size(), D, mism, comp};
-    hipLaunchKernelGGL(hk::pdist_kernel, dim3((unsigned)tiles), dim3(256), 0, st, a);
-    HCHK(hipGetLastError());
+    RCHK(pdist_launch(ctx, a, tiles, nout, st));
     HCHK(hipStreamSynchronize(st));
     return HALIGN_OK;
 }
@@ -2908,7 +2938,8 @@ int nj_groups(halign_ctx *ctx, std::vector<hk::NjGroup> &groups, double *dbase, 
     hk::NjArgs a{(const hk::NjGroup *)(b + o_g), dbase, (double *)(b + o_r), (uint8_t *)(b + o_act),
                  (int32_t *)(b + o_id), (int32_t *)(b + o_p), (double *)(b + o_b), (int32_t *)(b + o_nd)};
     const int bs = nmax > 2048 ? 1024 : nmax > 256 ? 512 : 256;
-    hipLaunchKernelGGL(hk::nj_kernel, dim3((unsigned)G), dim3(bs), 0, st, a);
+    const size_t lds = hk::nj_lds_bytes(nmax);   // at most 55 KiB
+    hipLaunchKernelGGL(hk::nj_kernel, dim3((unsigned)G), dim3(bs), lds, st, a, lds > 0 ? 1 : 0);
     HCHK(hipGetLastError());
     parent.resize(nt);
     blen.resize(nt);
@@ -2975,8 +3006,7 @@ int halign_pdist(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width, 
     if (b_rows) HCHK(hipMemcpyAsync(b + 4 * g.b0, b_rows, 4 * (size_t)nb, hipMemcpyDeviceToDevice, st));
     HCHK(hipMemcpyAsync(b + o_g, groups.data(), sizeof(hk::PdGroup), hipMemcpyHostToDevice, st));
     hk::PdArgs a{msa, width, (const int32_t *)b, (const hk::PdGroup *)(b + o_g), 1, D, mism, comp};
-    hipLaunchKernelGGL(hk::pdist_kernel, dim3((unsigned)tiles), dim3(256), 0, st, a);
-    HCHK(hipGetLastError());
+    RCHK(pdist_launch(ctx, a, tiles, (int64_t)na * nb, st));
     HCHK(hipStreamSynchronize(st));   // the host vectors above were copied from
     return HALIGN_OK;
 }
@@ -3075,42 +3105,103 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
         for (int x = 0; x < N; ++x) label[x] = map[label[x]];
         K = K2;
     }
-    // clusters of more than ceil(N / 10) rows are divided, once
-    std::vector<int32_t> nseed, nlab(N);
-    for (int c = 0; c < K; ++c) {
-        if (size[c] <= S) {
-            for (int x = 0; x < N; ++x)
-                if (label[x] == c) nlab[x] = (int32_t)nseed.size();
-            nseed.push_back(seed[c]);
-            continue;
-        }
-        const int nsd = (size[c] + 9) / 10;
-        const int base = (int)nseed.size();
-        for (int t = 0; t < N && (int)nseed.size() - base < nsd; ++t)
-            if (label[perm_host[t]] == c) nseed.push_back(perm_host[t]);
-        std::vector<int32_t> rows, mem;
+    // clusters of more than ceil(N / 10) rows are divided until none is left:
+    // among their first ceil(size / 10) rows in permutation order (nearest),
+    // or in runs of ceil(N / 10) rows in permutation order when one seed
+    // takes them all; empty clusters are dropped after each pass
+    for (;;) {
+        bool big = false;
+        for (int c = 0; c < K; ++c) big = big || size[c] > S;
+        if (!big) break;
+        std::vector<int32_t> nseed, nlab(N);
+        // the big clusters' rows and new seeds, one distance group each
+        std::vector<int32_t> rows;
+        std::vector<hk::PdGroup> gr;
+        std::vector<int> gbase;                     // per group: its cluster's first new seed
+        std::vector<std::vector<int32_t>> mem(K);
         for (int x = 0; x < N; ++x)
-            if (label[x] == c) mem.push_back(x);
-        rows = mem;
-        rows.insert(rows.end(), nseed.begin() + base, nseed.end());
-        const int nm = (int)mem.size();
-        std::vector<hk::PdGroup> gr(1);
-        gr[0] = hk::PdGroup{0, nm, nm, nsd, 0, nsd, 0, 0, 0};
-        RCHK(grow(ctx, ctx->njD, 8 * (size_t)nm * nsd));
+            if (size[label[x]] > S) mem[label[x]].push_back(x);
+        int64_t dtot = 0;
+        for (int c = 0; c < K; ++c) {
+            if (size[c] <= S) {
+                for (int x = 0; x < N; ++x)
+                    if (label[x] == c) nlab[x] = (int32_t)nseed.size();
+                nseed.push_back(seed[c]);
+                continue;
+            }
+            const int nsd = (size[c] + 9) / 10;
+            const int base = (int)nseed.size();
+            for (int t = 0; t < N && (int)nseed.size() - base < nsd; ++t)
+                if (label[perm_host[t]] == c) nseed.push_back(perm_host[t]);
+            const int64_t r0 = (int64_t)rows.size();
+            rows.insert(rows.end(), mem[c].begin(), mem[c].end());
+            rows.insert(rows.end(), nseed.begin() + base, nseed.end());
+            const int nm = (int)mem[c].size();
+            gr.push_back(hk::PdGroup{r0, r0 + nm, nm, nsd, dtot, nsd, 0, 0, 0});
+            gbase.push_back(base);
+            dtot += (int64_t)nm * nsd;
+        }
+        RCHK(grow(ctx, ctx->njD, 8 * (size_t)dtot));
         RCHK(pdist_groups(ctx, msa, width, rows, gr, (double *)ctx->njD.p, nullptr, nullptr, st));
-        std::vector<int32_t> lab;
-        RCHK(nearest_host(ctx, (const double *)ctx->njD.p, nm, nsd, lab, st));
-        for (int t = 0; t < nm; ++t) nlab[mem[t]] = base + lab[t];
-    }
-    {   // drop clusters left empty (a seed taken by an identical earlier one)
+        // the nearest new seed of every row of each divided cluster, on the GPU
+        std::vector<std::vector<int32_t>> glab(gr.size());
+        for (size_t gi = 0; gi < gr.size(); ++gi)
+            RCHK(nearest_host(ctx, (const double *)ctx->njD.p + gr[gi].o, gr[gi].na, gr[gi].nb, glab[gi], st));
+        // nearest new seed per row (ties to the earlier), or runs in permutation order
+        std::vector<int> remap(nseed.size(), -1);
+        {
+            // rebuild nseed in order, replacing each divided cluster's seeds by
+            // runs where needed
+            size_t gi = 0;
+            std::vector<int32_t> res;
+            int at = 0;   // position in nseed
+            for (int c = 0; c < K; ++c) {
+                if (size[c] <= S) {
+                    remap[at] = (int)res.size();
+                    res.push_back(nseed[at]);
+                    ++at;
+                    continue;
+                }
+                const hk::PdGroup &g = gr[gi];
+                const int nm = g.na, nsd = g.nb, base = gbase[gi];
+                const std::vector<int32_t> &lab = glab[gi];
+                bool split = false;
+                for (int t = 1; t < nm; ++t) split = split || lab[t] != lab[0];
+                if (split) {
+                    const int r0 = (int)res.size();
+                    for (int e = 0; e < nsd; ++e) res.push_back(nseed[base + e]);
+                    for (int t = 0; t < nm; ++t) nlab[mem[c][t]] = r0 + lab[t];
+                } else {
+                    int cnt = 0;
+                    for (int t = 0; t < N; ++t) {
+                        const int x = perm_host[t];
+                        if (label[x] != c) continue;
+                        if (cnt % S == 0) res.push_back(x);
+                        nlab[x] = (int32_t)res.size() - 1;
+                        ++cnt;
+                    }
+                }
+                at += nsd;
+                ++gi;
+            }
+            // the kept clusters' labels were set against nseed positions: move them
+            for (int x = 0; x < N; ++x)
+                if (size[label[x]] <= S) nlab[x] = remap[nlab[x]];
+            nseed.swap(res);
+        }
+        // drop empty clusters, keeping the order
         const int NK = (int)nseed.size();
         std::vector<int> sz(NK, 0), map(NK);
         for (int x = 0; x < N; ++x) sz[nlab[x]]++;
         int K2 = 0;
         for (int c = 0; c < NK; ++c) map[c] = sz[c] > 0 ? K2++ : -1;
         seed.assign(K2, 0);
+        size.assign(std::max(N + 1, K2), 0);
         for (int c = 0; c < NK; ++c)
-            if (map[c] >= 0) seed[map[c]] = nseed[c];
+            if (map[c] >= 0) {
+                seed[map[c]] = nseed[c];
+                size[map[c]] = sz[c];
+            }
         for (int x = 0; x < N; ++x) label[x] = map[nlab[x]];
         K = K2;
     }
@@ -3125,6 +3216,11 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
         std::vector<int64_t> at(coff.begin(), coff.end() - 1);
         for (int x = 0; x < N; ++x) rows[at[label[x]]++] = x;
         for (int c = 0; c < K; ++c) rows[N + c] = seed[c];
+    }
+    if (ctx->progress) {
+        int mx = 0;
+        for (int c = 0; c < K; ++c) mx = std::max(mx, csize[c]);
+        fprintf(stderr, "halign_nj_tree: %d rows, %d clusters (largest %d rows), %d seeds joined last\n", N, K, mx, K);
     }
     std::vector<hk::PdGroup> gr(K + 1);
     std::vector<hk::NjGroup> ng(K + 1);

@@ -39,6 +39,13 @@ struct PdArgs {
     int ngroups;
     double *D;
     int32_t *mism, *comp;   // optional
+    // column slices: nslice > 1 splits the width into slices of cslice
+    // columns (a multiple of kPdChunk), each slice's counts added atomically
+    // into acc (2 int32 per output, zeroed) and D formed by a finalize pass
+    int nslice;
+    int64_t cslice;
+    int32_t *acc;
+    int mode;   // 0: whole width, D out; 1: one slice into acc; 2: D (and counts) from acc
 };
 
 // bit 7 of each byte set when that byte of v is nonzero (no carries between bytes)
@@ -46,7 +53,8 @@ __device__ __forceinline__ uint32_t nz_bytes(uint32_t v) {
     return ((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v;
 }
 
-// A workgroup of 256 threads takes one 64 x 64 tile of a group's pairs; thread
+// A workgroup of 256 threads takes one 64 x 64 tile of a group's pairs (and
+// one column slice when the tiles are too few to fill the chip); thread
 // (ty, tx) counts pairs (4 ty + i, 4 tx + j), i, j < 4.  Each pass stages 64
 // columns of the tile's 128 rows in LDS (gap bytes past the width or past the
 // group's rows, which count nowhere), then compares four columns per word:
@@ -55,9 +63,10 @@ __device__ __forceinline__ uint32_t nz_bytes(uint32_t v) {
 __global__ void __launch_bounds__(256) pdist_kernel(PdArgs a) {
 #pragma clang fp contract(off)
     __shared__ uint32_t sa[kPdTile * kPdStride], sb[kPdTile * kPdStride];
-    // the group and tile of this workgroup
+    // the group and tile of this workgroup (and its column slice)
     int lo = 0, hi = a.ngroups - 1;
-    const int64_t t = blockIdx.x;
+    const int64_t t = a.mode == 1 ? blockIdx.x / a.nslice : blockIdx.x;
+    const int64_t slice = a.mode == 1 ? blockIdx.x - t * a.nslice : 0;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;
         if (a.groups[mid].tile0 <= t) lo = mid;
@@ -77,7 +86,9 @@ __global__ void __launch_bounds__(256) pdist_kernel(PdArgs a) {
     for (int i = 0; i < 4; ++i)
 #pragma unroll
         for (int j = 0; j < 4; ++j) mm[i][j] = cc[i][j] = 0u;
-    for (int64_t c0 = 0; c0 < a.width; c0 += kPdChunk) {
+    const int64_t cbeg = a.mode == 1 ? slice * a.cslice : 0;
+    const int64_t cend = a.mode == 1 ? min(a.width, cbeg + a.cslice) : (a.mode == 2 ? 0 : a.width);
+    for (int64_t c0 = cbeg; c0 < cend; c0 += kPdChunk) {
         uint32_t wa[4], wb[4];
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
@@ -129,6 +140,15 @@ __global__ void __launch_bounds__(256) pdist_kernel(PdArgs a) {
             const int s = tb * kPdTile + 4 * tx + j;
             if (s >= g.nb) continue;
             const int64_t o = g.o + (int64_t)r * g.ld + s;
+            if (a.mode == 1) {   // this slice's counts
+                if (mm[i][j]) atomicAdd(a.acc + 2 * o, (int)mm[i][j]);
+                if (cc[i][j]) atomicAdd(a.acc + 2 * o + 1, (int)cc[i][j]);
+                continue;
+            }
+            if (a.mode == 2) {
+                mm[i][j] = (uint32_t)a.acc[2 * o];
+                cc[i][j] = (uint32_t)a.acc[2 * o + 1];
+            }
             double d = cc[i][j] > 0u ? (double)mm[i][j] / (double)cc[i][j] : 1.0;
             if (g.diag0 && r == s) d = 0.0;
             a.D[o] = d;
@@ -188,19 +208,28 @@ __device__ __forceinline__ bool nj_before(const NjBest &x, const NjBest &y) {   
     return x.i < y.i || (x.i == y.i && x.j < y.j);
 }
 
+constexpr int kNjLdsMax = 6144;   // nodes whose row sums and flags fit in LDS (else global scratch)
+constexpr int kNjAhead = 32;      // matrix loads in flight per lane
+
+// LDS bytes of nj_kernel for problems of at most nmax nodes (0: global scratch)
+inline size_t nj_lds_bytes(int nmax) { return nmax <= kNjLdsMax ? (size_t)9 * nmax + 8 : 0; }
+
 // One workgroup per problem: each join recomputes the row sums (one lane per
-// row, in slot order), finds the smallest Q (each lane its rows, then a
-// workgroup reduction in (Q, i, j) order), writes the two branch lengths and
-// updates row and column i for the new node.
-__global__ void __launch_bounds__(1024) nj_kernel(NjArgs a) {
+// row, summing its column in slot order, which equals the row bit for bit as
+// D is kept symmetric), finds the smallest Q (one lane per column j over the
+// rows i < j, then a workgroup reduction in (Q, i, j) order),
+// writes the two branch lengths and updates row and column i for the new
+// node.  Row sums and active flags sit in LDS when the problem fits.
+__global__ void __launch_bounds__(1024) nj_kernel(NjArgs a, int lds) {
 #pragma clang fp contract(off)
+    extern __shared__ double nj_lds[];
     __shared__ NjBest red[32];
     __shared__ int sh_i, sh_j;
     const NjGroup g = a.groups[blockIdx.x];
     const int n = g.n, tid = threadIdx.x, bs = blockDim.x;
     double *D = a.D + g.d0;
-    double *r = a.r + g.s0;
-    uint8_t *act = a.act + g.s0;
+    double *r = lds ? nj_lds : a.r + g.s0;
+    uint8_t *act = lds ? reinterpret_cast<uint8_t *>(nj_lds + n) : a.act + g.s0;
     int32_t *id = a.id + g.s0;
     int32_t *parent = a.parent + g.t0;
     double *blen = a.blen + g.t0;
@@ -214,22 +243,33 @@ __global__ void __launch_bounds__(1024) nj_kernel(NjArgs a) {
         for (int i = tid; i < n; i += bs) {
             if (!act[i]) continue;
             double sum = 0.0;
-            const double *row = D + (int64_t)i * n;
-            for (int k = 0; k < n; ++k)
-                if (act[k]) sum = sum + row[k];
+            for (int k0 = 0; k0 < n; k0 += kNjAhead) {   // column i, kNjAhead loads in flight
+                double v[kNjAhead];
+#pragma unroll
+                for (int u = 0; u < kNjAhead; ++u) v[u] = k0 + u < n ? D[(int64_t)(k0 + u) * n + i] : 0.0;
+#pragma unroll
+                for (int u = 0; u < kNjAhead; ++u)
+                    if (k0 + u < n && act[k0 + u]) sum = sum + v[u];
+            }
             r[i] = sum;
         }
         __syncthreads();
         const double f = (double)(m - 2);
         NjBest b{0.0, -1, -1};
-        for (int i = tid; i < n; i += bs) {
-            if (!act[i]) continue;
-            const double ri = r[i];
-            const double *row = D + (int64_t)i * n;
-            for (int j = i + 1; j < n; ++j) {
-                if (!act[j]) continue;
-                const double q = f * row[j] - ri - r[j];
-                if (b.i < 0 || q < b.q) b = NjBest{q, i, j};
+        for (int j = tid; j < n; j += bs) {   // column j against rows i < j, kNjAhead loads in flight
+            if (!act[j]) continue;
+            const double rj = r[j];
+            for (int i0 = 0; i0 < j; i0 += kNjAhead) {
+                double v[kNjAhead];
+#pragma unroll
+                for (int u = 0; u < kNjAhead; ++u) v[u] = i0 + u < j ? D[(int64_t)(i0 + u) * n + j] : 0.0;
+#pragma unroll
+                for (int u = 0; u < kNjAhead; ++u) {
+                    const int i = i0 + u;
+                    if (i >= j || !act[i]) continue;
+                    const NjBest c{f * v[u] - r[i] - rj, i, j};
+                    if (nj_before(c, b)) b = c;
+                }
             }
         }
         // the workgroup's first pair in (Q, i, j) order

@@ -53,7 +53,7 @@ def _families(rng, sizes, width=160, p=0.05, p_gap=0.02):
     return np.array(rows, np.uint8)
 
 
-@pytest.mark.parametrize("n,w", [(1, 1), (5, 3), (70, 130), (130, 64), (64, 1000), (3, 0)])
+@pytest.mark.parametrize("n,w", [(1, 1), (5, 3), (70, 130), (130, 64), (64, 1000), (3, 0), (70, 5000), (130, 2049)])
 def test_pdist_counts(H, ctx, n, w):
     import torch
     rng = np.random.default_rng(n * 1000 + w)
