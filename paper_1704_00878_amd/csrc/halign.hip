@@ -2937,7 +2937,7 @@ int nj_groups(halign_ctx *ctx, std::vector<hk::NjGroup> &groups, double *dbase, 
     HCHK(hipMemcpyAsync(b + o_g, groups.data(), sizeof(hk::NjGroup) * G, hipMemcpyHostToDevice, st));
     hk::NjArgs a{(const hk::NjGroup *)(b + o_g), dbase, (double *)(b + o_r), (uint8_t *)(b + o_act),
                  (int32_t *)(b + o_id), (int32_t *)(b + o_p), (double *)(b + o_b), (int32_t *)(b + o_nd)};
-    const int bs = nmax > 2048 ? 1024 : nmax > 256 ? 512 : 256;
+    const int bs = nmax > 128 ? 1024 : 256;
     const size_t lds = hk::nj_lds_bytes(nmax);   // at most 55 KiB
     hipLaunchKernelGGL(hk::nj_kernel, dim3((unsigned)G), dim3(bs), lds, st, a, lds > 0 ? 1 : 0);
     HCHK(hipGetLastError());

@@ -216,8 +216,8 @@ inline size_t nj_lds_bytes(int nmax) { return nmax <= kNjLdsMax ? (size_t)9 * nm
 
 // One workgroup per problem: each join recomputes the row sums (one lane per
 // row, summing its column in slot order, which equals the row bit for bit as
-// D is kept symmetric), finds the smallest Q (one lane per column j over the
-// rows i < j, then a workgroup reduction in (Q, i, j) order),
+// D is kept symmetric), finds the smallest Q (the matrix spread row-major over
+// the lanes, then a workgroup reduction in (Q, i, j) order),
 // writes the two branch lengths and updates row and column i for the new
 // node.  Row sums and active flags sit in LDS when the problem fits.
 __global__ void __launch_bounds__(1024) nj_kernel(NjArgs a, int lds) {
@@ -256,19 +256,31 @@ __global__ void __launch_bounds__(1024) nj_kernel(NjArgs a, int lds) {
         __syncthreads();
         const double f = (double)(m - 2);
         NjBest b{0.0, -1, -1};
-        for (int j = tid; j < n; j += bs) {   // column j against rows i < j, kNjAhead loads in flight
-            if (!act[j]) continue;
-            const double rj = r[j];
-            for (int i0 = 0; i0 < j; i0 += kNjAhead) {
+        // the matrix row-major over all lanes, (i, j) stepped along with
+        // the index, kNjAhead loads in flight: pairs j > i of active rows
+        {
+            const int64_t nn = (int64_t)n * n;
+            int i = tid / n, j = tid - (tid / n) * n;
+            const int di = bs / n, dj = bs - (bs / n) * n;
+            for (int64_t e0 = tid; e0 < nn; e0 += (int64_t)bs * kNjAhead) {
                 double v[kNjAhead];
 #pragma unroll
-                for (int u = 0; u < kNjAhead; ++u) v[u] = i0 + u < j ? D[(int64_t)(i0 + u) * n + j] : 0.0;
+                for (int u = 0; u < kNjAhead; ++u) {
+                    const int64_t e = e0 + (int64_t)u * bs;
+                    v[u] = e < nn ? D[e] : 0.0;
+                }
 #pragma unroll
                 for (int u = 0; u < kNjAhead; ++u) {
-                    const int i = i0 + u;
-                    if (i >= j || !act[i]) continue;
-                    const NjBest c{f * v[u] - r[i] - rj, i, j};
-                    if (nj_before(c, b)) b = c;
+                    if (i < n && j > i && act[i] && act[j]) {
+                        const NjBest c{f * v[u] - r[i] - r[j], i, j};
+                        if (nj_before(c, b)) b = c;
+                    }
+                    i += di;
+                    j += dj;
+                    if (j >= n) {
+                        j -= n;
+                        ++i;
+                    }
                 }
             }
         }
