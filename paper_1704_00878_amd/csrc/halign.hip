@@ -118,7 +118,7 @@ struct halign_ctx {
     int64_t *mail_host = nullptr, *mail_dev = nullptr;   // coherent pinned mailbox: width, sequence number
     DevBuf nuctab, nucscr, nucdp;   // nucleotide path: segment table, matches and chains, stretch scratch
     DevBuf rowck;                   // chunked rows: residues before each chunk of blocks, per row
-    DevBuf njrows, njD, njS, njacc; // phylogeny: row lists and group tables, distance matrices, join scratch, slice counts
+    DevBuf njrows, njD, njS, njacc, njB; // phylogeny: row lists and group tables, distance matrices, join scratch, slice counts, chip-wide join scratch
     int64_t mail_seq = 0;
     uint32_t vtag = 0;        // tag of the last eager code check
     uint32_t *vflag = nullptr;   // the flag word those tags were raised in (cleared when it changes)
@@ -1162,7 +1162,7 @@ void halign_ctx_destroy(halign_ctx *ctx) {
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
     for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf,
                       &ctx->sbuf, &ctx->nuctab, &ctx->nucscr, &ctx->nucdp, &ctx->rowck,
-                      &ctx->njrows, &ctx->njD, &ctx->njS, &ctx->njacc})
+                      &ctx->njrows, &ctx->njD, &ctx->njS, &ctx->njacc, &ctx->njB})
         if (b->p) (void)hipFree(b->p);
     for (DevBuf &b : ctx->mlp)
         if (b.p) (void)hipFree(b.p);
@@ -2951,6 +2951,46 @@ int nj_groups(halign_ctx *ctx, std::vector<hk::NjGroup> &groups, double *dbase, 
     return HALIGN_OK;
 }
 
+// Problems above this many nodes are joined over the whole chip (three
+// launches per join); smaller ones one workgroup each, all in one launch.
+constexpr int kNjBigMin = 256;
+
+// Neighbour joining of one problem over the chip: D (device, n x n, modified);
+// the tree to the host (2n + 1 entries).
+int nj_big(halign_ctx *ctx, double *D, int n, std::vector<int32_t> &parent, std::vector<double> &blen, int *nodes,
+           hipStream_t st) {
+    const int64_t nn = (int64_t)n * n;
+    const int nparts = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (nn + 255) / 256));
+    const size_t nt = 2 * (size_t)n + 1;
+    const size_t o_r = 0, o_id = al256z(8 * (size_t)n), o_p = o_id + al256z(4 * (size_t)n), o_b = o_p + al256z(4 * nt),
+                 o_part = o_b + al256z(8 * nt), o_ctrl = o_part + al256z(sizeof(hk::NjBest) * nparts),
+                 o_nodes = o_ctrl + 256, o_act = o_nodes + 256, bytes = o_act + al256z(n);
+    RCHK(grow(ctx, ctx->njB, bytes));
+    char *b = (char *)ctx->njB.p;
+    hk::NjBigArgs a{n, D, (double *)(b + o_r), (uint8_t *)(b + o_act), (int32_t *)(b + o_id), (int32_t *)(b + o_p),
+                    (double *)(b + o_b), (hk::NjBest *)(b + o_part), nparts, (hk::NjCtrl *)(b + o_ctrl)};
+    const unsigned rg = (unsigned)((n + 255) / 256);
+    hipLaunchKernelGGL(hk::nj_big_init_kernel, dim3(rg), dim3(256), 0, st, a);
+    HCHK(hipGetLastError());
+    for (int t = 0; t < n - 3; ++t) {
+        hipLaunchKernelGGL(hk::nj_big_rows_kernel, dim3(rg), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(hk::nj_big_q_kernel, dim3((unsigned)nparts), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(hk::nj_big_join_kernel, dim3(1), dim3(256), 0, st, a);
+    }
+    HCHK(hipGetLastError());
+    hipLaunchKernelGGL(hk::nj_big_finish_kernel, dim3(1), dim3(1), 0, st, a, (int32_t *)(b + o_nodes));
+    HCHK(hipGetLastError());
+    parent.resize(nt);
+    blen.resize(nt);
+    int32_t nd = 0;
+    HCHK(hipMemcpyAsync(parent.data(), b + o_p, 4 * nt, hipMemcpyDeviceToHost, st));
+    HCHK(hipMemcpyAsync(blen.data(), b + o_b, 8 * nt, hipMemcpyDeviceToHost, st));
+    HCHK(hipMemcpyAsync(&nd, b + o_nodes, 4, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    *nodes = nd;
+    return HALIGN_OK;
+}
+
 // labels[i] = nearest of the nb columns of D (na x nb, device), to the host
 int nearest_host(halign_ctx *ctx, const double *D, int na, int nb, std::vector<int32_t> &label, hipStream_t st) {
     RCHK(grow(ctx, ctx->njS, al256z(4 * (size_t)na)));
@@ -3019,12 +3059,18 @@ int halign_nj(halign_ctx *ctx, const double *D, int32_t n, int32_t *parent_host,
     const size_t bytes = 8 * (size_t)n * n;
     RCHK(grow(ctx, ctx->njD, bytes));
     HCHK(hipMemcpyAsync(ctx->njD.p, D, bytes, hipMemcpyDeviceToDevice, st));
-    std::vector<hk::NjGroup> groups(1);
-    groups[0].n = n;
-    groups[0].d0 = 0;
     std::vector<int32_t> parent, nd;
     std::vector<double> blen;
-    RCHK(nj_groups(ctx, groups, (double *)ctx->njD.p, parent, blen, nd, st));
+    if (n > kNjBigMin) {
+        int nn = 0;
+        RCHK(nj_big(ctx, (double *)ctx->njD.p, n, parent, blen, &nn, st));
+        nd.assign(1, nn);
+    } else {
+        std::vector<hk::NjGroup> groups(1);
+        groups[0].n = n;
+        groups[0].d0 = 0;
+        RCHK(nj_groups(ctx, groups, (double *)ctx->njD.p, parent, blen, nd, st));
+    }
     memcpy(parent_host, parent.data(), 4 * (size_t)nd[0]);
     memcpy(blen_host, blen.data(), 8 * (size_t)nd[0]);
     *nodes = nd[0];
@@ -3235,9 +3281,46 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
     }
     RCHK(grow(ctx, ctx->njD, 8 * (size_t)dtot));
     RCHK(pdist_groups(ctx, msa, width, rows, gr, (double *)ctx->njD.p, nullptr, nullptr, st));
-    std::vector<int32_t> tp, tn;
+    // the joins: small problems in one launch, large ones over the chip; tree
+    // g at tp/tb offset ng[g].t0 (2n + 1 entries each), node count tn[g]
+    std::vector<int32_t> tp, tn(K + 1);
     std::vector<double> tb;
-    RCHK(nj_groups(ctx, ng, (double *)ctx->njD.p, tp, tb, tn, st));
+    {
+        std::vector<hk::NjGroup> small;
+        std::vector<int> sidx;
+        int64_t nt = 0;
+        for (int c = 0; c <= K; ++c) {
+            ng[c].t0 = nt;
+            nt += 2 * (int64_t)ng[c].n + 1;
+            if (ng[c].n <= kNjBigMin) {
+                small.push_back(ng[c]);
+                sidx.push_back(c);
+            }
+        }
+        tp.assign(nt, 0);
+        tb.assign(nt, 0.0);
+        if (!small.empty()) {
+            std::vector<int32_t> sp, sn;
+            std::vector<double> sb;
+            RCHK(nj_groups(ctx, small, (double *)ctx->njD.p, sp, sb, sn, st));
+            for (size_t q = 0; q < small.size(); ++q) {
+                const int c = sidx[q];
+                std::copy(sp.begin() + small[q].t0, sp.begin() + small[q].t0 + 2 * ng[c].n + 1, tp.begin() + ng[c].t0);
+                std::copy(sb.begin() + small[q].t0, sb.begin() + small[q].t0 + 2 * ng[c].n + 1, tb.begin() + ng[c].t0);
+                tn[c] = sn[q];
+            }
+        }
+        for (int c = 0; c <= K; ++c) {
+            if (ng[c].n <= kNjBigMin) continue;
+            std::vector<int32_t> bp;
+            std::vector<double> bb;
+            int nn = 0;
+            RCHK(nj_big(ctx, (double *)ctx->njD.p + ng[c].d0, ng[c].n, bp, bb, &nn, st));
+            std::copy(bp.begin(), bp.end(), tp.begin() + ng[c].t0);
+            std::copy(bb.begin(), bb.end(), tb.begin() + ng[c].t0);
+            tn[c] = nn;
+        }
+    }
     // the merge, node numbering as documented
     int next = N;
     std::vector<int> croot(K);

@@ -357,4 +357,174 @@ __global__ void __launch_bounds__(1024) nj_kernel(NjArgs a, int lds) {
     }
 }
 
+// ---- one large problem spread over the chip: three kernels per join ------
+// State of the join loop on the device: active nodes, the next node number,
+// the pair chosen.
+struct NjCtrl {
+    int m, next;
+};
+
+struct NjBigArgs {
+    int n;
+    double *D;
+    double *r;
+    uint8_t *act;
+    int32_t *id;
+    int32_t *parent;
+    double *blen;
+    NjBest *part;   // per workgroup of the Q pass
+    int nparts;
+    NjCtrl *ctrl;
+};
+
+__global__ void __launch_bounds__(256) nj_big_init_kernel(NjBigArgs a) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s < a.n) {
+        a.act[s] = 1;
+        a.id[s] = s;
+    }
+    if (s == 0) *a.ctrl = NjCtrl{a.n, a.n};
+}
+
+// row sums: one lane per active row, its column in slot order (the bits of the row)
+__global__ void __launch_bounds__(256) nj_big_rows_kernel(NjBigArgs a) {
+#pragma clang fp contract(off)
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    const int n = a.n;
+    if (i >= n || !a.act[i]) return;
+    double sum = 0.0;
+    // two batches of loads: the next one in flight while this one is summed
+    constexpr int B = 16;
+    double v[B], w[B];
+#pragma unroll
+    for (int u = 0; u < B; ++u) v[u] = u < n ? a.D[(int64_t)u * n + i] : 0.0;
+    for (int k0 = 0; k0 < n; k0 += B) {
+#pragma unroll
+        for (int u = 0; u < B; ++u) w[u] = k0 + B + u < n ? a.D[(int64_t)(k0 + B + u) * n + i] : 0.0;
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (k0 + u < n && a.act[k0 + u]) sum = sum + v[u];
+#pragma unroll
+        for (int u = 0; u < B; ++u) v[u] = w[u];
+    }
+    a.r[i] = sum;
+}
+
+// Q: workgroup b takes elements [b per, (b + 1) per) of the matrix row-major;
+// its first (Q, i, j) goes to part[b]
+__global__ void __launch_bounds__(256) nj_big_q_kernel(NjBigArgs a) {
+#pragma clang fp contract(off)
+    __shared__ NjBest red[4];
+    const int n = a.n, tid = threadIdx.x;
+    const int64_t nn = (int64_t)n * n, per = (nn + a.nparts - 1) / a.nparts;
+    const int64_t e0 = (int64_t)blockIdx.x * per, e1 = min(nn, e0 + per);
+    const double f = (double)(a.ctrl->m - 2);
+    NjBest b{0.0, -1, -1};
+    for (int64_t e = e0 + tid; e < e1; e += blockDim.x) {
+        const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
+        if (j <= i || !a.act[i] || !a.act[j]) continue;
+        const NjBest c{f * a.D[e] - a.r[i] - a.r[j], i, j};
+        if (nj_before(c, b)) b = c;
+    }
+    for (int o = 32; o >= 1; o >>= 1) {
+        NjBest y{__shfl_xor(b.q, o, 64), __shfl_xor(b.i, o, 64), __shfl_xor(b.j, o, 64)};
+        if (nj_before(y, b)) b = y;
+    }
+    if ((tid & 63) == 0) red[tid >> 6] = b;
+    __syncthreads();
+    if (tid == 0) {
+        NjBest w = red[0];
+        for (int x = 1; x < (int)(blockDim.x >> 6); ++x)
+            if (nj_before(red[x], w)) w = red[x];
+        a.part[blockIdx.x] = w;
+    }
+}
+
+// the join: the first pair over the parts, lengths, row and column i updated
+__global__ void __launch_bounds__(256) nj_big_join_kernel(NjBigArgs a) {
+#pragma clang fp contract(off)
+    __shared__ NjBest red[4];
+    __shared__ int sh_i, sh_j;
+    const int n = a.n, tid = threadIdx.x;
+    NjBest b{0.0, -1, -1};
+    for (int x = tid; x < a.nparts; x += blockDim.x)
+        if (nj_before(a.part[x], b)) b = a.part[x];
+    for (int o = 32; o >= 1; o >>= 1) {
+        NjBest y{__shfl_xor(b.q, o, 64), __shfl_xor(b.i, o, 64), __shfl_xor(b.j, o, 64)};
+        if (nj_before(y, b)) b = y;
+    }
+    if ((tid & 63) == 0) red[tid >> 6] = b;
+    __syncthreads();
+    const NjCtrl c = *a.ctrl;
+    if (tid == 0) {
+        NjBest w = red[0];
+        for (int x = 1; x < (int)(blockDim.x >> 6); ++x)
+            if (nj_before(red[x], w)) w = red[x];
+        const int bi = w.i, bj = w.j;
+        const double f = (double)(c.m - 2);
+        const double dij = a.D[(int64_t)bi * n + bj];
+        const double li = 0.5 * dij + (a.r[bi] - a.r[bj]) / (2.0 * f);
+        const double lj = dij - li;
+        a.parent[a.id[bi]] = c.next;
+        a.blen[a.id[bi]] = li;
+        a.parent[a.id[bj]] = c.next;
+        a.blen[a.id[bj]] = lj;
+        sh_i = bi;
+        sh_j = bj;
+    }
+    __syncthreads();
+    const int bi = sh_i, bj = sh_j;
+    const double dij = a.D[(int64_t)bi * n + bj];
+    for (int k = tid; k < n; k += blockDim.x) {
+        if (!a.act[k] || k == bi || k == bj) continue;
+        const double v = (a.D[(int64_t)bi * n + k] + a.D[(int64_t)bj * n + k] - dij) * 0.5;
+        a.D[(int64_t)bi * n + k] = v;
+        a.D[(int64_t)k * n + bi] = v;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        a.act[bj] = 0;
+        a.id[bi] = c.next;
+        *a.ctrl = NjCtrl{c.m - 1, c.next + 1};
+    }
+}
+
+// the last two or three nodes (or the single leaf), as in nj_kernel
+__global__ void nj_big_finish_kernel(NjBigArgs a, int32_t *nodes) {
+#pragma clang fp contract(off)
+    const int n = a.n;
+    const NjCtrl c = *a.ctrl;
+    int next = c.next;
+    int s[3], k = 0;
+    for (int i = 0; i < n && k < 3; ++i)
+        if (a.act[i]) s[k++] = i;
+    const double *D = a.D;
+    if (c.m == 3) {
+        const double dab = D[(int64_t)s[0] * n + s[1]], dac = D[(int64_t)s[0] * n + s[2]],
+                     dbc = D[(int64_t)s[1] * n + s[2]];
+        a.parent[a.id[s[0]]] = next;
+        a.blen[a.id[s[0]]] = (dab + dac - dbc) * 0.5;
+        a.parent[a.id[s[1]]] = next;
+        a.blen[a.id[s[1]]] = (dab + dbc - dac) * 0.5;
+        a.parent[a.id[s[2]]] = next;
+        a.blen[a.id[s[2]]] = (dac + dbc - dab) * 0.5;
+        a.parent[next] = -1;
+        a.blen[next] = 0.0;
+        ++next;
+    } else if (c.m == 2) {
+        const double dab = D[(int64_t)s[0] * n + s[1]];
+        a.parent[a.id[s[0]]] = next;
+        a.blen[a.id[s[0]]] = dab * 0.5;
+        a.parent[a.id[s[1]]] = next;
+        a.blen[a.id[s[1]]] = dab * 0.5;
+        a.parent[next] = -1;
+        a.blen[next] = 0.0;
+        ++next;
+    } else {
+        a.parent[a.id[s[0]]] = -1;
+        a.blen[a.id[s[0]]] = 0.0;
+    }
+    *nodes = next;
+}
+
 }  // namespace hk

@@ -93,7 +93,7 @@ def test_nj_family_distances(H, ctx, sizes):
 
 def test_nj_additive_and_ties(H, ctx):
     rng = np.random.default_rng(2)
-    for n in (5, 9, 33, 129):
+    for n in (5, 9, 33, 129, 300):
         # a tree metric with integer lengths (many exact ties in Q) and one with reals
         for integral in (True, False):
             par = [-1] + [int(rng.integers(0, v)) for v in range(1, 2 * n)]
@@ -112,8 +112,9 @@ def test_nj_additive_and_ties(H, ctx):
                         lca = max(common, key=lambda v: depth[v])
                         D[a, b] = depth[leaves[a]] + depth[leaves[b]] - 2 * depth[lca]
             _nj_both(H, ctx, D)
-    # all distances equal: every Q ties
-    for n in (4, 7, 64, 65):
+    # all distances equal: every Q ties (above 256 nodes the join runs over
+    # the chip, the ties then span workgroups)
+    for n in (4, 7, 64, 65, 257, 600):
         _nj_both(H, ctx, np.full((n, n), 2.5) * (1 - np.eye(n)))
 
 
