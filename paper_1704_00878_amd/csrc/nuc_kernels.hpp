@@ -400,13 +400,15 @@ __device__ __forceinline__ int nuc_chain_seq(const TM *mq, const TM *mp, TI *mbe
 
 constexpr int kChainLdsMax = 4096;   // matches of a sequence chained in LDS at most
 
-// LDS of the chain kernel for cap matches and aw aligned words: five 16-bit
-// arrays, then the words (4-byte aligned)
-inline size_t nuc_chain_lds_bytes(int cap, int aw) { return (size_t)2 * ((5 * (size_t)cap + 2) & ~(size_t)1) + 4 * (size_t)aw; }
+// LDS of the chain kernel (16-bit units): q, p, best, pred [cap] each, tails
+// [2 cap + 2], cut flags (bytes) [cap], then the aligned words (4-byte aligned)
+__host__ __device__ inline size_t nuc_chain_lal_off(int cap) { return ((6 * (size_t)cap + 2 + ((size_t)cap + 1) / 2) + 1) & ~(size_t)1; }
+inline size_t nuc_chain_lds_bytes(int cap, int aw) { return 2 * nuc_chain_lal_off(cap) + 4 * (size_t)aw; }
 
 // One 64-lane workgroup per sequence.  A sequence with at most a.chain_cap
 // matches has them staged in LDS (q, p < 65536 as 16-bit fields) and chained
-// there by lane 0; a larger one is chained by lane 0 in the global arrays.
+// there, segment by segment (below); a larger one is chained by lane 0 in the
+// global arrays.
 // Then the lanes share the slots: the anchors (aligned bits, scores) and one
 // stretch per slot (before the first anchor, between anchors, after the last;
 // slots past the chain get an empty descriptor).
@@ -414,6 +416,7 @@ __global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
     extern __shared__ uint16_t chain_lds[];
     const int cap = a.chain_cap;
     uint16_t *lq = chain_lds, *lp = lq + cap, *lbest = lp + cap, *lpred = lbest + cap, *ltails = lpred + cap;
+    uint8_t *lcut = reinterpret_cast<uint8_t *>(ltails + 2 * cap + 2);
     __shared__ int sh_L;
     const int x = blockIdx.x, lane = threadIdx.x;
     const int n = (int)(a.off[x + 1] - a.off[x]);
@@ -439,16 +442,73 @@ __global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
     bool ok = true;
     for (int i = lane; i + 1 < cnt; i += 64) ok = ok && qof(i + 1) > qof(i) && pof(i + 1) >= pof(i) + k;
     const bool ident = __ballot(!ok) == 0;
-    if (lane == 0 && !ident)
-        sh_L = inl ? nuc_chain_seq(lq, lp, lbest, lpred, ltails, cnt, k)
-                   : nuc_chain_seq(mq, mp, a.mbest + mb, a.mpred + mb, tails, cnt, k);
+    if (!ident && !inl) {
+        if (lane == 0) sh_L = nuc_chain_seq(mq, mp, a.mbest + mb, a.mpred + mb, tails, cnt, k);
+    } else if (!ident) {
+        // Cuts: b splits the matches when every match before it precedes every
+        // match from it on (max q before b < min q from b, p[b-1] + k <= p[b]).
+        // Then every match before b is inserted before b is queried, each query
+        // from b on finds the prefix's whole chain below its q, and later
+        // inserts touch only longer lengths: the chain is the prefix's chain
+        // followed by the rest's.  So each segment between cuts is chained on
+        // its own (lanes take the segments starting in their block), and the
+        // segments' chains are joined in order.
+        const int per = (cnt + 63) / 64, lo = min(cnt, lane * per), hi = min(cnt, lo + per);
+        int bmax = -1, bmin = 0x7fffffff;
+        for (int i = lo; i < hi; ++i) {
+            bmax = max(bmax, (int)lq[i]);
+            bmin = min(bmin, (int)lq[i]);
+        }
+        int pm = bmax, sm = bmin;   // inclusive prefix max, suffix min over the lanes
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t1 = __shfl_up(pm, d, 64), t2 = __shfl_down(sm, d, 64);
+            if (lane >= d) pm = max(pm, t1);
+            if (lane + d < 64) sm = min(sm, t2);
+        }
+        int runmax = __shfl_up(pm, 1, 64), runmin = __shfl_down(sm, 1, 64);
+        if (lane == 0) runmax = -1;
+        if (lane == 63) runmin = 0x7fffffff;
+        for (int i = hi - 1; i >= lo; --i) {   // min q from i on (lbest as scratch)
+            runmin = min(runmin, (int)lq[i]);
+            lbest[i] = (uint16_t)runmin;
+        }
+        for (int i = lo; i < hi; ++i) {
+            lcut[i] = (i == 0 || (runmax < (int)lbest[i] && (int)lp[i - 1] + k <= (int)lp[i])) ? 1 : 0;
+            runmax = max(runmax, (int)lq[i]);
+        }
+        __syncthreads();
+        for (int b = lo; b < hi; ++b) {
+            if (!lcut[b]) continue;
+            int e = b + 1;
+            while (e < cnt && !lcut[e]) ++e;
+            const int Ls = nuc_chain_seq(lq + b, lp + b, lbest + b, lpred + b, ltails + 2 * b, e - b, k);
+            lbest[b] = (uint16_t)Ls;   // the segment's chain length (its own best no longer needed)
+        }
+        __syncthreads();
+        int sl = 0;
+        for (int b = lo; b < hi; ++b)
+            if (lcut[b]) sl += lbest[b];
+        int inc = sl;
+        for (int d = 1; d < 64; d <<= 1) {
+            const int t1 = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += t1;
+        }
+        int o = inc - sl;
+        for (int b = lo; b < hi; ++b) {   // the chain, in order, into lpred (preds no longer needed)
+            if (!lcut[b]) continue;
+            const int Ls = lbest[b];
+            for (int t = 0; t < Ls; ++t) lpred[o + t] = (uint16_t)(b + ltails[2 * b + t]);
+            o += Ls;
+        }
+        if (lane == 63) sh_L = inc;
+    }
     __syncthreads();
     const int L = ident ? cnt : sh_L;
     auto anchor = [&](int t) __attribute__((always_inline)) -> int {   // match index of anchor t < L
-        return ident ? t : (inl ? (int)ltails[t] : tails[t]);
+        return ident ? t : (inl ? (int)lpred[t] : tails[t]);
     };
     uint32_t *al = a.aligned + (int64_t)x * a.aw;
-    uint32_t *lal = reinterpret_cast<uint32_t *>(chain_lds + ((5 * cap + 2) & ~1));   // [aw]: the aligned bits
+    uint32_t *lal = reinterpret_cast<uint32_t *>(chain_lds + nuc_chain_lal_off(cap));   // [aw]: the aligned bits
     for (int w = lane; w < a.aw; w += 64) lal[w] = 0u;
     __syncthreads();
     const uint64_t below = (1ull << lane) - 1ull;   // lanes under this one
