@@ -70,6 +70,7 @@ struct NucArgs {
 constexpr int kNucChunk = 256;   // match starts per scan chunk
 constexpr int kNucSmallW = 32;   // stretches at most this many columns wide: one lane, the row in registers
 constexpr int kNucTinyW = 20;    // narrow stretches at most this size both ways are listed apart
+constexpr int kNucTallH = 40;    // stretches taller than this take a wavefront too (rows across lanes)
 
 // The table's hash of a packed segment (the host fills the table with it).
 __host__ __device__ __forceinline__ uint32_t nuc_hash(unsigned long long key, int lg_t) {
@@ -526,16 +527,17 @@ __global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
         dc = (t < L ? qof(jt) * k : m) - ci;
         ds = (t < L ? pof(jt) : n) - sj;
     };
-    // narrow stretches: up to kNucTinyW x kNucTinyW from the front of the
-    // lane list, the others from its back, so most wavefronts get stretches
-    // of one size
+    // narrow stretches (at most kNucSmallW columns and kNucTallH rows): up to
+    // kNucTinyW x kNucTinyW from the front of the lane list, the others from
+    // its back, so most wavefronts get stretches of one size; the rest take
+    // a wavefront each
     auto tiny = [&](int dc, int ds) __attribute__((always_inline)) { return dc <= kNucTinyW && ds <= kNucTinyW; };
     int part = 0, nsm = 0, nwd = 0, nti = 0;
     for (int t = lane; t <= L; t += 64) {
         int ci, sj, dc, ds, jt;
         stretch(t, ci, sj, dc, ds, jt);
         const bool work = dc > 0 || ds > 0;
-        const bool wide = work && ds > kNucSmallW;
+        const bool wide = work && (ds > kNucSmallW || dc > kNucTallH);
         nti += work && !wide && tiny(dc, ds);
         nsm += work && !wide && !tiny(dc, ds);
         nwd += wide;
@@ -585,7 +587,7 @@ __global__ void __launch_bounds__(64) nuc_chain_kernel(NucArgs a) {
         int ci = 0, sj = 0, dc = 0, ds = 0, jt = 0;
         if (t <= L) stretch(t, ci, sj, dc, ds, jt);
         const bool work = t <= L && (dc > 0 || ds > 0);
-        const bool wide = work && ds > kNucSmallW;
+        const bool wide = work && (ds > kNucSmallW || dc > kNucTallH);
         const bool ti = work && !wide && tiny(dc, ds);
         const bool sm = work && !wide && !ti;
         const uint64_t bt = __ballot(ti), bs = __ballot(sm), bw = __ballot(wide);
@@ -678,9 +680,10 @@ __device__ __forceinline__ void nuc_traceback(const NucArgs &a, int x, int ci, i
     if (curw >= 0) atomicOr(al + curw, bits);
 }
 
-// Stretches at most kNucSmallW columns wide, one lane each (over the list
-// a.slist[0 .. a.lcount[0])): the row of (H, F) sits in registers, the codes
-// go to the stretch's code region, then the lane's traceback reads them back.
+// Stretches at most kNucSmallW columns wide and kNucTallH rows tall, one lane
+// each (over the list a.slist: lcount[0] entries from its front, lcount[2]
+// from its back): the row of (H, F) sits in registers, the codes go to the
+// stretch's code region, then the lane's traceback reads them back.
 __global__ void __launch_bounds__(256) nuc_stretch_small_kernel(NucArgs a) {
     NUC_SMAT_SETUP
     const int nt = a.lcount[0], ns = nt + a.lcount[2];   // the front's entries, then the back's
@@ -780,7 +783,7 @@ __device__ __forceinline__ int wave_prefix_max(int v, int lane) {
     return v;
 }
 
-// Wider stretches, one wavefront each (over the list a.blist[0 ..
+// Wider (or taller) stretches, one wavefront each (over the list a.blist[0 ..
 // a.lcount[1])), in strips of 64 columns, lane L owning column 64 b + 1 + L of
 // strip b and keeping (H, F) of the row above in registers.  E along a row is a
 // max-plus scan: with Ht = max(D, F) and A(j) = Ht(i, j) + ge j,
@@ -859,6 +862,7 @@ __global__ void __launch_bounds__(64) nuc_stretch_wave_kernel(NucArgs a) {
             }
         }
         if (dc == 0 && lane == 0) atomicAdd(a.score + x, -(go + ge * ds));   // H(0, ds)
+        if (ds == 0 && lane == 0) atomicAdd(a.score + x, -(go + ge * dc));   // H(dc, 0): no strips
         __syncthreads();   // the codes, written by every lane, before lane 0 reads them
         if (lane == 0) nuc_traceback(a, x, ci, dc, ds, code0);
     }
