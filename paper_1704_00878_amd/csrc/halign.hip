@@ -3108,6 +3108,7 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
     int K = S;
     std::vector<int> size(N + 1, 0);
     for (int x = 0; x < N; ++x) size[label[x]]++;
+    if (ctx->progress) fprintf(stderr, "halign_nj_tree: %d rows labelled against %d seeds\n", N, S);
     // clusters of fewer than 3 rows join the cluster of the nearest seed
     bool small = false;
     for (int c = 0; c < K; ++c) small = small || (size[c] > 0 && size[c] < 3);
@@ -3250,6 +3251,7 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
             }
         for (int x = 0; x < N; ++x) label[x] = map[nlab[x]];
         K = K2;
+        if (ctx->progress) fprintf(stderr, "halign_nj_tree: divide pass, %d clusters\n", K);
     }
     // distance matrices: each cluster over its rows (row order), then the seeds
     std::vector<int32_t> rows;
@@ -3310,8 +3312,10 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
                 tn[c] = sn[q];
             }
         }
+        if (ctx->progress) fprintf(stderr, "halign_nj_tree: %zu problems joined in one launch\n", small.size());
         for (int c = 0; c <= K; ++c) {
             if (ng[c].n <= kNjBigMin) continue;
+            if (ctx->progress) fprintf(stderr, "halign_nj_tree: joining %d nodes over the chip\n", ng[c].n);
             std::vector<int32_t> bp;
             std::vector<double> bb;
             int nn = 0;
