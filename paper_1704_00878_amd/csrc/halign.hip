@@ -2973,7 +2973,8 @@ int nj_big(halign_ctx *ctx, double *D, int n, std::vector<int32_t> &parent, std:
     hipLaunchKernelGGL(hk::nj_big_init_kernel, dim3(rg), dim3(256), 0, st, a);
     HCHK(hipGetLastError());
     for (int t = 0; t < n - 3; ++t) {
-        hipLaunchKernelGGL(hk::nj_big_rows_kernel, dim3(rg), dim3(256), 0, st, a);
+        hipLaunchKernelGGL(hk::nj_big_rows_kernel, dim3((unsigned)((n + hk::kNjRowsCols - 1) / hk::kNjRowsCols)),
+                           dim3(256), 0, st, a);
         hipLaunchKernelGGL(hk::nj_big_q_kernel, dim3((unsigned)nparts), dim3(256), 0, st, a);
         hipLaunchKernelGGL(hk::nj_big_join_kernel, dim3(1), dim3(256), 0, st, a);
     }

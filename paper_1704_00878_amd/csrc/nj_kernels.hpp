@@ -386,28 +386,41 @@ __global__ void __launch_bounds__(256) nj_big_init_kernel(NjBigArgs a) {
     if (s == 0) *a.ctrl = NjCtrl{a.n, a.n};
 }
 
-// row sums: one lane per active row, its column in slot order (the bits of the row)
+// row sums: a workgroup per 16 rows i0 .. i0 + 15; its 256 lanes stage the
+// columns i0 .. i0 + 15 of 256 rows k at a time in LDS (coalesced, all loads
+// in flight together), then lane t < 16 adds column i0 + t in slot order (the
+// bits of the row, D being symmetric)
+constexpr int kNjRowsCols = 16, kNjRowsChunk = 256;
+
 __global__ void __launch_bounds__(256) nj_big_rows_kernel(NjBigArgs a) {
 #pragma clang fp contract(off)
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    const int n = a.n;
-    if (i >= n || !a.act[i]) return;
+    __shared__ double blk[kNjRowsChunk * kNjRowsCols];
+    __shared__ uint8_t on[kNjRowsChunk];
+    const int n = a.n, tid = threadIdx.x;
+    const int i0 = blockIdx.x * kNjRowsCols;
+    const int ci = tid & (kNjRowsCols - 1), kr = tid / kNjRowsCols;   // this lane's column and first row in a chunk
+    const int i = i0 + ci;
     double sum = 0.0;
-    // two batches of loads: the next one in flight while this one is summed
-    constexpr int B = 16;
-    double v[B], w[B];
+    for (int k0 = 0; k0 < n; k0 += kNjRowsChunk) {
+        double v[kNjRowsChunk / 16];
 #pragma unroll
-    for (int u = 0; u < B; ++u) v[u] = u < n ? a.D[(int64_t)u * n + i] : 0.0;
-    for (int k0 = 0; k0 < n; k0 += B) {
+        for (int u = 0; u < kNjRowsChunk / 16; ++u) {
+            const int k = k0 + kr + 16 * u;
+            v[u] = (k < n && i < n) ? a.D[(int64_t)k * n + i] : 0.0;
+        }
+        const uint8_t onk = (tid < kNjRowsChunk && k0 + tid < n) ? a.act[k0 + tid] : (uint8_t)0;
+        __syncthreads();   // the previous chunk's sums are done with blk and on
+        if (tid < kNjRowsChunk) on[tid] = onk;
 #pragma unroll
-        for (int u = 0; u < B; ++u) w[u] = k0 + B + u < n ? a.D[(int64_t)(k0 + B + u) * n + i] : 0.0;
-#pragma unroll
-        for (int u = 0; u < B; ++u)
-            if (k0 + u < n && a.act[k0 + u]) sum = sum + v[u];
-#pragma unroll
-        for (int u = 0; u < B; ++u) v[u] = w[u];
+        for (int u = 0; u < kNjRowsChunk / 16; ++u) blk[(kr + 16 * u) * kNjRowsCols + ci] = v[u];
+        __syncthreads();
+        if (tid < kNjRowsCols) {
+            const int kn = min(kNjRowsChunk, n - k0);
+            for (int q = 0; q < kn; ++q)
+                if (on[q]) sum = sum + blk[q * kNjRowsCols + tid];
+        }
     }
-    a.r[i] = sum;
+    if (tid < kNjRowsCols && i0 + tid < n && a.act[i0 + tid]) a.r[i0 + tid] = sum;
 }
 
 // Q: workgroup b takes elements [b per, (b + 1) per) of the matrix row-major;
