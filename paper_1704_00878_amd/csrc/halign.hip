@@ -2862,13 +2862,14 @@ namespace {
 inline size_t al256z(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // The distance launch: whole width per tile, or, when the tiles are too few
-// to fill the chip and the MSA is wide, column slices of at least 1,024
+// to fill the chip several times over (under 8,192) and the MSA is wide,
+// column slices of at least 1,024
 // columns added atomically into zeroed counts and a finalize pass.  nout:
 // outputs the groups address (for the counts).
 int pdist_launch(halign_ctx *ctx, hk::PdArgs a, int64_t tiles, int64_t nout, hipStream_t st) {
     int64_t nslice = 1;
-    if (tiles < 2048 && a.width > 2048)
-        nslice = std::min<int64_t>((a.width + 1023) / 1024, (2048 + tiles - 1) / tiles);
+    if (tiles < 8192 && a.width > 2048)
+        nslice = std::min<int64_t>((a.width + 1023) / 1024, (8192 + tiles - 1) / tiles);
     a.nslice = 1;
     a.cslice = a.width;
     a.acc = nullptr;
