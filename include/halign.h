@@ -409,7 +409,9 @@ int halign_column_profile(const uint8_t *msa, int32_t n, int64_t width, int32_t 
  * p-distances between MSA rows: D[i * nb + j] = (columns where rows a_rows[i]
  * and b_rows[j] differ and both hold a residue, i.e. neither is HALIGN_GAP)
  * / (columns where both hold a residue), 1.0 where no column qualifies.
- * msa: device uint8 [n][width]; a_rows, b_rows: device int32 row indices
+ * msa: device uint8 [n][width], residue codes below 128 or HALIGN_GAP (a byte
+ * from 128 to 254 is not checked and compares by its low seven bits); a_rows,
+ * b_rows: device int32 row indices
  * (NULL: rows 0 .. na-1, 0 .. nb-1); D: device double [na][nb]; mism, comp:
  * device int32 [na][nb] (the two counts) or NULL.  The counts are exact and
  * the quotient is one IEEE division.  Asynchronous on stream. */

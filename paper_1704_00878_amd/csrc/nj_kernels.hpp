@@ -17,7 +17,7 @@ namespace hk {
 
 constexpr int kPdTile = 64;    // pairs per workgroup: 64 rows of A x 64 rows of B
 constexpr int kPdChunk = 64;   // columns staged per pass (16 words per row)
-constexpr int kPdStride = 17;  // LDS words per staged row (16 + 1: no bank conflicts between rows)
+constexpr int kPdStride = 17;  // LDS 64-bit words per staged row (16 + 1: no bank conflicts between rows)
 
 // One group of pairs: rows rows[a0 + i] (i < na) against rows[b0 + j] (j <
 // nb); D[i * ld + j] (and the counts, when given) at out offset o.  diag0:
@@ -53,16 +53,50 @@ __device__ __forceinline__ uint32_t nz_bytes(uint32_t v) {
     return ((v & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | v;
 }
 
+// Bytes c .. c + 15 of a row (the gap byte where the row is absent or past the
+// width), as four little-endian words: five aligned words realigned by the
+// row's byte offset where all of them lie inside the row, else byte by byte.
+__device__ __forceinline__ void pd_load16(const uint8_t *p, int64_t c, int64_t width, uint32_t w[4]) {
+    if (p && c + 20 <= width) {
+        const uint8_t *q = p + c;
+        const uint32_t *al = reinterpret_cast<const uint32_t *>(reinterpret_cast<uintptr_t>(q) & ~(uintptr_t)3);
+        const uint32_t sh = (uint32_t)(reinterpret_cast<uintptr_t>(q) & 3u);
+        uint32_t d[5];
+#pragma unroll
+        for (int i = 0; i < 5; ++i) d[i] = al[i];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) w[i] = __builtin_amdgcn_alignbyte(d[i + 1], d[i], sh);
+        return;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        uint32_t v = 0;
+#pragma unroll
+        for (int y = 0; y < 4; ++y) {
+            const int64_t cc = c + 4 * q + y;
+            v |= ((p && cc < width) ? (uint32_t)p[cc] : 255u) << (8 * y);
+        }
+        w[q] = v;
+    }
+}
+
 // A workgroup of 256 threads takes one 64 x 64 tile of a group's pairs (and
 // one column slice when the tiles are too few to fill the chip); thread
 // (ty, tx) counts pairs (4 ty + i, 4 tx + j), i, j < 4.  Each pass stages 64
 // columns of the tile's 128 rows in LDS (gap bytes past the width or past the
-// group's rows, which count nowhere), then compares four columns per word:
-// both residues where neither byte is the gap (255), a mismatch where they
-// also differ.
+// group's rows, which count nowhere): per word of four columns, the bytes with
+// bit 7 cleared and a mask with bit 7 set in each byte that is not the gap
+// (255), read together as one 64-bit word; per row, the 64 columns' non-gap
+// bits packed into two words.  Residue codes are below 128, so two residues
+// differ exactly where their low seven bits do, and bit 7 of
+// ((x ^ y) + 0x7F7F7F7F) marks those bytes without carries between bytes: a
+// pair-word costs one xor-add, one three-input and with both masks and one
+// popcount-add.  The residue pairs (both bytes not the gap) are counted on the
+// packed bits, 32 columns per and and popcount.
 __global__ void __launch_bounds__(256) pdist_kernel(PdArgs a) {
 #pragma clang fp contract(off)
-    __shared__ uint32_t sa[kPdTile * kPdStride], sb[kPdTile * kPdStride];
+    __shared__ uint2 sa[kPdTile * kPdStride], sb[kPdTile * kPdStride];
+    __shared__ uint32_t ga[kPdTile * 2], gb[kPdTile * 2];
     // the group and tile of this workgroup (and its column slice)
     int lo = 0, hi = a.ngroups - 1;
     const int64_t t = a.mode == 1 ? blockIdx.x / a.nslice : blockIdx.x;
@@ -77,7 +111,7 @@ __global__ void __launch_bounds__(256) pdist_kernel(PdArgs a) {
     const int ta = (int)(tl / g.tiles_b), tb = (int)(tl - (int64_t)ta * g.tiles_b);
     const int tid = threadIdx.x, tx = tid & 15, ty = tid >> 4;
     // staging: thread tid loads 16 bytes of row (tid >> 2) of each operand
-    const int lr = tid >> 2, lb = 16 * (tid & 3);
+    const int lr = tid >> 2, part = tid & 3, lb = 16 * part;
     const int ia = ta * kPdTile + lr, ib = tb * kPdTile + lr;
     const uint8_t *pa = ia < g.na ? a.msa + (int64_t)a.rows[g.a0 + ia] * a.width : nullptr;
     const uint8_t *pb = ib < g.nb ? a.msa + (int64_t)a.rows[g.b0 + ib] * a.width : nullptr;
@@ -90,45 +124,46 @@ __global__ void __launch_bounds__(256) pdist_kernel(PdArgs a) {
     const int64_t cend = a.mode == 1 ? min(a.width, cbeg + a.cslice) : (a.mode == 2 ? 0 : a.width);
     for (int64_t c0 = cbeg; c0 < cend; c0 += kPdChunk) {
         uint32_t wa[4], wb[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            uint32_t va = 0, vb = 0;
-#pragma unroll
-            for (int y = 0; y < 4; ++y) {
-                const int64_t c = c0 + lb + 4 * q + y;
-                const uint32_t ba = (pa && c < a.width) ? pa[c] : 255u;
-                const uint32_t bb = (pb && c < a.width) ? pb[c] : 255u;
-                va |= ba << (8 * y);
-                vb |= bb << (8 * y);
-            }
-            wa[q] = va;
-            wb[q] = vb;
-        }
+        pd_load16(pa, c0 + lb, a.width, wa);
+        pd_load16(pb, c0 + lb, a.width, wb);
         __syncthreads();   // the previous pass is done with the staged words
+        uint32_t bits_a = 0, bits_b = 0;   // 16 non-gap bits, at 0-3, 8-11, 16-19, 24-27
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
-            sa[lr * kPdStride + (lb >> 2) + q] = wa[q];
-            sb[lr * kPdStride + (lb >> 2) + q] = wb[q];
+            const uint32_t fa = nz_bytes(~wa[q]) & 0x80808080u, fb = nz_bytes(~wb[q]) & 0x80808080u;
+            sa[lr * kPdStride + 4 * part + q] = make_uint2(wa[q] & 0x7F7F7F7Fu, fa);
+            sb[lr * kPdStride + 4 * part + q] = make_uint2(wb[q] & 0x7F7F7F7Fu, fb);
+            bits_a |= fa >> (7 - q);
+            bits_b |= fb >> (7 - q);
+        }
+        // the odd part's bits fill the even part's gaps (any order of the
+        // columns' bits serves, the same for both operands)
+        const uint32_t na = __shfl_xor(bits_a, 1), nb = __shfl_xor(bits_b, 1);
+        if (!(part & 1)) {
+            ga[2 * lr + (part >> 1)] = bits_a | (na << 4);
+            gb[2 * lr + (part >> 1)] = bits_b | (nb << 4);
         }
         __syncthreads();
+#pragma unroll
+        for (int i = 0; i < 4; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int h = 0; h < 2; ++h)
+                    cc[i][j] += __popc(ga[2 * (4 * ty + i) + h] & gb[2 * (4 * tx + j) + h]);
 #pragma unroll 4
         for (int k = 0; k < kPdChunk / 4; ++k) {
-            uint32_t x[4], y[4], fx[4], fy[4];
+            uint2 x[4], y[4];
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
                 x[i] = sa[(4 * ty + i) * kPdStride + k];
                 y[i] = sb[(4 * tx + i) * kPdStride + k];
-                fx[i] = nz_bytes(~x[i]) & 0x80808080u;   // not the gap
-                fy[i] = nz_bytes(~y[i]) & 0x80808080u;
             }
 #pragma unroll
             for (int i = 0; i < 4; ++i)
 #pragma unroll
-                for (int j = 0; j < 4; ++j) {
-                    const uint32_t both = fx[i] & fy[j];
-                    cc[i][j] += __popc(both);
-                    mm[i][j] += __popc(nz_bytes(x[i] ^ y[j]) & both);
-                }
+                for (int j = 0; j < 4; ++j)
+                    mm[i][j] += __popc(((x[i].x ^ y[j].x) + 0x7F7F7F7Fu) & x[i].y & y[j].y);
         }
     }
 #pragma unroll

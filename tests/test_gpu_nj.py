@@ -65,6 +65,22 @@ def test_pdist_counts(H, ctx, n, w):
     assert (D.cpu().numpy() == oracle.pdist(m)).all()
 
 
+@pytest.mark.parametrize("n,w", [(70, 300), (3, 67)])
+def test_pdist_wide_codes(H, ctx, n, w):
+    """Residue codes up to 127, next to the gap byte 255 (it differs from 127
+    in bit 7 alone) and codes that share low bits with it."""
+    import torch
+    rng = np.random.default_rng(n + w)
+    m = _random_msa(rng, n, w, alpha=128)
+    m[:, ::7] = 127
+    m[1, ::5] = 0x7F & GAP
+    D, mm, cc = H.halign_pdist(ctx, _dev(m), counts=True)
+    torch.cuda.synchronize()
+    wm, wc = oracle.pdist_counts(m)
+    assert (mm.cpu().numpy() == wm).all() and (cc.cpu().numpy() == wc).all()
+    assert (D.cpu().numpy() == oracle.pdist(m)).all()
+
+
 def test_pdist_row_lists(H, ctx):
     import torch
     rng = np.random.default_rng(5)
