@@ -424,13 +424,15 @@ __global__ void __launch_bounds__(256) nj_big_init_kernel(NjBigArgs a) {
 // row sums: a workgroup per 16 rows i0 .. i0 + 15; its 256 lanes stage the
 // columns i0 .. i0 + 15 of 256 rows k at a time in LDS (coalesced, all loads
 // in flight together), then lane t < 16 adds column i0 + t in slot order (the
-// bits of the row, D being symmetric)
+// bits of the row, D being symmetric).  Rows k that are not active are staged
+// as +0.0: the sum starts at +0.0 and so is never -0.0 (round to nearest gives
+// x + (-x) = +0.0), and adding +0.0 to it leaves every bit, so the chain is
+// the sum over the active columns alone and runs without branches.
 constexpr int kNjRowsCols = 16, kNjRowsChunk = 256;
 
 __global__ void __launch_bounds__(256) nj_big_rows_kernel(NjBigArgs a) {
 #pragma clang fp contract(off)
     __shared__ double blk[kNjRowsChunk * kNjRowsCols];
-    __shared__ uint8_t on[kNjRowsChunk];
     const int n = a.n, tid = threadIdx.x;
     const int i0 = blockIdx.x * kNjRowsCols;
     const int ci = tid & (kNjRowsCols - 1), kr = tid / kNjRowsCols;   // this lane's column and first row in a chunk
@@ -441,18 +443,21 @@ __global__ void __launch_bounds__(256) nj_big_rows_kernel(NjBigArgs a) {
 #pragma unroll
         for (int u = 0; u < kNjRowsChunk / 16; ++u) {
             const int k = k0 + kr + 16 * u;
-            v[u] = (k < n && i < n) ? a.D[(int64_t)k * n + i] : 0.0;
+            v[u] = (k < n && i < n && a.act[k]) ? a.D[(int64_t)k * n + i] : 0.0;
         }
-        const uint8_t onk = (tid < kNjRowsChunk && k0 + tid < n) ? a.act[k0 + tid] : (uint8_t)0;
-        __syncthreads();   // the previous chunk's sums are done with blk and on
-        if (tid < kNjRowsChunk) on[tid] = onk;
+        __syncthreads();   // the previous chunk's sums are done with blk
 #pragma unroll
         for (int u = 0; u < kNjRowsChunk / 16; ++u) blk[(kr + 16 * u) * kNjRowsCols + ci] = v[u];
         __syncthreads();
         if (tid < kNjRowsCols) {
-            const int kn = min(kNjRowsChunk, n - k0);
-            for (int q = 0; q < kn; ++q)
-                if (on[q]) sum = sum + blk[q * kNjRowsCols + tid];
+            const int kn = min(kNjRowsChunk, (n - k0 + 15) & ~15);   // rows past n were staged as 0.0
+            for (int q0 = 0; q0 < kn; q0 += 16) {
+                double t[16];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) t[q] = blk[(q0 + q) * kNjRowsCols + tid];
+#pragma unroll
+                for (int q = 0; q < 16; ++q) sum = sum + t[q];
+            }
         }
     }
     if (tid < kNjRowsCols && i0 + tid < n && a.act[i0 + tid]) a.r[i0 + tid] = sum;
