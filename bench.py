@@ -313,6 +313,58 @@ def phylogeny_report(H, ctx, workload: str, reps: int, cpu: bool):
     return out
 
 
+PD_OPS_PER_PAIR_WORD = 3   # xor-add, three-input and, popcount-add per four columns of a pair
+INT_PEAK_TOPS = 39.32      # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz, int32 lane-ops
+
+
+def distance_report(H, ctx, workload: str, reps: int, cpu_rows: int):
+    """The NJ section's p-distances over every pair of rows of a protein MSA
+    (halign_msa of the workload, center 0): halign_pdist timed with the MSA
+    resident, in pair-columns per second, and its integer-ALU roofline; with
+    cpu_rows > 0, the oracle on the first cpu_rows rows (one host thread) and a
+    bit-for-bit check of that block."""
+    import torch
+    from paper_1704_00878_amd import synth
+    seqs = synth.generate(workload)
+    msa, _ = H.halign_msa(ctx, H.Scoring(), H.DeviceSeqs(seqs), 0)
+    n, w = int(msa.shape[0]), int(msa.shape[1])
+    log(f"bench: distances of the {workload} MSA ({n} x {w}): warm-up call")
+    D = H.halign_pdist(ctx, msa)
+    ts = []
+    for _ in range(reps):
+        del D
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        D = H.halign_pdist(ctx, msa)
+        torch.cuda.synchronize()
+        ts.append(time.perf_counter() - t)
+    ms = 1e3 * float(np.median(ts))
+    pc = float(n) * n * w
+    rate = pc / (ms / 1e3)
+    log(f"bench: distances {ms:.2f} ms, {rate / 1e12:.2f} T pair-columns/s")
+    achieved = rate * PD_OPS_PER_PAIR_WORD / 4 / 1e12
+    out = {"workload": f"{workload}: p-distances of all {n} x {n} row pairs of the {n} x {w} protein MSA",
+           "ms": round(ms, 3), "pair_columns_per_s": round(rate, 1),
+           "roofline": {"bound": "alu", "achieved": round(achieved, 3), "peak": INT_PEAK_TOPS, "unit": "TOP/s",
+                        "frac": round(achieved / INT_PEAK_TOPS, 4), "kernel": "pdist_kernel",
+                        "ops_per_pair_column": PD_OPS_PER_PAIR_WORD / 4},
+           "cpu_baseline": None}
+    if cpu_rows > 0:
+        import oracle
+        s = min(cpu_rows, n)
+        host = msa[:s].cpu().numpy()
+        t = time.perf_counter()
+        want = oracle.pdist(host)
+        dt = time.perf_counter() - t
+        got = D[:s, :s].cpu().numpy()
+        out["cpu_baseline"] = {"value": round(float(s) * s * w / dt, 1), "unit": "pair-columns/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": f"all pairs of the first {s} rows on one host thread ({dt:.2f} s)",
+                               "equal": bool((got == want).all())}
+    del D
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -337,6 +389,10 @@ def main():
                     "(none: skip)")
     ap.add_argument("--tree-only", action="store_true",
                     help="run only the phylogeny report and print it as one JSON line (profiling)")
+    ap.add_argument("--pdist", default="batch20k", help="protein set whose MSA the distance report takes all "
+                    "row pairs of ('none': skip)")
+    ap.add_argument("--pdist-only", action="store_true",
+                    help="run only the distance report and print it as one JSON line (profiling)")
     ap.add_argument("--anchors", type=int, default=50000, help="training anchors")
     ap.add_argument("--partners", type=int, default=64, help="training partners per anchor")
     ap.add_argument("--epochs", type=int, default=1)
@@ -364,6 +420,10 @@ def main():
     if args.tree_only:
         tree = phylogeny_report(H, H.Context(0), args.tree, args.steps, not args.no_cpu)
         print(json.dumps({"phylogeny": tree}), flush=True)
+        return
+    if args.pdist_only:
+        dist = distance_report(H, H.Context(0), args.pdist, args.steps, 0 if args.no_cpu else 256)
+        print(json.dumps({"distances": dist}), flush=True)
         return
     log(f"bench: generating {args.workload}")
     seqs = synth.generate(args.workload)
@@ -498,6 +558,9 @@ def main():
     tree = None
     if args.tree != "none":
         tree = phylogeny_report(H, ctx, args.tree, 3, not args.no_cpu)
+    dist = None
+    if args.pdist != "none":
+        dist = distance_report(H, ctx, args.pdist, 3, 0 if args.no_cpu else 256)
 
     ctx.set_autotune(not args.no_autotune)
     learned = None
@@ -525,6 +588,7 @@ def main():
         "learned_center": learned,
         "nucleotide": nuc,
         "phylogeny": tree,
+        "distances": dist,
     }
     print(json.dumps(out), flush=True)
     ctx.close()
