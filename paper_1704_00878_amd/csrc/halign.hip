@@ -2863,12 +2863,17 @@ inline size_t al256z(size_t b) { return (b + 255) & ~(size_t)255; }
 
 // The distance launch: whole width per tile, or, when the tiles are too few
 // to fill the chip several times over (under 8,192) and the MSA is wide,
-// column slices of at least 1,024
-// columns added atomically into zeroed counts and a finalize pass.  nout:
+// column slices (256 or 1,024 columns and up) added atomically into zeroed
+// counts and a finalize pass.  nout:
 // outputs the groups address (for the counts).
 int pdist_launch(halign_ctx *ctx, hk::PdArgs a, int64_t tiles, int64_t nout, hipStream_t st) {
     int64_t nslice = 1;
-    if (tiles < 8192 && a.width > 2048)
+    // few tiles: slices of 256 columns, about 256 workgroups in all (each
+    // slice's atomics cost more than a further slice hides); more tiles:
+    // slices of 1,024 columns up to 8,192 workgroups
+    if (tiles < 64 && a.width > 512)
+        nslice = std::min<int64_t>((a.width + 255) / 256, (256 + tiles - 1) / tiles);
+    else if (tiles < 8192 && a.width > 2048)
         nslice = std::min<int64_t>((a.width + 1023) / 1024, (8192 + tiles - 1) / tiles);
     a.nslice = 1;
     a.cslice = a.width;
@@ -2881,11 +2886,15 @@ int pdist_launch(halign_ctx *ctx, hk::PdArgs a, int64_t tiles, int64_t nout, hip
         a.acc = (int32_t *)ctx->njacc.p;
         RCHK(launch_fill((uint32_t *)a.acc, 0u, 2 * nout, st));
         a.mode = 1;
-        hipLaunchKernelGGL(hk::pdist_kernel, dim3((unsigned)(tiles * nslice)), dim3(256), 0, st, a);
+        // under four workgroups per CU the next pass's loads go out early
+        if (tiles * nslice < 1024)
+            hipLaunchKernelGGL(hk::pdist_kernel<true>, dim3((unsigned)(tiles * nslice)), dim3(256), 0, st, a);
+        else
+            hipLaunchKernelGGL(hk::pdist_kernel<false>, dim3((unsigned)(tiles * nslice)), dim3(256), 0, st, a);
         HCHK(hipGetLastError());
         a.mode = 2;
     }
-    hipLaunchKernelGGL(hk::pdist_kernel, dim3((unsigned)tiles), dim3(256), 0, st, a);
+    hipLaunchKernelGGL(hk::pdist_kernel<false>, dim3((unsigned)tiles), dim3(256), 0, st, a);
     HCHK(hipGetLastError());
     return HALIGN_OK;
 }

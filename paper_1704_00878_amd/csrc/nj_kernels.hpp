@@ -93,6 +93,7 @@ __device__ __forceinline__ void pd_load16(const uint8_t *p, int64_t c, int64_t w
 // pair-word costs one xor-add, one three-input and with both masks and one
 // popcount-add.  The residue pairs (both bytes not the gap) are counted on the
 // packed bits, 32 columns per and and popcount.
+template <bool PIPE>
 __global__ void __launch_bounds__(256) pdist_kernel(PdArgs a) {
 #pragma clang fp contract(off)
     __shared__ uint2 sa[kPdTile * kPdStride], sb[kPdTile * kPdStride];
@@ -122,10 +123,20 @@ __global__ void __launch_bounds__(256) pdist_kernel(PdArgs a) {
         for (int j = 0; j < 4; ++j) mm[i][j] = cc[i][j] = 0u;
     const int64_t cbeg = a.mode == 1 ? slice * a.cslice : 0;
     const int64_t cend = a.mode == 1 ? min(a.width, cbeg + a.cslice) : (a.mode == 2 ? 0 : a.width);
+    // PIPE (sliced launches, about one workgroup per CU): the next pass's
+    // bytes are loaded while this pass compares; otherwise after it, which
+    // keeps registers for more resident workgroups (the other workgroups on
+    // the CU hide the load latency)
+    uint32_t wa[4], wb[4];
+    if (PIPE && cbeg < cend) {
+        pd_load16(pa, cbeg + lb, a.width, wa);
+        pd_load16(pb, cbeg + lb, a.width, wb);
+    }
     for (int64_t c0 = cbeg; c0 < cend; c0 += kPdChunk) {
-        uint32_t wa[4], wb[4];
-        pd_load16(pa, c0 + lb, a.width, wa);
-        pd_load16(pb, c0 + lb, a.width, wb);
+        if (!PIPE) {
+            pd_load16(pa, c0 + lb, a.width, wa);
+            pd_load16(pb, c0 + lb, a.width, wb);
+        }
         __syncthreads();   // the previous pass is done with the staged words
         uint32_t bits_a = 0, bits_b = 0;   // 16 non-gap bits, at 0-3, 8-11, 16-19, 24-27
 #pragma unroll
@@ -144,6 +155,10 @@ __global__ void __launch_bounds__(256) pdist_kernel(PdArgs a) {
             gb[2 * lr + (part >> 1)] = bits_b | (nb << 4);
         }
         __syncthreads();
+        if (PIPE && c0 + kPdChunk < cend) {
+            pd_load16(pa, c0 + kPdChunk + lb, a.width, wa);
+            pd_load16(pb, c0 + kPdChunk + lb, a.width, wb);
+        }
 #pragma unroll
         for (int i = 0; i < 4; ++i)
 #pragma unroll
