@@ -269,7 +269,8 @@ inline size_t nj_lds_bytes(int nmax) { return nmax <= kNjLdsMax ? (size_t)9 * nm
 // D is kept symmetric), finds the smallest Q (the matrix spread row-major over
 // the lanes, then a workgroup reduction in (Q, i, j) order),
 // writes the two branch lengths and updates row and column i for the new
-// node.  Row sums and active flags sit in LDS when the problem fits.
+// node, and clears the row and column of the slot that leaves.  Row sums and
+// active flags sit in LDS when the problem fits.
 __global__ void __launch_bounds__(1024) nj_kernel(NjArgs a, int lds) {
 #pragma clang fp contract(off)
     extern __shared__ double nj_lds[];
@@ -292,14 +293,16 @@ __global__ void __launch_bounds__(1024) nj_kernel(NjArgs a, int lds) {
     while (m > 3) {
         for (int i = tid; i < n; i += bs) {
             if (!act[i]) continue;
+            // inactive slots' rows and columns hold +0.0, which leaves the sum
+            // (it starts at +0.0 and so is never -0.0) bit for bit: the chain
+            // is the sum over the active slots, without branches
             double sum = 0.0;
             for (int k0 = 0; k0 < n; k0 += kNjAhead) {   // column i, kNjAhead loads in flight
                 double v[kNjAhead];
 #pragma unroll
                 for (int u = 0; u < kNjAhead; ++u) v[u] = k0 + u < n ? D[(int64_t)(k0 + u) * n + i] : 0.0;
 #pragma unroll
-                for (int u = 0; u < kNjAhead; ++u)
-                    if (k0 + u < n && act[k0 + u]) sum = sum + v[u];
+                for (int u = 0; u < kNjAhead; ++u) sum = sum + v[u];
             }
             r[i] = sum;
         }
@@ -321,7 +324,9 @@ __global__ void __launch_bounds__(1024) nj_kernel(NjArgs a, int lds) {
                 }
 #pragma unroll
                 for (int u = 0; u < kNjAhead; ++u) {
-                    if (i < n && j > i && act[i] && act[j]) {
+                    // an inactive slot's sum is -inf: its pairs score +inf and
+                    // never come first (an active pair scores finite)
+                    if (i < n && j > i) {
                         const NjBest c{f * v[u] - r[i] - r[j], i, j};
                         if (nj_before(c, b)) b = c;
                     }
@@ -366,9 +371,15 @@ __global__ void __launch_bounds__(1024) nj_kernel(NjArgs a, int lds) {
             D[(int64_t)k * n + bi] = v;
         }
         __syncthreads();
+        // slot j leaves: its row and column to +0.0, its sum to -inf
+        for (int k = tid; k < n; k += bs) {
+            D[(int64_t)bj * n + k] = 0.0;
+            D[(int64_t)k * n + bj] = 0.0;
+        }
         if (tid == 0) {
             act[bj] = 0;
             id[bi] = next;
+            r[bj] = -__builtin_inf();
         }
         ++next;
         --m;
