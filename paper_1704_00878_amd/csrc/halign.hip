@@ -3003,6 +3003,35 @@ int nj_big(halign_ctx *ctx, double *D, int n, std::vector<int32_t> &parent, std:
 }
 
 // labels[i] = nearest of the nb columns of D (na x nb, device), to the host
+// labels[g][i] = nearest of the nb columns of group g's block (D + o, na x
+// nb): every group's launch, then one copy to the host
+int nearest_groups(halign_ctx *ctx, const double *D, const std::vector<hk::PdGroup> &gr,
+                   std::vector<std::vector<int32_t>> &label, hipStream_t st) {
+    size_t tot = 0;
+    for (auto &g : gr) tot += (size_t)std::max(0, g.na);
+    RCHK(grow(ctx, ctx->njS, al256z(4 * tot + 4)));
+    int32_t *lab = (int32_t *)ctx->njS.p;
+    size_t at = 0;
+    for (auto &g : gr) {
+        if (g.na > 0 && g.nb > 0)
+            hipLaunchKernelGGL(hk::nearest_kernel, dim3((unsigned)((g.na + 255) / 256)), dim3(256), 0, st, D + g.o,
+                               (int64_t)g.nb, g.na, g.nb, lab + at);
+        at += (size_t)std::max(0, g.na);
+    }
+    HCHK(hipGetLastError());
+    std::vector<int32_t> all(tot);
+    if (tot > 0) HCHK(hipMemcpyAsync(all.data(), lab, 4 * tot, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    label.resize(gr.size());
+    at = 0;
+    for (size_t gi = 0; gi < gr.size(); ++gi) {
+        const int na = std::max(0, gr[gi].na);
+        label[gi].assign(all.begin() + at, all.begin() + at + na);
+        at += na;
+    }
+    return HALIGN_OK;
+}
+
 int nearest_host(halign_ctx *ctx, const double *D, int na, int nb, std::vector<int32_t> &label, hipStream_t st) {
     RCHK(grow(ctx, ctx->njS, al256z(4 * (size_t)na)));
     int32_t *lab = (int32_t *)ctx->njS.p;
@@ -3130,11 +3159,13 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
         gr[0] = hk::PdGroup{0, 0, S, S, 0, S, 0, 0, 0};
         RCHK(grow(ctx, ctx->njD, 8 * (size_t)S * S));
         RCHK(pdist_groups(ctx, msa, width, rows, gr, (double *)ctx->njD.p, nullptr, nullptr, st));
-        std::vector<double> drow(S);
+        // the seeds' distances to the host in one copy
+        std::vector<double> dss((size_t)S * S);
+        HCHK(hipMemcpyAsync(dss.data(), ctx->njD.p, 8 * (size_t)S * S, hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
         for (int c = 0; c < K; ++c) {
             if (size[c] == 0 || size[c] >= 3) continue;
-            HCHK(hipMemcpy(drow.data(), (const double *)ctx->njD.p + (size_t)c * S, 8 * (size_t)S,
-                           hipMemcpyDeviceToHost));
+            const double *drow = dss.data() + (size_t)c * S;
             double best = 0.0;
             int bc = -1;
             for (int e = 0; e < K; ++e) {
@@ -3202,9 +3233,9 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
         RCHK(grow(ctx, ctx->njD, 8 * (size_t)dtot));
         RCHK(pdist_groups(ctx, msa, width, rows, gr, (double *)ctx->njD.p, nullptr, nullptr, st));
         // the nearest new seed of every row of each divided cluster, on the GPU
+        // (one launch per cluster, one copy back)
         std::vector<std::vector<int32_t>> glab(gr.size());
-        for (size_t gi = 0; gi < gr.size(); ++gi)
-            RCHK(nearest_host(ctx, (const double *)ctx->njD.p + gr[gi].o, gr[gi].na, gr[gi].nb, glab[gi], st));
+        RCHK(nearest_groups(ctx, (const double *)ctx->njD.p, gr, glab, st));
         // nearest new seed per row (ties to the earlier), or runs in permutation order
         std::vector<int> remap(nseed.size(), -1);
         {
