@@ -101,6 +101,7 @@ struct halign_ctx {
     bool capturing = false;   // a hipGraph capture of halign_sw_batch is in progress
     int use_graph = 0;        // halign_msa passes HALIGN_GRAPH to its batch
     hipStream_t cap_stream = nullptr;
+    hipStream_t aux_stream = nullptr;   // the tree's small joins beside the chip-wide ones
     struct GraphEntry {
         uint64_t key = 0;
         hipGraph_t graph = nullptr;
@@ -1160,6 +1161,7 @@ void halign_ctx_destroy(halign_ctx *ctx) {
     (void)hipDeviceSynchronize();
     graph_drop(ctx);
     if (ctx->cap_stream) (void)hipStreamDestroy(ctx->cap_stream);
+    if (ctx->aux_stream) (void)hipStreamDestroy(ctx->aux_stream);
     for (DevBuf *b : {&ctx->codes, &ctx->bound, &ctx->plan, &ctx->counter, &ctx->pairbuf, &ctx->msabuf, &ctx->spbuf,
                       &ctx->sbuf, &ctx->nuctab, &ctx->nucscr, &ctx->nucdp, &ctx->rowck,
                       &ctx->njrows, &ctx->njD, &ctx->njS, &ctx->njacc, &ctx->njB})
@@ -2927,8 +2929,15 @@ int pdist_groups(halign_ctx *ctx, const uint8_t *msa, int64_t width, const std::
 
 // Neighbour joining over groups (each D at its d0 in dbase, modified); the
 // trees come back to the host: tree g at t0 = 2 * (sum of earlier n) + g.
-int nj_groups(halign_ctx *ctx, std::vector<hk::NjGroup> &groups, double *dbase, std::vector<int32_t> &parent,
-              std::vector<double> &blen, std::vector<int32_t> &nodes, hipStream_t st) {
+// The one-workgroup joins of several problems (each group's offsets filled
+// in), enqueued on st; nj_groups_finish copies the trees to the host.
+struct NjLaunch {
+    size_t o_p = 0, o_b = 0, o_nd = 0;
+    int64_t nt = 0;
+    size_t G = 0;
+};
+
+int nj_groups_launch(halign_ctx *ctx, std::vector<hk::NjGroup> &groups, double *dbase, NjLaunch &L, hipStream_t st) {
     int64_t ns = 0, nt = 0;
     int nmax = 0;
     for (auto &g : groups) {
@@ -2951,14 +2960,32 @@ int nj_groups(halign_ctx *ctx, std::vector<hk::NjGroup> &groups, double *dbase, 
     const size_t lds = hk::nj_lds_bytes(nmax);   // at most 55 KiB
     hipLaunchKernelGGL(hk::nj_kernel, dim3((unsigned)G), dim3(bs), lds, st, a, lds > 0 ? 1 : 0);
     HCHK(hipGetLastError());
-    parent.resize(nt);
-    blen.resize(nt);
-    nodes.resize(G);
-    HCHK(hipMemcpyAsync(parent.data(), b + o_p, 4 * nt, hipMemcpyDeviceToHost, st));
-    HCHK(hipMemcpyAsync(blen.data(), b + o_b, 8 * nt, hipMemcpyDeviceToHost, st));
-    HCHK(hipMemcpyAsync(nodes.data(), b + o_nd, 4 * G, hipMemcpyDeviceToHost, st));
+    L.o_p = o_p;
+    L.o_b = o_b;
+    L.o_nd = o_nd;
+    L.nt = nt;
+    L.G = G;
+    return HALIGN_OK;
+}
+
+int nj_groups_finish(halign_ctx *ctx, const NjLaunch &L, std::vector<int32_t> &parent, std::vector<double> &blen,
+                     std::vector<int32_t> &nodes, hipStream_t st) {
+    char *b = (char *)ctx->njS.p;
+    parent.resize(L.nt);
+    blen.resize(L.nt);
+    nodes.resize(L.G);
+    HCHK(hipMemcpyAsync(parent.data(), b + L.o_p, 4 * L.nt, hipMemcpyDeviceToHost, st));
+    HCHK(hipMemcpyAsync(blen.data(), b + L.o_b, 8 * L.nt, hipMemcpyDeviceToHost, st));
+    HCHK(hipMemcpyAsync(nodes.data(), b + L.o_nd, 4 * L.G, hipMemcpyDeviceToHost, st));
     HCHK(hipStreamSynchronize(st));
     return HALIGN_OK;
+}
+
+int nj_groups(halign_ctx *ctx, std::vector<hk::NjGroup> &groups, double *dbase, std::vector<int32_t> &parent,
+              std::vector<double> &blen, std::vector<int32_t> &nodes, hipStream_t st) {
+    NjLaunch L;
+    RCHK(nj_groups_launch(ctx, groups, dbase, L, st));
+    return nj_groups_finish(ctx, L, parent, blen, nodes, st);
 }
 
 // Problems above this many nodes are joined over the whole chip (three
@@ -3343,18 +3370,18 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
         }
         tp.assign(nt, 0);
         tb.assign(nt, 0.0);
-        if (!small.empty()) {
-            std::vector<int32_t> sp, sn;
-            std::vector<double> sb;
-            RCHK(nj_groups(ctx, small, (double *)ctx->njD.p, sp, sb, sn, st));
-            for (size_t q = 0; q < small.size(); ++q) {
-                const int c = sidx[q];
-                std::copy(sp.begin() + small[q].t0, sp.begin() + small[q].t0 + 2 * ng[c].n + 1, tp.begin() + ng[c].t0);
-                std::copy(sb.begin() + small[q].t0, sb.begin() + small[q].t0 + 2 * ng[c].n + 1, tb.begin() + ng[c].t0);
-                tn[c] = sn[q];
-            }
+        // the small problems on a second stream, beside the chip-wide joins
+        // (their matrices, scratch and trees are disjoint; the distances are
+        // complete, pdist_groups having synchronised st)
+        bool any_big = false;
+        for (int c = 0; c <= K; ++c) any_big = any_big || ng[c].n > kNjBigMin;
+        hipStream_t sst = st;
+        if (any_big && !small.empty()) {
+            if (!ctx->aux_stream) HCHK(hipStreamCreateWithFlags(&ctx->aux_stream, hipStreamNonBlocking));
+            sst = ctx->aux_stream;
         }
-        if (ctx->progress) fprintf(stderr, "halign_nj_tree: %zu problems joined in one launch\n", small.size());
+        NjLaunch L;
+        if (!small.empty()) RCHK(nj_groups_launch(ctx, small, (double *)ctx->njD.p, L, sst));
         for (int c = 0; c <= K; ++c) {
             if (ng[c].n <= kNjBigMin) continue;
             if (ctx->progress) fprintf(stderr, "halign_nj_tree: joining %d nodes over the chip\n", ng[c].n);
@@ -3366,6 +3393,18 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
             std::copy(bb.begin(), bb.end(), tb.begin() + ng[c].t0);
             tn[c] = nn;
         }
+        if (!small.empty()) {
+            std::vector<int32_t> sp, sn;
+            std::vector<double> sb;
+            RCHK(nj_groups_finish(ctx, L, sp, sb, sn, sst));
+            for (size_t q = 0; q < small.size(); ++q) {
+                const int c = sidx[q];
+                std::copy(sp.begin() + small[q].t0, sp.begin() + small[q].t0 + 2 * ng[c].n + 1, tp.begin() + ng[c].t0);
+                std::copy(sb.begin() + small[q].t0, sb.begin() + small[q].t0 + 2 * ng[c].n + 1, tb.begin() + ng[c].t0);
+                tn[c] = sn[q];
+            }
+        }
+        if (ctx->progress) fprintf(stderr, "halign_nj_tree: %zu problems joined in one launch\n", small.size());
     }
     // the merge, node numbering as documented
     int next = N;
