@@ -3388,7 +3388,11 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
             std::vector<int32_t> bp;
             std::vector<double> bb;
             int nn = 0;
-            RCHK(nj_big(ctx, (double *)ctx->njD.p + ng[c].d0, ng[c].n, bp, bb, &nn, st));
+            const int rc = nj_big(ctx, (double *)ctx->njD.p + ng[c].d0, ng[c].n, bp, bb, &nn, st);
+            if (rc != HALIGN_OK) {   // the small joins finish before the scratch can be reused
+                if (sst != st) (void)hipStreamSynchronize(sst);
+                return rc;
+            }
             std::copy(bp.begin(), bp.end(), tp.begin() + ng[c].t0);
             std::copy(bb.begin(), bb.end(), tb.begin() + ng[c].t0);
             tn[c] = nn;
