@@ -2641,14 +2641,14 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
     const uint8_t *dc = seqs->residues + oh[center];
     Scoring S;
     RCHK(upload_matrix(ctx, sc, st, &S));
-    RCHK(validate_now(ctx, sc->alphabet, seqs->residues, oh[N], nullptr, 0, st));
+    // the code check and the center's copy to the host share one wait
+    RCHK(validate_codes(ctx, sc->alphabet, seqs->residues, oh[N], nullptr, 0, st));
+    std::vector<uint8_t> c(m);
+    if (m > 0) HCHK(hipMemcpyAsync(c.data(), dc, m, hipMemcpyDeviceToHost, st));
+    HCHK(hipStreamSynchronize(st));
+    RCHK(validate_check(ctx));
     // the center's segments, on the host: segment q (k codes 0..3) is indexed
     // when no other such segment has the same string
-    std::vector<uint8_t> c(m);
-    if (m > 0) {
-        HCHK(hipMemcpyAsync(c.data(), dc, m, hipMemcpyDeviceToHost, st));
-        HCHK(hipStreamSynchronize(st));
-    }
     const int nsg = m / k;
     std::vector<unsigned long long> key(nsg);
     std::vector<int32_t> segscore(std::max(nsg, 1), 0);
