@@ -2614,8 +2614,10 @@ int scan_i64(halign_ctx *ctx, const int64_t *in, int64_t n, int64_t add, int64_t
                            (const int64_t *)poff);
         HCHK(hipGetLastError());
     }
-    HCHK(hipMemcpyAsync(total_host, total_dev, 8, hipMemcpyDeviceToHost, st));
-    HCHK(hipStreamSynchronize(st));
+    if (total_host) {   // NULL: the caller reads total_dev itself
+        HCHK(hipMemcpyAsync(total_host, total_dev, 8, hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+    }
     return HALIGN_OK;
 }
 
@@ -2802,8 +2804,15 @@ int halign_nuc_align(halign_ctx *ctx, const halign_scoring *sc, const halign_seq
     // stretch scratch: row buffers and codes, one region per stretch
     int64_t nrow = 0, ncode = 0;
     int64_t *ro = (int64_t *)(sb + s_ro), *co = (int64_t *)(sb + s_co);
-    RCHK(scan_i64(ctx, a.srow, nslot, 0, ro, dtot, &nrow, st));
-    RCHK(scan_i64(ctx, a.scode, nslot, 0, co, dtot + 1, &ncode, st));
+    RCHK(scan_i64(ctx, a.srow, nslot, 0, ro, dtot, nullptr, st));
+    RCHK(scan_i64(ctx, a.scode, nslot, 0, co, dtot + 1, nullptr, st));
+    {   // both totals in one copy and one wait
+        int64_t t2[2] = {0, 0};
+        HCHK(hipMemcpyAsync(t2, dtot, 16, hipMemcpyDeviceToHost, st));
+        HCHK(hipStreamSynchronize(st));
+        nrow = t2[0];
+        ncode = t2[1];
+    }
     const size_t d_co = al256(8 * (size_t)nrow), dp_bytes = d_co + al256(4 * (size_t)ncode);
     RCHK(grow(ctx, ctx->nucdp, dp_bytes));
     a.srowoff = ro;
