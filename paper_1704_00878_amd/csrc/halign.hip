@@ -3009,12 +3009,13 @@ int nj_big(halign_ctx *ctx, double *D, int n, std::vector<int32_t> &parent, std:
     const int nparts = (int)std::max<int64_t>(1, std::min<int64_t>(2048, (nn + 255) / 256));
     const size_t nt = 2 * (size_t)n + 1;
     const size_t o_r = 0, o_id = al256z(8 * (size_t)n), o_p = o_id + al256z(4 * (size_t)n), o_b = o_p + al256z(4 * nt),
-                 o_part = o_b + al256z(8 * nt), o_ctrl = o_part + al256z(sizeof(hk::NjBest) * nparts),
+                 o_part = o_b + al256z(8 * nt), o_pd = o_part + al256z(sizeof(hk::NjBest) * nparts),
+                 o_ctrl = o_pd + al256z(8 * (size_t)nparts),
                  o_nodes = o_ctrl + 256, o_act = o_nodes + 256, bytes = o_act + al256z(n);
     RCHK(grow(ctx, ctx->njB, bytes));
     char *b = (char *)ctx->njB.p;
     hk::NjBigArgs a{n, D, (double *)(b + o_r), (uint8_t *)(b + o_act), (int32_t *)(b + o_id), (int32_t *)(b + o_p),
-                    (double *)(b + o_b), (hk::NjBest *)(b + o_part), nparts, (hk::NjCtrl *)(b + o_ctrl)};
+                    (double *)(b + o_b), (hk::NjBest *)(b + o_part), (double *)(b + o_pd), nparts, (hk::NjCtrl *)(b + o_ctrl)};
     const unsigned rg = (unsigned)((n + 255) / 256);
     hipLaunchKernelGGL(hk::nj_big_init_kernel, dim3(rg), dim3(256), 0, st, a);
     HCHK(hipGetLastError());

@@ -434,6 +434,7 @@ struct NjBigArgs {
     int32_t *parent;
     double *blen;
     NjBest *part;   // per workgroup of the Q pass
+    double *part_d; // D(i, j) of each part's pair
     int nparts;
     NjCtrl *ctrl;
 };
@@ -450,10 +451,11 @@ __global__ void __launch_bounds__(256) nj_big_init_kernel(NjBigArgs a) {
 // row sums: a workgroup per 16 rows i0 .. i0 + 15; its 256 lanes stage the
 // columns i0 .. i0 + 15 of 256 rows k at a time in LDS (coalesced, all loads
 // in flight together), then lane t < 16 adds column i0 + t in slot order (the
-// bits of the row, D being symmetric).  Rows k that are not active are staged
-// as +0.0: the sum starts at +0.0 and so is never -0.0 (round to nearest gives
-// x + (-x) = +0.0), and adding +0.0 to it leaves every bit, so the chain is
-// the sum over the active columns alone and runs without branches.
+// bits of the row, D being symmetric).  The rows of slots that have left
+// hold +0.0 (the join clears them): the sum starts at +0.0 and so is
+// never -0.0 (round to nearest gives x + (-x) = +0.0), and adding +0.0 to it
+// leaves every bit, so the chain is the sum over the active slots alone and
+// runs without flags or branches.
 constexpr int kNjRowsCols = 16, kNjRowsChunk = 256;
 
 __global__ void __launch_bounds__(256) nj_big_rows_kernel(NjBigArgs a) {
@@ -469,7 +471,7 @@ __global__ void __launch_bounds__(256) nj_big_rows_kernel(NjBigArgs a) {
 #pragma unroll
         for (int u = 0; u < kNjRowsChunk / 16; ++u) {
             const int k = k0 + kr + 16 * u;
-            v[u] = (k < n && i < n && a.act[k]) ? a.D[(int64_t)k * n + i] : 0.0;
+            v[u] = (k < n && i < n) ? a.D[(int64_t)k * n + i] : 0.0;
         }
         __syncthreads();   // the previous chunk's sums are done with blk
 #pragma unroll
@@ -494,81 +496,132 @@ __global__ void __launch_bounds__(256) nj_big_rows_kernel(NjBigArgs a) {
 __global__ void __launch_bounds__(256) nj_big_q_kernel(NjBigArgs a) {
 #pragma clang fp contract(off)
     __shared__ NjBest red[4];
+    __shared__ double redd[4];
     const int n = a.n, tid = threadIdx.x;
     const int64_t nn = (int64_t)n * n, per = (nn + a.nparts - 1) / a.nparts;
     const int64_t e0 = (int64_t)blockIdx.x * per, e1 = min(nn, e0 + per);
     const double f = (double)(a.ctrl->m - 2);
     NjBest b{0.0, -1, -1};
+    double bd = 0.0;
     for (int64_t e = e0 + tid; e < e1; e += blockDim.x) {
         const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
-        if (j <= i || !a.act[i] || !a.act[j]) continue;
-        const NjBest c{f * a.D[e] - a.r[i] - a.r[j], i, j};
-        if (nj_before(c, b)) b = c;
+        // a slot that has left has the sum -inf (and zeros in D): its pairs
+        // score +inf and never come first, so no flags are read
+        if (j <= i) continue;
+        const double d = a.D[e], ri = a.r[i], rj = a.r[j];
+        const NjBest c{f * d - ri - rj, i, j};
+        if (nj_before(c, b)) {
+            b = c;
+            bd = d;
+        }
     }
     for (int o = 32; o >= 1; o >>= 1) {
         NjBest y{__shfl_xor(b.q, o, 64), __shfl_xor(b.i, o, 64), __shfl_xor(b.j, o, 64)};
-        if (nj_before(y, b)) b = y;
+        const double yd = __shfl_xor(bd, o, 64);
+        if (nj_before(y, b)) {
+            b = y;
+            bd = yd;
+        }
     }
-    if ((tid & 63) == 0) red[tid >> 6] = b;
+    if ((tid & 63) == 0) {
+        red[tid >> 6] = b;
+        redd[tid >> 6] = bd;
+    }
     __syncthreads();
     if (tid == 0) {
         NjBest w = red[0];
+        double wd = redd[0];
         for (int x = 1; x < (int)(blockDim.x >> 6); ++x)
-            if (nj_before(red[x], w)) w = red[x];
+            if (nj_before(red[x], w)) {
+                w = red[x];
+                wd = redd[x];
+            }
         a.part[blockIdx.x] = w;
+        a.part_d[blockIdx.x] = wd;
     }
 }
 
-// the join: the first pair over the parts, lengths, row and column i updated
+constexpr int kNjPickAhead = 8;   // parts loaded per lane before comparing (2,048 parts in one batch)
+
+// the join: the first pair over the parts (every part's load in flight before
+// the first compare; D(i, j) comes with the pair), lengths, row and column i
+// updated, slot j's row cleared to +0.0 and its sum set to -inf for the next
+// row sums and Q
 __global__ void __launch_bounds__(256) nj_big_join_kernel(NjBigArgs a) {
 #pragma clang fp contract(off)
     __shared__ NjBest red[4];
-    __shared__ int sh_i, sh_j;
+    __shared__ double redd[4];
     const int n = a.n, tid = threadIdx.x;
     NjBest b{0.0, -1, -1};
-    for (int x = tid; x < a.nparts; x += blockDim.x)
-        if (nj_before(a.part[x], b)) b = a.part[x];
+    double bd = 0.0;
+    for (int x0 = 0; x0 < a.nparts; x0 += kNjPickAhead * (int)blockDim.x) {
+        NjBest p[kNjPickAhead];
+        double pd[kNjPickAhead];
+#pragma unroll
+        for (int h = 0; h < kNjPickAhead; ++h) {
+            const int x = x0 + h * (int)blockDim.x + tid;
+            p[h] = x < a.nparts ? a.part[x] : NjBest{0.0, -1, -1};
+            pd[h] = x < a.nparts ? a.part_d[x] : 0.0;
+        }
+#pragma unroll
+        for (int h = 0; h < kNjPickAhead; ++h)
+            if (nj_before(p[h], b)) {
+                b = p[h];
+                bd = pd[h];
+            }
+    }
     for (int o = 32; o >= 1; o >>= 1) {
         NjBest y{__shfl_xor(b.q, o, 64), __shfl_xor(b.i, o, 64), __shfl_xor(b.j, o, 64)};
-        if (nj_before(y, b)) b = y;
+        const double yd = __shfl_xor(bd, o, 64);
+        if (nj_before(y, b)) {
+            b = y;
+            bd = yd;
+        }
     }
-    if ((tid & 63) == 0) red[tid >> 6] = b;
+    if ((tid & 63) == 0) {
+        red[tid >> 6] = b;
+        redd[tid >> 6] = bd;
+    }
     __syncthreads();
+    NjBest w = red[0];
+    double dij = redd[0];
+    for (int x = 1; x < (int)(blockDim.x >> 6); ++x)
+        if (nj_before(red[x], w)) {
+            w = red[x];
+            dij = redd[x];
+        }
     const NjCtrl c = *a.ctrl;
+    const int bi = w.i, bj = w.j;
     if (tid == 0) {
-        NjBest w = red[0];
-        for (int x = 1; x < (int)(blockDim.x >> 6); ++x)
-            if (nj_before(red[x], w)) w = red[x];
-        const int bi = w.i, bj = w.j;
         const double f = (double)(c.m - 2);
-        const double dij = a.D[(int64_t)bi * n + bj];
         const double li = 0.5 * dij + (a.r[bi] - a.r[bj]) / (2.0 * f);
         const double lj = dij - li;
         a.parent[a.id[bi]] = c.next;
         a.blen[a.id[bi]] = li;
         a.parent[a.id[bj]] = c.next;
         a.blen[a.id[bj]] = lj;
-        sh_i = bi;
-        sh_j = bj;
     }
-    __syncthreads();
-    const int bi = sh_i, bj = sh_j;
-    const double dij = a.D[(int64_t)bi * n + bj];
+    // lane k alone reads and writes entry k of rows i and j and of column i
+    // (D(i, j) came with the pair), so clearing row j needs no barrier.  Row
+    // j must read +0.0 in the other slots' row sums; column j only enters
+    // slot j's own sum, which is not kept, and pairs with j score +inf in Q.
     for (int k = tid; k < n; k += blockDim.x) {
-        if (!a.act[k] || k == bi || k == bj) continue;
-        const double v = (a.D[(int64_t)bi * n + k] + a.D[(int64_t)bj * n + k] - dij) * 0.5;
-        a.D[(int64_t)bi * n + k] = v;
-        a.D[(int64_t)k * n + bi] = v;
+        if (a.act[k] && k != bi && k != bj) {
+            const double v = (a.D[(int64_t)bi * n + k] + a.D[(int64_t)bj * n + k] - dij) * 0.5;
+            a.D[(int64_t)bi * n + k] = v;
+            a.D[(int64_t)k * n + bi] = v;
+        }
+        a.D[(int64_t)bj * n + k] = 0.0;
     }
     __syncthreads();
     if (tid == 0) {
         a.act[bj] = 0;
         a.id[bi] = c.next;
+        a.r[bj] = -__builtin_inf();
         *a.ctrl = NjCtrl{c.m - 1, c.next + 1};
     }
 }
 
-// the last two or three nodes (or the single leaf), as in nj_kernel
 __global__ void nj_big_finish_kernel(NjBigArgs a, int32_t *nodes) {
 #pragma clang fp contract(off)
     const int n = a.n;
