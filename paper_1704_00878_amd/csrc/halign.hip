@@ -3360,8 +3360,46 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
         ng[c].d0 = dtot;
         dtot += (int64_t)sz * sz;
     }
-    RCHK(grow(ctx, ctx->njD, 8 * (size_t)dtot));
-    RCHK(pdist_groups(ctx, msa, width, rows, gr, (double *)ctx->njD.p, nullptr, nullptr, st));
+    // clusters of at most 64 rows, consecutive in `rows`, share 64-row tiles:
+    // one square group over the span (its pairs across clusters are computed
+    // and not used), each cluster's block then copied to its own matrix; a
+    // distance depends on its two rows alone, so the values are the same
+    std::vector<hk::PdGroup> gp;
+    std::vector<hk::PdExtract> ext;
+    int64_t ttot = dtot;
+    for (int c = 0; c < K;) {
+        if (csize[c] > hk::kPdTile) {
+            gp.push_back(gr[c++]);
+            continue;
+        }
+        const int first = c;
+        const int64_t R0 = coff[c];
+        int span = 0;
+        while (c < K && csize[c] <= hk::kPdTile && span + csize[c] <= hk::kPdTile) span += csize[c++];
+        if (c - first == 1) {
+            gp.push_back(gr[first]);
+            continue;
+        }
+        gp.push_back(hk::PdGroup{R0, R0, span, span, ttot, span, 1, 0, 0});
+        for (int q = first; q < c; ++q)
+            if (csize[q] > 0) {
+                const int64_t off = coff[q] - R0;
+                ext.push_back(hk::PdExtract{ttot + off * span + off, span, ng[q].d0, csize[q]});
+            }
+        ttot += (int64_t)span * span;
+    }
+    gp.push_back(gr[K]);
+    RCHK(grow(ctx, ctx->njD, 8 * (size_t)ttot));
+    RCHK(pdist_groups(ctx, msa, width, rows, gp, (double *)ctx->njD.p, nullptr, nullptr, st));
+    if (!ext.empty()) {
+        RCHK(grow(ctx, ctx->njrows, sizeof(hk::PdExtract) * ext.size()));
+        HCHK(hipMemcpyAsync(ctx->njrows.p, ext.data(), sizeof(hk::PdExtract) * ext.size(), hipMemcpyHostToDevice,
+                            st));
+        hipLaunchKernelGGL(hk::pd_extract_kernel, dim3((unsigned)ext.size()), dim3(256), 0, st,
+                           (double *)ctx->njD.p, (const hk::PdExtract *)ctx->njrows.p);
+        HCHK(hipGetLastError());
+        HCHK(hipStreamSynchronize(st));   // the small joins may run on another stream
+    }
     // the joins: small problems in one launch, large ones over the chip; tree
     // g at tp/tb offset ng[g].t0 (2n + 1 entries each), node count tn[g]
     std::vector<int32_t> tp, tn(K + 1);

@@ -208,6 +208,23 @@ __global__ void __launch_bounds__(256) pdist_kernel(PdArgs a) {
     }
 }
 
+// A block copied out of a shared distance tile: the sz x sz block at src
+// (row stride ld) to the contiguous sz x sz matrix at dst.
+struct PdExtract {
+    int64_t src, ld, dst;
+    int sz;
+};
+
+// one workgroup per block
+__global__ void __launch_bounds__(256) pd_extract_kernel(double *D, const PdExtract *ex) {
+    const PdExtract e = ex[blockIdx.x];
+    const int nn = e.sz * e.sz;
+    for (int x = threadIdx.x; x < nn; x += blockDim.x) {
+        const int r = x / e.sz, c = x - r * e.sz;
+        D[e.dst + x] = D[e.src + (int64_t)r * e.ld + c];
+    }
+}
+
 // label[i] = the first j with the smallest D[i * ld + j], j < nb (one lane per row).
 __global__ void __launch_bounds__(256) nearest_kernel(const double *D, int64_t ld, int na, int nb, int32_t *label) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
