@@ -3248,10 +3248,10 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
         for (int x = 0; x < N; ++x)
             if (size[label[x]] > S) mem[label[x]].push_back(x);
         int64_t dtot = 0;
+        std::vector<int32_t> kpos(K, -1);   // a kept cluster's seed position in nseed
         for (int c = 0; c < K; ++c) {
             if (size[c] <= S) {
-                for (int x = 0; x < N; ++x)
-                    if (label[x] == c) nlab[x] = (int32_t)nseed.size();
+                kpos[c] = (int32_t)nseed.size();
                 nseed.push_back(seed[c]);
                 continue;
             }
@@ -3267,6 +3267,8 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
             gbase.push_back(base);
             dtot += (int64_t)nm * nsd;
         }
+        for (int x = 0; x < N; ++x)   // rows of kept clusters: their seed's position
+            if (kpos[label[x]] >= 0) nlab[x] = kpos[label[x]];
         RCHK(grow(ctx, ctx->njD, 8 * (size_t)dtot));
         RCHK(pdist_groups(ctx, msa, width, rows, gr, (double *)ctx->njD.p, nullptr, nullptr, st));
         // the nearest new seed of every row of each divided cluster, on the GPU
