@@ -3196,6 +3196,8 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
         gr[0] = hk::PdGroup{0, 0, S, S, 0, S, 0, 0, 0};
         RCHK(grow(ctx, ctx->njD, 8 * (size_t)S * S));
         RCHK(pdist_groups(ctx, msa, width, rows, gr, (double *)ctx->njD.p, nullptr, nullptr, st));
+        std::vector<int> to(K);   // cluster a small one moved to (itself when kept)
+        for (int c = 0; c < K; ++c) to[c] = c;
         // the seeds' distances to the host in one copy
         std::vector<double> dss((size_t)S * S);
         HCHK(hipMemcpyAsync(dss.data(), ctx->njD.p, 8 * (size_t)S * S, hipMemcpyDeviceToHost, st));
@@ -3213,10 +3215,14 @@ int halign_nj_tree(halign_ctx *ctx, const uint8_t *msa, int32_t n, int64_t width
                 }
             }
             if (bc < 0) continue;
-            for (int x = 0; x < N; ++x)
-                if (label[x] == c) label[x] = bc;
+            to[c] = bc;   // the rows follow at the end, along the chain of moves
             size[bc] += size[c];
             size[c] = 0;
+        }
+        for (int x = 0; x < N; ++x) {
+            int c = label[x];
+            while (to[c] != c) c = to[c];
+            label[x] = c;
         }
     }
     {   // renumber the clusters left, in order
