@@ -522,8 +522,8 @@ __global__ void __launch_bounds__(256) nj_big_q_kernel(NjBigArgs a) {
     double bd = 0.0;
     for (int64_t e = e0 + tid; e < e1; e += blockDim.x) {
         const int i = (int)(e / n), j = (int)(e - (int64_t)i * n);
-        // a slot that has left has the sum -inf (and zeros in D): its pairs
-        // score +inf and never come first, so no flags are read
+        // a slot that has left has the sum -inf: its pairs score +inf (f D is
+        // finite) and never come first, so no flags are read
         if (j <= i) continue;
         const double d = a.D[e], ri = a.r[i], rj = a.r[j];
         const NjBest c{f * d - ri - rj, i, j};
