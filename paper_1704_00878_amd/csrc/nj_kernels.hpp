@@ -286,8 +286,8 @@ inline size_t nj_lds_bytes(int nmax) { return nmax <= kNjLdsMax ? (size_t)9 * nm
 // D is kept symmetric), finds the smallest Q (the matrix spread row-major over
 // the lanes, then a workgroup reduction in (Q, i, j) order),
 // writes the two branch lengths and updates row and column i for the new
-// node, and clears the row and column of the slot that leaves.  Row sums and
-// active flags sit in LDS when the problem fits.
+// node, and clears the row of the slot that leaves.  Row sums and active
+// flags sit in LDS when the problem fits.
 __global__ void __launch_bounds__(1024) nj_kernel(NjArgs a, int lds) {
 #pragma clang fp contract(off)
     extern __shared__ double nj_lds[];
@@ -388,11 +388,9 @@ __global__ void __launch_bounds__(1024) nj_kernel(NjArgs a, int lds) {
             D[(int64_t)k * n + bi] = v;
         }
         __syncthreads();
-        // slot j leaves: its row and column to +0.0, its sum to -inf
-        for (int k = tid; k < n; k += bs) {
-            D[(int64_t)bj * n + k] = 0.0;
-            D[(int64_t)k * n + bj] = 0.0;
-        }
+        // slot j leaves: its row to +0.0 (it enters every other column's
+        // sum; column j only enters j's own, which is not kept), its sum to -inf
+        for (int k = tid; k < n; k += bs) D[(int64_t)bj * n + k] = 0.0;
         if (tid == 0) {
             act[bj] = 0;
             id[bi] = next;
